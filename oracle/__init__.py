@@ -1,0 +1,172 @@
+"""CPU oracle (plain C++, exact int64) for filter -> sort-based equi-join -> group-by.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no code
+with the HIP library and imports nothing from it.
+
+Each wrapper takes and returns numpy arrays; see ``oracle.cpp`` for the
+definition each function computes and the passage of the paper it follows.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+
+I8, I32, I64 = 1, 2, 3
+LT, LE, GT, GE, EQ, NE = 0, 1, 2, 3, 4, 5
+_TYPES = {np.dtype(np.int8): I8, np.dtype(np.int32): I32, np.dtype(np.int64): I64}
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.cpp with g++ (-O2, IEEE arithmetic, no fast-math)."""
+    src = os.path.join(_HERE, "oracle.cpp")
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-fno-fast-math",
+                               "-o", tmp, src])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+_lib = None
+
+
+def _L():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        lib = ctypes.CDLL(_SO)
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        lib.orc_filter.argtypes = [i64, ctypes.c_int, vp, vp, ctypes.c_int, vp, vp, vp, vp]
+        lib.orc_filter.restype = i64
+        lib.orc_sort_pairs.argtypes = [vp, vp, i64, vp, vp]
+        lib.orc_sort_pairs.restype = None
+        lib.orc_join.argtypes = [vp, vp, i64, vp, vp, i64, vp, vp, i64]
+        lib.orc_join.restype = i64
+        lib.orc_groupby.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, i64]
+        lib.orc_groupby.restype = i64
+        lib.orc_fragment_flags.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp, vp, i64, i32, i32,
+                                           vp, vp, vp, vp, i64, vp]
+        lib.orc_fragment_flags.restype = i64
+        lib.orc_fragment_cust.argtypes = [vp, vp, vp, vp, i64, vp, vp, i64, i32, vp, vp, vp, i64,
+                                          i32, vp, vp, vp, vp, vp]
+        lib.orc_fragment_cust.restype = i64
+        lib.orc_overflow_flag.restype = ctypes.c_int
+        lib.orc_clear_overflow.restype = None
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def _check_overflow():
+    if _L().orc_overflow_flag():
+        _L().orc_clear_overflow()
+        raise OverflowError("oracle: exact int64 accumulation overflowed")
+
+
+def filter_rows(cols: list, preds: list) -> np.ndarray:
+    """Row ids (int32, increasing) where every predicate (col_index, op, k) holds."""
+    cols = [np.ascontiguousarray(c) for c in cols]
+    n = len(cols[0]) if cols else 0
+    ptrs = (ctypes.c_void_p * max(1, len(cols)))(*[c.ctypes.data for c in cols])
+    types = np.array([_TYPES[c.dtype] for c in cols] or [0], dtype=np.int32)
+    pc = np.array([p[0] for p in preds] or [0], dtype=np.int32)
+    po = np.array([p[1] for p in preds] or [0], dtype=np.int32)
+    pk = np.array([p[2] for p in preds] or [0], dtype=np.int64)
+    out = np.empty(max(1, n), dtype=np.int32)
+    w = _L().orc_filter(n, len(cols), ptrs, types.ctypes.data, len(preds), pc.ctypes.data,
+                        po.ctypes.data, pk.ctypes.data, out.ctypes.data)
+    return out[:w].copy()
+
+
+def sort_pairs(keys, vals=None):
+    keys = _c(keys, np.int32)
+    vals = None if vals is None else _c(vals, np.int32)
+    n = len(keys)
+    ko, vo = np.empty(n, np.int32), np.empty(n, np.int32)
+    if n:
+        _L().orc_sort_pairs(keys.ctypes.data, _p(vals), n, ko.ctypes.data, vo.ctypes.data)
+    return ko, vo
+
+
+def join(lkey, rkey, lrow=None, rrow=None, cap=None):
+    """Equi-join pairs (left payload, right payload) and the true count."""
+    lkey, rkey = _c(lkey, np.int32), _c(rkey, np.int32)
+    lrow = None if lrow is None else _c(lrow, np.int32)
+    rrow = None if rrow is None else _c(rrow, np.int32)
+    if cap is None:
+        cap = _L().orc_join(lkey.ctypes.data, _p(lrow), len(lkey), rkey.ctypes.data, _p(rrow),
+                            len(rkey), None, None, 0)
+    ol, orr = np.empty(max(1, cap), np.int32), np.empty(max(1, cap), np.int32)
+    J = _L().orc_join(lkey.ctypes.data, _p(lrow), len(lkey), rkey.ctypes.data, _p(rrow), len(rkey),
+                      ol.ctypes.data, orr.ctypes.data, cap)
+    w = min(J, cap)
+    return ol[:w].copy(), orr[:w].copy(), J
+
+
+def groupby(gkey, val, avg_in=None):
+    """(keys, sums, counts, avgs or None) with one row per distinct key, keys ascending."""
+    gkey, val = _c(gkey, np.int32), _c(val, np.int64)
+    avg_in = None if avg_in is None else _c(avg_in, np.int64)
+    n = len(gkey)
+    cap = max(1, n)
+    k, s, c, a = (np.empty(cap, np.int32), np.empty(cap, np.int64), np.empty(cap, np.int64),
+                  np.empty(cap, np.float64))
+    G = _L().orc_groupby(gkey.ctypes.data, n, val.ctypes.data, _p(avg_in), k.ctypes.data,
+                         s.ctypes.data, c.ctypes.data, a.ctypes.data, cap)
+    _check_overflow()
+    return k[:G].copy(), s[:G].copy(), c[:G].copy(), (a[:G].copy() if avg_in is not None else None)
+
+
+def fragment_flags(fact: dict, dim: dict, D: int, c: int) -> dict:
+    """The flags fragment (date < D, seg == c, fk = pk, group by flagA*2 + flagB)."""
+    f = {k: np.ascontiguousarray(v) for k, v in fact.items()}
+    d = {k: np.ascontiguousarray(v) for k, v in dim.items()}
+    cap = 8
+    k, s, cn, a = np.empty(cap, np.int32), np.empty(cap, np.int64), np.empty(cap, np.int64), np.empty(cap)
+    J = np.zeros(1, np.int64)
+    G = _L().orc_fragment_flags(f["fk"].ctypes.data, f["date"].ctypes.data, f["price"].ctypes.data,
+                                f["disc"].ctypes.data, f["flagA"].ctypes.data, f["flagB"].ctypes.data,
+                                len(f["fk"]), d["pk"].ctypes.data, d["seg"].ctypes.data, len(d["pk"]),
+                                D, c, k.ctypes.data, s.ctypes.data, cn.ctypes.data, a.ctypes.data, cap,
+                                J.ctypes.data)
+    _check_overflow()
+    return {"key": k[:G].copy(), "sum": s[:G].copy(), "cnt": cn[:G].copy(), "avg": a[:G].copy(),
+            "join_rows": int(J[0])}
+
+
+def fragment_cust(fact: dict, mid: dict, D: int, k: int = 100, gcap: int | None = None) -> dict:
+    """The custkey fragment (date < D, fk = pk, group by custkey, top-k by sum desc, key asc)."""
+    f = {kk: np.ascontiguousarray(v) for kk, v in fact.items()}
+    m = {kk: np.ascontiguousarray(v) for kk, v in mid.items()}
+    if gcap is None:
+        gcap = max(1, min(len(m["pk"]), int(m["custkey"].max()) + 1 if len(m["custkey"]) else 1))
+    key, s, cn = np.empty(gcap, np.int32), np.empty(gcap, np.int64), np.empty(gcap, np.int64)
+    tk, ts, tc = np.empty(max(1, k), np.int32), np.empty(max(1, k), np.int64), np.empty(max(1, k), np.int64)
+    kout = np.zeros(1, np.int32)
+    J = np.zeros(1, np.int64)
+    G = _L().orc_fragment_cust(f["fk"].ctypes.data, f["date"].ctypes.data, f["price"].ctypes.data,
+                               f["disc"].ctypes.data, len(f["fk"]), m["pk"].ctypes.data,
+                               m["custkey"].ctypes.data, len(m["pk"]), D, key.ctypes.data,
+                               s.ctypes.data, cn.ctypes.data, gcap, k, tk.ctypes.data, ts.ctypes.data,
+                               tc.ctypes.data, kout.ctypes.data, J.ctypes.data)
+    _check_overflow()
+    kk = int(kout[0])
+    w = min(G, gcap)
+    return {"key": key[:w].copy(), "sum": s[:w].copy(), "cnt": cn[:w].copy(), "groups": int(G),
+            "top_key": tk[:kk].copy(), "top_sum": ts[:kk].copy(), "top_cnt": tc[:kk].copy(),
+            "join_rows": int(J[0])}

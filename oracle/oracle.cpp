@@ -1,0 +1,272 @@
+// CPU oracle for the filter -> sort-based equi-join -> group-by path.
+//
+// TEST INFRASTRUCTURE ONLY.  Nothing in the product path may call this code:
+// only the tests, the smoke check and the CPU-baseline leg of the benchmark
+// load it.  It shares no code, header, table or helper with the HIP library.
+//
+// Every function computes the plain relational definition of its operator,
+// one row at a time, with exact 64-bit integer arithmetic (overflow checked)
+// and the C++ standard library only.  The paper's operators (Section 5 and
+// Algorithms 1-2) reach these definitions exactly: sorting, histogram-based
+// joins and sort-based grouping reorder work but do not change the result.
+//
+//   filter      Section 3.1 (Listing 1 and the selection-vector variant):
+//               the rows whose predicate holds, in input order.
+//   sort        Algorithm 1 (sort of the key columns), Algorithm 2 (sort of
+//               the group keys), Section 5.4 (radix sort): ascending by key,
+//               stable, payload carried along.
+//   join        Section 5.2 / Algorithm 1: the pairs (left row, right row)
+//               whose keys are equal; late materialisation returns index
+//               pairs.  Canonical order: left input order, then right input
+//               order (for key-sorted inputs this is the left-major order of
+//               the quotient / remainder step of Algorithm 1).
+//   group-by    Section 5.4 / Algorithm 2: one output row per distinct key,
+//               in ascending key order, with sum, count and average.
+//   fragments   the whole filter -> join -> group-by query of the workloads,
+//               as a hash join followed by a hash aggregation.
+//
+// Parity status: every function here is pinned by tests against library
+// routines, brute force on small inputs and closed-form invariants.
+#include <algorithm>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <numeric>
+#include <unordered_map>
+#include <vector>
+
+namespace {
+
+enum { ORC_I8 = 1, ORC_I32 = 2, ORC_I64 = 3 };
+enum { ORC_LT = 0, ORC_LE = 1, ORC_GT = 2, ORC_GE = 3, ORC_EQ = 4, ORC_NE = 5 };
+
+int g_overflow = 0;   // set when an exact int64 accumulation would overflow
+
+inline int64_t add_checked(int64_t a, int64_t b) {
+    int64_t r;
+    if (__builtin_add_overflow(a, b, &r)) g_overflow = 1;
+    return r;
+}
+
+inline int64_t mul_checked(int64_t a, int64_t b) {
+    int64_t r;
+    if (__builtin_mul_overflow(a, b, &r)) g_overflow = 1;
+    return r;
+}
+
+int64_t load_value(const void* col, int type, int64_t i) {
+    switch (type) {
+        case ORC_I8: return static_cast<const int8_t*>(col)[i];
+        case ORC_I32: return static_cast<const int32_t*>(col)[i];
+        default: return static_cast<const int64_t*>(col)[i];
+    }
+}
+
+bool compare(int64_t x, int op, int64_t k) {
+    switch (op) {
+        case ORC_LT: return x < k;
+        case ORC_LE: return x <= k;
+        case ORC_GT: return x > k;
+        case ORC_GE: return x >= k;
+        case ORC_EQ: return x == k;
+        default: return x != k;
+    }
+}
+
+// Revenue expression of the workloads, price * (100 - disc), in the exact
+// fixed-point unit cent * percent (the paper evaluates the same expression on
+// doubles, Section 5.1).
+inline int64_t revenue(int64_t price, int64_t disc) {
+    return mul_checked(price, 100 - disc);
+}
+
+struct Agg {
+    int64_t sum = 0, cnt = 0, sum_avg = 0;
+};
+
+}  // namespace
+
+extern "C" {
+
+int orc_overflow_flag(void) { return g_overflow; }
+void orc_clear_overflow(void) { g_overflow = 0; }
+
+// Filter (Section 3.1): rows i in [0, n) for which every predicate
+// cols[pred_col[p]][i] <op> k[p] holds, written in increasing order.
+// Returns the number of rows written.
+int64_t orc_filter(int64_t n, int ncols, const void* const* cols, const int32_t* types, int np,
+                   const int32_t* pred_col, const int32_t* pred_op, const int64_t* pred_k,
+                   int32_t* out_rows) {
+    (void)ncols;
+    int64_t w = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        bool keep = true;
+        for (int p = 0; p < np && keep; ++p)
+            keep = compare(load_value(cols[pred_col[p]], types[pred_col[p]], i), pred_op[p], pred_k[p]);
+        if (keep) out_rows[w++] = static_cast<int32_t>(i);
+    }
+    return w;
+}
+
+// Sort (Algorithms 1-2): the pairs ordered by key ascending; equal keys keep
+// their input order.  vals may be null (the payload is then the input index).
+void orc_sort_pairs(const int32_t* keys, const int32_t* vals, int64_t n, int32_t* keys_out,
+                    int32_t* vals_out) {
+    std::vector<int64_t> idx(static_cast<size_t>(n));
+    std::iota(idx.begin(), idx.end(), 0);
+    std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) {
+        return keys[a] != keys[b] ? keys[a] < keys[b] : a < b;
+    });
+    for (int64_t i = 0; i < n; ++i) {
+        keys_out[i] = keys[idx[i]];
+        vals_out[i] = vals ? vals[idx[i]] : static_cast<int32_t>(idx[i]);
+    }
+}
+
+// Equi-join (Section 5.2): every (lrow[i], rrow[j]) with lkey[i] == rkey[j],
+// ordered by i, then j.  Writes at most cap pairs; returns the true count.
+int64_t orc_join(const int32_t* lkey, const int32_t* lrow, int64_t nl, const int32_t* rkey,
+                 const int32_t* rrow, int64_t nr, int32_t* out_l, int32_t* out_r, int64_t cap) {
+    std::unordered_map<int32_t, std::vector<int64_t>> right;  // key -> right positions, in order
+    right.reserve(static_cast<size_t>(nr));
+    for (int64_t j = 0; j < nr; ++j) right[rkey[j]].push_back(j);
+    int64_t w = 0;
+    for (int64_t i = 0; i < nl; ++i) {
+        auto it = right.find(lkey[i]);
+        if (it == right.end()) continue;
+        for (int64_t j : it->second) {
+            if (w < cap) {
+                out_l[w] = lrow ? lrow[i] : static_cast<int32_t>(i);
+                out_r[w] = rrow ? rrow[j] : static_cast<int32_t>(j);
+            }
+            ++w;
+        }
+    }
+    return w;
+}
+
+// Group-by aggregation (Section 5.4, Algorithm 2): one row per distinct key in
+// ascending order with sum(val), count and avg(avg_in) = (double)sum(avg_in) /
+// (double)count.  avg_in may be null (out_avg is then not written).  Writes at
+// most gcap groups; returns the number of groups.
+int64_t orc_groupby(const int32_t* gkey, int64_t n, const int64_t* val, const int64_t* avg_in,
+                    int32_t* out_key, int64_t* out_sum, int64_t* out_cnt, double* out_avg,
+                    int64_t gcap) {
+    std::map<int32_t, Agg> groups;
+    for (int64_t i = 0; i < n; ++i) {
+        Agg& a = groups[gkey[i]];
+        a.sum = add_checked(a.sum, val[i]);
+        a.cnt += 1;
+        if (avg_in) a.sum_avg = add_checked(a.sum_avg, avg_in[i]);
+    }
+    int64_t g = 0;
+    for (const auto& kv : groups) {
+        if (g < gcap) {
+            out_key[g] = kv.first;
+            out_sum[g] = kv.second.sum;
+            out_cnt[g] = kv.second.cnt;
+            if (avg_in && out_avg)
+                out_avg[g] = static_cast<double>(kv.second.sum_avg) / static_cast<double>(kv.second.cnt);
+        }
+        ++g;
+    }
+    return g;
+}
+
+// Flags fragment: date < D on the fact table, seg == c on the dimension,
+// fact.fk = dim.pk, group by the packed key flagA * 2 + flagB, aggregates
+// sum(price * (100 - disc)), count and avg(price).  Groups in ascending key
+// order; returns the number of groups (at most 6, never more than gcap
+// written).  out_join (nullable) receives the join cardinality.
+int64_t orc_fragment_flags(const int32_t* fk, const int32_t* date, const int64_t* price,
+                           const int64_t* disc, const int8_t* flagA, const int8_t* flagB,
+                           int64_t n_fact, const int32_t* pk, const int8_t* seg, int64_t n_dim,
+                           int32_t D, int32_t c, int32_t* out_key, int64_t* out_sum,
+                           int64_t* out_cnt, double* out_avg, int64_t gcap, int64_t* out_join) {
+    std::unordered_multimap<int32_t, int64_t> dim;   // build side: filtered dimension rows
+    dim.reserve(static_cast<size_t>(n_dim));
+    for (int64_t d = 0; d < n_dim; ++d)
+        if (seg[d] == c) dim.emplace(pk[d], d);
+    std::map<int32_t, Agg> groups;
+    int64_t joined = 0;
+    for (int64_t f = 0; f < n_fact; ++f) {           // probe side: filtered fact rows
+        if (!(date[f] < D)) continue;
+        auto range = dim.equal_range(fk[f]);
+        for (auto it = range.first; it != range.second; ++it) {
+            Agg& a = groups[flagA[f] * 2 + flagB[f]];
+            a.sum = add_checked(a.sum, revenue(price[f], disc[f]));
+            a.cnt += 1;
+            a.sum_avg = add_checked(a.sum_avg, price[f]);
+            ++joined;
+        }
+    }
+    if (out_join) *out_join = joined;
+    int64_t g = 0;
+    for (const auto& kv : groups) {
+        if (g < gcap) {
+            out_key[g] = kv.first;
+            out_sum[g] = kv.second.sum;
+            out_cnt[g] = kv.second.cnt;
+            out_avg[g] = static_cast<double>(kv.second.sum_avg) / static_cast<double>(kv.second.cnt);
+        }
+        ++g;
+    }
+    return g;
+}
+
+// Custkey fragment: date < D on the fact table, fact.fk = mid.pk, group by
+// mid.custkey, aggregates sum(price * (100 - disc)) and count.  All groups go
+// out in ascending custkey order (at most gcap written); the first k rows of
+// the order (sum descending, custkey ascending) go to the top_* arrays and
+// *out_k receives min(k, groups).  Returns the number of groups.
+int64_t orc_fragment_cust(const int32_t* fk, const int32_t* date, const int64_t* price,
+                          const int64_t* disc, int64_t n_fact, const int32_t* pk,
+                          const int32_t* custkey, int64_t n_mid, int32_t D, int32_t* out_key,
+                          int64_t* out_sum, int64_t* out_cnt, int64_t gcap, int32_t k,
+                          int32_t* top_key, int64_t* top_sum, int64_t* top_cnt, int32_t* out_k,
+                          int64_t* out_join) {
+    std::unordered_multimap<int32_t, int64_t> mid;
+    mid.reserve(static_cast<size_t>(n_mid));
+    for (int64_t r = 0; r < n_mid; ++r) mid.emplace(pk[r], r);
+    std::unordered_map<int32_t, Agg> groups;
+    int64_t joined = 0;
+    for (int64_t f = 0; f < n_fact; ++f) {
+        if (!(date[f] < D)) continue;
+        auto range = mid.equal_range(fk[f]);
+        for (auto it = range.first; it != range.second; ++it) {
+            Agg& a = groups[custkey[it->second]];
+            a.sum = add_checked(a.sum, revenue(price[f], disc[f]));
+            a.cnt += 1;
+            ++joined;
+        }
+    }
+    if (out_join) *out_join = joined;
+    std::vector<std::pair<int32_t, Agg>> rows(groups.begin(), groups.end());
+    std::sort(rows.begin(), rows.end(),
+              [](const std::pair<int32_t, Agg>& a, const std::pair<int32_t, Agg>& b) {
+                  return a.first < b.first;
+              });
+    const int64_t G = static_cast<int64_t>(rows.size());
+    for (int64_t g = 0; g < G && g < gcap; ++g) {
+        out_key[g] = rows[g].first;
+        out_sum[g] = rows[g].second.sum;
+        out_cnt[g] = rows[g].second.cnt;
+    }
+    // ORDER BY sum DESC, custkey ASC, first k rows (Section 5: sort operator).
+    std::sort(rows.begin(), rows.end(),
+              [](const std::pair<int32_t, Agg>& a, const std::pair<int32_t, Agg>& b) {
+                  if (a.second.sum != b.second.sum) return a.second.sum > b.second.sum;
+                  return a.first < b.first;
+              });
+    const int64_t kk = std::min<int64_t>(k, G);
+    for (int64_t i = 0; i < kk; ++i) {
+        top_key[i] = rows[i].first;
+        top_sum[i] = rows[i].second.sum;
+        top_cnt[i] = rows[i].second.cnt;
+    }
+    *out_k = static_cast<int32_t>(kk);
+    return G;
+}
+
+}  // extern "C"

@@ -1,0 +1,247 @@
+"""Checks that pin the oracle to something other than itself.
+
+Each check compares one oracle function with a library routine (numpy's
+flatnonzero / stable argsort / intersect1d / bincount, Python's correctly
+rounded int division), with brute force over all pairs on small inputs, or
+with a closed-form identity.  The checks raise AssertionError; they are run
+against the real oracle (test_oracle.py) and against planted mistakes
+(test_oracle_mutants.py), where at least one of them must fail.
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+import datagen
+import oracle
+
+REV = lambda price, disc: int(price) * (100 - int(disc))  # noqa: E731  (price*(100-disc), cent*percent)
+
+
+def _rng(seed):
+    return np.random.default_rng(seed)
+
+
+# --------------------------------------------------------------------------- filter
+
+def check_filter():
+    rng = _rng(1)
+    n = 3000
+    date = rng.integers(0, 2557, n).astype(np.int32)
+    seg = rng.integers(0, 5, n).astype(np.int8)
+    big = rng.integers(-2**40, 2**40, n).astype(np.int64)
+    cols = [date, seg, big]
+    ops = {oracle.LT: np.less, oracle.LE: np.less_equal, oracle.GT: np.greater,
+           oracle.GE: np.greater_equal, oracle.EQ: np.equal, oracle.NE: np.not_equal}
+    for D in (0, 1, 1200, 2556, 2557, 2**31 - 1):
+        for op, fn in ops.items():
+            got = oracle.filter_rows(cols, [(0, op, D)])
+            want = np.flatnonzero(fn(date, D)).astype(np.int32)
+            assert np.array_equal(got, want), ("filter", D, op)
+    got = oracle.filter_rows(cols, [(0, oracle.LT, 2400), (1, oracle.EQ, 1), (2, oracle.GE, 0)])
+    want = np.flatnonzero((date < 2400) & (seg == 1) & (big >= 0)).astype(np.int32)
+    assert np.array_equal(got, want), "filter conjunction"
+    assert len(oracle.filter_rows([date[:0]], [(0, oracle.LT, 5)])) == 0
+    got = oracle.filter_rows([seg], [(0, oracle.EQ, 7)])      # a value that never occurs
+    assert len(got) == 0
+
+
+# --------------------------------------------------------------------------- sort
+
+def check_sort():
+    rng = _rng(2)
+    cases = [rng.integers(0, 50, 5000), rng.integers(0, 2**31 - 1, 4000), np.zeros(300, np.int64),
+             np.arange(1000)[::-1], np.array([7]), np.array([], np.int64),
+             np.array([2**31 - 1, 0, 2**31 - 1, 5, 0])]
+    for keys in cases:
+        keys = keys.astype(np.int32)
+        vals = rng.integers(-2**31, 2**31 - 1, len(keys)).astype(np.int32)
+        ko, vo = oracle.sort_pairs(keys, vals)
+        order = np.argsort(keys, kind="stable")
+        assert np.array_equal(ko, keys[order]), "sort keys"
+        assert np.array_equal(vo, vals[order]), "sort payload (stability)"
+        ko2, io = oracle.sort_pairs(keys)                  # payload = input index
+        assert np.array_equal(io, order.astype(np.int32)), "sort permutation"
+
+
+# --------------------------------------------------------------------------- join
+
+def _brute_join(lkey, rkey, lrow, rrow):
+    out = []
+    for i in range(len(lkey)):
+        for j in range(len(rkey)):
+            if lkey[i] == rkey[j]:
+                out.append((int(lrow[i]), int(rrow[j])))
+    return out
+
+
+def check_join():
+    rng = _rng(3)
+    for trial in range(12):
+        nl, nr = int(rng.integers(0, 300)), int(rng.integers(0, 120))
+        hi = int(rng.integers(1, 40))
+        lkey = np.sort(rng.integers(0, hi, nl)).astype(np.int32)
+        rkey = np.sort(rng.integers(0, hi, nr)).astype(np.int32)
+        lrow = rng.permutation(max(nl, 1))[:nl].astype(np.int32)
+        rrow = rng.permutation(max(nr, 1))[:nr].astype(np.int32)
+        ol, orr, J = oracle.join(lkey, rkey, lrow, rrow)
+        want = _brute_join(lkey, rkey, lrow, rrow)
+        assert J == len(want), ("join size", trial)
+        assert list(zip(ol.tolist(), orr.tolist())) == want, ("join pairs / order", trial)
+        # closed form of Algorithm 1: outSize = sum_k leftHist[k] * rightHist[k]
+        if nl and nr:
+            L = max(int(lkey.max()), int(rkey.max())) + 1
+            assert J == int(np.dot(np.bincount(lkey, minlength=L).astype(np.int64),
+                                   np.bincount(rkey, minlength=L).astype(np.int64)))
+    # every row on one key: J = n * m
+    ol, orr, J = oracle.join(np.full(70, 3, np.int32), np.full(40, 3, np.int32))
+    assert J == 70 * 40 and np.array_equal(ol, np.repeat(np.arange(70), 40)) \
+        and np.array_equal(orr, np.tile(np.arange(40), 70))
+    # unique keys on both sides: the matches are the set intersection
+    a = np.sort(rng.choice(5000, 800, replace=False)).astype(np.int32)
+    b = np.sort(rng.choice(5000, 900, replace=False)).astype(np.int32)
+    ol, orr, J = oracle.join(a, b)
+    inter = np.intersect1d(a, b)
+    assert J == len(inter) and np.array_equal(a[ol], inter) and np.array_equal(b[orr], inter)
+    # no matches, empty sides
+    assert oracle.join(np.arange(10, dtype=np.int32), np.arange(10, 20, dtype=np.int32))[2] == 0
+    assert oracle.join(np.zeros(0, np.int32), np.arange(5, dtype=np.int32))[2] == 0
+    assert oracle.join(np.arange(5, dtype=np.int32), np.zeros(0, np.int32))[2] == 0
+    # capacity: the first cap pairs of the canonical order, true count still returned
+    lk = np.array([1, 1, 2], np.int32)
+    rk = np.array([1, 1, 2, 2], np.int32)
+    ol, orr, J = oracle.join(lk, rk, cap=3)
+    assert J == 6 and list(zip(ol, orr)) == [(0, 0), (0, 1), (1, 0)]
+
+
+# --------------------------------------------------------------------------- group-by
+
+def check_groupby():
+    rng = _rng(4)
+    for trial in range(10):
+        n = int(rng.integers(0, 2000))
+        keys = rng.integers(0, int(rng.integers(1, 60)), n).astype(np.int32)
+        val = rng.integers(-10**9, 10**9, n).astype(np.int64)
+        price = rng.integers(0, 10**7, n).astype(np.int64)
+        k, s, c, a = oracle.groupby(keys, val, price)
+        ref = {}
+        for key, v, p in zip(keys.tolist(), val.tolist(), price.tolist()):
+            e = ref.setdefault(key, [0, 0, 0])
+            e[0] += v; e[1] += 1; e[2] += p
+        assert k.tolist() == sorted(ref), ("group keys", trial)
+        for i, key in enumerate(k.tolist()):
+            assert s[i] == ref[key][0] and c[i] == ref[key][1], ("group aggregates", trial)
+            # Python's int / int is correctly rounded: the exact average, rounded once
+            assert a[i] == ref[key][2] / ref[key][1], ("avg rounding", trial)
+        assert int(c.sum()) == n and int(s.sum()) == int(val.sum())   # conservation
+    # one group: reduces to a plain sum and mean
+    val = rng.integers(0, 10**9, 777).astype(np.int64)
+    k, s, c, a = oracle.groupby(np.full(777, 5, np.int32), val, val)
+    assert k.tolist() == [5] and s[0] == int(val.sum()) and c[0] == 777
+    assert a[0] == int(val.sum()) / 777
+    # empty input: no groups
+    k, s, c, a = oracle.groupby(np.zeros(0, np.int32), np.zeros(0, np.int64), np.zeros(0, np.int64))
+    assert len(k) == 0
+
+
+# --------------------------------------------------------------------------- fragments
+
+def brute_flags(fact, dim, D, c):
+    """All fact x dim pairs, compared directly; aggregates in Python integers."""
+    eq = fact["fk"][:, None] == dim["pk"][None, :]
+    eq &= (fact["date"] < D)[:, None]
+    eq &= (dim["seg"] == c)[None, :]
+    fi, di = np.nonzero(eq)
+    ref = {}
+    for f in fi.tolist():
+        g = int(fact["flagA"][f]) * 2 + int(fact["flagB"][f])
+        e = ref.setdefault(g, [0, 0, 0])
+        e[0] += REV(fact["price"][f], fact["disc"][f]); e[1] += 1; e[2] += int(fact["price"][f])
+    return ref, len(fi)
+
+
+def check_fragment_flags():
+    for seed, n, m, fk_hi, D, c, dup in [(11, 2000, 200, 200, 2400, 1, False),
+                                         (12, 1500, 150, 260, 1000, 3, False),
+                                         (13, 1000, 300, 50, 2557, 0, True),
+                                         (14, 500, 40, 40, 0, 1, False),
+                                         (15, 0, 40, 40, 2400, 1, False),
+                                         (16, 800, 90, 90, 2400, 9, False)]:
+        fr = datagen.random_flags_fragment(seed, n, m, fk_hi, D, c, dup_dim=dup)
+        got = oracle.fragment_flags(fr.fact, fr.dim, D, c)
+        ref, J = brute_flags(fr.fact, fr.dim, D, c)
+        assert got["join_rows"] == J, ("flags join size", seed)
+        assert got["key"].tolist() == sorted(ref), ("flags groups", seed)
+        for i, g in enumerate(got["key"].tolist()):
+            s, cn, sp = ref[g]
+            assert got["sum"][i] == s and got["cnt"][i] == cn, ("flags aggregates", seed)
+            assert got["avg"][i] == sp / cn, ("flags avg", seed)
+
+
+def check_fragment_flags_invariants():
+    fr = datagen.config0()
+    got = oracle.fragment_flags(fr.fact, fr.dim, fr.D, fr.c)
+    f, d = fr.fact, fr.dim
+    # J from histograms: sum over qualifying fact rows of the number of qualifying dim rows per key
+    hits = np.bincount(d["pk"][d["seg"] == fr.c], minlength=1500)
+    keep = f["date"] < fr.D
+    w = hits[f["fk"]] * keep
+    J = int(w.sum())
+    assert got["join_rows"] == J and int(got["cnt"].sum()) == J
+    v = f["price"] * (100 - f["disc"])
+    assert int(got["sum"].sum()) == int((v * w).sum())                     # sum conservation
+    g = f["flagA"].astype(np.int64) * 2 + f["flagB"]
+    for i, key in enumerate(got["key"].tolist()):
+        sel = w * (g == key)
+        assert got["cnt"][i] == int(sel.sum()) and got["sum"][i] == int((v * sel).sum())
+        assert got["avg"][i] == int((f["price"] * sel).sum()) / int(sel.sum())
+    assert len(got["key"]) == 6                       # all six (flagA, flagB) groups occur
+
+
+def brute_cust(fact, mid, D):
+    eq = (fact["fk"][:, None] == mid["pk"][None, :]) & (fact["date"] < D)[:, None]
+    fi, ri = np.nonzero(eq)
+    ref = {}
+    for f, r in zip(fi.tolist(), ri.tolist()):
+        e = ref.setdefault(int(mid["custkey"][r]), [0, 0])
+        e[0] += REV(fact["price"][f], fact["disc"][f]); e[1] += 1
+    return ref, len(fi)
+
+
+def check_fragment_cust():
+    for seed, n, m, cust, D, k in [(21, 2000, 300, 40, 2400, 10), (22, 1200, 100, 500, 1800, 100),
+                                    (23, 900, 200, 3, 2557, 5), (24, 0, 50, 10, 2400, 100)]:
+        fr = datagen.config2(seed=seed, n=n, m=m, cust_hi=cust)
+        got = oracle.fragment_cust(fr.fact, fr.mid, D, k)
+        ref, J = brute_cust(fr.fact, fr.mid, D)
+        assert got["join_rows"] == J and got["groups"] == len(ref), ("cust sizes", seed)
+        assert got["key"].tolist() == sorted(ref), ("cust groups", seed)
+        for i, g in enumerate(got["key"].tolist()):
+            assert got["sum"][i] == ref[g][0] and got["cnt"][i] == ref[g][1], ("cust aggs", seed)
+        order = sorted(ref, key=lambda g: (-ref[g][0], g))[:k]
+        assert got["top_key"].tolist() == order, ("cust top-k", seed)
+        assert got["top_sum"].tolist() == [ref[g][0] for g in order]
+        assert got["top_cnt"].tolist() == [ref[g][1] for g in order]
+    # mid keys with repeats: a many-to-many join
+    fr = datagen.config2(seed=25, n=1500, m=200, cust_hi=30)
+    mid = {"pk": datagen.uniform(25, datagen.COL_MID_PK, 200, 0, 120, np.int32),
+           "custkey": fr.mid["custkey"]}
+    got = oracle.fragment_cust(fr.fact, mid, 2400, 50)
+    ref, J = brute_cust(fr.fact, mid, 2400)
+    assert got["join_rows"] == J and got["key"].tolist() == sorted(ref), "cust many-to-many"
+    for i, g in enumerate(got["key"].tolist()):
+        assert got["sum"][i] == ref[g][0] and got["cnt"][i] == ref[g][1], "cust many-to-many aggs"
+
+
+def check_topk_ties():
+    # equal sums: custkey ascending decides
+    fact = {"fk": np.array([0, 1, 2, 3], np.int32), "date": np.zeros(4, np.int32),
+            "price": np.full(4, 100, np.int64), "disc": np.zeros(4, np.int64)}
+    mid = {"pk": np.array([3, 2, 1, 0], np.int32), "custkey": np.array([9, 4, 7, 1], np.int32)}
+    got = oracle.fragment_cust(fact, mid, 10, 3)
+    assert got["top_key"].tolist() == [1, 4, 7] and got["top_sum"].tolist() == [10000] * 3
+
+
+ALL_CHECKS = [check_filter, check_sort, check_join, check_groupby, check_fragment_flags,
+              check_fragment_flags_invariants, check_fragment_cust, check_topk_ties]

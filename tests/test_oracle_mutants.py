@@ -1,0 +1,59 @@
+"""Plant plausible mistakes in a copy of the oracle (on the CPU) and check that
+at least one pin catches each of them."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+import oracle
+import pins
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.cpp")
+
+# (name, original text, mutated text): a dropped term, a wrong sign, a wrong
+# comparison, a transposed operand, a wrong index, a dropped tie-break ...
+MUTANTS = [
+    ("revenue_sign", "mul_checked(price, 100 - disc)", "mul_checked(price, 100 + disc)"),
+    ("revenue_dropped_term", "mul_checked(price, 100 - disc)", "mul_checked(price, 100)"),
+    ("lt_as_le", "case ORC_LT: return x < k;", "case ORC_LT: return x <= k;"),
+    ("fragment_filter_off_by_one", "if (!(date[f] < D)) continue;\n        auto range = dim",
+     "if (!(date[f] <= D)) continue;\n        auto range = dim"),
+    ("sort_unstable", "return keys[a] != keys[b] ? keys[a] < keys[b] : a < b;",
+     "return keys[a] != keys[b] ? keys[a] < keys[b] : a > b;"),
+    ("join_transposed", "out_l[w] = lrow ? lrow[i] : static_cast<int32_t>(i);",
+     "out_l[w] = lrow ? lrow[i ? i - 1 : 0] : static_cast<int32_t>(i);"),
+    ("group_key_transposed", "groups[flagA[f] * 2 + flagB[f]]", "groups[flagB[f] * 2 + flagA[f]]"),
+    ("avg_wrong_divisor", "static_cast<double>(kv.second.sum_avg) / static_cast<double>(kv.second.cnt);\n        }\n        ++g;\n    }\n    return g;\n}\n\n// Flags",
+     "static_cast<double>(kv.second.sum_avg) / static_cast<double>(kv.second.cnt + 1);\n        }\n        ++g;\n    }\n    return g;\n}\n\n// Flags"),
+    ("count_dropped", "a.cnt += 1;\n            a.sum_avg = add_checked(a.sum_avg, price[f]);",
+     "a.sum_avg = add_checked(a.sum_avg, price[f]);"),
+    ("topk_tiebreak", "return a.first < b.first;\n              });\n    const int64_t kk",
+     "return a.first > b.first;\n              });\n    const int64_t kk"),
+    ("cust_uses_fact_key", "Agg& a = groups[custkey[it->second]];", "Agg& a = groups[fk[f]];"),
+    ("mid_first_match_only", "for (auto it = range.first; it != range.second; ++it) {\n            Agg& a = groups[custkey",
+     "for (auto it = range.first; it != range.second; it = range.second) {\n            Agg& a = groups[custkey"),
+]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,orig,mut", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_mutant_is_caught(tmp_path, name, orig, mut):
+    text = open(SRC).read()
+    assert text.count(orig) == 1, "mutation anchor must match exactly once: " + name
+    src = tmp_path / "oracle_mut.cpp"
+    src.write_text(text.replace(orig, mut))
+    so = tmp_path / "liboracle_mut.so"
+    subprocess.check_call(["g++", "-O1", "-std=c++17", "-fPIC", "-shared", "-o", str(so), str(src)])
+    saved = (oracle._lib, oracle._SO)
+    oracle._lib, oracle._SO = None, str(so)
+    failed = []
+    try:
+        for check in pins.ALL_CHECKS:
+            try:
+                check()
+            except AssertionError:
+                failed.append(check.__name__)
+    finally:
+        oracle._lib, oracle._SO = saved
+    assert failed, "no pin caught mutant " + name
