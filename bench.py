@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Throughput of filter -> sort-based equi-join -> group-by (+ top-100) on one MI355X.
+
+Workload (default): the 60M-row fact table joined to the 15M-row mid table,
+date < 2400, group by custkey (about 1.5M groups), exact int64 sum and count,
+then ORDER BY sum DESC, custkey ASC LIMIT 100.  Inputs are seeded synthetic
+columns (the generator in datagen/), resident in HBM before timing starts.
+
+A step is one whole fragment: both filters, both key sorts, the join, the
+group-key sort, the run reduction and the top-100, launched on one stream.
+W untimed warm-up steps, then exactly K timed steps between two events after
+a device synchronisation; value = fact rows / second.
+
+The per-launch profiler of the library (HIP events recorded on the launch
+stream around every kernel) is on during the timed steps; the roofline figure
+uses the dominant kernel family's measured durations and its algorithmic
+bytes (what the kernel must read and write), from the actual row counts.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fact rows/s filter→join→group-by (% of HBM peak); p50/p99 fragment latency"
+HBM_PEAK_GBS = 8000.0
+DOMINANT = "radix_pass_pairs_v8"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(label, N, n_f, M, J, G):
+    """Bytes each launch of a kernel family must read and write in this design (per launch list)."""
+    return {
+        "radix_hist": None,                       # two launches: fact (fk, date) and mid (pk)
+        "radix_pass_fused_v8": 8 * N + 16 * n_f + 12 * n_f,   # read fk, date (+price, disc of kept rows), write key+revenue
+        "radix_pass_fused_v4": 8 * M + 8 * M,                 # read pk, custkey; write key+custkey
+        "radix_pass_pairs_v4": 16 * M,
+        "join_keyval": 12 * n_f + 4 * M + 4 * J + 12 * J,     # sorted fact, mid keys, custkey of matches; write (custkey, revenue)
+        "segreduce": 12 * J + 20 * G,
+    }.get(label)
+
+
+def reference_model_bytes(N, n_f, M, J, G, P, Pm, Pg):
+    """The sort-based method's reference pass structure (each pass reads its input and writes its
+    output once; 8-bit digits), evaluated with the actual counts."""
+    F1 = 8 * N + 8 * n_f
+    F2 = 5 * M + 8 * M
+    S1 = 4 * n_f + 16 * P * n_f
+    S2 = 4 * M + 16 * Pm * M
+    J1 = 4 * (n_f + M)
+    J2 = 8 * (n_f + M) + 8 * J
+    G1 = 8 * J + 20 * J + 12 * J
+    A1 = 4 * J + 2 * Pg * 12 * J
+    A2 = 12 * J + 28 * G
+    T1 = 12 * G
+    return F1 + F2 + S1 + S2 + J1 + J2 + G1 + A1 + A2 + T1
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--digit-bits", type=int, default=8, choices=[4, 8, 11])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="time without the per-launch events")
+    ap.add_argument("--with-copy", action="store_true",
+                    help="after the steps, run a plain 1 GiB device copy (calibrates HBM counters)")
+    ap.add_argument("--rows", type=int, default=0, help="fact rows (0: the full 60M workload)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (requested --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2203_01877_amd as tqp
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+
+    t0 = time.time()
+    if args.rows:
+        m = max(1, args.rows // 4)
+        fr = datagen.config2(n=args.rows, m=m, cust_hi=max(1, args.rows // 40))
+    else:
+        fr = datagen.config2()
+    N, M = len(fr.fact["fk"]), len(fr.mid["pk"])
+    n_f = int(np.count_nonzero(fr.fact["date"] < fr.D))
+    log("generated %d fact rows, %d mid rows in %.1fs" % (N, M, time.time() - t0))
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    fact = tqp.to_device({k: fr.fact[k] for k in ("fk", "date", "price", "disc")}, dev)
+    mid = tqp.to_device(fr.mid, dev)
+    key_bits = datagen.bits_for(max(int(fr.fact["fk"].max()), M - 1) + 1)
+    cust_bits = datagen.bits_for(fr.cust_hi)
+    ctx = tqp.Context(0)
+    ctx.set_digit_bits(args.digit_bits)
+    run = tqp.CustFragmentRunner(ctx, fact, mid, fr.D, fr.k, key_bits=key_bits, cust_bits=cust_bits,
+                                 gcap=min(N, fr.cust_hi))
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        run.run()
+    torch.cuda.synchronize()
+    log("warmup done")
+    if not args.no_profile:
+        ctx.profile_read()              # drop warm-up records
+        ctx.set_profiling(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        run.run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    recs = ctx.profile_read() if not args.no_profile else []
+    ctx.set_profiling(False)
+    ms = total_ms / args.steps
+    log("timed %d steps: %.3f ms/step" % (args.steps, ms))
+
+    res = run.result(all_groups=False)
+    J, G = res["join_rows"], res["groups"]
+    errors = ctx.errors()
+    if errors:
+        log("device error flags: %#x" % errors)
+        sys.exit(3)
+
+    # ---------------------------------------------------------------- per-kernel figures
+    per = {}
+    for name, t in recs:
+        per.setdefault(name, []).append(t)
+    stage_ms = {k: round(sum(v) / args.steps, 4) for k, v in sorted(per.items())}
+    roofline = None
+    if DOMINANT in per:
+        # launches of the dominant family per step: fact passes after the first, then every group pass
+        pd_f = max(1, -(-key_bits // args.digit_bits))
+        pd_g = max(1, -(-cust_bits // args.digit_bits))
+        sizes = [n_f] * (pd_f - 1) + [J] * pd_g
+        durs = per[DOMINANT]
+        if len(durs) == len(sizes) * args.steps:
+            bytes_total = sum(24 * s for s in sizes) * args.steps
+            achieved = bytes_total / (sum(durs) * 1e-3) / 1e9
+            roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "kernel": "k_radix_pass<RadixCfg<%d,256,...>, SrcPairs<u64>, u64>" % args.digit_bits,
+                        "launches": len(durs), "avg_launch_ms": round(sum(durs) / len(durs), 4),
+                        "bytes_per_launch": round(bytes_total / len(durs))}
+        else:
+            log("dominant kernel launch count %d does not match %d passes x %d steps"
+                % (len(durs), len(sizes), args.steps))
+
+    P = max(1, -(-key_bits // 8))
+    Pm = max(1, -(-datagen.bits_for(M) // 8))
+    Pg = max(1, -(-cust_bits // 8))
+    bref = reference_model_bytes(N, n_f, M, J, G, P, Pm, Pg)
+    value = N / (ms * 1e-3)
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "fact rows/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": "60M-row fact x 15M-row mid: date<2400, fk=pk, group by custkey, sum+count, "
+                               "top-100 by sum desc" if not args.rows else "scaled custkey fragment",
+                   "fact_rows": N, "mid_rows": M, "filtered_fact_rows": n_f, "join_rows": J, "groups": G,
+                   "digit_bits": args.digit_bits, "key_bits": key_bits, "cust_bits": cust_bits},
+        "roofline": roofline,
+        "hbm_fraction_ref_model": round(bref / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+        "ref_model_bytes": bref,
+        "stage_ms": stage_ms,
+        "profiled": not args.no_profile,
+    }
+
+    if args.with_copy:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = 1
+        t1 = time.perf_counter()
+        want = oracle.fragment_cust(fr.fact, fr.mid, fr.D, fr.k, gcap=min(N, fr.cust_hi))
+        dt = time.perf_counter() - t1
+        ok = (want["groups"] == G and want["join_rows"] == J
+              and np.array_equal(want["top_key"], res["top_key"]) and np.array_equal(want["top_sum"], res["top_sum"]))
+        out["cpu_baseline"] = {"value": round(N / dt, 1), "unit": "fact rows/s", "cores": threads, "kind": "oracle",
+                               "sample": "the whole workload (%d fact rows, %d mid rows), one run, single thread, "
+                                         "%.1f s" % (N, M, dt),
+                               "matches_gpu": bool(ok)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,262 @@
+/*
+ * tqp.h — C ABI of the MI355X (gfx950) filter -> sort-based equi-join ->
+ * group-by library.
+ *
+ * The operators follow "Query Processing on Tensor Computation Runtimes"
+ * (Section 5 and Algorithms 1-2): a filter that turns a predicate into a
+ * selection of rows (Section 3.1), a sort-based equi-join that returns pairs
+ * of row indexes (Section 5.2, Algorithm 1), a sort-based group-by
+ * aggregation (Section 5.4, Algorithm 2) and an ORDER BY ... LIMIT k sort
+ * (Section 5, operator list).  Inputs are columns: one contiguous device
+ * buffer per column (Section 4.1).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Pointers named d_* and every column / output pointer are DEVICE pointers,
+ *   owned by the caller.  The library keeps none of them after the call
+ *   returns.  Structures passed by pointer (tqp_column, tqp_pred, fragment
+ *   descriptors) live in HOST memory and are read during the call only.
+ * - Calls are asynchronous on `stream`; argument errors are reported
+ *   synchronously through the return value and tqp_last_error().
+ * - Workspace: every call that needs scratch memory takes (ws, ws_bytes).
+ *   With ws == NULL the call only writes the number of bytes it needs to
+ *   *ws_bytes and returns TQP_OK.  Otherwise ws must be a device buffer of at
+ *   least *ws_bytes bytes, 256-byte aligned, not used by any other call until
+ *   this call's work on `stream` has completed.  The library clears what it
+ *   needs inside the workspace with its own kernels.
+ * - Data-dependent sizes (rows kept by a filter, join rows, groups) are
+ *   written to device counters (d_count, d_ngroups ...); the host is never
+ *   synchronised.  When a true size exceeds the caller's capacity, only
+ *   `cap` rows are written, the true size is still stored, and the context's
+ *   device error word gets TQP_DEVERR_CAPACITY (see tqp_ctx_errors).
+ * - Keys of sorts and joins are non-negative int32.  `key_bits` declares that
+ *   every key is < 2^key_bits (1..31; 0 means 31).  A key outside that range
+ *   sets TQP_DEVERR_KEY_RANGE and leaves the output unspecified.
+ * - Element counts are limited to 2^30 - 1 per call (TQP_ERR_UNSUPPORTED
+ *   beyond).
+ * - All integer aggregates are exact int64; averages are one IEEE double
+ *   division of the exact sum by the count.
+ */
+#ifndef TQP_H
+#define TQP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TQP_OK = 0,
+    TQP_ERR_INVALID = 1,      /* bad argument (null pointer, negative size, bad enum) */
+    TQP_ERR_WORKSPACE = 2,    /* ws_bytes smaller than the size query returned */
+    TQP_ERR_CAPACITY = 3,     /* reported by tqp_ctx_errors when an output overflowed */
+    TQP_ERR_HIP = 4,          /* a HIP runtime call or kernel launch failed */
+    TQP_ERR_UNSUPPORTED = 5   /* size or option outside what the library implements */
+} tqp_status;
+
+typedef enum { TQP_I8 = 1, TQP_I32 = 2, TQP_I64 = 3 } tqp_dtype;
+
+/* Comparison of a column with a constant (Section 5.1 expressions). */
+typedef enum { TQP_LT = 0, TQP_LE = 1, TQP_GT = 2, TQP_GE = 3, TQP_EQ = 4, TQP_NE = 5 } tqp_cmp;
+
+/* Device error bits (OR-ed by kernels into the context's error word). */
+#define TQP_DEVERR_KEY_RANGE 1u   /* a key was negative or >= 2^key_bits */
+#define TQP_DEVERR_SPIN 2u        /* an inter-tile wait hit its safety bound */
+#define TQP_DEVERR_CAPACITY 4u    /* an output count exceeded its capacity */
+
+/* One column: device pointer to n contiguous values of `type`. */
+typedef struct {
+    const void* data;
+    int32_t type;             /* tqp_dtype */
+    int32_t reserved;
+} tqp_column;
+
+/* One conjunct of a filter: cols[col] <op> k. */
+typedef struct {
+    int32_t col;
+    int32_t op;               /* tqp_cmp */
+    int64_t k;
+} tqp_pred;
+
+typedef struct tqp_ctx tqp_ctx;
+
+/* ---------------------------------------------------------------- context
+ * A context binds the library to one device and owns a small device error
+ * word and the tuning table (radix digit width, tile shape per workload).
+ * It is not thread-safe: use one context per host thread. */
+tqp_status tqp_ctx_create(int device, tqp_ctx** out);
+void tqp_ctx_destroy(tqp_ctx* ctx);
+
+/* Thread-local description of the last error returned on this thread. */
+const char* tqp_last_error(void);
+
+/* Synchronises `stream`, copies the device error word to *errors (a bitmask
+ * of TQP_DEVERR_*) and clears it when `clear` is non-zero. */
+tqp_status tqp_ctx_errors(tqp_ctx* ctx, hipStream_t stream, uint32_t* errors, int clear);
+
+/* Radix digit width used by sorts: 4, 8 or 11 bits (0 restores the default
+ * of 8).  The batch autotuner sets it per workload. */
+tqp_status tqp_ctx_set_digit_bits(tqp_ctx* ctx, int bits);
+
+/* Per-launch timing.  While profiling is on, every kernel the library
+ * launches is bracketed by two events recorded on the launch stream (this
+ * adds a little host work per launch).  tqp_ctx_profile_read synchronises
+ * `stream` and the device, writes up to `cap` records (kernel label and
+ * duration in milliseconds, in launch order) to `out`, the number of records
+ * to *n, and clears them. */
+typedef struct {
+    char name[40];
+    double ms;
+} tqp_prof_entry;
+
+tqp_status tqp_ctx_set_profiling(tqp_ctx* ctx, int on);
+tqp_status tqp_ctx_profile_read(tqp_ctx* ctx, hipStream_t stream, tqp_prof_entry* out, int cap, int* n);
+
+/* ---------------------------------------------------------------- filter
+ * Section 3.1 (Listing 1 and the selection-vector form): the row ids i in
+ * [0, n) for which every predicate cols[p.col][i] <p.op> p.k holds, in
+ * increasing order, written to out_rowid; carry (nullable, int32[n]) is
+ * compacted the same way into out_carry.  At most 4 predicates.  The number
+ * of selected rows goes to *d_count (device int64). */
+tqp_status tqp_filter(tqp_ctx* ctx, const tqp_column* cols, int ncols, int64_t n,
+                      const tqp_pred* preds, int npreds, const int32_t* carry,
+                      int32_t* out_rowid, int32_t* out_carry, int64_t cap, int64_t* d_count,
+                      void* ws, size_t* ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------- sort
+ * Algorithm 1 (sort of each join-key column with its index) and Algorithm 2
+ * (sort of the group keys): stable ascending LSD radix sort of the pairs
+ * (keys[i], vals[i]).  vals == NULL sorts the pairs (keys[i], i), so vals_out
+ * receives the sorting permutation; vals_out == NULL sorts keys only.  The
+ * element count is n, or *d_n (device int64, <= n) when d_n is not NULL.
+ * Outputs must not alias inputs. */
+tqp_status tqp_sort(tqp_ctx* ctx, const int32_t* keys, const int32_t* vals, int64_t n,
+                    const int64_t* d_n, int key_bits, int32_t* keys_out, int32_t* vals_out,
+                    void* ws, size_t* ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------- join
+ * Section 5.2, Algorithm 1: equi-join of two inputs already sorted by key
+ * (ascending).  For every pair i, j with lkey[i] == rkey[j] one output row
+ * (lrow[i], rrow[j]) — the index pairs of late materialisation — in the order
+ * (i, j) ascending, i.e. key ascending and, within a key, left-major as in
+ * the quotient / remainder step of Algorithm 1.  lrow / rrow may be NULL
+ * (the positions i / j are emitted).  Sizes nl / nr, or the device counts
+ * *d_nl / *d_nr when given.  The true number of output rows goes to
+ * *d_count; at most cap rows are written. */
+tqp_status tqp_join(tqp_ctx* ctx, const int32_t* lkey, const int32_t* lrow, int64_t nl,
+                    const int64_t* d_nl, const int32_t* rkey, const int32_t* rrow, int64_t nr,
+                    const int64_t* d_nr, int32_t* out_l, int32_t* out_r, int64_t cap,
+                    int64_t* d_count, void* ws, size_t* ws_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------- group-by
+ * Section 5.4, Algorithm 2: sort the group keys, permute the value columns
+ * by the sorted order, find the runs of equal keys and evaluate the
+ * aggregates per run.  Output: one row per distinct key in ascending key
+ * order: out_key, out_sum = sum(sum_in), out_cnt = count, and (when avg_in
+ * and out_avg are not NULL) out_avg = (double)sum(avg_in) / (double)count.
+ * Keys are non-negative int32 < 2^key_bits.  n or *d_n elements.  The
+ * number of groups goes to *d_ngroups; at most gcap groups are written. */
+tqp_status tqp_groupby_agg(tqp_ctx* ctx, const int32_t* gkey, int64_t n, const int64_t* d_n,
+                           int key_bits, const int64_t* sum_in, const int64_t* avg_in,
+                           int32_t* out_key, int64_t* out_sum, int64_t* out_cnt, double* out_avg,
+                           int64_t gcap, int64_t* d_ngroups, void* ws, size_t* ws_bytes,
+                           hipStream_t stream);
+
+/* ---------------------------------------------------------------- top-k
+ * ORDER BY sum DESC, key ASC LIMIT k over aggregated groups (keys must be
+ * unique, as group-by output is): rows (key, sum, cnt) of the first min(k, n)
+ * groups; the row count goes to *d_k (device int32).  1 <= k <= 1024. */
+tqp_status tqp_topk(tqp_ctx* ctx, const int32_t* key, const int64_t* sum, const int64_t* cnt,
+                    int64_t n, const int64_t* d_n, int k, int32_t* out_key, int64_t* out_sum,
+                    int64_t* out_cnt, int32_t* d_k, void* ws, size_t* ws_bytes,
+                    hipStream_t stream);
+
+/* ---------------------------------------------------------------- fragments
+ * Whole query fragments: filter -> sort-based join -> group-by in one launch
+ * sequence on one stream, with every intermediate in the workspace and the
+ * filters, the revenue expression and (for few groups) the aggregation fused
+ * into the neighbouring kernels. */
+
+/* Flags fragment:
+ *   SELECT flagA*2+flagB AS g, SUM(price*(100-disc)), COUNT(*), AVG(price)
+ *   FROM fact JOIN dim ON fact.fk = dim.pk
+ *   WHERE fact.date < D AND dim.seg = c GROUP BY g ORDER BY g
+ * price is int64 cents, disc int64 percent, so SUM is exact in cent*percent.
+ * The fact rows are [row0, row0 + n_fact) of the given columns (row0 lets a
+ * fragment cover a range of a larger resident table). */
+typedef struct {
+    const int32_t* fk;
+    const int32_t* date;
+    const int64_t* price;
+    const int64_t* disc;
+    const int8_t* flagA;      /* values 0..2 */
+    const int8_t* flagB;      /* values 0..1 */
+    int64_t row0;
+    int64_t n_fact;
+    const int32_t* pk;
+    const int8_t* seg;
+    int64_t n_dim;
+    int32_t D;
+    int32_t c;
+    int32_t key_bits;         /* fk and pk < 2^key_bits (0: 31) */
+    int32_t reserved;
+} tqp_flags_fragment;
+
+/* Outputs of a flags fragment (device pointers): up to 6 groups. */
+typedef struct {
+    int32_t* key;             /* [8] */
+    int64_t* sum;             /* [8] */
+    int64_t* cnt;             /* [8] */
+    double* avg;              /* [8] */
+    int64_t* d_ngroups;       /* number of groups written */
+    int64_t* d_join;          /* join cardinality (nullable) */
+} tqp_flags_out;
+
+tqp_status tqp_fragment_flags(tqp_ctx* ctx, const tqp_flags_fragment* f, const tqp_flags_out* o,
+                              void* ws, size_t* ws_bytes, hipStream_t stream);
+
+/* Custkey fragment:
+ *   SELECT mid.custkey, SUM(price*(100-disc)), COUNT(*)
+ *   FROM fact JOIN mid ON fact.fk = mid.pk WHERE fact.date < D
+ *   GROUP BY mid.custkey, plus ORDER BY sum DESC, custkey ASC LIMIT k. */
+typedef struct {
+    const int32_t* fk;
+    const int32_t* date;
+    const int64_t* price;
+    const int64_t* disc;
+    int64_t n_fact;
+    const int32_t* pk;
+    const int32_t* custkey;
+    int64_t n_mid;
+    int32_t D;
+    int32_t key_bits;         /* fk and pk < 2^key_bits (0: 31) */
+    int32_t cust_bits;        /* custkey < 2^cust_bits (0: 31) */
+    int32_t k;                /* top rows wanted, 1..1024 */
+    int64_t join_cap;         /* capacity for join rows (n_fact suffices when pks are unique) */
+} tqp_cust_fragment;
+
+typedef struct {
+    int32_t* key;             /* [gcap] all groups, custkey ascending */
+    int64_t* sum;             /* [gcap] */
+    int64_t* cnt;             /* [gcap] */
+    int64_t gcap;
+    int64_t* d_ngroups;
+    int64_t* d_join;          /* join cardinality (nullable) */
+    int32_t* top_key;         /* [k] */
+    int64_t* top_sum;         /* [k] */
+    int64_t* top_cnt;         /* [k] */
+    int32_t* d_topk;          /* rows in the top arrays */
+} tqp_cust_out;
+
+tqp_status tqp_fragment_cust(tqp_ctx* ctx, const tqp_cust_fragment* f, const tqp_cust_out* o,
+                             void* ws, size_t* ws_bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TQP_H */

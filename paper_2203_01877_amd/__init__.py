@@ -1,0 +1,274 @@
+"""MI355X (gfx950) filter -> sort-based equi-join -> group-by, behind a C ABI.
+
+The Python layer only marshals arguments: it allocates device buffers with
+PyTorch (memory and streams are all PyTorch is used for), passes raw pointers
+and the current HIP stream to libtqp.so, and wraps the results.  Every step of
+the computation runs in the library's HIP kernels; there is no CPU fallback.
+
+Operators (the paper's Section 5 and Algorithms 1-2):
+    filter        predicate -> selection vector of row ids   (Section 3.1)
+    sort          stable LSD radix sort of (key, payload)     (Algorithms 1-2)
+    join          sort-based equi-join -> index pairs          (Section 5.2, Algorithm 1)
+    groupby_agg   sort-based group-by with sum/count/avg       (Section 5.4, Algorithm 2)
+    topk          ORDER BY sum DESC, key ASC LIMIT k
+Fragments (whole queries in one launch sequence):
+    FlagsFragmentRunner   date < D AND seg = c, fact.fk = dim.pk, group by (flagA, flagB)
+    CustFragmentRunner    date < D, fact.fk = mid.pk, group by custkey, top-k
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import (DEVERR_CAPACITY, DEVERR_KEY_RANGE, DEVERR_SPIN, TQP_EQ, TQP_GE, TQP_GT, TQP_LE, TQP_LT,
+                   TQP_NE, TQPError, check)
+
+__all__ = ["Context", "filter", "sort", "join", "groupby_agg", "topk", "FlagsFragmentRunner",
+           "CustFragmentRunner", "TQPError", "TQP_LT", "TQP_LE", "TQP_GT", "TQP_GE", "TQP_EQ", "TQP_NE",
+           "DEVERR_KEY_RANGE", "DEVERR_SPIN", "DEVERR_CAPACITY"]
+
+_DTYPES = {torch.int8: _lib.TQP_I8, torch.int32: _lib.TQP_I32, torch.int64: _lib.TQP_I64}
+
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """A tqp_ctx on one device (error word + tuning)."""
+
+    def __init__(self, device: int = 0):
+        self.lib = _lib.load()
+        self.device = device
+        h = ctypes.c_void_p()
+        with torch.cuda.device(device):
+            check(self.lib.tqp_ctx_create(device, ctypes.byref(h)), "tqp_ctx_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tqp_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def errors(self, clear: bool = True, stream=None) -> int:
+        e = ctypes.c_uint32(0)
+        check(self.lib.tqp_ctx_errors(self.h, _stream(stream), ctypes.byref(e), int(clear)), "tqp_ctx_errors")
+        return int(e.value)
+
+    def set_digit_bits(self, bits: int) -> None:
+        check(self.lib.tqp_ctx_set_digit_bits(self.h, bits), "tqp_ctx_set_digit_bits")
+
+    def set_profiling(self, on: bool) -> None:
+        check(self.lib.tqp_ctx_set_profiling(self.h, int(bool(on))), "tqp_ctx_set_profiling")
+
+    def profile_read(self, stream=None, cap: int = 1 << 16) -> list:
+        """[(kernel label, milliseconds)] of the launches since the last read, in launch order."""
+        buf = (_lib.ProfEntry * cap)()
+        n = ctypes.c_int(0)
+        check(self.lib.tqp_ctx_profile_read(self.h, _stream(stream), buf, cap, ctypes.byref(n)),
+              "tqp_ctx_profile_read")
+        return [(buf[i].name.decode(), float(buf[i].ms)) for i in range(min(n.value, cap))]
+
+
+def _workspace(call, where, device):
+    """Size query (ws = NULL), then a device buffer of that size."""
+    sz = ctypes.c_size_t(0)
+    check(call(None, ctypes.byref(sz)), where + " (size query)")
+    ws = torch.empty(max(int(sz.value), 256), dtype=torch.uint8, device=device)
+    return ws, sz
+
+
+def _run(call, where, device):
+    ws, sz = _workspace(call, where, device)
+    check(call(_p(ws), ctypes.byref(sz)), where)
+    return ws
+
+
+def _dev(ctx):
+    return torch.device("cuda", ctx.device)
+
+
+def filter(ctx: Context, cols: list, preds: list, carry=None, cap: int | None = None, stream=None):
+    """Row ids where every (col_index, op, k) predicate holds.  Returns (rowid, carry_out, d_count)."""
+    n = cols[0].numel() if cols else 0
+    cap = n if cap is None else cap
+    dev = _dev(ctx)
+    carr = (_lib.Column * max(1, len(cols)))(*[_lib.Column(c.data_ptr(), _DTYPES[c.dtype], 0) for c in cols])
+    parr = (_lib.Pred * max(1, len(preds)))(*[_lib.Pred(p[0], p[1], p[2]) for p in preds])
+    out = torch.empty(max(1, cap), dtype=torch.int32, device=dev)
+    outc = torch.empty(max(1, cap), dtype=torch.int32, device=dev) if carry is not None else None
+    cnt = torch.empty(1, dtype=torch.int64, device=dev)
+    s = _stream(stream)
+    _run(lambda ws, sz: ctx.lib.tqp_filter(ctx.h, carr, len(cols), n, parr, len(preds), _p(carry), _p(out),
+                                           _p(outc), cap, _p(cnt), ws, sz, s), "tqp_filter", dev)
+    return out, outc, cnt
+
+
+def sort(ctx: Context, keys, vals=None, key_bits: int = 0, perm: bool = False, d_n=None, stream=None):
+    """Stable ascending sort.  vals given: (keys, vals) sorted together; perm=True: the
+    permutation comes back as the payload; otherwise keys only."""
+    n = keys.numel()
+    dev = _dev(ctx)
+    ko = torch.empty(max(1, n), dtype=torch.int32, device=dev)
+    vo = torch.empty(max(1, n), dtype=torch.int32, device=dev) if (vals is not None or perm) else None
+    s = _stream(stream)
+    _run(lambda ws, sz: ctx.lib.tqp_sort(ctx.h, _p(keys), _p(vals), n, _p(d_n), key_bits, _p(ko), _p(vo), ws, sz,
+                                         s), "tqp_sort", dev)
+    return ko[:n], (vo[:n] if vo is not None else None)
+
+
+def join(ctx: Context, lkey, rkey, lrow=None, rrow=None, cap: int | None = None, d_nl=None, d_nr=None,
+         stream=None):
+    """Sort-based equi-join of key-sorted inputs.  Returns (out_l, out_r, d_count)."""
+    nl, nr = lkey.numel(), rkey.numel()
+    cap = nl if cap is None else cap
+    dev = _dev(ctx)
+    ol = torch.empty(max(1, cap), dtype=torch.int32, device=dev)
+    orr = torch.empty(max(1, cap), dtype=torch.int32, device=dev)
+    cnt = torch.empty(1, dtype=torch.int64, device=dev)
+    s = _stream(stream)
+    _run(lambda ws, sz: ctx.lib.tqp_join(ctx.h, _p(lkey), _p(lrow), nl, _p(d_nl), _p(rkey), _p(rrow), nr, _p(d_nr),
+                                         _p(ol), _p(orr), cap, _p(cnt), ws, sz, s), "tqp_join", dev)
+    return ol, orr, cnt
+
+
+def groupby_agg(ctx: Context, gkey, sum_in, avg_in=None, key_bits: int = 0, gcap: int | None = None, d_n=None,
+                stream=None):
+    """Sort-based group-by: dict of device tensors key/sum/cnt/avg (capacity gcap) and d_ngroups."""
+    n = gkey.numel()
+    gcap = max(1, n) if gcap is None else gcap
+    dev = _dev(ctx)
+    out = {"key": torch.empty(max(1, gcap), dtype=torch.int32, device=dev),
+           "sum": torch.empty(max(1, gcap), dtype=torch.int64, device=dev),
+           "cnt": torch.empty(max(1, gcap), dtype=torch.int64, device=dev),
+           "avg": torch.empty(max(1, gcap), dtype=torch.float64, device=dev) if avg_in is not None else None,
+           "d_ngroups": torch.empty(1, dtype=torch.int64, device=dev)}
+    s = _stream(stream)
+    _run(lambda ws, sz: ctx.lib.tqp_groupby_agg(ctx.h, _p(gkey), n, _p(d_n), key_bits, _p(sum_in), _p(avg_in),
+                                                _p(out["key"]), _p(out["sum"]), _p(out["cnt"]), _p(out["avg"]),
+                                                gcap, _p(out["d_ngroups"]), ws, sz, s), "tqp_groupby_agg", dev)
+    return out
+
+
+def topk(ctx: Context, key, sum_, cnt, k: int, d_n=None, stream=None):
+    """ORDER BY sum DESC, key ASC LIMIT k: dict of key/sum/cnt (capacity k) and d_k."""
+    n = key.numel()
+    dev = _dev(ctx)
+    out = {"key": torch.empty(k, dtype=torch.int32, device=dev), "sum": torch.empty(k, dtype=torch.int64, device=dev),
+           "cnt": torch.empty(k, dtype=torch.int64, device=dev), "d_k": torch.empty(1, dtype=torch.int32, device=dev)}
+    s = _stream(stream)
+    _run(lambda ws, sz: ctx.lib.tqp_topk(ctx.h, _p(key), _p(sum_), _p(cnt), n, _p(d_n), k, _p(out["key"]),
+                                         _p(out["sum"]), _p(out["cnt"]), _p(out["d_k"]), ws, sz, s), "tqp_topk", dev)
+    return out
+
+
+class FlagsFragmentRunner:
+    """Prepared flags fragment over device-resident columns: outputs and workspace are
+    allocated once; run() only launches."""
+
+    def __init__(self, ctx: Context, fact: dict, dim: dict, D: int, c: int, key_bits: int = 0,
+                 row0: int = 0, n_fact: int | None = None):
+        self.ctx = ctx
+        dev = _dev(ctx)
+        self.fact, self.dim = fact, dim
+        n_fact = fact["fk"].numel() - row0 if n_fact is None else n_fact
+        self.desc = _lib.FlagsFragment(fact["fk"].data_ptr(), fact["date"].data_ptr(), fact["price"].data_ptr(),
+                                       fact["disc"].data_ptr(), fact["flagA"].data_ptr(), fact["flagB"].data_ptr(),
+                                       row0, n_fact, dim["pk"].data_ptr(), dim["seg"].data_ptr(), dim["pk"].numel(),
+                                       D, c, key_bits, 0)
+        self.out = {"key": torch.empty(8, dtype=torch.int32, device=dev),
+                    "sum": torch.empty(8, dtype=torch.int64, device=dev),
+                    "cnt": torch.empty(8, dtype=torch.int64, device=dev),
+                    "avg": torch.empty(8, dtype=torch.float64, device=dev),
+                    "d_ngroups": torch.empty(1, dtype=torch.int64, device=dev),
+                    "d_join": torch.empty(1, dtype=torch.int64, device=dev)}
+        o = self.out
+        self.odesc = _lib.FlagsOut(o["key"].data_ptr(), o["sum"].data_ptr(), o["cnt"].data_ptr(), o["avg"].data_ptr(),
+                                   o["d_ngroups"].data_ptr(), o["d_join"].data_ptr())
+        sz = ctypes.c_size_t(0)
+        check(ctx.lib.tqp_fragment_flags(ctx.h, ctypes.byref(self.desc), ctypes.byref(self.odesc), None,
+                                         ctypes.byref(sz), None), "tqp_fragment_flags (size query)")
+        self.ws = torch.empty(max(256, sz.value), dtype=torch.uint8, device=dev)
+        self.ws_bytes = ctypes.c_size_t(sz.value)
+
+    def run(self, stream=None):
+        check(self.ctx.lib.tqp_fragment_flags(self.ctx.h, ctypes.byref(self.desc), ctypes.byref(self.odesc),
+                                              _p(self.ws), ctypes.byref(self.ws_bytes), _stream(stream)),
+              "tqp_fragment_flags")
+
+    def result(self) -> dict:
+        """Host copy of the result (synchronises)."""
+        o = {k: v.cpu() for k, v in self.out.items()}
+        G = int(o["d_ngroups"][0])
+        return {"key": o["key"][:G].numpy(), "sum": o["sum"][:G].numpy(), "cnt": o["cnt"][:G].numpy(),
+                "avg": o["avg"][:G].numpy(), "join_rows": int(o["d_join"][0])}
+
+
+class CustFragmentRunner:
+    """Prepared custkey fragment (join to the mid table, group by custkey, top-k)."""
+
+    def __init__(self, ctx: Context, fact: dict, mid: dict, D: int, k: int = 100, key_bits: int = 0,
+                 cust_bits: int = 0, gcap: int | None = None, join_cap: int | None = None):
+        self.ctx = ctx
+        dev = _dev(ctx)
+        self.fact, self.mid = fact, mid
+        n, m = fact["fk"].numel(), mid["pk"].numel()
+        join_cap = n if join_cap is None else join_cap
+        if gcap is None:
+            gcap = min(max(1, join_cap), 1 << (cust_bits if cust_bits else 31))
+        self.k = k
+        self.desc = _lib.CustFragment(fact["fk"].data_ptr(), fact["date"].data_ptr(), fact["price"].data_ptr(),
+                                      fact["disc"].data_ptr(), n, mid["pk"].data_ptr(), mid["custkey"].data_ptr(),
+                                      m, D, key_bits, cust_bits, k, join_cap)
+        self.out = {"key": torch.empty(gcap, dtype=torch.int32, device=dev),
+                    "sum": torch.empty(gcap, dtype=torch.int64, device=dev),
+                    "cnt": torch.empty(gcap, dtype=torch.int64, device=dev),
+                    "d_ngroups": torch.empty(1, dtype=torch.int64, device=dev),
+                    "d_join": torch.empty(1, dtype=torch.int64, device=dev),
+                    "top_key": torch.empty(k, dtype=torch.int32, device=dev),
+                    "top_sum": torch.empty(k, dtype=torch.int64, device=dev),
+                    "top_cnt": torch.empty(k, dtype=torch.int64, device=dev),
+                    "d_topk": torch.empty(1, dtype=torch.int32, device=dev)}
+        o = self.out
+        self.odesc = _lib.CustOut(o["key"].data_ptr(), o["sum"].data_ptr(), o["cnt"].data_ptr(), gcap,
+                                  o["d_ngroups"].data_ptr(), o["d_join"].data_ptr(), o["top_key"].data_ptr(),
+                                  o["top_sum"].data_ptr(), o["top_cnt"].data_ptr(), o["d_topk"].data_ptr())
+        sz = ctypes.c_size_t(0)
+        check(ctx.lib.tqp_fragment_cust(ctx.h, ctypes.byref(self.desc), ctypes.byref(self.odesc), None,
+                                        ctypes.byref(sz), None), "tqp_fragment_cust (size query)")
+        self.ws = torch.empty(max(256, sz.value), dtype=torch.uint8, device=dev)
+        self.ws_bytes = ctypes.c_size_t(sz.value)
+
+    def run(self, stream=None):
+        check(self.ctx.lib.tqp_fragment_cust(self.ctx.h, ctypes.byref(self.desc), ctypes.byref(self.odesc),
+                                             _p(self.ws), ctypes.byref(self.ws_bytes), _stream(stream)),
+              "tqp_fragment_cust")
+
+    def result(self, all_groups: bool = True) -> dict:
+        o = {k: v.cpu() for k, v in self.out.items()}
+        G = int(o["d_ngroups"][0])
+        kk = int(o["d_topk"][0])
+        r = {"groups": G, "join_rows": int(o["d_join"][0]), "top_key": o["top_key"][:kk].numpy(),
+             "top_sum": o["top_sum"][:kk].numpy(), "top_cnt": o["top_cnt"][:kk].numpy()}
+        if all_groups:
+            w = min(G, o["key"].numel())
+            r.update(key=o["key"][:w].numpy(), sum=o["sum"][:w].numpy(), cnt=o["cnt"][:w].numpy())
+        return r
+
+
+def to_device(table: dict, device="cuda") -> dict:
+    """Copy a dict of numpy columns to device tensors (the resident columnar layout)."""
+    return {k: torch.from_numpy(v).to(device) for k, v in table.items()}

@@ -1,0 +1,115 @@
+"""ctypes declarations of the C ABI in include/tqp.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO = os.path.join(HERE, "libtqp.so")
+
+c_i32, c_i64, c_u32, c_vp, c_int = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int
+c_size_p = ctypes.POINTER(ctypes.c_size_t)
+
+TQP_OK, TQP_ERR_INVALID, TQP_ERR_WORKSPACE, TQP_ERR_CAPACITY, TQP_ERR_HIP, TQP_ERR_UNSUPPORTED = range(6)
+STATUS_NAMES = {0: "TQP_OK", 1: "TQP_ERR_INVALID", 2: "TQP_ERR_WORKSPACE", 3: "TQP_ERR_CAPACITY",
+                4: "TQP_ERR_HIP", 5: "TQP_ERR_UNSUPPORTED"}
+TQP_I8, TQP_I32, TQP_I64 = 1, 2, 3
+TQP_LT, TQP_LE, TQP_GT, TQP_GE, TQP_EQ, TQP_NE = range(6)
+DEVERR_KEY_RANGE, DEVERR_SPIN, DEVERR_CAPACITY = 1, 2, 4
+
+
+class ProfEntry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 40), ("ms", ctypes.c_double)]
+
+
+class Column(ctypes.Structure):
+    _fields_ = [("data", c_vp), ("type", c_i32), ("reserved", c_i32)]
+
+
+class Pred(ctypes.Structure):
+    _fields_ = [("col", c_i32), ("op", c_i32), ("k", c_i64)]
+
+
+class FlagsFragment(ctypes.Structure):
+    _fields_ = [("fk", c_vp), ("date", c_vp), ("price", c_vp), ("disc", c_vp), ("flagA", c_vp),
+                ("flagB", c_vp), ("row0", c_i64), ("n_fact", c_i64), ("pk", c_vp), ("seg", c_vp),
+                ("n_dim", c_i64), ("D", c_i32), ("c", c_i32), ("key_bits", c_i32), ("reserved", c_i32)]
+
+
+class FlagsOut(ctypes.Structure):
+    _fields_ = [("key", c_vp), ("sum", c_vp), ("cnt", c_vp), ("avg", c_vp), ("d_ngroups", c_vp),
+                ("d_join", c_vp)]
+
+
+class CustFragment(ctypes.Structure):
+    _fields_ = [("fk", c_vp), ("date", c_vp), ("price", c_vp), ("disc", c_vp), ("n_fact", c_i64),
+                ("pk", c_vp), ("custkey", c_vp), ("n_mid", c_i64), ("D", c_i32), ("key_bits", c_i32),
+                ("cust_bits", c_i32), ("k", c_i32), ("join_cap", c_i64)]
+
+
+class CustOut(ctypes.Structure):
+    _fields_ = [("key", c_vp), ("sum", c_vp), ("cnt", c_vp), ("gcap", c_i64), ("d_ngroups", c_vp),
+                ("d_join", c_vp), ("top_key", c_vp), ("top_sum", c_vp), ("top_cnt", c_vp), ("d_topk", c_vp)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """The HIP library.  There is no fallback: without libtqp.so nothing runs."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(SO):
+        raise ImportError("libtqp.so is not built (run paper_2203_01877_amd.build.build()); "
+                          "the library has no CPU fallback")
+    lib = ctypes.CDLL(SO)
+    S = c_int  # tqp_status
+    lib.tqp_ctx_create.argtypes = [c_int, ctypes.POINTER(c_vp)]
+    lib.tqp_ctx_create.restype = S
+    lib.tqp_ctx_destroy.argtypes = [c_vp]
+    lib.tqp_ctx_destroy.restype = None
+    lib.tqp_last_error.argtypes = []
+    lib.tqp_last_error.restype = ctypes.c_char_p
+    lib.tqp_ctx_errors.argtypes = [c_vp, c_vp, ctypes.POINTER(c_u32), c_int]
+    lib.tqp_ctx_errors.restype = S
+    lib.tqp_ctx_set_digit_bits.argtypes = [c_vp, c_int]
+    lib.tqp_ctx_set_digit_bits.restype = S
+    lib.tqp_ctx_set_profiling.argtypes = [c_vp, c_int]
+    lib.tqp_ctx_set_profiling.restype = S
+    lib.tqp_ctx_profile_read.argtypes = [c_vp, c_vp, ctypes.POINTER(ProfEntry), c_int, ctypes.POINTER(c_int)]
+    lib.tqp_ctx_profile_read.restype = S
+    lib.tqp_filter.argtypes = [c_vp, ctypes.POINTER(Column), c_int, c_i64, ctypes.POINTER(Pred), c_int, c_vp,
+                               c_vp, c_vp, c_i64, c_vp, c_vp, c_size_p, c_vp]
+    lib.tqp_filter.restype = S
+    lib.tqp_sort.argtypes = [c_vp, c_vp, c_vp, c_i64, c_vp, c_int, c_vp, c_vp, c_vp, c_size_p, c_vp]
+    lib.tqp_sort.restype = S
+    lib.tqp_join.argtypes = [c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_i64, c_vp,
+                             c_vp, c_size_p, c_vp]
+    lib.tqp_join.restype = S
+    lib.tqp_groupby_agg.argtypes = [c_vp, c_vp, c_i64, c_vp, c_int, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i64,
+                                    c_vp, c_vp, c_size_p, c_vp]
+    lib.tqp_groupby_agg.restype = S
+    lib.tqp_topk.argtypes = [c_vp, c_vp, c_vp, c_vp, c_i64, c_vp, c_int, c_vp, c_vp, c_vp, c_vp, c_vp,
+                             c_size_p, c_vp]
+    lib.tqp_topk.restype = S
+    lib.tqp_fragment_flags.argtypes = [c_vp, ctypes.POINTER(FlagsFragment), ctypes.POINTER(FlagsOut), c_vp,
+                                       c_size_p, c_vp]
+    lib.tqp_fragment_flags.restype = S
+    lib.tqp_fragment_cust.argtypes = [c_vp, ctypes.POINTER(CustFragment), ctypes.POINTER(CustOut), c_vp,
+                                      c_size_p, c_vp]
+    lib.tqp_fragment_cust.restype = S
+    _lib = lib
+    return lib
+
+
+class TQPError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = load().tqp_last_error().decode(errors="replace")
+        super().__init__("%s: %s (%s)" % (where, STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+def check(status: int, where: str) -> None:
+    if status != TQP_OK:
+        raise TQPError(status, where)

@@ -1,0 +1,197 @@
+// Context, error reporting and small utility kernels of the C ABI.
+#include <cstring>
+#include <string>
+
+#include "host.hpp"
+#include "segreduce.hpp"
+#include "topk.hpp"
+
+namespace tqp {
+
+static thread_local char g_err[512] = "";
+
+tqp_status fail(tqp_status st, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+void clear_error() { g_err[0] = 0; }
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+__global__ void k_fill_u128(uint4* p, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const uint4 z = make_uint4(0, 0, 0, 0);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = z;
+}
+
+int prof_begin(tqp_ctx* c, hipStream_t s, const char* name) {
+    if (!c || !c->prof) return -1;
+    hipEvent_t ev[2];
+    for (int i = 0; i < 2; ++i) {
+        if (!c->pool.empty()) {
+            ev[i] = c->pool.back();
+            c->pool.pop_back();
+        } else if (hipEventCreate(&ev[i]) != hipSuccess) {
+            return -1;
+        }
+    }
+    if (hipEventRecord(ev[0], s) != hipSuccess) return -1;
+    c->recs.push_back({name, ev[0], ev[1]});
+    return (int)c->recs.size() - 1;
+}
+
+void prof_end(tqp_ctx* c, hipStream_t s, int idx) {
+    if (!c || idx < 0 || idx >= (int)c->recs.size()) return;
+    (void)hipEventRecord(c->recs[idx].b, s);
+}
+
+// Clears bytes (a multiple of 4) at p with a kernel (no memset node, so the
+// sequence stays safe to capture and replay as a graph).
+tqp_status fill_zero(void* p, size_t bytes, hipStream_t stream, tqp_ctx* ctx) {
+    if (bytes == 0) return TQP_OK;
+    const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+    if ((a & 15) == 0 && (bytes & 15) == 0) {
+        const int64_t n = (int64_t)(bytes / 16);
+        TQP_LAUNCH(ctx, stream, "fill",
+                   k_fill_u128<<<grid_for(n, 256 * 4, 2048), 256, 0, stream>>>(static_cast<uint4*>(p), n));
+    } else {
+        const int64_t n = (int64_t)(bytes / 4);
+        TQP_LAUNCH(ctx, stream, "fill",
+                   k_fill_u32<<<grid_for(n, 256 * 4, 2048), 256, 0, stream>>>(static_cast<uint32_t*>(p), n, 0u));
+    }
+    return TQP_OK;
+}
+
+__global__ void k_avg(const int64_t* sa, const int64_t* cnt, double* avg, const int64_t* d_ngroups,
+                      int64_t gcap) {
+    int64_t G = *d_ngroups;
+    if (G > gcap) G = gcap;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < G; g += stride)
+        avg[g] = (double)sa[g] / (double)cnt[g];
+}
+
+__global__ void k_topk_emit(const TopCand* c, int k, const int64_t* gcnt, int32_t* out_key,
+                            int64_t* out_sum, int64_t* out_cnt, int32_t* d_k) {
+    __shared__ int s_n;
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < k; i += blockDim.x) {
+        const TopCand x = c[i];
+        if (x.idx >= 0) {
+            out_key[i] = x.key;
+            out_sum[i] = x.sum;
+            out_cnt[i] = gcnt[x.idx];
+            atomicAdd(&s_n, 1);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *d_k = s_n;
+}
+
+}  // namespace tqp
+
+using namespace tqp;
+
+extern "C" {
+
+const char* tqp_last_error(void) { return g_err; }
+
+tqp_status tqp_ctx_create(int device, tqp_ctx** out) {
+    clear_error();
+    if (!out) return fail(TQP_ERR_INVALID, "out is null");
+    int ndev = 0;
+    TQP_TRY_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(TQP_ERR_INVALID, "device %d of %d", device, ndev);
+    TQP_TRY_HIP(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    TQP_TRY_HIP(hipGetDeviceProperties(&prop, device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(TQP_ERR_UNSUPPORTED, "built for gfx950, device is %s", prop.gcnArchName);
+    tqp_ctx* c = new tqp_ctx;
+    c->device = device;
+    c->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    if (hipMalloc(&c->d_err, 256) != hipSuccess) {
+        delete c;
+        return fail(TQP_ERR_HIP, "hipMalloc of the error word failed");
+    }
+    if (hipMemset(c->d_err, 0, 256) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        (void)hipFree(c->d_err);
+        delete c;
+        return fail(TQP_ERR_HIP, "clearing the error word failed");
+    }
+    *out = c;
+    return TQP_OK;
+}
+
+void tqp_ctx_destroy(tqp_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto& r : ctx->recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : ctx->pool) (void)hipEventDestroy(e);
+    (void)hipFree(ctx->d_err);
+    delete ctx;
+}
+
+tqp_status tqp_ctx_set_profiling(tqp_ctx* ctx, int on) {
+    clear_error();
+    if (!ctx) return fail(TQP_ERR_INVALID, "null context");
+    ctx->prof = on != 0;
+    return TQP_OK;
+}
+
+tqp_status tqp_ctx_profile_read(tqp_ctx* ctx, hipStream_t stream, tqp_prof_entry* out, int cap, int* n) {
+    clear_error();
+    if (!ctx || !n || (cap > 0 && !out)) return fail(TQP_ERR_INVALID, "null argument");
+    TQP_TRY_HIP(hipStreamSynchronize(stream));
+    TQP_TRY_HIP(hipDeviceSynchronize());
+    int w = 0;
+    for (auto& r : ctx->recs) {
+        if (w < cap) {
+            float ms = 0.f;
+            TQP_TRY_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+            std::snprintf(out[w].name, sizeof out[w].name, "%s", r.name);
+            out[w].ms = ms;
+        }
+        ++w;
+        ctx->pool.push_back(r.a);
+        ctx->pool.push_back(r.b);
+    }
+    ctx->recs.clear();
+    *n = w;
+    return TQP_OK;
+}
+
+tqp_status tqp_ctx_errors(tqp_ctx* ctx, hipStream_t stream, uint32_t* errors, int clear) {
+    clear_error();
+    if (!ctx || !errors) return fail(TQP_ERR_INVALID, "null argument");
+    TQP_TRY_HIP(hipStreamSynchronize(stream));
+    TQP_TRY_HIP(hipMemcpy(errors, ctx->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    if (clear) {
+        TQP_TRY_HIP(hipMemset(ctx->d_err, 0, sizeof(uint32_t)));
+        TQP_TRY_HIP(hipDeviceSynchronize());
+    }
+    return TQP_OK;
+}
+
+tqp_status tqp_ctx_set_digit_bits(tqp_ctx* ctx, int bits) {
+    clear_error();
+    if (!ctx) return fail(TQP_ERR_INVALID, "null context");
+    if (bits == 0) bits = 8;
+    if (bits != 4 && bits != 8 && bits != 11) return fail(TQP_ERR_UNSUPPORTED, "digit width %d", bits);
+    ctx->digit_bits = bits;
+    return TQP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,234 @@
+// Device primitives for CDNA4 (gfx950): 64-lane wavefront ballots and scans,
+// agent-scope atomics for decoupled look-back, and small block-wide helpers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tqp {
+
+constexpr int WAVE = 64;
+
+// Error bits OR-ed into the context's device flag word by kernels.
+enum : uint32_t {
+    FLAG_KEY_RANGE = 1u,      // a key had bits above the declared key width (or was negative)
+    FLAG_SPIN_LIMIT = 2u,     // a look-back wait hit its bound (never expected)
+    FLAG_CAPACITY = 4u,       // an output count exceeded the caller's capacity
+};
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+__device__ __forceinline__ uint64_t lanemask_lt() { return (uint64_t(1) << lane_id()) - 1; }
+__device__ __forceinline__ uint64_t lanemask_le() {
+    return lane_id() == 63 ? ~uint64_t(0) : (uint64_t(2) << lane_id()) - 1;
+}
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ int popc64(uint64_t m) { return __popcll(m); }
+
+// ---------------------------------------------------------------- atomics
+template <class T>
+__device__ __forceinline__ T ld_relaxed(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ void st_relaxed(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ T atomic_add(T* p, T v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void set_flag(uint32_t* flags, uint32_t bit) {
+    if (flags) __hip_atomic_fetch_or(flags, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bound on look-back polls of one predecessor.  A predecessor always holds a
+// lower dynamic tile id, is already resident, and publishes without waiting on
+// its successors, so the wait ends; the bound only turns a bug into an error
+// flag instead of a hang.
+constexpr uint32_t SPIN_LIMIT = 1u << 22;
+
+// ---------------------------------------------------------------- wave scans
+template <class T>
+__device__ __forceinline__ T wave_incl_sum(T v) {
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        T u = __shfl_up(v, d, WAVE);
+        if (lane_id() >= d) v += u;
+    }
+    return v;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, WAVE);
+    return v;
+}
+
+// Segmented inclusive scan across the wave: a lane with head=true starts a
+// new segment.  Returns the running sum of the lane's segment up to the lane.
+template <class T>
+__device__ __forceinline__ T wave_seg_incl_sum(T v, uint64_t headmask) {
+    // distance back to the segment head (inclusive of own lane)
+    const int l = lane_id();
+    const uint64_t upto = headmask & lanemask_le();
+    const int seg_start = upto ? 63 - __clzll(upto) : 0;   // highest head at or below lane
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        T u = __shfl_up(v, d, WAVE);
+        if (l - d >= seg_start) v += u;
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------- block scans
+// Exclusive scan of one value per thread over the block; *total receives the
+// block sum.  lds must hold BLOCK/WAVE elements.
+template <int BLOCK, class T>
+__device__ __forceinline__ T block_excl_sum(T v, T* lds, T* total) {
+    constexpr int W = BLOCK / WAVE;
+    const int w = threadIdx.x / WAVE;
+    T inc = wave_incl_sum(v);
+    if (lane_id() == WAVE - 1) lds[w] = inc;
+    __syncthreads();
+    T wave_off = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+        T x = lds[i];
+        if (i < w) wave_off += x;
+        tot += x;
+    }
+    __syncthreads();
+    *total = tot;
+    return wave_off + inc - v;
+}
+
+// In-place exclusive scan of an LDS array of `count` elements (count a multiple
+// of BLOCK or smaller than BLOCK); returns the total.  scratch holds BLOCK/WAVE.
+template <int BLOCK, class T>
+__device__ __forceinline__ T block_excl_scan_array(T* arr, int count, T* scratch) {
+    const int per = (count + BLOCK - 1) / BLOCK;          // consecutive elements per thread
+    const int base = threadIdx.x * per;
+    T local = 0;
+    for (int i = 0; i < per; ++i)
+        if (base + i < count) local += arr[base + i];
+    T total;
+    T off = block_excl_sum<BLOCK>(local, scratch, &total);
+    for (int i = 0; i < per; ++i) {
+        if (base + i < count) {
+            T x = arr[base + i];
+            arr[base + i] = off;
+            off += x;
+        }
+    }
+    __syncthreads();
+    return total;
+}
+
+// ---------------------------------------------------------------- look-back (64-bit)
+// Status word of a tile in a single-value decoupled look-back: two flag bits
+// over a 62-bit non-negative value.
+constexpr uint64_t ST64_AGG = uint64_t(1) << 62;
+constexpr uint64_t ST64_INC = uint64_t(2) << 62;
+constexpr uint64_t ST64_VAL = (uint64_t(1) << 62) - 1;
+
+// Called by one thread: publishes the tile's aggregate, walks back over the
+// predecessors until an inclusive prefix is found, publishes its own
+// inclusive prefix and returns the exclusive one.
+__device__ __forceinline__ int64_t lookback64(uint64_t* status, int64_t tile, int64_t agg,
+                                              uint32_t* flags) {
+    if (tile == 0) {
+        st_relaxed(status, ST64_INC | (uint64_t)agg);
+        return 0;
+    }
+    st_relaxed(status + tile, ST64_AGG | (uint64_t)agg);
+    int64_t excl = 0;
+    int64_t j = tile - 1;
+    uint32_t spins = 0;
+    while (j >= 0) {
+        const uint64_t s = ld_relaxed(status + j);
+        const uint64_t f = s & ~ST64_VAL;
+        if (f == 0) {
+            if (++spins > SPIN_LIMIT) { set_flag(flags, FLAG_SPIN_LIMIT); break; }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        excl += (int64_t)(s & ST64_VAL);
+        if (f == ST64_INC) break;
+        --j;
+    }
+    st_relaxed(status + tile, ST64_INC | (uint64_t)(excl + agg));
+    return excl;
+}
+
+// ---------------------------------------------------------------- wave search
+// First index i in [0, n) with pred(a[i]) true, pred = (a[i] > key) when
+// upper, else (a[i] >= key); n if none.  a is sorted ascending.  The whole
+// wave takes part: each round probes 64 evenly spaced positions, so a search
+// over n elements takes about log64(n) dependent loads.
+__device__ __forceinline__ int64_t wave_bound(const uint32_t* a, int64_t n, uint32_t key, bool upper) {
+    int64_t lo = 0, hi = n;   // the answer lies in [lo, hi]
+    const int l = lane_id();
+    while (lo < hi) {
+        const int64_t span = hi - lo;
+        const int64_t step = (span + WAVE - 1) / WAVE;
+        const int64_t p = lo + (int64_t)l * step;
+        bool t = true;
+        if (p < hi) {
+            const uint32_t x = a[p];
+            t = upper ? (x > key) : (x >= key);
+        }
+        const uint64_t m = ballot(t);
+        if (m == 0) {
+            lo = lo + (int64_t)(WAVE - 1) * step + 1;
+        } else {
+            const int f = __ffsll((unsigned long long)m) - 1;
+            const int64_t first_true = lo + (int64_t)f * step;
+            if (f == 0) {
+                hi = lo;
+            } else {
+                lo = lo + (int64_t)(f - 1) * step + 1;
+                hi = first_true < hi ? first_true : hi;
+            }
+        }
+    }
+    return lo;
+}
+
+// Plain binary searches (one thread).
+template <class T>
+__device__ __forceinline__ int lower_bound_lds(const T* a, int n, T key) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (a[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+template <class T>
+__device__ __forceinline__ int upper_bound_lds(const T* a, int n, T key) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (a[mid] <= key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+__device__ __forceinline__ int64_t lower_bound_glb(const uint32_t* a, int64_t lo, int64_t hi, uint32_t key) {
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (a[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+__device__ __forceinline__ int64_t upper_bound_glb(const uint32_t* a, int64_t lo, int64_t hi, uint32_t key) {
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (a[mid] <= key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------- fill
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v);
+
+}  // namespace tqp

@@ -1,0 +1,226 @@
+// Whole fragments: filter -> sort-based join -> group-by in one launch
+// sequence, every intermediate in the workspace, no host synchronisation.
+#include "fragment.hpp"
+
+namespace tqp {
+
+// Groups of the flags fragment in ascending packed-key order, skipping
+// packed keys no row reached (SQL emits no empty group).
+__global__ void k_flags_finalize(const int64_t* acc, const int64_t* d_join_in, tqp_flags_out o) {
+    if (threadIdx.x != 0) return;
+    int64_t g = 0;
+    for (int k = 0; k < 8; ++k) {
+        const int64_t s = acc[k * 3], c = acc[k * 3 + 1], p = acc[k * 3 + 2];
+        if (c == 0) continue;
+        o.key[g] = k;
+        o.sum[g] = s;
+        o.cnt[g] = c;
+        o.avg[g] = (double)p / (double)c;
+        ++g;
+    }
+    *o.d_ngroups = g;
+    if (o.d_join) *o.d_join = *d_join_in;
+}
+
+template <class Cfg>
+void flags_reserve(Arena& a, const tqp_flags_fragment& f, FlagsBufs<Cfg>& b) {
+    const int kb = norm_key_bits(f.key_bits);
+    b.fact = radix_reserve<Cfg, uint32_t>(a, f.n_fact, kb);
+    b.dim = radix_reserve<Cfg, uint32_t>(a, f.n_dim, kb);
+    b.jstatus = a.zero<uint64_t>((f.n_fact + JCfgFrag::TILE - 1) / JCfgFrag::TILE);
+    b.jcounter = a.zero<uint32_t>(1);
+    b.d_join = a.zero<int64_t>(1);
+    b.acc = a.zero<int64_t>(24);
+    b.fkeys = a.scratch<uint32_t>(f.n_fact);
+    b.fvals = a.scratch<uint32_t>(f.n_fact);
+    b.dkeys = a.scratch<uint32_t>(f.n_dim);
+    b.dvals = a.scratch<uint32_t>(f.n_dim);
+}
+
+template <class Cfg>
+tqp_status flags_launch(tqp_ctx* ctx, const tqp_flags_fragment& f, const tqp_flags_out& o,
+                        const FlagsBufs<Cfg>& b, hipStream_t s) {
+    const int kb = norm_key_bits(f.key_bits);
+    const uint32_t mask = key_mask_for(kb);
+    tqp_status st;
+    // fact side: date < D fused into the sort, payload = global fact row id
+    SrcFilterRowid<int32_t> fsrc{f.fk + f.row0, f.date + f.row0, CMP_LT, f.D, f.n_fact, f.row0};
+    if ((st = radix_launch<Cfg, uint32_t>(b.fact, fsrc, f.n_fact, true, nullptr, mask, b.fkeys, b.fvals, ctx,
+                                          s)) != TQP_OK)
+        return st;
+    // dim side: seg == c fused into the sort, payload = dim row id
+    SrcFilterRowid<int8_t> dsrc{f.pk, f.seg, CMP_EQ, f.c, f.n_dim, 0};
+    if ((st = radix_launch<Cfg, uint32_t>(b.dim, dsrc, f.n_dim, true, nullptr, mask, b.dkeys, b.dvals, ctx,
+                                          s)) != TQP_OK)
+        return st;
+    // join + gather + direct aggregation over the six packed groups
+    EmitFlagsAgg<JCfgFrag::BLOCK> e{};
+    e.price = f.price;
+    e.disc = f.disc;
+    e.flagA = f.flagA;
+    e.flagB = f.flagB;
+    e.acc = b.acc;
+    const int64_t tiles = (f.n_fact + JCfgFrag::TILE - 1) / JCfgFrag::TILE;
+    const int grid = grid_for(tiles, 1, (int64_t)ctx->num_cus * 3);
+    TQP_LAUNCH(ctx, s, "join_flags_agg",
+               k_join<JCfgFrag, uint32_t, uint32_t, EmitFlagsAgg<JCfgFrag::BLOCK>><<<grid, JCfgFrag::BLOCK, 0, s>>>(
+                   b.fkeys, b.fvals, f.n_fact, b.fact.d_cnt, b.dkeys, (const uint32_t*)nullptr, f.n_dim,
+                   b.dim.d_cnt, b.jstatus, b.jcounter, b.d_join, INT64_MAX, e, ctx->d_err));
+    TQP_LAUNCH(ctx, s, "flags_finalize", k_flags_finalize<<<1, 64, 0, s>>>(b.acc, b.d_join, o));
+    return TQP_OK;
+}
+
+tqp_status check_flags(const tqp_flags_fragment* f, const tqp_flags_out* o) {
+    if (!f || !o) return fail(TQP_ERR_INVALID, "null fragment or output");
+    if (f->n_fact < 0 || f->n_dim < 0 || f->row0 < 0) return fail(TQP_ERR_INVALID, "negative size");
+    if (f->n_fact > MAX_ELEMS || f->n_dim > MAX_ELEMS) return fail(TQP_ERR_UNSUPPORTED, "fragment too large");
+    if (f->row0 + f->n_fact > (int64_t(1) << 31)) return fail(TQP_ERR_UNSUPPORTED, "fact row ids beyond int32");
+    if ((f->n_fact && (!f->fk || !f->date || !f->price || !f->disc || !f->flagA || !f->flagB)) ||
+        (f->n_dim && (!f->pk || !f->seg)))
+        return fail(TQP_ERR_INVALID, "null column");
+    if (!o->key || !o->sum || !o->cnt || !o->avg || !o->d_ngroups) return fail(TQP_ERR_INVALID, "null output");
+    return TQP_OK;
+}
+
+template <class Cfg>
+void cust_reserve(Arena& a, const tqp_cust_fragment& f, const tqp_cust_out& o, CustBufs<Cfg>& b) {
+    const int kb = norm_key_bits(f.key_bits);
+    const int cb = norm_key_bits(f.cust_bits);
+    b.fact = radix_reserve<Cfg, uint64_t>(a, f.n_fact, kb);
+    b.mid = radix_reserve<Cfg, uint32_t>(a, f.n_mid, kb);
+    b.jstatus = a.zero<uint64_t>((f.n_fact + JCfgFrag::TILE - 1) / JCfgFrag::TILE);
+    b.jcounter = a.zero<uint32_t>(1);
+    b.d_join = a.zero<int64_t>(1);
+    b.grp = radix_reserve<Cfg, uint64_t>(a, f.join_cap, cb);
+    b.sstatus = a.zero<uint64_t>((f.join_cap + SCfgFrag::TILE - 1) / SCfgFrag::TILE);
+    b.scounter = a.zero<uint32_t>(1);
+    b.fkeys = a.scratch<uint32_t>(f.n_fact);
+    b.fvals = a.scratch<uint64_t>(f.n_fact);
+    b.mkeys = a.scratch<uint32_t>(f.n_mid);
+    b.mvals = a.scratch<uint32_t>(f.n_mid);
+    b.gkeys_in = a.scratch<uint32_t>(f.join_cap);
+    b.gvals_in = a.scratch<uint64_t>(f.join_cap);
+    b.gkeys = a.scratch<uint32_t>(f.join_cap);
+    b.gvals = a.scratch<uint64_t>(f.join_cap);
+    b.topk = topk_reserve(a, o.gcap, f.k);
+}
+
+template <class Cfg>
+tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_out& o, const CustBufs<Cfg>& b,
+                       hipStream_t s) {
+    const int kb = norm_key_bits(f.key_bits);
+    const int cb = norm_key_bits(f.cust_bits);
+    tqp_status st;
+    if ((st = fill_zero(o.sum, o.gcap * 8, s, ctx)) != TQP_OK) return st;
+    if ((st = fill_zero(o.cnt, o.gcap * 8, s, ctx)) != TQP_OK) return st;
+    // fact side: date < D fused into the sort; the payload is the revenue
+    // price * (100 - disc), evaluated while the row is read
+    SrcFilterRevenue fsrc{f.fk, f.date, f.price, f.disc, CMP_LT, f.D, f.n_fact};
+    if ((st = radix_launch<Cfg, uint64_t>(b.fact, fsrc, f.n_fact, true, nullptr, key_mask_for(kb), b.fkeys,
+                                          b.fvals, ctx, s)) != TQP_OK)
+        return st;
+    // mid side: (pk, custkey)
+    SrcKeyCol msrc{f.pk, f.custkey, f.n_mid};
+    if ((st = radix_launch<Cfg, uint32_t>(b.mid, msrc, f.n_mid, true, nullptr, key_mask_for(kb), b.mkeys,
+                                          b.mvals, ctx, s)) != TQP_OK)
+        return st;
+    // join: emits (custkey, revenue) and the digit histograms of custkey
+    using Emit = EmitKeyVal<JCfgFrag::BLOCK, Cfg::RADIX_BITS>;
+    Emit e{};
+    e.out_key = b.gkeys_in;
+    e.out_val = b.gvals_in;
+    e.cap = f.join_cap;
+    e.key_mask = key_mask_for(cb);
+    e.flags = ctx->d_err;
+    e.hist = b.grp.hist;
+    e.npass = b.grp.pd.npass;
+    for (int p = 0; p < b.grp.pd.npass && p < Emit::NP; ++p) {
+        e.shift[p] = b.grp.pd.shift[p];
+        e.bits[p] = b.grp.pd.bits[p];
+    }
+    const int64_t tiles = (f.n_fact + JCfgFrag::TILE - 1) / JCfgFrag::TILE;
+    const int grid = grid_for(tiles, 1, (int64_t)ctx->num_cus * 3);
+    TQP_LAUNCH(ctx, s, "join_keyval",
+               k_join<JCfgFrag, uint64_t, uint32_t, Emit><<<grid, JCfgFrag::BLOCK, 0, s>>>(
+                   b.fkeys, b.fvals, f.n_fact, b.fact.d_cnt, b.mkeys, b.mvals, f.n_mid, (const int64_t*)nullptr,
+                   b.jstatus, b.jcounter, b.d_join, f.join_cap, e, ctx->d_err));
+    // group-by: sort (custkey, revenue) by custkey, then reduce runs
+    SrcPairs<uint64_t> gsrc{b.gkeys_in, b.gvals_in, f.join_cap, b.d_join};
+    if ((st = radix_launch<Cfg, uint64_t>(b.grp, gsrc, f.join_cap, false, b.d_join, key_mask_for(cb), b.gkeys,
+                                          b.gvals, ctx, s)) != TQP_OK)
+        return st;
+    ValsDirect vs{reinterpret_cast<const int64_t*>(b.gvals), nullptr};
+    SegOut so{o.key, o.sum, o.cnt, nullptr, o.gcap, o.d_ngroups};
+    TQP_LAUNCH(ctx, s, "segreduce",
+               k_segreduce<SCfgFrag, ValsDirect><<<grid_for(f.join_cap, SCfgFrag::TILE, 0), SCfgFrag::BLOCK, 0, s>>>(
+                   b.gkeys, vs, f.join_cap, b.d_join, b.sstatus, b.scounter, so, ctx->d_err));
+    // ORDER BY sum DESC, custkey ASC LIMIT k
+    if ((st = topk_launch(b.topk, o.key, o.sum, o.cnt, o.d_ngroups, f.k, o.top_key, o.top_sum, o.top_cnt,
+                          o.d_topk, s, ctx)) != TQP_OK)
+        return st;
+    if (o.d_join) {
+        TQP_LAUNCH(ctx, s, "copy_count", k_copy_i64<<<1, 64, 0, s>>>(b.d_join, o.d_join));
+    }
+    return TQP_OK;
+}
+
+__global__ void k_copy_i64(const int64_t* src, int64_t* dst) {
+    if (threadIdx.x == 0) *dst = *src;
+}
+
+tqp_status check_cust(const tqp_cust_fragment* f, const tqp_cust_out* o) {
+    if (!f || !o) return fail(TQP_ERR_INVALID, "null fragment or output");
+    if (f->n_fact < 0 || f->n_mid < 0 || f->join_cap < 0 || o->gcap < 0) return fail(TQP_ERR_INVALID, "negative size");
+    if (f->n_fact > MAX_ELEMS || f->n_mid > MAX_ELEMS || f->join_cap > MAX_ELEMS || o->gcap > MAX_ELEMS)
+        return fail(TQP_ERR_UNSUPPORTED, "fragment too large");
+    if (f->k < 1 || f->k > 1024) return fail(TQP_ERR_UNSUPPORTED, "k = %d", f->k);
+    if ((f->n_fact && (!f->fk || !f->date || !f->price || !f->disc)) || (f->n_mid && (!f->pk || !f->custkey)))
+        return fail(TQP_ERR_INVALID, "null column");
+    if (!o->key || !o->sum || !o->cnt || !o->d_ngroups || !o->top_key || !o->top_sum || !o->top_cnt || !o->d_topk)
+        return fail(TQP_ERR_INVALID, "null output");
+    return TQP_OK;
+}
+
+}  // namespace tqp
+
+using namespace tqp;
+
+extern "C" {
+
+tqp_status tqp_fragment_flags(tqp_ctx* ctx, const tqp_flags_fragment* f, const tqp_flags_out* o, void* ws,
+                              size_t* ws_bytes, hipStream_t stream) {
+    clear_error();
+    if (!ctx) return fail(TQP_ERR_INVALID, "null context");
+    tqp_status st = check_flags(f, o);
+    if (st != TQP_OK) return st;
+    return with_radix_cfg(ctx->digit_bits, [&](auto cfg) -> tqp_status {
+        using Cfg = decltype(cfg);
+        FlagsBufs<Cfg> b;
+        Arena a;
+        auto plan = [&](Arena& ar) { flags_reserve<Cfg>(ar, *f, b); };
+        tqp_status s2 = with_workspace(ctx, ws, ws_bytes, stream, plan, a);
+        if (s2 != TQP_OK || !ws) return s2;
+        if ((s2 = fill_zero(a.base, a.zsize, stream, ctx)) != TQP_OK) return s2;
+        return flags_launch<Cfg>(ctx, *f, *o, b, stream);
+    });
+}
+
+tqp_status tqp_fragment_cust(tqp_ctx* ctx, const tqp_cust_fragment* f, const tqp_cust_out* o, void* ws,
+                             size_t* ws_bytes, hipStream_t stream) {
+    clear_error();
+    if (!ctx) return fail(TQP_ERR_INVALID, "null context");
+    tqp_status st = check_cust(f, o);
+    if (st != TQP_OK) return st;
+    return with_radix_cfg(ctx->digit_bits, [&](auto cfg) -> tqp_status {
+        using Cfg = decltype(cfg);
+        CustBufs<Cfg> b;
+        Arena a;
+        auto plan = [&](Arena& ar) { cust_reserve<Cfg>(ar, *f, *o, b); };
+        tqp_status s2 = with_workspace(ctx, ws, ws_bytes, stream, plan, a);
+        if (s2 != TQP_OK || !ws) return s2;
+        if ((s2 = fill_zero(a.base, a.zsize, stream, ctx)) != TQP_OK) return s2;
+        return cust_launch<Cfg>(ctx, *f, *o, b, stream);
+    });
+}
+
+}  // extern "C"

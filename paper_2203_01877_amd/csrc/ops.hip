@@ -1,0 +1,236 @@
+// C ABI of the single operators: filter, sort, join, group-by, top-k.
+#include "filter.hpp"
+#include "fragment.hpp"
+#include "host.hpp"
+#include "join.hpp"
+#include "radix.hpp"
+#include "segreduce.hpp"
+#include "topk.hpp"
+
+namespace tqp {
+
+using JCfg = JoinCfg<256, 4, 4096>;
+using SCfg = SegCfg<256, 16>;
+constexpr int FILTER_BLOCK = 256, FILTER_ITEMS = 16;
+constexpr int TOPK_BLOCK = 256, TOPK_CH = 2048;
+
+// ---------------------------------------------------------------- top-k plan
+// Level l reads n_in[l] candidates (level 0: the groups) in chunks of CH and
+// writes k per chunk; the last level has one chunk.
+TopkBufs topk_reserve(Arena& a, int64_t n_upper, int k) {
+    TopkBufs t;
+    int64_t n = n_upper < 1 ? 1 : n_upper;
+    for (int l = 0; l < TOPK_MAX_LEVELS; ++l) {
+        t.n_in[l] = l == 0 ? n_upper : n;
+        t.blocks[l] = (n + TOPK_CH - 1) / TOPK_CH;
+        t.cand[l] = a.scratch<TopCand>(t.blocks[l] * k);
+        t.levels = l + 1;
+        if (t.blocks[l] == 1) break;
+        n = t.blocks[l] * k;
+    }
+    return t;
+}
+
+tqp_status topk_launch(const TopkBufs& t, const int32_t* key, const int64_t* sum, const int64_t* cnt,
+                       const int64_t* d_n, int k, int32_t* out_key, int64_t* out_sum, int64_t* out_cnt,
+                       int32_t* d_k, hipStream_t s, tqp_ctx* ctx) {
+    for (int l = 0; l < t.levels; ++l) {
+        TQP_LAUNCH(ctx, s, "topk_level",
+                   k_topk_level<TOPK_BLOCK, TOPK_CH><<<(unsigned)t.blocks[l], TOPK_BLOCK, 0, s>>>(
+                       key, sum, t.n_in[l], l == 0 ? d_n : nullptr, l == 0 ? nullptr : t.cand[l - 1], t.cand[l], k));
+    }
+    TQP_LAUNCH(ctx, s, "topk_emit",
+               k_topk_emit<<<1, 256, 0, s>>>(t.cand[t.levels - 1], k, cnt, out_key, out_sum, out_cnt, d_k));
+    return TQP_OK;
+}
+
+}  // namespace tqp
+
+using namespace tqp;
+
+extern "C" {
+
+tqp_status tqp_filter(tqp_ctx* ctx, const tqp_column* cols, int ncols, int64_t n, const tqp_pred* preds,
+                      int npreds, const int32_t* carry, int32_t* out_rowid, int32_t* out_carry, int64_t cap,
+                      int64_t* d_count, void* ws, size_t* ws_bytes, hipStream_t stream) {
+    clear_error();
+    if (!ctx || !d_count || (cap > 0 && !out_rowid) || n < 0 || cap < 0 || npreds < 0 || ncols < 0)
+        return fail(TQP_ERR_INVALID, "tqp_filter: null pointer or negative size");
+    if (n > MAX_ELEMS) return fail(TQP_ERR_UNSUPPORTED, "tqp_filter: n = %lld", (long long)n);
+    if (npreds > FILTER_MAX_PREDS) return fail(TQP_ERR_UNSUPPORTED, "tqp_filter: %d predicates", npreds);
+    if (n > 0 && cap > 0 && (carry == nullptr) != (out_carry == nullptr))
+        return fail(TQP_ERR_INVALID, "tqp_filter: carry and out_carry must both be given or both null");
+    if (n == 0 || cap == 0) { carry = nullptr; out_carry = nullptr; }
+    FilterPreds fp{};
+    fp.np = npreds;
+    for (int p = 0; p < npreds; ++p) {
+        const tqp_pred& q = preds[p];
+        if (q.col < 0 || q.col >= ncols || !cols || (n > 0 && !cols[q.col].data))
+            return fail(TQP_ERR_INVALID, "tqp_filter: predicate %d names column %d", p, q.col);
+        if (q.op < TQP_LT || q.op > TQP_NE) return fail(TQP_ERR_INVALID, "tqp_filter: op %d", q.op);
+        const int t = cols[q.col].type;
+        if (t != TQP_I8 && t != TQP_I32 && t != TQP_I64) return fail(TQP_ERR_INVALID, "tqp_filter: type %d", t);
+        fp.col[p] = cols[q.col].data;
+        fp.type[p] = t;
+        fp.op[p] = q.op;
+        fp.k[p] = q.k;
+    }
+    constexpr int TILE = FILTER_BLOCK * FILTER_ITEMS;
+    const int64_t tiles = (n + TILE - 1) / TILE;
+    uint64_t* status = nullptr;
+    uint32_t* counter = nullptr;
+    Arena a;
+    auto plan = [&](Arena& ar) {
+        status = ar.zero<uint64_t>(tiles);
+        counter = ar.zero<uint32_t>(1);
+    };
+    tqp_status st = with_workspace(ctx, ws, ws_bytes, stream, plan, a);
+    if (st != TQP_OK || !ws) return st;
+    if ((st = fill_zero(a.base, a.zsize, stream, ctx)) != TQP_OK) return st;
+    TQP_LAUNCH(ctx, stream, "filter",
+               k_filter<FILTER_BLOCK, FILTER_ITEMS><<<grid_for(n, TILE, 0), FILTER_BLOCK, 0, stream>>>(
+                   fp, n, carry, out_rowid, out_carry, cap, d_count, status, counter, ctx->d_err));
+    return TQP_OK;
+}
+
+tqp_status tqp_sort(tqp_ctx* ctx, const int32_t* keys, const int32_t* vals, int64_t n, const int64_t* d_n,
+                    int key_bits, int32_t* keys_out, int32_t* vals_out, void* ws, size_t* ws_bytes,
+                    hipStream_t stream) {
+    clear_error();
+    if (!ctx || n < 0 || (n > 0 && (!keys || !keys_out)))
+        return fail(TQP_ERR_INVALID, "tqp_sort: null pointer or n < 0");
+    if (n > 0 && vals && !vals_out) return fail(TQP_ERR_INVALID, "tqp_sort: vals given without vals_out");
+    if (n > MAX_ELEMS) return fail(TQP_ERR_UNSUPPORTED, "tqp_sort: n = %lld", (long long)n);
+    const int kb = norm_key_bits(key_bits);
+    const uint32_t mask = key_mask_for(kb);
+    return with_radix_cfg(ctx->digit_bits, [&](auto cfg) -> tqp_status {
+        using Cfg = decltype(cfg);
+        Arena a;
+        tqp_status st;
+        if (vals_out) {
+            RadixBufs<Cfg, uint32_t> b;
+            auto plan = [&](Arena& ar) { b = radix_reserve<Cfg, uint32_t>(ar, n, kb); };
+            st = with_workspace(ctx, ws, ws_bytes, stream, plan, a);
+            if (st != TQP_OK || !ws) return st;
+            if ((st = fill_zero(a.base, a.zsize, stream, ctx)) != TQP_OK) return st;
+            SrcPairs<uint32_t> src{reinterpret_cast<const uint32_t*>(keys),
+                                   reinterpret_cast<const uint32_t*>(vals), n, d_n};
+            return radix_launch<Cfg, uint32_t>(b, src, n, true, nullptr, mask,
+                                               reinterpret_cast<uint32_t*>(keys_out),
+                                               reinterpret_cast<uint32_t*>(vals_out), ctx, stream);
+        }
+        RadixBufs<Cfg, NoVal> b;
+        auto plan = [&](Arena& ar) { b = radix_reserve<Cfg, NoVal>(ar, n, kb); };
+        st = with_workspace(ctx, ws, ws_bytes, stream, plan, a);
+        if (st != TQP_OK || !ws) return st;
+        if ((st = fill_zero(a.base, a.zsize, stream, ctx)) != TQP_OK) return st;
+        SrcPairs<NoVal> src{reinterpret_cast<const uint32_t*>(keys), nullptr, n, d_n};
+        return radix_launch<Cfg, NoVal>(b, src, n, true, nullptr, mask, reinterpret_cast<uint32_t*>(keys_out),
+                                        nullptr, ctx, stream);
+    });
+}
+
+tqp_status tqp_join(tqp_ctx* ctx, const int32_t* lkey, const int32_t* lrow, int64_t nl, const int64_t* d_nl,
+                    const int32_t* rkey, const int32_t* rrow, int64_t nr, const int64_t* d_nr, int32_t* out_l,
+                    int32_t* out_r, int64_t cap, int64_t* d_count, void* ws, size_t* ws_bytes,
+                    hipStream_t stream) {
+    clear_error();
+    if (!ctx || !d_count || nl < 0 || nr < 0 || cap < 0 || (nl > 0 && !lkey) || (nr > 0 && !rkey) ||
+        (cap > 0 && (!out_l || !out_r)))
+        return fail(TQP_ERR_INVALID, "tqp_join: null pointer or negative size");
+    if (nl > MAX_ELEMS || nr > MAX_ELEMS) return fail(TQP_ERR_UNSUPPORTED, "tqp_join: input too large");
+    const int64_t tiles = (nl + JCfg::TILE - 1) / JCfg::TILE;
+    uint64_t* status = nullptr;
+    uint32_t* counter = nullptr;
+    Arena a;
+    auto plan = [&](Arena& ar) {
+        status = ar.zero<uint64_t>(tiles);
+        counter = ar.zero<uint32_t>(1);
+    };
+    tqp_status st = with_workspace(ctx, ws, ws_bytes, stream, plan, a);
+    if (st != TQP_OK || !ws) return st;
+    if ((st = fill_zero(a.base, a.zsize, stream, ctx)) != TQP_OK) return st;
+    EmitPairs e{out_l, out_r, cap};
+    const int grid = grid_for(tiles, 1, (int64_t)ctx->num_cus * 3);
+    TQP_LAUNCH(ctx, stream, "join_pairs",
+               k_join<JCfg, uint32_t, uint32_t, EmitPairs><<<grid, JCfg::BLOCK, 0, stream>>>(
+                   reinterpret_cast<const uint32_t*>(lkey), reinterpret_cast<const uint32_t*>(lrow), nl, d_nl,
+                   reinterpret_cast<const uint32_t*>(rkey), reinterpret_cast<const uint32_t*>(rrow), nr, d_nr,
+                   status, counter, d_count, cap, e, ctx->d_err));
+    return TQP_OK;
+}
+
+tqp_status tqp_groupby_agg(tqp_ctx* ctx, const int32_t* gkey, int64_t n, const int64_t* d_n, int key_bits,
+                           const int64_t* sum_in, const int64_t* avg_in, int32_t* out_key, int64_t* out_sum,
+                           int64_t* out_cnt, double* out_avg, int64_t gcap, int64_t* d_ngroups, void* ws,
+                           size_t* ws_bytes, hipStream_t stream) {
+    clear_error();
+    if (!ctx || !d_ngroups || n < 0 || gcap < 0 || (n > 0 && (!gkey || !sum_in)) ||
+        (gcap > 0 && (!out_key || !out_sum || !out_cnt)))
+        return fail(TQP_ERR_INVALID, "tqp_groupby_agg: null pointer or negative size");
+    if (n == 0 && out_avg) avg_in = nullptr, out_avg = nullptr;
+    if ((avg_in == nullptr) != (out_avg == nullptr))
+        return fail(TQP_ERR_INVALID, "tqp_groupby_agg: avg_in and out_avg must both be given or both null");
+    if (n > MAX_ELEMS) return fail(TQP_ERR_UNSUPPORTED, "tqp_groupby_agg: n = %lld", (long long)n);
+    const int kb = norm_key_bits(key_bits);
+    const uint32_t mask = key_mask_for(kb);
+    return with_radix_cfg(ctx->digit_bits, [&](auto cfg) -> tqp_status {
+        using Cfg = decltype(cfg);
+        RadixBufs<Cfg, uint32_t> b;
+        uint32_t* skeys = nullptr;
+        uint32_t* perm = nullptr;
+        int64_t* sa = nullptr;
+        uint64_t* sstatus = nullptr;
+        uint32_t* scounter = nullptr;
+        const int64_t stiles = (n + SCfg::TILE - 1) / SCfg::TILE;
+        Arena a;
+        auto plan = [&](Arena& ar) {
+            b = radix_reserve<Cfg, uint32_t>(ar, n, kb);
+            sstatus = ar.zero<uint64_t>(stiles);
+            scounter = ar.zero<uint32_t>(1);
+            skeys = ar.scratch<uint32_t>(n);
+            perm = ar.scratch<uint32_t>(n);
+            sa = avg_in ? ar.scratch<int64_t>(gcap) : nullptr;
+        };
+        tqp_status st = with_workspace(ctx, ws, ws_bytes, stream, plan, a);
+        if (st != TQP_OK || !ws) return st;
+        if ((st = fill_zero(a.base, a.zsize, stream, ctx)) != TQP_OK) return st;
+        if ((st = fill_zero(out_sum, gcap * 8, stream, ctx)) != TQP_OK) return st;
+        if ((st = fill_zero(out_cnt, gcap * 8, stream, ctx)) != TQP_OK) return st;
+        if (sa && (st = fill_zero(sa, gcap * 8, stream, ctx)) != TQP_OK) return st;
+        // Algorithm 2: sort the keys and obtain the permutation (grpsInvIdx) ...
+        SrcPairs<uint32_t> src{reinterpret_cast<const uint32_t*>(gkey), nullptr, n, d_n};
+        st = radix_launch<Cfg, uint32_t>(b, src, n, true, nullptr, mask, skeys, perm, ctx, stream);
+        if (st != TQP_OK) return st;
+        // ... then runs of equal keys and their aggregates, values read through the permutation.
+        ValsGather vs{reinterpret_cast<const int32_t*>(perm), sum_in, avg_in};
+        SegOut o{out_key, out_sum, out_cnt, sa, gcap, d_ngroups};
+        TQP_LAUNCH(ctx, stream, "segreduce_gather",
+                   k_segreduce<SCfg, ValsGather><<<grid_for(n, SCfg::TILE, 0), SCfg::BLOCK, 0, stream>>>(
+                       skeys, vs, n, b.d_cnt, sstatus, scounter, o, ctx->d_err));
+        if (avg_in) {
+            TQP_LAUNCH(ctx, stream, "avg",
+                       k_avg<<<grid_for(gcap, 256 * 4, 1024), 256, 0, stream>>>(sa, out_cnt, out_avg, d_ngroups,
+                                                                                 gcap));
+        }
+        return TQP_OK;
+    });
+}
+
+tqp_status tqp_topk(tqp_ctx* ctx, const int32_t* key, const int64_t* sum, const int64_t* cnt, int64_t n,
+                    const int64_t* d_n, int k, int32_t* out_key, int64_t* out_sum, int64_t* out_cnt,
+                    int32_t* d_k, void* ws, size_t* ws_bytes, hipStream_t stream) {
+    clear_error();
+    if (!ctx || !out_key || !out_sum || !out_cnt || !d_k || n < 0 || (n > 0 && (!key || !sum || !cnt)))
+        return fail(TQP_ERR_INVALID, "tqp_topk: null pointer or n < 0");
+    if (k < 1 || k > 1024) return fail(TQP_ERR_UNSUPPORTED, "tqp_topk: k = %d", k);
+    if (n > MAX_ELEMS) return fail(TQP_ERR_UNSUPPORTED, "tqp_topk: n = %lld", (long long)n);
+    TopkBufs t;
+    Arena a;
+    auto plan = [&](Arena& ar) { t = topk_reserve(ar, n, k); };
+    tqp_status st = with_workspace(ctx, ws, ws_bytes, stream, plan, a);
+    if (st != TQP_OK || !ws) return st;
+    return topk_launch(t, key, sum, cnt, d_n, k, out_key, out_sum, out_cnt, d_k, stream, ctx);
+}
+
+}  // extern "C"

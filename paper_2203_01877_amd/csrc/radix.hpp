@@ -1,0 +1,377 @@
+// LSD radix sort of (key, payload) pairs: one histogram read for all digit
+// passes, then one "onesweep" kernel per pass that ranks a tile in LDS with
+// 64-lane ballots, finds its global digit offsets by decoupled look-back and
+// writes the tile out digit by digit.  Stable, ascending, key-width trimmed.
+//
+// The sort is the first step of the sort-based join (Algorithm 1: both key
+// columns are sorted with their row ids) and of the sort-based aggregation
+// (Algorithm 2: the packed group key is sorted, Section 5.4 names radix sort).
+#pragma once
+#include <type_traits>
+
+#include "dev.hpp"
+
+namespace tqp {
+
+struct NoVal {};
+
+// ------------------------------------------------------------------ sources
+// A source yields, for index i of its domain, whether the element takes part,
+// its key and its payload.  size() may depend on a device-side count.
+
+// Plain (key, value) arrays, optionally bounded by a device count.
+template <class V>
+struct SrcPairs {
+    const uint32_t* keys;
+    const V* vals;             // null: payload is the element index (V must be uint32_t)
+    int64_t n_upper;
+    const int64_t* d_n;
+    __device__ int64_t size() const {
+        if (!d_n) return n_upper;
+        int64_t n = *d_n;
+        return n < n_upper ? n : n_upper;
+    }
+    __device__ bool load_key(int64_t i, uint32_t& k) const {
+        k = keys[i];
+        return true;
+    }
+    __device__ bool load(int64_t i, uint32_t& k, V& v) const {
+        k = keys[i];
+        if (vals) v = vals[i];
+        else v = (V)i;
+        return true;
+    }
+};
+
+template <>
+struct SrcPairs<NoVal> {
+    const uint32_t* keys;
+    const NoVal* vals;
+    int64_t n_upper;
+    const int64_t* d_n;
+    __device__ int64_t size() const {
+        if (!d_n) return n_upper;
+        int64_t n = *d_n;
+        return n < n_upper ? n : n_upper;
+    }
+    __device__ bool load_key(int64_t i, uint32_t& k) const {
+        k = keys[i];
+        return true;
+    }
+    __device__ bool load(int64_t i, uint32_t& k, NoVal&) const {
+        k = keys[i];
+        return true;
+    }
+};
+
+// Predicate constants of a pushed-down comparison.
+enum CmpOp : int32_t { CMP_LT = 0, CMP_LE = 1, CMP_GT = 2, CMP_GE = 3, CMP_EQ = 4, CMP_NE = 5 };
+
+__device__ __forceinline__ bool cmp_eval(int64_t x, int32_t op, int64_t k) {
+    switch (op) {
+        case CMP_LT: return x < k;
+        case CMP_LE: return x <= k;
+        case CMP_GT: return x > k;
+        case CMP_GE: return x >= k;
+        case CMP_EQ: return x == k;
+        default: return x != k;
+    }
+}
+
+// key column + one filter column (date < D, seg == c ...), payload = row id.
+// This fuses the filter (Section 3.1: predicate -> selection) into the first
+// sort pass: rows that fail the predicate are never written.
+template <class FT>
+struct SrcFilterRowid {
+    const int32_t* key;
+    const FT* fcol;
+    int32_t op;
+    int64_t k;
+    int64_t n;
+    int64_t row0;              // row id offset (a fragment over a row range of a larger table)
+    __device__ int64_t size() const { return n; }
+    __device__ bool load_key(int64_t i, uint32_t& kk) const {
+        kk = (uint32_t)key[i];
+        return cmp_eval((int64_t)fcol[i], op, k);
+    }
+    __device__ bool load(int64_t i, uint32_t& kk, uint32_t& v) const {
+        kk = (uint32_t)key[i];
+        v = (uint32_t)(row0 + i);
+        return cmp_eval((int64_t)fcol[i], op, k);
+    }
+};
+
+// fact key + date filter, payload = price * (100 - disc) computed on the fly
+// (the revenue expression evaluated before the join instead of after it).
+struct SrcFilterRevenue {
+    const int32_t* key;
+    const int32_t* date;
+    const int64_t* price;
+    const int64_t* disc;
+    int32_t op;
+    int64_t k;
+    int64_t n;
+    __device__ int64_t size() const { return n; }
+    __device__ bool load_key(int64_t i, uint32_t& kk) const {
+        kk = (uint32_t)key[i];
+        return cmp_eval((int64_t)date[i], op, k);
+    }
+    __device__ bool load(int64_t i, uint32_t& kk, uint64_t& v) const {
+        kk = (uint32_t)key[i];
+        bool ok = cmp_eval((int64_t)date[i], op, k);
+        if (ok) v = (uint64_t)(price[i] * (100 - disc[i]));
+        return ok;
+    }
+};
+
+// key column + int32 payload column, no filter (the mid table side).
+struct SrcKeyCol {
+    const int32_t* key;
+    const int32_t* val;
+    int64_t n;
+    __device__ int64_t size() const { return n; }
+    __device__ bool load_key(int64_t i, uint32_t& kk) const {
+        kk = (uint32_t)key[i];
+        return true;
+    }
+    __device__ bool load(int64_t i, uint32_t& kk, uint32_t& v) const {
+        kk = (uint32_t)key[i];
+        v = (uint32_t)val[i];
+        return true;
+    }
+};
+
+// ------------------------------------------------------------------ sinks
+template <class V>
+struct DstPairs {
+    uint32_t* keys;
+    V* vals;
+    __device__ void store(int64_t i, uint32_t k, const V& v) const {
+        keys[i] = k;
+        vals[i] = v;
+    }
+};
+template <>
+struct DstPairs<NoVal> {
+    uint32_t* keys;
+    NoVal* vals;
+    __device__ void store(int64_t i, uint32_t k, const NoVal&) const { keys[i] = k; }
+};
+
+template <class V> struct ValBytes { static constexpr int value = sizeof(V); };
+template <> struct ValBytes<NoVal> { static constexpr int value = 0; };
+
+// ------------------------------------------------------------------ config
+template <int RB, int BLOCK_, int ITEMS_>
+struct RadixCfg {
+    static constexpr int RADIX_BITS = RB;
+    static constexpr int RADIX = 1 << RB;
+    static constexpr int BLOCK = BLOCK_;
+    static constexpr int ITEMS = ITEMS_;
+    static constexpr int TILE = BLOCK_ * ITEMS_;
+    static constexpr int WAVES = BLOCK_ / WAVE;
+    static constexpr int MAX_PASSES = (32 + RB - 1) / RB;
+};
+
+constexpr uint32_t ST_AGG = 1u << 30;       // tile aggregate published
+constexpr uint32_t ST_INC = 2u << 30;       // inclusive prefix published
+constexpr uint32_t ST_VAL = (1u << 30) - 1;
+
+struct PassDesc {
+    int32_t shift[8];
+    int32_t bits[8];
+    int32_t npass;
+};
+
+// ------------------------------------------------------------------ histogram
+// One read of the input: digit histograms of every pass (LDS-privatised, then
+// merged with one global atomic per bin and block), the number of elements
+// that take part, and the key-width check.
+template <class Cfg, class Src>
+__global__ void __launch_bounds__(Cfg::BLOCK)
+k_radix_hist(Src src, PassDesc pd, uint32_t key_mask, uint32_t* hist, int64_t* d_count,
+             uint32_t* flags) {
+    constexpr int R = Cfg::RADIX;
+    __shared__ uint32_t h[Cfg::MAX_PASSES * R];
+    __shared__ uint32_t s_cnt;
+    __shared__ uint32_t s_bad;
+    for (int i = threadIdx.x; i < pd.npass * R; i += Cfg::BLOCK) h[i] = 0;
+    if (threadIdx.x == 0) { s_cnt = 0; s_bad = 0; }
+    __syncthreads();
+    const int64_t n = src.size();
+    uint32_t cnt = 0, bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * Cfg::BLOCK + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * Cfg::BLOCK) {
+        uint32_t k;
+        if (!src.load_key(i, k)) continue;
+        ++cnt;
+        bad |= k & ~key_mask;
+        for (int p = 0; p < pd.npass; ++p) {
+            uint32_t d = (k >> pd.shift[p]) & ((1u << pd.bits[p]) - 1);
+            atomicAdd(&h[p * R + d], 1u);
+        }
+    }
+    cnt = wave_sum(cnt);
+    if (lane_id() == 0 && cnt) atomicAdd(&s_cnt, cnt);
+    if (bad) atomicOr(&s_bad, 1u);
+    __syncthreads();
+    for (int i = threadIdx.x; i < pd.npass * R; i += Cfg::BLOCK)
+        if (h[i]) atomic_add(&hist[i], h[i]);
+    if (threadIdx.x == 0) {
+        if (d_count && s_cnt) atomic_add(d_count, (int64_t)s_cnt);
+        if (s_bad) set_flag(flags, FLAG_KEY_RANGE);
+    }
+}
+
+// ------------------------------------------------------------------ one pass
+template <class Cfg, class V>
+struct PassSmem {
+    static constexpr int R = Cfg::RADIX;
+    uint32_t keys[Cfg::TILE];
+    typename std::conditional<ValBytes<V>::value == 0, char, V>::type
+        vals[ValBytes<V>::value == 0 ? 1 : Cfg::TILE];
+    uint32_t wave_hist[Cfg::WAVES][R];
+    uint32_t local_start[R];
+    int32_t delta[R];
+    uint32_t scratch[Cfg::WAVES];
+    uint32_t tile;
+};
+
+template <class Cfg, class Src, class V>
+__global__ void __launch_bounds__(Cfg::BLOCK)
+k_radix_pass(Src src, DstPairs<V> dst, int shift, int bits, const uint32_t* hist,
+             uint32_t* status, uint32_t* tile_counter, uint32_t* flags) {
+    constexpr int R = Cfg::RADIX, ITEMS = Cfg::ITEMS, TILE = Cfg::TILE, W = Cfg::WAVES;
+    __shared__ PassSmem<Cfg, V> sm;
+    const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
+
+    if (tid == 0) sm.tile = atomicAdd(tile_counter, 1u);
+    for (int i = tid; i < W * R; i += Cfg::BLOCK) (&sm.wave_hist[0][0])[i] = 0;
+    __syncthreads();
+    const uint32_t tile = sm.tile;
+    const int64_t n = src.size();
+    const int64_t ntiles = (n + TILE - 1) / TILE;
+    if ((int64_t)tile >= ntiles) return;
+    const uint32_t dmask = (1u << bits) - 1;
+
+    // Load: wave w owns the contiguous chunk [w*ITEMS*64, (w+1)*ITEMS*64) of the
+    // tile, item j of lane l is element chunk + j*64 + l (coalesced loads).
+    const int64_t base = (int64_t)tile * TILE + (int64_t)w * ITEMS * WAVE;
+    uint32_t key[ITEMS];
+    V val[ITEMS];
+    uint32_t rank[ITEMS];
+    bool valid[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        int64_t i = base + j * WAVE + l;
+        valid[j] = false;
+        if (i < n) valid[j] = src.load(i, key[j], val[j]);
+    }
+
+    // Rank: peers with the same digit found by one ballot per digit bit; the
+    // per-wave counter of the digit gives the rank of earlier items.
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t d = valid[j] ? (key[j] >> shift) & dmask : 0;
+        uint64_t peers = ballot(valid[j]);
+#pragma unroll
+        for (int b = 0; b < Cfg::RADIX_BITS; ++b) {
+            if (b < bits) {
+                const bool bit = (d >> b) & 1;
+                const uint64_t t = ballot(bit);
+                peers &= bit ? t : ~t;
+            }
+        }
+        if (valid[j]) {
+            const uint32_t before = sm.wave_hist[w][d];
+            const uint64_t lower = peers & lanemask_lt();
+            const int r = popc64(lower);
+            rank[j] = before + r;
+            if ((peers >> l) == 1) sm.wave_hist[w][d] = before + popc64(peers);   // last peer
+        }
+    }
+    __syncthreads();
+
+    // Per digit: exclusive prefix over waves, tile count, publish, look back.
+    for (int d = tid; d < R; d += Cfg::BLOCK) {
+        uint32_t run = 0;
+#pragma unroll
+        for (int ww = 0; ww < W; ++ww) {
+            uint32_t c = sm.wave_hist[ww][d];
+            sm.wave_hist[ww][d] = run;
+            run += c;
+        }
+        sm.local_start[d] = run;   // tile count for now; scanned below
+        if (d <= (int)dmask) {
+            uint32_t* st = status + (int64_t)tile * R + d;
+            if (tile == 0) {
+                st_relaxed(st, ST_INC | run);
+                sm.delta[d] = 0;
+            } else {
+                st_relaxed(st, ST_AGG | run);
+                uint32_t excl = 0;
+                int64_t j = (int64_t)tile - 1;
+                uint32_t spins = 0;
+                while (j >= 0) {
+                    uint32_t s = ld_relaxed(status + j * R + d);
+                    if ((s & ~ST_VAL) == 0) {
+                        if (++spins > SPIN_LIMIT) { set_flag(flags, FLAG_SPIN_LIMIT); break; }
+                        __builtin_amdgcn_s_sleep(1);
+                        continue;
+                    }
+                    excl += s & ST_VAL;
+                    if ((s & ~ST_VAL) == ST_INC) break;
+                    --j;
+                }
+                st_relaxed(st, ST_INC | (excl + run));
+                sm.delta[d] = (int32_t)excl;
+            }
+        }
+    }
+    __syncthreads();
+    // Tile-local digit starts (exclusive scan of the tile counts), then the
+    // global digit base (exclusive scan of this pass's histogram).
+    const uint32_t tile_total = block_excl_scan_array<Cfg::BLOCK>(sm.local_start, R, sm.scratch);
+    {
+        // digit base from the global histogram, computed per block
+        const int per = (R + Cfg::BLOCK - 1) / Cfg::BLOCK;
+        const int b0 = tid * per;
+        uint32_t loc = 0;
+        for (int i = 0; i < per; ++i)
+            if (b0 + i < R && b0 + i <= (int)dmask) loc += hist[b0 + i];
+        uint32_t tot;
+        uint32_t off = block_excl_sum<Cfg::BLOCK>(loc, sm.scratch, &tot);
+        for (int i = 0; i < per; ++i) {
+            int d = b0 + i;
+            if (d < R && d <= (int)dmask) {
+                sm.delta[d] = (int32_t)(off + (uint32_t)sm.delta[d]) - (int32_t)sm.local_start[d];
+                off += hist[d];
+            }
+        }
+    }
+    __syncthreads();
+
+    // Local scatter into LDS in digit order.
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        if (valid[j]) {
+            const uint32_t d = (key[j] >> shift) & dmask;
+            const uint32_t pos = sm.local_start[d] + sm.wave_hist[w][d] + rank[j];
+            sm.keys[pos] = key[j];
+            if constexpr (ValBytes<V>::value != 0) sm.vals[pos] = val[j];
+        }
+    }
+    __syncthreads();
+    // Coalesced write-out: consecutive LDS slots of one digit go to
+    // consecutive global positions.
+    const uint32_t count = tile_total;
+    for (uint32_t p = tid; p < count; p += Cfg::BLOCK) {
+        const uint32_t k = sm.keys[p];
+        const uint32_t d = (k >> shift) & dmask;
+        const int64_t g = (int64_t)p + sm.delta[d];
+        if constexpr (ValBytes<V>::value != 0) dst.store(g, k, sm.vals[p]);
+        else dst.store(g, k, NoVal{});
+    }
+}
+
+}  // namespace tqp

@@ -1,0 +1,177 @@
+// Sort-based group-by, second half (Section 5.4, Algorithm 2): over keys that
+// are already sorted, mark the first element of every run of equal keys
+// (uniqueConsecutive), number the runs (the inverse index) and reduce each
+// run's values: sum, count and the sum behind an average.
+//
+// Each wave walks a contiguous chunk of the tile 64 elements at a time: run
+// heads come from one ballot, the run number from a popcount plus the tile's
+// base (block scan + decoupled look-back over the head counts), the partial
+// sums from a segmented wave scan with the open run carried from one round to
+// the next.  A run that lies entirely inside one chunk is stored; the pieces of
+// a run cut by a chunk boundary are added atomically into zeroed outputs
+// (integer adds, so the result does not depend on their order).
+#pragma once
+#include "dev.hpp"
+
+namespace tqp {
+
+template <int BLOCK_, int ITEMS_>
+struct SegCfg {
+    static constexpr int BLOCK = BLOCK_;
+    static constexpr int ITEMS = ITEMS_;
+    static constexpr int TILE = BLOCK_ * ITEMS_;
+    static constexpr int WAVES = BLOCK_ / WAVE;
+};
+
+// Values stored next to the sorted keys.
+struct ValsDirect {
+    const int64_t* v;
+    const int64_t* a;          // nullable
+    __device__ void get(int64_t i, int64_t& x, int64_t& y) const {
+        x = v[i];
+        y = a ? a[i] : 0;
+    }
+};
+
+// Values reached through the sort permutation (Algorithm 2 permutes every
+// data column by the sorted order of the group keys).
+struct ValsGather {
+    const int32_t* perm;
+    const int64_t* v;
+    const int64_t* a;          // nullable
+    __device__ void get(int64_t i, int64_t& x, int64_t& y) const {
+        const int32_t r = perm[i];
+        x = v[r];
+        y = a ? a[r] : 0;
+    }
+};
+
+struct SegOut {
+    int32_t* key;
+    int64_t* sum;
+    int64_t* cnt;
+    int64_t* sa;               // nullable: sum of the averaged column
+    int64_t gcap;
+    int64_t* d_ngroups;
+};
+
+__device__ __forceinline__ void seg_flush(const SegOut& o, int64_t seg, int64_t v, int64_t c, int64_t a,
+                                          bool complete) {
+    if (seg < 0 || seg >= o.gcap) return;
+    if (complete) {
+        o.sum[seg] = v;
+        o.cnt[seg] = c;
+        if (o.sa) o.sa[seg] = a;
+    } else {
+        atomic_add(&o.sum[seg], v);
+        atomic_add(&o.cnt[seg], c);
+        if (o.sa) atomic_add(&o.sa[seg], a);
+    }
+}
+
+template <class Cfg, class VS>
+__global__ void __launch_bounds__(Cfg::BLOCK)
+k_segreduce(const uint32_t* keys, VS vs, int64_t n_upper, const int64_t* d_n, uint64_t* status,
+            uint32_t* tile_counter, SegOut out, uint32_t* flags) {
+    constexpr int ITEMS = Cfg::ITEMS, TILE = Cfg::TILE, W = Cfg::WAVES;
+    __shared__ int64_t s_scan[W];
+    __shared__ int64_t s_wave[W];
+    __shared__ int64_t s_base;
+    __shared__ uint32_t s_tile;
+    const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
+
+    int64_t n = n_upper;
+    if (d_n) { int64_t t = *d_n; n = t < n ? t : n; }
+    if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    const int64_t ntiles = (n + TILE - 1) / TILE;
+    if (tile >= ntiles) {
+        if (ntiles == 0 && tile == 0 && tid == 0) *out.d_ngroups = 0;
+        return;
+    }
+
+    const int64_t chunk = tile * TILE + (int64_t)w * ITEMS * WAVE;
+    uint32_t key[ITEMS];
+    uint64_t hm[ITEMS];
+    int64_t wave_heads = 0;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int64_t i = chunk + j * WAVE + l;
+        bool head = false;
+        key[j] = 0;
+        if (i < n) {
+            key[j] = keys[i];
+            head = (i == 0) || (keys[i - 1] != key[j]);
+        }
+        hm[j] = ballot(head);
+        wave_heads += popc64(hm[j]);
+    }
+    if (l == 0) s_wave[w] = wave_heads;
+    __syncthreads();
+    if (tid == 0) {
+        int64_t tot = 0;
+        for (int ww = 0; ww < W; ++ww) { int64_t x = s_wave[ww]; s_scan[ww] = tot; tot += x; }
+        const int64_t base = lookback64(status, tile, tot, flags);
+        s_base = base;
+        if (tile == ntiles - 1) {
+            *out.d_ngroups = base + tot;
+            if (base + tot > out.gcap) set_flag(flags, FLAG_CAPACITY);
+        }
+    }
+    __syncthreads();
+    const int64_t seg_base = s_base + s_scan[w];
+
+    int64_t open_v = 0, open_c = 0, open_a = 0, open_seg = -1;
+    bool has_open = false, open_here = false;
+    int64_t heads_so_far = 0;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int64_t i = chunk + j * WAVE + l;
+        const bool valid = i < n;
+        const uint64_t h = hm[j];
+        if (has_open && (h & 1)) {              // the open run ended at the previous round
+            if (l == 0) seg_flush(out, open_seg, open_v, open_c, open_a, open_here);
+            has_open = false;
+        }
+        const uint64_t upto = h & lanemask_le();
+        const int64_t seg = seg_base + heads_so_far + popc64(upto) - 1;
+        const bool head = (h >> l) & 1;
+        if (valid && head && seg < out.gcap) out.key[seg] = key[j];
+        int64_t v = 0, a = 0, c = 0;
+        if (valid) { vs.get(i, v, a); c = 1; }
+        v = wave_seg_incl_sum(v, h);
+        c = wave_seg_incl_sum(c, h);
+        a = wave_seg_incl_sum(a, h);
+        const bool cont = upto == 0;            // run began before this round
+        if (cont && has_open) { v += open_v; c += open_c; a += open_a; }
+        const bool here = cont ? (has_open && open_here) : true;
+        const bool last_global = valid && (i == n - 1);
+        const bool next_head = (l < WAVE - 1) && ((h >> (l + 1)) & 1);
+        if (valid && (next_head || last_global)) seg_flush(out, seg, v, c, a, here);
+        const int64_t i63 = chunk + j * WAVE + (WAVE - 1);
+        if (i63 < n - 1) {                      // lane 63 valid and not the global end: run stays open
+            open_v = __shfl(v, WAVE - 1, WAVE);
+            open_c = __shfl(c, WAVE - 1, WAVE);
+            open_a = __shfl(a, WAVE - 1, WAVE);
+            open_seg = __shfl(seg, WAVE - 1, WAVE);
+            open_here = __shfl((int)here, WAVE - 1, WAVE) != 0;
+            has_open = true;
+        } else {
+            has_open = false;
+        }
+        heads_so_far += popc64(h);
+    }
+    if (has_open) {                             // the chunk's last run may continue past it
+        const int64_t last = chunk + (int64_t)ITEMS * WAVE - 1;
+        const uint32_t lk = __shfl(key[ITEMS - 1], WAVE - 1, WAVE);
+        const bool ends = keys[last + 1] != lk;
+        if (l == 0) seg_flush(out, open_seg, open_v, open_c, open_a, open_here && ends);
+    }
+}
+
+// avg = (double)sum / (double)count, one IEEE division per group.
+__global__ void k_avg(const int64_t* sa, const int64_t* cnt, double* avg, const int64_t* d_ngroups,
+                      int64_t gcap);
+
+}  // namespace tqp

@@ -1,0 +1,188 @@
+"""HIP operators against the oracle, element by element, on the same seeded inputs.
+
+Sizes span several tiles and a ragged tail (tiles are 4096 rows for the
+filter, sort and group-by kernels, 1024 left rows for the join), plus the
+empty and one-element cases.  Integer and index outputs must match bit for
+bit; averages are one IEEE division of exact integers on both sides and must
+match bit for bit too.
+"""
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [0, 1, 63, 4095, 4096, 4097, 70_001, 300_007]
+
+
+def _rng(seed):
+    return np.random.default_rng(seed)
+
+
+@pytest.fixture(scope="module")
+def ctx(hip):
+    return hip.Context(0)
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _np(t, n=None):
+    a = t.cpu().numpy()
+    return a if n is None else a[:n]
+
+
+# ------------------------------------------------------------------ filter
+@pytest.mark.parametrize("n", SIZES)
+def test_filter_parity(hip, ctx, n):
+    rng = _rng(n + 1)
+    date = rng.integers(0, 2557, n).astype(np.int32)
+    seg = rng.integers(0, 5, n).astype(np.int8)
+    price = rng.integers(90_000, 10_500_000, n).astype(np.int64)
+    carry = rng.integers(-2**31, 2**31 - 1, n).astype(np.int32)
+    cols = [date, seg, price]
+    for preds in ([(0, oracle.LT, 2400)], [(0, oracle.LT, 2400), (1, oracle.EQ, 1)],
+                  [(2, oracle.GE, 5_000_000), (0, oracle.NE, 7), (1, oracle.LE, 2)], [(0, oracle.LT, 0)]):
+        want = oracle.filter_rows(cols, preds)
+        rows, cout, cnt = hip.filter(ctx, [_dev(c) for c in cols], preds, carry=_dev(carry))
+        k = int(_np(cnt)[0])
+        assert k == len(want)
+        assert np.array_equal(_np(rows, k), want)
+        assert np.array_equal(_np(cout, k), carry[want])
+    assert ctx.errors() == 0
+
+
+def test_filter_capacity(hip, ctx):
+    date = np.arange(10_000, dtype=np.int32) % 2557
+    rows, _, cnt = hip.filter(ctx, [_dev(date)], [(0, oracle.LT, 2400)], cap=1000)
+    want = oracle.filter_rows([date], [(0, oracle.LT, 2400)])
+    assert int(_np(cnt)[0]) == len(want)
+    assert np.array_equal(_np(rows, 1000), want[:1000])
+    assert ctx.errors() == hip.DEVERR_CAPACITY
+
+
+# ------------------------------------------------------------------ sort
+@pytest.mark.parametrize("digit_bits", [4, 8, 11])
+@pytest.mark.parametrize("key_bits", [1, 11, 18, 25, 31])
+@pytest.mark.parametrize("n", [0, 1, 4097, 300_007])
+def test_sort_parity(hip, ctx, digit_bits, key_bits, n):
+    rng = _rng(key_bits * 7 + n)
+    hi = min(2**key_bits, 2**31 - 1)
+    keys = rng.integers(0, hi, n).astype(np.int32)
+    if n > 10:
+        keys[: n // 3] = keys[0]          # long runs of one key
+    vals = rng.integers(-2**31, 2**31 - 1, n).astype(np.int32)
+    ctx.set_digit_bits(digit_bits)
+    try:
+        wk, wv = oracle.sort_pairs(keys, vals)
+        ko, vo = hip.sort(ctx, _dev(keys), _dev(vals), key_bits=key_bits)
+        assert np.array_equal(_np(ko), wk) and np.array_equal(_np(vo), wv)
+        wk2, perm = oracle.sort_pairs(keys)
+        ko, po = hip.sort(ctx, _dev(keys), key_bits=key_bits, perm=True)
+        assert np.array_equal(_np(ko), wk2) and np.array_equal(_np(po), perm)
+        ko, _ = hip.sort(ctx, _dev(keys), key_bits=key_bits)
+        assert np.array_equal(_np(ko), wk)
+    finally:
+        ctx.set_digit_bits(8)
+    assert ctx.errors() == 0
+
+
+def test_sort_device_count(hip, ctx):
+    import torch
+    rng = _rng(5)
+    keys = rng.integers(0, 1 << 20, 50_000).astype(np.int32)
+    d_n = torch.tensor([33_333], dtype=torch.int64, device="cuda")
+    ko, vo = hip.sort(ctx, _dev(keys), key_bits=20, perm=True, d_n=d_n)
+    wk, wp = oracle.sort_pairs(keys[:33_333])
+    assert np.array_equal(_np(ko, 33_333), wk) and np.array_equal(_np(vo, 33_333), wp)
+
+
+def test_sort_key_range_flag(hip, ctx):
+    keys = np.array([1, 2, 3, 1 << 12], dtype=np.int32)
+    hip.sort(ctx, _dev(keys), key_bits=12)
+    assert ctx.errors() & hip.DEVERR_KEY_RANGE
+
+
+# ------------------------------------------------------------------ join
+def _join_case(hip, ctx, lkey, rkey, cap=None):
+    lkey = np.sort(lkey).astype(np.int32)
+    rkey = np.sort(rkey).astype(np.int32)
+    rng = _rng(len(lkey) + 3 * len(rkey))
+    lrow = rng.permutation(max(1, len(lkey)))[: len(lkey)].astype(np.int32)
+    rrow = rng.permutation(max(1, len(rkey)))[: len(rkey)].astype(np.int32)
+    wl, wr, J = oracle.join(lkey, rkey, lrow, rrow, cap=cap)
+    ol, orr, cnt = hip.join(ctx, _dev(lkey), _dev(rkey), _dev(lrow), _dev(rrow),
+                            cap=cap if cap is not None else J)
+    assert int(_np(cnt)[0]) == J
+    w = len(wl)
+    assert np.array_equal(_np(ol, w), wl) and np.array_equal(_np(orr, w), wr)
+
+
+@pytest.mark.parametrize("nl,nr,hi", [(0, 10, 5), (10, 0, 5), (1, 1, 1), (5000, 300, 1500), (300_007, 40_000, 150_000),
+                                      (200_000, 150_000, 150_000), (4097, 5, 3), (20_000, 20_000, 1_000_000)])
+def test_join_parity(hip, ctx, nl, nr, hi):
+    rng = _rng(nl * 31 + nr)
+    _join_case(hip, ctx, rng.integers(0, hi, nl), rng.integers(0, hi, nr))
+    assert ctx.errors() == 0
+
+
+def test_join_pk_fk(hip, ctx):
+    rng = _rng(11)
+    pk = rng.permutation(100_000)
+    fk = rng.integers(0, 125_000, 400_000)
+    _join_case(hip, ctx, fk, pk)
+
+
+def test_join_one_key_everywhere(hip, ctx):
+    _join_case(hip, ctx, np.full(3000, 7), np.full(250, 7))     # J = 750,000 from one bucket
+
+
+def test_join_wide_window(hip, ctx):
+    # sparse left keys against a dense right side: each left tile spans far more
+    # right rows than the LDS window holds (global binary-search path)
+    rng = _rng(12)
+    _join_case(hip, ctx, rng.integers(0, 2_000_000, 3000), rng.integers(0, 2_000_000, 1_500_000))
+
+
+def test_join_capacity(hip, ctx):
+    rng = _rng(13)
+    _join_case(hip, ctx, rng.integers(0, 50, 20_000), rng.integers(0, 50, 2_000), cap=12_345)
+    assert ctx.errors() == hip.DEVERR_CAPACITY
+
+
+# ------------------------------------------------------------------ group-by
+@pytest.mark.parametrize("n,domain", [(0, 5), (1, 5), (4097, 1), (70_001, 6), (300_007, 5000),
+                                      (300_007, 1 << 20), (65_536, 65_536)])
+def test_groupby_parity(hip, ctx, n, domain):
+    rng = _rng(n + domain)
+    keys = rng.integers(0, domain, n).astype(np.int32)
+    val = rng.integers(0, 1_050_000_000, n).astype(np.int64)
+    price = rng.integers(90_000, 10_500_000, n).astype(np.int64)
+    wk, ws, wc, wa = oracle.groupby(keys, val, price)
+    kb = max(1, int(domain - 1).bit_length())
+    out = hip.groupby_agg(ctx, _dev(keys), _dev(val), _dev(price), key_bits=kb, gcap=max(1, len(wk)))
+    G = int(_np(out["d_ngroups"])[0])
+    assert G == len(wk)
+    assert np.array_equal(_np(out["key"], G), wk)
+    assert np.array_equal(_np(out["sum"], G), ws) and np.array_equal(_np(out["cnt"], G), wc)
+    assert np.array_equal(_np(out["avg"], G).view(np.int64), wa.view(np.int64))   # bit-exact
+    assert ctx.errors() == 0
+
+
+# ------------------------------------------------------------------ top-k
+@pytest.mark.parametrize("n,k", [(0, 10), (5, 10), (100, 100), (2048, 100), (2049, 7), (1_500_000, 100),
+                                 (300_000, 1024)])
+def test_topk_parity(hip, ctx, n, k):
+    rng = _rng(n + k)
+    key = rng.permutation(max(1, 2 * n))[:n].astype(np.int32)       # unique keys
+    s = rng.integers(0, 1000, n).astype(np.int64) * 1_000_003       # many equal sums
+    c = rng.integers(1, 50, n).astype(np.int64)
+    order = sorted(range(n), key=lambda i: (-int(s[i]), int(key[i])))[:k]
+    out = hip.topk(ctx, _dev(key), _dev(s), _dev(c), k)
+    kk = int(_np(out["d_k"])[0])
+    assert kk == min(k, n)
+    assert np.array_equal(_np(out["key"], kk), key[order])
+    assert np.array_equal(_np(out["sum"], kk), s[order]) and np.array_equal(_np(out["cnt"], kk), c[order])
