@@ -3,6 +3,7 @@
 #include <string>
 
 #include "host.hpp"
+#include "join.hpp"
 #include "segreduce.hpp"
 #include "topk.hpp"
 
@@ -67,6 +68,22 @@ tqp_status fill_zero(void* p, size_t bytes, hipStream_t stream, tqp_ctx* ctx) {
                    k_fill_u32<<<grid_for(n, 256 * 4, 2048), 256, 0, stream>>>(static_cast<uint32_t*>(p), n, 0u));
     }
     return TQP_OK;
+}
+
+__global__ void k_join_windows(const uint32_t* lkey, int64_t nl_upper, const int64_t* d_nl,
+                               const uint32_t* rkey, int64_t nr_upper, const int64_t* d_nr, int tile_size,
+                               int64_t* win) {
+    int64_t nl = nl_upper, nr = nr_upper;
+    if (d_nl) { const int64_t t = *d_nl; nl = t < nl ? t : nl; }
+    if (d_nr) { const int64_t t = *d_nr; nr = t < nr ? t : nr; }
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t ntiles = (nl + tile_size - 1) / tile_size;
+    if (t >= ntiles) return;
+    const int64_t i0 = t * tile_size;
+    const int64_t i1 = (i0 + tile_size < nl ? i0 + tile_size : nl) - 1;
+    const int64_t lo = lower_bound_glb(rkey, 0, nr, lkey[i0]);
+    win[2 * t] = lo;
+    win[2 * t + 1] = upper_bound_glb(rkey, lo, nr, lkey[i1]);
 }
 
 __global__ void k_avg(const int64_t* sa, const int64_t* cnt, double* avg, const int64_t* d_ngroups,

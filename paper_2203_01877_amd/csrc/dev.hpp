@@ -80,6 +80,13 @@ __device__ __forceinline__ T wave_seg_incl_sum(T v, uint64_t headmask) {
     return v;
 }
 
+// Broadcast of a 4- or 8-byte value from lane src.
+__device__ __forceinline__ uint32_t shfl_any(uint32_t v, int src) { return __shfl(v, src, WAVE); }
+__device__ __forceinline__ uint64_t shfl_any(uint64_t v, int src) {
+    const uint32_t lo = __shfl((uint32_t)v, src, WAVE), hi = __shfl((uint32_t)(v >> 32), src, WAVE);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // ---------------------------------------------------------------- block scans
 // Exclusive scan of one value per thread over the block; *total receives the
 // block sum.  lds must hold BLOCK/WAVE elements.
@@ -131,32 +138,43 @@ constexpr uint64_t ST64_AGG = uint64_t(1) << 62;
 constexpr uint64_t ST64_INC = uint64_t(2) << 62;
 constexpr uint64_t ST64_VAL = (uint64_t(1) << 62) - 1;
 
-// Called by one thread: publishes the tile's aggregate, walks back over the
-// predecessors until an inclusive prefix is found, publishes its own
-// inclusive prefix and returns the exclusive one.
+// Called by all 64 lanes of one wave: publishes the tile's aggregate, reads
+// the 64 preceding status words at once (one memory round trip), adds
+// aggregates up to the nearest inclusive prefix, and repeats further back if
+// none of the 64 had one.  Publishes the tile's inclusive prefix and returns
+// the exclusive one (the same value in every lane).
 __device__ __forceinline__ int64_t lookback64(uint64_t* status, int64_t tile, int64_t agg,
                                               uint32_t* flags) {
+    const int l = lane_id();
     if (tile == 0) {
-        st_relaxed(status, ST64_INC | (uint64_t)agg);
+        if (l == 0) st_relaxed(status, ST64_INC | (uint64_t)agg);
         return 0;
     }
-    st_relaxed(status + tile, ST64_AGG | (uint64_t)agg);
+    if (l == 0) st_relaxed(status + tile, ST64_AGG | (uint64_t)agg);
     int64_t excl = 0;
     int64_t j = tile - 1;
     uint32_t spins = 0;
     while (j >= 0) {
-        const uint64_t s = ld_relaxed(status + j);
+        const int64_t idx = j - l;
+        const uint64_t s = idx >= 0 ? ld_relaxed(status + idx) : ST64_INC;
         const uint64_t f = s & ~ST64_VAL;
-        if (f == 0) {
-            if (++spins > SPIN_LIMIT) { set_flag(flags, FLAG_SPIN_LIMIT); break; }
+        const uint64_t inc = ballot(f == ST64_INC);
+        const uint64_t zero = ballot(f == 0);
+        const int first_inc = inc ? __ffsll((unsigned long long)inc) - 1 : WAVE;
+        const int first_zero = zero ? __ffsll((unsigned long long)zero) - 1 : WAVE;
+        if (first_zero < first_inc) {          // a predecessor has not published yet
+            excl += wave_sum(l < first_zero ? (int64_t)(s & ST64_VAL) : (int64_t)0);
+            j -= first_zero;
+            if (++spins > SPIN_LIMIT) { if (l == 0) set_flag(flags, FLAG_SPIN_LIMIT); break; }
             __builtin_amdgcn_s_sleep(1);
             continue;
         }
-        excl += (int64_t)(s & ST64_VAL);
-        if (f == ST64_INC) break;
-        --j;
+        const int upto = first_inc < WAVE ? first_inc + 1 : WAVE;
+        excl += wave_sum(l < upto ? (int64_t)(s & ST64_VAL) : (int64_t)0);
+        j -= upto;
+        if (first_inc < WAVE) break;
     }
-    st_relaxed(status + tile, ST64_INC | (uint64_t)(excl + agg));
+    if (l == 0) st_relaxed(status + tile, ST64_INC | (uint64_t)(excl + agg));
     return excl;
 }
 

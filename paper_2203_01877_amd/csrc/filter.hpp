@@ -63,14 +63,18 @@ k_filter(FilterPreds fp, int64_t n, const int32_t* carry, int32_t* out_row, int3
     }
     if (l == 0) s_wave[w] = wc;
     __syncthreads();
-    if (tid == 0) {
+    if (w == 0) {
         int64_t tot = 0;
-        for (int ww = 0; ww < W; ++ww) { int64_t x = s_wave[ww]; s_wave[ww] = tot; tot += x; }
+        for (int ww = 0; ww < W; ++ww) tot += s_wave[ww];
         const int64_t base = lookback64(status, tile, tot, flags);
-        s_base = base;
-        if (tile == ntiles - 1) {
-            *d_count = base + tot;
-            if (base + tot > cap) set_flag(flags, FLAG_CAPACITY);
+        if (tid == 0) {
+            int64_t run = 0;
+            for (int ww = 0; ww < W; ++ww) { const int64_t x = s_wave[ww]; s_wave[ww] = run; run += x; }
+            s_base = base;
+            if (tile == ntiles - 1) {
+                *d_count = base + tot;
+                if (base + tot > cap) set_flag(flags, FLAG_CAPACITY);
+            }
         }
     }
     __syncthreads();

@@ -27,8 +27,7 @@ void flags_reserve(Arena& a, const tqp_flags_fragment& f, FlagsBufs<Cfg>& b) {
     const int kb = norm_key_bits(f.key_bits);
     b.fact = radix_reserve<Cfg, uint32_t>(a, f.n_fact, kb);
     b.dim = radix_reserve<Cfg, uint32_t>(a, f.n_dim, kb);
-    b.jstatus = a.zero<uint64_t>((f.n_fact + JCfgFrag::TILE - 1) / JCfgFrag::TILE);
-    b.jcounter = a.zero<uint32_t>(1);
+    b.join = join_reserve<JCfgFrag>(a, f.n_fact);
     b.d_join = a.zero<int64_t>(1);
     b.acc = a.zero<int64_t>(24);
     b.fkeys = a.scratch<uint32_t>(f.n_fact);
@@ -60,12 +59,10 @@ tqp_status flags_launch(tqp_ctx* ctx, const tqp_flags_fragment& f, const tqp_fla
     e.flagA = f.flagA;
     e.flagB = f.flagB;
     e.acc = b.acc;
-    const int64_t tiles = (f.n_fact + JCfgFrag::TILE - 1) / JCfgFrag::TILE;
-    const int grid = grid_for(tiles, 1, (int64_t)ctx->num_cus * 3);
-    TQP_LAUNCH(ctx, s, "join_flags_agg",
-               k_join<JCfgFrag, uint32_t, uint32_t, EmitFlagsAgg<JCfgFrag::BLOCK>><<<grid, JCfgFrag::BLOCK, 0, s>>>(
-                   b.fkeys, b.fvals, f.n_fact, b.fact.d_cnt, b.dkeys, (const uint32_t*)nullptr, f.n_dim,
-                   b.dim.d_cnt, b.jstatus, b.jcounter, b.d_join, INT64_MAX, e, ctx->d_err));
+    if ((st = join_launch<JCfgFrag, uint32_t, uint32_t>(ctx, s, "join_flags_agg", b.join, b.fkeys, b.fvals, f.n_fact,
+                                                        b.fact.d_cnt, b.dkeys, (const uint32_t*)nullptr, f.n_dim,
+                                                        b.dim.d_cnt, b.d_join, INT64_MAX, e)) != TQP_OK)
+        return st;
     TQP_LAUNCH(ctx, s, "flags_finalize", k_flags_finalize<<<1, 64, 0, s>>>(b.acc, b.d_join, o));
     return TQP_OK;
 }
@@ -88,8 +85,7 @@ void cust_reserve(Arena& a, const tqp_cust_fragment& f, const tqp_cust_out& o, C
     const int cb = norm_key_bits(f.cust_bits);
     b.fact = radix_reserve<Cfg, uint64_t>(a, f.n_fact, kb);
     b.mid = radix_reserve<Cfg, uint32_t>(a, f.n_mid, kb);
-    b.jstatus = a.zero<uint64_t>((f.n_fact + JCfgFrag::TILE - 1) / JCfgFrag::TILE);
-    b.jcounter = a.zero<uint32_t>(1);
+    b.join = join_reserve<JCfgFrag>(a, f.n_fact);
     b.d_join = a.zero<int64_t>(1);
     b.grp = radix_reserve<Cfg, uint64_t>(a, f.join_cap, cb);
     b.sstatus = a.zero<uint64_t>((f.join_cap + SCfgFrag::TILE - 1) / SCfgFrag::TILE);
@@ -138,12 +134,10 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
         e.shift[p] = b.grp.pd.shift[p];
         e.bits[p] = b.grp.pd.bits[p];
     }
-    const int64_t tiles = (f.n_fact + JCfgFrag::TILE - 1) / JCfgFrag::TILE;
-    const int grid = grid_for(tiles, 1, (int64_t)ctx->num_cus * 3);
-    TQP_LAUNCH(ctx, s, "join_keyval",
-               k_join<JCfgFrag, uint64_t, uint32_t, Emit><<<grid, JCfgFrag::BLOCK, 0, s>>>(
-                   b.fkeys, b.fvals, f.n_fact, b.fact.d_cnt, b.mkeys, b.mvals, f.n_mid, (const int64_t*)nullptr,
-                   b.jstatus, b.jcounter, b.d_join, f.join_cap, e, ctx->d_err));
+    if ((st = join_launch<JCfgFrag, uint64_t, uint32_t>(ctx, s, "join_keyval", b.join, b.fkeys, b.fvals, f.n_fact,
+                                                        b.fact.d_cnt, b.mkeys, b.mvals, f.n_mid,
+                                                        (const int64_t*)nullptr, b.d_join, f.join_cap, e)) != TQP_OK)
+        return st;
     // group-by: sort (custkey, revenue) by custkey, then reduce runs
     SrcPairs<uint64_t> gsrc{b.gkeys_in, b.gvals_in, f.join_cap, b.d_join};
     if ((st = radix_launch<Cfg, uint64_t>(b.grp, gsrc, f.join_cap, false, b.d_join, key_mask_for(cb), b.gkeys,

@@ -9,14 +9,50 @@
 
 namespace tqp {
 
-using JCfgFrag = JoinCfg<256, 4, 4096>;
+using JCfgFrag = JoinCfg<256, 8, 4096>;
 using SCfgFrag = SegCfg<256, 16>;
+
+// Join scratch: the R window of every left tile, the look-back status words
+// and the dynamic tile counter.
+struct JoinBufs {
+    int64_t tiles = 0;
+    int64_t* win = nullptr;
+    uint64_t* status = nullptr;
+    uint32_t* counter = nullptr;
+};
+
+template <class Cfg>
+JoinBufs join_reserve(Arena& a, int64_t nl_upper) {
+    JoinBufs b;
+    b.tiles = (nl_upper + Cfg::TILE - 1) / Cfg::TILE;
+    b.status = a.zero<uint64_t>(b.tiles);
+    b.counter = a.zero<uint32_t>(1);
+    b.win = a.scratch<int64_t>(2 * b.tiles);
+    return b;
+}
+
+template <class Cfg, class LP, class RP, class Emit>
+tqp_status join_launch(tqp_ctx* ctx, hipStream_t s, const char* name, const JoinBufs& b, const uint32_t* lkey,
+                       const LP* lpay, int64_t nl, const int64_t* d_nl, const uint32_t* rkey, const RP* rpay,
+                       int64_t nr, const int64_t* d_nr, int64_t* d_count, int64_t cap, const Emit& e) {
+    const int64_t tiles = b.tiles;
+    if (tiles > 0) {
+        TQP_LAUNCH(ctx, s, "join_windows",
+                   k_join_windows<<<grid_for(tiles, 256, 0), 256, 0, s>>>(lkey, nl, d_nl, rkey, nr, d_nr,
+                                                                            Cfg::TILE, b.win));
+    }
+    const int grid = grid_for(tiles, 1, (int64_t)ctx->num_cus * 4);
+    TQP_LAUNCH(ctx, s, name,
+               k_join<Cfg, LP, RP, Emit><<<grid, Cfg::BLOCK, 0, s>>>(lkey, lpay, nl, d_nl, rkey, rpay, nr, d_nr,
+                                                                   b.win, b.status, b.counter, d_count, cap, e,
+                                                                   ctx->d_err));
+    return TQP_OK;
+}
 
 template <class Cfg>
 struct FlagsBufs {
     RadixBufs<Cfg, uint32_t> fact, dim;
-    uint64_t* jstatus = nullptr;
-    uint32_t* jcounter = nullptr;
+    JoinBufs join;
     int64_t* d_join = nullptr;
     int64_t* acc = nullptr;
     uint32_t *fkeys = nullptr, *fvals = nullptr, *dkeys = nullptr, *dvals = nullptr;
@@ -43,8 +79,7 @@ struct CustBufs {
     RadixBufs<Cfg, uint64_t> fact;
     RadixBufs<Cfg, uint32_t> mid;
     RadixBufs<Cfg, uint64_t> grp;
-    uint64_t* jstatus = nullptr;
-    uint32_t* jcounter = nullptr;
+    JoinBufs join;
     int64_t* d_join = nullptr;
     uint64_t* sstatus = nullptr;
     uint32_t* scounter = nullptr;

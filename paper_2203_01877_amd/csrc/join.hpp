@@ -36,18 +36,9 @@ struct JoinCfg {
     static constexpr int WAVES = BLOCK_ / WAVE;
 };
 
-template <class Cfg, class LP>
-struct JoinSmem {
-    static_assert(Cfg::WAVES >= 2, "the two window searches run on waves 0 and 1");
-    uint32_t lkey[Cfg::TILE];
-    LP lpay[Cfg::TILE];
-    int64_t off[Cfg::TILE + 1];
-    int32_t lb[Cfg::TILE];
-    uint32_t rkey[Cfg::RWIN];
-    int64_t scratch[Cfg::WAVES];
-    int64_t win_lo, win_hi, tile_base;
-    uint32_t tile;
-};
+// Matches of one left element at most this many are emitted by its own lane;
+// elements with more are expanded by the whole wave, 64 outputs at a time.
+constexpr int JOIN_LANE_MAX = 4;
 
 // ------------------------------------------------------------------ emitters
 // Index pairs (late materialisation: the join returns row-index pairs).
@@ -154,119 +145,122 @@ struct EmitFlagsAgg {
     }
 };
 
-// ------------------------------------------------------------------ kernel
+// ------------------------------------------------------------------ kernels
+// R window of every left tile: [lower_bound(R, first key), upper_bound(R, last
+// key)).  One thread per tile; all tiles search at once.
+__global__ void k_join_windows(const uint32_t* lkey, int64_t nl_upper, const int64_t* d_nl,
+                               const uint32_t* rkey, int64_t nr_upper, const int64_t* d_nr, int tile_size,
+                               int64_t* win);
+
 template <class Cfg, class LP, class RP, class Emit>
 __global__ void __launch_bounds__(Cfg::BLOCK)
 k_join(const uint32_t* lkey, const LP* lpay, int64_t nl_upper, const int64_t* d_nl,
-       const uint32_t* rkey, const RP* rpay, int64_t nr_upper, const int64_t* d_nr,
+       const uint32_t* rkey, const RP* rpay, int64_t nr_upper, const int64_t* d_nr, const int64_t* win,
        uint64_t* status, uint32_t* tile_counter, int64_t* d_count, int64_t cap, Emit emit,
        uint32_t* flags) {
-    constexpr int TILE = Cfg::TILE, ITEMS = Cfg::ITEMS, BLOCK = Cfg::BLOCK, RWIN = Cfg::RWIN;
-    __shared__ JoinSmem<Cfg, LP> sm;
+    constexpr int TILE = Cfg::TILE, ITEMS = Cfg::ITEMS, RWIN = Cfg::RWIN, W = Cfg::WAVES;
+    __shared__ uint32_t s_rkey[RWIN];
+    __shared__ int64_t s_wave[W];
+    __shared__ int64_t s_base;
+    __shared__ uint32_t s_tile;
     __shared__ typename Emit::Smem esm;
-    const int tid = threadIdx.x, w = tid / WAVE;
+    const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
 
-    int64_t nl = nl_upper, nr = nr_upper;
+    int64_t nl = nl_upper;
     if (d_nl) { int64_t t = *d_nl; nl = t < nl ? t : nl; }
-    if (d_nr) { int64_t t = *d_nr; nr = t < nr ? t : nr; }
+    (void)nr_upper;
+    (void)d_nr;
     const int64_t ntiles = (nl + TILE - 1) / TILE;
     Emit e = emit;
     e.init(esm);
     if (ntiles == 0 && blockIdx.x == 0 && tid == 0) *d_count = 0;
 
     for (;;) {
-        if (tid == 0) sm.tile = atomicAdd(tile_counter, 1u);
+        if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
         __syncthreads();
-        const int64_t tile = sm.tile;
+        const int64_t tile = s_tile;
         if (tile >= ntiles) break;
-        const int64_t t0 = tile * TILE;
-        const int tn = (int)((nl - t0) < TILE ? (nl - t0) : TILE);
-
-        for (int i = tid; i < tn; i += BLOCK) {
-            sm.lkey[i] = lkey[t0 + i];
-            sm.lpay[i] = lpay ? lpay[t0 + i] : (LP)(t0 + i);
-        }
-        __syncthreads();
-        // R window of the tile's key range.
-        if (w == 0) {
-            int64_t lo = wave_bound(rkey, nr, sm.lkey[0], false);
-            if (lane_id() == 0) sm.win_lo = lo;
-        } else if (w == 1) {
-            int64_t hi = wave_bound(rkey, nr, sm.lkey[tn - 1], true);
-            if (lane_id() == 0) sm.win_hi = hi;
-        }
-        __syncthreads();
-        const int64_t wlo = sm.win_lo, whi = sm.win_hi;
+        const int64_t wlo = win[2 * tile], whi = win[2 * tile + 1];
         const int64_t wn = whi - wlo;
         const bool in_lds = wn <= RWIN;
         if (in_lds)
-            for (int i = tid; i < wn; i += BLOCK) sm.rkey[i] = rkey[wlo + i];
-        __syncthreads();
-
-        // Per left element: first match and match count (blocked layout).
-        int64_t tsum = 0;
-        int64_t cnt[ITEMS];
-        int32_t first[ITEMS];
-        uint32_t prev_key = 0;
-        int64_t prev_lb = -1, prev_cnt = 0;
+            for (int i = tid; i < wn; i += Cfg::BLOCK) s_rkey[i] = rkey[wlo + i];
+        // The wave's contiguous chunk of the tile, 64 elements per round.
+        const int64_t chunk = tile * TILE + (int64_t)w * ITEMS * WAVE;
+        uint32_t key[ITEMS];
+        LP pay[ITEMS];
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
-            const int i = tid * ITEMS + j;
+            const int64_t i = chunk + j * WAVE + l;
+            key[j] = 0;
+            if (i < nl) {
+                key[j] = lkey[i];
+                pay[j] = lpay ? lpay[i] : (LP)i;
+            }
+        }
+        __syncthreads();
+        // Match count and first match of each element: rightHist of its key.
+        int32_t cnt[ITEMS];
+        int64_t first[ITEMS], off[ITEMS];      // off: exclusive offset of the element within the wave chunk
+        int64_t wave_total = 0;
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const int64_t i = chunk + j * WAVE + l;
             cnt[j] = 0;
             first[j] = 0;
-            if (i < tn) {
-                const uint32_t k = sm.lkey[i];
-                if (prev_lb >= 0 && k == prev_key) {
-                    first[j] = (int32_t)prev_lb;
-                    cnt[j] = prev_cnt;
+            if (i < nl) {
+                int64_t lb, ub;
+                if (in_lds) {
+                    lb = wlo + lower_bound_lds(s_rkey, (int)wn, key[j]);
+                    ub = wlo + upper_bound_lds(s_rkey, (int)wn, key[j]);
                 } else {
-                    int64_t lb, ub;
-                    if (in_lds) {
-                        lb = wlo + lower_bound_lds(sm.rkey, (int)wn, k);
-                        ub = wlo + upper_bound_lds(sm.rkey, (int)wn, k);
-                    } else {
-                        lb = lower_bound_glb(rkey, wlo, whi, k);
-                        ub = upper_bound_glb(rkey, lb, whi, k);
-                    }
-                    first[j] = (int32_t)lb;
-                    cnt[j] = ub - lb;
-                    prev_key = k;
-                    prev_lb = lb;
-                    prev_cnt = cnt[j];
+                    lb = lower_bound_glb(rkey, wlo, whi, key[j]);
+                    ub = upper_bound_glb(rkey, lb, whi, key[j]);
                 }
-                tsum += cnt[j];
+                first[j] = lb;
+                cnt[j] = (int32_t)(ub - lb);
             }
+            const int64_t incl = wave_incl_sum((int64_t)cnt[j]);
+            off[j] = wave_total + incl - cnt[j];
+            wave_total += __shfl(incl, WAVE - 1, WAVE);
         }
-        int64_t ttot;
-        int64_t toff = block_excl_sum<BLOCK>(tsum, sm.scratch, &ttot);
-#pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-            const int i = tid * ITEMS + j;
-            if (i < tn) {
-                sm.off[i] = toff;
-                sm.lb[i] = first[j];
-                toff += cnt[j];
-            }
-        }
-        if (tid == 0) {
-            const int64_t base = lookback64(status, tile, ttot, flags);
-            sm.tile_base = base;
-            if (tile == ntiles - 1) {
-                *d_count = base + ttot;
-                if (base + ttot > cap) set_flag(flags, FLAG_CAPACITY);
+        if (l == 0) s_wave[w] = wave_total;
+        __syncthreads();
+        // Tile output base: block scan of the wave totals + decoupled look-back.
+        if (w == 0) {
+            int64_t tot = 0;
+            for (int ww = 0; ww < W; ++ww) tot += s_wave[ww];
+            const int64_t base = lookback64(status, tile, tot, flags);
+            if (tid == 0) {
+                s_base = base;
+                if (tile == ntiles - 1) {
+                    *d_count = base + tot;
+                    if (base + tot > cap) set_flag(flags, FLAG_CAPACITY);
+                }
             }
         }
         __syncthreads();
-        const int64_t base = sm.tile_base;
-        // Expansion: output slot q of the tile -> (left element, right element).
-        for (int64_t q = tid; q < ttot; q += BLOCK) {
-            int lo = 0, hi = tn;      // last i with off[i] <= q
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (sm.off[mid] <= q) lo = mid; else hi = mid;
+        int64_t wbase = s_base;
+        for (int ww = 0; ww < w; ++ww) wbase += s_wave[ww];
+        // Expansion: output o of element i pairs it with right element first + (o - offset(i)).
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const int64_t o = wbase + off[j];
+            const bool small = cnt[j] <= JOIN_LANE_MAX;
+            if (small)
+                for (int t = 0; t < cnt[j]; ++t)
+                    e(o + t, key[j], pay[j], rpay ? rpay[first[j] + t] : (RP)(first[j] + t), esm);
+            uint64_t heavy = ballot(!small);
+            while (heavy) {
+                const int src = __ffsll((unsigned long long)heavy) - 1;
+                heavy &= heavy - 1;
+                const int c = __shfl(cnt[j], src, WAVE);
+                const int64_t f = __shfl(first[j], src, WAVE);
+                const int64_t oo = __shfl(o, src, WAVE);
+                const uint32_t kk = __shfl(key[j], src, WAVE);
+                const LP pp = shfl_any(pay[j], src);
+                for (int q = l; q < c; q += WAVE) e(oo + q, kk, pp, rpay ? rpay[f + q] : (RP)(f + q), esm);
             }
-            const int64_t r = (int64_t)sm.lb[lo] + (q - sm.off[lo]);
-            e(base + q, sm.lkey[lo], sm.lpay[lo], rpay ? rpay[r] : (RP)r, esm);
         }
         __syncthreads();
     }

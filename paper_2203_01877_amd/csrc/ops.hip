@@ -9,7 +9,7 @@
 
 namespace tqp {
 
-using JCfg = JoinCfg<256, 4, 4096>;
+using JCfg = JoinCfg<256, 8, 4096>;
 using SCfg = SegCfg<256, 16>;
 constexpr int FILTER_BLOCK = 256, FILTER_ITEMS = 16;
 constexpr int TOPK_BLOCK = 256, TOPK_CH = 2048;
@@ -139,24 +139,20 @@ tqp_status tqp_join(tqp_ctx* ctx, const int32_t* lkey, const int32_t* lrow, int6
         (cap > 0 && (!out_l || !out_r)))
         return fail(TQP_ERR_INVALID, "tqp_join: null pointer or negative size");
     if (nl > MAX_ELEMS || nr > MAX_ELEMS) return fail(TQP_ERR_UNSUPPORTED, "tqp_join: input too large");
-    const int64_t tiles = (nl + JCfg::TILE - 1) / JCfg::TILE;
-    uint64_t* status = nullptr;
-    uint32_t* counter = nullptr;
+    JoinBufs b;
     Arena a;
-    auto plan = [&](Arena& ar) {
-        status = ar.zero<uint64_t>(tiles);
-        counter = ar.zero<uint32_t>(1);
-    };
+    auto plan = [&](Arena& ar) { b = join_reserve<JCfg>(ar, nl); };
     tqp_status st = with_workspace(ctx, ws, ws_bytes, stream, plan, a);
     if (st != TQP_OK || !ws) return st;
     if ((st = fill_zero(a.base, a.zsize, stream, ctx)) != TQP_OK) return st;
     EmitPairs e{out_l, out_r, cap};
-    const int grid = grid_for(tiles, 1, (int64_t)ctx->num_cus * 3);
-    TQP_LAUNCH(ctx, stream, "join_pairs",
-               k_join<JCfg, uint32_t, uint32_t, EmitPairs><<<grid, JCfg::BLOCK, 0, stream>>>(
-                   reinterpret_cast<const uint32_t*>(lkey), reinterpret_cast<const uint32_t*>(lrow), nl, d_nl,
-                   reinterpret_cast<const uint32_t*>(rkey), reinterpret_cast<const uint32_t*>(rrow), nr, d_nr,
-                   status, counter, d_count, cap, e, ctx->d_err));
+    if ((st = join_launch<JCfg, uint32_t, uint32_t>(ctx, stream, "join_pairs", b,
+                                                    reinterpret_cast<const uint32_t*>(lkey),
+                                                    reinterpret_cast<const uint32_t*>(lrow), nl, d_nl,
+                                                    reinterpret_cast<const uint32_t*>(rkey),
+                                                    reinterpret_cast<const uint32_t*>(rrow), nr, d_nr, d_count, cap,
+                                                    e)) != TQP_OK)
+        return st;
     return TQP_OK;
 }
 

@@ -162,8 +162,9 @@ template <class V> struct ValBytes { static constexpr int value = sizeof(V); };
 template <> struct ValBytes<NoVal> { static constexpr int value = 0; };
 
 // ------------------------------------------------------------------ config
-template <int RB, int BLOCK_, int ITEMS_>
+template <int RB, int BLOCK_, int ITEMS_, int LB_ = 16>
 struct RadixCfg {
+    static constexpr int LOOKBACK = LB_;     // predecessors read per look-back round
     static constexpr int RADIX_BITS = RB;
     static constexpr int RADIX = 1 << RB;
     static constexpr int BLOCK = BLOCK_;
@@ -224,18 +225,64 @@ k_radix_hist(Src src, PassDesc pd, uint32_t key_mask, uint32_t* hist, int64_t* d
 }
 
 // ------------------------------------------------------------------ one pass
+// LDS of one pass: the per-wave digit counters are only live while ranking and
+// the staged tile only while scattering, so the two share storage.
 template <class Cfg, class V>
 struct PassSmem {
     static constexpr int R = Cfg::RADIX;
-    uint32_t keys[Cfg::TILE];
-    typename std::conditional<ValBytes<V>::value == 0, char, V>::type
-        vals[ValBytes<V>::value == 0 ? 1 : Cfg::TILE];
-    uint32_t wave_hist[Cfg::WAVES][R];
+    struct Stage {
+        uint32_t keys[Cfg::TILE];
+        typename std::conditional<ValBytes<V>::value == 0, char, V>::type
+            vals[ValBytes<V>::value == 0 ? 1 : Cfg::TILE];
+    };
+    union {
+        uint32_t wave_hist[Cfg::WAVES][R];
+        Stage stage;
+    } u;
     uint32_t local_start[R];
     int32_t delta[R];
     uint32_t scratch[Cfg::WAVES];
     uint32_t tile;
 };
+
+// Exclusive prefix of digit d over the tiles before `tile` (one thread per
+// digit).  Walks back from tile - 1 reading LOOKBACK_WINDOW status words per
+// round (the loads are issued together, so a round costs one memory round
+// trip however many tiles it covers), adding aggregates until it meets an
+// inclusive prefix.
+template <int LOOKBACK_WINDOW>
+__device__ __forceinline__ uint32_t radix_lookback(const uint32_t* status, int64_t tile, int R, int d,
+                                                   uint32_t* flags) {
+    uint32_t excl = 0;
+    int64_t j = tile - 1;
+    uint32_t spins = 0;
+    while (j >= 0) {
+        uint32_t s[LOOKBACK_WINDOW];
+#pragma unroll
+        for (int i = 0; i < LOOKBACK_WINDOW; ++i)
+            s[i] = (j - i >= 0) ? ld_relaxed(status + (j - i) * R + d) : ST_INC;
+        uint32_t acc = 0;
+        int used = 0;
+        bool done = false, stall = false;
+#pragma unroll
+        for (int i = 0; i < LOOKBACK_WINDOW; ++i) {
+            if (done || stall) continue;
+            const uint32_t f = s[i] & ~ST_VAL;
+            if (f == 0) { stall = true; continue; }
+            acc += s[i] & ST_VAL;
+            used = i + 1;
+            if (f == ST_INC) done = true;
+        }
+        excl += acc;
+        j -= used;
+        if (done) break;
+        if (stall) {
+            if (++spins > SPIN_LIMIT) { set_flag(flags, FLAG_SPIN_LIMIT); break; }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    return excl;
+}
 
 template <class Cfg, class Src, class V>
 __global__ void __launch_bounds__(Cfg::BLOCK)
@@ -246,20 +293,21 @@ k_radix_pass(Src src, DstPairs<V> dst, int shift, int bits, const uint32_t* hist
     const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
 
     if (tid == 0) sm.tile = atomicAdd(tile_counter, 1u);
-    for (int i = tid; i < W * R; i += Cfg::BLOCK) (&sm.wave_hist[0][0])[i] = 0;
+    for (int i = tid; i < W * R; i += Cfg::BLOCK) (&sm.u.wave_hist[0][0])[i] = 0;
     __syncthreads();
     const uint32_t tile = sm.tile;
     const int64_t n = src.size();
     const int64_t ntiles = (n + TILE - 1) / TILE;
     if ((int64_t)tile >= ntiles) return;
     const uint32_t dmask = (1u << bits) - 1;
+    const int nd = (int)dmask + 1;            // digits of this pass (<= R)
 
     // Load: wave w owns the contiguous chunk [w*ITEMS*64, (w+1)*ITEMS*64) of the
     // tile, item j of lane l is element chunk + j*64 + l (coalesced loads).
     const int64_t base = (int64_t)tile * TILE + (int64_t)w * ITEMS * WAVE;
     uint32_t key[ITEMS];
     V val[ITEMS];
-    uint32_t rank[ITEMS];
+    uint32_t pos[ITEMS];
     bool valid[ITEMS];
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
@@ -283,93 +331,81 @@ k_radix_pass(Src src, DstPairs<V> dst, int shift, int bits, const uint32_t* hist
             }
         }
         if (valid[j]) {
-            const uint32_t before = sm.wave_hist[w][d];
+            const uint32_t before = sm.u.wave_hist[w][d];
             const uint64_t lower = peers & lanemask_lt();
-            const int r = popc64(lower);
-            rank[j] = before + r;
-            if ((peers >> l) == 1) sm.wave_hist[w][d] = before + popc64(peers);   // last peer
+            pos[j] = before + popc64(lower);
+            if ((peers >> l) == 1) sm.u.wave_hist[w][d] = before + popc64(peers);   // last peer
         }
     }
     __syncthreads();
 
-    // Per digit: exclusive prefix over waves, tile count, publish, look back.
+    // Per digit: exclusive prefix over waves (in place), tile count, publish
+    // the tile aggregate as early as possible.
     for (int d = tid; d < R; d += Cfg::BLOCK) {
         uint32_t run = 0;
 #pragma unroll
         for (int ww = 0; ww < W; ++ww) {
-            uint32_t c = sm.wave_hist[ww][d];
-            sm.wave_hist[ww][d] = run;
+            const uint32_t c = sm.u.wave_hist[ww][d];
+            sm.u.wave_hist[ww][d] = run;
             run += c;
         }
         sm.local_start[d] = run;   // tile count for now; scanned below
-        if (d <= (int)dmask) {
-            uint32_t* st = status + (int64_t)tile * R + d;
-            if (tile == 0) {
-                st_relaxed(st, ST_INC | run);
-                sm.delta[d] = 0;
-            } else {
-                st_relaxed(st, ST_AGG | run);
-                uint32_t excl = 0;
-                int64_t j = (int64_t)tile - 1;
-                uint32_t spins = 0;
-                while (j >= 0) {
-                    uint32_t s = ld_relaxed(status + j * R + d);
-                    if ((s & ~ST_VAL) == 0) {
-                        if (++spins > SPIN_LIMIT) { set_flag(flags, FLAG_SPIN_LIMIT); break; }
-                        __builtin_amdgcn_s_sleep(1);
-                        continue;
-                    }
-                    excl += s & ST_VAL;
-                    if ((s & ~ST_VAL) == ST_INC) break;
-                    --j;
-                }
-                st_relaxed(st, ST_INC | (excl + run));
-                sm.delta[d] = (int32_t)excl;
-            }
-        }
+        if (d < nd) st_relaxed(status + (int64_t)tile * R + d, (tile == 0 ? ST_INC : ST_AGG) | run);
     }
     __syncthreads();
-    // Tile-local digit starts (exclusive scan of the tile counts), then the
-    // global digit base (exclusive scan of this pass's histogram).
+    // Tile-local digit starts (exclusive scan of the tile counts, in place).
     const uint32_t tile_total = block_excl_scan_array<Cfg::BLOCK>(sm.local_start, R, sm.scratch);
+    // Global digit base: exclusive scan of this pass's histogram.
     {
-        // digit base from the global histogram, computed per block
         const int per = (R + Cfg::BLOCK - 1) / Cfg::BLOCK;
         const int b0 = tid * per;
         uint32_t loc = 0;
         for (int i = 0; i < per; ++i)
-            if (b0 + i < R && b0 + i <= (int)dmask) loc += hist[b0 + i];
+            if (b0 + i < nd) loc += hist[b0 + i];
         uint32_t tot;
         uint32_t off = block_excl_sum<Cfg::BLOCK>(loc, sm.scratch, &tot);
         for (int i = 0; i < per; ++i) {
-            int d = b0 + i;
-            if (d < R && d <= (int)dmask) {
-                sm.delta[d] = (int32_t)(off + (uint32_t)sm.delta[d]) - (int32_t)sm.local_start[d];
+            const int d = b0 + i;
+            if (d < nd) {
+                sm.delta[d] = (int32_t)off - (int32_t)sm.local_start[d];
                 off += hist[d];
             }
         }
     }
-    __syncthreads();
-
-    // Local scatter into LDS in digit order.
+    // Positions inside the tile, while the per-wave offsets are still in LDS.
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         if (valid[j]) {
             const uint32_t d = (key[j] >> shift) & dmask;
-            const uint32_t pos = sm.local_start[d] + sm.wave_hist[w][d] + rank[j];
-            sm.keys[pos] = key[j];
-            if constexpr (ValBytes<V>::value != 0) sm.vals[pos] = val[j];
+            pos[j] += sm.local_start[d] + sm.u.wave_hist[w][d];
+        }
+    }
+    __syncthreads();
+    // Stage the tile in digit order (overwrites the counters) ...
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        if (valid[j]) {
+            sm.u.stage.keys[pos[j]] = key[j];
+            if constexpr (ValBytes<V>::value != 0) sm.u.stage.vals[pos[j]] = val[j];
+        }
+    }
+    // ... while one thread per digit looks back for the tile's global offset.
+    for (int d = tid; d < nd; d += Cfg::BLOCK) {
+        if (tile != 0) {
+            const uint32_t excl = radix_lookback<Cfg::LOOKBACK>(status, tile, R, d, flags);
+            st_relaxed(status + (int64_t)tile * R + d,
+                       ST_INC | (excl + (d + 1 < R ? sm.local_start[d + 1] : tile_total) - sm.local_start[d]));
+            sm.delta[d] += (int32_t)excl;
         }
     }
     __syncthreads();
     // Coalesced write-out: consecutive LDS slots of one digit go to
     // consecutive global positions.
-    const uint32_t count = tile_total;
-    for (uint32_t p = tid; p < count; p += Cfg::BLOCK) {
-        const uint32_t k = sm.keys[p];
+    for (uint32_t p = tid; p < tile_total; p += Cfg::BLOCK) {
+        const uint32_t k = sm.u.stage.keys[p];
         const uint32_t d = (k >> shift) & dmask;
         const int64_t g = (int64_t)p + sm.delta[d];
-        if constexpr (ValBytes<V>::value != 0) dst.store(g, k, sm.vals[p]);
+        if constexpr (ValBytes<V>::value != 0) dst.store(g, k, sm.u.stage.vals[p]);
         else dst.store(g, k, NoVal{});
     }
 }

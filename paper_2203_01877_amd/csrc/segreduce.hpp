@@ -109,14 +109,18 @@ k_segreduce(const uint32_t* keys, VS vs, int64_t n_upper, const int64_t* d_n, ui
     }
     if (l == 0) s_wave[w] = wave_heads;
     __syncthreads();
-    if (tid == 0) {
+    if (w == 0) {
         int64_t tot = 0;
-        for (int ww = 0; ww < W; ++ww) { int64_t x = s_wave[ww]; s_scan[ww] = tot; tot += x; }
+        for (int ww = 0; ww < W; ++ww) tot += s_wave[ww];
         const int64_t base = lookback64(status, tile, tot, flags);
-        s_base = base;
-        if (tile == ntiles - 1) {
-            *out.d_ngroups = base + tot;
-            if (base + tot > out.gcap) set_flag(flags, FLAG_CAPACITY);
+        if (tid == 0) {
+            int64_t run = 0;
+            for (int ww = 0; ww < W; ++ww) { s_scan[ww] = run; run += s_wave[ww]; }
+            s_base = base;
+            if (tile == ntiles - 1) {
+                *out.d_ngroups = base + tot;
+                if (base + tot > out.gcap) set_flag(flags, FLAG_CAPACITY);
+            }
         }
     }
     __syncthreads();
