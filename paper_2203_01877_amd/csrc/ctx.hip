@@ -95,6 +95,30 @@ __global__ void k_avg(const int64_t* sa, const int64_t* cnt, double* avg, const 
         avg[g] = (double)sa[g] / (double)cnt[g];
 }
 
+__global__ void k_topk_filter(const int32_t* gkey, const int64_t* gsum, int64_t n_upper, const int64_t* d_n,
+                              const TopCand* thr, int k, TopCand* out, int64_t* d_out) {
+    int64_t n = n_upper;
+    if (d_n) { const int64_t t = *d_n; n = t < n ? t : n; }
+    const TopCand T = thr[k - 1];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
+        const int64_t g = base + threadIdx.x;
+        bool keep = false;
+        TopCand x;
+        if (g < n) {
+            x.sum = gsum[g];
+            x.key = gkey[g];
+            x.idx = (int32_t)g;
+            keep = T.idx < 0 || !top_before(T, x);
+        }
+        const uint64_t m = ballot(keep);
+        int64_t pos = 0;
+        if (lane_id() == 0 && m) pos = atomic_add(d_out, (int64_t)popc64(m));
+        pos = __shfl(pos, 0, WAVE);
+        if (keep) out[pos + popc64(m & lanemask_lt())] = x;
+    }
+}
+
 __global__ void k_topk_emit(const TopCand* c, int k, const int64_t* gcnt, int32_t* out_key,
                             int64_t* out_sum, int64_t* out_cnt, int32_t* d_k) {
     __shared__ int s_n;

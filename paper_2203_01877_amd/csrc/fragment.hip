@@ -146,7 +146,7 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
     ValsDirect vs{reinterpret_cast<const int64_t*>(b.gvals), nullptr};
     SegOut so{o.key, o.sum, o.cnt, nullptr, o.gcap, o.d_ngroups};
     TQP_LAUNCH(ctx, s, "segreduce",
-               k_segreduce<SCfgFrag, ValsDirect><<<grid_for(f.join_cap, SCfgFrag::TILE, 0), SCfgFrag::BLOCK, 0, s>>>(
+               k_segreduce<SCfgFrag, ValsDirect, false><<<grid_for(f.join_cap, SCfgFrag::TILE, 0), SCfgFrag::BLOCK, 0, s>>>(
                    b.gkeys, vs, f.join_cap, b.d_join, b.sstatus, b.scounter, so, ctx->d_err));
     // ORDER BY sum DESC, custkey ASC LIMIT k
     if ((st = topk_launch(b.topk, o.key, o.sum, o.cnt, o.d_ngroups, f.k, o.top_key, o.top_sum, o.top_cnt,

@@ -58,15 +58,23 @@ struct FlagsBufs {
     uint32_t *fkeys = nullptr, *fvals = nullptr, *dkeys = nullptr, *dvals = nullptr;
 };
 
-// Levels of the top-k reduction: each keeps k of every CH candidates, so with
-// k <= CH / 2 a level at least halves the set; 32 levels cover 2^30 groups.
+// Top-k scratch: the levels over a sample of the groups (giving the
+// threshold), the filtered candidates and their count, and the levels over
+// the candidates.  Each level keeps k of every CH candidates (k <= CH / 2, so
+// a level at least halves the set); 32 levels cover 2^30 groups.
 constexpr int TOPK_MAX_LEVELS = 32;
+constexpr int TOPK_CH = 2048;
+constexpr int64_t TOPK_SAMPLE = 16384;
 
 struct TopkBufs {
-    int levels = 0;
-    int64_t n_in[TOPK_MAX_LEVELS] = {0};
+    int slevels = 0, levels = 0;
+    int64_t n_upper = 0, sample = 0;
+    int64_t sblocks[TOPK_MAX_LEVELS] = {0};
     int64_t blocks[TOPK_MAX_LEVELS] = {0};
+    TopCand* scand[TOPK_MAX_LEVELS] = {nullptr};
     TopCand* cand[TOPK_MAX_LEVELS] = {nullptr};
+    TopCand* filtered = nullptr;
+    int64_t* d_nf = nullptr;
 };
 
 TopkBufs topk_reserve(Arena& a, int64_t n_upper, int k);

@@ -12,32 +12,54 @@ namespace tqp {
 using JCfg = JoinCfg<256, 8, 4096>;
 using SCfg = SegCfg<256, 16>;
 constexpr int FILTER_BLOCK = 256, FILTER_ITEMS = 16;
-constexpr int TOPK_BLOCK = 256, TOPK_CH = 2048;
+constexpr int TOPK_BLOCK = 1024;
 
 // ---------------------------------------------------------------- top-k plan
-// Level l reads n_in[l] candidates (level 0: the groups) in chunks of CH and
-// writes k per chunk; the last level has one chunk.
+// Worst-case level structure for n candidates: level l gets n_l rows in
+// max(1, ceil(n_l / CH)) chunks and leaves k per chunk.
+static int topk_plan_levels(int64_t n, int k, int64_t* blocks, TopCand** cand, Arena& a) {
+    int levels = 0;
+    for (int l = 0; l < TOPK_MAX_LEVELS; ++l) {
+        int64_t b = (n + TOPK_CH - 1) / TOPK_CH;
+        if (b < 1) b = 1;
+        blocks[l] = b;
+        cand[l] = a.scratch<TopCand>(b * k);
+        levels = l + 1;
+        if (b == 1) break;
+        n = b * k;
+    }
+    return levels;
+}
+
 TopkBufs topk_reserve(Arena& a, int64_t n_upper, int k) {
     TopkBufs t;
-    int64_t n = n_upper < 1 ? 1 : n_upper;
-    for (int l = 0; l < TOPK_MAX_LEVELS; ++l) {
-        t.n_in[l] = l == 0 ? n_upper : n;
-        t.blocks[l] = (n + TOPK_CH - 1) / TOPK_CH;
-        t.cand[l] = a.scratch<TopCand>(t.blocks[l] * k);
-        t.levels = l + 1;
-        if (t.blocks[l] == 1) break;
-        n = t.blocks[l] * k;
-    }
+    t.n_upper = n_upper;
+    t.sample = n_upper < TOPK_SAMPLE ? n_upper : TOPK_SAMPLE;
+    t.slevels = topk_plan_levels(t.sample, k, t.sblocks, t.scand, a);
+    t.d_nf = a.zero<int64_t>(1);
+    t.filtered = a.scratch<TopCand>(n_upper > 0 ? n_upper : 1);
+    t.levels = topk_plan_levels(n_upper, k, t.blocks, t.cand, a);
     return t;
 }
 
 tqp_status topk_launch(const TopkBufs& t, const int32_t* key, const int64_t* sum, const int64_t* cnt,
                        const int64_t* d_n, int k, int32_t* out_key, int64_t* out_sum, int64_t* out_cnt,
                        int32_t* d_k, hipStream_t s, tqp_ctx* ctx) {
+    // 1. first k of the sample (the leading groups) -> threshold
+    for (int l = 0; l < t.slevels; ++l) {
+        TQP_LAUNCH(ctx, s, "topk_sample",
+                   k_topk_level<TOPK_BLOCK, TOPK_CH><<<(unsigned)t.sblocks[l], TOPK_BLOCK, 0, s>>>(
+                       key, sum, t.sample, d_n, l == 0 ? nullptr : t.scand[l - 1], t.scand[l], k, l));
+    }
+    // 2. groups not ordered after the threshold
+    TQP_LAUNCH(ctx, s, "topk_filter",
+               k_topk_filter<<<grid_for(t.n_upper, 256 * 8, (int64_t)ctx->num_cus * 8), 256, 0, s>>>(
+                   key, sum, t.n_upper, d_n, t.scand[t.slevels - 1], k, t.filtered, t.d_nf));
+    // 3. first k of the candidates
     for (int l = 0; l < t.levels; ++l) {
         TQP_LAUNCH(ctx, s, "topk_level",
                    k_topk_level<TOPK_BLOCK, TOPK_CH><<<(unsigned)t.blocks[l], TOPK_BLOCK, 0, s>>>(
-                       key, sum, t.n_in[l], l == 0 ? d_n : nullptr, l == 0 ? nullptr : t.cand[l - 1], t.cand[l], k));
+                       nullptr, nullptr, t.n_upper, t.d_nf, l == 0 ? t.filtered : t.cand[l - 1], t.cand[l], k, l));
     }
     TQP_LAUNCH(ctx, s, "topk_emit",
                k_topk_emit<<<1, 256, 0, s>>>(t.cand[t.levels - 1], k, cnt, out_key, out_sum, out_cnt, d_k));
@@ -202,7 +224,7 @@ tqp_status tqp_groupby_agg(tqp_ctx* ctx, const int32_t* gkey, int64_t n, const i
         ValsGather vs{reinterpret_cast<const int32_t*>(perm), sum_in, avg_in};
         SegOut o{out_key, out_sum, out_cnt, sa, gcap, d_ngroups};
         TQP_LAUNCH(ctx, stream, "segreduce_gather",
-                   k_segreduce<SCfg, ValsGather><<<grid_for(n, SCfg::TILE, 0), SCfg::BLOCK, 0, stream>>>(
+                   k_segreduce<SCfg, ValsGather, true><<<grid_for(n, SCfg::TILE, 0), SCfg::BLOCK, 0, stream>>>(
                        skeys, vs, n, b.d_cnt, sstatus, scounter, o, ctx->d_err));
         if (avg_in) {
             TQP_LAUNCH(ctx, stream, "avg",
@@ -226,6 +248,7 @@ tqp_status tqp_topk(tqp_ctx* ctx, const int32_t* key, const int64_t* sum, const 
     auto plan = [&](Arena& ar) { t = topk_reserve(ar, n, k); };
     tqp_status st = with_workspace(ctx, ws, ws_bytes, stream, plan, a);
     if (st != TQP_OK || !ws) return st;
+    if ((st = fill_zero(a.base, a.zsize, stream, ctx)) != TQP_OK) return st;
     return topk_launch(t, key, sum, cnt, d_n, k, out_key, out_sum, out_cnt, d_k, stream, ctx);
 }
 

@@ -69,7 +69,7 @@ __device__ __forceinline__ void seg_flush(const SegOut& o, int64_t seg, int64_t 
     }
 }
 
-template <class Cfg, class VS>
+template <class Cfg, class VS, bool AVG>
 __global__ void __launch_bounds__(Cfg::BLOCK)
 k_segreduce(const uint32_t* keys, VS vs, int64_t n_upper, const int64_t* d_n, uint64_t* status,
             uint32_t* tile_counter, SegOut out, uint32_t* flags) {
@@ -91,6 +91,7 @@ k_segreduce(const uint32_t* keys, VS vs, int64_t n_upper, const int64_t* d_n, ui
         return;
     }
 
+    // Keys and run heads of the wave's contiguous chunk, 64 per round.
     const int64_t chunk = tile * TILE + (int64_t)w * ITEMS * WAVE;
     uint32_t key[ITEMS];
     uint64_t hm[ITEMS];
@@ -142,11 +143,11 @@ k_segreduce(const uint32_t* keys, VS vs, int64_t n_upper, const int64_t* d_n, ui
         const int64_t seg = seg_base + heads_so_far + popc64(upto) - 1;
         const bool head = (h >> l) & 1;
         if (valid && head && seg < out.gcap) out.key[seg] = key[j];
-        int64_t v = 0, a = 0, c = 0;
-        if (valid) { vs.get(i, v, a); c = 1; }
-        v = wave_seg_incl_sum(v, h);
-        c = wave_seg_incl_sum(c, h);
-        a = wave_seg_incl_sum(a, h);
+        int64_t x = 0, y = 0;
+        if (valid) vs.get(i, x, y);
+        int64_t v = wave_seg_incl_sum(x, h);
+        int64_t c = wave_seg_incl_sum((int32_t)(valid ? 1 : 0), h);
+        int64_t a = AVG ? wave_seg_incl_sum(y, h) : 0;
         const bool cont = upto == 0;            // run began before this round
         if (cont && has_open) { v += open_v; c += open_c; a += open_a; }
         const bool here = cont ? (has_open && open_here) : true;
@@ -157,7 +158,7 @@ k_segreduce(const uint32_t* keys, VS vs, int64_t n_upper, const int64_t* d_n, ui
         if (i63 < n - 1) {                      // lane 63 valid and not the global end: run stays open
             open_v = __shfl(v, WAVE - 1, WAVE);
             open_c = __shfl(c, WAVE - 1, WAVE);
-            open_a = __shfl(a, WAVE - 1, WAVE);
+            if (AVG) open_a = __shfl(a, WAVE - 1, WAVE);
             open_seg = __shfl(seg, WAVE - 1, WAVE);
             open_here = __shfl((int)here, WAVE - 1, WAVE) != 0;
             has_open = true;
