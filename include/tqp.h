@@ -255,6 +255,37 @@ typedef struct {
 tqp_status tqp_fragment_cust(tqp_ctx* ctx, const tqp_cust_fragment* f, const tqp_cust_out* o,
                              void* ws, size_t* ws_bytes, hipStream_t stream);
 
+/* ---------------------------------------------------------------- batches
+ * Many flags fragments (each with its own fact and dim columns, D and c) run
+ * as one launch sequence: every stage is one persistent kernel over all
+ * fragments, pulling (fragment, tile) work items from a device counter.  The
+ * paper runs operators one after another (Section 4.3); batching fragments
+ * into shared launches is this library's addition.
+ *
+ * tqp_batch_create: with ws == NULL writes the workspace size to *ws_bytes.
+ * Otherwise prepares the batch over ws (device, 256-byte aligned, owned by
+ * the caller, kept by the batch until tqp_batch_destroy) and copies the
+ * descriptors to the device (synchronous).  Each fragment's results go to
+ * its tqp_flags_out, exactly as tqp_fragment_flags would write them.
+ * Configurations: 0 = 4-bit digits / 2048-row tiles, 1 = 8-bit / 2048,
+ * 2 = 8-bit / 4096 (default), 3 = 11-bit / 4096.
+ * tqp_batch_autotune runs every configuration `reps` times on `stream`, keeps
+ * the fastest and writes the mean time of each to times_ms[4] (nullable).
+ * tqp_batch_capture records the launch sequence of the chosen configuration
+ * into a hipGraph (stream must not be the null stream); tqp_batch_replay
+ * launches that graph.  Calls that share a batch must not overlap in time. */
+typedef struct tqp_batch tqp_batch;
+
+tqp_status tqp_batch_create(tqp_ctx* ctx, const tqp_flags_fragment* frags, const tqp_flags_out* outs, int nf,
+                            void* ws, size_t* ws_bytes, tqp_batch** out);
+void tqp_batch_destroy(tqp_batch* b);
+tqp_status tqp_batch_run(tqp_batch* b, hipStream_t stream);
+tqp_status tqp_batch_set_config(tqp_batch* b, int config);
+tqp_status tqp_batch_config(const tqp_batch* b, int* config, int* digit_bits, const char** name);
+tqp_status tqp_batch_autotune(tqp_batch* b, hipStream_t stream, int reps, float* times_ms);
+tqp_status tqp_batch_capture(tqp_batch* b, hipStream_t stream);
+tqp_status tqp_batch_replay(tqp_batch* b, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

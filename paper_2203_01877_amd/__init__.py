@@ -26,7 +26,7 @@ from ._lib import (DEVERR_CAPACITY, DEVERR_KEY_RANGE, DEVERR_SPIN, TQP_EQ, TQP_G
                    TQP_NE, TQPError, check)
 
 __all__ = ["Context", "filter", "sort", "join", "groupby_agg", "topk", "FlagsFragmentRunner",
-           "CustFragmentRunner", "TQPError", "TQP_LT", "TQP_LE", "TQP_GT", "TQP_GE", "TQP_EQ", "TQP_NE",
+           "CustFragmentRunner", "BatchRunner", "TQPError", "TQP_LT", "TQP_LE", "TQP_GT", "TQP_GE", "TQP_EQ", "TQP_NE",
            "DEVERR_KEY_RANGE", "DEVERR_SPIN", "DEVERR_CAPACITY"]
 
 _DTYPES = {torch.int8: _lib.TQP_I8, torch.int32: _lib.TQP_I32, torch.int64: _lib.TQP_I64}
@@ -267,6 +267,99 @@ class CustFragmentRunner:
             w = min(G, o["key"].numel())
             r.update(key=o["key"][:w].numpy(), sum=o["sum"][:w].numpy(), cnt=o["cnt"][:w].numpy())
         return r
+
+
+class BatchRunner:
+    """Many flags fragments in one launch sequence (persistent kernels over a device work queue),
+    with an autotuner and hipGraph capture / replay.
+
+    fragments: list of dicts with device columns fact / dim and D, c, key_bits (optional row0, n_fact).
+    Outputs for all fragments live in one set of device tensors [nf, 8]."""
+
+    CONFIGS = ("digit4_tile2048", "digit8_tile2048", "digit8_tile4096", "digit11_tile4096")
+
+    def __init__(self, ctx: Context, fragments: list):
+        self.ctx = ctx
+        dev = _dev(ctx)
+        nf = len(fragments)
+        self.nf = nf
+        self.fragments = fragments
+        self.out = {"key": torch.empty((max(1, nf), 8), dtype=torch.int32, device=dev),
+                    "sum": torch.empty((max(1, nf), 8), dtype=torch.int64, device=dev),
+                    "cnt": torch.empty((max(1, nf), 8), dtype=torch.int64, device=dev),
+                    "avg": torch.empty((max(1, nf), 8), dtype=torch.float64, device=dev),
+                    "d_ngroups": torch.empty(max(1, nf), dtype=torch.int64, device=dev),
+                    "d_join": torch.empty(max(1, nf), dtype=torch.int64, device=dev)}
+        descs = (_lib.FlagsFragment * max(1, nf))()
+        outs = (_lib.FlagsOut * max(1, nf))()
+        o = self.out
+        for i, fr in enumerate(fragments):
+            fact, dim = fr["fact"], fr["dim"]
+            row0 = fr.get("row0", 0)
+            n_fact = fr.get("n_fact", fact["fk"].numel() - row0)
+            descs[i] = _lib.FlagsFragment(fact["fk"].data_ptr(), fact["date"].data_ptr(), fact["price"].data_ptr(),
+                                          fact["disc"].data_ptr(), fact["flagA"].data_ptr(),
+                                          fact["flagB"].data_ptr(), row0, n_fact, dim["pk"].data_ptr(),
+                                          dim["seg"].data_ptr(), dim["pk"].numel(), fr["D"], fr["c"],
+                                          fr.get("key_bits", 0), 0)
+            outs[i] = _lib.FlagsOut(o["key"][i].data_ptr(), o["sum"][i].data_ptr(), o["cnt"][i].data_ptr(),
+                                    o["avg"][i].data_ptr(), o["d_ngroups"][i:].data_ptr(),
+                                    o["d_join"][i:].data_ptr())
+        self._descs, self._outs = descs, outs
+        sz = ctypes.c_size_t(0)
+        check(ctx.lib.tqp_batch_create(ctx.h, descs, outs, nf, None, ctypes.byref(sz), None),
+              "tqp_batch_create (size query)")
+        self.ws = torch.empty(max(256, sz.value), dtype=torch.uint8, device=dev)
+        h = ctypes.c_void_p()
+        check(ctx.lib.tqp_batch_create(ctx.h, descs, outs, nf, _p(self.ws), ctypes.byref(sz), ctypes.byref(h)),
+              "tqp_batch_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            torch.cuda.synchronize()
+            self.ctx.lib.tqp_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, stream=None):
+        check(self.ctx.lib.tqp_batch_run(self.h, _stream(stream)), "tqp_batch_run")
+
+    def set_config(self, config: int):
+        check(self.ctx.lib.tqp_batch_set_config(self.h, config), "tqp_batch_set_config")
+
+    def config(self) -> tuple:
+        c, d, name = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_char_p()
+        check(self.ctx.lib.tqp_batch_config(self.h, ctypes.byref(c), ctypes.byref(d), ctypes.byref(name)),
+              "tqp_batch_config")
+        return c.value, d.value, name.value.decode()
+
+    def autotune(self, reps: int = 3, stream=None) -> dict:
+        t = (ctypes.c_float * 4)()
+        check(self.ctx.lib.tqp_batch_autotune(self.h, _stream(stream), reps, t), "tqp_batch_autotune")
+        return {name: float(t[i]) for i, name in enumerate(self.CONFIGS)}
+
+    def capture(self, stream):
+        """Record the launch sequence into a hipGraph (stream must not be the default stream)."""
+        check(self.ctx.lib.tqp_batch_capture(self.h, _stream(stream)), "tqp_batch_capture")
+
+    def replay(self, stream=None):
+        check(self.ctx.lib.tqp_batch_replay(self.h, _stream(stream)), "tqp_batch_replay")
+
+    def results(self) -> list:
+        o = {k: v.cpu() for k, v in self.out.items()}
+        res = []
+        for i in range(self.nf):
+            G = int(o["d_ngroups"][i])
+            res.append({"key": o["key"][i, :G].numpy(), "sum": o["sum"][i, :G].numpy(),
+                        "cnt": o["cnt"][i, :G].numpy(), "avg": o["avg"][i, :G].numpy(),
+                        "join_rows": int(o["d_join"][i])})
+        return res
 
 
 def to_device(table: dict, device="cuda") -> dict:

@@ -99,6 +99,24 @@ def load() -> ctypes.CDLL:
     lib.tqp_fragment_cust.argtypes = [c_vp, ctypes.POINTER(CustFragment), ctypes.POINTER(CustOut), c_vp,
                                       c_size_p, c_vp]
     lib.tqp_fragment_cust.restype = S
+    lib.tqp_batch_create.argtypes = [c_vp, ctypes.POINTER(FlagsFragment), ctypes.POINTER(FlagsOut), c_int, c_vp,
+                                     c_size_p, ctypes.POINTER(c_vp)]
+    lib.tqp_batch_create.restype = S
+    lib.tqp_batch_destroy.argtypes = [c_vp]
+    lib.tqp_batch_destroy.restype = None
+    lib.tqp_batch_run.argtypes = [c_vp, c_vp]
+    lib.tqp_batch_run.restype = S
+    lib.tqp_batch_set_config.argtypes = [c_vp, c_int]
+    lib.tqp_batch_set_config.restype = S
+    lib.tqp_batch_config.argtypes = [c_vp, ctypes.POINTER(c_int), ctypes.POINTER(c_int),
+                                     ctypes.POINTER(ctypes.c_char_p)]
+    lib.tqp_batch_config.restype = S
+    lib.tqp_batch_autotune.argtypes = [c_vp, c_vp, c_int, ctypes.POINTER(ctypes.c_float)]
+    lib.tqp_batch_autotune.restype = S
+    lib.tqp_batch_capture.argtypes = [c_vp, c_vp]
+    lib.tqp_batch_capture.restype = S
+    lib.tqp_batch_replay.argtypes = [c_vp, c_vp]
+    lib.tqp_batch_replay.restype = S
     _lib = lib
     return lib
 

@@ -97,6 +97,7 @@ struct CustBufs {
 };
 
 __global__ void k_copy_i64(const int64_t* src, int64_t* dst);
+tqp_status check_flags(const tqp_flags_fragment* f, const tqp_flags_out* o);
 __global__ void k_flags_finalize(const int64_t* acc, const int64_t* d_join_in, tqp_flags_out o);
 
 }  // namespace tqp

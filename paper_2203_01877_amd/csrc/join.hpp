@@ -129,20 +129,25 @@ struct EmitFlagsAgg {
             p[k] += on ? pr : 0;
         }
     }
-    __device__ void finish(Smem& sm) {
+    // Block-wide sums of the register accumulators added to dst[G][3], which
+    // are then cleared (the batched join flushes after every tile).
+    __device__ void flush(Smem& sm, int64_t* dst) {
         const int w = threadIdx.x / WAVE;
 #pragma unroll
         for (int k = 0; k < G; ++k) {
             int64_t a = wave_sum(s[k]), b = wave_sum(c[k]), d = wave_sum(p[k]);
             if (lane_id() == 0) { sm.a[w][k * 3] = a; sm.a[w][k * 3 + 1] = b; sm.a[w][k * 3 + 2] = d; }
+            s[k] = 0; c[k] = 0; p[k] = 0;
         }
         __syncthreads();
         if (threadIdx.x < G * 3) {
             int64_t t = 0;
             for (int ww = 0; ww < BLOCK / WAVE; ++ww) t += sm.a[ww][threadIdx.x];
-            if (t) atomic_add(&acc[threadIdx.x], t);
+            if (t) atomic_add(&dst[threadIdx.x], t);
         }
+        __syncthreads();
     }
+    __device__ void finish(Smem& sm) { flush(sm, acc); }
 };
 
 // ------------------------------------------------------------------ kernels
@@ -152,117 +157,133 @@ __global__ void k_join_windows(const uint32_t* lkey, int64_t nl_upper, const int
                                const uint32_t* rkey, int64_t nr_upper, const int64_t* d_nr, int tile_size,
                                int64_t* win);
 
+template <class Cfg>
+struct JoinSmem {
+    uint32_t rkey[Cfg::RWIN];
+    int64_t wave[Cfg::WAVES];
+    int64_t base;
+    uint32_t tile;
+    int32_t seg;
+};
+
+// One left tile (shared by the single-input kernel and the batched kernel):
+// match counts from the tile's R window, output base by look-back, expansion
+// into the emitter.  ntiles is the number of tiles of this left input; the
+// last one stores the join size.
+template <class Cfg, class LP, class RP, class Emit>
+__device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, int64_t nl, const uint32_t* rkey,
+                                          const RP* rpay, int64_t wlo, int64_t whi, int64_t tile, int64_t ntiles,
+                                          uint64_t* status, int64_t* d_count, int64_t cap, Emit& e,
+                                          typename Emit::Smem& esm, JoinSmem<Cfg>& sm, uint32_t* flags) {
+    constexpr int TILE = Cfg::TILE, ITEMS = Cfg::ITEMS, RWIN = Cfg::RWIN, W = Cfg::WAVES;
+    const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
+    const int64_t wn = whi - wlo;
+    const bool in_lds = wn <= RWIN;
+    if (in_lds)
+        for (int i = tid; i < wn; i += Cfg::BLOCK) sm.rkey[i] = rkey[wlo + i];
+    // The wave's contiguous chunk of the tile, 64 elements per round.
+    const int64_t chunk = tile * TILE + (int64_t)w * ITEMS * WAVE;
+    uint32_t key[ITEMS];
+    LP pay[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int64_t i = chunk + j * WAVE + l;
+        key[j] = 0;
+        if (i < nl) {
+            key[j] = lkey[i];
+            pay[j] = lpay ? lpay[i] : (LP)i;
+        }
+    }
+    __syncthreads();
+    // Match count and first match of each element: rightHist of its key.
+    int32_t cnt[ITEMS];
+    int64_t first[ITEMS], off[ITEMS];      // off: exclusive offset of the element within the wave chunk
+    int64_t wave_total = 0;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int64_t i = chunk + j * WAVE + l;
+        cnt[j] = 0;
+        first[j] = 0;
+        if (i < nl) {
+            int64_t lb, ub;
+            if (in_lds) {
+                lb = wlo + lower_bound_lds(sm.rkey, (int)wn, key[j]);
+                ub = wlo + upper_bound_lds(sm.rkey, (int)wn, key[j]);
+            } else {
+                lb = lower_bound_glb(rkey, wlo, whi, key[j]);
+                ub = upper_bound_glb(rkey, lb, whi, key[j]);
+            }
+            first[j] = lb;
+            cnt[j] = (int32_t)(ub - lb);
+        }
+        const int64_t incl = wave_incl_sum((int64_t)cnt[j]);
+        off[j] = wave_total + incl - cnt[j];
+        wave_total += __shfl(incl, WAVE - 1, WAVE);
+    }
+    if (l == 0) sm.wave[w] = wave_total;
+    __syncthreads();
+    // Tile output base: block scan of the wave totals + decoupled look-back.
+    if (w == 0) {
+        int64_t tot = 0;
+        for (int ww = 0; ww < W; ++ww) tot += sm.wave[ww];
+        const int64_t base = lookback64(status, tile, tot, flags);
+        if (tid == 0) {
+            sm.base = base;
+            if (tile == ntiles - 1) {
+                *d_count = base + tot;
+                if (base + tot > cap) set_flag(flags, FLAG_CAPACITY);
+            }
+        }
+    }
+    __syncthreads();
+    int64_t wbase = sm.base;
+    for (int ww = 0; ww < w; ++ww) wbase += sm.wave[ww];
+    // Expansion: output o of element i pairs it with right element first + (o - offset(i)).
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int64_t o = wbase + off[j];
+        const bool small = cnt[j] <= JOIN_LANE_MAX;
+        if (small)
+            for (int t = 0; t < cnt[j]; ++t)
+                e(o + t, key[j], pay[j], rpay ? rpay[first[j] + t] : (RP)(first[j] + t), esm);
+        uint64_t heavy = ballot(!small);
+        while (heavy) {
+            const int src = __ffsll((unsigned long long)heavy) - 1;
+            heavy &= heavy - 1;
+            const int c = __shfl(cnt[j], src, WAVE);
+            const int64_t f = __shfl(first[j], src, WAVE);
+            const int64_t oo = __shfl(o, src, WAVE);
+            const uint32_t kk = __shfl(key[j], src, WAVE);
+            const LP pp = shfl_any(pay[j], src);
+            for (int q = l; q < c; q += WAVE) e(oo + q, kk, pp, rpay ? rpay[f + q] : (RP)(f + q), esm);
+        }
+    }
+    __syncthreads();
+}
+
 template <class Cfg, class LP, class RP, class Emit>
 __global__ void __launch_bounds__(Cfg::BLOCK)
 k_join(const uint32_t* lkey, const LP* lpay, int64_t nl_upper, const int64_t* d_nl,
        const uint32_t* rkey, const RP* rpay, int64_t nr_upper, const int64_t* d_nr, const int64_t* win,
        uint64_t* status, uint32_t* tile_counter, int64_t* d_count, int64_t cap, Emit emit,
        uint32_t* flags) {
-    constexpr int TILE = Cfg::TILE, ITEMS = Cfg::ITEMS, RWIN = Cfg::RWIN, W = Cfg::WAVES;
-    __shared__ uint32_t s_rkey[RWIN];
-    __shared__ int64_t s_wave[W];
-    __shared__ int64_t s_base;
-    __shared__ uint32_t s_tile;
+    __shared__ JoinSmem<Cfg> sm;
     __shared__ typename Emit::Smem esm;
-    const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
-
     int64_t nl = nl_upper;
     if (d_nl) { int64_t t = *d_nl; nl = t < nl ? t : nl; }
     (void)nr_upper;
     (void)d_nr;
-    const int64_t ntiles = (nl + TILE - 1) / TILE;
+    const int64_t ntiles = (nl + Cfg::TILE - 1) / Cfg::TILE;
     Emit e = emit;
     e.init(esm);
-    if (ntiles == 0 && blockIdx.x == 0 && tid == 0) *d_count = 0;
-
+    if (ntiles == 0 && blockIdx.x == 0 && threadIdx.x == 0) *d_count = 0;
     for (;;) {
-        if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
+        if (threadIdx.x == 0) sm.tile = atomicAdd(tile_counter, 1u);
         __syncthreads();
-        const int64_t tile = s_tile;
+        const int64_t tile = sm.tile;
         if (tile >= ntiles) break;
-        const int64_t wlo = win[2 * tile], whi = win[2 * tile + 1];
-        const int64_t wn = whi - wlo;
-        const bool in_lds = wn <= RWIN;
-        if (in_lds)
-            for (int i = tid; i < wn; i += Cfg::BLOCK) s_rkey[i] = rkey[wlo + i];
-        // The wave's contiguous chunk of the tile, 64 elements per round.
-        const int64_t chunk = tile * TILE + (int64_t)w * ITEMS * WAVE;
-        uint32_t key[ITEMS];
-        LP pay[ITEMS];
-#pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-            const int64_t i = chunk + j * WAVE + l;
-            key[j] = 0;
-            if (i < nl) {
-                key[j] = lkey[i];
-                pay[j] = lpay ? lpay[i] : (LP)i;
-            }
-        }
-        __syncthreads();
-        // Match count and first match of each element: rightHist of its key.
-        int32_t cnt[ITEMS];
-        int64_t first[ITEMS], off[ITEMS];      // off: exclusive offset of the element within the wave chunk
-        int64_t wave_total = 0;
-#pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-            const int64_t i = chunk + j * WAVE + l;
-            cnt[j] = 0;
-            first[j] = 0;
-            if (i < nl) {
-                int64_t lb, ub;
-                if (in_lds) {
-                    lb = wlo + lower_bound_lds(s_rkey, (int)wn, key[j]);
-                    ub = wlo + upper_bound_lds(s_rkey, (int)wn, key[j]);
-                } else {
-                    lb = lower_bound_glb(rkey, wlo, whi, key[j]);
-                    ub = upper_bound_glb(rkey, lb, whi, key[j]);
-                }
-                first[j] = lb;
-                cnt[j] = (int32_t)(ub - lb);
-            }
-            const int64_t incl = wave_incl_sum((int64_t)cnt[j]);
-            off[j] = wave_total + incl - cnt[j];
-            wave_total += __shfl(incl, WAVE - 1, WAVE);
-        }
-        if (l == 0) s_wave[w] = wave_total;
-        __syncthreads();
-        // Tile output base: block scan of the wave totals + decoupled look-back.
-        if (w == 0) {
-            int64_t tot = 0;
-            for (int ww = 0; ww < W; ++ww) tot += s_wave[ww];
-            const int64_t base = lookback64(status, tile, tot, flags);
-            if (tid == 0) {
-                s_base = base;
-                if (tile == ntiles - 1) {
-                    *d_count = base + tot;
-                    if (base + tot > cap) set_flag(flags, FLAG_CAPACITY);
-                }
-            }
-        }
-        __syncthreads();
-        int64_t wbase = s_base;
-        for (int ww = 0; ww < w; ++ww) wbase += s_wave[ww];
-        // Expansion: output o of element i pairs it with right element first + (o - offset(i)).
-#pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-            const int64_t o = wbase + off[j];
-            const bool small = cnt[j] <= JOIN_LANE_MAX;
-            if (small)
-                for (int t = 0; t < cnt[j]; ++t)
-                    e(o + t, key[j], pay[j], rpay ? rpay[first[j] + t] : (RP)(first[j] + t), esm);
-            uint64_t heavy = ballot(!small);
-            while (heavy) {
-                const int src = __ffsll((unsigned long long)heavy) - 1;
-                heavy &= heavy - 1;
-                const int c = __shfl(cnt[j], src, WAVE);
-                const int64_t f = __shfl(first[j], src, WAVE);
-                const int64_t oo = __shfl(o, src, WAVE);
-                const uint32_t kk = __shfl(key[j], src, WAVE);
-                const LP pp = shfl_any(pay[j], src);
-                for (int q = l; q < c; q += WAVE) e(oo + q, kk, pp, rpay ? rpay[f + q] : (RP)(f + q), esm);
-            }
-        }
-        __syncthreads();
+        join_tile<Cfg, LP, RP, Emit>(lkey, lpay, nl, rkey, rpay, win[2 * tile], win[2 * tile + 1], tile, ntiles,
+                                     status, d_count, cap, e, esm, sm, flags);
     }
     e.finish(esm);
 }

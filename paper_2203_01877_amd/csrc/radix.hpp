@@ -284,24 +284,19 @@ __device__ __forceinline__ uint32_t radix_lookback(const uint32_t* status, int64
     return excl;
 }
 
+// One tile of one pass (shared by the single-input kernel and the batched
+// kernel).  The caller has obtained the tile id in increasing order from a
+// counter, so every predecessor of the tile is held by a running block.
 template <class Cfg, class Src, class V>
-__global__ void __launch_bounds__(Cfg::BLOCK)
-k_radix_pass(Src src, DstPairs<V> dst, int shift, int bits, const uint32_t* hist,
-             uint32_t* status, uint32_t* tile_counter, uint32_t* flags) {
+__device__ __forceinline__ void radix_pass_tile(const Src& src, const DstPairs<V>& dst, int shift, int bits,
+                                                const uint32_t* hist, uint32_t* status, uint32_t tile,
+                                                int64_t n, uint32_t* flags, PassSmem<Cfg, V>& sm) {
     constexpr int R = Cfg::RADIX, ITEMS = Cfg::ITEMS, TILE = Cfg::TILE, W = Cfg::WAVES;
-    __shared__ PassSmem<Cfg, V> sm;
     const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
-
-    if (tid == 0) sm.tile = atomicAdd(tile_counter, 1u);
     for (int i = tid; i < W * R; i += Cfg::BLOCK) (&sm.u.wave_hist[0][0])[i] = 0;
     __syncthreads();
-    const uint32_t tile = sm.tile;
-    const int64_t n = src.size();
-    const int64_t ntiles = (n + TILE - 1) / TILE;
-    if ((int64_t)tile >= ntiles) return;
     const uint32_t dmask = (1u << bits) - 1;
     const int nd = (int)dmask + 1;            // digits of this pass (<= R)
-
     // Load: wave w owns the contiguous chunk [w*ITEMS*64, (w+1)*ITEMS*64) of the
     // tile, item j of lane l is element chunk + j*64 + l (coalesced loads).
     const int64_t base = (int64_t)tile * TILE + (int64_t)w * ITEMS * WAVE;
@@ -408,6 +403,19 @@ k_radix_pass(Src src, DstPairs<V> dst, int shift, int bits, const uint32_t* hist
         if constexpr (ValBytes<V>::value != 0) dst.store(g, k, sm.u.stage.vals[p]);
         else dst.store(g, k, NoVal{});
     }
+}
+
+template <class Cfg, class Src, class V>
+__global__ void __launch_bounds__(Cfg::BLOCK)
+k_radix_pass(Src src, DstPairs<V> dst, int shift, int bits, const uint32_t* hist,
+             uint32_t* status, uint32_t* tile_counter, uint32_t* flags) {
+    __shared__ PassSmem<Cfg, V> sm;
+    if (threadIdx.x == 0) sm.tile = atomicAdd(tile_counter, 1u);
+    __syncthreads();
+    const uint32_t tile = sm.tile;
+    const int64_t n = src.size();
+    if ((int64_t)tile >= (n + Cfg::TILE - 1) / Cfg::TILE) return;
+    radix_pass_tile<Cfg, Src, V>(src, dst, shift, bits, hist, status, tile, n, flags, sm);
 }
 
 }  // namespace tqp
