@@ -286,6 +286,96 @@ tqp_status tqp_batch_autotune(tqp_batch* b, hipStream_t stream, int reps, float*
 tqp_status tqp_batch_capture(tqp_batch* b, hipStream_t stream);
 tqp_status tqp_batch_replay(tqp_batch* b, hipStream_t stream);
 
+/* ---------------------------------------------------------------- serving
+ * A request loop over device-resident tables: requests are submitted from
+ * any host thread, stamped on arrival, admitted first-come first-served into
+ * free slots while the in-flight working set (each request's exact workspace
+ * and outputs) stays within budget_bytes, and launched at once on the slot's
+ * own stream, so requests that arrive while others run overlap on the device.
+ * Flags requests that wait together are launched as one batch (up to
+ * max_batch of them in one slot).  A background thread admits, launches and
+ * collects; results are read with tqp_server_poll.  With slots = 1 and
+ * max_batch = 1 the server runs one request at a time: the serial form.
+ *
+ * Resident tables (device, owned by the caller, unchanged while the server
+ * lives): the fact table carries two keys, fk_mid into the mid table and
+ * fk_dim into the dim table. */
+typedef struct {
+    const int32_t* fk_mid;
+    const int32_t* fk_dim;
+    const int32_t* date;
+    const int64_t* price;
+    const int64_t* disc;
+    const int8_t* flagA;
+    const int8_t* flagB;
+    int64_t n_fact;
+    const int32_t* mid_pk;
+    const int32_t* mid_custkey;
+    int64_t n_mid;
+    const int32_t* dim_pk;
+    const int8_t* dim_seg;
+    int64_t n_dim;
+    int32_t key_bits_mid;     /* fk_mid and mid_pk < 2^key_bits_mid */
+    int32_t key_bits_dim;     /* fk_dim and dim_pk < 2^key_bits_dim */
+    int32_t cust_bits;        /* custkey < 2^cust_bits */
+    int32_t slots;            /* requests on the device at once (1..64) */
+    int32_t max_batch;        /* flags requests coalesced into one launch (1..256) */
+    int32_t reserved;
+    int64_t max_flags_rows;   /* largest fact row range of a flags request */
+    size_t budget_bytes;      /* HBM working-set budget of in-flight requests */
+} tqp_server_config;
+
+#define TQP_REQ_CUST 0        /* custkey fragment over the whole fact table, top-k */
+#define TQP_REQ_FLAGS 1       /* flags fragment over fact rows [row0, row0 + n_rows) */
+#define TQP_TOPK_MAX 128
+
+typedef struct {
+    int32_t kind;             /* TQP_REQ_* */
+    int32_t D;
+    int32_t c;                /* flags: segment value */
+    int32_t k;                /* custkey: top rows, 1..TQP_TOPK_MAX */
+    int64_t row0;
+    int64_t n_rows;
+    uint64_t tag;             /* caller's value, returned with the result */
+} tqp_request;
+
+typedef struct {
+    uint64_t id;
+    uint64_t tag;
+    int32_t kind;
+    int32_t status;           /* TQP_OK, or the error of the launch */
+    int64_t join_rows;
+    int64_t groups;
+    int32_t key[8];           /* flags: groups in key order */
+    int64_t sum[8];
+    int64_t cnt[8];
+    double avg[8];
+    int32_t top_n;            /* custkey: rows in top_* */
+    int32_t top_key[TQP_TOPK_MAX];
+    int64_t top_sum[TQP_TOPK_MAX];
+    int64_t top_cnt[TQP_TOPK_MAX];
+    double t_arrival;         /* seconds on the server clock */
+    double t_admit;
+    double t_done;            /* result visible on the host */
+    int32_t slot;
+    int32_t batch_size;       /* requests launched together with this one */
+} tqp_result;
+
+typedef struct tqp_server tqp_server;
+
+tqp_status tqp_server_create(tqp_ctx* ctx, const tqp_server_config* cfg, tqp_server** out);
+void tqp_server_destroy(tqp_server* s);
+/* Seconds since the server was created (the clock of the t_* fields). */
+double tqp_server_now(const tqp_server* s);
+tqp_status tqp_server_submit(tqp_server* s, const tqp_request* req, uint64_t* id);
+/* Moves up to cap finished results to out; *n receives how many. */
+tqp_status tqp_server_poll(tqp_server* s, tqp_result* out, int cap, int* n);
+/* Blocks until every submitted request has finished. */
+tqp_status tqp_server_drain(tqp_server* s);
+/* Counters: requests submitted, finished, launches, peak in-flight bytes. */
+tqp_status tqp_server_stats(const tqp_server* s, uint64_t* submitted, uint64_t* finished, uint64_t* launches,
+                            size_t* peak_bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,7 +26,7 @@ from ._lib import (DEVERR_CAPACITY, DEVERR_KEY_RANGE, DEVERR_SPIN, TQP_EQ, TQP_G
                    TQP_NE, TQPError, check)
 
 __all__ = ["Context", "filter", "sort", "join", "groupby_agg", "topk", "FlagsFragmentRunner",
-           "CustFragmentRunner", "BatchRunner", "TQPError", "TQP_LT", "TQP_LE", "TQP_GT", "TQP_GE", "TQP_EQ", "TQP_NE",
+           "CustFragmentRunner", "BatchRunner", "Server", "TQPError", "TQP_LT", "TQP_LE", "TQP_GT", "TQP_GE", "TQP_EQ", "TQP_NE",
            "DEVERR_KEY_RANGE", "DEVERR_SPIN", "DEVERR_CAPACITY"]
 
 _DTYPES = {torch.int8: _lib.TQP_I8, torch.int32: _lib.TQP_I32, torch.int64: _lib.TQP_I64}
@@ -360,6 +360,82 @@ class BatchRunner:
                         "cnt": o["cnt"][i, :G].numpy(), "avg": o["avg"][i, :G].numpy(),
                         "join_rows": int(o["d_join"][i])})
         return res
+
+
+class Server:
+    """Request loop over device-resident tables (tqp_server_*): requests are stamped on submit,
+    admitted into slots under an HBM budget, launched on per-slot streams (waiting flags requests
+    coalesced into one batch), and finished results are polled.  The server uses its own context
+    from a background thread."""
+
+    def __init__(self, tables: dict, slots: int = 8, max_batch: int = 32, max_flags_rows: int = 4_000_000,
+                 budget_bytes: int = 200 << 30, key_bits_mid: int = 0, key_bits_dim: int = 0, cust_bits: int = 0,
+                 device: int = 0):
+        self.ctx = Context(device)
+        self.tables = tables
+        f, m, d = tables["fact"], tables["mid"], tables["dim"]
+        cfg = _lib.ServerConfig(f["fk"].data_ptr(), f["fk_dim"].data_ptr(), f["date"].data_ptr(),
+                                f["price"].data_ptr(), f["disc"].data_ptr(), f["flagA"].data_ptr(),
+                                f["flagB"].data_ptr(), f["fk"].numel(), m["pk"].data_ptr(), m["custkey"].data_ptr(),
+                                m["pk"].numel(), d["pk"].data_ptr(), d["seg"].data_ptr(), d["pk"].numel(),
+                                key_bits_mid, key_bits_dim, cust_bits, slots, max_batch, 0,
+                                min(max_flags_rows, f["fk"].numel()), budget_bytes)
+        h = ctypes.c_void_p()
+        torch.cuda.synchronize()
+        check(self.ctx.lib.tqp_server_create(self.ctx.h, ctypes.byref(cfg), ctypes.byref(h)), "tqp_server_create")
+        self.h = h
+        self._buf = (_lib.Result * 1024)()
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.tqp_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def now(self) -> float:
+        return float(self.ctx.lib.tqp_server_now(self.h))
+
+    def submit(self, kind: int, D: int, c: int = 0, k: int = 100, row0: int = 0, n_rows: int = 0,
+               tag: int = 0) -> int:
+        rid = ctypes.c_uint64(0)
+        req = _lib.Request(kind, D, c, k, row0, n_rows, tag)
+        check(self.ctx.lib.tqp_server_submit(self.h, ctypes.byref(req), ctypes.byref(rid)), "tqp_server_submit")
+        return int(rid.value)
+
+    def poll(self) -> list:
+        out = []
+        while True:
+            n = ctypes.c_int(0)
+            check(self.ctx.lib.tqp_server_poll(self.h, self._buf, len(self._buf), ctypes.byref(n)), "tqp_server_poll")
+            for i in range(n.value):
+                r = self._buf[i]
+                d = {"id": r.id, "tag": r.tag, "kind": r.kind, "status": r.status, "join_rows": r.join_rows,
+                     "groups": r.groups, "t_arrival": r.t_arrival, "t_admit": r.t_admit, "t_done": r.t_done,
+                     "slot": r.slot, "batch_size": r.batch_size}
+                if r.kind == _lib.REQ_FLAGS:
+                    G = max(0, min(8, r.groups))
+                    d.update(key=list(r.key[:G]), sum=list(r.sum[:G]), cnt=list(r.cnt[:G]), avg=list(r.avg[:G]))
+                else:
+                    T = max(0, min(_lib.TOPK_MAX, r.top_n))
+                    d.update(top_key=list(r.top_key[:T]), top_sum=list(r.top_sum[:T]), top_cnt=list(r.top_cnt[:T]))
+                out.append(d)
+            if n.value < len(self._buf):
+                return out
+
+    def drain(self):
+        check(self.ctx.lib.tqp_server_drain(self.h), "tqp_server_drain")
+
+    def stats(self) -> dict:
+        a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        p = ctypes.c_size_t()
+        check(self.ctx.lib.tqp_server_stats(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(p)),
+              "tqp_server_stats")
+        return {"submitted": a.value, "finished": b.value, "launches": c.value, "peak_bytes": p.value}
 
 
 def to_device(table: dict, device="cuda") -> dict:

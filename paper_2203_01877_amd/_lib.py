@@ -52,6 +52,31 @@ class CustOut(ctypes.Structure):
                 ("d_join", c_vp), ("top_key", c_vp), ("top_sum", c_vp), ("top_cnt", c_vp), ("d_topk", c_vp)]
 
 
+TOPK_MAX = 128
+REQ_CUST, REQ_FLAGS = 0, 1
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("fk_mid", c_vp), ("fk_dim", c_vp), ("date", c_vp), ("price", c_vp), ("disc", c_vp),
+                ("flagA", c_vp), ("flagB", c_vp), ("n_fact", c_i64), ("mid_pk", c_vp), ("mid_custkey", c_vp),
+                ("n_mid", c_i64), ("dim_pk", c_vp), ("dim_seg", c_vp), ("n_dim", c_i64), ("key_bits_mid", c_i32),
+                ("key_bits_dim", c_i32), ("cust_bits", c_i32), ("slots", c_i32), ("max_batch", c_i32),
+                ("reserved", c_i32), ("max_flags_rows", c_i64), ("budget_bytes", ctypes.c_size_t)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("kind", c_i32), ("D", c_i32), ("c", c_i32), ("k", c_i32), ("row0", c_i64), ("n_rows", c_i64),
+                ("tag", ctypes.c_uint64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("tag", ctypes.c_uint64), ("kind", c_i32), ("status", c_i32),
+                ("join_rows", c_i64), ("groups", c_i64), ("key", c_i32 * 8), ("sum", c_i64 * 8), ("cnt", c_i64 * 8),
+                ("avg", ctypes.c_double * 8), ("top_n", c_i32), ("top_key", c_i32 * TOPK_MAX),
+                ("top_sum", c_i64 * TOPK_MAX), ("top_cnt", c_i64 * TOPK_MAX), ("t_arrival", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double), ("slot", c_i32), ("batch_size", c_i32)]
+
+
 _lib = None
 
 
@@ -117,6 +142,21 @@ def load() -> ctypes.CDLL:
     lib.tqp_batch_capture.restype = S
     lib.tqp_batch_replay.argtypes = [c_vp, c_vp]
     lib.tqp_batch_replay.restype = S
+    lib.tqp_server_create.argtypes = [c_vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(c_vp)]
+    lib.tqp_server_create.restype = S
+    lib.tqp_server_destroy.argtypes = [c_vp]
+    lib.tqp_server_destroy.restype = None
+    lib.tqp_server_now.argtypes = [c_vp]
+    lib.tqp_server_now.restype = ctypes.c_double
+    lib.tqp_server_submit.argtypes = [c_vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+    lib.tqp_server_submit.restype = S
+    lib.tqp_server_poll.argtypes = [c_vp, ctypes.POINTER(Result), c_int, ctypes.POINTER(c_int)]
+    lib.tqp_server_poll.restype = S
+    lib.tqp_server_drain.argtypes = [c_vp]
+    lib.tqp_server_drain.restype = S
+    lib.tqp_server_stats.argtypes = [c_vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
+                                     ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_size_t)]
+    lib.tqp_server_stats.restype = S
     _lib = lib
     return lib
 

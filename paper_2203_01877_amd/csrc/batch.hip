@@ -283,9 +283,17 @@ struct CandPlan {
 
 }  // namespace
 
+// Host copies of one configuration's descriptor tables.
+struct HostTables {
+    std::vector<BatchSeg> segs;
+    std::vector<BatchFrag> frags;
+    std::vector<int64_t> hist_prefix, pass_prefix, join_prefix;
+};
+
 struct tqp_batch {
     tqp_ctx* ctx = nullptr;
     int nf = 0;
+    int cand_mask = (1 << NCAND) - 1;    // configurations planned in the workspace
     std::vector<tqp_flags_fragment> frags;
     std::vector<tqp_flags_out> outs;
     char* ws = nullptr;
@@ -294,7 +302,7 @@ struct tqp_batch {
     int chosen = CAND_R8;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    void* dev_tables = nullptr;          // descriptor tables of all candidates
+    std::vector<HostTables>* host = nullptr;   // host copies of the descriptor tables (kept for async uploads)
     float tuned_ms[NCAND] = {0, 0, 0, 0};
 };
 
@@ -306,11 +314,6 @@ int cand_radix_bits() { return Cfg::RADIX_BITS; }
 // Lays out (or sizes, when base is null) every candidate's workspace and
 // builds its descriptor tables on the host.  Scratch buffers (the ping-pong
 // keys and row ids) are shared; each candidate has its own zero region.
-struct HostTables {
-    std::vector<BatchSeg> segs;
-    std::vector<BatchFrag> frags;
-    std::vector<int64_t> hist_prefix, pass_prefix, join_prefix;
-};
 
 template <class Cfg>
 void plan_candidate(tqp_batch* b, int c, char* base, size_t& off, size_t scratch_off, HostTables& ht) {
@@ -415,16 +418,64 @@ void for_each_cand(int c, F&& f) {
     }
 }
 
-// Zero regions of all candidates follow the shared scratch.
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+size_t tables_bytes(int nf) {
+    const int S = 2 * nf;
+    return align256(sizeof(BatchSeg) * std::max(1, S)) + align256(sizeof(BatchFrag) * std::max(1, nf)) +
+           align256(sizeof(int64_t) * (S + 1)) + align256(sizeof(int64_t) * 8 * (S + 1)) +
+           align256(sizeof(int64_t) * (nf + 1));
+}
+
+// Workspace: shared scratch, then each planned configuration's zero region,
+// then each planned configuration's descriptor tables.
 size_t plan_all(tqp_batch* b, char* base, std::vector<HostTables>* tables) {
     const size_t scratch = scratch_bytes(b);
     size_t off = scratch;
     for (int c = 0; c < NCAND; ++c) {
+        if (!(b->cand_mask & (1 << c))) continue;
         HostTables ht;
         for_each_cand(c, [&](auto cfg) { plan_candidate<decltype(cfg)>(b, c, base, off, 0, ht); });
         if (tables) (*tables)[c] = std::move(ht);
     }
-    return (off + 255) & ~size_t(255);
+    off = align256(off);
+    for (int c = 0; c < NCAND; ++c) {
+        if (!(b->cand_mask & (1 << c))) continue;
+        CandPlan& cp = b->cand[c];
+        const int S = 2 * b->nf, nf = b->nf;
+        char* p = base ? base + off : nullptr;
+        auto adv = [&](size_t bytes) { char* q = p; if (p) p += align256(bytes); off += align256(bytes); return q; };
+        cp.d_segs = (BatchSeg*)adv(sizeof(BatchSeg) * std::max(1, S));
+        cp.d_frags = (BatchFrag*)adv(sizeof(BatchFrag) * std::max(1, nf));
+        cp.d_hist_prefix = (int64_t*)adv(sizeof(int64_t) * (S + 1));
+        cp.d_pass_prefix = (int64_t*)adv(sizeof(int64_t) * 8 * (S + 1));
+        cp.d_join_prefix = (int64_t*)adv(sizeof(int64_t) * (nf + 1));
+    }
+    return align256(off);
+}
+
+// Copies the planned descriptor tables to the workspace (asynchronously on
+// `stream` when given; the host copies stay alive in the batch).
+tqp_status upload_tables(tqp_batch* b, hipStream_t stream, bool sync) {
+    const int S = 2 * b->nf, nf = b->nf;
+    for (int c = 0; c < NCAND; ++c) {
+        if (!(b->cand_mask & (1 << c))) continue;
+        CandPlan& cp = b->cand[c];
+        HostTables& ht = (*b->host)[c];
+        struct { void* d; const void* h; size_t n; } cps[5] = {
+            {cp.d_segs, ht.segs.data(), sizeof(BatchSeg) * S},
+            {cp.d_frags, ht.frags.data(), sizeof(BatchFrag) * nf},
+            {cp.d_hist_prefix, ht.hist_prefix.data(), sizeof(int64_t) * (S + 1)},
+            {cp.d_pass_prefix, ht.pass_prefix.data(), sizeof(int64_t) * 8 * (S + 1)},
+            {cp.d_join_prefix, ht.join_prefix.data(), sizeof(int64_t) * (nf + 1)}};
+        for (auto& x : cps) {
+            if (!x.n) continue;
+            hipError_t e = sync ? hipMemcpy(x.d, x.h, x.n, hipMemcpyHostToDevice)
+                                : hipMemcpyAsync(x.d, x.h, x.n, hipMemcpyHostToDevice, stream);
+            if (e != hipSuccess) return fail(TQP_ERR_HIP, "batch descriptor upload: %s", hipGetErrorString(e));
+        }
+    }
+    return TQP_OK;
 }
 
 template <class Cfg>
@@ -473,75 +524,66 @@ void drop_graph(tqp_batch* b) {
 
 }  // namespace
 
+namespace tqp {
+
+tqp_status batch_prepare(tqp_ctx* ctx, const tqp_flags_fragment* frags, const tqp_flags_out* outs, int nf,
+                         int cand_mask, int chosen, void* ws, size_t* ws_bytes, hipStream_t stream, bool sync,
+                         tqp_batch** out) {
+    if (!ctx || !ws_bytes || nf < 0 || (nf > 0 && (!frags || !outs)))
+        return fail(TQP_ERR_INVALID, "batch: bad argument");
+    for (int f = 0; f < nf; ++f) {
+        tqp_status st = check_flags(&frags[f], &outs[f]);
+        if (st != TQP_OK) return st;
+    }
+    tqp_batch* b = new tqp_batch;
+    b->ctx = ctx;
+    b->nf = nf;
+    b->cand_mask = cand_mask;
+    b->chosen = chosen;
+    b->frags.assign(frags, frags + nf);
+    b->outs.assign(outs, outs + nf);
+    const size_t need = plan_all(b, nullptr, nullptr);
+    if (!ws) {
+        *ws_bytes = need;
+        delete b;
+        return TQP_OK;
+    }
+    tqp_status st = TQP_OK;
+    if (!out) st = fail(TQP_ERR_INVALID, "batch: out is null");
+    else if (*ws_bytes < need) st = fail(TQP_ERR_WORKSPACE, "batch workspace of %zu bytes, %zu needed", *ws_bytes, need);
+    else if (reinterpret_cast<uintptr_t>(ws) & 255) st = fail(TQP_ERR_INVALID, "workspace not 256-byte aligned");
+    if (st != TQP_OK) { delete b; return st; }
+    b->ws = static_cast<char*>(ws);
+    b->ws_bytes = *ws_bytes;
+    b->host = new std::vector<HostTables>(NCAND);
+    plan_all(b, b->ws, b->host);
+    if ((st = upload_tables(b, stream, sync)) != TQP_OK) {
+        delete b->host;
+        delete b;
+        return st;
+    }
+    *out = b;
+    return TQP_OK;
+}
+
+tqp_status batch_launch(tqp_batch* b, hipStream_t stream) { return run_candidate(b, b->chosen, stream); }
+
+void batch_free(tqp_batch* b) { tqp_batch_destroy(b); }
+
+}  // namespace tqp
+
 extern "C" {
 
 tqp_status tqp_batch_create(tqp_ctx* ctx, const tqp_flags_fragment* frags, const tqp_flags_out* outs, int nf, void* ws,
                             size_t* ws_bytes, tqp_batch** out) {
     clear_error();
-    if (!ctx || !ws_bytes || nf < 0 || (nf > 0 && (!frags || !outs))) return fail(TQP_ERR_INVALID, "tqp_batch_create: bad argument");
-    for (int f = 0; f < nf; ++f) {
-        tqp_status st = check_flags(&frags[f], &outs[f]);
-        if (st != TQP_OK) return st;
-    }
-    tqp_batch tmp;
-    tmp.ctx = ctx;
-    tmp.nf = nf;
-    tmp.frags.assign(frags, frags + nf);
-    tmp.outs.assign(outs, outs + nf);
-    const size_t need = plan_all(&tmp, nullptr, nullptr);
-    if (!ws) {
-        *ws_bytes = need;
-        return TQP_OK;
-    }
-    if (!out) return fail(TQP_ERR_INVALID, "tqp_batch_create: out is null");
-    if (*ws_bytes < need) return fail(TQP_ERR_WORKSPACE, "batch workspace of %zu bytes, %zu needed", *ws_bytes, need);
-    if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(TQP_ERR_INVALID, "workspace not 256-byte aligned");
-    tqp_batch* b = new tqp_batch(tmp);
-    b->ws = static_cast<char*>(ws);
-    b->ws_bytes = *ws_bytes;
-    std::vector<HostTables> tables(NCAND);
-    plan_all(b, b->ws, &tables);
-    // One device allocation holds every candidate's descriptor tables.
-    const int S = 2 * nf;
-    size_t per = 0;
-    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-    per += al(sizeof(BatchSeg) * std::max(1, S)) + al(sizeof(BatchFrag) * std::max(1, nf)) +
-           al(sizeof(int64_t) * (S + 1)) + al(sizeof(int64_t) * 8 * (S + 1)) + al(sizeof(int64_t) * (nf + 1));
-    if (hipMalloc(&b->dev_tables, per * NCAND) != hipSuccess) {
-        delete b;
-        return fail(TQP_ERR_HIP, "tqp_batch_create: descriptor table allocation failed");
-    }
-    for (int c = 0; c < NCAND; ++c) {
-        char* p = static_cast<char*>(b->dev_tables) + per * c;
-        CandPlan& cp = b->cand[c];
-        HostTables& ht = tables[c];
-        cp.d_segs = (BatchSeg*)p; p += al(sizeof(BatchSeg) * std::max(1, S));
-        cp.d_frags = (BatchFrag*)p; p += al(sizeof(BatchFrag) * std::max(1, nf));
-        cp.d_hist_prefix = (int64_t*)p; p += al(sizeof(int64_t) * (S + 1));
-        cp.d_pass_prefix = (int64_t*)p; p += al(sizeof(int64_t) * 8 * (S + 1));
-        cp.d_join_prefix = (int64_t*)p;
-        hipError_t e = hipSuccess;
-        if (S) e = hipMemcpy(cp.d_segs, ht.segs.data(), sizeof(BatchSeg) * S, hipMemcpyHostToDevice);
-        if (e == hipSuccess && nf) e = hipMemcpy(cp.d_frags, ht.frags.data(), sizeof(BatchFrag) * nf, hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(cp.d_hist_prefix, ht.hist_prefix.data(), sizeof(int64_t) * (S + 1), hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(cp.d_pass_prefix, ht.pass_prefix.data(), sizeof(int64_t) * 8 * (S + 1), hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(cp.d_join_prefix, ht.join_prefix.data(), sizeof(int64_t) * (nf + 1), hipMemcpyHostToDevice);
-        if (e != hipSuccess) {
-            (void)hipFree(b->dev_tables);
-            delete b;
-            return fail(TQP_ERR_HIP, "tqp_batch_create: upload failed: %s", hipGetErrorString(e));
-        }
-    }
-    b->chosen = CAND_R8;
-    *out = b;
-    return TQP_OK;
+    return batch_prepare(ctx, frags, outs, nf, (1 << NCAND) - 1, CAND_R8, ws, ws_bytes, nullptr, true, out);
 }
 
 void tqp_batch_destroy(tqp_batch* b) {
     if (!b) return;
     drop_graph(b);
-    (void)hipDeviceSynchronize();
-    if (b->dev_tables) (void)hipFree(b->dev_tables);
+    delete b->host;
     delete b;
 }
 
@@ -553,7 +595,8 @@ tqp_status tqp_batch_run(tqp_batch* b, hipStream_t stream) {
 
 tqp_status tqp_batch_set_config(tqp_batch* b, int config) {
     clear_error();
-    if (!b || config < 0 || config >= NCAND) return fail(TQP_ERR_INVALID, "tqp_batch_set_config: config %d", config);
+    if (!b || config < 0 || config >= NCAND || !(b->cand_mask & (1 << config)))
+        return fail(TQP_ERR_INVALID, "tqp_batch_set_config: config %d", config);
     if (config != b->chosen) drop_graph(b);
     b->chosen = config;
     return TQP_OK;
@@ -579,6 +622,7 @@ tqp_status tqp_batch_autotune(tqp_batch* b, hipStream_t stream, int reps, float*
     int best = b->chosen;
     float best_ms = 0.f;
     for (int c = 0; c < NCAND; ++c) {
+        if (!(b->cand_mask & (1 << c))) continue;
         tqp_status st = run_candidate(b, c, stream);          // warm-up
         if (st != TQP_OK) { b->ctx->prof = prof; return st; }
         TQP_TRY_HIP(hipEventRecord(e0, stream));
@@ -593,7 +637,7 @@ tqp_status tqp_batch_autotune(tqp_batch* b, hipStream_t stream, int reps, float*
         ms /= reps;
         b->tuned_ms[c] = ms;
         if (times_ms) times_ms[c] = ms;
-        if (c == 0 || ms < best_ms) { best_ms = ms; best = c; }
+        if (best_ms == 0.f || ms < best_ms) { best_ms = ms; best = c; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -98,6 +98,16 @@ struct CustBufs {
 
 __global__ void k_copy_i64(const int64_t* src, int64_t* dst);
 tqp_status check_flags(const tqp_flags_fragment* f, const tqp_flags_out* o);
+
+// Batch preparation without any allocation: descriptor tables go into the
+// workspace, uploaded on `stream` (or synchronously); only the configurations
+// in cand_mask are planned.  Used by tqp_batch_create and by the server.
+tqp_status batch_prepare(tqp_ctx* ctx, const tqp_flags_fragment* frags, const tqp_flags_out* outs, int nf,
+                         int cand_mask, int chosen, void* ws, size_t* ws_bytes, hipStream_t stream, bool sync,
+                         tqp_batch** out);
+tqp_status batch_launch(tqp_batch* b, hipStream_t stream);
+void batch_free(tqp_batch* b);
+constexpr int BATCH_CONFIG_DEFAULT = 2;
 __global__ void k_flags_finalize(const int64_t* acc, const int64_t* d_join_in, tqp_flags_out o);
 
 }  // namespace tqp

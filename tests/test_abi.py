@@ -58,3 +58,33 @@ def test_binding_struct_layouts_match_header():
     assert ctypes.sizeof(L.FlagsOut) == 6 * 8
     assert ctypes.sizeof(L.CustFragment) == 4 * 8 + 8 + 2 * 8 + 8 + 4 * 4 + 8
     assert ctypes.sizeof(L.CustOut) == 3 * 8 + 8 + 6 * 8
+
+
+def test_struct_layouts_match_the_c_header(tmp_path):
+    """Sizes and field offsets of every struct in include/tqp.h, as the host compiler lays them out,
+    equal those of the ctypes declarations of the binding."""
+    import shutil
+    import subprocess
+    import paper_2203_01877_amd._lib as L
+    if not shutil.which("g++"):
+        pytest.skip("no g++")
+    structs = {"tqp_column": L.Column, "tqp_pred": L.Pred, "tqp_flags_fragment": L.FlagsFragment,
+               "tqp_flags_out": L.FlagsOut, "tqp_cust_fragment": L.CustFragment, "tqp_cust_out": L.CustOut,
+               "tqp_prof_entry": L.ProfEntry, "tqp_server_config": L.ServerConfig, "tqp_request": L.Request,
+               "tqp_result": L.Result}
+    lines = ['#include "tqp.h"', "#include <cstddef>", "#include <cstdio>", "int main() {"]
+    for cname, py in structs.items():
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
+        for fname, _ in py._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, fname, cname, fname))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.cpp"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["g++", "-std=c++17", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+                           "-I", "/opt/rocm/include", str(src), "-o", str(exe)])
+    got = dict(line.split() for line in subprocess.check_output([str(exe)]).decode().splitlines())
+    for cname, py in structs.items():
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert int(got["%s.%s" % (cname, fname)]) == getattr(py, fname).offset, (cname, fname)
