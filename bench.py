@@ -204,9 +204,13 @@ def main():
     if args.with_copy:
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
+        ctx.set_profiling(True)
         for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
+            ctx.copy(dst, src, 1 << 30)
+        copy_ms = [t for _, t in ctx.profile_read()]
+        ctx.set_profiling(False)
+        out["copy_1GiB_ms"] = round(sum(copy_ms) / len(copy_ms), 4)
+        out["copy_GBps"] = round(2 * (1 << 30) / (sum(copy_ms) / len(copy_ms) * 1e-3) / 1e9, 1)
 
     if not args.no_cpu_baseline:
         import oracle

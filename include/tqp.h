@@ -102,6 +102,11 @@ tqp_status tqp_ctx_errors(tqp_ctx* ctx, hipStream_t stream, uint32_t* errors, in
  * of 8).  The batch autotuner sets it per workload. */
 tqp_status tqp_ctx_set_digit_bits(tqp_ctx* ctx, int bits);
 
+/* Plain device-to-device copy of `bytes` (a multiple of 16, 16-byte aligned
+ * pointers) with one streaming kernel: moves columns, and is the reference
+ * kernel of known size against which hardware traffic counters are read. */
+tqp_status tqp_copy(tqp_ctx* ctx, void* dst, const void* src, size_t bytes, hipStream_t stream);
+
 /* Per-launch timing.  While profiling is on, every kernel the library
  * launches is bracketed by two events recorded on the launch stream (this
  * adds a little host work per launch).  tqp_ctx_profile_read synchronises

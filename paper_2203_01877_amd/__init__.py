@@ -71,6 +71,10 @@ class Context:
     def set_digit_bits(self, bits: int) -> None:
         check(self.lib.tqp_ctx_set_digit_bits(self.h, bits), "tqp_ctx_set_digit_bits")
 
+    def copy(self, dst, src, nbytes: int, stream=None) -> None:
+        """Device copy of nbytes (multiple of 16) with the library's streaming copy kernel."""
+        check(self.lib.tqp_copy(self.h, _p(dst), _p(src), nbytes, _stream(stream)), "tqp_copy")
+
     def set_profiling(self, on: bool) -> None:
         check(self.lib.tqp_ctx_set_profiling(self.h, int(bool(on))), "tqp_ctx_set_profiling")
 

@@ -100,6 +100,8 @@ def load() -> ctypes.CDLL:
     lib.tqp_ctx_errors.restype = S
     lib.tqp_ctx_set_digit_bits.argtypes = [c_vp, c_int]
     lib.tqp_ctx_set_digit_bits.restype = S
+    lib.tqp_copy.argtypes = [c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]
+    lib.tqp_copy.restype = S
     lib.tqp_ctx_set_profiling.argtypes = [c_vp, c_int]
     lib.tqp_ctx_set_profiling.restype = S
     lib.tqp_ctx_profile_read.argtypes = [c_vp, c_vp, ctypes.POINTER(ProfEntry), c_int, ctypes.POINTER(c_int)]

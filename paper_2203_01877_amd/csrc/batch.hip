@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(Cfg::BLOCK)
 k_batch_join(const BatchSeg* segs, const BatchFrag* frags, int nfrag, const int64_t* prefix, uint32_t* counter,
              uint32_t* flags) {
     using Emit = EmitFlagsAgg<Cfg::BLOCK>;
-    __shared__ JoinSmem<Cfg> sm;
+    __shared__ JoinSmem<Cfg, uint32_t> sm;
     __shared__ typename Emit::Smem esm;
     __shared__ int64_t s_item;
     const int64_t total = prefix[nfrag];
@@ -257,7 +257,7 @@ using namespace tqp;
 // ------------------------------------------------------------------ host side
 namespace {
 
-using BJCfg = JoinCfg<256, 8, 4096>;
+using BJCfg = JoinCfg<256, 8, 2048>;
 
 // Candidate configurations the autotuner times.
 enum { CAND_R4 = 0, CAND_R8S = 1, CAND_R8 = 2, CAND_R11 = 3, NCAND = 4 };

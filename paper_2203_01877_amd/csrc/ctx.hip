@@ -26,6 +26,11 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
+__global__ void k_copy_u128(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
 __global__ void k_fill_u128(uint4* p, int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const uint4 z = make_uint4(0, 0, 0, 0);
@@ -168,6 +173,13 @@ tqp_status tqp_ctx_create(int device, tqp_ctx** out) {
         delete c;
         return fail(TQP_ERR_HIP, "clearing the error word failed");
     }
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->join, hipEventDisableTiming) != hipSuccess) {
+        (void)hipFree(c->d_err);
+        delete c;
+        return fail(TQP_ERR_HIP, "creating the side stream failed");
+    }
     *out = c;
     return TQP_OK;
 }
@@ -181,6 +193,9 @@ void tqp_ctx_destroy(tqp_ctx* ctx) {
         (void)hipEventDestroy(r.b);
     }
     for (auto e : ctx->pool) (void)hipEventDestroy(e);
+    if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+    if (ctx->join) (void)hipEventDestroy(ctx->join);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
     (void)hipFree(ctx->d_err);
     delete ctx;
 }
@@ -197,6 +212,7 @@ tqp_status tqp_ctx_profile_read(tqp_ctx* ctx, hipStream_t stream, tqp_prof_entry
     if (!ctx || !n || (cap > 0 && !out)) return fail(TQP_ERR_INVALID, "null argument");
     TQP_TRY_HIP(hipStreamSynchronize(stream));
     TQP_TRY_HIP(hipDeviceSynchronize());
+    TQP_TRY_HIP(hipStreamSynchronize(ctx->side));
     int w = 0;
     for (auto& r : ctx->recs) {
         if (w < cap) {
@@ -223,6 +239,19 @@ tqp_status tqp_ctx_errors(tqp_ctx* ctx, hipStream_t stream, uint32_t* errors, in
         TQP_TRY_HIP(hipMemset(ctx->d_err, 0, sizeof(uint32_t)));
         TQP_TRY_HIP(hipDeviceSynchronize());
     }
+    return TQP_OK;
+}
+
+tqp_status tqp_copy(tqp_ctx* ctx, void* dst, const void* src, size_t bytes, hipStream_t stream) {
+    clear_error();
+    if (!ctx || (bytes && (!dst || !src))) return fail(TQP_ERR_INVALID, "tqp_copy: null argument");
+    if ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src) | bytes) & 15)
+        return fail(TQP_ERR_INVALID, "tqp_copy: pointers and size must be multiples of 16 bytes");
+    if (!bytes) return TQP_OK;
+    const int64_t n = (int64_t)(bytes / 16);
+    TQP_LAUNCH(ctx, stream, "copy",
+               k_copy_u128<<<grid_for(n, 256 * 8, (int64_t)ctx->num_cus * 8), 256, 0, stream>>>(
+                   static_cast<const uint4*>(src), static_cast<uint4*>(dst), n));
     return TQP_OK;
 }
 

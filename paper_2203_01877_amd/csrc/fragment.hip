@@ -109,18 +109,22 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
     tqp_status st;
     if ((st = fill_zero(o.sum, o.gcap * 8, s, ctx)) != TQP_OK) return st;
     if ((st = fill_zero(o.cnt, o.gcap * 8, s, ctx)) != TQP_OK) return st;
+    // mid side, (pk, custkey), sorted on the side stream while the fact side
+    // is sorted on s
+    if ((st = side_fork(ctx, s)) != TQP_OK) return st;
+    SrcKeyCol msrc{f.pk, f.custkey, f.n_mid};
+    if ((st = radix_launch<Cfg, uint32_t>(b.mid, msrc, f.n_mid, true, nullptr, key_mask_for(kb), b.mkeys,
+                                          b.mvals, ctx, ctx->side)) != TQP_OK)
+        return st;
     // fact side: date < D fused into the sort; the payload is the revenue
     // price * (100 - disc), evaluated while the row is read
     SrcFilterRevenue fsrc{f.fk, f.date, f.price, f.disc, CMP_LT, f.D, f.n_fact};
     if ((st = radix_launch<Cfg, uint64_t>(b.fact, fsrc, f.n_fact, true, nullptr, key_mask_for(kb), b.fkeys,
                                           b.fvals, ctx, s)) != TQP_OK)
         return st;
-    // mid side: (pk, custkey)
-    SrcKeyCol msrc{f.pk, f.custkey, f.n_mid};
-    if ((st = radix_launch<Cfg, uint32_t>(b.mid, msrc, f.n_mid, true, nullptr, key_mask_for(kb), b.mkeys,
-                                          b.mvals, ctx, s)) != TQP_OK)
-        return st;
-    // join: emits (custkey, revenue) and the digit histograms of custkey
+
+    if ((st = side_join(ctx, s)) != TQP_OK) return st;
+    // join: emits (custkey, revenue)
     using Emit = EmitKeyVal<JCfgFrag::BLOCK, Cfg::RADIX_BITS>;
     Emit e{};
     e.out_key = b.gkeys_in;
@@ -128,7 +132,7 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
     e.cap = f.join_cap;
     e.key_mask = key_mask_for(cb);
     e.flags = ctx->d_err;
-    e.hist = b.grp.hist;
+    e.hist = nullptr;
     e.npass = b.grp.pd.npass;
     for (int p = 0; p < b.grp.pd.npass && p < Emit::NP; ++p) {
         e.shift[p] = b.grp.pd.shift[p];
@@ -140,7 +144,7 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
         return st;
     // group-by: sort (custkey, revenue) by custkey, then reduce runs
     SrcPairs<uint64_t> gsrc{b.gkeys_in, b.gvals_in, f.join_cap, b.d_join};
-    if ((st = radix_launch<Cfg, uint64_t>(b.grp, gsrc, f.join_cap, false, b.d_join, key_mask_for(cb), b.gkeys,
+    if ((st = radix_launch<Cfg, uint64_t>(b.grp, gsrc, f.join_cap, true, b.d_join, key_mask_for(cb), b.gkeys,
                                           b.gvals, ctx, s)) != TQP_OK)
         return st;
     ValsDirect vs{reinterpret_cast<const int64_t*>(b.gvals), nullptr};

@@ -9,7 +9,7 @@
 
 namespace tqp {
 
-using JCfgFrag = JoinCfg<256, 8, 4096>;
+using JCfgFrag = JoinCfg<256, 8, 2048>;
 using SCfgFrag = SegCfg<256, 16>;
 
 // Join scratch: the R window of every left tile, the look-back status words

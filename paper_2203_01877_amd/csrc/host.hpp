@@ -26,6 +26,8 @@ struct tqp_ctx {
     bool prof = false;           // record a pair of events around every launch
     std::vector<tqp_prof_rec> recs;
     std::vector<hipEvent_t> pool;
+    hipStream_t side = nullptr;  // second stream for independent work inside one call
+    hipEvent_t fork = nullptr, join = nullptr;
 };
 
 namespace tqp {
@@ -105,6 +107,19 @@ tqp_status with_workspace(tqp_ctx* ctx, void* ws, size_t* ws_bytes, hipStream_t 
 }
 
 tqp_status fill_zero(void* p, size_t bytes, hipStream_t stream, tqp_ctx* ctx = nullptr);
+
+// Fork: work launched on ctx->side after this call starts after everything
+// already queued on s.  Join: s waits for everything queued on ctx->side.
+inline tqp_status side_fork(tqp_ctx* ctx, hipStream_t s) {
+    TQP_TRY_HIP(hipEventRecord(ctx->fork, s));
+    TQP_TRY_HIP(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
+    return TQP_OK;
+}
+inline tqp_status side_join(tqp_ctx* ctx, hipStream_t s) {
+    TQP_TRY_HIP(hipEventRecord(ctx->join, ctx->side));
+    TQP_TRY_HIP(hipStreamWaitEvent(s, ctx->join, 0));
+    return TQP_OK;
+}
 
 inline int grid_for(int64_t work, int64_t per_block, int64_t cap_blocks) {
     int64_t g = (work + per_block - 1) / per_block;

@@ -157,9 +157,14 @@ __global__ void k_join_windows(const uint32_t* lkey, int64_t nl_upper, const int
                                const uint32_t* rkey, int64_t nr_upper, const int64_t* d_nr, int tile_size,
                                int64_t* win);
 
-template <class Cfg>
+template <class Cfg, class RP>
 struct JoinSmem {
-    uint32_t rkey[Cfg::RWIN];
+    // Direct table of the tile's key range: for key value v in [kmin, kmin + KRANGE),
+    // first[v - kmin] = first right position (relative to the window) with
+    // that key, cnt[...] = number of right rows with it (rightHist of v).
+    int32_t first[Cfg::RWIN];
+    int32_t cnt[Cfg::RWIN];
+    RP rpay[Cfg::RWIN];
     int64_t wave[Cfg::WAVES];
     int64_t base;
     uint32_t tile;
@@ -167,22 +172,33 @@ struct JoinSmem {
 };
 
 // One left tile (shared by the single-input kernel and the batched kernel):
-// match counts from the tile's R window, output base by look-back, expansion
-// into the emitter.  ntiles is the number of tiles of this left input; the
-// last one stores the join size.
+// match counts, output base by look-back, expansion into the emitter.  When
+// the tile's key range and its R window both fit RWIN, counts and first
+// matches come from a direct LDS table built from the window (two LDS reads
+// per left element) and the right payloads are staged in LDS; otherwise from
+// binary searches over the window in global memory.  ntiles is the number of
+// tiles of this left input; the last one stores the join size.
 template <class Cfg, class LP, class RP, class Emit>
 __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, int64_t nl, const uint32_t* rkey,
                                           const RP* rpay, int64_t wlo, int64_t whi, int64_t tile, int64_t ntiles,
                                           uint64_t* status, int64_t* d_count, int64_t cap, Emit& e,
-                                          typename Emit::Smem& esm, JoinSmem<Cfg>& sm, uint32_t* flags) {
+                                          typename Emit::Smem& esm, JoinSmem<Cfg, RP>& sm, uint32_t* flags) {
     constexpr int TILE = Cfg::TILE, ITEMS = Cfg::ITEMS, RWIN = Cfg::RWIN, W = Cfg::WAVES;
     const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
+    const int64_t t0 = tile * TILE;
+    const int64_t tlast = (t0 + TILE < nl ? t0 + TILE : nl) - 1;
+    const uint32_t kmin = lkey[t0], kmax = lkey[tlast];
     const int64_t wn = whi - wlo;
-    const bool in_lds = wn <= RWIN;
-    if (in_lds)
-        for (int i = tid; i < wn; i += Cfg::BLOCK) sm.rkey[i] = rkey[wlo + i];
+    const bool direct = wn <= RWIN && (int64_t)kmax - (int64_t)kmin < RWIN;
+    if (direct) {
+        const int range = (int)(kmax - kmin) + 1;
+        for (int i = tid; i < range; i += Cfg::BLOCK) {
+            sm.cnt[i] = 0;
+            sm.first[i] = RWIN;
+        }
+    }
     // The wave's contiguous chunk of the tile, 64 elements per round.
-    const int64_t chunk = tile * TILE + (int64_t)w * ITEMS * WAVE;
+    const int64_t chunk = t0 + (int64_t)w * ITEMS * WAVE;
     uint32_t key[ITEMS];
     LP pay[ITEMS];
 #pragma unroll
@@ -195,6 +211,16 @@ __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, 
         }
     }
     __syncthreads();
+    if (direct) {
+        for (int i = tid; i < wn; i += Cfg::BLOCK) {
+            const uint32_t k = rkey[wlo + i];
+            const int v = (int)(k - kmin);       // window keys lie in [kmin, kmax]
+            atomicMin(&sm.first[v], i);
+            atomicAdd(&sm.cnt[v], 1);
+            sm.rpay[i] = rpay ? rpay[wlo + i] : (RP)(wlo + i);
+        }
+        __syncthreads();
+    }
     // Match count and first match of each element: rightHist of its key.
     int32_t cnt[ITEMS];
     int64_t first[ITEMS], off[ITEMS];      // off: exclusive offset of the element within the wave chunk
@@ -205,16 +231,16 @@ __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, 
         cnt[j] = 0;
         first[j] = 0;
         if (i < nl) {
-            int64_t lb, ub;
-            if (in_lds) {
-                lb = wlo + lower_bound_lds(sm.rkey, (int)wn, key[j]);
-                ub = wlo + upper_bound_lds(sm.rkey, (int)wn, key[j]);
+            if (direct) {
+                const int v = (int)(key[j] - kmin);
+                cnt[j] = sm.cnt[v];
+                first[j] = sm.first[v];      // relative to the window
             } else {
-                lb = lower_bound_glb(rkey, wlo, whi, key[j]);
-                ub = upper_bound_glb(rkey, lb, whi, key[j]);
+                const int64_t lb = lower_bound_glb(rkey, wlo, whi, key[j]);
+                const int64_t ub = upper_bound_glb(rkey, lb, whi, key[j]);
+                first[j] = lb;
+                cnt[j] = (int32_t)(ub - lb);
             }
-            first[j] = lb;
-            cnt[j] = (int32_t)(ub - lb);
         }
         const int64_t incl = wave_incl_sum((int64_t)cnt[j]);
         off[j] = wave_total + incl - cnt[j];
@@ -239,13 +265,16 @@ __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, 
     int64_t wbase = sm.base;
     for (int ww = 0; ww < w; ++ww) wbase += sm.wave[ww];
     // Expansion: output o of element i pairs it with right element first + (o - offset(i)).
+    auto right = [&](int64_t r) -> RP {
+        if (direct) return sm.rpay[r];
+        return rpay ? rpay[r] : (RP)r;
+    };
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const int64_t o = wbase + off[j];
         const bool small = cnt[j] <= JOIN_LANE_MAX;
         if (small)
-            for (int t = 0; t < cnt[j]; ++t)
-                e(o + t, key[j], pay[j], rpay ? rpay[first[j] + t] : (RP)(first[j] + t), esm);
+            for (int t = 0; t < cnt[j]; ++t) e(o + t, key[j], pay[j], right(first[j] + t), esm);
         uint64_t heavy = ballot(!small);
         while (heavy) {
             const int src = __ffsll((unsigned long long)heavy) - 1;
@@ -255,7 +284,7 @@ __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, 
             const int64_t oo = __shfl(o, src, WAVE);
             const uint32_t kk = __shfl(key[j], src, WAVE);
             const LP pp = shfl_any(pay[j], src);
-            for (int q = l; q < c; q += WAVE) e(oo + q, kk, pp, rpay ? rpay[f + q] : (RP)(f + q), esm);
+            for (int q = l; q < c; q += WAVE) e(oo + q, kk, pp, right(f + q), esm);
         }
     }
     __syncthreads();
@@ -267,7 +296,7 @@ k_join(const uint32_t* lkey, const LP* lpay, int64_t nl_upper, const int64_t* d_
        const uint32_t* rkey, const RP* rpay, int64_t nr_upper, const int64_t* d_nr, const int64_t* win,
        uint64_t* status, uint32_t* tile_counter, int64_t* d_count, int64_t cap, Emit emit,
        uint32_t* flags) {
-    __shared__ JoinSmem<Cfg> sm;
+    __shared__ JoinSmem<Cfg, RP> sm;
     __shared__ typename Emit::Smem esm;
     int64_t nl = nl_upper;
     if (d_nl) { int64_t t = *d_nl; nl = t < nl ? t : nl; }
