@@ -164,9 +164,8 @@ def main():
     roofline = None
     if DOMINANT in per:
         # launches of the dominant family per step: fact passes after the first, then every group pass
-        pd_f = max(1, -(-key_bits // args.digit_bits))
-        pd_g = max(1, -(-cust_bits // args.digit_bits))
-        sizes = [n_f] * (pd_f - 1) + [J] * pd_g
+        plan = run.plan()
+        sizes = [n_f] * (plan["fact_passes"] - 1) + [J] * plan["group_passes"]
         durs = per[DOMINANT]
         if len(durs) == len(sizes) * args.steps:
             bytes_total = sum(24 * s for s in sizes) * args.steps
@@ -193,7 +192,8 @@ def main():
         "config": {"workload": "60M-row fact x 15M-row mid: date<2400, fk=pk, group by custkey, sum+count, "
                                "top-100 by sum desc" if not args.rows else "scaled custkey fragment",
                    "fact_rows": N, "mid_rows": M, "filtered_fact_rows": n_f, "join_rows": J, "groups": G,
-                   "digit_bits": args.digit_bits, "key_bits": key_bits, "cust_bits": cust_bits},
+                   "digit_bits": args.digit_bits, "key_bits": key_bits, "cust_bits": cust_bits,
+                   "plan": run.plan()},
         "roofline": roofline,
         "hbm_fraction_ref_model": round(bref / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
         "ref_model_bytes": bref,

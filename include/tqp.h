@@ -260,6 +260,14 @@ typedef struct {
 tqp_status tqp_fragment_cust(tqp_ctx* ctx, const tqp_cust_fragment* f, const tqp_cust_out* o,
                              void* ws, size_t* ws_bytes, hipStream_t stream);
 
+/* The launch plan tqp_fragment_cust uses for f with the context's digit
+ * width (host only): radix passes of the fact, mid and group-key sorts, the
+ * low fact-key bits the fact sort leaves to the join (its tiles then cover
+ * bucket-aligned key ranges) and the low group-key bits resolved in LDS by
+ * the bucket aggregation.  Any output pointer may be NULL. */
+tqp_status tqp_fragment_cust_plan(tqp_ctx* ctx, const tqp_cust_fragment* f, int* fact_passes, int* fact_lowb,
+                                  int* mid_passes, int* group_passes, int* group_lowb);
+
 /* ---------------------------------------------------------------- batches
  * Many flags fragments (each with its own fact and dim columns, D and c) run
  * as one launch sequence: every stage is one persistent kernel over all

@@ -256,6 +256,14 @@ class CustFragmentRunner:
         self.ws = torch.empty(max(256, sz.value), dtype=torch.uint8, device=dev)
         self.ws_bytes = ctypes.c_size_t(sz.value)
 
+    def plan(self) -> dict:
+        """Radix passes and low-bit choices of this fragment (host only)."""
+        v = [ctypes.c_int(0) for _ in range(5)]
+        check(self.ctx.lib.tqp_fragment_cust_plan(self.ctx.h, ctypes.byref(self.desc), *[ctypes.byref(x) for x in v]),
+              "tqp_fragment_cust_plan")
+        return dict(zip(("fact_passes", "fact_lowb", "mid_passes", "group_passes", "group_lowb"),
+                        [x.value for x in v]))
+
     def run(self, stream=None):
         check(self.ctx.lib.tqp_fragment_cust(self.ctx.h, ctypes.byref(self.desc), ctypes.byref(self.odesc),
                                              _p(self.ws), ctypes.byref(self.ws_bytes), _stream(stream)),

@@ -126,6 +126,9 @@ def load() -> ctypes.CDLL:
     lib.tqp_fragment_cust.argtypes = [c_vp, ctypes.POINTER(CustFragment), ctypes.POINTER(CustOut), c_vp,
                                       c_size_p, c_vp]
     lib.tqp_fragment_cust.restype = S
+    ip = ctypes.POINTER(c_int)
+    lib.tqp_fragment_cust_plan.argtypes = [c_vp, ctypes.POINTER(CustFragment), ip, ip, ip, ip, ip]
+    lib.tqp_fragment_cust_plan.restype = S
     lib.tqp_batch_create.argtypes = [c_vp, ctypes.POINTER(FlagsFragment), ctypes.POINTER(FlagsOut), c_int, c_vp,
                                      c_size_p, ctypes.POINTER(c_vp)]
     lib.tqp_batch_create.restype = S

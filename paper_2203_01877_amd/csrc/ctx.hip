@@ -77,7 +77,7 @@ tqp_status fill_zero(void* p, size_t bytes, hipStream_t stream, tqp_ctx* ctx) {
 
 __global__ void k_join_windows(const uint32_t* lkey, int64_t nl_upper, const int64_t* d_nl,
                                const uint32_t* rkey, int64_t nr_upper, const int64_t* d_nr, int tile_size,
-                               int64_t* win) {
+                               int64_t* win, int lowb) {
     int64_t nl = nl_upper, nr = nr_upper;
     if (d_nl) { const int64_t t = *d_nl; nl = t < nl ? t : nl; }
     if (d_nr) { const int64_t t = *d_nr; nr = t < nr ? t : nr; }
@@ -86,9 +86,11 @@ __global__ void k_join_windows(const uint32_t* lkey, int64_t nl_upper, const int
     if (t >= ntiles) return;
     const int64_t i0 = t * tile_size;
     const int64_t i1 = (i0 + tile_size < nl ? i0 + tile_size : nl) - 1;
-    const int64_t lo = lower_bound_glb(rkey, 0, nr, lkey[i0]);
+    uint32_t kmin, kmax;
+    tile_key_range(lkey, i0, i1, lowb, kmin, kmax);
+    const int64_t lo = lower_bound_glb(rkey, 0, nr, kmin);
     win[2 * t] = lo;
-    win[2 * t + 1] = upper_bound_glb(rkey, lo, nr, lkey[i1]);
+    win[2 * t + 1] = upper_bound_glb(rkey, lo, nr, kmax);
 }
 
 __global__ void k_avg(const int64_t* sa, const int64_t* cnt, double* avg, const int64_t* d_ngroups,

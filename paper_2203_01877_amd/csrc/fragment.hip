@@ -1,8 +1,31 @@
 // Whole fragments: filter -> sort-based join -> group-by in one launch
 // sequence, every intermediate in the workspace, no host synchronisation.
+#include <cmath>
+
 #include "fragment.hpp"
 
 namespace tqp {
+
+constexpr int BUCKET_LOWB_DEFAULT = 7;
+constexpr int BUCKET_BLOCK = 256;
+
+// Low key bits the fact sort may leave out.  A join tile of TILE left rows
+// over keys spread evenly on [0, 2^kb) spans about TILE * 2^kb / n key values
+// plus one bucket of 2^s; both must fit the join's LDS table (RWIN), and the
+// sorted high bits should fill whole radix passes.  Tiles that do not fit
+// fall back to binary searches, so this is a cost choice, not a correctness
+// condition.
+int fact_low_bits(int64_t n, int kb, int rb) {
+    if (n <= 0) return 0;
+    const double spread = (double)JCfgFrag::TILE * std::ldexp(1.0, kb) / (double)n;
+    const double room = 0.85 * JCfgFrag::RWIN - spread;
+    if (room < 64) return 0;
+    int smax = 0;
+    while (smax + 1 <= kb && std::ldexp(1.0, smax + 1) <= room) ++smax;
+    const int passes = (kb - smax + rb - 1) / rb;
+    int s = kb - passes * rb;
+    return s < 0 ? 0 : s;
+}
 
 // Groups of the flags fragment in ascending packed-key order, skipping
 // packed keys no row reached (SQL emits no empty group).
@@ -83,12 +106,21 @@ template <class Cfg>
 void cust_reserve(Arena& a, const tqp_cust_fragment& f, const tqp_cust_out& o, CustBufs<Cfg>& b) {
     const int kb = norm_key_bits(f.key_bits);
     const int cb = norm_key_bits(f.cust_bits);
-    b.fact = radix_reserve<Cfg, uint64_t>(a, f.n_fact, kb);
+    // The join needs the fact keys sorted only on their bits above fact_lowb
+    // when a join tile still spans a small key range: then the low digits are
+    // never sorted.
+    b.fact_lowb = fact_low_bits(f.n_fact, kb, Cfg::RADIX_BITS);
+    b.fact = radix_reserve<Cfg, uint64_t>(a, f.n_fact, kb, b.fact_lowb);
     b.mid = radix_reserve<Cfg, uint32_t>(a, f.n_mid, kb);
     b.join = join_reserve<JCfgFrag>(a, f.n_fact);
     b.d_join = a.zero<int64_t>(1);
-    b.grp = radix_reserve<Cfg, uint64_t>(a, f.join_cap, cb);
-    b.sstatus = a.zero<uint64_t>((f.join_cap + SCfgFrag::TILE - 1) / SCfgFrag::TILE);
+    // group-by: radix passes over the custkey bits above lowb, then one
+    // bucket-aggregation block per value of those bits
+    b.lowb = cb < BUCKET_LOWB_DEFAULT + 1 ? cb - 1 : BUCKET_LOWB_DEFAULT;
+    if (b.lowb < 0) b.lowb = 0;
+    b.nbuckets = int64_t(1) << (cb - b.lowb);
+    b.grp = radix_reserve<Cfg, uint64_t>(a, f.join_cap, cb, b.lowb);
+    b.sstatus = a.zero<uint64_t>(b.nbuckets);
     b.scounter = a.zero<uint32_t>(1);
     b.fkeys = a.scratch<uint32_t>(f.n_fact);
     b.fvals = a.scratch<uint64_t>(f.n_fact);
@@ -140,18 +172,19 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
     }
     if ((st = join_launch<JCfgFrag, uint64_t, uint32_t>(ctx, s, "join_keyval", b.join, b.fkeys, b.fvals, f.n_fact,
                                                         b.fact.d_cnt, b.mkeys, b.mvals, f.n_mid,
-                                                        (const int64_t*)nullptr, b.d_join, f.join_cap, e)) != TQP_OK)
+                                                        (const int64_t*)nullptr, b.d_join, f.join_cap, e,
+                                                        b.fact_lowb)) != TQP_OK)
         return st;
     // group-by: sort (custkey, revenue) by custkey, then reduce runs
     SrcPairs<uint64_t> gsrc{b.gkeys_in, b.gvals_in, f.join_cap, b.d_join};
     if ((st = radix_launch<Cfg, uint64_t>(b.grp, gsrc, f.join_cap, true, b.d_join, key_mask_for(cb), b.gkeys,
                                           b.gvals, ctx, s)) != TQP_OK)
         return st;
-    ValsDirect vs{reinterpret_cast<const int64_t*>(b.gvals), nullptr};
     SegOut so{o.key, o.sum, o.cnt, nullptr, o.gcap, o.d_ngroups};
-    TQP_LAUNCH(ctx, s, "segreduce",
-               k_segreduce<SCfgFrag, ValsDirect, false><<<grid_for(f.join_cap, SCfgFrag::TILE, 0), SCfgFrag::BLOCK, 0, s>>>(
-                   b.gkeys, vs, f.join_cap, b.d_join, b.sstatus, b.scounter, so, ctx->d_err));
+    TQP_LAUNCH(ctx, s, "bucket_agg",
+               k_bucket_agg<BUCKET_BLOCK><<<(unsigned)b.nbuckets, BUCKET_BLOCK, 0, s>>>(
+                   b.gkeys, reinterpret_cast<const int64_t*>(b.gvals), f.join_cap, b.d_join, b.lowb, b.nbuckets,
+                   b.sstatus, b.scounter, so, ctx->d_err));
     // ORDER BY sum DESC, custkey ASC LIMIT k
     if ((st = topk_launch(b.topk, o.key, o.sum, o.cnt, o.d_ngroups, f.k, o.top_key, o.top_sum, o.top_cnt,
                           o.d_topk, s, ctx)) != TQP_OK)
@@ -200,6 +233,25 @@ tqp_status tqp_fragment_flags(tqp_ctx* ctx, const tqp_flags_fragment* f, const t
         if (s2 != TQP_OK || !ws) return s2;
         if ((s2 = fill_zero(a.base, a.zsize, stream, ctx)) != TQP_OK) return s2;
         return flags_launch<Cfg>(ctx, *f, *o, b, stream);
+    });
+}
+
+tqp_status tqp_fragment_cust_plan(tqp_ctx* ctx, const tqp_cust_fragment* f, int* fact_passes, int* fact_lowb,
+                                  int* mid_passes, int* group_passes, int* group_lowb) {
+    clear_error();
+    if (!ctx || !f) return fail(TQP_ERR_INVALID, "null argument");
+    return with_radix_cfg(ctx->digit_bits, [&](auto cfg) -> tqp_status {
+        using Cfg = decltype(cfg);
+        tqp_cust_out o{};
+        CustBufs<Cfg> b;
+        Arena a;
+        cust_reserve<Cfg>(a, *f, o, b);
+        if (fact_passes) *fact_passes = b.fact.pd.npass;
+        if (fact_lowb) *fact_lowb = b.fact_lowb;
+        if (mid_passes) *mid_passes = b.mid.pd.npass;
+        if (group_passes) *group_passes = b.grp.pd.npass;
+        if (group_lowb) *group_lowb = b.lowb;
+        return TQP_OK;
     });
 }
 

@@ -34,18 +34,19 @@ JoinBufs join_reserve(Arena& a, int64_t nl_upper) {
 template <class Cfg, class LP, class RP, class Emit>
 tqp_status join_launch(tqp_ctx* ctx, hipStream_t s, const char* name, const JoinBufs& b, const uint32_t* lkey,
                        const LP* lpay, int64_t nl, const int64_t* d_nl, const uint32_t* rkey, const RP* rpay,
-                       int64_t nr, const int64_t* d_nr, int64_t* d_count, int64_t cap, const Emit& e) {
+                       int64_t nr, const int64_t* d_nr, int64_t* d_count, int64_t cap, const Emit& e,
+                       int lowb = 0) {
     const int64_t tiles = b.tiles;
     if (tiles > 0) {
         TQP_LAUNCH(ctx, s, "join_windows",
                    k_join_windows<<<grid_for(tiles, 256, 0), 256, 0, s>>>(lkey, nl, d_nl, rkey, nr, d_nr,
-                                                                            Cfg::TILE, b.win));
+                                                                            Cfg::TILE, b.win, lowb));
     }
     const int grid = grid_for(tiles, 1, (int64_t)ctx->num_cus * 4);
     TQP_LAUNCH(ctx, s, name,
                k_join<Cfg, LP, RP, Emit><<<grid, Cfg::BLOCK, 0, s>>>(lkey, lpay, nl, d_nl, rkey, rpay, nr, d_nr,
                                                                    b.win, b.status, b.counter, d_count, cap, e,
-                                                                   ctx->d_err));
+                                                                   ctx->d_err, lowb));
     return TQP_OK;
 }
 
@@ -85,8 +86,11 @@ tqp_status topk_launch(const TopkBufs& t, const int32_t* key, const int64_t* sum
 template <class Cfg>
 struct CustBufs {
     RadixBufs<Cfg, uint64_t> fact;
+    int fact_lowb = 0;         // fact key bits left unsorted (the join resolves them)
     RadixBufs<Cfg, uint32_t> mid;
     RadixBufs<Cfg, uint64_t> grp;
+    int lowb = 0;              // group-key bits resolved in LDS by the bucket kernel
+    int64_t nbuckets = 0;
     JoinBufs join;
     int64_t* d_join = nullptr;
     uint64_t* sstatus = nullptr;

@@ -164,10 +164,13 @@ struct RadixBufs {
     V* vtmp = nullptr;
 };
 
+// skip_low: the lowest skip_low key bits are left unsorted (the passes cover
+// bits [skip_low, key_bits)).
 template <class Cfg, class V>
-RadixBufs<Cfg, V> radix_reserve(Arena& a, int64_t n_upper, int key_bits) {
+RadixBufs<Cfg, V> radix_reserve(Arena& a, int64_t n_upper, int key_bits, int skip_low = 0) {
     RadixBufs<Cfg, V> b;
-    b.pd = make_passes(key_bits, Cfg::RADIX_BITS);
+    b.pd = make_passes(key_bits - skip_low, Cfg::RADIX_BITS);
+    for (int p = 0; p < b.pd.npass; ++p) b.pd.shift[p] += skip_low;
     b.ntiles = (n_upper + Cfg::TILE - 1) / Cfg::TILE;
     b.hist = a.zero<uint32_t>((int64_t)b.pd.npass * Cfg::RADIX);
     b.status = a.zero<uint32_t>((int64_t)b.pd.npass * b.ntiles * Cfg::RADIX);

@@ -155,7 +155,7 @@ struct EmitFlagsAgg {
 // key)).  One thread per tile; all tiles search at once.
 __global__ void k_join_windows(const uint32_t* lkey, int64_t nl_upper, const int64_t* d_nl,
                                const uint32_t* rkey, int64_t nr_upper, const int64_t* d_nr, int tile_size,
-                               int64_t* win);
+                               int64_t* win, int lowb);
 
 template <class Cfg, class RP>
 struct JoinSmem {
@@ -178,16 +178,33 @@ struct JoinSmem {
 // per left element) and the right payloads are staged in LDS; otherwise from
 // binary searches over the window in global memory.  ntiles is the number of
 // tiles of this left input; the last one stores the join size.
+//
+// The right keys must be fully sorted.  The left keys need only be sorted on
+// their bits above lowb: every key of the tile then lies in its bucket-aligned
+// range, and each left element is looked up on its own, so the pairs of a
+// tile come out in the tile's element order instead of key order (the same
+// pairs; lowb = 0 keeps the canonical order).
+// Key range of a left tile whose keys are sorted on their bits above lowb
+// (lowb = 0: fully sorted): from the bucket of its first key to the end of
+// the bucket of its last key.
+__device__ __forceinline__ void tile_key_range(const uint32_t* lkey, int64_t first, int64_t last, int lowb,
+                                               uint32_t& kmin, uint32_t& kmax) {
+    kmin = (lkey[first] >> lowb) << lowb;
+    kmax = ((lkey[last] >> lowb) << lowb) | ((1u << lowb) - 1);
+}
+
 template <class Cfg, class LP, class RP, class Emit>
 __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, int64_t nl, const uint32_t* rkey,
                                           const RP* rpay, int64_t wlo, int64_t whi, int64_t tile, int64_t ntiles,
                                           uint64_t* status, int64_t* d_count, int64_t cap, Emit& e,
-                                          typename Emit::Smem& esm, JoinSmem<Cfg, RP>& sm, uint32_t* flags) {
+                                          typename Emit::Smem& esm, JoinSmem<Cfg, RP>& sm, uint32_t* flags,
+                                          int lowb = 0) {
     constexpr int TILE = Cfg::TILE, ITEMS = Cfg::ITEMS, RWIN = Cfg::RWIN, W = Cfg::WAVES;
     const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
     const int64_t t0 = tile * TILE;
     const int64_t tlast = (t0 + TILE < nl ? t0 + TILE : nl) - 1;
-    const uint32_t kmin = lkey[t0], kmax = lkey[tlast];
+    uint32_t kmin, kmax;
+    tile_key_range(lkey, t0, tlast, lowb, kmin, kmax);
     const int64_t wn = whi - wlo;
     const bool direct = wn <= RWIN && (int64_t)kmax - (int64_t)kmin < RWIN;
     if (direct) {
@@ -295,7 +312,7 @@ __global__ void __launch_bounds__(Cfg::BLOCK)
 k_join(const uint32_t* lkey, const LP* lpay, int64_t nl_upper, const int64_t* d_nl,
        const uint32_t* rkey, const RP* rpay, int64_t nr_upper, const int64_t* d_nr, const int64_t* win,
        uint64_t* status, uint32_t* tile_counter, int64_t* d_count, int64_t cap, Emit emit,
-       uint32_t* flags) {
+       uint32_t* flags, int lowb) {
     __shared__ JoinSmem<Cfg, RP> sm;
     __shared__ typename Emit::Smem esm;
     int64_t nl = nl_upper;
@@ -312,7 +329,7 @@ k_join(const uint32_t* lkey, const LP* lpay, int64_t nl_upper, const int64_t* d_
         const int64_t tile = sm.tile;
         if (tile >= ntiles) break;
         join_tile<Cfg, LP, RP, Emit>(lkey, lpay, nl, rkey, rpay, win[2 * tile], win[2 * tile + 1], tile, ntiles,
-                                     status, d_count, cap, e, esm, sm, flags);
+                                     status, d_count, cap, e, esm, sm, flags, lowb);
     }
     e.finish(esm);
 }

@@ -175,6 +175,91 @@ k_segreduce(const uint32_t* keys, VS vs, int64_t n_upper, const int64_t* d_n, ui
     }
 }
 
+// Group-by over keys sorted by their high bits only (Algorithm 2 with the
+// last radix digit resolved in LDS): bucket b holds the keys whose bits above
+// `lowb` equal b, contiguous in the sorted array.  One block per bucket (in
+// bucket order, from a counter) accumulates sum and count per low-bit value in
+// LDS, which is the counting sort of the last digit and the run reduction in
+// one step, then writes the bucket's non-empty groups in ascending key order
+// at the offset given by a look-back over the buckets' group counts.
+constexpr int BUCKET_LOWB_MAX = 9;
+
+template <int BLOCK>
+__global__ void __launch_bounds__(BLOCK)
+k_bucket_agg(const uint32_t* keys, const int64_t* vals, int64_t n_upper, const int64_t* d_n, int lowb,
+             int64_t nbuckets, uint64_t* status, uint32_t* counter, SegOut out, uint32_t* flags) {
+    constexpr int SLOTS = 1 << BUCKET_LOWB_MAX;
+    __shared__ unsigned long long s_sum[SLOTS];
+    __shared__ unsigned long long s_cnt[SLOTS];
+    __shared__ int64_t s_lo, s_hi, s_base;
+    __shared__ int32_t s_wave[BLOCK / WAVE];
+    __shared__ uint32_t s_b;
+    const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
+    int64_t n = n_upper;
+    if (d_n) { const int64_t t = *d_n; n = t < n ? t : n; }
+    if (tid == 0) s_b = atomicAdd(counter, 1u);
+    const int slots = 1 << lowb;
+    for (int i = tid; i < slots; i += BLOCK) { s_sum[i] = 0; s_cnt[i] = 0; }
+    __syncthreads();
+    const int64_t b = s_b;
+    if (b >= nbuckets) return;
+    // bucket bounds: two wave-wide searches
+    if (w == 0) {
+        const int64_t lo = wave_bound(keys, n, (uint32_t)(b << lowb), false);
+        if (l == 0) s_lo = lo;
+    } else if (w == 1) {
+        const int64_t hi = b + 1 < nbuckets ? wave_bound(keys, n, (uint32_t)((b + 1) << lowb), false) : n;
+        if (l == 0) s_hi = hi;
+    }
+    __syncthreads();
+    const int64_t lo = s_lo, hi = s_hi;
+    const uint32_t lmask = (uint32_t)slots - 1;
+    for (int64_t i = lo + tid; i < hi; i += BLOCK) {
+        const uint32_t k = keys[i] & lmask;
+        atomicAdd(&s_sum[k], (unsigned long long)vals[i]);
+        atomicAdd(&s_cnt[k], 1ull);
+    }
+    __syncthreads();
+    // non-empty slots in ascending order -> local group index
+    const int per = (slots + BLOCK - 1) / BLOCK;      // consecutive slots per thread
+    int mine = 0;
+    for (int q = 0; q < per; ++q) {
+        const int sl = tid * per + q;
+        if (sl < slots && s_cnt[sl]) ++mine;
+    }
+    const int incl = wave_incl_sum(mine);
+    if (l == WAVE - 1) s_wave[w] = incl;
+    __syncthreads();
+    int total = 0, woff = 0;
+    for (int ww = 0; ww < BLOCK / WAVE; ++ww) {
+        if (ww < w) woff += s_wave[ww];
+        total += s_wave[ww];
+    }
+    if (w == 0) {
+        const int64_t base = lookback64(status, b, total, flags);
+        if (tid == 0) {
+            s_base = base;
+            if (b == nbuckets - 1) {
+                *out.d_ngroups = base + total;
+                if (base + total > out.gcap) set_flag(flags, FLAG_CAPACITY);
+            }
+        }
+    }
+    __syncthreads();
+    int64_t g = s_base + woff + incl - mine;
+    for (int q = 0; q < per; ++q) {
+        const int sl = tid * per + q;
+        if (sl < slots && s_cnt[sl]) {
+            if (g < out.gcap) {
+                out.key[g] = (int32_t)((b << lowb) | sl);
+                out.sum[g] = (int64_t)s_sum[sl];
+                out.cnt[g] = (int64_t)s_cnt[sl];
+            }
+            ++g;
+        }
+    }
+}
+
 // avg = (double)sum / (double)count, one IEEE division per group.
 __global__ void k_avg(const int64_t* sa, const int64_t* cnt, double* avg, const int64_t* d_ngroups,
                       int64_t gcap);
