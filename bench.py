@@ -6,15 +6,17 @@ date < 2400, group by custkey (about 1.5M groups), exact int64 sum and count,
 then ORDER BY sum DESC, custkey ASC LIMIT 100.  Inputs are seeded synthetic
 columns (the generator in datagen/), resident in HBM before timing starts.
 
-A step is one whole fragment: both filters, both key sorts, the join, the
-group-key sort, the run reduction and the top-100, launched on one stream.
-W untimed warm-up steps, then exactly K timed steps between two events after
-a device synchronisation; value = fact rows / second.
+A step is one whole fragment: the filter, both key sorts, the join, the
+group-key sort, the bucket aggregation and the top-100, launched on the
+caller's stream (the mid-side sort on a forked side stream).  W untimed
+warm-up steps, then exactly K timed steps between two events after a device
+synchronisation; value = fact rows / second.
 
-The per-launch profiler of the library (HIP events recorded on the launch
-stream around every kernel) is on during the timed steps; the roofline figure
-uses the dominant kernel family's measured durations and its algorithmic
-bytes (what the kernel must read and write), from the actual row counts.
+Then the same K steps run again with the library's per-launch profiler on
+(HIP events recorded on the launch stream around every kernel): the roofline
+figure uses the dominant kernel family's measured durations and its
+algorithmic bytes (what the kernel must read and write), from the actual row
+counts; ms_per_step_profiled is that run's step time.
 
 Prints one JSON line.
 """
@@ -38,16 +40,19 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(label, N, n_f, M, J, G):
-    """Bytes each launch of a kernel family must read and write in this design (per launch list)."""
+def algorithmic_bytes(plan, N, n_f, M, J, G):
+    """Bytes per step each kernel family must read and write in this design, summed over its
+    launches in one step (the row counts are the actual ones)."""
     return {
-        "radix_hist": None,                       # two launches: fact (fk, date) and mid (pk)
-        "radix_pass_fused_v8": 8 * N + 16 * n_f + 12 * n_f,   # read fk, date (+price, disc of kept rows), write key+revenue
-        "radix_pass_fused_v4": 8 * M + 8 * M,                 # read pk, custkey; write key+custkey
-        "radix_pass_pairs_v4": 16 * M,
-        "join_keyval": 12 * n_f + 4 * M + 4 * J + 12 * J,     # sorted fact, mid keys, custkey of matches; write (custkey, revenue)
-        "segreduce": 12 * J + 20 * G,
-    }.get(label)
+        "radix_hist": 8 * N + 4 * M + 4 * J,                  # fact fk+date, mid pk, group custkey
+        "radix_pass_fused_v8": 8 * N + 16 * n_f + 12 * n_f,   # fk, date (+price, disc of kept rows); key+revenue out
+        "radix_pass_pairs_v8": 24 * (n_f * (plan["fact_passes"] - 1) + J * plan["group_passes"]),
+        "radix_pass_fused_v4": 16 * M,                        # pk, custkey in; key+custkey out
+        "radix_pass_pairs_v4": 16 * M * (plan["mid_passes"] - 1),
+        "join_keyval": 12 * n_f + 8 * M + 12 * J,             # sorted fact pairs, mid keys+custkey; (custkey, revenue) out
+        "bucket_agg": 12 * J + 20 * G,
+        "topk_filter": 12 * G,
+    }
 
 
 def reference_model_bytes(N, n_f, M, J, G, P, Pm, Pg):
@@ -133,21 +138,31 @@ def main():
         run.run()
     torch.cuda.synchronize()
     log("warmup done")
-    if not args.no_profile:
-        ctx.profile_read()              # drop warm-up records
-        ctx.set_profiling(True)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        run.run()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    total_ms = e0.elapsed_time(e1)
-    recs = ctx.profile_read() if not args.no_profile else []
-    ctx.set_profiling(False)
-    ms = total_ms / args.steps
+
+    def timed_steps(profiled):
+        """K steps between two stream events after a device synchronisation; with
+        profiled, the library also records an event pair around every launch."""
+        if profiled:
+            ctx.profile_read()              # drop earlier records
+            ctx.set_profiling(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            run.run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        recs = ctx.profile_read() if profiled else []
+        ctx.set_profiling(False)
+        return e0.elapsed_time(e1) / args.steps, recs
+
+    # the step time comes from a run without per-launch events; the per-kernel
+    # durations of the roofline from a second, profiled run of the same steps
+    ms, _ = timed_steps(False)
     log("timed %d steps: %.3f ms/step" % (args.steps, ms))
+    ms_prof, recs = (None, []) if args.no_profile else timed_steps(True)
+    if ms_prof is not None:
+        log("timed %d profiled steps: %.3f ms/step" % (args.steps, ms_prof))
 
     res = run.result(all_groups=False)
     J, G = res["join_rows"], res["groups"]
@@ -161,6 +176,9 @@ def main():
     for name, t in recs:
         per.setdefault(name, []).append(t)
     stage_ms = {k: round(sum(v) / args.steps, 4) for k, v in sorted(per.items())}
+    stage_bytes = algorithmic_bytes(run.plan(), N, n_f, M, J, G) if per else {}
+    stage_gbps = {k: round(b / (stage_ms[k] * 1e-3) / 1e9, 1) for k, b in stage_bytes.items()
+                  if stage_ms.get(k)}
     roofline = None
     if DOMINANT in per:
         # launches of the dominant family per step: fact passes after the first, then every group pass
@@ -198,7 +216,8 @@ def main():
         "hbm_fraction_ref_model": round(bref / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
         "ref_model_bytes": bref,
         "stage_ms": stage_ms,
-        "profiled": not args.no_profile,
+        "stage_gbps": stage_gbps,
+        "ms_per_step_profiled": None if ms_prof is None else round(ms_prof, 4),
     }
 
     if args.with_copy:

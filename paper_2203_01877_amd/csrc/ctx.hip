@@ -93,6 +93,15 @@ __global__ void k_join_windows(const uint32_t* lkey, int64_t nl_upper, const int
     win[2 * t + 1] = upper_bound_glb(rkey, lo, nr, kmax);
 }
 
+__global__ void k_bucket_bounds(const uint32_t* keys, int64_t n_upper, const int64_t* d_n, int lowb,
+                                int64_t nbuckets, int64_t* starts) {
+    int64_t n = n_upper;
+    if (d_n) { const int64_t t = *d_n; n = t < n ? t : n; }
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > nbuckets) return;
+    starts[b] = b == nbuckets ? n : lower_bound_glb(keys, 0, n, (uint32_t)(b << lowb));
+}
+
 __global__ void k_avg(const int64_t* sa, const int64_t* cnt, double* avg, const int64_t* d_ngroups,
                       int64_t gcap) {
     int64_t G = *d_ngroups;
@@ -103,45 +112,53 @@ __global__ void k_avg(const int64_t* sa, const int64_t* cnt, double* avg, const 
 }
 
 __global__ void k_topk_filter(const int32_t* gkey, const int64_t* gsum, int64_t n_upper, const int64_t* d_n,
-                              const TopCand* thr, int k, TopCand* out, int64_t* d_out) {
+                              const int64_t* thr, TopCand* out, int64_t* d_out) {
+    // Survivors of a block's contiguous chunk are counted in LDS first, so the
+    // shared output counter sees one atomic per block.
+    constexpr int CHUNK_ITEMS = 8;
+    __shared__ int32_t s_cnt;
+    __shared__ int64_t s_base;
     int64_t n = n_upper;
     if (d_n) { const int64_t t = *d_n; n = t < n ? t : n; }
-    const TopCand T = thr[k - 1];
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
-        const int64_t g = base + threadIdx.x;
-        bool keep = false;
-        TopCand x;
-        if (g < n) {
-            x.sum = gsum[g];
-            x.key = gkey[g];
-            x.idx = (int32_t)g;
-            keep = T.idx < 0 || !top_before(T, x);
+    const int64_t T = thr[0];
+    const int64_t chunk = (int64_t)blockDim.x * CHUNK_ITEMS;
+    for (int64_t c0 = (int64_t)blockIdx.x * chunk; c0 < n; c0 += (int64_t)gridDim.x * chunk) {
+        if (threadIdx.x == 0) s_cnt = 0;
+        __syncthreads();
+        int64_t sm[CHUNK_ITEMS];
+#pragma unroll
+        for (int j = 0; j < CHUNK_ITEMS; ++j) {
+            const int64_t g = c0 + (int64_t)j * blockDim.x + threadIdx.x;
+            sm[j] = g < n ? gsum[g] : INT64_MIN;
         }
-        const uint64_t m = ballot(keep);
-        int64_t pos = 0;
-        if (lane_id() == 0 && m) pos = atomic_add(d_out, (int64_t)popc64(m));
-        pos = __shfl(pos, 0, WAVE);
-        if (keep) out[pos + popc64(m & lanemask_lt())] = x;
-    }
-}
-
-__global__ void k_topk_emit(const TopCand* c, int k, const int64_t* gcnt, int32_t* out_key,
-                            int64_t* out_sum, int64_t* out_cnt, int32_t* d_k) {
-    __shared__ int s_n;
-    if (threadIdx.x == 0) s_n = 0;
-    __syncthreads();
-    for (int i = threadIdx.x; i < k; i += blockDim.x) {
-        const TopCand x = c[i];
-        if (x.idx >= 0) {
-            out_key[i] = x.key;
-            out_sum[i] = x.sum;
-            out_cnt[i] = gcnt[x.idx];
-            atomicAdd(&s_n, 1);
+        bool keep[CHUNK_ITEMS];
+        int32_t slot[CHUNK_ITEMS];
+#pragma unroll
+        for (int j = 0; j < CHUNK_ITEMS; ++j) {
+            const int64_t g = c0 + (int64_t)j * blockDim.x + threadIdx.x;
+            keep[j] = g < n && sm[j] >= T;
+            const uint64_t m = ballot(keep[j]);
+            int32_t wbase = 0;
+            if (lane_id() == 0 && m) wbase = atomicAdd(&s_cnt, (int32_t)popc64(m));
+            wbase = __shfl(wbase, 0, WAVE);
+            slot[j] = wbase + popc64(m & lanemask_lt());
         }
+        __syncthreads();
+        if (threadIdx.x == 0) s_base = s_cnt ? atomic_add(d_out, (int64_t)s_cnt) : 0;
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < CHUNK_ITEMS; ++j) {
+            if (keep[j]) {
+                const int64_t g = c0 + (int64_t)j * blockDim.x + threadIdx.x;
+                TopCand x;
+                x.sum = sm[j];
+                x.key = gkey[g];
+                x.idx = (int32_t)g;
+                out[s_base + slot[j]] = x;
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    if (threadIdx.x == 0) *d_k = s_n;
 }
 
 }  // namespace tqp

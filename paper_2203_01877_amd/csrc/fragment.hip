@@ -121,6 +121,7 @@ void cust_reserve(Arena& a, const tqp_cust_fragment& f, const tqp_cust_out& o, C
     b.nbuckets = int64_t(1) << (cb - b.lowb);
     b.grp = radix_reserve<Cfg, uint64_t>(a, f.join_cap, cb, b.lowb);
     b.sstatus = a.zero<uint64_t>(b.nbuckets);
+    b.bstarts = a.scratch<int64_t>(b.nbuckets + 1);
     b.scounter = a.zero<uint32_t>(1);
     b.fkeys = a.scratch<uint32_t>(f.n_fact);
     b.fvals = a.scratch<uint64_t>(f.n_fact);
@@ -181,9 +182,12 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
                                           b.gvals, ctx, s)) != TQP_OK)
         return st;
     SegOut so{o.key, o.sum, o.cnt, nullptr, o.gcap, o.d_ngroups};
+    TQP_LAUNCH(ctx, s, "bucket_bounds",
+               k_bucket_bounds<<<grid_for(b.nbuckets + 1, 256, 0), 256, 0, s>>>(b.gkeys, f.join_cap, b.d_join,
+                                                                                  b.lowb, b.nbuckets, b.bstarts));
     TQP_LAUNCH(ctx, s, "bucket_agg",
                k_bucket_agg<BUCKET_BLOCK><<<(unsigned)b.nbuckets, BUCKET_BLOCK, 0, s>>>(
-                   b.gkeys, reinterpret_cast<const int64_t*>(b.gvals), f.join_cap, b.d_join, b.lowb, b.nbuckets,
+                   b.gkeys, reinterpret_cast<const int64_t*>(b.gvals), b.bstarts, b.lowb, b.nbuckets,
                    b.sstatus, b.scounter, so, ctx->d_err));
     // ORDER BY sum DESC, custkey ASC LIMIT k
     if ((st = topk_launch(b.topk, o.key, o.sum, o.cnt, o.d_ngroups, f.k, o.top_key, o.top_sum, o.top_cnt,

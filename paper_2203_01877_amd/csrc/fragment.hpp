@@ -9,7 +9,7 @@
 
 namespace tqp {
 
-using JCfgFrag = JoinCfg<256, 8, 2048>;
+using JCfgFrag = JoinCfg<512, 4, 2048>;
 using SCfgFrag = SegCfg<256, 16>;
 
 // Join scratch: the R window of every left tile, the look-back status words
@@ -59,23 +59,18 @@ struct FlagsBufs {
     uint32_t *fkeys = nullptr, *fvals = nullptr, *dkeys = nullptr, *dvals = nullptr;
 };
 
-// Top-k scratch: the levels over a sample of the groups (giving the
-// threshold), the filtered candidates and their count, and the levels over
-// the candidates.  Each level keeps k of every CH candidates (k <= CH / 2, so
-// a level at least halves the set); 32 levels cover 2^30 groups.
-constexpr int TOPK_MAX_LEVELS = 32;
-constexpr int TOPK_CH = 2048;
-constexpr int64_t TOPK_SAMPLE = 16384;
-
+// Top-k scratch: the sample threshold, the filtered candidates and their
+// count, and the chunk levels over the candidates.  Each level keeps k of
+// every CH candidates (k <= CH / 2, so a level at least halves the set); 32
+// levels cover 2^30 groups.
 struct TopkBufs {
-    int slevels = 0, levels = 0;
-    int64_t n_upper = 0, sample = 0;
-    int64_t sblocks[TOPK_MAX_LEVELS] = {0};
+    int levels = 0;            // chunk levels planned for the worst case
+    int64_t n_upper = 0;
     int64_t blocks[TOPK_MAX_LEVELS] = {0};
-    TopCand* scand[TOPK_MAX_LEVELS] = {nullptr};
-    TopCand* cand[TOPK_MAX_LEVELS] = {nullptr};
+    TopkLevels lvl = {};
     TopCand* filtered = nullptr;
     int64_t* d_nf = nullptr;
+    int64_t* thr = nullptr;
 };
 
 TopkBufs topk_reserve(Arena& a, int64_t n_upper, int k);
@@ -91,6 +86,7 @@ struct CustBufs {
     RadixBufs<Cfg, uint64_t> grp;
     int lowb = 0;              // group-key bits resolved in LDS by the bucket kernel
     int64_t nbuckets = 0;
+    int64_t* bstarts = nullptr;    // start of every bucket, nbuckets + 1
     JoinBufs join;
     int64_t* d_join = nullptr;
     uint64_t* sstatus = nullptr;

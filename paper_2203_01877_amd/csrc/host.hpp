@@ -194,7 +194,7 @@ tqp_status radix_launch(const RadixBufs<Cfg, V>& b, const Src0& src0, int64_t n_
     const int64_t tiles = b.ntiles;
     if (tiles == 0) return TQP_OK;
     if (run_hist) {
-        const int g = grid_for(n_upper, (int64_t)Cfg::BLOCK * 16, (int64_t)ctx->num_cus * 4);
+        const int g = grid_for(n_upper, (int64_t)Cfg::BLOCK * HIST_ITEMS * 4, (int64_t)ctx->num_cus * 2);
         TQP_LAUNCH(ctx, s, "radix_hist",
                    k_radix_hist<Cfg, Src0><<<g, Cfg::BLOCK, 0, s>>>(src0, b.pd, key_mask, b.hist, b.d_cnt,
                                                                     ctx->d_err));

@@ -239,8 +239,10 @@ __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, 
         __syncthreads();
     }
     // Match count and first match of each element: rightHist of its key.
-    int32_t cnt[ITEMS];
-    int64_t first[ITEMS], off[ITEMS];      // off: exclusive offset of the element within the wave chunk
+    // first is relative to the window (windows hold fewer than 2^31 rows).
+    // The per-element output offsets are not kept: the emit phase redoes the
+    // wave scans, which costs less than holding them across the look-back.
+    int32_t cnt[ITEMS], first[ITEMS];
     int64_t wave_total = 0;
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
@@ -251,17 +253,15 @@ __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, 
             if (direct) {
                 const int v = (int)(key[j] - kmin);
                 cnt[j] = sm.cnt[v];
-                first[j] = sm.first[v];      // relative to the window
+                first[j] = sm.first[v];
             } else {
                 const int64_t lb = lower_bound_glb(rkey, wlo, whi, key[j]);
                 const int64_t ub = upper_bound_glb(rkey, lb, whi, key[j]);
-                first[j] = lb;
+                first[j] = (int32_t)(lb - wlo);
                 cnt[j] = (int32_t)(ub - lb);
             }
         }
-        const int64_t incl = wave_incl_sum((int64_t)cnt[j]);
-        off[j] = wave_total + incl - cnt[j];
-        wave_total += __shfl(incl, WAVE - 1, WAVE);
+        wave_total += wave_sum((int64_t)cnt[j]);
     }
     if (l == 0) sm.wave[w] = wave_total;
     __syncthreads();
@@ -282,13 +282,15 @@ __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, 
     int64_t wbase = sm.base;
     for (int ww = 0; ww < w; ++ww) wbase += sm.wave[ww];
     // Expansion: output o of element i pairs it with right element first + (o - offset(i)).
-    auto right = [&](int64_t r) -> RP {
+    auto right = [&](int64_t r) -> RP {        // r relative to the window
         if (direct) return sm.rpay[r];
-        return rpay ? rpay[r] : (RP)r;
+        return rpay ? rpay[wlo + r] : (RP)(wlo + r);
     };
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-        const int64_t o = wbase + off[j];
+        const int64_t incl = wave_incl_sum((int64_t)cnt[j]);
+        const int64_t o = wbase + incl - cnt[j];
+        wbase += __shfl(incl, WAVE - 1, WAVE);
         const bool small = cnt[j] <= JOIN_LANE_MAX;
         if (small)
             for (int t = 0; t < cnt[j]; ++t) e(o + t, key[j], pay[j], right(first[j] + t), esm);

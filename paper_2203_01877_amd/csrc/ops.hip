@@ -12,57 +12,43 @@ namespace tqp {
 using JCfg = JoinCfg<256, 8, 4096>;
 using SCfg = SegCfg<256, 16>;
 constexpr int FILTER_BLOCK = 256, FILTER_ITEMS = 16;
-constexpr int TOPK_BLOCK = 1024;
 
 // ---------------------------------------------------------------- top-k plan
-// Worst-case level structure for n candidates: level l gets n_l rows in
-// max(1, ceil(n_l / CH)) chunks and leaves k per chunk.
-static int topk_plan_levels(int64_t n, int k, int64_t* blocks, TopCand** cand, Arena& a) {
-    int levels = 0;
-    for (int l = 0; l < TOPK_MAX_LEVELS; ++l) {
-        int64_t b = (n + TOPK_CH - 1) / TOPK_CH;
-        if (b < 1) b = 1;
-        blocks[l] = b;
-        cand[l] = a.scratch<TopCand>(b * k);
-        levels = l + 1;
-        if (b == 1) break;
-        n = b * k;
-    }
-    return levels;
-}
-
+// Chunk levels for the worst case (every group survives the filter): level l
+// runs while its input n_l exceeds TOPK_DIRECT and leaves k per chunk of CH.
 TopkBufs topk_reserve(Arena& a, int64_t n_upper, int k) {
     TopkBufs t;
     t.n_upper = n_upper;
-    t.sample = n_upper < TOPK_SAMPLE ? n_upper : TOPK_SAMPLE;
-    t.slevels = topk_plan_levels(t.sample, k, t.sblocks, t.scand, a);
     t.d_nf = a.zero<int64_t>(1);
+    t.thr = a.scratch<int64_t>(1);
     t.filtered = a.scratch<TopCand>(n_upper > 0 ? n_upper : 1);
-    t.levels = topk_plan_levels(n_upper, k, t.blocks, t.cand, a);
+    int64_t n = n_upper;
+    while (n > TOPK_DIRECT && t.levels < TOPK_MAX_LEVELS) {
+        const int64_t b = (n + TOPK_CH - 1) / TOPK_CH;
+        t.blocks[t.levels] = b;
+        t.lvl.out[t.levels] = a.scratch<TopCand>(b * k);
+        ++t.levels;
+        n = b * k;
+    }
     return t;
 }
 
 tqp_status topk_launch(const TopkBufs& t, const int32_t* key, const int64_t* sum, const int64_t* cnt,
                        const int64_t* d_n, int k, int32_t* out_key, int64_t* out_sum, int64_t* out_cnt,
                        int32_t* d_k, hipStream_t s, tqp_ctx* ctx) {
-    // 1. first k of the sample (the leading groups) -> threshold
-    for (int l = 0; l < t.slevels; ++l) {
-        TQP_LAUNCH(ctx, s, "topk_sample",
-                   k_topk_level<TOPK_BLOCK, TOPK_CH><<<(unsigned)t.sblocks[l], TOPK_BLOCK, 0, s>>>(
-                       key, sum, t.sample, d_n, l == 0 ? nullptr : t.scand[l - 1], t.scand[l], k, l));
-    }
-    // 2. groups not ordered after the threshold
+    TQP_LAUNCH(ctx, s, "topk_thresh",
+               (k_topk_thresh<TOPK_BLOCK, TOPK_SAMPLE_PER><<<1, TOPK_BLOCK, 0, s>>>(sum, t.n_upper, d_n, k, t.thr)));
     TQP_LAUNCH(ctx, s, "topk_filter",
-               k_topk_filter<<<grid_for(t.n_upper, 256 * 8, (int64_t)ctx->num_cus * 8), 256, 0, s>>>(
-                   key, sum, t.n_upper, d_n, t.scand[t.slevels - 1], k, t.filtered, t.d_nf));
-    // 3. first k of the candidates
+               k_topk_filter<<<grid_for(t.n_upper, 256 * 8, (int64_t)ctx->num_cus * 4), 256, 0, s>>>(
+                   key, sum, t.n_upper, d_n, t.thr, t.filtered, t.d_nf));
     for (int l = 0; l < t.levels; ++l) {
         TQP_LAUNCH(ctx, s, "topk_level",
-                   k_topk_level<TOPK_BLOCK, TOPK_CH><<<(unsigned)t.blocks[l], TOPK_BLOCK, 0, s>>>(
-                       nullptr, nullptr, t.n_upper, t.d_nf, l == 0 ? t.filtered : t.cand[l - 1], t.cand[l], k, l));
+                   (k_topk_level<TOPK_BLOCK, TOPK_CH><<<(unsigned)t.blocks[l], TOPK_BLOCK, 0, s>>>(
+                       t.d_nf, l == 0 ? t.filtered : t.lvl.out[l - 1], t.lvl.out[l], k, l)));
     }
-    TQP_LAUNCH(ctx, s, "topk_emit",
-               k_topk_emit<<<1, 256, 0, s>>>(t.cand[t.levels - 1], k, cnt, out_key, out_sum, out_cnt, d_k));
+    TQP_LAUNCH(ctx, s, "topk_final",
+               (k_topk_final<TOPK_BLOCK, TOPK_FINAL_PER><<<1, TOPK_BLOCK, 0, s>>>(t.d_nf, t.filtered, t.lvl, t.levels, k,
+                                                                         cnt, out_key, out_sum, out_cnt, d_k)));
     return TQP_OK;
 }
 
@@ -241,7 +227,7 @@ tqp_status tqp_topk(tqp_ctx* ctx, const int32_t* key, const int64_t* sum, const 
     clear_error();
     if (!ctx || !out_key || !out_sum || !out_cnt || !d_k || n < 0 || (n > 0 && (!key || !sum || !cnt)))
         return fail(TQP_ERR_INVALID, "tqp_topk: null pointer or n < 0");
-    if (k < 1 || k > 1024) return fail(TQP_ERR_UNSUPPORTED, "tqp_topk: k = %d", k);
+    if (k < 1 || k > TOPK_K_MAX) return fail(TQP_ERR_UNSUPPORTED, "tqp_topk: k = %d", k);
     if (n > MAX_ELEMS) return fail(TQP_ERR_UNSUPPORTED, "tqp_topk: n = %lld", (long long)n);
     TopkBufs t;
     Arena a;

@@ -185,6 +185,8 @@ struct PassDesc {
 };
 
 // ------------------------------------------------------------------ histogram
+constexpr int HIST_ITEMS = 8;
+
 // One read of the input: digit histograms of every pass (LDS-privatised, then
 // merged with one global atomic per bin and block), the number of elements
 // that take part, and the key-width check.
@@ -201,15 +203,28 @@ k_radix_hist(Src src, PassDesc pd, uint32_t key_mask, uint32_t* hist, int64_t* d
     __syncthreads();
     const int64_t n = src.size();
     uint32_t cnt = 0, bad = 0;
-    for (int64_t i = (int64_t)blockIdx.x * Cfg::BLOCK + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * Cfg::BLOCK) {
-        uint32_t k;
-        if (!src.load_key(i, k)) continue;
-        ++cnt;
-        bad |= k & ~key_mask;
-        for (int p = 0; p < pd.npass; ++p) {
-            uint32_t d = (k >> pd.shift[p]) & ((1u << pd.bits[p]) - 1);
-            atomicAdd(&h[p * R + d], 1u);
+    // HIST_ITEMS loads per thread are issued before any counter update, so
+    // each wave keeps that many requests in flight.
+    constexpr int U = HIST_ITEMS;
+    const int64_t step = (int64_t)gridDim.x * Cfg::BLOCK * U;
+    for (int64_t base = (int64_t)blockIdx.x * Cfg::BLOCK * U + threadIdx.x; base < n; base += step) {
+        uint32_t kk[U];
+        bool ok[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int64_t i = base + (int64_t)j * Cfg::BLOCK;
+            ok[j] = i < n && src.load_key(i, kk[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            if (!ok[j]) continue;
+            const uint32_t k = kk[j];
+            ++cnt;
+            bad |= k & ~key_mask;
+            for (int p = 0; p < pd.npass; ++p) {
+                uint32_t d = (k >> pd.shift[p]) & ((1u << pd.bits[p]) - 1);
+                atomicAdd(&h[p * R + d], 1u);
+            }
         }
     }
     cnt = wave_sum(cnt);

@@ -184,40 +184,46 @@ k_segreduce(const uint32_t* keys, VS vs, int64_t n_upper, const int64_t* d_n, ui
 // at the offset given by a look-back over the buckets' group counts.
 constexpr int BUCKET_LOWB_MAX = 9;
 
+// Start of every bucket in the high-bit-sorted keys (starts[nbuckets] = n),
+// one binary search per bucket.
+__global__ void k_bucket_bounds(const uint32_t* keys, int64_t n_upper, const int64_t* d_n, int lowb,
+                                int64_t nbuckets, int64_t* starts);
+
 template <int BLOCK>
 __global__ void __launch_bounds__(BLOCK)
-k_bucket_agg(const uint32_t* keys, const int64_t* vals, int64_t n_upper, const int64_t* d_n, int lowb,
+k_bucket_agg(const uint32_t* keys, const int64_t* vals, const int64_t* starts, int lowb,
              int64_t nbuckets, uint64_t* status, uint32_t* counter, SegOut out, uint32_t* flags) {
     constexpr int SLOTS = 1 << BUCKET_LOWB_MAX;
+    constexpr int U = 8;                               // loads in flight per thread
     __shared__ unsigned long long s_sum[SLOTS];
-    __shared__ unsigned long long s_cnt[SLOTS];
-    __shared__ int64_t s_lo, s_hi, s_base;
+    __shared__ uint32_t s_cnt[SLOTS];
+    __shared__ int64_t s_base;
     __shared__ int32_t s_wave[BLOCK / WAVE];
     __shared__ uint32_t s_b;
     const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
-    int64_t n = n_upper;
-    if (d_n) { const int64_t t = *d_n; n = t < n ? t : n; }
     if (tid == 0) s_b = atomicAdd(counter, 1u);
     const int slots = 1 << lowb;
     for (int i = tid; i < slots; i += BLOCK) { s_sum[i] = 0; s_cnt[i] = 0; }
     __syncthreads();
     const int64_t b = s_b;
     if (b >= nbuckets) return;
-    // bucket bounds: two wave-wide searches
-    if (w == 0) {
-        const int64_t lo = wave_bound(keys, n, (uint32_t)(b << lowb), false);
-        if (l == 0) s_lo = lo;
-    } else if (w == 1) {
-        const int64_t hi = b + 1 < nbuckets ? wave_bound(keys, n, (uint32_t)((b + 1) << lowb), false) : n;
-        if (l == 0) s_hi = hi;
-    }
-    __syncthreads();
-    const int64_t lo = s_lo, hi = s_hi;
+    const int64_t lo = starts[b], hi = starts[b + 1];
     const uint32_t lmask = (uint32_t)slots - 1;
-    for (int64_t i = lo + tid; i < hi; i += BLOCK) {
-        const uint32_t k = keys[i] & lmask;
-        atomicAdd(&s_sum[k], (unsigned long long)vals[i]);
-        atomicAdd(&s_cnt[k], 1ull);
+    for (int64_t i0 = lo + tid; i0 < hi; i0 += (int64_t)BLOCK * U) {
+        uint32_t k[U];
+        int64_t v[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int64_t i = i0 + (int64_t)j * BLOCK;
+            if (i < hi) { k[j] = keys[i] & lmask; v[j] = vals[i]; }
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            if (i0 + (int64_t)j * BLOCK < hi) {
+                atomicAdd(&s_sum[k[j]], (unsigned long long)v[j]);
+                atomicAdd(&s_cnt[k[j]], 1u);
+            }
+        }
     }
     __syncthreads();
     // non-empty slots in ascending order -> local group index

@@ -175,12 +175,26 @@ def test_groupby_parity(hip, ctx, n, domain):
 # ------------------------------------------------------------------ top-k
 @pytest.mark.parametrize("n,k", [(0, 10), (5, 10), (100, 100), (2048, 100), (2049, 7), (1_500_000, 100),
                                  (300_000, 1024)])
-def test_topk_parity(hip, ctx, n, k):
+@pytest.mark.parametrize("dist", ["random", "equal", "signed", "ascending"])
+def test_topk_parity(hip, ctx, n, k, dist):
+    """Sum distributions: many ties; all equal (every group passes the
+    threshold, so the chunk levels and the final merge rounds all run);
+    negative and positive sums; sums growing with the key (the strided
+    sample still bounds the threshold)."""
+    if dist != "random" and n > 300_000:
+        pytest.skip("the large case runs with the random distribution only")
     rng = _rng(n + k)
     key = rng.permutation(max(1, 2 * n))[:n].astype(np.int32)       # unique keys
-    s = rng.integers(0, 1000, n).astype(np.int64) * 1_000_003       # many equal sums
+    if dist == "random":
+        s = rng.integers(0, 1000, n).astype(np.int64) * 1_000_003   # many equal sums
+    elif dist == "equal":
+        s = np.full(n, 777, dtype=np.int64)
+    elif dist == "signed":
+        s = rng.integers(-10**15, 10**15, n).astype(np.int64)
+    else:
+        s = key.astype(np.int64) * 3 - n
     c = rng.integers(1, 50, n).astype(np.int64)
-    order = sorted(range(n), key=lambda i: (-int(s[i]), int(key[i])))[:k]
+    order = np.lexsort((key, -s))[:k]
     out = hip.topk(ctx, _dev(key), _dev(s), _dev(c), k)
     kk = int(_np(out["d_k"])[0])
     assert kk == min(k, n)
