@@ -9,15 +9,15 @@
 
 namespace tqp {
 
-using JCfgFrag = JoinCfg<512, 4, 2048>;
+using JCfgFrag = JoinCfg<256, 8, 2048>;
 using SCfgFrag = SegCfg<256, 16>;
 
-// Join scratch: the R window of every left tile, the look-back status words
-// and the dynamic tile counter.
+// Join scratch: the R window of every left tile, the dynamic tile counter,
+// and the per-tile output counts / offsets of the two-kernel join.
 struct JoinBufs {
     int64_t tiles = 0;
     int64_t* win = nullptr;
-    uint64_t* status = nullptr;
+    int64_t* tile_off = nullptr;
     uint32_t* counter = nullptr;
 };
 
@@ -25,12 +25,17 @@ template <class Cfg>
 JoinBufs join_reserve(Arena& a, int64_t nl_upper) {
     JoinBufs b;
     b.tiles = (nl_upper + Cfg::TILE - 1) / Cfg::TILE;
-    b.status = a.zero<uint64_t>(b.tiles);
     b.counter = a.zero<uint32_t>(1);
     b.win = a.scratch<int64_t>(2 * b.tiles);
+    b.tile_off = a.scratch<int64_t>(b.tiles > 0 ? b.tiles : 1);
     return b;
 }
 
+// Emitters that write at output positions run the two-kernel join (per-tile
+// counts, their scan, then the expansion at known bases); aggregating
+// emitters need only the join size and run the expansion directly.  Either
+// way *d_count ends up holding the join size; for the aggregating form it
+// must be zero on entry.
 template <class Cfg, class LP, class RP, class Emit>
 tqp_status join_launch(tqp_ctx* ctx, hipStream_t s, const char* name, const JoinBufs& b, const uint32_t* lkey,
                        const LP* lpay, int64_t nl, const int64_t* d_nl, const uint32_t* rkey, const RP* rpay,
@@ -43,10 +48,20 @@ tqp_status join_launch(tqp_ctx* ctx, hipStream_t s, const char* name, const Join
                                                                             Cfg::TILE, b.win, lowb));
     }
     const int grid = grid_for(tiles, 1, (int64_t)ctx->num_cus * 4);
+    if (Emit::ORDERED) {
+        if (tiles > 0) {
+            TQP_LAUNCH(ctx, s, "join_count",
+                       k_join_count<Cfg><<<grid, Cfg::BLOCK, 0, s>>>(lkey, nl, d_nl, rkey, b.win, b.tile_off, lowb));
+        }
+        TQP_LAUNCH(ctx, s, "join_scan",
+                   k_join_scan<<<1, JOIN_SCAN_BLOCK, 0, s>>>(b.tile_off, nl, d_nl, Cfg::TILE, d_count, cap,
+                                                            ctx->d_err));
+        if (tiles == 0) return TQP_OK;
+    }
     TQP_LAUNCH(ctx, s, name,
-               k_join<Cfg, LP, RP, Emit><<<grid, Cfg::BLOCK, 0, s>>>(lkey, lpay, nl, d_nl, rkey, rpay, nr, d_nr,
-                                                                   b.win, b.status, b.counter, d_count, cap, e,
-                                                                   ctx->d_err, lowb));
+               k_join<Cfg, LP, RP, Emit><<<grid, Cfg::BLOCK, 0, s>>>(
+                   lkey, lpay, nl, d_nl, rkey, rpay, b.win, nullptr, b.counter, Emit::ORDERED ? b.tile_off : nullptr,
+                   d_count, cap, e, ctx->d_err, lowb));
     return TQP_OK;
 }
 

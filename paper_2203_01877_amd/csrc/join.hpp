@@ -43,6 +43,7 @@ constexpr int JOIN_LANE_MAX = 4;
 // ------------------------------------------------------------------ emitters
 // Index pairs (late materialisation: the join returns row-index pairs).
 struct EmitPairs {
+    static constexpr bool ORDERED = true;      // writes at the output positions
     int32_t* out_l;
     int32_t* out_r;
     int64_t cap;
@@ -61,6 +62,7 @@ struct EmitPairs {
 // digit histograms of the following group-key sort accumulated on the way.
 template <int BLOCK, int RB>
 struct EmitKeyVal {
+    static constexpr bool ORDERED = true;
     static constexpr int R = 1 << RB;
     static constexpr int NP = (32 + RB - 1) / RB;
     uint32_t* out_key;
@@ -103,6 +105,7 @@ struct EmitKeyVal {
 // flagA * 2 + flagB in registers; flush once per block.
 template <int BLOCK>
 struct EmitFlagsAgg {
+    static constexpr bool ORDERED = false;     // aggregates only: positions unused
     static constexpr int G = 8;
     const int64_t* price;
     const int64_t* disc;
@@ -193,12 +196,69 @@ __device__ __forceinline__ void tile_key_range(const uint32_t* lkey, int64_t fir
     kmax = ((lkey[last] >> lowb) << lowb) | ((1u << lowb) - 1);
 }
 
+// Output rows of one left tile, for the counting kernel of the two-kernel
+// join: the same direct table (counts only) or global searches as join_tile,
+// with no payload traffic.  The value is returned to every thread.
+template <class Cfg, class RP>
+__device__ __forceinline__ int64_t join_tile_count(const uint32_t* lkey, int64_t nl, const uint32_t* rkey,
+                                                   int64_t wlo, int64_t whi, int64_t tile, JoinSmem<Cfg, RP>& sm,
+                                                   int lowb) {
+    constexpr int TILE = Cfg::TILE, ITEMS = Cfg::ITEMS, RWIN = Cfg::RWIN, W = Cfg::WAVES;
+    const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
+    const int64_t t0 = tile * TILE;
+    const int64_t tlast = (t0 + TILE < nl ? t0 + TILE : nl) - 1;
+    uint32_t kmin, kmax;
+    tile_key_range(lkey, t0, tlast, lowb, kmin, kmax);
+    const int64_t wn = whi - wlo;
+    const bool direct = wn <= RWIN && (int64_t)kmax - (int64_t)kmin < RWIN;
+    if (direct) {
+        const int range = (int)(kmax - kmin) + 1;
+        for (int i = tid; i < range; i += Cfg::BLOCK) sm.cnt[i] = 0;
+    }
+    const int64_t chunk = t0 + (int64_t)w * ITEMS * WAVE;
+    uint32_t key[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int64_t i = chunk + j * WAVE + l;
+        key[j] = i < nl ? lkey[i] : 0;
+    }
+    __syncthreads();
+    if (direct) {
+        for (int i = tid; i < wn; i += Cfg::BLOCK) atomicAdd(&sm.cnt[(int)(rkey[wlo + i] - kmin)], 1);
+        __syncthreads();
+    }
+    int64_t c = 0;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int64_t i = chunk + j * WAVE + l;
+        if (i < nl) {
+            if (direct) {
+                c += sm.cnt[(int)(key[j] - kmin)];
+            } else {
+                const int64_t lb = lower_bound_glb(rkey, wlo, whi, key[j]);
+                c += upper_bound_glb(rkey, lb, whi, key[j]) - lb;
+            }
+        }
+    }
+    c = wave_sum(c);
+    if (l == 0) sm.wave[w] = c;
+    __syncthreads();
+    int64_t tot = 0;
+    for (int ww = 0; ww < W; ++ww) tot += sm.wave[ww];
+    __syncthreads();
+    return tot;
+}
+
+// tile_off (two-kernel join): the tile's output base, from the exclusive scan
+// of the counting kernel's tile totals; null: the base comes from a decoupled
+// look-back over status, and the last tile stores the join size.  Emitters
+// that do not use output positions add the tile total to *d_count instead.
 template <class Cfg, class LP, class RP, class Emit>
 __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, int64_t nl, const uint32_t* rkey,
                                           const RP* rpay, int64_t wlo, int64_t whi, int64_t tile, int64_t ntiles,
                                           uint64_t* status, int64_t* d_count, int64_t cap, Emit& e,
                                           typename Emit::Smem& esm, JoinSmem<Cfg, RP>& sm, uint32_t* flags,
-                                          int lowb = 0) {
+                                          int lowb = 0, const int64_t* tile_off = nullptr) {
     constexpr int TILE = Cfg::TILE, ITEMS = Cfg::ITEMS, RWIN = Cfg::RWIN, W = Cfg::WAVES;
     const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
     const int64_t t0 = tile * TILE;
@@ -265,16 +325,25 @@ __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, 
     }
     if (l == 0) sm.wave[w] = wave_total;
     __syncthreads();
-    // Tile output base: block scan of the wave totals + decoupled look-back.
+    // Tile output base: block scan of the wave totals + the tile's offset.
     if (w == 0) {
         int64_t tot = 0;
         for (int ww = 0; ww < W; ++ww) tot += sm.wave[ww];
-        const int64_t base = lookback64(status, tile, tot, flags);
-        if (tid == 0) {
-            sm.base = base;
-            if (tile == ntiles - 1) {
-                *d_count = base + tot;
-                if (base + tot > cap) set_flag(flags, FLAG_CAPACITY);
+        if (!Emit::ORDERED) {
+            if (tid == 0) {
+                sm.base = 0;
+                if (tot) atomic_add(d_count, tot);
+            }
+        } else if (tile_off) {
+            if (tid == 0) sm.base = tile_off[tile];
+        } else {
+            const int64_t base = lookback64(status, tile, tot, flags);
+            if (tid == 0) {
+                sm.base = base;
+                if (tile == ntiles - 1) {
+                    *d_count = base + tot;
+                    if (base + tot > cap) set_flag(flags, FLAG_CAPACITY);
+                }
             }
         }
     }
@@ -309,29 +378,60 @@ __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, 
     __syncthreads();
 }
 
+// Per-tile output counts (first kernel of the two-kernel join), tiles in a
+// grid-stride loop.
+template <class Cfg>
+__global__ void __launch_bounds__(Cfg::BLOCK)
+k_join_count(const uint32_t* lkey, int64_t nl_upper, const int64_t* d_nl, const uint32_t* rkey,
+             const int64_t* win, int64_t* tile_cnt, int lowb) {
+    __shared__ JoinSmem<Cfg, uint8_t> sm;
+    int64_t nl = nl_upper;
+    if (d_nl) { const int64_t t = *d_nl; nl = t < nl ? t : nl; }
+    const int64_t ntiles = (nl + Cfg::TILE - 1) / Cfg::TILE;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t t = join_tile_count<Cfg, uint8_t>(lkey, nl, rkey, win[2 * tile], win[2 * tile + 1], tile, sm,
+                                                        lowb);
+        if (threadIdx.x == 0) tile_cnt[tile] = t;
+    }
+}
+
+// Exclusive scan of the per-tile counts, in place, by one block of
+// JOIN_SCAN_BLOCK threads; *d_count = the join size.
+constexpr int JOIN_SCAN_BLOCK = 1024;
+__global__ void k_join_scan(int64_t* tile_cnt, int64_t nl_upper, const int64_t* d_nl, int tile_size,
+                            int64_t* d_count, int64_t cap, uint32_t* flags);
+
+// The join.  With tile_off (two-kernel join) tiles go in a grid-stride loop
+// and bases come from tile_off; otherwise tiles are pulled from a counter and
+// bases come from the look-back (or are unused, for emitters that only
+// aggregate).  The kernel is persistent, so emitters can accumulate across
+// tiles and flush once.
 template <class Cfg, class LP, class RP, class Emit>
 __global__ void __launch_bounds__(Cfg::BLOCK)
 k_join(const uint32_t* lkey, const LP* lpay, int64_t nl_upper, const int64_t* d_nl,
-       const uint32_t* rkey, const RP* rpay, int64_t nr_upper, const int64_t* d_nr, const int64_t* win,
-       uint64_t* status, uint32_t* tile_counter, int64_t* d_count, int64_t cap, Emit emit,
-       uint32_t* flags, int lowb) {
+       const uint32_t* rkey, const RP* rpay, const int64_t* win, uint64_t* status, uint32_t* tile_counter,
+       const int64_t* tile_off, int64_t* d_count, int64_t cap, Emit emit, uint32_t* flags, int lowb) {
     __shared__ JoinSmem<Cfg, RP> sm;
     __shared__ typename Emit::Smem esm;
     int64_t nl = nl_upper;
     if (d_nl) { int64_t t = *d_nl; nl = t < nl ? t : nl; }
-    (void)nr_upper;
-    (void)d_nr;
     const int64_t ntiles = (nl + Cfg::TILE - 1) / Cfg::TILE;
     Emit e = emit;
     e.init(esm);
-    if (ntiles == 0 && blockIdx.x == 0 && threadIdx.x == 0) *d_count = 0;
-    for (;;) {
-        if (threadIdx.x == 0) sm.tile = atomicAdd(tile_counter, 1u);
-        __syncthreads();
-        const int64_t tile = sm.tile;
-        if (tile >= ntiles) break;
-        join_tile<Cfg, LP, RP, Emit>(lkey, lpay, nl, rkey, rpay, win[2 * tile], win[2 * tile + 1], tile, ntiles,
-                                     status, d_count, cap, e, esm, sm, flags, lowb);
+    if (Emit::ORDERED && !tile_off && ntiles == 0 && blockIdx.x == 0 && threadIdx.x == 0) *d_count = 0;
+    if (tile_off) {
+        for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+            join_tile<Cfg, LP, RP, Emit>(lkey, lpay, nl, rkey, rpay, win[2 * tile], win[2 * tile + 1], tile, ntiles,
+                                         status, d_count, cap, e, esm, sm, flags, lowb, tile_off);
+    } else {
+        for (;;) {
+            if (threadIdx.x == 0) sm.tile = atomicAdd(tile_counter, 1u);
+            __syncthreads();
+            const int64_t tile = sm.tile;
+            if (tile >= ntiles) break;
+            join_tile<Cfg, LP, RP, Emit>(lkey, lpay, nl, rkey, rpay, win[2 * tile], win[2 * tile + 1], tile, ntiles,
+                                         status, d_count, cap, e, esm, sm, flags, lowb);
+        }
     }
     e.finish(esm);
 }
