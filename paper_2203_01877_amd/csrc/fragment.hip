@@ -6,8 +6,17 @@
 
 namespace tqp {
 
-constexpr int BUCKET_LOWB_DEFAULT = 7;
-constexpr int BUCKET_BLOCK = 256;
+// Group-key bits left to the bucket kernel: enough that the bits above them
+// take one radix pass (a digit's worth of buckets), at most BUCKET_LOWB_MAX.
+// Small slot tables go to 256-thread blocks, large ones to one 1024-thread
+// block per CU.
+int bucket_low_bits(int cb, int rb) {
+    int lowb = cb - rb;
+    if (lowb < 0) lowb = 0;
+    if (lowb > BUCKET_LOWB_MAX) lowb = BUCKET_LOWB_MAX;
+    return lowb;
+}
+constexpr int BUCKET_SMALL_LOWB = 9;
 
 // Low key bits the fact sort may leave out.  A join tile of TILE left rows
 // over keys spread evenly on [0, 2^kb) spans about TILE * 2^kb / n key values
@@ -116,8 +125,7 @@ void cust_reserve(Arena& a, const tqp_cust_fragment& f, const tqp_cust_out& o, C
     b.d_join = a.zero<int64_t>(1);
     // group-by: radix passes over the custkey bits above lowb, then one
     // bucket-aggregation block per value of those bits
-    b.lowb = cb < BUCKET_LOWB_DEFAULT + 1 ? cb - 1 : BUCKET_LOWB_DEFAULT;
-    if (b.lowb < 0) b.lowb = 0;
+    b.lowb = bucket_low_bits(cb, Cfg::RADIX_BITS);
     b.nbuckets = int64_t(1) << (cb - b.lowb);
     b.grp = radix_reserve<Cfg, uint64_t>(a, f.join_cap, cb, b.lowb);
     b.sstatus = a.zero<uint64_t>(b.nbuckets);
@@ -185,10 +193,16 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
     TQP_LAUNCH(ctx, s, "bucket_bounds",
                k_bucket_bounds<<<grid_for(b.nbuckets + 1, 256, 0), 256, 0, s>>>(b.gkeys, f.join_cap, b.d_join,
                                                                                   b.lowb, b.nbuckets, b.bstarts));
-    TQP_LAUNCH(ctx, s, "bucket_agg",
-               k_bucket_agg<BUCKET_BLOCK><<<(unsigned)b.nbuckets, BUCKET_BLOCK, 0, s>>>(
-                   b.gkeys, reinterpret_cast<const int64_t*>(b.gvals), b.bstarts, b.lowb, b.nbuckets,
-                   b.sstatus, b.scounter, so, ctx->d_err));
+    const int64_t* gv = reinterpret_cast<const int64_t*>(b.gvals);
+    if (b.lowb <= BUCKET_SMALL_LOWB) {
+        TQP_LAUNCH(ctx, s, "bucket_agg",
+                   (k_bucket_agg<256, 1 << BUCKET_SMALL_LOWB><<<(unsigned)b.nbuckets, 256, 0, s>>>(
+                       b.gkeys, gv, b.bstarts, b.lowb, b.nbuckets, b.sstatus, b.scounter, so, ctx->d_err)));
+    } else {
+        TQP_LAUNCH(ctx, s, "bucket_agg",
+                   (k_bucket_agg<1024, 1 << BUCKET_LOWB_MAX><<<(unsigned)b.nbuckets, 1024, 0, s>>>(
+                       b.gkeys, gv, b.bstarts, b.lowb, b.nbuckets, b.sstatus, b.scounter, so, ctx->d_err)));
+    }
     // ORDER BY sum DESC, custkey ASC LIMIT k
     if ((st = topk_launch(b.topk, o.key, o.sum, o.cnt, o.d_ngroups, f.k, o.top_key, o.top_sum, o.top_cnt,
                           o.d_topk, s, ctx)) != TQP_OK)

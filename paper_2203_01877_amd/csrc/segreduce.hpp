@@ -182,18 +182,18 @@ k_segreduce(const uint32_t* keys, VS vs, int64_t n_upper, const int64_t* d_n, ui
 // LDS, which is the counting sort of the last digit and the run reduction in
 // one step, then writes the bucket's non-empty groups in ascending key order
 // at the offset given by a look-back over the buckets' group counts.
-constexpr int BUCKET_LOWB_MAX = 9;
+constexpr int BUCKET_LOWB_MAX = 13;        // 8192 slots: 96 KB of LDS
 
 // Start of every bucket in the high-bit-sorted keys (starts[nbuckets] = n),
 // one binary search per bucket.
 __global__ void k_bucket_bounds(const uint32_t* keys, int64_t n_upper, const int64_t* d_n, int lowb,
                                 int64_t nbuckets, int64_t* starts);
 
-template <int BLOCK>
+template <int BLOCK, int SLOTS>
 __global__ void __launch_bounds__(BLOCK)
 k_bucket_agg(const uint32_t* keys, const int64_t* vals, const int64_t* starts, int lowb,
              int64_t nbuckets, uint64_t* status, uint32_t* counter, SegOut out, uint32_t* flags) {
-    constexpr int SLOTS = 1 << BUCKET_LOWB_MAX;
+    static_assert(SLOTS <= (1 << BUCKET_LOWB_MAX), "slot table larger than the LDS budget");
     constexpr int U = 8;                               // loads in flight per thread
     __shared__ unsigned long long s_sum[SLOTS];
     __shared__ uint32_t s_cnt[SLOTS];

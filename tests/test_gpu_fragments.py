@@ -106,8 +106,10 @@ def _assert_cust(got, want):
 
 @pytest.mark.parametrize("digit_bits", [4, 8, 11])
 @pytest.mark.parametrize("n,m,cust", [(1, 5, 3), (50_000, 10_000, 2_000), (400_000, 100_000, 30_000),
-                                      (300_007, 80_000, 1)])
+                                      (300_007, 80_000, 1), (1_500_000, 400_000, (1 << 20) + 7)])
 def test_cust_small(hip, ctx, digit_bits, n, m, cust):
+    """Custkey domains from one value to 2^21 (8192-slot buckets: one group
+    pass at 8- and 11-bit digits, two at 4-bit digits)."""
     fr = datagen.config2(seed=300 + n, n=n, m=m, cust_hi=cust)
     want = oracle.fragment_cust(fr.fact, fr.mid, fr.D, fr.k, gcap=min(n, cust))
     _assert_cust(_cust(hip, ctx, fr, digit_bits), want)
