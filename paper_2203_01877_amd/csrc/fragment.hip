@@ -120,7 +120,9 @@ void cust_reserve(Arena& a, const tqp_cust_fragment& f, const tqp_cust_out& o, C
     // never sorted.
     b.fact_lowb = fact_low_bits(f.n_fact, kb, Cfg::RADIX_BITS);
     b.fact = radix_reserve<Cfg, uint64_t>(a, f.n_fact, kb, b.fact_lowb);
-    b.mid = radix_reserve<Cfg, uint32_t>(a, f.n_mid, kb);
+    // the mid keys need the same high bits only: each join tile counting-sorts
+    // its window of them in LDS
+    b.mid = radix_reserve<Cfg, uint32_t>(a, f.n_mid, kb, b.fact_lowb);
     b.join = join_reserve<JCfgFrag>(a, f.n_fact);
     b.d_join = a.zero<int64_t>(1);
     // group-by: radix passes over the custkey bits above lowb, then one
@@ -173,20 +175,20 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
     e.cap = f.join_cap;
     e.key_mask = key_mask_for(cb);
     e.flags = ctx->d_err;
-    e.hist = nullptr;
+    e.hist = b.grp.hist;       // digit counts of the group-key sort, taken on the way out
     e.npass = b.grp.pd.npass;
     for (int p = 0; p < b.grp.pd.npass && p < Emit::NP; ++p) {
         e.shift[p] = b.grp.pd.shift[p];
         e.bits[p] = b.grp.pd.bits[p];
     }
-    if ((st = join_launch<JCfgFrag, uint64_t, uint32_t>(ctx, s, "join_keyval", b.join, b.fkeys, b.fvals, f.n_fact,
-                                                        b.fact.d_cnt, b.mkeys, b.mvals, f.n_mid,
-                                                        (const int64_t*)nullptr, b.d_join, f.join_cap, e,
-                                                        b.fact_lowb)) != TQP_OK)
+    if ((st = join_launch<JCfgFrag, uint64_t, uint32_t, Emit, true>(
+             ctx, s, "join_keyval", b.join, b.fkeys, b.fvals, f.n_fact, b.fact.d_cnt, b.mkeys, b.mvals, f.n_mid,
+             (const int64_t*)nullptr, b.d_join, f.join_cap, e, b.fact_lowb, b.fact_lowb)) != TQP_OK)
         return st;
-    // group-by: sort (custkey, revenue) by custkey, then reduce runs
+    // group-by: sort (custkey, revenue) on the custkey bits above lowb (the
+    // histogram came from the join), then aggregate each bucket
     SrcPairs<uint64_t> gsrc{b.gkeys_in, b.gvals_in, f.join_cap, b.d_join};
-    if ((st = radix_launch<Cfg, uint64_t>(b.grp, gsrc, f.join_cap, true, b.d_join, key_mask_for(cb), b.gkeys,
+    if ((st = radix_launch<Cfg, uint64_t>(b.grp, gsrc, f.join_cap, false, b.d_join, key_mask_for(cb), b.gkeys,
                                           b.gvals, ctx, s)) != TQP_OK)
         return st;
     SegOut so{o.key, o.sum, o.cnt, nullptr, o.gcap, o.d_ngroups};

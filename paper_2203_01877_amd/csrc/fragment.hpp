@@ -19,6 +19,8 @@ struct JoinBufs {
     int64_t* win = nullptr;
     int64_t* tile_off = nullptr;
     uint32_t* counter = nullptr;
+    uint32_t* scan_list = nullptr;     // tiles left to k_join_scan_tiles, and their count
+    uint32_t* scan_n = nullptr;
 };
 
 template <class Cfg>
@@ -28,6 +30,8 @@ JoinBufs join_reserve(Arena& a, int64_t nl_upper) {
     b.counter = a.zero<uint32_t>(1);
     b.win = a.scratch<int64_t>(2 * b.tiles);
     b.tile_off = a.scratch<int64_t>(b.tiles > 0 ? b.tiles : 1);
+    b.scan_list = a.scratch<uint32_t>(b.tiles > 0 ? b.tiles : 1);
+    b.scan_n = a.zero<uint32_t>(1);
     return b;
 }
 
@@ -36,11 +40,11 @@ JoinBufs join_reserve(Arena& a, int64_t nl_upper) {
 // emitters need only the join size and run the expansion directly.  Either
 // way *d_count ends up holding the join size; for the aggregating form it
 // must be zero on entry.
-template <class Cfg, class LP, class RP, class Emit>
+template <class Cfg, class LP, class RP, class Emit, bool PARTIAL = false>
 tqp_status join_launch(tqp_ctx* ctx, hipStream_t s, const char* name, const JoinBufs& b, const uint32_t* lkey,
                        const LP* lpay, int64_t nl, const int64_t* d_nl, const uint32_t* rkey, const RP* rpay,
                        int64_t nr, const int64_t* d_nr, int64_t* d_count, int64_t cap, const Emit& e,
-                       int lowb = 0) {
+                       int lowb = 0, int rlowb = 0) {
     const int64_t tiles = b.tiles;
     if (tiles > 0) {
         TQP_LAUNCH(ctx, s, "join_windows",
@@ -51,7 +55,8 @@ tqp_status join_launch(tqp_ctx* ctx, hipStream_t s, const char* name, const Join
     if (Emit::ORDERED) {
         if (tiles > 0) {
             TQP_LAUNCH(ctx, s, "join_count",
-                       k_join_count<Cfg><<<grid, Cfg::BLOCK, 0, s>>>(lkey, nl, d_nl, rkey, b.win, b.tile_off, lowb));
+                       k_join_count<Cfg><<<grid, Cfg::BLOCK, 0, s>>>(lkey, nl, d_nl, rkey, b.win, b.tile_off, lowb,
+                                                                     rlowb));
         }
         TQP_LAUNCH(ctx, s, "join_scan",
                    k_join_scan<<<1, JOIN_SCAN_BLOCK, 0, s>>>(b.tile_off, nl, d_nl, Cfg::TILE, d_count, cap,
@@ -59,9 +64,14 @@ tqp_status join_launch(tqp_ctx* ctx, hipStream_t s, const char* name, const Join
         if (tiles == 0) return TQP_OK;
     }
     TQP_LAUNCH(ctx, s, name,
-               k_join<Cfg, LP, RP, Emit><<<grid, Cfg::BLOCK, 0, s>>>(
+               (k_join<Cfg, LP, RP, Emit, PARTIAL><<<grid, Cfg::BLOCK, 0, s>>>(
                    lkey, lpay, nl, d_nl, rkey, rpay, b.win, nullptr, b.counter, Emit::ORDERED ? b.tile_off : nullptr,
-                   d_count, cap, e, ctx->d_err, lowb));
+                   d_count, cap, e, ctx->d_err, lowb, rlowb, b.scan_list, b.scan_n)));
+    if constexpr (PARTIAL) {
+        TQP_LAUNCH(ctx, s, "join_scan_tiles",
+                   (k_join_scan_tiles<Cfg, LP, RP, Emit><<<ctx->num_cus, Cfg::BLOCK, 0, s>>>(
+                       lkey, lpay, nl, d_nl, rkey, rpay, b.win, b.tile_off, b.scan_list, b.scan_n, e, rlowb)));
+    }
     return TQP_OK;
 }
 

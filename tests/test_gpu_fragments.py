@@ -5,6 +5,8 @@ oracle bit for bit (sums, counts, join size, averages).  The custkey fragment
 runs at small sizes and at the full 60M x 15M workload that the benchmark
 times, compared group by group.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -80,7 +82,7 @@ def test_flags_row_range(hip, ctx):
     _assert_flags(r.result(), oracle.fragment_flags(sub, fr.dim, fr.D, fr.c))
 
 
-def _cust(hip, ctx, fr, digit_bits=8, cust_bits=None):
+def _cust(hip, ctx, fr, digit_bits=8, cust_bits=None, join_cap=None):
     fact = hip.to_device({k: fr.fact[k] for k in ("fk", "date", "price", "disc")})
     mid = hip.to_device(fr.mid)
     kb = datagen.bits_for(max(int(fr.fact["fk"].max(initial=0)), int(fr.mid["pk"].max(initial=0))) + 1)
@@ -88,7 +90,7 @@ def _cust(hip, ctx, fr, digit_bits=8, cust_bits=None):
     ctx.set_digit_bits(digit_bits)
     try:
         r = hip.CustFragmentRunner(ctx, fact, mid, fr.D, fr.k, key_bits=kb, cust_bits=cb,
-                                   gcap=min(len(fr.fact["fk"]) or 1, fr.cust_hi))
+                                   gcap=min(len(fr.fact["fk"]) or 1, fr.cust_hi), join_cap=join_cap)
         r.run()
         return r.result()
     finally:
@@ -113,6 +115,25 @@ def test_cust_small(hip, ctx, digit_bits, n, m, cust):
     fr = datagen.config2(seed=300 + n, n=n, m=m, cust_hi=cust)
     want = oracle.fragment_cust(fr.fact, fr.mid, fr.D, fr.k, gcap=min(n, cust))
     _assert_cust(_cust(hip, ctx, fr, digit_bits), want)
+    assert ctx.errors() == 0
+
+
+@pytest.mark.parametrize("digit_bits", [4, 8, 11])
+@pytest.mark.parametrize("shape", ["dup", "hot"])
+def test_cust_partial_mid(hip, ctx, digit_bits, shape):
+    """1.5M fact rows, so both key sorts leave 3 to 8 low bits to the join.
+    dup: every mid key on two rows (the join's in-LDS counting sort of a
+    window holding equal keys); hot: one key on 5000 mid rows (its windows
+    exceed the LDS table, so those tiles scan key buckets instead)."""
+    fr = datagen.config2(seed=77, n=1_500_000, m=400_000, cust_hi=50_000)
+    pk = fr.mid["pk"].copy()
+    if shape == "dup":
+        pk //= 2
+    else:
+        pk[::80] = 12345
+    fr = dataclasses.replace(fr, mid=dict(fr.mid, pk=pk))
+    want = oracle.fragment_cust(fr.fact, fr.mid, fr.D, fr.k, gcap=fr.cust_hi)
+    _assert_cust(_cust(hip, ctx, fr, digit_bits, join_cap=2 * len(fr.fact["fk"])), want)
     assert ctx.errors() == 0
 
 
