@@ -55,6 +55,26 @@ def algorithmic_bytes(plan, N, n_f, M, J, G):
     }
 
 
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary, or
+    None when the kernel's source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "radix_pass_pairs_v8_cfg2_hbm.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and not line.startswith(" "))
+    src = b"".join(open(os.path.join(ROOT, "paper_2203_01877_amd", "csrc", f), "rb").read()
+                   for f in ("radix.hpp", "dev.hpp"))
+    if fields.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    try:
+        return int(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def reference_model_bytes(N, n_f, M, J, G, P, Pm, Pg):
     """The sort-based method's reference pass structure (each pass reads its input and writes its
     output once; 8-bit digits), evaluated with the actual counts."""
@@ -189,7 +209,7 @@ def main():
             bytes_total = sum(24 * s for s in sizes) * args.steps
             achieved = bytes_total / (sum(durs) * 1e-3) / 1e9
             roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                         "kernel": "k_radix_pass<RadixCfg<%d,%s>, SrcPairs<u64>, u64>" % (args.digit_bits, {4: "256,8,8", 8: "512,8,8", 11: "512,8,8"}[args.digit_bits]),
                         "launches": len(durs), "avg_launch_ms": round(sum(durs) / len(durs), 4),
                         "bytes_per_launch": round(bytes_total / len(durs))}
