@@ -38,7 +38,6 @@ struct BatchFrag {
     const int8_t* flagA;
     const int8_t* flagB;
     int64_t* acc;              // [8][3]
-    uint64_t* jstatus;
     int64_t* d_join;
     int64_t* win;
     tqp_flags_out out;
@@ -223,8 +222,8 @@ k_batch_join(const BatchSeg* segs, const BatchFrag* frags, int nfrag, const int6
             e.flagB = fr.flagB;
             join_tile<Cfg, uint32_t, uint32_t, Emit>(L.bk[(L.npass - 1) & 1], L.bv[(L.npass - 1) & 1], nl,
                                                      R.bk[(R.npass - 1) & 1], (const uint32_t*)nullptr,
-                                                     fr.win[2 * tile], fr.win[2 * tile + 1], tile, ntiles, fr.jstatus,
-                                                     fr.d_join, INT64_MAX, e, esm, sm, flags);
+                                                     fr.win[2 * tile], fr.win[2 * tile + 1], tile, 0, fr.d_join, e,
+                                                     esm, sm);
             e.flush(esm, fr.acc);
         }
         __syncthreads();
@@ -368,7 +367,6 @@ void plan_candidate(tqp_batch* b, int c, char* base, size_t& off, size_t scratch
         bf.flagB = fr.flagB;
         bf.acc = (int64_t*)take(24 * 8);
         const int64_t jt = (fr.n_fact + BJCfg::TILE - 1) / BJCfg::TILE;
-        bf.jstatus = (uint64_t*)take((size_t)jt * 8);
         bf.d_join = (int64_t*)take(8);
         bf.win = (int64_t*)stake((size_t)(2 * jt + 2) * 8);
         bf.out = b->outs[f];

@@ -102,39 +102,6 @@ __global__ void k_bucket_bounds(const uint32_t* keys, int64_t n_upper, const int
     starts[b] = b == nbuckets ? n : lower_bound_glb(keys, 0, n, (uint32_t)(b << lowb));
 }
 
-__global__ void __launch_bounds__(JOIN_SCAN_BLOCK)
-k_join_scan(int64_t* tile_cnt, int64_t nl_upper, const int64_t* d_nl, int tile_size, int64_t* d_count,
-            int64_t cap, uint32_t* flags) {
-    constexpr int PER = 8;
-    __shared__ int64_t scratch[JOIN_SCAN_BLOCK / WAVE];
-    int64_t nl = nl_upper;
-    if (d_nl) { const int64_t t = *d_nl; nl = t < nl ? t : nl; }
-    const int64_t ntiles = (nl + tile_size - 1) / tile_size;
-    int64_t carry = 0;
-    for (int64_t c0 = 0; c0 < ntiles; c0 += (int64_t)JOIN_SCAN_BLOCK * PER) {
-        const int64_t b0 = c0 + (int64_t)threadIdx.x * PER;
-        int64_t v[PER];
-        int64_t local = 0;
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            v[j] = b0 + j < ntiles ? tile_cnt[b0 + j] : 0;
-            local += v[j];
-        }
-        int64_t total;
-        int64_t off = carry + block_excl_sum<JOIN_SCAN_BLOCK>(local, scratch, &total);
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            if (b0 + j < ntiles) tile_cnt[b0 + j] = off;
-            off += v[j];
-        }
-        carry += total;
-    }
-    if (threadIdx.x == 0) {
-        *d_count = carry;
-        if (carry > cap) set_flag(flags, FLAG_CAPACITY);
-    }
-}
-
 __global__ void k_avg(const int64_t* sa, const int64_t* cnt, double* avg, const int64_t* d_ngroups,
                       int64_t gcap) {
     int64_t G = *d_ngroups;

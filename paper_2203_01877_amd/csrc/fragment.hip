@@ -150,8 +150,6 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
     const int kb = norm_key_bits(f.key_bits);
     const int cb = norm_key_bits(f.cust_bits);
     tqp_status st;
-    if ((st = fill_zero(o.sum, o.gcap * 8, s, ctx)) != TQP_OK) return st;
-    if ((st = fill_zero(o.cnt, o.gcap * 8, s, ctx)) != TQP_OK) return st;
     // mid side, (pk, custkey), sorted on the side stream while the fact side
     // is sorted on s
     if ((st = side_fork(ctx, s)) != TQP_OK) return st;
@@ -183,7 +181,7 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
     }
     if ((st = join_launch<JCfgFrag, uint64_t, uint32_t, Emit, true>(
              ctx, s, "join_keyval", b.join, b.fkeys, b.fvals, f.n_fact, b.fact.d_cnt, b.mkeys, b.mvals, f.n_mid,
-             (const int64_t*)nullptr, b.d_join, f.join_cap, e, b.fact_lowb, b.fact_lowb)) != TQP_OK)
+             (const int64_t*)nullptr, b.d_join, f.join_cap, e, b.fact_lowb, b.fact_lowb, o.d_join)) != TQP_OK)
         return st;
     // group-by: sort (custkey, revenue) on the custkey bits above lowb (the
     // histogram came from the join), then aggregate each bucket
@@ -192,31 +190,29 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
                                           b.gvals, ctx, s)) != TQP_OK)
         return st;
     SegOut so{o.key, o.sum, o.cnt, nullptr, o.gcap, o.d_ngroups};
-    TQP_LAUNCH(ctx, s, "bucket_bounds",
-               k_bucket_bounds<<<grid_for(b.nbuckets + 1, 256, 0), 256, 0, s>>>(b.gkeys, f.join_cap, b.d_join,
-                                                                                  b.lowb, b.nbuckets, b.bstarts));
+    // bucket starts: with one group pass the buckets are its digits, so the
+    // pass's histogram gives them; otherwise one search per bucket
+    const uint32_t* bhist = b.grp.pd.npass == 1 ? b.grp.hist : nullptr;
+    if (!bhist) {
+        TQP_LAUNCH(ctx, s, "bucket_bounds",
+                   k_bucket_bounds<<<grid_for(b.nbuckets + 1, 256, 0), 256, 0, s>>>(b.gkeys, f.join_cap, b.d_join,
+                                                                                      b.lowb, b.nbuckets, b.bstarts));
+    }
     const int64_t* gv = reinterpret_cast<const int64_t*>(b.gvals);
     if (b.lowb <= BUCKET_SMALL_LOWB) {
         TQP_LAUNCH(ctx, s, "bucket_agg",
                    (k_bucket_agg<256, 1 << BUCKET_SMALL_LOWB><<<(unsigned)b.nbuckets, 256, 0, s>>>(
-                       b.gkeys, gv, b.bstarts, b.lowb, b.nbuckets, b.sstatus, b.scounter, so, ctx->d_err)));
+                       b.gkeys, gv, b.bstarts, bhist, b.lowb, b.nbuckets, b.sstatus, b.scounter, so, ctx->d_err)));
     } else {
         TQP_LAUNCH(ctx, s, "bucket_agg",
                    (k_bucket_agg<1024, 1 << BUCKET_LOWB_MAX><<<(unsigned)b.nbuckets, 1024, 0, s>>>(
-                       b.gkeys, gv, b.bstarts, b.lowb, b.nbuckets, b.sstatus, b.scounter, so, ctx->d_err)));
+                       b.gkeys, gv, b.bstarts, bhist, b.lowb, b.nbuckets, b.sstatus, b.scounter, so, ctx->d_err)));
     }
     // ORDER BY sum DESC, custkey ASC LIMIT k
     if ((st = topk_launch(b.topk, o.key, o.sum, o.cnt, o.d_ngroups, f.k, o.top_key, o.top_sum, o.top_cnt,
                           o.d_topk, s, ctx)) != TQP_OK)
         return st;
-    if (o.d_join) {
-        TQP_LAUNCH(ctx, s, "copy_count", k_copy_i64<<<1, 64, 0, s>>>(b.d_join, o.d_join));
-    }
     return TQP_OK;
-}
-
-__global__ void k_copy_i64(const int64_t* src, int64_t* dst) {
-    if (threadIdx.x == 0) *dst = *src;
 }
 
 tqp_status check_cust(const tqp_cust_fragment* f, const tqp_cust_out* o) {

@@ -12,14 +12,17 @@ namespace tqp {
 using JCfgFrag = JoinCfg<256, 8, 2048>;
 using SCfgFrag = SegCfg<256, 16>;
 
-// Join scratch: the R window of every left tile, the dynamic tile counter,
-// and the per-tile output counts / offsets of the two-kernel join.
+// Join scratch: the R window of every left tile, the dynamic tile counter
+// (aggregating emitters), the per-tile and per-block output counts of the
+// two-kernel join, and the queue of tiles left to the bucket-scan kernel.
 struct JoinBufs {
     int64_t tiles = 0;
     int64_t* win = nullptr;
-    int64_t* tile_off = nullptr;
+    int64_t* tile_cnt = nullptr;
+    int64_t* blk_total = nullptr;
     uint32_t* counter = nullptr;
-    uint32_t* scan_list = nullptr;     // tiles left to k_join_scan_tiles, and their count
+    uint32_t* scan_list = nullptr;
+    int64_t* scan_base = nullptr;
     uint32_t* scan_n = nullptr;
 };
 
@@ -27,24 +30,27 @@ template <class Cfg>
 JoinBufs join_reserve(Arena& a, int64_t nl_upper) {
     JoinBufs b;
     b.tiles = (nl_upper + Cfg::TILE - 1) / Cfg::TILE;
+    const int64_t t = b.tiles > 0 ? b.tiles : 1;
     b.counter = a.zero<uint32_t>(1);
     b.win = a.scratch<int64_t>(2 * b.tiles);
-    b.tile_off = a.scratch<int64_t>(b.tiles > 0 ? b.tiles : 1);
-    b.scan_list = a.scratch<uint32_t>(b.tiles > 0 ? b.tiles : 1);
+    b.tile_cnt = a.scratch<int64_t>(t);
+    b.blk_total = a.scratch<int64_t>(t);       // the grid never exceeds the tile count
+    b.scan_list = a.scratch<uint32_t>(t);
+    b.scan_base = a.scratch<int64_t>(t);
     b.scan_n = a.zero<uint32_t>(1);
     return b;
 }
 
 // Emitters that write at output positions run the two-kernel join (per-tile
-// counts, their scan, then the expansion at known bases); aggregating
-// emitters need only the join size and run the expansion directly.  Either
-// way *d_count ends up holding the join size; for the aggregating form it
-// must be zero on entry.
+// counts, then the expansion, each block over the same contiguous range of
+// tiles); aggregating emitters need only the join size and run the expansion
+// directly.  Either way *d_count ends up holding the join size; for the
+// aggregating form it must be zero on entry.
 template <class Cfg, class LP, class RP, class Emit, bool PARTIAL = false>
 tqp_status join_launch(tqp_ctx* ctx, hipStream_t s, const char* name, const JoinBufs& b, const uint32_t* lkey,
                        const LP* lpay, int64_t nl, const int64_t* d_nl, const uint32_t* rkey, const RP* rpay,
                        int64_t nr, const int64_t* d_nr, int64_t* d_count, int64_t cap, const Emit& e,
-                       int lowb = 0, int rlowb = 0) {
+                       int lowb = 0, int rlowb = 0, int64_t* d_count_out = nullptr) {
     const int64_t tiles = b.tiles;
     if (tiles > 0) {
         TQP_LAUNCH(ctx, s, "join_windows",
@@ -52,25 +58,19 @@ tqp_status join_launch(tqp_ctx* ctx, hipStream_t s, const char* name, const Join
                                                                             Cfg::TILE, b.win, lowb));
     }
     const int grid = grid_for(tiles, 1, (int64_t)ctx->num_cus * 4);
-    if (Emit::ORDERED) {
-        if (tiles > 0) {
-            TQP_LAUNCH(ctx, s, "join_count",
-                       k_join_count<Cfg><<<grid, Cfg::BLOCK, 0, s>>>(lkey, nl, d_nl, rkey, b.win, b.tile_off, lowb,
-                                                                     rlowb));
-        }
-        TQP_LAUNCH(ctx, s, "join_scan",
-                   k_join_scan<<<1, JOIN_SCAN_BLOCK, 0, s>>>(b.tile_off, nl, d_nl, Cfg::TILE, d_count, cap,
-                                                            ctx->d_err));
-        if (tiles == 0) return TQP_OK;
+    if (Emit::ORDERED && tiles > 0) {
+        TQP_LAUNCH(ctx, s, "join_count",
+                   k_join_count<Cfg><<<grid, Cfg::BLOCK, 0, s>>>(lkey, nl, d_nl, rkey, b.win, b.tile_cnt,
+                                                                 b.blk_total, lowb, rlowb));
     }
     TQP_LAUNCH(ctx, s, name,
                (k_join<Cfg, LP, RP, Emit, PARTIAL><<<grid, Cfg::BLOCK, 0, s>>>(
-                   lkey, lpay, nl, d_nl, rkey, rpay, b.win, nullptr, b.counter, Emit::ORDERED ? b.tile_off : nullptr,
-                   d_count, cap, e, ctx->d_err, lowb, rlowb, b.scan_list, b.scan_n)));
+                   lkey, lpay, nl, d_nl, rkey, rpay, b.win, b.counter, b.tile_cnt, b.blk_total, d_count,
+                   d_count_out, cap, e, ctx->d_err, lowb, rlowb, b.scan_list, b.scan_base, b.scan_n)));
     if constexpr (PARTIAL) {
         TQP_LAUNCH(ctx, s, "join_scan_tiles",
                    (k_join_scan_tiles<Cfg, LP, RP, Emit><<<ctx->num_cus, Cfg::BLOCK, 0, s>>>(
-                       lkey, lpay, nl, d_nl, rkey, rpay, b.win, b.tile_off, b.scan_list, b.scan_n, e, rlowb)));
+                       lkey, lpay, nl, d_nl, rkey, rpay, b.win, b.scan_list, b.scan_base, b.scan_n, e, rlowb)));
     }
     return TQP_OK;
 }
@@ -121,7 +121,6 @@ struct CustBufs {
     TopkBufs topk;
 };
 
-__global__ void k_copy_i64(const int64_t* src, int64_t* dst);
 tqp_status check_flags(const tqp_flags_fragment* f, const tqp_flags_out* o);
 
 // Batch preparation without any allocation: descriptor tables go into the

@@ -263,17 +263,17 @@ __device__ __forceinline__ int64_t join_tile_count(const uint32_t* lkey, int64_t
     return tot;
 }
 
-// tile_off (two-kernel join): the tile's output base, from the exclusive scan
-// of the counting kernel's tile totals; null: the base comes from a decoupled
-// look-back over status, and the last tile stores the join size.  Emitters
-// that do not use output positions add the tile total to *d_count instead.
+// base: the tile's output base (emitters that write at output positions;
+// the counting kernel's totals give it).  Emitters that only aggregate add
+// the tile's total to *d_count instead.  With PARTIAL, a tile whose window
+// does not fit the LDS table is queued (tile, base) for k_join_scan_tiles.
 template <class Cfg, class LP, class RP, class Emit, bool PARTIAL = false>
 __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, int64_t nl, const uint32_t* rkey,
-                                          const RP* rpay, int64_t wlo, int64_t whi, int64_t tile, int64_t ntiles,
-                                          uint64_t* status, int64_t* d_count, int64_t cap, Emit& e,
-                                          typename Emit::Smem& esm, JoinSmem<Cfg, RP>& sm, uint32_t* flags,
-                                          int lowb = 0, const int64_t* tile_off = nullptr, int rlowb = 0,
-                                          uint32_t* scan_list = nullptr, uint32_t* scan_n = nullptr) {
+                                          const RP* rpay, int64_t wlo, int64_t whi, int64_t tile, int64_t base,
+                                          int64_t* d_count, Emit& e, typename Emit::Smem& esm,
+                                          JoinSmem<Cfg, RP>& sm, int lowb = 0, int rlowb = 0,
+                                          uint32_t* scan_list = nullptr, int64_t* scan_base = nullptr,
+                                          uint32_t* scan_n = nullptr) {
     constexpr int TILE = Cfg::TILE, ITEMS = Cfg::ITEMS, RWIN = Cfg::RWIN, W = Cfg::WAVES;
     const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
     const int64_t t0 = tile * TILE;
@@ -286,7 +286,11 @@ __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, 
         // R sorted on its bits above rlowb only and a window beyond the LDS
         // table: the tile is queued for k_join_scan_tiles
         if (!direct && rlowb != 0) {
-            if (tid == 0) scan_list[atomicAdd(scan_n, 1u)] = (uint32_t)tile;
+            if (tid == 0) {
+                const uint32_t q = atomicAdd(scan_n, 1u);
+                scan_list[q] = (uint32_t)tile;
+                scan_base[q] = base;
+            }
             __syncthreads();
             return;
         }
@@ -366,30 +370,13 @@ __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, 
     }
     if (l == 0) sm.wave[w] = wave_total;
     __syncthreads();
-    // Tile output base: block scan of the wave totals + the tile's offset.
-    if (w == 0) {
+    // Wave bases: the tile's base plus the totals of the waves before.
+    if (!Emit::ORDERED && tid == 0) {
         int64_t tot = 0;
         for (int ww = 0; ww < W; ++ww) tot += sm.wave[ww];
-        if (!Emit::ORDERED) {
-            if (tid == 0) {
-                sm.base = 0;
-                if (tot) atomic_add(d_count, tot);
-            }
-        } else if (tile_off) {
-            if (tid == 0) sm.base = tile_off[tile];
-        } else {
-            const int64_t base = lookback64(status, tile, tot, flags);
-            if (tid == 0) {
-                sm.base = base;
-                if (tile == ntiles - 1) {
-                    *d_count = base + tot;
-                    if (base + tot > cap) set_flag(flags, FLAG_CAPACITY);
-                }
-            }
-        }
+        if (tot) atomic_add(d_count, tot);
     }
-    __syncthreads();
-    int64_t wbase = sm.base;
+    int64_t wbase = base;
     for (int ww = 0; ww < w; ++ww) wbase += sm.wave[ww];
     // Expansion: output o of element i pairs it with right element first + (o - offset(i)).
     auto right = [&](int64_t r) -> RP {        // r relative to the window
@@ -419,40 +406,49 @@ __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, 
     __syncthreads();
 }
 
-// Per-tile output counts (first kernel of the two-kernel join), tiles in a
-// grid-stride loop.
+// Tiles [t0, t1) of block b when ntiles tiles are split into contiguous
+// ranges over the grid (the counting and expanding kernels split alike).
+__device__ __forceinline__ void join_block_range(int64_t ntiles, int64_t& t0, int64_t& t1) {
+    const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+    t0 = (int64_t)blockIdx.x * per;
+    t1 = t0 + per < ntiles ? t0 + per : ntiles;
+    if (t0 > t1) t0 = t1;
+}
+
+// Per-tile output counts (first kernel of the two-kernel join): tile_cnt of
+// every tile and blk_total of every block's contiguous range of tiles.
 template <class Cfg>
 __global__ void __launch_bounds__(Cfg::BLOCK)
 k_join_count(const uint32_t* lkey, int64_t nl_upper, const int64_t* d_nl, const uint32_t* rkey,
-             const int64_t* win, int64_t* tile_cnt, int lowb, int rlowb) {
+             const int64_t* win, int64_t* tile_cnt, int64_t* blk_total, int lowb, int rlowb) {
     __shared__ JoinSmem<Cfg, uint8_t> sm;
     int64_t nl = nl_upper;
     if (d_nl) { const int64_t t = *d_nl; nl = t < nl ? t : nl; }
     const int64_t ntiles = (nl + Cfg::TILE - 1) / Cfg::TILE;
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    int64_t t0, t1, sum = 0;
+    join_block_range(ntiles, t0, t1);
+    for (int64_t tile = t0; tile < t1; ++tile) {
         const int64_t t = join_tile_count<Cfg, uint8_t>(lkey, nl, rkey, win[2 * tile], win[2 * tile + 1], tile, sm,
                                                         lowb, rlowb);
         if (threadIdx.x == 0) tile_cnt[tile] = t;
+        sum += t;
     }
+    if (threadIdx.x == 0) blk_total[blockIdx.x] = sum;
 }
 
-// Exclusive scan of the per-tile counts, in place, by one block of
-// JOIN_SCAN_BLOCK threads; *d_count = the join size.
-constexpr int JOIN_SCAN_BLOCK = 1024;
-__global__ void k_join_scan(int64_t* tile_cnt, int64_t nl_upper, const int64_t* d_nl, int tile_size,
-                            int64_t* d_count, int64_t cap, uint32_t* flags);
-
-// The join.  With tile_off (two-kernel join) tiles go in a grid-stride loop
-// and bases come from tile_off; otherwise tiles are pulled from a counter and
-// bases come from the look-back (or are unused, for emitters that only
-// aggregate).  The kernel is persistent, so emitters can accumulate across
-// tiles and flush once.
+// The join.  Emitters that write at output positions: each block expands its
+// contiguous range of tiles, the first at the sum of the earlier blocks'
+// totals and each next one after the previous tile's count; the last block
+// stores the join size (also to d_count_out, if not null).  Aggregating
+// emitters: tiles are pulled from a
+// counter.  The kernel is persistent, so emitters can accumulate across tiles
+// and flush once.
 template <class Cfg, class LP, class RP, class Emit, bool PARTIAL = false>
 __global__ void __launch_bounds__(Cfg::BLOCK)
 k_join(const uint32_t* lkey, const LP* lpay, int64_t nl_upper, const int64_t* d_nl,
-       const uint32_t* rkey, const RP* rpay, const int64_t* win, uint64_t* status, uint32_t* tile_counter,
-       const int64_t* tile_off, int64_t* d_count, int64_t cap, Emit emit, uint32_t* flags, int lowb,
-       int rlowb, uint32_t* scan_list, uint32_t* scan_n) {
+       const uint32_t* rkey, const RP* rpay, const int64_t* win, uint32_t* tile_counter, const int64_t* tile_cnt,
+       const int64_t* blk_total, int64_t* d_count, int64_t* d_count_out, int64_t cap, Emit emit, uint32_t* flags,
+       int lowb, int rlowb, uint32_t* scan_list, int64_t* scan_base, uint32_t* scan_n) {
     __shared__ JoinSmem<Cfg, RP> sm;
     __shared__ typename Emit::Smem esm;
     int64_t nl = nl_upper;
@@ -460,12 +456,29 @@ k_join(const uint32_t* lkey, const LP* lpay, int64_t nl_upper, const int64_t* d_
     const int64_t ntiles = (nl + Cfg::TILE - 1) / Cfg::TILE;
     Emit e = emit;
     e.init(esm);
-    if (Emit::ORDERED && !tile_off && ntiles == 0 && blockIdx.x == 0 && threadIdx.x == 0) *d_count = 0;
-    if (tile_off) {
-        for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x)
+    if constexpr (Emit::ORDERED) {
+        if (threadIdx.x < WAVE) {
+            int64_t acc = 0;
+            for (int64_t b = threadIdx.x; b < blockIdx.x; b += WAVE) acc += blk_total[b];
+            acc = wave_sum(acc);
+            if (threadIdx.x == 0) sm.base = acc;
+        }
+        __syncthreads();
+        int64_t run = sm.base;
+        int64_t t0, t1;
+        join_block_range(ntiles, t0, t1);
+        for (int64_t tile = t0; tile < t1; ++tile) {
+            const int64_t base = run;
+            run += tile_cnt[tile];
             join_tile<Cfg, LP, RP, Emit, PARTIAL>(lkey, lpay, nl, rkey, rpay, win[2 * tile], win[2 * tile + 1], tile,
-                                                  ntiles, status, d_count, cap, e, esm, sm, flags, lowb, tile_off,
-                                                  rlowb, scan_list, scan_n);
+                                                  base, d_count, e, esm, sm, lowb, rlowb, scan_list, scan_base,
+                                                  scan_n);
+        }
+        if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+            *d_count = run;
+            if (d_count_out) *d_count_out = run;
+            if (run > cap) set_flag(flags, FLAG_CAPACITY);
+        }
     } else {
         for (;;) {
             if (threadIdx.x == 0) sm.tile = atomicAdd(tile_counter, 1u);
@@ -473,8 +486,7 @@ k_join(const uint32_t* lkey, const LP* lpay, int64_t nl_upper, const int64_t* d_
             const int64_t tile = sm.tile;
             if (tile >= ntiles) break;
             join_tile<Cfg, LP, RP, Emit, PARTIAL>(lkey, lpay, nl, rkey, rpay, win[2 * tile], win[2 * tile + 1], tile,
-                                                  ntiles, status, d_count, cap, e, esm, sm, flags, lowb, nullptr,
-                                                  rlowb, scan_list, scan_n);
+                                                  0, d_count, e, esm, sm, lowb, rlowb);
         }
     }
     e.finish(esm);
@@ -484,12 +496,12 @@ k_join(const uint32_t* lkey, const LP* lpay, int64_t nl_upper, const int64_t* d_
 // beyond the LDS table), with the same element-to-wave layout: an element's
 // matches are the rows of its key bucket that hold its key, found by scanning
 // the bucket, in bucket order (for the counts, then again for the outputs).
-// The tile's output base comes from tile_off.
+// The tile's output base was queued with it.
 template <class Cfg, class LP, class RP, class Emit>
 __global__ void __launch_bounds__(Cfg::BLOCK)
 k_join_scan_tiles(const uint32_t* lkey, const LP* lpay, int64_t nl_upper, const int64_t* d_nl,
-                  const uint32_t* rkey, const RP* rpay, const int64_t* win, const int64_t* tile_off,
-                  const uint32_t* scan_list, const uint32_t* scan_n, Emit emit, int rlowb) {
+                  const uint32_t* rkey, const RP* rpay, const int64_t* win, const uint32_t* scan_list,
+                  const int64_t* scan_base, const uint32_t* scan_n, Emit emit, int rlowb) {
     __shared__ int64_t s_wave[Cfg::WAVES];
     __shared__ typename Emit::Smem esm;
     const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
@@ -517,7 +529,7 @@ k_join_scan_tiles(const uint32_t* lkey, const LP* lpay, int64_t nl_upper, const 
         }
         if (l == 0) s_wave[w] = total;
         __syncthreads();
-        int64_t wbase = tile_off[tile];
+        int64_t wbase = scan_base[q];
         for (int ww = 0; ww < w; ++ww) wbase += s_wave[ww];
         for (int j = 0; j < Cfg::ITEMS; ++j) {
             const int64_t i = chunk + j * WAVE + l;

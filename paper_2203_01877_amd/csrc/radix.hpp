@@ -116,11 +116,14 @@ struct SrcFilterRevenue {
         kk = (uint32_t)key[i];
         return cmp_eval((int64_t)date[i], op, k);
     }
+    // price and disc are read with the key and date, whatever the predicate
+    // says, so a row costs one memory round trip instead of two (the rows the
+    // filter drops cost their 16 bytes).
     __device__ bool load(int64_t i, uint32_t& kk, uint64_t& v) const {
         kk = (uint32_t)key[i];
-        bool ok = cmp_eval((int64_t)date[i], op, k);
-        if (ok) v = (uint64_t)(price[i] * (100 - disc[i]));
-        return ok;
+        const int64_t p = price[i], d = disc[i];
+        v = (uint64_t)(p * (100 - d));
+        return cmp_eval((int64_t)date[i], op, k);
     }
 };
 

@@ -191,7 +191,7 @@ __global__ void k_bucket_bounds(const uint32_t* keys, int64_t n_upper, const int
 
 template <int BLOCK, int SLOTS>
 __global__ void __launch_bounds__(BLOCK)
-k_bucket_agg(const uint32_t* keys, const int64_t* vals, const int64_t* starts, int lowb,
+k_bucket_agg(const uint32_t* keys, const int64_t* vals, const int64_t* starts, const uint32_t* bhist, int lowb,
              int64_t nbuckets, uint64_t* status, uint32_t* counter, SegOut out, uint32_t* flags) {
     static_assert(SLOTS <= (1 << BUCKET_LOWB_MAX), "slot table larger than the LDS budget");
     constexpr int U = 8;                               // loads in flight per thread
@@ -207,7 +207,24 @@ k_bucket_agg(const uint32_t* keys, const int64_t* vals, const int64_t* starts, i
     __syncthreads();
     const int64_t b = s_b;
     if (b >= nbuckets) return;
-    const int64_t lo = starts[b], hi = starts[b + 1];
+    int64_t lo, hi;
+    if (bhist) {
+        // bucket b = digit b of the single sort pass: it starts after the
+        // elements of the smaller digits
+        if (w == 0) {
+            int64_t acc = 0;
+            for (int64_t d = l; d < b; d += WAVE) acc += bhist[d];
+            acc = wave_sum(acc);
+            if (l == 0) s_base = acc;
+        }
+        __syncthreads();
+        lo = s_base;
+        hi = lo + bhist[b];
+        __syncthreads();
+    } else {
+        lo = starts[b];
+        hi = starts[b + 1];
+    }
     const uint32_t lmask = (uint32_t)slots - 1;
     for (int64_t i0 = lo + tid; i0 < hi; i0 += (int64_t)BLOCK * U) {
         uint32_t k[U];

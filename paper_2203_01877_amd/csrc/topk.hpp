@@ -2,9 +2,9 @@
 // applied to the aggregated groups).
 //
 // 1. Threshold.  One block finds, by radix select, the exact k-th largest sum
-//    T of an evenly strided sample of the groups.  The sample holds k groups
-//    whose sum is at least T, so no group with a smaller sum can be among the
-//    overall first k.
+//    T of a sample of the groups (runs spread evenly over them).  The sample
+//    holds k groups whose sum is at least T, so no group with a smaller sum
+//    can be among the overall first k.
 // 2. Filter.  One streaming pass keeps the groups with sum >= T.
 // 3. Chunk levels (only when many groups survive).  Each level sorts chunks
 //    of CH candidates in LDS with a bitonic network and keeps the first k of
@@ -87,9 +87,11 @@ template <int BLOCK, int PER, bool LO>
 struct BlockSelect {
     uint32_t h[256];
     uint64_t wmax[BLOCK / WAVE], wmin[BLOCK / WAVE];
+    uint32_t wlo[BLOCK / WAVE];
     uint64_t prefix_hi;
     uint32_t prefix_lo;
     uint32_t need;
+    uint32_t whole;            // the chosen byte's candidates are all selected
 };
 
 template <int BLOCK, int PER, bool LO>
@@ -120,6 +122,7 @@ __device__ __forceinline__ void block_select(BlockSelect<BLOCK, PER, LO>& sm, co
         sm.prefix_hi = same == 8 ? M : (same == 0 ? 0 : M & (~uint64_t(0) << (64 - 8 * same)));
         sm.prefix_lo = 0;
         sm.need = (uint32_t)need;
+        sm.whole = 0;
         sm.wmax[0] = (uint64_t)same;
     }
     __syncthreads();
@@ -167,9 +170,50 @@ __device__ __forceinline__ void block_select(BlockSelect<BLOCK, PER, LO>& sm, co
                 if (in_hi) sm.prefix_hi |= (uint64_t)byte << sh;
                 else sm.prefix_lo |= byte << sh;
                 sm.need = nd - acc;
+                sm.whole = c[q] == nd - acc;
             }
         }
         __syncthreads();
+        if (sm.whole) {
+            // every candidate under the chosen prefix is selected: the
+            // need-th largest is the smallest of them
+            const int shn = sh;
+            const uint64_t mhi2 = in_hi ? (shn >= 64 ? 0 : ~uint64_t(0) << shn) : ~uint64_t(0);
+            const uint32_t mlo2 = in_hi ? 0u : (shn >= 32 ? 0u : ~0u << shn);
+            const uint64_t phi2 = sm.prefix_hi & mhi2;
+            const uint32_t plo2 = sm.prefix_lo & mlo2;
+            uint64_t bh = ~uint64_t(0);
+#pragma unroll
+            for (int j = 0; j < PER; ++j)
+                if (valid[j] && (hi[j] & mhi2) == phi2 && (lo[j] & mlo2) == plo2 && hi[j] < bh) bh = hi[j];
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) {
+                const uint64_t o = __shfl_xor(bh, d, WAVE);
+                bh = o < bh ? o : bh;
+            }
+            if (l == 0) sm.wmin[w] = bh;
+            __syncthreads();
+            uint64_t mh = ~uint64_t(0);
+            for (int ww = 0; ww < BLOCK / WAVE; ++ww) mh = sm.wmin[ww] < mh ? sm.wmin[ww] : mh;
+            uint32_t bl = ~0u;
+            if (LO) {
+#pragma unroll
+                for (int j = 0; j < PER; ++j)
+                    if (valid[j] && hi[j] == mh && (lo[j] & mlo2) == plo2 && lo[j] < bl) bl = lo[j];
+#pragma unroll
+                for (int d = 32; d >= 1; d >>= 1) {
+                    const uint32_t o = __shfl_xor(bl, d, WAVE);
+                    bl = o < bl ? o : bl;
+                }
+                if (l == 0) sm.wlo[w] = bl;
+                __syncthreads();
+                for (int ww = 0; ww < BLOCK / WAVE; ++ww) bl = sm.wlo[ww] < bl ? sm.wlo[ww] : bl;
+            }
+            t_hi = mh;
+            t_lo = LO ? bl : 0;
+            __syncthreads();
+            return;
+        }
     }
     t_hi = sm.prefix_hi;
     t_lo = sm.prefix_lo;
@@ -191,6 +235,9 @@ k_topk_thresh(const int64_t* gsum, int64_t n_upper, const int64_t* d_n, int k, i
         if (threadIdx.x == 0) thr[0] = INT64_MIN;
         return;
     }
+    // PER runs of BLOCK consecutive groups, spread evenly over the groups
+    // (one run per load round, so every load of the block is contiguous)
+    const int64_t run = n > m ? n / PER : BLOCK;   // >= BLOCK when n > m
     uint64_t hi[PER];
     uint32_t lo[PER];
     bool valid[PER];
@@ -198,7 +245,7 @@ k_topk_thresh(const int64_t* gsum, int64_t n_upper, const int64_t* d_n, int k, i
     for (int j = 0; j < PER; ++j) {
         const int64_t i = (int64_t)j * BLOCK + threadIdx.x;
         valid[j] = i < m;
-        hi[j] = valid[j] ? order_hi(gsum[i * n / m]) : 0;
+        hi[j] = valid[j] ? order_hi(gsum[(int64_t)j * run + threadIdx.x]) : 0;
         lo[j] = 0;
     }
     uint64_t t_hi;
