@@ -102,6 +102,8 @@ def main():
     ap.add_argument("--with-copy", action="store_true",
                     help="after the steps, run a plain 1 GiB device copy (calibrates HBM counters)")
     ap.add_argument("--rows", type=int, default=0, help="fact rows (0: the full 60M workload)")
+    ap.add_argument("--date-lt", type=int, default=None,
+                    help="config 2 with another filter constant D (date < D; the workload uses 2400)")
     ap.add_argument("--config", type=int, default=2, choices=[2, 3, 4],
                     help="2: the 60M-row custkey fragment (default); 3: 256 flags fragments, batched vs plain; "
                          "4: served mix under Poisson arrivals, concurrent vs serial")
@@ -137,6 +139,8 @@ def main():
         fr = datagen.config2(n=args.rows, m=m, cust_hi=max(1, args.rows // 40))
     else:
         fr = datagen.config2()
+    if args.date_lt is not None:
+        fr.D = args.date_lt
     N, M = len(fr.fact["fk"]), len(fr.mid["pk"])
     n_f = int(np.count_nonzero(fr.fact["date"] < fr.D))
     log("generated %d fact rows, %d mid rows in %.1fs" % (N, M, time.time() - t0))
@@ -227,8 +231,8 @@ def main():
         "metric": METRIC, "value": round(value, 1), "unit": "fact rows/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "int64", "data": "synthetic",
-        "config": {"workload": "60M-row fact x 15M-row mid: date<2400, fk=pk, group by custkey, sum+count, "
-                               "top-100 by sum desc" if not args.rows else "scaled custkey fragment",
+        "config": {"workload": ("60M-row fact x 15M-row mid: date<%d, fk=pk, group by custkey, sum+count, "
+                                "top-100 by sum desc" % fr.D) if not args.rows else "scaled custkey fragment",
                    "fact_rows": N, "mid_rows": M, "filtered_fact_rows": n_f, "join_rows": J, "groups": G,
                    "digit_bits": args.digit_bits, "key_bits": key_bits, "cust_bits": cust_bits,
                    "plan": run.plan()},

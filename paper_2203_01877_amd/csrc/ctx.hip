@@ -4,6 +4,7 @@
 
 #include "host.hpp"
 #include "join.hpp"
+#include "radix.hpp"
 #include "segreduce.hpp"
 #include "topk.hpp"
 
@@ -100,6 +101,52 @@ __global__ void k_bucket_bounds(const uint32_t* keys, int64_t n_upper, const int
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b > nbuckets) return;
     starts[b] = b == nbuckets ? n : lower_bound_glb(keys, 0, n, (uint32_t)(b << lowb));
+}
+
+__global__ void __launch_bounds__(FINISH_BLOCK)
+k_finish_sort(const uint32_t* kin, const uint32_t* vin, const int64_t* starts, uint32_t* kout, uint32_t* vout) {
+    constexpr int U = 8;      // loads in flight per thread
+    __shared__ uint32_t cnt[FINISH_SPAN];
+    __shared__ uint32_t scratch[FINISH_BLOCK / WAVE];
+    const int tid = threadIdx.x;
+    const int64_t lo = starts[blockIdx.x], hi = starts[blockIdx.x + 1];
+    if (lo >= hi) return;
+    const uint32_t base = (uint32_t)blockIdx.x << FINISH_LOG2;
+    for (int i = tid; i < FINISH_SPAN; i += FINISH_BLOCK) cnt[i] = 0;
+    __syncthreads();
+    // keys outside the span occur only in inputs that are not sorted on the
+    // high bits (a broken key width): skipped, never indexed
+    for (int64_t i0 = lo + tid; i0 < hi; i0 += (int64_t)FINISH_BLOCK * U) {
+        uint32_t d[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int64_t i = i0 + (int64_t)j * FINISH_BLOCK;
+            d[j] = i < hi ? kin[i] - base : FINISH_SPAN;
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            if (d[j] < FINISH_SPAN) atomicAdd(&cnt[d[j]], 1u);
+    }
+    __syncthreads();
+    block_excl_scan_array<FINISH_BLOCK>(cnt, FINISH_SPAN, scratch);
+    for (int64_t i0 = lo + tid; i0 < hi; i0 += (int64_t)FINISH_BLOCK * U) {
+        uint32_t k[U], v[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int64_t i = i0 + (int64_t)j * FINISH_BLOCK;
+            k[j] = base + FINISH_SPAN;
+            if (i < hi) { k[j] = kin[i]; v[j] = vin[i]; }
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint32_t d = k[j] - base;
+            if (d < FINISH_SPAN) {
+                const int64_t p = lo + atomicAdd(&cnt[d], 1u);
+                kout[p] = k[j];
+                vout[p] = v[j];
+            }
+        }
+    }
 }
 
 __global__ void k_avg(const int64_t* sa, const int64_t* cnt, double* avg, const int64_t* d_ngroups,

@@ -119,10 +119,18 @@ void cust_reserve(Arena& a, const tqp_cust_fragment& f, const tqp_cust_out& o, C
     // when a join tile still spans a small key range: then the low digits are
     // never sorted.
     b.fact_lowb = fact_low_bits(f.n_fact, kb, Cfg::RADIX_BITS);
+    if (b.fact_lowb > FINISH_LOG2) b.fact_lowb = FINISH_LOG2;      // the mid finishing pass covers at most this
     b.fact = radix_reserve<Cfg, uint64_t>(a, f.n_fact, kb, b.fact_lowb);
-    // the mid keys need the same high bits only: each join tile counting-sorts
-    // its window of them in LDS
+    // the mid keys: radix passes over the same high bits, then one finishing
+    // pass sorts each span of 8192 keys in LDS (the join's binary-search
+    // fallback needs them fully sorted)
     b.mid = radix_reserve<Cfg, uint32_t>(a, f.n_mid, kb, b.fact_lowb);
+    if (b.fact_lowb > 0) {
+        b.mkeys_full = a.scratch<uint32_t>(f.n_mid);
+        b.mvals_full = a.scratch<uint32_t>(f.n_mid);
+        b.nspans = ((int64_t(1) << kb) + FINISH_SPAN - 1) >> FINISH_LOG2;
+        b.mspans = a.scratch<int64_t>(b.nspans + 1);
+    }
     b.join = join_reserve<JCfgFrag>(a, f.n_fact);
     b.d_join = a.zero<int64_t>(1);
     // group-by: radix passes over the custkey bits above lowb, then one
@@ -157,6 +165,20 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
     if ((st = radix_launch<Cfg, uint32_t>(b.mid, msrc, f.n_mid, true, nullptr, key_mask_for(kb), b.mkeys,
                                           b.mvals, ctx, ctx->side)) != TQP_OK)
         return st;
+    const uint32_t* mk = b.mkeys;
+    const uint32_t* mv = b.mvals;
+    if (b.fact_lowb > 0 && f.n_mid > 0) {
+        // the join's fallback searches need the mid keys fully sorted: finish
+        // the low bits span by span
+        TQP_LAUNCH(ctx, ctx->side, "finish_bounds",
+                   k_bucket_bounds<<<grid_for(b.nspans + 1, 256, 0), 256, 0, ctx->side>>>(
+                       b.mkeys, f.n_mid, nullptr, FINISH_LOG2, b.nspans, b.mspans));
+        TQP_LAUNCH(ctx, ctx->side, "finish_sort",
+                   k_finish_sort<<<(unsigned)b.nspans, FINISH_BLOCK, 0, ctx->side>>>(b.mkeys, b.mvals, b.mspans,
+                                                                                    b.mkeys_full, b.mvals_full));
+        mk = b.mkeys_full;
+        mv = b.mvals_full;
+    }
     // fact side: date < D fused into the sort; the payload is the revenue
     // price * (100 - disc), evaluated while the row is read
     SrcFilterRevenue fsrc{f.fk, f.date, f.price, f.disc, CMP_LT, f.D, f.n_fact};
@@ -179,9 +201,9 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
         e.shift[p] = b.grp.pd.shift[p];
         e.bits[p] = b.grp.pd.bits[p];
     }
-    if ((st = join_launch<JCfgFrag, uint64_t, uint32_t, Emit, true>(
-             ctx, s, "join_keyval", b.join, b.fkeys, b.fvals, f.n_fact, b.fact.d_cnt, b.mkeys, b.mvals, f.n_mid,
-             (const int64_t*)nullptr, b.d_join, f.join_cap, e, b.fact_lowb, b.fact_lowb, o.d_join)) != TQP_OK)
+    if ((st = join_launch<JCfgFrag, uint64_t, uint32_t>(ctx, s, "join_keyval", b.join, b.fkeys, b.fvals, f.n_fact,
+                                                        b.fact.d_cnt, mk, mv, f.n_mid, (const int64_t*)nullptr,
+                                                        b.d_join, f.join_cap, e, b.fact_lowb, o.d_join)) != TQP_OK)
         return st;
     // group-by: sort (custkey, revenue) on the custkey bits above lowb (the
     // histogram came from the join), then aggregate each bucket

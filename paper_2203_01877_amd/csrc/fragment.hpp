@@ -13,17 +13,14 @@ using JCfgFrag = JoinCfg<256, 8, 2048>;
 using SCfgFrag = SegCfg<256, 16>;
 
 // Join scratch: the R window of every left tile, the dynamic tile counter
-// (aggregating emitters), the per-tile and per-block output counts of the
-// two-kernel join, and the queue of tiles left to the bucket-scan kernel.
+// (aggregating emitters), and the per-tile and per-block output counts of
+// the two-kernel join.
 struct JoinBufs {
     int64_t tiles = 0;
     int64_t* win = nullptr;
     int64_t* tile_cnt = nullptr;
     int64_t* blk_total = nullptr;
     uint32_t* counter = nullptr;
-    uint32_t* scan_list = nullptr;
-    int64_t* scan_base = nullptr;
-    uint32_t* scan_n = nullptr;
 };
 
 template <class Cfg>
@@ -35,9 +32,6 @@ JoinBufs join_reserve(Arena& a, int64_t nl_upper) {
     b.win = a.scratch<int64_t>(2 * b.tiles);
     b.tile_cnt = a.scratch<int64_t>(t);
     b.blk_total = a.scratch<int64_t>(t);       // the grid never exceeds the tile count
-    b.scan_list = a.scratch<uint32_t>(t);
-    b.scan_base = a.scratch<int64_t>(t);
-    b.scan_n = a.zero<uint32_t>(1);
     return b;
 }
 
@@ -46,11 +40,11 @@ JoinBufs join_reserve(Arena& a, int64_t nl_upper) {
 // tiles); aggregating emitters need only the join size and run the expansion
 // directly.  Either way *d_count ends up holding the join size; for the
 // aggregating form it must be zero on entry.
-template <class Cfg, class LP, class RP, class Emit, bool PARTIAL = false>
+template <class Cfg, class LP, class RP, class Emit>
 tqp_status join_launch(tqp_ctx* ctx, hipStream_t s, const char* name, const JoinBufs& b, const uint32_t* lkey,
                        const LP* lpay, int64_t nl, const int64_t* d_nl, const uint32_t* rkey, const RP* rpay,
                        int64_t nr, const int64_t* d_nr, int64_t* d_count, int64_t cap, const Emit& e,
-                       int lowb = 0, int rlowb = 0, int64_t* d_count_out = nullptr) {
+                       int lowb = 0, int64_t* d_count_out = nullptr) {
     const int64_t tiles = b.tiles;
     if (tiles > 0) {
         TQP_LAUNCH(ctx, s, "join_windows",
@@ -61,17 +55,12 @@ tqp_status join_launch(tqp_ctx* ctx, hipStream_t s, const char* name, const Join
     if (Emit::ORDERED && tiles > 0) {
         TQP_LAUNCH(ctx, s, "join_count",
                    k_join_count<Cfg><<<grid, Cfg::BLOCK, 0, s>>>(lkey, nl, d_nl, rkey, b.win, b.tile_cnt,
-                                                                 b.blk_total, lowb, rlowb));
+                                                                 b.blk_total, lowb));
     }
     TQP_LAUNCH(ctx, s, name,
-               (k_join<Cfg, LP, RP, Emit, PARTIAL><<<grid, Cfg::BLOCK, 0, s>>>(
+               (k_join<Cfg, LP, RP, Emit><<<grid, Cfg::BLOCK, 0, s>>>(
                    lkey, lpay, nl, d_nl, rkey, rpay, b.win, b.counter, b.tile_cnt, b.blk_total, d_count,
-                   d_count_out, cap, e, ctx->d_err, lowb, rlowb, b.scan_list, b.scan_base, b.scan_n)));
-    if constexpr (PARTIAL) {
-        TQP_LAUNCH(ctx, s, "join_scan_tiles",
-                   (k_join_scan_tiles<Cfg, LP, RP, Emit><<<ctx->num_cus, Cfg::BLOCK, 0, s>>>(
-                       lkey, lpay, nl, d_nl, rkey, rpay, b.win, b.scan_list, b.scan_base, b.scan_n, e, rlowb)));
-    }
+                   d_count_out, cap, e, ctx->d_err, lowb)));
     return TQP_OK;
 }
 
@@ -117,6 +106,9 @@ struct CustBufs {
     uint64_t* sstatus = nullptr;
     uint32_t* scounter = nullptr;
     uint32_t *fkeys = nullptr, *mkeys = nullptr, *mvals = nullptr, *gkeys_in = nullptr, *gkeys = nullptr;
+    uint32_t *mkeys_full = nullptr, *mvals_full = nullptr;   // mid after the finishing pass (fact_lowb > 0)
+    int64_t* mspans = nullptr;                                // start of every finishing span, spans + 1
+    int64_t nspans = 0;
     uint64_t *fvals = nullptr, *gvals_in = nullptr, *gvals = nullptr;
     TopkBufs topk;
 };

@@ -169,7 +169,6 @@ struct JoinSmem {
     int32_t cnt[Cfg::RWIN];
     RP rpay[Cfg::RWIN];
     int64_t wave[Cfg::WAVES];
-    int32_t scan[Cfg::WAVES];
     int64_t base;
     uint32_t tile;
     int32_t seg;
@@ -197,22 +196,13 @@ __device__ __forceinline__ void tile_key_range(const uint32_t* lkey, int64_t fir
     kmax = ((lkey[last] >> lowb) << lowb) | ((1u << lowb) - 1);
 }
 
-// Rows of R in the bucket of key (the keys that agree with it above rlowb)
-// when R is sorted on its bits above rlowb only: [r, rend).
-__device__ __forceinline__ void right_bucket(const uint32_t* rkey, int64_t wlo, int64_t whi, uint32_t key,
-                                             int rlowb, int64_t& r, int64_t& rend) {
-    const uint32_t lm = (1u << rlowb) - 1;
-    r = lower_bound_glb(rkey, wlo, whi, key & ~lm);
-    rend = upper_bound_glb(rkey, r, whi, key | lm);
-}
-
 // Output rows of one left tile, for the counting kernel of the two-kernel
 // join: the same direct table (counts only) or global searches as join_tile,
 // with no payload traffic.  The value is returned to every thread.
 template <class Cfg, class RP>
 __device__ __forceinline__ int64_t join_tile_count(const uint32_t* lkey, int64_t nl, const uint32_t* rkey,
                                                    int64_t wlo, int64_t whi, int64_t tile, JoinSmem<Cfg, RP>& sm,
-                                                   int lowb, int rlowb) {
+                                                   int lowb) {
     constexpr int TILE = Cfg::TILE, ITEMS = Cfg::ITEMS, RWIN = Cfg::RWIN, W = Cfg::WAVES;
     const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
     const int64_t t0 = tile * TILE;
@@ -234,7 +224,14 @@ __device__ __forceinline__ int64_t join_tile_count(const uint32_t* lkey, int64_t
     }
     __syncthreads();
     if (direct) {
-        for (int i = tid; i < wn; i += Cfg::BLOCK) atomicAdd(&sm.cnt[(int)(rkey[wlo + i] - kmin)], 1);
+        // keys outside [kmin, kmax] occur only in inputs that break the
+        // declared key width (already flagged): they are skipped, never
+        // indexed
+        const uint32_t range = kmax - kmin + 1;
+        for (int i = tid; i < wn; i += Cfg::BLOCK) {
+            const uint32_t v = rkey[wlo + i] - kmin;
+            if (v < range) atomicAdd(&sm.cnt[v], 1);
+        }
         __syncthreads();
     }
     int64_t c = 0;
@@ -243,14 +240,11 @@ __device__ __forceinline__ int64_t join_tile_count(const uint32_t* lkey, int64_t
         const int64_t i = chunk + j * WAVE + l;
         if (i < nl) {
             if (direct) {
-                c += sm.cnt[(int)(key[j] - kmin)];
-            } else if (rlowb == 0) {
+                const uint32_t v = key[j] - kmin;
+                if (v <= kmax - kmin) c += sm.cnt[v];
+            } else {
                 const int64_t lb = lower_bound_glb(rkey, wlo, whi, key[j]);
                 c += upper_bound_glb(rkey, lb, whi, key[j]) - lb;
-            } else {
-                int64_t r, rend;
-                right_bucket(rkey, wlo, whi, key[j], rlowb, r, rend);
-                for (; r < rend; ++r) c += rkey[r] == key[j];
             }
         }
     }
@@ -265,15 +259,12 @@ __device__ __forceinline__ int64_t join_tile_count(const uint32_t* lkey, int64_t
 
 // base: the tile's output base (emitters that write at output positions;
 // the counting kernel's totals give it).  Emitters that only aggregate add
-// the tile's total to *d_count instead.  With PARTIAL, a tile whose window
-// does not fit the LDS table is queued (tile, base) for k_join_scan_tiles.
-template <class Cfg, class LP, class RP, class Emit, bool PARTIAL = false>
+// the tile's total to *d_count instead.
+template <class Cfg, class LP, class RP, class Emit>
 __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, int64_t nl, const uint32_t* rkey,
                                           const RP* rpay, int64_t wlo, int64_t whi, int64_t tile, int64_t base,
                                           int64_t* d_count, Emit& e, typename Emit::Smem& esm,
-                                          JoinSmem<Cfg, RP>& sm, int lowb = 0, int rlowb = 0,
-                                          uint32_t* scan_list = nullptr, int64_t* scan_base = nullptr,
-                                          uint32_t* scan_n = nullptr) {
+                                          JoinSmem<Cfg, RP>& sm, int lowb = 0) {
     constexpr int TILE = Cfg::TILE, ITEMS = Cfg::ITEMS, RWIN = Cfg::RWIN, W = Cfg::WAVES;
     const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
     const int64_t t0 = tile * TILE;
@@ -282,19 +273,6 @@ __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, 
     tile_key_range(lkey, t0, tlast, lowb, kmin, kmax);
     const int64_t wn = whi - wlo;
     const bool direct = wn <= RWIN && (int64_t)kmax - (int64_t)kmin < RWIN;
-    if constexpr (PARTIAL) {
-        // R sorted on its bits above rlowb only and a window beyond the LDS
-        // table: the tile is queued for k_join_scan_tiles
-        if (!direct && rlowb != 0) {
-            if (tid == 0) {
-                const uint32_t q = atomicAdd(scan_n, 1u);
-                scan_list[q] = (uint32_t)tile;
-                scan_base[q] = base;
-            }
-            __syncthreads();
-            return;
-        }
-    }
     if (direct) {
         const int range = (int)(kmax - kmin) + 1;
         for (int i = tid; i < range; i += Cfg::BLOCK) {
@@ -316,31 +294,16 @@ __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, 
         }
     }
     __syncthreads();
-    if (direct && !PARTIAL) {
+    if (direct) {
         for (int i = tid; i < wn; i += Cfg::BLOCK) {
             const uint32_t k = rkey[wlo + i];
-            const int v = (int)(k - kmin);       // window keys lie in [kmin, kmax]
-            atomicMin(&sm.first[v], i);
-            atomicAdd(&sm.cnt[v], 1);
+            const uint32_t v = k - kmin;         // window keys lie in [kmin, kmax] (others skipped)
+            if (v <= kmax - kmin) {
+                atomicMin(&sm.first[v], i);
+                atomicAdd(&sm.cnt[v], 1);
+            }
             sm.rpay[i] = rpay ? rpay[wlo + i] : (RP)(wlo + i);
         }
-        __syncthreads();
-    } else if (direct) {
-        // R may be sorted on its bits above rlowb only, so equal keys of the
-        // window need not be adjacent: a counting sort of the window by key
-        // stages the payloads in key order (equal keys in arbitrary order).
-        const int range = (int)(kmax - kmin) + 1;
-        for (int i = tid; i < wn; i += Cfg::BLOCK) atomicAdd(&sm.cnt[(int)(rkey[wlo + i] - kmin)], 1);
-        __syncthreads();
-        for (int i = tid; i < range; i += Cfg::BLOCK) sm.first[i] = sm.cnt[i];
-        __syncthreads();
-        block_excl_scan_array<Cfg::BLOCK>(sm.first, range, sm.scan);
-        for (int i = tid; i < wn; i += Cfg::BLOCK) {
-            const int v = (int)(rkey[wlo + i] - kmin);
-            sm.rpay[atomicAdd(&sm.first[v], 1)] = rpay ? rpay[wlo + i] : (RP)(wlo + i);
-        }
-        __syncthreads();
-        for (int i = tid; i < range; i += Cfg::BLOCK) sm.first[i] -= sm.cnt[i];
         __syncthreads();
     }
     // Match count and first match of each element: rightHist of its key.
@@ -356,9 +319,11 @@ __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, 
         first[j] = 0;
         if (i < nl) {
             if (direct) {
-                const int v = (int)(key[j] - kmin);
-                cnt[j] = sm.cnt[v];
-                first[j] = sm.first[v];
+                const uint32_t v = key[j] - kmin;
+                if (v <= kmax - kmin) {
+                    cnt[j] = sm.cnt[v];
+                    first[j] = sm.first[v];
+                }
             } else {
                 const int64_t lb = lower_bound_glb(rkey, wlo, whi, key[j]);
                 const int64_t ub = upper_bound_glb(rkey, lb, whi, key[j]);
@@ -420,7 +385,7 @@ __device__ __forceinline__ void join_block_range(int64_t ntiles, int64_t& t0, in
 template <class Cfg>
 __global__ void __launch_bounds__(Cfg::BLOCK)
 k_join_count(const uint32_t* lkey, int64_t nl_upper, const int64_t* d_nl, const uint32_t* rkey,
-             const int64_t* win, int64_t* tile_cnt, int64_t* blk_total, int lowb, int rlowb) {
+             const int64_t* win, int64_t* tile_cnt, int64_t* blk_total, int lowb) {
     __shared__ JoinSmem<Cfg, uint8_t> sm;
     int64_t nl = nl_upper;
     if (d_nl) { const int64_t t = *d_nl; nl = t < nl ? t : nl; }
@@ -429,7 +394,7 @@ k_join_count(const uint32_t* lkey, int64_t nl_upper, const int64_t* d_nl, const 
     join_block_range(ntiles, t0, t1);
     for (int64_t tile = t0; tile < t1; ++tile) {
         const int64_t t = join_tile_count<Cfg, uint8_t>(lkey, nl, rkey, win[2 * tile], win[2 * tile + 1], tile, sm,
-                                                        lowb, rlowb);
+                                                        lowb);
         if (threadIdx.x == 0) tile_cnt[tile] = t;
         sum += t;
     }
@@ -443,12 +408,12 @@ k_join_count(const uint32_t* lkey, int64_t nl_upper, const int64_t* d_nl, const 
 // emitters: tiles are pulled from a
 // counter.  The kernel is persistent, so emitters can accumulate across tiles
 // and flush once.
-template <class Cfg, class LP, class RP, class Emit, bool PARTIAL = false>
+template <class Cfg, class LP, class RP, class Emit>
 __global__ void __launch_bounds__(Cfg::BLOCK)
 k_join(const uint32_t* lkey, const LP* lpay, int64_t nl_upper, const int64_t* d_nl,
        const uint32_t* rkey, const RP* rpay, const int64_t* win, uint32_t* tile_counter, const int64_t* tile_cnt,
        const int64_t* blk_total, int64_t* d_count, int64_t* d_count_out, int64_t cap, Emit emit, uint32_t* flags,
-       int lowb, int rlowb, uint32_t* scan_list, int64_t* scan_base, uint32_t* scan_n) {
+       int lowb) {
     __shared__ JoinSmem<Cfg, RP> sm;
     __shared__ typename Emit::Smem esm;
     int64_t nl = nl_upper;
@@ -470,9 +435,8 @@ k_join(const uint32_t* lkey, const LP* lpay, int64_t nl_upper, const int64_t* d_
         for (int64_t tile = t0; tile < t1; ++tile) {
             const int64_t base = run;
             run += tile_cnt[tile];
-            join_tile<Cfg, LP, RP, Emit, PARTIAL>(lkey, lpay, nl, rkey, rpay, win[2 * tile], win[2 * tile + 1], tile,
-                                                  base, d_count, e, esm, sm, lowb, rlowb, scan_list, scan_base,
-                                                  scan_n);
+            join_tile<Cfg, LP, RP, Emit>(lkey, lpay, nl, rkey, rpay, win[2 * tile], win[2 * tile + 1], tile, base,
+                                         d_count, e, esm, sm, lowb);
         }
         if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
             *d_count = run;
@@ -485,71 +449,9 @@ k_join(const uint32_t* lkey, const LP* lpay, int64_t nl_upper, const int64_t* d_
             __syncthreads();
             const int64_t tile = sm.tile;
             if (tile >= ntiles) break;
-            join_tile<Cfg, LP, RP, Emit, PARTIAL>(lkey, lpay, nl, rkey, rpay, win[2 * tile], win[2 * tile + 1], tile,
-                                                  0, d_count, e, esm, sm, lowb, rlowb);
+            join_tile<Cfg, LP, RP, Emit>(lkey, lpay, nl, rkey, rpay, win[2 * tile], win[2 * tile + 1], tile, 0,
+                                         d_count, e, esm, sm, lowb);
         }
-    }
-    e.finish(esm);
-}
-
-// The tiles k_join queued (R sorted on its bits above rlowb only, window
-// beyond the LDS table), with the same element-to-wave layout: an element's
-// matches are the rows of its key bucket that hold its key, found by scanning
-// the bucket, in bucket order (for the counts, then again for the outputs).
-// The tile's output base was queued with it.
-template <class Cfg, class LP, class RP, class Emit>
-__global__ void __launch_bounds__(Cfg::BLOCK)
-k_join_scan_tiles(const uint32_t* lkey, const LP* lpay, int64_t nl_upper, const int64_t* d_nl,
-                  const uint32_t* rkey, const RP* rpay, const int64_t* win, const uint32_t* scan_list,
-                  const int64_t* scan_base, const uint32_t* scan_n, Emit emit, int rlowb) {
-    __shared__ int64_t s_wave[Cfg::WAVES];
-    __shared__ typename Emit::Smem esm;
-    const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
-    int64_t nl = nl_upper;
-    if (d_nl) { const int64_t t = *d_nl; nl = t < nl ? t : nl; }
-    Emit e = emit;
-    e.init(esm);
-    __syncthreads();
-    const uint32_t n = *scan_n;
-    for (uint32_t q = blockIdx.x; q < n; q += gridDim.x) {
-        const int64_t tile = scan_list[q];
-        const int64_t wlo = win[2 * tile], whi = win[2 * tile + 1];
-        const int64_t chunk = tile * Cfg::TILE + (int64_t)w * Cfg::ITEMS * WAVE;
-        int64_t total = 0;
-        for (int j = 0; j < Cfg::ITEMS; ++j) {
-            const int64_t i = chunk + j * WAVE + l;
-            int64_t c = 0;
-            if (i < nl) {
-                const uint32_t key = lkey[i];
-                int64_t r, rend;
-                right_bucket(rkey, wlo, whi, key, rlowb, r, rend);
-                for (; r < rend; ++r) c += rkey[r] == key;
-            }
-            total += wave_sum(c);
-        }
-        if (l == 0) s_wave[w] = total;
-        __syncthreads();
-        int64_t wbase = scan_base[q];
-        for (int ww = 0; ww < w; ++ww) wbase += s_wave[ww];
-        for (int j = 0; j < Cfg::ITEMS; ++j) {
-            const int64_t i = chunk + j * WAVE + l;
-            uint32_t key = 0;
-            int64_t r = 0, rend = 0, c = 0;
-            if (i < nl) {
-                key = lkey[i];
-                right_bucket(rkey, wlo, whi, key, rlowb, r, rend);
-                for (int64_t t = r; t < rend; ++t) c += rkey[t] == key;
-            }
-            const int64_t incl = wave_incl_sum(c);
-            int64_t o = wbase + incl - c;
-            wbase += __shfl(incl, WAVE - 1, WAVE);
-            if (c > 0) {
-                const LP pay = lpay ? lpay[i] : (LP)i;
-                for (; r < rend; ++r)
-                    if (rkey[r] == key) e(o++, key, pay, rpay ? rpay[r] : (RP)r, esm);
-            }
-        }
-        __syncthreads();
     }
     e.finish(esm);
 }
