@@ -104,16 +104,26 @@ __global__ void k_bucket_bounds(const uint32_t* keys, int64_t n_upper, const int
 }
 
 __global__ void __launch_bounds__(FINISH_BLOCK)
-k_finish_sort(const uint32_t* kin, const uint32_t* vin, const int64_t* starts, uint32_t* kout, uint32_t* vout) {
-    constexpr int U = 8;      // loads in flight per thread
+k_finish_sort(const uint32_t* kin, const uint32_t* vin, int64_t n, uint32_t* kout, uint32_t* vout) {
+    constexpr int U = 8;                              // loads in flight per thread
+    constexpr int W = FINISH_BLOCK / WAVE;
+    constexpr int SLICE = FINISH_SPAN / W;            // counters scanned by one wave
     __shared__ uint32_t cnt[FINISH_SPAN];
-    __shared__ uint32_t scratch[FINISH_BLOCK / WAVE];
-    const int tid = threadIdx.x;
-    const int64_t lo = starts[blockIdx.x], hi = starts[blockIdx.x + 1];
-    if (lo >= hi) return;
+    __shared__ uint32_t s_wtot[W];
+    __shared__ int64_t s_lo, s_hi;
+    const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
     const uint32_t base = (uint32_t)blockIdx.x << FINISH_LOG2;
+    if (w == 0) {
+        const int64_t lo = wave_bound(kin, n, base, false);
+        if (l == 0) s_lo = lo;
+    } else if (w == 1) {
+        const int64_t hi = wave_bound(kin, n, base + FINISH_SPAN, false);
+        if (l == 0) s_hi = hi;
+    }
     for (int i = tid; i < FINISH_SPAN; i += FINISH_BLOCK) cnt[i] = 0;
     __syncthreads();
+    const int64_t lo = s_lo, hi = s_hi;
+    if (lo >= hi) return;
     // keys outside the span occur only in inputs that are not sorted on the
     // high bits (a broken key width): skipped, never indexed
     for (int64_t i0 = lo + tid; i0 < hi; i0 += (int64_t)FINISH_BLOCK * U) {
@@ -128,7 +138,22 @@ k_finish_sort(const uint32_t* kin, const uint32_t* vin, const int64_t* starts, u
             if (d[j] < FINISH_SPAN) atomicAdd(&cnt[d[j]], 1u);
     }
     __syncthreads();
-    block_excl_scan_array<FINISH_BLOCK>(cnt, FINISH_SPAN, scratch);
+    // exclusive scan of the counters: wave w scans its slice 64 entries at a
+    // time (one per lane), then adds the totals of the slices before it
+    uint32_t carry = 0;
+    for (int c = w * SLICE; c < (w + 1) * SLICE; c += WAVE) {
+        const uint32_t x = cnt[c + l];
+        const uint32_t inc = wave_incl_sum(x);
+        cnt[c + l] = carry + inc - x;
+        carry += __shfl(inc, WAVE - 1, WAVE);
+    }
+    if (l == 0) s_wtot[w] = carry;
+    __syncthreads();
+    uint32_t off = 0;
+    for (int ww = 0; ww < w; ++ww) off += s_wtot[ww];
+    if (off)
+        for (int c = w * SLICE; c < (w + 1) * SLICE; c += WAVE) cnt[c + l] += off;
+    __syncthreads();
     for (int64_t i0 = lo + tid; i0 < hi; i0 += (int64_t)FINISH_BLOCK * U) {
         uint32_t k[U], v[U];
 #pragma unroll

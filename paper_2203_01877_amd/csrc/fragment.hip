@@ -129,7 +129,6 @@ void cust_reserve(Arena& a, const tqp_cust_fragment& f, const tqp_cust_out& o, C
         b.mkeys_full = a.scratch<uint32_t>(f.n_mid);
         b.mvals_full = a.scratch<uint32_t>(f.n_mid);
         b.nspans = ((int64_t(1) << kb) + FINISH_SPAN - 1) >> FINISH_LOG2;
-        b.mspans = a.scratch<int64_t>(b.nspans + 1);
     }
     b.join = join_reserve<JCfgFrag>(a, f.n_fact);
     b.d_join = a.zero<int64_t>(1);
@@ -170,11 +169,8 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
     if (b.fact_lowb > 0 && f.n_mid > 0) {
         // the join's fallback searches need the mid keys fully sorted: finish
         // the low bits span by span
-        TQP_LAUNCH(ctx, ctx->side, "finish_bounds",
-                   k_bucket_bounds<<<grid_for(b.nspans + 1, 256, 0), 256, 0, ctx->side>>>(
-                       b.mkeys, f.n_mid, nullptr, FINISH_LOG2, b.nspans, b.mspans));
         TQP_LAUNCH(ctx, ctx->side, "finish_sort",
-                   k_finish_sort<<<(unsigned)b.nspans, FINISH_BLOCK, 0, ctx->side>>>(b.mkeys, b.mvals, b.mspans,
+                   k_finish_sort<<<(unsigned)b.nspans, FINISH_BLOCK, 0, ctx->side>>>(b.mkeys, b.mvals, f.n_mid,
                                                                                     b.mkeys_full, b.mvals_full));
         mk = b.mkeys_full;
         mv = b.mvals_full;

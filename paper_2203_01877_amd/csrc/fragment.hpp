@@ -107,8 +107,7 @@ struct CustBufs {
     uint32_t* scounter = nullptr;
     uint32_t *fkeys = nullptr, *mkeys = nullptr, *mvals = nullptr, *gkeys_in = nullptr, *gkeys = nullptr;
     uint32_t *mkeys_full = nullptr, *mvals_full = nullptr;   // mid after the finishing pass (fact_lowb > 0)
-    int64_t* mspans = nullptr;                                // start of every finishing span, spans + 1
-    int64_t nspans = 0;
+    int64_t nspans = 0;                                       // 4096-key spans of the finishing pass
     uint64_t *fvals = nullptr, *gvals_in = nullptr, *gvals = nullptr;
     TopkBufs topk;
 };

@@ -439,13 +439,12 @@ k_radix_pass(Src src, DstPairs<V> dst, int shift, int bits, const uint32_t* hist
 // ---------------------------------------------------------- finishing pass
 // Completes the sort of keys already sorted on their bits above lowb
 // (lowb <= FINISH_LOG2): the rows whose key lies in one span [s << FINISH_LOG2,
-// (s + 1) << FINISH_LOG2) are contiguous (starts[s], from one search per
-// span), so one block per span counting-sorts them in LDS (count per key,
+// (s + 1) << FINISH_LOG2) are contiguous (two 64-way wave searches find
+// them), so one block per span counting-sorts them in LDS (count per key,
 // scan, scatter).  Equal keys end up in arbitrary order.
 constexpr int FINISH_LOG2 = 12;
 constexpr int FINISH_SPAN = 1 << FINISH_LOG2;
 constexpr int FINISH_BLOCK = 256;
-__global__ void k_finish_sort(const uint32_t* kin, const uint32_t* vin, const int64_t* starts, uint32_t* kout,
-                              uint32_t* vout);
+__global__ void k_finish_sort(const uint32_t* kin, const uint32_t* vin, int64_t n, uint32_t* kout, uint32_t* vout);
 
 }  // namespace tqp
