@@ -66,7 +66,7 @@ def measured_traffic():
         return None
     fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and not line.startswith(" "))
     src = b"".join(open(os.path.join(ROOT, "paper_2203_01877_amd", "csrc", f), "rb").read()
-                   for f in ("radix.hpp", "dev.hpp"))
+                   for f in ("radix.hpp", "dev.hpp", "host.hpp"))
     if fields.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
         return None
     try:
@@ -214,7 +214,7 @@ def main():
             achieved = bytes_total / (sum(durs) * 1e-3) / 1e9
             roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                        "kernel": "k_radix_pass<RadixCfg<%d,%s>, SrcPairs<u64>, u64>" % (args.digit_bits, {4: "256,8,8", 8: "512,8,8", 11: "512,8,8"}[args.digit_bits]),
+                        "kernel": "k_radix_pass<RadixCfg<%d,%s>, SrcPairs<u64>, u64>" % (args.digit_bits, {4: "256,8,8", 8: "512,12,8", 11: "512,8,8"}[args.digit_bits]),
                         "launches": len(durs), "avg_launch_ms": round(sum(durs) / len(durs), 4),
                         "bytes_per_launch": round(bytes_total / len(durs))}
         else:

@@ -232,7 +232,7 @@ tqp_status radix_launch(const RadixBufs<Cfg, V>& b, const Src0& src0, int64_t n_
 
 // Digit-width dispatch: the context's digit width picks the configuration.
 using R4 = RadixCfg<4, 256, 8, 8>;
-using R8 = RadixCfg<8, 512, 8, 8>;
+using R8 = RadixCfg<8, 512, 12, 8>;
 using R11 = RadixCfg<11, 512, 8, 8>;
 
 template <class F>
