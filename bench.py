@@ -33,7 +33,6 @@ sys.path.insert(0, ROOT)
 
 METRIC = "fact rows/s filter→join→group-by (% of HBM peak); p50/p99 fragment latency"
 HBM_PEAK_GBS = 8000.0
-DOMINANT = "radix_pass_pairs_v8"
 
 
 def log(*a):
@@ -44,33 +43,51 @@ def algorithmic_bytes(plan, N, n_f, M, J, G):
     """Bytes per step each kernel family must read and write in this design, summed over its
     launches in one step (the row counts are the actual ones)."""
     return {
-        "radix_hist": 8 * N + 4 * M + 4 * J,                  # fact fk+date, mid pk, group custkey
-        "radix_pass_fused_v8": 8 * N + 16 * n_f + 12 * n_f,   # fk, date (+price, disc of kept rows); key+revenue out
+        "radix_hist": 8 * N + 4 * M,                          # fact fk+date, mid pk
+        "radix_pass_fused_v8": 24 * N + 12 * n_f,             # fk, date, price, disc per row; key+revenue per kept row
         "radix_pass_pairs_v8": 24 * (n_f * (plan["fact_passes"] - 1) + J * plan["group_passes"]),
         "radix_pass_fused_v4": 16 * M,                        # pk, custkey in; key+custkey out
         "radix_pass_pairs_v4": 16 * M * (plan["mid_passes"] - 1),
+        "finish_sort": 16 * M,                                # mid (key, custkey) in and out
+        "join_count": 4 * n_f + 4 * M,                        # sorted fact keys, mid keys
         "join_keyval": 12 * n_f + 8 * M + 12 * J,             # sorted fact pairs, mid keys+custkey; (custkey, revenue) out
         "bucket_agg": 12 * J + 20 * G,
         "topk_filter": 12 * G,
     }
 
 
-def measured_traffic():
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter summary, or
-    None when the kernel's source has changed since the counters were taken."""
+# Kernel families the roofline may describe: the launches' algorithmic bytes, the kernel, and the
+# sources whose hash must match the committed counter summary for its traffic figure to be used.
+ROOFLINE_FAMILIES = {
+    "radix_pass_fused_v8": ("k_radix_pass<RadixCfg<8,512,12,8>, SrcFilterRevenue, u64>",
+                            ("radix.hpp", "dev.hpp", "host.hpp")),
+    "radix_pass_pairs_v8": ("k_radix_pass<RadixCfg<8,512,12,8>, SrcPairs<u64>, u64>",
+                            ("radix.hpp", "dev.hpp", "host.hpp")),
+    "join_keyval": ("k_join<JoinCfg<256,8,2048>, u64, u32, EmitKeyVal<256,8>>",
+                    ("join.hpp", "dev.hpp", "fragment.hpp")),
+    "bucket_agg": ("k_bucket_agg<1024,8192>", ("segreduce.hpp", "dev.hpp")),
+}
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "cfg2_hbm_traffic.md")
+
+
+def source_hash(files):
     import hashlib
-    path = os.path.join(ROOT, "profiles", "radix_pass_pairs_v8_cfg2_hbm.md")
+    return hashlib.sha256(b"".join(open(os.path.join(ROOT, "paper_2203_01877_amd", "csrc", f), "rb").read()
+                                   for f in files)).hexdigest()
+
+
+def measured_traffic(family):
+    """HBM bytes per launch of a kernel family from the committed rocprofv3 counter summary, or None
+    when the family's sources have changed since the counters were taken."""
     try:
-        text = open(path).read()
+        text = open(TRAFFIC_SUMMARY).read()
     except OSError:
         return None
     fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and not line.startswith(" "))
-    src = b"".join(open(os.path.join(ROOT, "paper_2203_01877_amd", "csrc", f), "rb").read()
-                   for f in ("radix.hpp", "dev.hpp", "host.hpp"))
-    if fields.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
+    if fields.get("source_sha256[%s]" % family) != source_hash(ROOFLINE_FAMILIES[family][1]):
         return None
     try:
-        return int(fields["traffic_bytes_per_launch"])
+        return int(fields["traffic_bytes_per_launch[%s]" % family])
     except (KeyError, ValueError):
         return None
 
@@ -203,23 +220,32 @@ def main():
     stage_bytes = algorithmic_bytes(run.plan(), N, n_f, M, J, G) if per else {}
     stage_gbps = {k: round(b / (stage_ms[k] * 1e-3) / 1e9, 1) for k, b in stage_bytes.items()
                   if stage_ms.get(k)}
+    # roofline: the family with the most measured time per step among the big single-stream kernels
     roofline = None
-    if DOMINANT in per:
-        # launches of the dominant family per step: fact passes after the first, then every group pass
-        plan = run.plan()
-        sizes = [n_f] * (plan["fact_passes"] - 1) + [J] * plan["group_passes"]
-        durs = per[DOMINANT]
+    plan = run.plan()
+    launch_bytes = {
+        "radix_pass_fused_v8": [24 * N + 12 * n_f],
+        "radix_pass_pairs_v8": [24 * n_f] * (plan["fact_passes"] - 1) + [24 * J] * plan["group_passes"],
+        "join_keyval": [12 * n_f + 8 * M + 12 * J],
+        "bucket_agg": [12 * J + 20 * G],
+    }
+    timed = {f: sum(per[f]) for f in launch_bytes if f in per}
+    if args.digit_bits == 8 and timed:
+        fam = max(timed, key=timed.get)
+        durs = per[fam]
+        sizes = launch_bytes[fam]
         if len(durs) == len(sizes) * args.steps:
-            bytes_total = sum(24 * s for s in sizes) * args.steps
+            bytes_total = sum(sizes) * args.steps
             achieved = bytes_total / (sum(durs) * 1e-3) / 1e9
             roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
-                        "kernel": "k_radix_pass<RadixCfg<%d,%s>, SrcPairs<u64>, u64>" % (args.digit_bits, {4: "256,8,8", 8: "512,12,8", 11: "512,8,8"}[args.digit_bits]),
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(fam),
+                        "kernel": ROOFLINE_FAMILIES[fam][0], "family": fam,
                         "launches": len(durs), "avg_launch_ms": round(sum(durs) / len(durs), 4),
-                        "bytes_per_launch": round(bytes_total / len(durs))}
+                        "bytes_per_launch": round(bytes_total / len(durs)),
+                        "share_of_profiled_step": round(sum(durs) / args.steps / ms_prof, 3)}
         else:
-            log("dominant kernel launch count %d does not match %d passes x %d steps"
-                % (len(durs), len(sizes), args.steps))
+            log("kernel %s: launch count %d does not match %d per step x %d steps"
+                % (fam, len(durs), len(sizes), args.steps))
 
     P = max(1, -(-key_bits // 8))
     Pm = max(1, -(-datagen.bits_for(M) // 8))
