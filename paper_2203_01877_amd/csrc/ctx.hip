@@ -129,9 +129,10 @@ k_finish_sort(const uint32_t* kin, const uint32_t* vin, int64_t n, uint32_t* kou
     for (int64_t i0 = lo + tid; i0 < hi; i0 += (int64_t)FINISH_BLOCK * U) {
         uint32_t d[U];
 #pragma unroll
-        for (int j = 0; j < U; ++j) {
+        for (int j = 0; j < U; ++j) {          // clamped index: no branch between the loads
             const int64_t i = i0 + (int64_t)j * FINISH_BLOCK;
-            d[j] = i < hi ? kin[i] - base : FINISH_SPAN;
+            d[j] = kin[i < hi ? i : hi - 1] - base;
+            if (i >= hi) d[j] = FINISH_SPAN;
         }
 #pragma unroll
         for (int j = 0; j < U; ++j)
@@ -159,8 +160,10 @@ k_finish_sort(const uint32_t* kin, const uint32_t* vin, int64_t n, uint32_t* kou
 #pragma unroll
         for (int j = 0; j < U; ++j) {
             const int64_t i = i0 + (int64_t)j * FINISH_BLOCK;
-            k[j] = base + FINISH_SPAN;
-            if (i < hi) { k[j] = kin[i]; v[j] = vin[i]; }
+            const int64_t ic = i < hi ? i : hi - 1;
+            k[j] = kin[ic];
+            v[j] = vin[ic];
+            if (i >= hi) k[j] = base + FINISH_SPAN;
         }
 #pragma unroll
         for (int j = 0; j < U; ++j) {

@@ -36,6 +36,11 @@ struct JoinCfg {
     static constexpr int WAVES = BLOCK_ / WAVE;
 };
 
+// Window rows each thread loads per round while building a tile's LDS table
+// (the expanding kernel has fewer registers to spare than the counting one).
+constexpr int TABLE_ITEMS = 4;
+constexpr int COUNT_TABLE_ITEMS = 8;
+
 // Matches of one left element at most this many are emitted by its own lane;
 // elements with more are expanded by the whole wave, 64 outputs at a time.
 constexpr int JOIN_LANE_MAX = 4;
@@ -228,9 +233,20 @@ __device__ __forceinline__ int64_t join_tile_count(const uint32_t* lkey, int64_t
         // declared key width (already flagged): they are skipped, never
         // indexed
         const uint32_t range = kmax - kmin + 1;
-        for (int i = tid; i < wn; i += Cfg::BLOCK) {
-            const uint32_t v = rkey[wlo + i] - kmin;
-            if (v < range) atomicAdd(&sm.cnt[v], 1);
+        // COUNT_TABLE_ITEMS window keys per thread and round, loaded before
+        // any is used (clamped index: no branch between the loads)
+        for (int i0 = tid; i0 < wn; i0 += Cfg::BLOCK * COUNT_TABLE_ITEMS) {
+            uint32_t kk[COUNT_TABLE_ITEMS];
+#pragma unroll
+            for (int u = 0; u < COUNT_TABLE_ITEMS; ++u) {
+                const int i = i0 + u * Cfg::BLOCK;
+                kk[u] = rkey[wlo + (i < wn ? i : wn - 1)];
+            }
+#pragma unroll
+            for (int u = 0; u < COUNT_TABLE_ITEMS; ++u) {
+                const uint32_t v = kk[u] - kmin;
+                if (i0 + u * Cfg::BLOCK < wn && v < range) atomicAdd(&sm.cnt[v], 1);
+            }
         }
         __syncthreads();
     }
@@ -295,15 +311,35 @@ __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, 
     }
     __syncthreads();
     if (direct) {
-        for (int i = tid; i < wn; i += Cfg::BLOCK) {
-            const uint32_t k = rkey[wlo + i];
-            const uint32_t v = k - kmin;         // window keys lie in [kmin, kmax] (others skipped)
-            if (v <= kmax - kmin) {
-                atomicMin(&sm.first[v], i);
-                atomicAdd(&sm.cnt[v], 1);
+        // TABLE_ITEMS window rows per thread and round, loaded before any is
+        // used (clamped index: no branch between the loads)
+        auto build = [&](auto load_pay) {
+            for (int i0 = tid; i0 < wn; i0 += Cfg::BLOCK * TABLE_ITEMS) {
+                uint32_t kk[TABLE_ITEMS];
+                RP pp[TABLE_ITEMS];
+#pragma unroll
+                for (int u = 0; u < TABLE_ITEMS; ++u) {
+                    const int i = i0 + u * Cfg::BLOCK;
+                    const int ic = i < wn ? i : (int)wn - 1;
+                    kk[u] = rkey[wlo + ic];
+                    pp[u] = load_pay(wlo + ic);
+                }
+#pragma unroll
+                for (int u = 0; u < TABLE_ITEMS; ++u) {
+                    const int i = i0 + u * Cfg::BLOCK;
+                    if (i < wn) {
+                        const uint32_t v = kk[u] - kmin;     // window keys lie in [kmin, kmax] (others skipped)
+                        if (v <= kmax - kmin) {
+                            atomicMin(&sm.first[v], i);
+                            atomicAdd(&sm.cnt[v], 1);
+                        }
+                        sm.rpay[i] = pp[u];
+                    }
+                }
             }
-            sm.rpay[i] = rpay ? rpay[wlo + i] : (RP)(wlo + i);
-        }
+        };
+        if (rpay) build([&](int64_t r) { return rpay[r]; });
+        else build([&](int64_t r) { return (RP)r; });
         __syncthreads();
     }
     // Match count and first match of each element: rightHist of its key.

@@ -121,6 +121,12 @@ tqp_status tqp_sort(tqp_ctx* ctx, const int32_t* keys, const int32_t* vals, int6
             st = with_workspace(ctx, ws, ws_bytes, stream, plan, a);
             if (st != TQP_OK || !ws) return st;
             if ((st = fill_zero(a.base, a.zsize, stream, ctx)) != TQP_OK) return st;
+            if (!vals) {       // payload = input position
+                SrcKeysIndex src{reinterpret_cast<const uint32_t*>(keys), n, d_n};
+                return radix_launch<Cfg, uint32_t>(b, src, n, true, nullptr, mask,
+                                                   reinterpret_cast<uint32_t*>(keys_out),
+                                                   reinterpret_cast<uint32_t*>(vals_out), ctx, stream);
+            }
             SrcPairs<uint32_t> src{reinterpret_cast<const uint32_t*>(keys),
                                    reinterpret_cast<const uint32_t*>(vals), n, d_n};
             return radix_launch<Cfg, uint32_t>(b, src, n, true, nullptr, mask,
@@ -203,7 +209,7 @@ tqp_status tqp_groupby_agg(tqp_ctx* ctx, const int32_t* gkey, int64_t n, const i
         if ((st = fill_zero(out_cnt, gcap * 8, stream, ctx)) != TQP_OK) return st;
         if (sa && (st = fill_zero(sa, gcap * 8, stream, ctx)) != TQP_OK) return st;
         // Algorithm 2: sort the keys and obtain the permutation (grpsInvIdx) ...
-        SrcPairs<uint32_t> src{reinterpret_cast<const uint32_t*>(gkey), nullptr, n, d_n};
+        SrcKeysIndex src{reinterpret_cast<const uint32_t*>(gkey), n, d_n};
         st = radix_launch<Cfg, uint32_t>(b, src, n, true, nullptr, mask, skeys, perm, ctx, stream);
         if (st != TQP_OK) return st;
         // ... then runs of equal keys and their aggregates, values read through the permutation.

@@ -19,11 +19,14 @@ struct NoVal {};
 // A source yields, for index i of its domain, whether the element takes part,
 // its key and its payload.  size() may depend on a device-side count.
 
+// Loads are branch-free and unconditional (callers clamp the index), so the
+// compiler keeps every item's loads of a thread in flight together.
+
 // Plain (key, value) arrays, optionally bounded by a device count.
 template <class V>
 struct SrcPairs {
     const uint32_t* keys;
-    const V* vals;             // null: payload is the element index (V must be uint32_t)
+    const V* vals;             // not null (SrcKeysIndex pairs keys with their index)
     int64_t n_upper;
     const int64_t* d_n;
     __device__ int64_t size() const {
@@ -37,8 +40,28 @@ struct SrcPairs {
     }
     __device__ bool load(int64_t i, uint32_t& k, V& v) const {
         k = keys[i];
-        if (vals) v = vals[i];
-        else v = (V)i;
+        v = vals[i];
+        return true;
+    }
+};
+
+// Keys with their element index as the payload.
+struct SrcKeysIndex {
+    const uint32_t* keys;
+    int64_t n_upper;
+    const int64_t* d_n;
+    __device__ int64_t size() const {
+        if (!d_n) return n_upper;
+        int64_t n = *d_n;
+        return n < n_upper ? n : n_upper;
+    }
+    __device__ bool load_key(int64_t i, uint32_t& k) const {
+        k = keys[i];
+        return true;
+    }
+    __device__ bool load(int64_t i, uint32_t& k, uint32_t& v) const {
+        k = keys[i];
+        v = (uint32_t)i;
         return true;
     }
 };
@@ -67,15 +90,19 @@ struct SrcPairs<NoVal> {
 // Predicate constants of a pushed-down comparison.
 enum CmpOp : int32_t { CMP_LT = 0, CMP_LE = 1, CMP_GT = 2, CMP_GE = 3, CMP_EQ = 4, CMP_NE = 5 };
 
+// Branch-free on purpose: with a switch, the compiler waits for each item's
+// loads before the next item's (it will not move loads across the branches),
+// so a thread kept one item in flight instead of all of them.  Operators
+// outside CMP_LT..CMP_EQ compare for inequality.
 __device__ __forceinline__ bool cmp_eval(int64_t x, int32_t op, int64_t k) {
-    switch (op) {
-        case CMP_LT: return x < k;
-        case CMP_LE: return x <= k;
-        case CMP_GT: return x > k;
-        case CMP_GE: return x >= k;
-        case CMP_EQ: return x == k;
-        default: return x != k;
-    }
+    const bool lt = x < k, eq = x == k;
+    bool r = (op == CMP_LT) & lt;
+    r |= (op == CMP_LE) & (lt | eq);
+    r |= (op == CMP_GT) & !(lt | eq);
+    r |= (op == CMP_GE) & !lt;
+    r |= (op == CMP_EQ) & eq;
+    r |= (op < CMP_LT || op > CMP_EQ) & !eq;
+    return r;
 }
 
 // key column + one filter column (date < D, seg == c ...), payload = row id.
@@ -216,7 +243,8 @@ k_radix_hist(Src src, PassDesc pd, uint32_t key_mask, uint32_t* hist, int64_t* d
 #pragma unroll
         for (int j = 0; j < U; ++j) {
             const int64_t i = base + (int64_t)j * Cfg::BLOCK;
-            ok[j] = i < n && src.load_key(i, kk[j]);
+            const bool in = i < n;
+            ok[j] = src.load_key(in ? i : n - 1, kk[j]) && in;     // base < n, so n >= 1
         }
 #pragma unroll
         for (int j = 0; j < U; ++j) {
@@ -324,9 +352,9 @@ __device__ __forceinline__ void radix_pass_tile(const Src& src, const DstPairs<V
     bool valid[ITEMS];
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-        int64_t i = base + j * WAVE + l;
-        valid[j] = false;
-        if (i < n) valid[j] = src.load(i, key[j], val[j]);
+        const int64_t i = base + j * WAVE + l;
+        const bool in = i < n;
+        valid[j] = src.load(in ? i : n - 1, key[j], val[j]) && in;   // n >= 1: the tile exists
     }
 
     // Rank: peers with the same digit found by one ballot per digit bit; the

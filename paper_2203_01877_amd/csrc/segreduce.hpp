@@ -230,9 +230,11 @@ k_bucket_agg(const uint32_t* keys, const int64_t* vals, const int64_t* starts, c
         uint32_t k[U];
         int64_t v[U];
 #pragma unroll
-        for (int j = 0; j < U; ++j) {
+        for (int j = 0; j < U; ++j) {          // clamped index: no branch between the loads
             const int64_t i = i0 + (int64_t)j * BLOCK;
-            if (i < hi) { k[j] = keys[i] & lmask; v[j] = vals[i]; }
+            const int64_t ic = i < hi ? i : hi - 1;
+            k[j] = keys[ic] & lmask;
+            v[j] = vals[ic];
         }
 #pragma unroll
         for (int j = 0; j < U; ++j) {
