@@ -47,9 +47,14 @@ struct BatchFrag {
 struct SrcSeg {
     const BatchSeg* s;
     __device__ int64_t size() const { return s->n; }
+    // Both typed reads are issued (the other at index 0, always in range) and
+    // the value selected afterwards: no branch between the loads of a tile's
+    // items.
     __device__ bool pass_row(int64_t i) const {
-        const int64_t x = s->ftype == 1 ? (int64_t)((const int8_t*)s->fcol)[i] : (int64_t)((const int32_t*)s->fcol)[i];
-        return cmp_eval(x, s->op, s->k);
+        const bool i8 = s->ftype == 1;
+        const int64_t x8 = ((const int8_t*)s->fcol)[i8 ? i : 0];
+        const int64_t x32 = ((const int32_t*)s->fcol)[i8 ? 0 : i];
+        return cmp_eval(i8 ? x8 : x32, s->op, s->k);
     }
     __device__ bool load_key(int64_t i, uint32_t& kk) const {
         kk = (uint32_t)s->key[i];
@@ -107,12 +112,25 @@ k_batch_hist(const BatchSeg* segs, int nseg, const int64_t* prefix, uint32_t* co
         const uint32_t kmask = sg.shift[np - 1] + sg.bits[np - 1] >= 32
                                    ? 0xFFFFFFFFu : ((1u << (sg.shift[np - 1] + sg.bits[np - 1])) - 1);
         uint32_t cnt = 0, bad = 0;
-        for (int64_t i = r0 + threadIdx.x; i < r1; i += Cfg::BLOCK) {
-            uint32_t k;
-            if (!src.load_key(i, k)) continue;
-            ++cnt;
-            bad |= k & ~kmask;
-            for (int p = 0; p < np; ++p) atomicAdd(&h[p * R + ((k >> sg.shift[p]) & ((1u << sg.bits[p]) - 1))], 1u);
+        constexpr int U = HIST_ITEMS;
+        for (int64_t i0 = r0 + threadIdx.x; i0 < r1; i0 += (int64_t)Cfg::BLOCK * U) {
+            uint32_t kk[U];
+            bool ok[U];
+#pragma unroll
+            for (int j = 0; j < U; ++j) {      // clamped index: no branch between the loads
+                const int64_t i = i0 + (int64_t)j * Cfg::BLOCK;
+                const bool in = i < r1;
+                ok[j] = src.load_key(in ? i : r1 - 1, kk[j]) && in;
+            }
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                if (!ok[j]) continue;
+                const uint32_t k = kk[j];
+                ++cnt;
+                bad |= k & ~kmask;
+                for (int p = 0; p < np; ++p)
+                    atomicAdd(&h[p * R + ((k >> sg.shift[p]) & ((1u << sg.bits[p]) - 1))], 1u);
+            }
         }
         cnt = wave_sum(cnt);
         if (lane_id() == 0 && cnt) atomicAdd(&s_cnt, cnt);

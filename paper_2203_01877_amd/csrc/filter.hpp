@@ -19,19 +19,29 @@ struct FilterPreds {
     int32_t op[FILTER_MAX_PREDS];
     int64_t k[FILTER_MAX_PREDS];
     int32_t np;
-    __device__ bool eval(int64_t i) const {
-        bool ok = true;
+    // ok[j] for rows idx[j] (already clamped into range): per predicate, the
+    // column type is decided once and all the rows' values are loaded before
+    // any is compared, so they are in flight together.
+    template <int ITEMS>
+    __device__ void eval(const int64_t (&idx)[ITEMS], bool (&ok)[ITEMS]) const {
+        for (int p = 0; p < np; ++p) {
+            int64_t x[ITEMS];
+            if (type[p] == 1) {
+                const int8_t* c = (const int8_t*)col[p];
 #pragma unroll
-        for (int p = 0; p < FILTER_MAX_PREDS; ++p) {
-            if (p < np) {
-                int64_t x;
-                if (type[p] == 1) x = ((const int8_t*)col[p])[i];
-                else if (type[p] == 2) x = ((const int32_t*)col[p])[i];
-                else x = ((const int64_t*)col[p])[i];
-                ok = ok && cmp_eval(x, op[p], k[p]);
+                for (int j = 0; j < ITEMS; ++j) x[j] = c[idx[j]];
+            } else if (type[p] == 2) {
+                const int32_t* c = (const int32_t*)col[p];
+#pragma unroll
+                for (int j = 0; j < ITEMS; ++j) x[j] = c[idx[j]];
+            } else {
+                const int64_t* c = (const int64_t*)col[p];
+#pragma unroll
+                for (int j = 0; j < ITEMS; ++j) x[j] = c[idx[j]];
             }
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) ok[j] = ok[j] & cmp_eval(x[j], op[p], k[p]);
         }
-        return ok;
     }
 };
 
@@ -55,10 +65,18 @@ k_filter(FilterPreds fp, int64_t n, const int32_t* carry, int32_t* out_row, int3
     const int64_t chunk = tile * TILE + (int64_t)w * ITEMS * WAVE;
     uint64_t m[ITEMS];
     int64_t wc = 0;
+    int64_t idx[ITEMS];
+    bool ok[ITEMS];
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const int64_t i = chunk + j * WAVE + l;
-        m[j] = ballot(i < n && fp.eval(i));
+        ok[j] = i < n;
+        idx[j] = ok[j] ? i : n - 1;       // n >= 1: the tile exists
+    }
+    fp.eval<ITEMS>(idx, ok);
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        m[j] = ballot(ok[j]);
         wc += popc64(m[j]);
     }
     if (l == 0) s_wave[w] = wc;

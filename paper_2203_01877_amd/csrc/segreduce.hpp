@@ -96,15 +96,19 @@ k_segreduce(const uint32_t* keys, VS vs, int64_t n_upper, const int64_t* d_n, ui
     uint32_t key[ITEMS];
     uint64_t hm[ITEMS];
     int64_t wave_heads = 0;
+    uint32_t prev[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {          // clamped indices: no branch between the loads
+        const int64_t i = chunk + j * WAVE + l;
+        const int64_t ic = i < n ? i : n - 1;  // n >= 1: the tile exists
+        key[j] = keys[ic];
+        prev[j] = keys[ic > 0 ? ic - 1 : 0];
+    }
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const int64_t i = chunk + j * WAVE + l;
-        bool head = false;
-        key[j] = 0;
-        if (i < n) {
-            key[j] = keys[i];
-            head = (i == 0) || (keys[i - 1] != key[j]);
-        }
+        const bool head = i < n && (i == 0 || prev[j] != key[j]);
+        if (i >= n) key[j] = 0;
         hm[j] = ballot(head);
         wave_heads += popc64(hm[j]);
     }

@@ -245,7 +245,8 @@ k_topk_thresh(const int64_t* gsum, int64_t n_upper, const int64_t* d_n, int k, i
     for (int j = 0; j < PER; ++j) {
         const int64_t i = (int64_t)j * BLOCK + threadIdx.x;
         valid[j] = i < m;
-        hi[j] = valid[j] ? order_hi(gsum[(int64_t)j * run + threadIdx.x]) : 0;
+        // clamped index (the sample has at least k >= 1 rows): no branch between the loads
+        hi[j] = order_hi(gsum[valid[j] ? (int64_t)j * run + threadIdx.x : 0]);
         lo[j] = 0;
     }
     uint64_t t_hi;
