@@ -39,34 +39,55 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(plan, N, n_f, M, J, G):
+def algorithmic_bytes(plan, N, n_f, M, J, G, PB):
     """Bytes per step each kernel family must read and write in this design, summed over its
-    launches in one step (the row counts are the actual ones)."""
+    launches in one step (the row counts are the actual ones; PB is the revenue payload width in
+    bytes, 8 or 4)."""
+    R = 4 + PB                                                # a (key, revenue) row
     return {
         "radix_hist": 8 * N + 4 * M,                          # fact fk+date, mid pk
-        "radix_pass_fused_v8": 24 * N + 12 * n_f,             # fk, date, price, disc per row; key+revenue per kept row
-        "radix_pass_pairs_v8": 24 * (n_f * (plan["fact_passes"] - 1) + J * plan["group_passes"]),
-        "radix_pass_fused_v4": 16 * M,                        # pk, custkey in; key+custkey out
-        "radix_pass_pairs_v4": 16 * M * (plan["mid_passes"] - 1),
+        "fact_pass_fused": 24 * N + R * n_f,                  # fk, date, price, disc per row; key+revenue per kept row
+        "fact_pass": 2 * R * n_f * (plan["fact_passes"] - 1),
+        "mid_pass_first": 16 * M,                             # pk, custkey in; key+custkey out
+        "mid_pass": 16 * M * (plan["mid_passes"] - 1),
         "finish_sort": 16 * M,                                # mid (key, custkey) in and out
         "join_count": 4 * n_f + 4 * M,                        # sorted fact keys, mid keys
-        "join_keyval": 12 * n_f + 8 * M + 12 * J,             # sorted fact pairs, mid keys+custkey; (custkey, revenue) out
-        "bucket_agg": 12 * J + 20 * G,
+        "join_keyval": R * n_f + 8 * M + R * J,               # sorted fact pairs, mid keys+custkey; (custkey, revenue) out
+        "group_pass": 2 * R * J * plan["group_passes"],
+        "bucket_agg": R * J + 20 * G,
         "topk_filter": 12 * G,
     }
 
 
-# Kernel families the roofline may describe: the launches' algorithmic bytes, the kernel, and the
-# sources whose hash must match the committed counter summary for its traffic figure to be used.
-ROOFLINE_FAMILIES = {
-    "radix_pass_fused_v8": ("k_radix_pass<RadixCfg<8,512,12,8>, SrcFilterRevenue, u64>",
-                            ("radix.hpp", "dev.hpp", "host.hpp")),
-    "radix_pass_pairs_v8": ("k_radix_pass<RadixCfg<8,512,12,8>, SrcPairs<u64>, u64>",
-                            ("radix.hpp", "dev.hpp", "host.hpp")),
-    "join_keyval": ("k_join<JoinCfg<256,8,2048>, u64, u32, EmitKeyVal<256,8>>",
-                    ("join.hpp", "dev.hpp", "fragment.hpp")),
-    "bucket_agg": ("k_bucket_agg<1024,8192>", ("segreduce.hpp", "dev.hpp")),
-}
+def launch_bytes(plan, N, n_f, M, J, G, PB):
+    """Algorithmic bytes of each launch of the kernel families the roofline may describe."""
+    R = 4 + PB
+    return {
+        "fact_pass_fused": [24 * N + R * n_f],
+        "fact_pass": [2 * R * n_f] * (plan["fact_passes"] - 1),
+        "group_pass": [2 * R * J] * plan["group_passes"],
+        "join_keyval": [R * n_f + 8 * M + R * J],
+        "bucket_agg": [R * J + 20 * G],
+    }
+
+
+def roofline_families(PB):
+    """Kernel families the roofline may describe: the kernel (as the profiler names it, shortened)
+    and the sources whose hash must match the committed counter summary for its traffic figure to
+    be used."""
+    v = "u64" if PB == 8 else "u32"
+    a = "long" if PB == 8 else "u32"
+    radix = ("radix.hpp", "dev.hpp", "host.hpp")
+    return {
+        "fact_pass_fused": ("k_radix_pass<RadixCfg<8,512,12,8>, SrcFilterRevenue<%s>, %s, 1>" % (v, v), radix),
+        "fact_pass": ("k_radix_pass<RadixCfg<8,512,12,8>, SrcPairs<%s>, %s, 1>" % (v, v), radix),
+        "group_pass": ("k_radix_pass<RadixCfg<8,512,12,8>, SrcPairs<%s>, %s, 3>" % (v, v), radix),
+        "join_keyval": ("k_join<JoinCfg<256,8,2048>, %s, u32, EmitKeyVal<256,8,%s>>" % (v, v),
+                        ("join.hpp", "dev.hpp", "fragment.hpp")),
+        "bucket_agg": ("k_bucket_agg<1024,8192,%s>" % a, ("segreduce.hpp", "dev.hpp")),
+    }
+
+
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "cfg2_hbm_traffic.md")
 
 
@@ -76,15 +97,18 @@ def source_hash(files):
                                    for f in files)).hexdigest()
 
 
-def measured_traffic(family):
+def measured_traffic(family, files, PB):
     """HBM bytes per launch of a kernel family from the committed rocprofv3 counter summary, or None
-    when the family's sources have changed since the counters were taken."""
+    when the family's sources have changed since the counters were taken (or they were taken with
+    another payload width)."""
     try:
         text = open(TRAFFIC_SUMMARY).read()
     except OSError:
         return None
     fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and not line.startswith(" "))
-    if fields.get("source_sha256[%s]" % family) != source_hash(ROOFLINE_FAMILIES[family][1]):
+    if fields.get("revenue_bytes") != str(PB):
+        return None
+    if fields.get("source_sha256[%s]" % family) != source_hash(files):
         return None
     try:
         return int(fields["traffic_bytes_per_launch[%s]" % family])
@@ -119,6 +143,10 @@ def main():
     ap.add_argument("--with-copy", action="store_true",
                     help="after the steps, run a plain 1 GiB device copy (calibrates HBM counters)")
     ap.add_argument("--rows", type=int, default=0, help="fact rows (0: the full 60M workload)")
+    ap.add_argument("--revenue-bits", type=int, default=32, choices=[32, 64],
+                    help="declared width of the revenue price*(100-disc) carried through sort, join and "
+                         "group-by (the workload's maximum is about 1.05e9 < 2^32; sums are int64 either way, "
+                         "and a row outside the declared width sets a device error flag)")
     ap.add_argument("--date-lt", type=int, default=None,
                     help="config 2 with another filter constant D (date < D; the workload uses 2400)")
     ap.add_argument("--config", type=int, default=2, choices=[2, 3, 4],
@@ -170,8 +198,9 @@ def main():
     cust_bits = datagen.bits_for(fr.cust_hi)
     ctx = tqp.Context(0)
     ctx.set_digit_bits(args.digit_bits)
+    PB = args.revenue_bits // 8
     run = tqp.CustFragmentRunner(ctx, fact, mid, fr.D, fr.k, key_bits=key_bits, cust_bits=cust_bits,
-                                 gcap=min(N, fr.cust_hi))
+                                 gcap=min(N, fr.cust_hi), revenue_bits=args.revenue_bits)
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
 
@@ -217,29 +246,26 @@ def main():
     for name, t in recs:
         per.setdefault(name, []).append(t)
     stage_ms = {k: round(sum(v) / args.steps, 4) for k, v in sorted(per.items())}
-    stage_bytes = algorithmic_bytes(run.plan(), N, n_f, M, J, G) if per else {}
+    stage_bytes = algorithmic_bytes(run.plan(), N, n_f, M, J, G, PB) if per else {}
     stage_gbps = {k: round(b / (stage_ms[k] * 1e-3) / 1e9, 1) for k, b in stage_bytes.items()
                   if stage_ms.get(k)}
     # roofline: the family with the most measured time per step among the big single-stream kernels
     roofline = None
     plan = run.plan()
-    launch_bytes = {
-        "radix_pass_fused_v8": [24 * N + 12 * n_f],
-        "radix_pass_pairs_v8": [24 * n_f] * (plan["fact_passes"] - 1) + [24 * J] * plan["group_passes"],
-        "join_keyval": [12 * n_f + 8 * M + 12 * J],
-        "bucket_agg": [12 * J + 20 * G],
-    }
-    timed = {f: sum(per[f]) for f in launch_bytes if f in per}
+    lbytes = launch_bytes(plan, N, n_f, M, J, G, PB)
+    families = roofline_families(PB)
+    timed = {f: sum(per[f]) for f in lbytes if f in per}
     if args.digit_bits == 8 and timed:
         fam = max(timed, key=timed.get)
         durs = per[fam]
-        sizes = launch_bytes[fam]
+        sizes = lbytes[fam]
         if len(durs) == len(sizes) * args.steps:
             bytes_total = sum(sizes) * args.steps
             achieved = bytes_total / (sum(durs) * 1e-3) / 1e9
             roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(fam),
-                        "kernel": ROOFLINE_FAMILIES[fam][0], "family": fam,
+                        "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "traffic": measured_traffic(fam, families[fam][1], PB),
+                        "kernel": families[fam][0], "family": fam,
                         "launches": len(durs), "avg_launch_ms": round(sum(durs) / len(durs), 4),
                         "bytes_per_launch": round(bytes_total / len(durs)),
                         "share_of_profiled_step": round(sum(durs) / args.steps / ms_prof, 3)}
@@ -261,6 +287,7 @@ def main():
                                 "top-100 by sum desc" % fr.D) if not args.rows else "scaled custkey fragment",
                    "fact_rows": N, "mid_rows": M, "filtered_fact_rows": n_f, "join_rows": J, "groups": G,
                    "digit_bits": args.digit_bits, "key_bits": key_bits, "cust_bits": cust_bits,
+                   "revenue_bits": args.revenue_bits,
                    "plan": run.plan()},
         "roofline": roofline,
         "hbm_fraction_ref_model": round(bref / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),

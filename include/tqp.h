@@ -67,6 +67,7 @@ typedef enum { TQP_LT = 0, TQP_LE = 1, TQP_GT = 2, TQP_GE = 3, TQP_EQ = 4, TQP_N
 #define TQP_DEVERR_KEY_RANGE 1u   /* a key was negative or >= 2^key_bits */
 #define TQP_DEVERR_SPIN 2u        /* an inter-tile wait hit its safety bound */
 #define TQP_DEVERR_CAPACITY 4u    /* an output count exceeded its capacity */
+#define TQP_DEVERR_VALUE_RANGE 8u /* a value was outside its declared width (revenue_bits) */
 
 /* One column: device pointer to n contiguous values of `type`. */
 typedef struct {
@@ -242,6 +243,11 @@ typedef struct {
     int32_t cust_bits;        /* custkey < 2^cust_bits (0: 31) */
     int32_t k;                /* top rows wanted, 1..1024 */
     int64_t join_cap;         /* capacity for join rows (n_fact suffices when pks are unique) */
+    int32_t revenue_bits;     /* 0 or 64: revenue carried as int64.  32: the caller declares that
+                               * every kept row's price*(100-disc) lies in [0, 2^32); it is carried
+                               * in 4 bytes through the sorts and the join (sums stay exact int64).
+                               * A row outside sets TQP_DEVERR_VALUE_RANGE (results unspecified). */
+    int32_t reserved;
 } tqp_cust_fragment;
 
 typedef struct {

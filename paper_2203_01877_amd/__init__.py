@@ -22,12 +22,12 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import (DEVERR_CAPACITY, DEVERR_KEY_RANGE, DEVERR_SPIN, TQP_EQ, TQP_GE, TQP_GT, TQP_LE, TQP_LT,
-                   TQP_NE, TQPError, check)
+from ._lib import (DEVERR_CAPACITY, DEVERR_KEY_RANGE, DEVERR_SPIN, DEVERR_VALUE_RANGE, TQP_EQ, TQP_GE, TQP_GT,
+                   TQP_LE, TQP_LT, TQP_NE, TQPError, check)
 
 __all__ = ["Context", "filter", "sort", "join", "groupby_agg", "topk", "FlagsFragmentRunner",
            "CustFragmentRunner", "BatchRunner", "Server", "TQPError", "TQP_LT", "TQP_LE", "TQP_GT", "TQP_GE", "TQP_EQ", "TQP_NE",
-           "DEVERR_KEY_RANGE", "DEVERR_SPIN", "DEVERR_CAPACITY"]
+           "DEVERR_KEY_RANGE", "DEVERR_SPIN", "DEVERR_CAPACITY", "DEVERR_VALUE_RANGE"]
 
 _DTYPES = {torch.int8: _lib.TQP_I8, torch.int32: _lib.TQP_I32, torch.int64: _lib.TQP_I64}
 
@@ -225,7 +225,7 @@ class CustFragmentRunner:
     """Prepared custkey fragment (join to the mid table, group by custkey, top-k)."""
 
     def __init__(self, ctx: Context, fact: dict, mid: dict, D: int, k: int = 100, key_bits: int = 0,
-                 cust_bits: int = 0, gcap: int | None = None, join_cap: int | None = None):
+                 cust_bits: int = 0, gcap: int | None = None, join_cap: int | None = None, revenue_bits: int = 0):
         self.ctx = ctx
         dev = _dev(ctx)
         self.fact, self.mid = fact, mid
@@ -236,7 +236,7 @@ class CustFragmentRunner:
         self.k = k
         self.desc = _lib.CustFragment(fact["fk"].data_ptr(), fact["date"].data_ptr(), fact["price"].data_ptr(),
                                       fact["disc"].data_ptr(), n, mid["pk"].data_ptr(), mid["custkey"].data_ptr(),
-                                      m, D, key_bits, cust_bits, k, join_cap)
+                                      m, D, key_bits, cust_bits, k, join_cap, revenue_bits, 0)
         self.out = {"key": torch.empty(gcap, dtype=torch.int32, device=dev),
                     "sum": torch.empty(gcap, dtype=torch.int64, device=dev),
                     "cnt": torch.empty(gcap, dtype=torch.int64, device=dev),

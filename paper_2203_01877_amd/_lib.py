@@ -15,7 +15,7 @@ STATUS_NAMES = {0: "TQP_OK", 1: "TQP_ERR_INVALID", 2: "TQP_ERR_WORKSPACE", 3: "T
                 4: "TQP_ERR_HIP", 5: "TQP_ERR_UNSUPPORTED"}
 TQP_I8, TQP_I32, TQP_I64 = 1, 2, 3
 TQP_LT, TQP_LE, TQP_GT, TQP_GE, TQP_EQ, TQP_NE = range(6)
-DEVERR_KEY_RANGE, DEVERR_SPIN, DEVERR_CAPACITY = 1, 2, 4
+DEVERR_KEY_RANGE, DEVERR_SPIN, DEVERR_CAPACITY, DEVERR_VALUE_RANGE = 1, 2, 4, 8
 
 
 class ProfEntry(ctypes.Structure):
@@ -44,7 +44,8 @@ class FlagsOut(ctypes.Structure):
 class CustFragment(ctypes.Structure):
     _fields_ = [("fk", c_vp), ("date", c_vp), ("price", c_vp), ("disc", c_vp), ("n_fact", c_i64),
                 ("pk", c_vp), ("custkey", c_vp), ("n_mid", c_i64), ("D", c_i32), ("key_bits", c_i32),
-                ("cust_bits", c_i32), ("k", c_i32), ("join_cap", c_i64)]
+                ("cust_bits", c_i32), ("k", c_i32), ("join_cap", c_i64), ("revenue_bits", c_i32),
+                ("reserved", c_i32)]
 
 
 class CustOut(ctypes.Structure):

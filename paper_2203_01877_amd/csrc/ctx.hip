@@ -28,17 +28,8 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
 }
 
 __global__ void k_copy_u128(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n) {
-    constexpr int U = 4;       // 16-byte loads in flight per thread
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i + (U - 1) * stride < n; i += U * stride) {
-        uint4 v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = src[i + u * stride];
-#pragma unroll
-        for (int u = 0; u < U; ++u) dst[i + u * stride] = v[u];
-    }
-    for (; i < n; i += stride) dst[i] = src[i];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
 }
 
 __global__ void k_fill_u128(uint4* p, int64_t n) {

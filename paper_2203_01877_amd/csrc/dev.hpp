@@ -13,6 +13,7 @@ enum : uint32_t {
     FLAG_KEY_RANGE = 1u,      // a key had bits above the declared key width (or was negative)
     FLAG_SPIN_LIMIT = 2u,     // a look-back wait hit its bound (never expected)
     FLAG_CAPACITY = 4u,       // an output count exceeded the caller's capacity
+    FLAG_VALUE_RANGE = 8u,    // a value was outside its declared width
 };
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }

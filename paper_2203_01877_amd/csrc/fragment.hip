@@ -1,6 +1,7 @@
 // Whole fragments: filter -> sort-based join -> group-by in one launch
 // sequence, every intermediate in the workspace, no host synchronisation.
 #include <cmath>
+#include <type_traits>
 
 #include "fragment.hpp"
 
@@ -17,6 +18,8 @@ int bucket_low_bits(int cb, int rb) {
     return lowb;
 }
 constexpr int BUCKET_SMALL_LOWB = 9;
+// profile tags of the custkey fragment's three sorts
+constexpr int SORT_TAG_FACT = 1, SORT_TAG_MID = 2, SORT_TAG_GROUP = 3;
 
 // Low key bits the fact sort may leave out.  A join tile of TILE left rows
 // over keys spread evenly on [0, 2^kb) spans about TILE * 2^kb / n key values
@@ -111,8 +114,8 @@ tqp_status check_flags(const tqp_flags_fragment* f, const tqp_flags_out* o) {
     return TQP_OK;
 }
 
-template <class Cfg>
-void cust_reserve(Arena& a, const tqp_cust_fragment& f, const tqp_cust_out& o, CustBufs<Cfg>& b) {
+template <class Cfg, class VT>
+void cust_reserve(Arena& a, const tqp_cust_fragment& f, const tqp_cust_out& o, CustBufs<Cfg, VT>& b) {
     const int kb = norm_key_bits(f.key_bits);
     const int cb = norm_key_bits(f.cust_bits);
     // The join needs the fact keys sorted only on their bits above fact_lowb
@@ -120,7 +123,7 @@ void cust_reserve(Arena& a, const tqp_cust_fragment& f, const tqp_cust_out& o, C
     // never sorted.
     b.fact_lowb = fact_low_bits(f.n_fact, kb, Cfg::RADIX_BITS);
     if (b.fact_lowb > FINISH_LOG2) b.fact_lowb = FINISH_LOG2;      // the mid finishing pass covers at most this
-    b.fact = radix_reserve<Cfg, uint64_t>(a, f.n_fact, kb, b.fact_lowb);
+    b.fact = radix_reserve<Cfg, VT>(a, f.n_fact, kb, b.fact_lowb);
     // the mid keys: radix passes over the same high bits, then one finishing
     // pass sorts each span of 8192 keys in LDS (the join's binary-search
     // fallback needs them fully sorted)
@@ -136,23 +139,23 @@ void cust_reserve(Arena& a, const tqp_cust_fragment& f, const tqp_cust_out& o, C
     // bucket-aggregation block per value of those bits
     b.lowb = bucket_low_bits(cb, Cfg::RADIX_BITS);
     b.nbuckets = int64_t(1) << (cb - b.lowb);
-    b.grp = radix_reserve<Cfg, uint64_t>(a, f.join_cap, cb, b.lowb);
+    b.grp = radix_reserve<Cfg, VT>(a, f.join_cap, cb, b.lowb);
     b.sstatus = a.zero<uint64_t>(b.nbuckets);
     b.bstarts = a.scratch<int64_t>(b.nbuckets + 1);
     b.scounter = a.zero<uint32_t>(1);
     b.fkeys = a.scratch<uint32_t>(f.n_fact);
-    b.fvals = a.scratch<uint64_t>(f.n_fact);
+    b.fvals = a.scratch<VT>(f.n_fact);
     b.mkeys = a.scratch<uint32_t>(f.n_mid);
     b.mvals = a.scratch<uint32_t>(f.n_mid);
     b.gkeys_in = a.scratch<uint32_t>(f.join_cap);
-    b.gvals_in = a.scratch<uint64_t>(f.join_cap);
+    b.gvals_in = a.scratch<VT>(f.join_cap);
     b.gkeys = a.scratch<uint32_t>(f.join_cap);
-    b.gvals = a.scratch<uint64_t>(f.join_cap);
+    b.gvals = a.scratch<VT>(f.join_cap);
     b.topk = topk_reserve(a, o.gcap, f.k);
 }
 
-template <class Cfg>
-tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_out& o, const CustBufs<Cfg>& b,
+template <class Cfg, class VT>
+tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_out& o, const CustBufs<Cfg, VT>& b,
                        hipStream_t s) {
     const int kb = norm_key_bits(f.key_bits);
     const int cb = norm_key_bits(f.cust_bits);
@@ -161,8 +164,9 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
     // is sorted on s
     if ((st = side_fork(ctx, s)) != TQP_OK) return st;
     SrcKeyCol msrc{f.pk, f.custkey, f.n_mid};
-    if ((st = radix_launch<Cfg, uint32_t>(b.mid, msrc, f.n_mid, true, nullptr, key_mask_for(kb), b.mkeys,
-                                          b.mvals, ctx, ctx->side)) != TQP_OK)
+    if ((st = radix_launch<Cfg, uint32_t, SORT_TAG_MID>(b.mid, msrc, f.n_mid, true, nullptr, key_mask_for(kb),
+                                                        b.mkeys, b.mvals, ctx, ctx->side, "mid_pass_first",
+                                                        "mid_pass")) != TQP_OK)
         return st;
     const uint32_t* mk = b.mkeys;
     const uint32_t* mv = b.mvals;
@@ -177,14 +181,15 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
     }
     // fact side: date < D fused into the sort; the payload is the revenue
     // price * (100 - disc), evaluated while the row is read
-    SrcFilterRevenue fsrc{f.fk, f.date, f.price, f.disc, CMP_LT, f.D, f.n_fact};
-    if ((st = radix_launch<Cfg, uint64_t>(b.fact, fsrc, f.n_fact, true, nullptr, key_mask_for(kb), b.fkeys,
-                                          b.fvals, ctx, s)) != TQP_OK)
+    SrcFilterRevenue<VT> fsrc{f.fk, f.date, f.price, f.disc, CMP_LT, f.D, f.n_fact};
+    if ((st = radix_launch<Cfg, VT, SORT_TAG_FACT>(b.fact, fsrc, f.n_fact, true, nullptr, key_mask_for(kb),
+                                                   b.fkeys, b.fvals, ctx, s, "fact_pass_fused", "fact_pass")) !=
+        TQP_OK)
         return st;
 
     if ((st = side_join(ctx, s)) != TQP_OK) return st;
     // join: emits (custkey, revenue)
-    using Emit = EmitKeyVal<JCfgFrag::BLOCK, Cfg::RADIX_BITS>;
+    using Emit = EmitKeyVal<JCfgFrag::BLOCK, Cfg::RADIX_BITS, VT>;
     Emit e{};
     e.out_key = b.gkeys_in;
     e.out_val = b.gvals_in;
@@ -197,15 +202,16 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
         e.shift[p] = b.grp.pd.shift[p];
         e.bits[p] = b.grp.pd.bits[p];
     }
-    if ((st = join_launch<JCfgFrag, uint64_t, uint32_t>(ctx, s, "join_keyval", b.join, b.fkeys, b.fvals, f.n_fact,
-                                                        b.fact.d_cnt, mk, mv, f.n_mid, (const int64_t*)nullptr,
-                                                        b.d_join, f.join_cap, e, b.fact_lowb, o.d_join)) != TQP_OK)
+    if ((st = join_launch<JCfgFrag, VT, uint32_t>(ctx, s, "join_keyval", b.join, b.fkeys, b.fvals, f.n_fact,
+                                                  b.fact.d_cnt, mk, mv, f.n_mid, (const int64_t*)nullptr, b.d_join,
+                                                  f.join_cap, e, b.fact_lowb, o.d_join)) != TQP_OK)
         return st;
     // group-by: sort (custkey, revenue) on the custkey bits above lowb (the
     // histogram came from the join), then aggregate each bucket
-    SrcPairs<uint64_t> gsrc{b.gkeys_in, b.gvals_in, f.join_cap, b.d_join};
-    if ((st = radix_launch<Cfg, uint64_t>(b.grp, gsrc, f.join_cap, false, b.d_join, key_mask_for(cb), b.gkeys,
-                                          b.gvals, ctx, s)) != TQP_OK)
+    SrcPairs<VT> gsrc{b.gkeys_in, b.gvals_in, f.join_cap, b.d_join};
+    if ((st = radix_launch<Cfg, VT, SORT_TAG_GROUP>(b.grp, gsrc, f.join_cap, false, b.d_join, key_mask_for(cb),
+                                                    b.gkeys, b.gvals, ctx, s, "group_pass", "group_pass")) !=
+        TQP_OK)
         return st;
     SegOut so{o.key, o.sum, o.cnt, nullptr, o.gcap, o.d_ngroups};
     // bucket starts: with one group pass the buckets are its digits, so the
@@ -216,14 +222,16 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
                    k_bucket_bounds<<<grid_for(b.nbuckets + 1, 256, 0), 256, 0, s>>>(b.gkeys, f.join_cap, b.d_join,
                                                                                       b.lowb, b.nbuckets, b.bstarts));
     }
-    const int64_t* gv = reinterpret_cast<const int64_t*>(b.gvals);
+    // the aggregation reads int64 values, or 32-bit values known to be in [0, 2^32)
+    using AV = typename std::conditional<sizeof(VT) == 8, int64_t, uint32_t>::type;
+    const AV* gv = reinterpret_cast<const AV*>(b.gvals);
     if (b.lowb <= BUCKET_SMALL_LOWB) {
         TQP_LAUNCH(ctx, s, "bucket_agg",
-                   (k_bucket_agg<256, 1 << BUCKET_SMALL_LOWB><<<(unsigned)b.nbuckets, 256, 0, s>>>(
+                   (k_bucket_agg<256, 1 << BUCKET_SMALL_LOWB, AV><<<(unsigned)b.nbuckets, 256, 0, s>>>(
                        b.gkeys, gv, b.bstarts, bhist, b.lowb, b.nbuckets, b.sstatus, b.scounter, so, ctx->d_err)));
     } else {
         TQP_LAUNCH(ctx, s, "bucket_agg",
-                   (k_bucket_agg<1024, 1 << BUCKET_LOWB_MAX><<<(unsigned)b.nbuckets, 1024, 0, s>>>(
+                   (k_bucket_agg<1024, 1 << BUCKET_LOWB_MAX, AV><<<(unsigned)b.nbuckets, 1024, 0, s>>>(
                        b.gkeys, gv, b.bstarts, bhist, b.lowb, b.nbuckets, b.sstatus, b.scounter, so, ctx->d_err)));
     }
     // ORDER BY sum DESC, custkey ASC LIMIT k
@@ -239,6 +247,8 @@ tqp_status check_cust(const tqp_cust_fragment* f, const tqp_cust_out* o) {
     if (f->n_fact > MAX_ELEMS || f->n_mid > MAX_ELEMS || f->join_cap > MAX_ELEMS || o->gcap > MAX_ELEMS)
         return fail(TQP_ERR_UNSUPPORTED, "fragment too large");
     if (f->k < 1 || f->k > 1024) return fail(TQP_ERR_UNSUPPORTED, "k = %d", f->k);
+    if (f->revenue_bits != 0 && f->revenue_bits != 32 && f->revenue_bits != 64)
+        return fail(TQP_ERR_UNSUPPORTED, "revenue_bits = %d (0, 32 or 64)", f->revenue_bits);
     if ((f->n_fact && (!f->fk || !f->date || !f->price || !f->disc)) || (f->n_mid && (!f->pk || !f->custkey)))
         return fail(TQP_ERR_INVALID, "null column");
     if (!o->key || !o->sum || !o->cnt || !o->d_ngroups || !o->top_key || !o->top_sum || !o->top_cnt || !o->d_topk)
@@ -277,9 +287,9 @@ tqp_status tqp_fragment_cust_plan(tqp_ctx* ctx, const tqp_cust_fragment* f, int*
     return with_radix_cfg(ctx->digit_bits, [&](auto cfg) -> tqp_status {
         using Cfg = decltype(cfg);
         tqp_cust_out o{};
-        CustBufs<Cfg> b;
+        CustBufs<Cfg, uint64_t> b;
         Arena a;
-        cust_reserve<Cfg>(a, *f, o, b);
+        cust_reserve<Cfg, uint64_t>(a, *f, o, b);
         if (fact_passes) *fact_passes = b.fact.pd.npass;
         if (fact_lowb) *fact_lowb = b.fact_lowb;
         if (mid_passes) *mid_passes = b.mid.pd.npass;
@@ -297,13 +307,17 @@ tqp_status tqp_fragment_cust(tqp_ctx* ctx, const tqp_cust_fragment* f, const tqp
     if (st != TQP_OK) return st;
     return with_radix_cfg(ctx->digit_bits, [&](auto cfg) -> tqp_status {
         using Cfg = decltype(cfg);
-        CustBufs<Cfg> b;
-        Arena a;
-        auto plan = [&](Arena& ar) { cust_reserve<Cfg>(ar, *f, *o, b); };
-        tqp_status s2 = with_workspace(ctx, ws, ws_bytes, stream, plan, a);
-        if (s2 != TQP_OK || !ws) return s2;
-        if ((s2 = fill_zero(a.base, a.zsize, stream, ctx)) != TQP_OK) return s2;
-        return cust_launch<Cfg>(ctx, *f, *o, b, stream);
+        auto run = [&](auto vt) -> tqp_status {
+            using VT = decltype(vt);
+            CustBufs<Cfg, VT> b;
+            Arena a;
+            auto plan = [&](Arena& ar) { cust_reserve<Cfg, VT>(ar, *f, *o, b); };
+            tqp_status s2 = with_workspace(ctx, ws, ws_bytes, stream, plan, a);
+            if (s2 != TQP_OK || !ws) return s2;
+            if ((s2 = fill_zero(a.base, a.zsize, stream, ctx)) != TQP_OK) return s2;
+            return cust_launch<Cfg, VT>(ctx, *f, *o, b, stream);
+        };
+        return f->revenue_bits == 32 ? run(uint32_t{}) : run(uint64_t{});
     });
 }
 

@@ -92,12 +92,13 @@ tqp_status topk_launch(const TopkBufs& t, const int32_t* key, const int64_t* sum
                        const int64_t* d_n, int k, int32_t* out_key, int64_t* out_sum, int64_t* out_cnt,
                        int32_t* d_k, hipStream_t s, tqp_ctx* ctx);
 
-template <class Cfg>
+template <class Cfg, class VT>
 struct CustBufs {
-    RadixBufs<Cfg, uint64_t> fact;
+    // VT: the revenue payload, uint64_t (int64 bits) or uint32_t (declared 32-bit revenue)
+    RadixBufs<Cfg, VT> fact;
     int fact_lowb = 0;         // fact key bits left unsorted (the join resolves them)
     RadixBufs<Cfg, uint32_t> mid;
-    RadixBufs<Cfg, uint64_t> grp;
+    RadixBufs<Cfg, VT> grp;
     int lowb = 0;              // group-key bits resolved in LDS by the bucket kernel
     int64_t nbuckets = 0;
     int64_t* bstarts = nullptr;    // start of every bucket, nbuckets + 1
@@ -108,7 +109,7 @@ struct CustBufs {
     uint32_t *fkeys = nullptr, *mkeys = nullptr, *mvals = nullptr, *gkeys_in = nullptr, *gkeys = nullptr;
     uint32_t *mkeys_full = nullptr, *mvals_full = nullptr;   // mid after the finishing pass (fact_lowb > 0)
     int64_t nspans = 0;                                       // 4096-key spans of the finishing pass
-    uint64_t *fvals = nullptr, *gvals_in = nullptr, *gvals = nullptr;
+    VT *fvals = nullptr, *gvals_in = nullptr, *gvals = nullptr;
     TopkBufs topk;
 };
 

@@ -186,10 +186,13 @@ RadixBufs<Cfg, V> radix_reserve(Arena& a, int64_t n_upper, int key_bits, int ski
 // Histogram (unless the caller accumulated it already) and one pass kernel per
 // digit.  Pass 0 reads src0; later passes read the previous pass's output,
 // bounded by the count of elements that took part (*count_src).
-template <class Cfg, class V, class Src0>
+// first_label / pass_label (string literals, optional) name the first and the
+// later pass kernels in the per-launch profile.
+template <class Cfg, class V, int Tag = 0, class Src0>
 tqp_status radix_launch(const RadixBufs<Cfg, V>& b, const Src0& src0, int64_t n_upper, bool run_hist,
                         const int64_t* count_src, uint32_t key_mask, uint32_t* keys_out, V* vals_out,
-                        tqp_ctx* ctx, hipStream_t s) {
+                        tqp_ctx* ctx, hipStream_t s, const char* first_label = nullptr,
+                        const char* pass_label = nullptr) {
     const int np = b.pd.npass;
     const int64_t tiles = b.ntiles;
     if (tiles == 0) return TQP_OK;
@@ -204,6 +207,8 @@ tqp_status radix_launch(const RadixBufs<Cfg, V>& b, const Src0& src0, int64_t n_
     const char* pairs_name = VB == 8 ? "radix_pass_pairs_v8" : VB == 4 ? "radix_pass_pairs_v4" : "radix_pass_pairs_v0";
     const char* first_name = std::is_same<Src0, SrcPairs<V>>::value ? pairs_name
                              : VB == 8 ? "radix_pass_fused_v8" : VB == 4 ? "radix_pass_fused_v4" : "radix_pass_fused_v0";
+    if (pass_label) pairs_name = pass_label;
+    if (first_label) first_name = first_label;
     const uint32_t* in_k = nullptr;
     const V* in_v = nullptr;
     for (int p = 0; p < np; ++p) {
@@ -214,13 +219,13 @@ tqp_status radix_launch(const RadixBufs<Cfg, V>& b, const Src0& src0, int64_t n_
         uint32_t* st = b.status + (int64_t)p * tiles * Cfg::RADIX;
         if (p == 0) {
             TQP_LAUNCH(ctx, s, first_name,
-                       k_radix_pass<Cfg, Src0, V><<<(unsigned)tiles, Cfg::BLOCK, 0, s>>>(
+                       k_radix_pass<Cfg, Src0, V, Tag><<<(unsigned)tiles, Cfg::BLOCK, 0, s>>>(
                            src0, dst, b.pd.shift[p], b.pd.bits[p], b.hist + p * Cfg::RADIX, st, b.counters + p,
                            ctx->d_err));
         } else {
             SrcPairs<V> src{in_k, in_v, n_upper, count_src};
             TQP_LAUNCH(ctx, s, pairs_name,
-                       k_radix_pass<Cfg, SrcPairs<V>, V><<<(unsigned)tiles, Cfg::BLOCK, 0, s>>>(
+                       k_radix_pass<Cfg, SrcPairs<V>, V, Tag><<<(unsigned)tiles, Cfg::BLOCK, 0, s>>>(
                            src, dst, b.pd.shift[p], b.pd.bits[p], b.hist + p * Cfg::RADIX, st, b.counters + p,
                            ctx->d_err));
         }

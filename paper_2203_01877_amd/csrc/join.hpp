@@ -63,15 +63,15 @@ struct EmitPairs {
     __device__ void finish(Smem&) {}
 };
 
-// (group key from the right side, 64-bit value from the left side), with the
+// (group key from the right side, value V from the left side), with the
 // digit histograms of the following group-key sort accumulated on the way.
-template <int BLOCK, int RB>
+template <int BLOCK, int RB, class V = uint64_t>
 struct EmitKeyVal {
     static constexpr bool ORDERED = true;
     static constexpr int R = 1 << RB;
     static constexpr int NP = (32 + RB - 1) / RB;
     uint32_t* out_key;
-    uint64_t* out_val;
+    V* out_val;
     int64_t cap;
     uint32_t key_mask;         // group keys must fit the declared width
     uint32_t* flags;

@@ -129,8 +129,13 @@ struct SrcFilterRowid {
 };
 
 // fact key + date filter, payload = price * (100 - disc) computed on the fly
-// (the revenue expression evaluated before the join instead of after it).
+// (the revenue expression evaluated before the join instead of after it),
+// carried as VT: uint64_t (the int64 value), or uint32_t when the caller
+// declares that every kept row's revenue lies in [0, 2^32) (a kept row
+// outside is reported through the pass's value-range flag).
+template <class VT>
 struct SrcFilterRevenue {
+    static constexpr bool CHECKS = sizeof(VT) < 8;
     const int32_t* key;
     const int32_t* date;
     const int64_t* price;
@@ -145,14 +150,29 @@ struct SrcFilterRevenue {
     }
     // price and disc are read with the key and date, whatever the predicate
     // says, so a row costs one memory round trip instead of two (the rows the
-    // filter drops cost their 16 bytes).
-    __device__ bool load(int64_t i, uint32_t& kk, uint64_t& v) const {
+    // filter drops cost their 16 bytes).  bad collects kept rows whose value
+    // does not fit VT.
+    __device__ bool load(int64_t i, uint32_t& kk, VT& v, uint32_t& bad) const {
         kk = (uint32_t)key[i];
         const int64_t p = price[i], d = disc[i];
-        v = (uint64_t)(p * (100 - d));
-        return cmp_eval((int64_t)date[i], op, k);
+        const int64_t rev = p * (100 - d);
+        v = (VT)rev;
+        const bool ok = cmp_eval((int64_t)date[i], op, k);
+        if constexpr (CHECKS) bad |= (uint32_t)ok & (uint32_t)((uint64_t)rev >> 32 != 0);
+        return ok;
+    }
+    __device__ bool load(int64_t i, uint32_t& kk, VT& v) const {
+        uint32_t unused = 0;
+        return load(i, kk, v, unused);
     }
 };
+
+// Sources with CHECKS = true take a fourth load argument that collects values
+// outside their declared width.
+template <class S, class = void>
+struct SrcChecks : std::false_type {};
+template <class S>
+struct SrcChecks<S, std::void_t<decltype(S::CHECKS)>> : std::integral_constant<bool, S::CHECKS> {};
 
 // key column + int32 payload column, no filter (the mid table side).
 struct SrcKeyCol {
@@ -350,11 +370,18 @@ __device__ __forceinline__ void radix_pass_tile(const Src& src, const DstPairs<V
     V val[ITEMS];
     uint32_t pos[ITEMS];
     bool valid[ITEMS];
+    uint32_t bad = 0;
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const int64_t i = base + j * WAVE + l;
         const bool in = i < n;
-        valid[j] = src.load(in ? i : n - 1, key[j], val[j]) && in;   // n >= 1: the tile exists
+        if constexpr (SrcChecks<Src>::value)
+            valid[j] = src.load(in ? i : n - 1, key[j], val[j], bad) && in;   // n >= 1: the tile exists
+        else
+            valid[j] = src.load(in ? i : n - 1, key[j], val[j]) && in;
+    }
+    if constexpr (SrcChecks<Src>::value) {
+        if (bad) set_flag(flags, FLAG_VALUE_RANGE);
     }
 
     // Rank: peers with the same digit found by one ballot per digit bit; the
@@ -451,7 +478,9 @@ __device__ __forceinline__ void radix_pass_tile(const Src& src, const DstPairs<V
     }
 }
 
-template <class Cfg, class Src, class V>
+// Tag only separates the launches of different sorts in a profile (the
+// kernel symbol carries it); it changes nothing in the code.
+template <class Cfg, class Src, class V, int Tag = 0>
 __global__ void __launch_bounds__(Cfg::BLOCK)
 k_radix_pass(Src src, DstPairs<V> dst, int shift, int bits, const uint32_t* hist,
              uint32_t* status, uint32_t* tile_counter, uint32_t* flags) {

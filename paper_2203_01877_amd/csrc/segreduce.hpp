@@ -193,9 +193,10 @@ constexpr int BUCKET_LOWB_MAX = 13;        // 8192 slots: 96 KB of LDS
 __global__ void k_bucket_bounds(const uint32_t* keys, int64_t n_upper, const int64_t* d_n, int lowb,
                                 int64_t nbuckets, int64_t* starts);
 
-template <int BLOCK, int SLOTS>
+// vals: int64 values (VT = int64_t) or values in [0, 2^32) (VT = uint32_t).
+template <int BLOCK, int SLOTS, class VT = int64_t>
 __global__ void __launch_bounds__(BLOCK)
-k_bucket_agg(const uint32_t* keys, const int64_t* vals, const int64_t* starts, const uint32_t* bhist, int lowb,
+k_bucket_agg(const uint32_t* keys, const VT* vals, const int64_t* starts, const uint32_t* bhist, int lowb,
              int64_t nbuckets, uint64_t* status, uint32_t* counter, SegOut out, uint32_t* flags) {
     static_assert(SLOTS <= (1 << BUCKET_LOWB_MAX), "slot table larger than the LDS budget");
     constexpr int U = 8;                               // loads in flight per thread
@@ -232,7 +233,7 @@ k_bucket_agg(const uint32_t* keys, const int64_t* vals, const int64_t* starts, c
     const uint32_t lmask = (uint32_t)slots - 1;
     for (int64_t i0 = lo + tid; i0 < hi; i0 += (int64_t)BLOCK * U) {
         uint32_t k[U];
-        int64_t v[U];
+        VT v[U];
 #pragma unroll
         for (int j = 0; j < U; ++j) {          // clamped index: no branch between the loads
             const int64_t i = i0 + (int64_t)j * BLOCK;

@@ -56,7 +56,7 @@ def test_binding_struct_layouts_match_header():
     assert ctypes.sizeof(L.Column) == 16 and ctypes.sizeof(L.Pred) == 16
     assert ctypes.sizeof(L.FlagsFragment) == 6 * 8 + 8 + 8 + 2 * 8 + 8 + 4 * 4
     assert ctypes.sizeof(L.FlagsOut) == 6 * 8
-    assert ctypes.sizeof(L.CustFragment) == 4 * 8 + 8 + 2 * 8 + 8 + 4 * 4 + 8
+    assert ctypes.sizeof(L.CustFragment) == 4 * 8 + 8 + 2 * 8 + 8 + 4 * 4 + 8 + 2 * 4
     assert ctypes.sizeof(L.CustOut) == 3 * 8 + 8 + 6 * 8
 
 

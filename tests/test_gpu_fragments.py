@@ -82,7 +82,7 @@ def test_flags_row_range(hip, ctx):
     _assert_flags(r.result(), oracle.fragment_flags(sub, fr.dim, fr.D, fr.c))
 
 
-def _cust(hip, ctx, fr, digit_bits=8, cust_bits=None, join_cap=None):
+def _cust(hip, ctx, fr, digit_bits=8, cust_bits=None, join_cap=None, revenue_bits=0):
     fact = hip.to_device({k: fr.fact[k] for k in ("fk", "date", "price", "disc")})
     mid = hip.to_device(fr.mid)
     kb = datagen.bits_for(max(int(fr.fact["fk"].max(initial=0)), int(fr.mid["pk"].max(initial=0))) + 1)
@@ -90,7 +90,8 @@ def _cust(hip, ctx, fr, digit_bits=8, cust_bits=None, join_cap=None):
     ctx.set_digit_bits(digit_bits)
     try:
         r = hip.CustFragmentRunner(ctx, fact, mid, fr.D, fr.k, key_bits=kb, cust_bits=cb,
-                                   gcap=min(len(fr.fact["fk"]) or 1, fr.cust_hi), join_cap=join_cap)
+                                   gcap=min(len(fr.fact["fk"]) or 1, fr.cust_hi), join_cap=join_cap,
+                                   revenue_bits=revenue_bits)
         r.run()
         return r.result()
     finally:
@@ -106,16 +107,49 @@ def _assert_cust(got, want):
     assert np.array_equal(got["top_sum"], want["top_sum"]) and np.array_equal(got["top_cnt"], want["top_cnt"])
 
 
+@pytest.mark.parametrize("revenue_bits", [64, 32])
 @pytest.mark.parametrize("digit_bits", [4, 8, 11])
 @pytest.mark.parametrize("n,m,cust", [(1, 5, 3), (50_000, 10_000, 2_000), (400_000, 100_000, 30_000),
                                       (300_007, 80_000, 1), (1_500_000, 400_000, (1 << 20) + 7)])
-def test_cust_small(hip, ctx, digit_bits, n, m, cust):
+def test_cust_small(hip, ctx, digit_bits, n, m, cust, revenue_bits):
     """Custkey domains from one value to 2^21 (8192-slot buckets: one group
-    pass at 8- and 11-bit digits, two at 4-bit digits)."""
+    pass at 8- and 11-bit digits, two at 4-bit digits), with the revenue
+    carried in 64 or 32 bits (sums are int64 either way)."""
     fr = datagen.config2(seed=300 + n, n=n, m=m, cust_hi=cust)
     want = oracle.fragment_cust(fr.fact, fr.mid, fr.D, fr.k, gcap=min(n, cust))
-    _assert_cust(_cust(hip, ctx, fr, digit_bits), want)
+    _assert_cust(_cust(hip, ctx, fr, digit_bits, revenue_bits=revenue_bits), want)
     assert ctx.errors() == 0
+
+
+@pytest.mark.parametrize("digit_bits", [4, 8])
+def test_cust_revenue_width(hip, ctx, digit_bits):
+    """A kept row whose revenue needs more than 32 bits sets the value-range
+    flag under revenue_bits=32; the same rows behind the filter do not, and
+    the 64-bit path sums them exactly."""
+    fr = datagen.config2(seed=91, n=200_000, m=50_000, cust_hi=5_000)
+    price = fr.fact["price"].copy()
+    price[::997] = 60_000_000_000          # revenue 6e12 > 2^32 - 1
+    big = dataclasses.replace(fr, fact=dict(fr.fact, price=price))
+    want = oracle.fragment_cust(big.fact, big.mid, big.D, big.k, gcap=big.cust_hi)
+    assert int(want["sum"].max()) >= 1 << 32
+    ctx.errors()
+    _assert_cust(_cust(hip, ctx, big, digit_bits, revenue_bits=64), want)
+    assert ctx.errors() == 0
+    _cust(hip, ctx, big, digit_bits, revenue_bits=32)
+    assert ctx.errors() & hip.DEVERR_VALUE_RANGE
+    # the same prices only on rows the filter drops: no flag, exact result
+    date = fr.fact["date"].copy()
+    date[::997] = fr.D
+    hidden = dataclasses.replace(big, fact=dict(big.fact, date=date))
+    want = oracle.fragment_cust(hidden.fact, hidden.mid, hidden.D, hidden.k, gcap=hidden.cust_hi)
+    _assert_cust(_cust(hip, ctx, hidden, digit_bits, revenue_bits=32), want)
+    assert ctx.errors() == 0
+
+
+def test_cust_revenue_bits_rejected(hip, ctx):
+    fr = datagen.config2(seed=5, n=1000, m=300, cust_hi=100)
+    with pytest.raises(hip.TQPError):
+        _cust(hip, ctx, fr, revenue_bits=16)
 
 
 @pytest.mark.parametrize("digit_bits", [4, 8, 11])
@@ -139,11 +173,13 @@ def test_cust_partial_mid(hip, ctx, digit_bits, shape):
 
 @pytest.mark.timeout(600)
 def test_config2_full(hip, ctx):
-    """The 60M-row workload the benchmark times, every group compared."""
+    """The 60M-row workload the benchmark times (revenue carried in 32 bits),
+    and the same with 64-bit revenue, every group compared."""
     fr = datagen.config2()
     want = oracle.fragment_cust(fr.fact, fr.mid, fr.D, fr.k, gcap=fr.cust_hi)
-    got = _cust(hip, ctx, fr)
-    _assert_cust(got, want)
+    for revenue_bits in (32, 64):
+        got = _cust(hip, ctx, fr, revenue_bits=revenue_bits)
+        _assert_cust(got, want)
+        assert ctx.errors() == 0
     # statistical sanity of the recipe (not parity): 4 of 5 fact keys match, 93.86% pass the date filter
     assert abs(got["join_rows"] / 60e6 - 0.8 * 2400 / 2557) < 0.002
-    assert ctx.errors() == 0
