@@ -77,11 +77,12 @@ def roofline_families(PB):
     be used."""
     v = "u64" if PB == 8 else "u32"
     a = "long" if PB == 8 else "u32"
+    cfg = "RadixCfg<8,512,%d,8,16>" % (12 if PB == 8 else 16)      # 8-bit digits, 512 threads x 12 or 16 items
     radix = ("radix.hpp", "dev.hpp", "host.hpp")
     return {
-        "fact_pass_fused": ("k_radix_pass<RadixCfg<8,512,12,8>, SrcFilterRevenue<%s>, %s, 1>" % (v, v), radix),
-        "fact_pass": ("k_radix_pass<RadixCfg<8,512,12,8>, SrcPairs<%s>, %s, 1>" % (v, v), radix),
-        "group_pass": ("k_radix_pass<RadixCfg<8,512,12,8>, SrcPairs<%s>, %s, 3>" % (v, v), radix),
+        "fact_pass_fused": ("k_radix_pass<%s, SrcFilterRevenue<%s>, %s, 1>" % (cfg, v, v), radix),
+        "fact_pass": ("k_radix_pass<%s, SrcPairs<%s>, %s, 1>" % (cfg, v, v), radix),
+        "group_pass": ("k_radix_pass<%s, SrcPairs<%s>, %s, 3>" % (cfg, v, v), radix),
         "join_keyval": ("k_join<JoinCfg<256,8,2048>, %s, u32, EmitKeyVal<256,8,%s>>" % (v, v),
                         ("join.hpp", "dev.hpp", "fragment.hpp")),
         "bucket_agg": ("k_bucket_agg<1024,8192,%s>" % a, ("segreduce.hpp", "dev.hpp")),

@@ -238,10 +238,11 @@ k_batch_join(const BatchSeg* segs, const BatchFrag* frags, int nfrag, const int6
             e.disc = fr.disc;
             e.flagA = fr.flagA;
             e.flagB = fr.flagB;
-            join_tile<Cfg, uint32_t, uint32_t, Emit>(L.bk[(L.npass - 1) & 1], L.bv[(L.npass - 1) & 1], nl,
-                                                     R.bk[(R.npass - 1) & 1], (const uint32_t*)nullptr,
-                                                     fr.win[2 * tile], fr.win[2 * tile + 1], tile, 0, fr.d_join, e,
-                                                     esm, sm);
+            const uint32_t* lk = L.bk[(L.npass - 1) & 1];
+            join_tile<Cfg, uint32_t, uint32_t, Emit>(lk, L.bv[(L.npass - 1) & 1], nl, R.bk[(R.npass - 1) & 1],
+                                                     (const uint32_t*)nullptr,
+                                                     tile_geo(lk, nl, fr.win, tile, Cfg::TILE), tile, 0, fr.d_join,
+                                                     e, esm, sm);
             e.flush(esm, fr.acc);
         }
         __syncthreads();

@@ -88,7 +88,7 @@ __global__ void k_join_windows(const uint32_t* lkey, int64_t nl_upper, const int
     const int64_t i0 = t * tile_size;
     const int64_t i1 = (i0 + tile_size < nl ? i0 + tile_size : nl) - 1;
     uint32_t kmin, kmax;
-    tile_key_range(lkey, i0, i1, lowb, kmin, kmax);
+    tile_key_range(TileGeo{0, 0, lkey[i0], lkey[i1]}, lowb, kmin, kmax);
     const int64_t lo = lower_bound_glb(rkey, 0, nr, kmin);
     win[2 * t] = lo;
     win[2 * t + 1] = upper_bound_glb(rkey, lo, nr, kmax);
@@ -101,6 +101,21 @@ __global__ void k_bucket_bounds(const uint32_t* keys, int64_t n_upper, const int
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b > nbuckets) return;
     starts[b] = b == nbuckets ? n : lower_bound_glb(keys, 0, n, (uint32_t)(b << lowb));
+}
+
+__global__ void __launch_bounds__(CHUNK_SCAN_BLOCK)
+k_radix_chunk_scan(const uint32_t* ctot, int nchunks, const uint32_t* hist0, int R, uint32_t* cbase) {
+    __shared__ uint32_t scratch[CHUNK_SCAN_BLOCK / WAVE];
+    const int d = blockIdx.x;
+    const int c = threadIdx.x;
+    uint32_t below = 0;
+    for (int i = threadIdx.x; i < d; i += CHUNK_SCAN_BLOCK) below += hist0[i];
+    uint32_t base;
+    block_excl_sum<CHUNK_SCAN_BLOCK>(below, scratch, &base);
+    const uint32_t v = c < nchunks ? ctot[(int64_t)c * R + d] : 0;
+    uint32_t tot;
+    const uint32_t excl = block_excl_sum<CHUNK_SCAN_BLOCK>(v, scratch, &tot);
+    if (c < nchunks) cbase[(int64_t)c * R + d] = base + excl;
 }
 
 __global__ void __launch_bounds__(FINISH_BLOCK)

@@ -123,7 +123,9 @@ void cust_reserve(Arena& a, const tqp_cust_fragment& f, const tqp_cust_out& o, C
     // never sorted.
     b.fact_lowb = fact_low_bits(f.n_fact, kb, Cfg::RADIX_BITS);
     if (b.fact_lowb > FINISH_LOG2) b.fact_lowb = FINISH_LOG2;      // the mid finishing pass covers at most this
-    b.fact = radix_reserve<Cfg, VT>(a, f.n_fact, kb, b.fact_lowb);
+    // the fused first pass keeps its look-back: pre-counting it costs the
+    // histogram kernel more than the pass saves while the mid sort shares HBM
+    b.fact = radix_reserve<Cfg, VT>(a, f.n_fact, kb, b.fact_lowb, false);
     // the mid keys: radix passes over the same high bits, then one finishing
     // pass sorts each span of 8192 keys in LDS (the join's binary-search
     // fallback needs them fully sorted)
@@ -139,7 +141,7 @@ void cust_reserve(Arena& a, const tqp_cust_fragment& f, const tqp_cust_out& o, C
     // bucket-aggregation block per value of those bits
     b.lowb = bucket_low_bits(cb, Cfg::RADIX_BITS);
     b.nbuckets = int64_t(1) << (cb - b.lowb);
-    b.grp = radix_reserve<Cfg, VT>(a, f.join_cap, cb, b.lowb);
+    b.grp = radix_reserve<Cfg, VT>(a, f.join_cap, cb, b.lowb, false);
     b.sstatus = a.zero<uint64_t>(b.nbuckets);
     b.bstarts = a.scratch<int64_t>(b.nbuckets + 1);
     b.scounter = a.zero<uint32_t>(1);

@@ -157,23 +157,42 @@ struct RadixBufs {
     PassDesc pd{};
     int64_t ntiles = 0;
     uint32_t* hist = nullptr;       // npass * RADIX
-    uint32_t* status = nullptr;     // npass * ntiles * RADIX
+    uint32_t* status = nullptr;     // per look-back pass: ntiles * RADIX
     uint32_t* counters = nullptr;   // npass tile counters
+    // pre-counted first pass (when the histogram kernel runs): per tile and
+    // chunk counts, chunk bases
+    int64_t nchunks = 0;
+    int tpc = 0;
+    uint32_t* pre = nullptr;        // ntiles * RADIX
+    uint32_t* ctot = nullptr;       // nchunks * RADIX
+    uint32_t* cbase = nullptr;      // nchunks * RADIX
     int64_t* d_cnt = nullptr;       // elements that take part (from the histogram)
     uint32_t* ktmp = nullptr;
     V* vtmp = nullptr;
 };
 
 // skip_low: the lowest skip_low key bits are left unsorted (the passes cover
-// bits [skip_low, key_bits)).
-template <class Cfg, class V>
-RadixBufs<Cfg, V> radix_reserve(Arena& a, int64_t n_upper, int key_bits, int skip_low = 0) {
-    RadixBufs<Cfg, V> b;
+// bits [skip_low, key_bits)).  counted: the caller launches with the
+// histogram kernel, whose tile counts spare the first pass its look-back
+// (false when the histogram comes from elsewhere).
+template <class Cfg0, class V>
+RadixBufs<Cfg0, V> radix_reserve(Arena& a, int64_t n_upper, int key_bits, int skip_low = 0, bool counted = true) {
+    using Cfg = typename Cfg0::template ForVal<V>;
+    RadixBufs<Cfg0, V> b;
     b.pd = make_passes(key_bits - skip_low, Cfg::RADIX_BITS);
     for (int p = 0; p < b.pd.npass; ++p) b.pd.shift[p] += skip_low;
     b.ntiles = (n_upper + Cfg::TILE - 1) / Cfg::TILE;
     b.hist = a.zero<uint32_t>((int64_t)b.pd.npass * Cfg::RADIX);
-    b.status = a.zero<uint32_t>((int64_t)b.pd.npass * b.ntiles * Cfg::RADIX);
+    if (counted && b.ntiles > 0) {
+        b.nchunks = b.ntiles < COUNT_CHUNKS ? b.ntiles : COUNT_CHUNKS;
+        b.tpc = (int)((b.ntiles + b.nchunks - 1) / b.nchunks);
+        b.nchunks = (b.ntiles + b.tpc - 1) / b.tpc;          // every chunk holds at least one tile
+        b.pre = a.scratch<uint32_t>(b.ntiles * Cfg::RADIX);
+        b.ctot = a.scratch<uint32_t>(b.nchunks * Cfg::RADIX);
+        b.cbase = a.scratch<uint32_t>(b.nchunks * Cfg::RADIX);
+    }
+    const int look_passes = b.pd.npass - (b.pre ? 1 : 0);
+    b.status = a.zero<uint32_t>((int64_t)look_passes * b.ntiles * Cfg::RADIX);
     b.counters = a.zero<uint32_t>(b.pd.npass);
     b.d_cnt = a.zero<int64_t>(1);
     if (b.pd.npass > 1) {
@@ -188,15 +207,25 @@ RadixBufs<Cfg, V> radix_reserve(Arena& a, int64_t n_upper, int key_bits, int ski
 // bounded by the count of elements that took part (*count_src).
 // first_label / pass_label (string literals, optional) name the first and the
 // later pass kernels in the per-launch profile.
-template <class Cfg, class V, int Tag = 0, class Src0>
-tqp_status radix_launch(const RadixBufs<Cfg, V>& b, const Src0& src0, int64_t n_upper, bool run_hist,
+template <class Cfg0, class V, int Tag = 0, class Src0>
+tqp_status radix_launch(const RadixBufs<Cfg0, V>& b, const Src0& src0, int64_t n_upper, bool run_hist,
                         const int64_t* count_src, uint32_t key_mask, uint32_t* keys_out, V* vals_out,
                         tqp_ctx* ctx, hipStream_t s, const char* first_label = nullptr,
                         const char* pass_label = nullptr) {
+    using Cfg = typename Cfg0::template ForVal<V>;
     const int np = b.pd.npass;
     const int64_t tiles = b.ntiles;
     if (tiles == 0) return TQP_OK;
-    if (run_hist) {
+    const bool counted = run_hist && b.pre;
+    if (counted) {
+        TQP_LAUNCH(ctx, s, "radix_hist",
+                   k_radix_hist_tiles<Cfg, Src0><<<(unsigned)b.nchunks, Cfg::BLOCK, 0, s>>>(
+                       src0, b.pd, key_mask, b.hist, b.d_cnt, ctx->d_err, b.pre, b.ctot, b.tpc, tiles));
+        TQP_LAUNCH(ctx, s, "radix_chunk_scan",
+                   k_radix_chunk_scan<<<1u << b.pd.bits[0], CHUNK_SCAN_BLOCK, 0, s>>>(
+                       b.ctot, (int)b.nchunks, b.hist, Cfg::RADIX, b.cbase));
+        count_src = b.d_cnt;
+    } else if (run_hist) {
         const int g = grid_for(n_upper, (int64_t)Cfg::BLOCK * HIST_ITEMS * 4, (int64_t)ctx->num_cus * 2);
         TQP_LAUNCH(ctx, s, "radix_hist",
                    k_radix_hist<Cfg, Src0><<<g, Cfg::BLOCK, 0, s>>>(src0, b.pd, key_mask, b.hist, b.d_cnt,
@@ -216,8 +245,14 @@ tqp_status radix_launch(const RadixBufs<Cfg, V>& b, const Src0& src0, int64_t n_
         uint32_t* ok = to_final ? keys_out : b.ktmp;
         V* ov = to_final ? vals_out : b.vtmp;
         DstPairs<V> dst{ok, ov};
-        uint32_t* st = b.status + (int64_t)p * tiles * Cfg::RADIX;
-        if (p == 0) {
+        const int sp = counted ? p - 1 : p;     // look-back passes only have status words
+        uint32_t* st = sp >= 0 ? b.status + (int64_t)sp * tiles * Cfg::RADIX : nullptr;
+        if (p == 0 && counted) {
+            TQP_LAUNCH(ctx, s, first_name,
+                       k_radix_pass_counted<Cfg, Src0, V, Tag><<<(unsigned)tiles, Cfg::BLOCK, 0, s>>>(
+                           src0, dst, b.pd.shift[p], b.pd.bits[p], PassCounts{b.pre, b.cbase, b.tpc},
+                           ctx->d_err));
+        } else if (p == 0) {
             TQP_LAUNCH(ctx, s, first_name,
                        k_radix_pass<Cfg, Src0, V, Tag><<<(unsigned)tiles, Cfg::BLOCK, 0, s>>>(
                            src0, dst, b.pd.shift[p], b.pd.bits[p], b.hist + p * Cfg::RADIX, st, b.counters + p,
@@ -237,7 +272,7 @@ tqp_status radix_launch(const RadixBufs<Cfg, V>& b, const Src0& src0, int64_t n_
 
 // Digit-width dispatch: the context's digit width picks the configuration.
 using R4 = RadixCfg<4, 256, 8, 8>;
-using R8 = RadixCfg<8, 512, 12, 8>;
+using R8 = RadixCfg<8, 512, 12, 8, 16>;
 using R11 = RadixCfg<11, 512, 8, 8>;
 
 template <class F>

@@ -192,13 +192,26 @@ struct JoinSmem {
 // range, and each left element is looked up on its own, so the pairs of a
 // tile come out in the tile's element order instead of key order (the same
 // pairs; lowb = 0 keeps the canonical order).
+// What a left tile needs before its rows are read: its R window and its
+// first and last left keys.  The persistent kernels load it one tile ahead,
+// so that a tile's row loads and window loads go out together.
+struct TileGeo {
+    int64_t wlo, whi;
+    uint32_t kfirst, klast;
+};
+__device__ __forceinline__ TileGeo tile_geo(const uint32_t* lkey, int64_t nl, const int64_t* win, int64_t tile,
+                                            int tile_size) {
+    const int64_t t0 = tile * tile_size;
+    const int64_t tl = (t0 + tile_size < nl ? t0 + tile_size : nl) - 1;
+    return TileGeo{win[2 * tile], win[2 * tile + 1], lkey[t0], lkey[tl]};
+}
+
 // Key range of a left tile whose keys are sorted on their bits above lowb
 // (lowb = 0: fully sorted): from the bucket of its first key to the end of
 // the bucket of its last key.
-__device__ __forceinline__ void tile_key_range(const uint32_t* lkey, int64_t first, int64_t last, int lowb,
-                                               uint32_t& kmin, uint32_t& kmax) {
-    kmin = (lkey[first] >> lowb) << lowb;
-    kmax = ((lkey[last] >> lowb) << lowb) | ((1u << lowb) - 1);
+__device__ __forceinline__ void tile_key_range(const TileGeo& g, int lowb, uint32_t& kmin, uint32_t& kmax) {
+    kmin = (g.kfirst >> lowb) << lowb;
+    kmax = ((g.klast >> lowb) << lowb) | ((1u << lowb) - 1);
 }
 
 // Output rows of one left tile, for the counting kernel of the two-kernel
@@ -206,26 +219,37 @@ __device__ __forceinline__ void tile_key_range(const uint32_t* lkey, int64_t fir
 // with no payload traffic.  The value is returned to every thread.
 template <class Cfg, class RP>
 __device__ __forceinline__ int64_t join_tile_count(const uint32_t* lkey, int64_t nl, const uint32_t* rkey,
-                                                   int64_t wlo, int64_t whi, int64_t tile, JoinSmem<Cfg, RP>& sm,
+                                                   const TileGeo& g, int64_t tile, JoinSmem<Cfg, RP>& sm,
                                                    int lowb) {
     constexpr int TILE = Cfg::TILE, ITEMS = Cfg::ITEMS, RWIN = Cfg::RWIN, W = Cfg::WAVES;
     const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
     const int64_t t0 = tile * TILE;
-    const int64_t tlast = (t0 + TILE < nl ? t0 + TILE : nl) - 1;
     uint32_t kmin, kmax;
-    tile_key_range(lkey, t0, tlast, lowb, kmin, kmax);
+    tile_key_range(g, lowb, kmin, kmax);
+    const int64_t wlo = g.wlo, whi = g.whi;
     const int64_t wn = whi - wlo;
     const bool direct = wn <= RWIN && (int64_t)kmax - (int64_t)kmin < RWIN;
-    if (direct) {
-        const int range = (int)(kmax - kmin) + 1;
-        for (int i = tid; i < range; i += Cfg::BLOCK) sm.cnt[i] = 0;
-    }
+    // The tile's keys and the first round of window keys are loaded together
+    // (clamped indexes: no branch between the loads); the table is cleared
+    // while they are in flight.
     const int64_t chunk = t0 + (int64_t)w * ITEMS * WAVE;
     uint32_t key[ITEMS];
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const int64_t i = chunk + j * WAVE + l;
-        key[j] = i < nl ? lkey[i] : 0;
+        key[j] = lkey[i < nl ? i : nl - 1];                 // the tile exists, so nl >= 1
+    }
+    uint32_t kk0[COUNT_TABLE_ITEMS];
+    if (direct && wn > 0) {
+#pragma unroll
+        for (int u = 0; u < COUNT_TABLE_ITEMS; ++u) {
+            const int i = tid + u * Cfg::BLOCK;
+            kk0[u] = rkey[wlo + (i < wn ? i : wn - 1)];
+        }
+    }
+    if (direct) {
+        const int range = (int)(kmax - kmin) + 1;
+        for (int i = tid; i < range; i += Cfg::BLOCK) sm.cnt[i] = 0;
     }
     __syncthreads();
     if (direct) {
@@ -233,9 +257,14 @@ __device__ __forceinline__ int64_t join_tile_count(const uint32_t* lkey, int64_t
         // declared key width (already flagged): they are skipped, never
         // indexed
         const uint32_t range = kmax - kmin + 1;
-        // COUNT_TABLE_ITEMS window keys per thread and round, loaded before
-        // any is used (clamped index: no branch between the loads)
-        for (int i0 = tid; i0 < wn; i0 += Cfg::BLOCK * COUNT_TABLE_ITEMS) {
+        if (wn > 0) {
+#pragma unroll
+            for (int u = 0; u < COUNT_TABLE_ITEMS; ++u) {
+                const uint32_t v = kk0[u] - kmin;
+                if (tid + u * Cfg::BLOCK < wn && v < range) atomicAdd(&sm.cnt[v], 1);
+            }
+        }
+        for (int i0 = tid + Cfg::BLOCK * COUNT_TABLE_ITEMS; i0 < wn; i0 += Cfg::BLOCK * COUNT_TABLE_ITEMS) {
             uint32_t kk[COUNT_TABLE_ITEMS];
 #pragma unroll
             for (int u = 0; u < COUNT_TABLE_ITEMS; ++u) {
@@ -278,15 +307,15 @@ __device__ __forceinline__ int64_t join_tile_count(const uint32_t* lkey, int64_t
 // the tile's total to *d_count instead.
 template <class Cfg, class LP, class RP, class Emit>
 __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, int64_t nl, const uint32_t* rkey,
-                                          const RP* rpay, int64_t wlo, int64_t whi, int64_t tile, int64_t base,
+                                          const RP* rpay, const TileGeo& g, int64_t tile, int64_t base,
                                           int64_t* d_count, Emit& e, typename Emit::Smem& esm,
                                           JoinSmem<Cfg, RP>& sm, int lowb = 0) {
     constexpr int TILE = Cfg::TILE, ITEMS = Cfg::ITEMS, RWIN = Cfg::RWIN, W = Cfg::WAVES;
     const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
     const int64_t t0 = tile * TILE;
-    const int64_t tlast = (t0 + TILE < nl ? t0 + TILE : nl) - 1;
     uint32_t kmin, kmax;
-    tile_key_range(lkey, t0, tlast, lowb, kmin, kmax);
+    tile_key_range(g, lowb, kmin, kmax);
+    const int64_t wlo = g.wlo, whi = g.whi;
     const int64_t wn = whi - wlo;
     const bool direct = wn <= RWIN && (int64_t)kmax - (int64_t)kmin < RWIN;
     if (direct) {
@@ -428,9 +457,12 @@ k_join_count(const uint32_t* lkey, int64_t nl_upper, const int64_t* d_nl, const 
     const int64_t ntiles = (nl + Cfg::TILE - 1) / Cfg::TILE;
     int64_t t0, t1, sum = 0;
     join_block_range(ntiles, t0, t1);
+    TileGeo g{};
+    if (t0 < t1) g = tile_geo(lkey, nl, win, t0, Cfg::TILE);
     for (int64_t tile = t0; tile < t1; ++tile) {
-        const int64_t t = join_tile_count<Cfg, uint8_t>(lkey, nl, rkey, win[2 * tile], win[2 * tile + 1], tile, sm,
-                                                        lowb);
+        const TileGeo cur = g;
+        if (tile + 1 < t1) g = tile_geo(lkey, nl, win, tile + 1, Cfg::TILE);     // one tile ahead
+        const int64_t t = join_tile_count<Cfg, uint8_t>(lkey, nl, rkey, cur, tile, sm, lowb);
         if (threadIdx.x == 0) tile_cnt[tile] = t;
         sum += t;
     }
@@ -471,8 +503,8 @@ k_join(const uint32_t* lkey, const LP* lpay, int64_t nl_upper, const int64_t* d_
         for (int64_t tile = t0; tile < t1; ++tile) {
             const int64_t base = run;
             run += tile_cnt[tile];
-            join_tile<Cfg, LP, RP, Emit>(lkey, lpay, nl, rkey, rpay, win[2 * tile], win[2 * tile + 1], tile, base,
-                                         d_count, e, esm, sm, lowb);
+            join_tile<Cfg, LP, RP, Emit>(lkey, lpay, nl, rkey, rpay, tile_geo(lkey, nl, win, tile, Cfg::TILE), tile,
+                                         base, d_count, e, esm, sm, lowb);
         }
         if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
             *d_count = run;
@@ -485,8 +517,8 @@ k_join(const uint32_t* lkey, const LP* lpay, int64_t nl_upper, const int64_t* d_
             __syncthreads();
             const int64_t tile = sm.tile;
             if (tile >= ntiles) break;
-            join_tile<Cfg, LP, RP, Emit>(lkey, lpay, nl, rkey, rpay, win[2 * tile], win[2 * tile + 1], tile, 0,
-                                         d_count, e, esm, sm, lowb);
+            join_tile<Cfg, LP, RP, Emit>(lkey, lpay, nl, rkey, rpay, tile_geo(lkey, nl, win, tile, Cfg::TILE), tile,
+                                         0, d_count, e, esm, sm, lowb);
         }
     }
     e.finish(esm);

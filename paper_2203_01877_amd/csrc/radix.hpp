@@ -212,8 +212,13 @@ template <class V> struct ValBytes { static constexpr int value = sizeof(V); };
 template <> struct ValBytes<NoVal> { static constexpr int value = 0; };
 
 // ------------------------------------------------------------------ config
-template <int RB, int BLOCK_, int ITEMS_, int LB_ = 16>
+// ITEMS_NARROW_: items per thread when the payload has at most 4 bytes (the
+// staged tile then takes less LDS, so the tile can be longer: longer digit
+// runs per tile, fewer look-backs per element).
+template <int RB, int BLOCK_, int ITEMS_, int LB_ = 16, int ITEMS_NARROW_ = ITEMS_>
 struct RadixCfg {
+    template <class V>
+    using ForVal = RadixCfg<RB, BLOCK_, (ValBytes<V>::value <= 4 ? ITEMS_NARROW_ : ITEMS_), LB_, ITEMS_NARROW_>;
     static constexpr int LOOKBACK = LB_;     // predecessors read per look-back round
     static constexpr int RADIX_BITS = RB;
     static constexpr int RADIX = 1 << RB;
@@ -290,6 +295,95 @@ k_radix_hist(Src src, PassDesc pd, uint32_t key_mask, uint32_t* hist, int64_t* d
     }
 }
 
+// Pre-counted first pass.  The histogram kernel below walks the tiles of the
+// first pass itself (block c owns the contiguous tiles [c*tpc, (c+1)*tpc)),
+// so besides the global histograms it records, per tile and digit, the count
+// of earlier tiles of the same chunk (pre), and per chunk and digit the chunk
+// total (ctot).  A one-block-per-digit scan turns the chunk totals into chunk
+// bases (cbase: the digit's global start plus the counts of earlier chunks).
+// The first pass then knows every tile's global offsets up front and needs no
+// look-back: its tiles run in any order.
+constexpr int COUNT_CHUNKS = 512;        // chunks (blocks) of the counting kernel, at most 1024
+constexpr int CHUNK_SCAN_BLOCK = 1024;
+
+template <class Cfg, class Src>
+__global__ void __launch_bounds__(Cfg::BLOCK)
+k_radix_hist_tiles(Src src, PassDesc pd, uint32_t key_mask, uint32_t* hist, int64_t* d_count,
+                   uint32_t* flags, uint32_t* pre, uint32_t* ctot, int tpc, int64_t ntiles_cap) {
+    constexpr int R = Cfg::RADIX, ITEMS = Cfg::ITEMS, TILE = Cfg::TILE;
+    // h[0, R): the current tile's first-pass counts; h[R, npass*R): later
+    // passes' counts over the chunk
+    __shared__ uint32_t h[Cfg::MAX_PASSES * R];
+    __shared__ uint32_t run[R];
+    __shared__ uint32_t s_cnt;
+    __shared__ uint32_t s_bad;
+    for (int i = threadIdx.x; i < pd.npass * R; i += Cfg::BLOCK) h[i] = 0;
+    for (int i = threadIdx.x; i < R; i += Cfg::BLOCK) run[i] = 0;
+    if (threadIdx.x == 0) { s_cnt = 0; s_bad = 0; }
+    const int64_t n = src.size();
+    int64_t ntiles = (n + TILE - 1) / TILE;
+    if (ntiles > ntiles_cap) ntiles = ntiles_cap;          // the tiles pre holds
+    const int64_t t0 = (int64_t)blockIdx.x * tpc;
+    const int64_t t1 = t0 + tpc < ntiles ? t0 + tpc : ntiles;
+    const int sh0 = pd.shift[0];
+    const uint32_t m0 = (1u << pd.bits[0]) - 1;
+    uint32_t cnt = 0, bad = 0;
+    // the next tile's loads are issued before the current tile is counted
+    uint32_t kc[ITEMS], kn[ITEMS];
+    bool oc[ITEMS], on[ITEMS];
+    auto load = [&](int64_t t, uint32_t* kk, bool* ok) {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const int64_t i = t * TILE + (int64_t)j * Cfg::BLOCK + threadIdx.x;
+            const bool in = i < n;
+            ok[j] = src.load_key(in ? i : n - 1, kk[j]) && in;     // t < ntiles, so n >= 1
+        }
+    };
+    if (t0 < t1) load(t0, kc, oc);
+    for (int64_t t = t0; t < t1; ++t) {
+        if (t + 1 < t1) load(t + 1, kn, on);
+        __syncthreads();                      // the tile counters are clear
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            if (!oc[j]) continue;
+            const uint32_t k = kc[j];
+            ++cnt;
+            bad |= k & ~key_mask;
+            atomicAdd(&h[(k >> sh0) & m0], 1u);
+            for (int p = 1; p < pd.npass; ++p)
+                atomicAdd(&h[p * R + ((k >> pd.shift[p]) & ((1u << pd.bits[p]) - 1))], 1u);
+        }
+        __syncthreads();
+        for (int d = threadIdx.x; d < R; d += Cfg::BLOCK) {
+            const uint32_t c = h[d];
+            pre[t * R + d] = run[d];
+            run[d] += c;
+            h[d] = 0;
+        }
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) { kc[j] = kn[j]; oc[j] = on[j]; }
+    }
+    cnt = wave_sum(cnt);
+    if (lane_id() == 0 && cnt) atomicAdd(&s_cnt, cnt);
+    if (bad) atomicOr(&s_bad, 1u);
+    __syncthreads();
+    for (int d = threadIdx.x; d < R; d += Cfg::BLOCK) {
+        ctot[(int64_t)blockIdx.x * R + d] = run[d];
+        if (run[d]) atomic_add(&hist[d], run[d]);
+    }
+    for (int i = R + threadIdx.x; i < pd.npass * R; i += Cfg::BLOCK)
+        if (h[i]) atomic_add(&hist[i], h[i]);
+    if (threadIdx.x == 0) {
+        if (d_count && s_cnt) atomic_add(d_count, (int64_t)s_cnt);
+        if (s_bad) set_flag(flags, FLAG_KEY_RANGE);
+    }
+}
+
+// cbase[c][d] = (count of digits below d) + (count of d in chunks before c);
+// one block per digit, one thread per chunk.
+__global__ void k_radix_chunk_scan(const uint32_t* ctot, int nchunks, const uint32_t* hist0, int R,
+                                   uint32_t* cbase);
+
 // ------------------------------------------------------------------ one pass
 // LDS of one pass: the per-wave digit counters are only live while ranking and
 // the staged tile only while scattering, so the two share storage.
@@ -353,10 +447,18 @@ __device__ __forceinline__ uint32_t radix_lookback(const uint32_t* status, int64
 // One tile of one pass (shared by the single-input kernel and the batched
 // kernel).  The caller has obtained the tile id in increasing order from a
 // counter, so every predecessor of the tile is held by a running block.
-template <class Cfg, class Src, class V>
+// Global offsets of a pre-counted first pass (see k_radix_hist_tiles).
+struct PassCounts {
+    const uint32_t* pre;
+    const uint32_t* cbase;
+    int tpc;
+};
+
+template <class Cfg, class Src, class V, bool COUNTED = false>
 __device__ __forceinline__ void radix_pass_tile(const Src& src, const DstPairs<V>& dst, int shift, int bits,
                                                 const uint32_t* hist, uint32_t* status, uint32_t tile,
-                                                int64_t n, uint32_t* flags, PassSmem<Cfg, V>& sm) {
+                                                int64_t n, uint32_t* flags, PassSmem<Cfg, V>& sm,
+                                                PassCounts pc = {}) {
     constexpr int R = Cfg::RADIX, ITEMS = Cfg::ITEMS, TILE = Cfg::TILE, W = Cfg::WAVES;
     const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
     for (int i = tid; i < W * R; i += Cfg::BLOCK) (&sm.u.wave_hist[0][0])[i] = 0;
@@ -371,6 +473,17 @@ __device__ __forceinline__ void radix_pass_tile(const Src& src, const DstPairs<V
     uint32_t pos[ITEMS];
     bool valid[ITEMS];
     uint32_t bad = 0;
+    // pre-counted: the tile's global digit offsets, read with the items
+    constexpr int PER = (R + Cfg::BLOCK - 1) / Cfg::BLOCK;
+    uint32_t goff[PER];
+    if constexpr (COUNTED) {
+        const int64_t c = tile / pc.tpc;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int d = tid + q * Cfg::BLOCK;
+            goff[q] = d < nd ? pc.cbase[c * R + d] + pc.pre[(int64_t)tile * R + d] : 0;
+        }
+    }
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const int64_t i = base + j * WAVE + l;
@@ -418,13 +531,21 @@ __device__ __forceinline__ void radix_pass_tile(const Src& src, const DstPairs<V
             run += c;
         }
         sm.local_start[d] = run;   // tile count for now; scanned below
-        if (d < nd) st_relaxed(status + (int64_t)tile * R + d, (tile == 0 ? ST_INC : ST_AGG) | run);
+        if constexpr (!COUNTED) {
+            if (d < nd) st_relaxed(status + (int64_t)tile * R + d, (tile == 0 ? ST_INC : ST_AGG) | run);
+        }
     }
     __syncthreads();
     // Tile-local digit starts (exclusive scan of the tile counts, in place).
     const uint32_t tile_total = block_excl_scan_array<Cfg::BLOCK>(sm.local_start, R, sm.scratch);
-    // Global digit base: exclusive scan of this pass's histogram.
-    {
+    if constexpr (COUNTED) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int d = tid + q * Cfg::BLOCK;
+            if (d < nd) sm.delta[d] = (int32_t)goff[q] - (int32_t)sm.local_start[d];
+        }
+    } else {
+        // Global digit base: exclusive scan of this pass's histogram.
         const int per = (R + Cfg::BLOCK - 1) / Cfg::BLOCK;
         const int b0 = tid * per;
         uint32_t loc = 0;
@@ -458,7 +579,7 @@ __device__ __forceinline__ void radix_pass_tile(const Src& src, const DstPairs<V
         }
     }
     // ... while one thread per digit looks back for the tile's global offset.
-    for (int d = tid; d < nd; d += Cfg::BLOCK) {
+    for (int d = tid; d < nd && !COUNTED; d += Cfg::BLOCK) {
         if (tile != 0) {
             const uint32_t excl = radix_lookback<Cfg::LOOKBACK>(status, tile, R, d, flags);
             st_relaxed(status + (int64_t)tile * R + d,
@@ -491,6 +612,17 @@ k_radix_pass(Src src, DstPairs<V> dst, int shift, int bits, const uint32_t* hist
     const int64_t n = src.size();
     if ((int64_t)tile >= (n + Cfg::TILE - 1) / Cfg::TILE) return;
     radix_pass_tile<Cfg, Src, V>(src, dst, shift, bits, hist, status, tile, n, flags, sm);
+}
+
+// First pass with pre-counted offsets: tile = block, no waits.
+template <class Cfg, class Src, class V, int Tag = 0>
+__global__ void __launch_bounds__(Cfg::BLOCK)
+k_radix_pass_counted(Src src, DstPairs<V> dst, int shift, int bits, PassCounts pc, uint32_t* flags) {
+    __shared__ PassSmem<Cfg, V> sm;
+    const uint32_t tile = blockIdx.x;
+    const int64_t n = src.size();
+    if ((int64_t)tile >= (n + Cfg::TILE - 1) / Cfg::TILE) return;
+    radix_pass_tile<Cfg, Src, V, true>(src, dst, shift, bits, nullptr, nullptr, tile, n, flags, sm, pc);
 }
 
 // ---------------------------------------------------------- finishing pass

@@ -90,6 +90,25 @@ def test_sort_parity(hip, ctx, digit_bits, key_bits, n):
     assert ctx.errors() == 0
 
 
+@pytest.mark.parametrize("digit_bits", [4, 8, 11])
+def test_sort_many_tiles_per_chunk(hip, ctx, digit_bits):
+    """5M keys: the histogram kernel's chunks hold several tiles each (the
+    first pass's pre-counted offsets span chunks), with a ragged last tile."""
+    n = 5_000_003
+    rng = _rng(811 + digit_bits)
+    keys = rng.integers(0, 1 << 25, n).astype(np.int32)
+    keys[1000:400_000] = 77            # a digit run across many tiles
+    vals = np.arange(n, dtype=np.int32)
+    ctx.set_digit_bits(digit_bits)
+    try:
+        wk, wv = oracle.sort_pairs(keys, vals)
+        ko, vo = hip.sort(ctx, _dev(keys), _dev(vals), key_bits=25)
+        assert np.array_equal(_np(ko), wk) and np.array_equal(_np(vo), wv)
+    finally:
+        ctx.set_digit_bits(8)
+    assert ctx.errors() == 0
+
+
 def test_sort_device_count(hip, ctx):
     import torch
     rng = _rng(5)
