@@ -161,7 +161,7 @@ k_finish_sort(const uint32_t* kin, const uint32_t* vin, int64_t n, uint32_t* kou
         const uint32_t x = cnt[c + l];
         const uint32_t inc = wave_incl_sum(x);
         cnt[c + l] = carry + inc - x;
-        carry += __shfl(inc, WAVE - 1, WAVE);
+        carry += wave_read(inc, WAVE - 1);
     }
     if (l == 0) s_wtot[w] = carry;
     __syncthreads();

@@ -2,6 +2,7 @@
 // agent-scope atomics for decoupled look-back, and small block-wide helpers.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <type_traits>
 #include <stdint.h>
 
 namespace tqp {
@@ -48,21 +49,59 @@ __device__ __forceinline__ void set_flag(uint32_t* flags, uint32_t bit) {
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
 
 // ---------------------------------------------------------------- wave scans
+// Sums across the 64 lanes of a wave (all lanes active) on DPP lane moves:
+// an ALU operand modifier, so a step costs a few cycles instead of an LDS
+// permute round trip.  row_shr:n moves values n lanes up within each row of
+// 16 lanes; row_bcast:15 / row_bcast:31 copy the last lane of a row into the
+// rows selected by the row mask.  Lanes with no source (or outside the row
+// mask) read 0.
+namespace dpp {
+constexpr int ROW_SHR1 = 0x111, ROW_SHR2 = 0x112, ROW_SHR4 = 0x114, ROW_SHR8 = 0x118;
+constexpr int ROW_BCAST15 = 0x142, ROW_BCAST31 = 0x143;
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t mov(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t mov(uint64_t v) {
+    return ((uint64_t)mov<CTRL, ROWS>((uint32_t)(v >> 32)) << 32) | mov<CTRL, ROWS>((uint32_t)v);
+}
+}  // namespace dpp
+
+template <class T>
+using lane_word_t = typename std::conditional<sizeof(T) == 4, uint32_t, uint64_t>::type;
+
+// Inclusive prefix sum over the lanes (4- or 8-byte integers, wrapping).
 template <class T>
 __device__ __forceinline__ T wave_incl_sum(T v) {
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        T u = __shfl_up(v, d, WAVE);
-        if (lane_id() >= d) v += u;
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "4- or 8-byte integers");
+    lane_word_t<T> x = (lane_word_t<T>)v;
+    x += dpp::mov<dpp::ROW_SHR1, 0xF>(x);
+    x += dpp::mov<dpp::ROW_SHR2, 0xF>(x);
+    x += dpp::mov<dpp::ROW_SHR4, 0xF>(x);
+    x += dpp::mov<dpp::ROW_SHR8, 0xF>(x);        // rows of 16 scanned
+    x += dpp::mov<dpp::ROW_BCAST15, 0xA>(x);     // rows 1 and 3 add the last lane of rows 0 and 2
+    x += dpp::mov<dpp::ROW_BCAST31, 0xC>(x);     // rows 2 and 3 add lane 31
+    return (T)x;
+}
+
+// Value of lane `lane` (the same for every lane of the wave) in every lane.
+template <class T>
+__device__ __forceinline__ T wave_read(T v, int lane) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "4- or 8-byte values");
+    if constexpr (sizeof(T) == 4) {
+        return (T)(lane_word_t<T>)__builtin_amdgcn_readlane((int)(lane_word_t<T>)v, lane);
+    } else {
+        const uint64_t x = (uint64_t)v;
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, lane);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), lane);
+        return (T)(((uint64_t)hi << 32) | lo);
     }
-    return v;
 }
 
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, WAVE);
-    return v;
+    return wave_read(wave_incl_sum(v), WAVE - 1);
 }
 
 // Segmented inclusive scan across the wave: a lane with head=true starts a

@@ -417,7 +417,7 @@ __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, 
     for (int j = 0; j < ITEMS; ++j) {
         const int64_t incl = wave_incl_sum((int64_t)cnt[j]);
         const int64_t o = wbase + incl - cnt[j];
-        wbase += __shfl(incl, WAVE - 1, WAVE);
+        wbase += wave_read(incl, WAVE - 1);
         const bool small = cnt[j] <= JOIN_LANE_MAX;
         if (small)
             for (int t = 0; t < cnt[j]; ++t) e(o + t, key[j], pay[j], right(first[j] + t), esm);
@@ -425,11 +425,11 @@ __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, 
         while (heavy) {
             const int src = __ffsll((unsigned long long)heavy) - 1;
             heavy &= heavy - 1;
-            const int c = __shfl(cnt[j], src, WAVE);
-            const int64_t f = __shfl(first[j], src, WAVE);
-            const int64_t oo = __shfl(o, src, WAVE);
-            const uint32_t kk = __shfl(key[j], src, WAVE);
-            const LP pp = shfl_any(pay[j], src);
+            const int c = wave_read(cnt[j], src);
+            const int64_t f = wave_read(first[j], src);
+            const int64_t oo = wave_read(o, src);
+            const uint32_t kk = wave_read(key[j], src);
+            const LP pp = wave_read(pay[j], src);
             for (int q = l; q < c; q += WAVE) e(oo + q, kk, pp, right(f + q), esm);
         }
     }
