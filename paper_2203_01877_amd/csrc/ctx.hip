@@ -230,7 +230,7 @@ __global__ void k_topk_filter(const int32_t* gkey, const int64_t* gsum, int64_t 
             const uint64_t m = ballot(keep[j]);
             int32_t wbase = 0;
             if (lane_id() == 0 && m) wbase = atomicAdd(&s_cnt, (int32_t)popc64(m));
-            wbase = __shfl(wbase, 0, WAVE);
+            wbase = wave_read(wbase, 0);
             slot[j] = wbase + popc64(m & lanemask_lt());
         }
         __syncthreads();

@@ -58,13 +58,27 @@ constexpr uint32_t SPIN_LIMIT = 1u << 22;
 namespace dpp {
 constexpr int ROW_SHR1 = 0x111, ROW_SHR2 = 0x112, ROW_SHR4 = 0x114, ROW_SHR8 = 0x118;
 constexpr int ROW_BCAST15 = 0x142, ROW_BCAST31 = 0x143;
+// fill: what lanes with no source read
 template <int CTRL, int ROWS>
-__device__ __forceinline__ uint32_t mov(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, false);
+__device__ __forceinline__ uint32_t mov(uint32_t v, uint32_t fill = 0) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)fill, (int)v, CTRL, ROWS, 0xF, false);
 }
 template <int CTRL, int ROWS>
-__device__ __forceinline__ uint64_t mov(uint64_t v) {
-    return ((uint64_t)mov<CTRL, ROWS>((uint32_t)(v >> 32)) << 32) | mov<CTRL, ROWS>((uint32_t)v);
+__device__ __forceinline__ uint64_t mov(uint64_t v, uint64_t fill = 0) {
+    return ((uint64_t)mov<CTRL, ROWS>((uint32_t)(v >> 32), (uint32_t)(fill >> 32)) << 32) |
+           mov<CTRL, ROWS>((uint32_t)v, (uint32_t)fill);
+}
+// Inclusive scan with op (identity id) over the lanes of unsigned 4- or
+// 8-byte words.
+template <class U, class Op>
+__device__ __forceinline__ U scan(U x, U id, Op op) {
+    x = op(x, mov<ROW_SHR1, 0xF>(x, id));
+    x = op(x, mov<ROW_SHR2, 0xF>(x, id));
+    x = op(x, mov<ROW_SHR4, 0xF>(x, id));
+    x = op(x, mov<ROW_SHR8, 0xF>(x, id));
+    x = op(x, mov<ROW_BCAST15, 0xA>(x, id));
+    x = op(x, mov<ROW_BCAST31, 0xC>(x, id));
+    return x;
 }
 }  // namespace dpp
 
@@ -104,27 +118,38 @@ __device__ __forceinline__ T wave_sum(T v) {
     return wave_read(wave_incl_sum(v), WAVE - 1);
 }
 
+// Maximum / minimum over the lanes of unsigned 4- or 8-byte words.
+template <class U>
+__device__ __forceinline__ U wave_max(U v) {
+    static_assert(std::is_unsigned<U>::value && (sizeof(U) == 4 || sizeof(U) == 8), "unsigned words");
+    return wave_read(dpp::scan<U>(v, U(0), [](U a, U b) { return a > b ? a : b; }), WAVE - 1);
+}
+template <class U>
+__device__ __forceinline__ U wave_min(U v) {
+    static_assert(std::is_unsigned<U>::value && (sizeof(U) == 4 || sizeof(U) == 8), "unsigned words");
+    return wave_read(dpp::scan<U>(v, ~U(0), [](U a, U b) { return a < b ? a : b; }), WAVE - 1);
+}
+
 // Segmented inclusive scan across the wave: a lane with head=true starts a
 // new segment.  Returns the running sum of the lane's segment up to the lane.
 template <class T>
 __device__ __forceinline__ T wave_seg_incl_sum(T v, uint64_t headmask) {
-    // distance back to the segment head (inclusive of own lane)
-    const int l = lane_id();
-    const uint64_t upto = headmask & lanemask_le();
-    const int seg_start = upto ? 63 - __clzll(upto) : 0;   // highest head at or below lane
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        T u = __shfl_up(v, d, WAVE);
-        if (l - d >= seg_start) v += u;
-    }
-    return v;
-}
-
-// Broadcast of a 4- or 8-byte value from lane src.
-__device__ __forceinline__ uint32_t shfl_any(uint32_t v, int src) { return __shfl(v, src, WAVE); }
-__device__ __forceinline__ uint64_t shfl_any(uint64_t v, int src) {
-    const uint32_t lo = __shfl((uint32_t)v, src, WAVE), hi = __shfl((uint32_t)(v >> 32), src, WAVE);
-    return ((uint64_t)hi << 32) | lo;
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "4- or 8-byte integers");
+    // (sum, segment-started) pairs: a lane whose window already holds a head
+    // keeps its sum, otherwise it adds the window before it
+    lane_word_t<T> x = (lane_word_t<T>)v;
+    uint32_t f = (uint32_t)(headmask >> lane_id()) & 1u;
+    auto step = [&](auto xs, uint32_t fs) {
+        x = f ? x : x + xs;
+        f |= fs;
+    };
+    step(dpp::mov<dpp::ROW_SHR1, 0xF>(x), dpp::mov<dpp::ROW_SHR1, 0xF>(f));
+    step(dpp::mov<dpp::ROW_SHR2, 0xF>(x), dpp::mov<dpp::ROW_SHR2, 0xF>(f));
+    step(dpp::mov<dpp::ROW_SHR4, 0xF>(x), dpp::mov<dpp::ROW_SHR4, 0xF>(f));
+    step(dpp::mov<dpp::ROW_SHR8, 0xF>(x), dpp::mov<dpp::ROW_SHR8, 0xF>(f));
+    step(dpp::mov<dpp::ROW_BCAST15, 0xA>(x), dpp::mov<dpp::ROW_BCAST15, 0xA>(f));
+    step(dpp::mov<dpp::ROW_BCAST31, 0xC>(x), dpp::mov<dpp::ROW_BCAST31, 0xC>(f));
+    return (T)x;
 }
 
 // ---------------------------------------------------------------- block scans

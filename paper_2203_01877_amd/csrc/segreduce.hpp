@@ -160,11 +160,11 @@ k_segreduce(const uint32_t* keys, VS vs, int64_t n_upper, const int64_t* d_n, ui
         if (valid && (next_head || last_global)) seg_flush(out, seg, v, c, a, here);
         const int64_t i63 = chunk + j * WAVE + (WAVE - 1);
         if (i63 < n - 1) {                      // lane 63 valid and not the global end: run stays open
-            open_v = __shfl(v, WAVE - 1, WAVE);
-            open_c = __shfl(c, WAVE - 1, WAVE);
-            if (AVG) open_a = __shfl(a, WAVE - 1, WAVE);
-            open_seg = __shfl(seg, WAVE - 1, WAVE);
-            open_here = __shfl((int)here, WAVE - 1, WAVE) != 0;
+            open_v = wave_read(v, WAVE - 1);
+            open_c = wave_read(c, WAVE - 1);
+            if (AVG) open_a = wave_read(a, WAVE - 1);
+            open_seg = wave_read(seg, WAVE - 1);
+            open_here = wave_read((int)here, WAVE - 1) != 0;
             has_open = true;
         } else {
             has_open = false;
@@ -173,7 +173,7 @@ k_segreduce(const uint32_t* keys, VS vs, int64_t n_upper, const int64_t* d_n, ui
     }
     if (has_open) {                             // the chunk's last run may continue past it
         const int64_t last = chunk + (int64_t)ITEMS * WAVE - 1;
-        const uint32_t lk = __shfl(key[ITEMS - 1], WAVE - 1, WAVE);
+        const uint32_t lk = wave_read(key[ITEMS - 1], WAVE - 1);
         const bool ends = keys[last + 1] != lk;
         if (l == 0) seg_flush(out, open_seg, open_v, open_c, open_a, open_here && ends);
     }

@@ -103,12 +103,8 @@ __device__ __forceinline__ void block_select(BlockSelect<BLOCK, PER, LO>& sm, co
 #pragma unroll
     for (int j = 0; j < PER; ++j)
         if (valid[j]) { mx = hi[j] > mx ? hi[j] : mx; mn = hi[j] < mn ? hi[j] : mn; }
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        const uint64_t a = __shfl_xor(mx, d, WAVE), b = __shfl_xor(mn, d, WAVE);
-        mx = a > mx ? a : mx;
-        mn = b < mn ? b : mn;
-    }
+    mx = wave_max(mx);
+    mn = wave_min(mn);
     if (l == 0) { sm.wmax[w] = mx; sm.wmin[w] = mn; }
     __syncthreads();
     if (tid == 0) {
@@ -145,7 +141,7 @@ __device__ __forceinline__ void block_select(BlockSelect<BLOCK, PER, LO>& sm, co
             const uint64_t mm = ballot(match);
             if (!mm) continue;
             const int lead = __ffsll((unsigned long long)mm) - 1;
-            const uint32_t d0 = __shfl(d, lead, WAVE);
+            const uint32_t d0 = wave_read(d, lead);
             if (!ballot(match && d != d0)) {
                 if (l == lead) atomicAdd(&sm.h[d0], (uint32_t)popc64(mm));
             } else if (match) {
@@ -186,11 +182,7 @@ __device__ __forceinline__ void block_select(BlockSelect<BLOCK, PER, LO>& sm, co
 #pragma unroll
             for (int j = 0; j < PER; ++j)
                 if (valid[j] && (hi[j] & mhi2) == phi2 && (lo[j] & mlo2) == plo2 && hi[j] < bh) bh = hi[j];
-#pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) {
-                const uint64_t o = __shfl_xor(bh, d, WAVE);
-                bh = o < bh ? o : bh;
-            }
+            bh = wave_min(bh);
             if (l == 0) sm.wmin[w] = bh;
             __syncthreads();
             uint64_t mh = ~uint64_t(0);
@@ -200,11 +192,7 @@ __device__ __forceinline__ void block_select(BlockSelect<BLOCK, PER, LO>& sm, co
 #pragma unroll
                 for (int j = 0; j < PER; ++j)
                     if (valid[j] && hi[j] == mh && (lo[j] & mlo2) == plo2 && lo[j] < bl) bl = lo[j];
-#pragma unroll
-                for (int d = 32; d >= 1; d >>= 1) {
-                    const uint32_t o = __shfl_xor(bl, d, WAVE);
-                    bl = o < bl ? o : bl;
-                }
+                bl = wave_min(bl);
                 if (l == 0) sm.wlo[w] = bl;
                 __syncthreads();
                 for (int ww = 0; ww < BLOCK / WAVE; ++ww) bl = sm.wlo[ww] < bl ? sm.wlo[ww] : bl;
