@@ -51,7 +51,19 @@ tqp_status join_launch(tqp_ctx* ctx, hipStream_t s, const char* name, const Join
                    k_join_windows<<<grid_for(tiles, 256, 0), 256, 0, s>>>(lkey, nl, d_nl, rkey, nr, d_nr,
                                                                             Cfg::TILE, b.win, lowb));
     }
-    const int grid = grid_for(tiles, 1, (int64_t)ctx->num_cus * 4);
+    // persistent blocks: as many as fit on the chip at once (both kernels
+    // split the tiles over the same grid)
+    static const int per_cu = [] {
+        int a = 8, b = 8;
+        if (Emit::ORDERED &&
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_join_count<Cfg>, Cfg::BLOCK, 0) != hipSuccess)
+            a = 4;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_join<Cfg, LP, RP, Emit>, Cfg::BLOCK, 0) != hipSuccess)
+            b = 4;
+        const int m = a < b ? a : b;
+        return m < 1 ? 1 : m > 8 ? 8 : m;
+    }();
+    const int grid = grid_for(tiles, 1, (int64_t)ctx->num_cus * per_cu);
     if (Emit::ORDERED && tiles > 0) {
         TQP_LAUNCH(ctx, s, "join_count",
                    k_join_count<Cfg><<<grid, Cfg::BLOCK, 0, s>>>(lkey, nl, d_nl, rkey, b.win, b.tile_cnt,

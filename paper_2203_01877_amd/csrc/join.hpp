@@ -413,14 +413,29 @@ __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, 
         if (direct) return sm.rpay[r];
         return rpay ? rpay[wlo + r] : (RP)(wlo + r);
     };
+    // Writing emitters read the first match of every element ahead of the
+    // stores (independent reads: their latencies overlap); the aggregating
+    // ones keep their registers for the gathers.
+    constexpr bool AHEAD = Emit::ORDERED;
+    RP r0[AHEAD ? ITEMS : 1];
+    if constexpr (AHEAD) {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) r0[j] = cnt[j] > 0 ? right(first[j]) : RP{};
+    }
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const int64_t incl = wave_incl_sum((int64_t)cnt[j]);
         const int64_t o = wbase + incl - cnt[j];
         wbase += wave_read(incl, WAVE - 1);
         const bool small = cnt[j] <= JOIN_LANE_MAX;
-        if (small)
+        if constexpr (AHEAD) {
+            if (small && cnt[j] > 0) {
+                e(o, key[j], pay[j], r0[j], esm);
+                for (int t = 1; t < cnt[j]; ++t) e(o + t, key[j], pay[j], right(first[j] + t), esm);
+            }
+        } else if (small) {
             for (int t = 0; t < cnt[j]; ++t) e(o + t, key[j], pay[j], right(first[j] + t), esm);
+        }
         uint64_t heavy = ballot(!small);
         while (heavy) {
             const int src = __ffsll((unsigned long long)heavy) - 1;
