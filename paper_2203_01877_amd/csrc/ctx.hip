@@ -78,7 +78,7 @@ tqp_status fill_zero(void* p, size_t bytes, hipStream_t stream, tqp_ctx* ctx) {
 
 __global__ void k_join_windows(const uint32_t* lkey, int64_t nl_upper, const int64_t* d_nl,
                                const uint32_t* rkey, int64_t nr_upper, const int64_t* d_nr, int tile_size,
-                               int64_t* win, int lowb) {
+                               int64_t* win, int lowb, const int64_t* rbstart, int64_t nbkt) {
     int64_t nl = nl_upper, nr = nr_upper;
     if (d_nl) { const int64_t t = *d_nl; nl = t < nl ? t : nl; }
     if (d_nr) { const int64_t t = *d_nr; nr = t < nr ? t : nr; }
@@ -89,6 +89,13 @@ __global__ void k_join_windows(const uint32_t* lkey, int64_t nl_upper, const int
     const int64_t i1 = (i0 + tile_size < nl ? i0 + tile_size : nl) - 1;
     uint32_t kmin, kmax;
     tile_key_range(TileGeo{0, 0, lkey[i0], lkey[i1]}, lowb, kmin, kmax);
+    if (rbstart) {
+        // keys beyond the declared width (flagged elsewhere) are clamped, never indexed
+        const int64_t b0 = kmin >> lowb, b1 = ((int64_t)kmax >> lowb) + 1;
+        win[2 * t] = rbstart[b0 < nbkt ? b0 : nbkt];
+        win[2 * t + 1] = rbstart[b1 < nbkt ? b1 : nbkt];
+        return;
+    }
     const int64_t lo = lower_bound_glb(rkey, 0, nr, kmin);
     win[2 * t] = lo;
     win[2 * t + 1] = upper_bound_glb(rkey, lo, nr, kmax);
@@ -119,7 +126,8 @@ k_radix_chunk_scan(const uint32_t* ctot, int nchunks, const uint32_t* hist0, int
 }
 
 __global__ void __launch_bounds__(FINISH_BLOCK)
-k_finish_sort(const uint32_t* kin, const uint32_t* vin, int64_t n, uint32_t* kout, uint32_t* vout) {
+k_finish_sort(const uint32_t* kin, const uint32_t* vin, int64_t n, uint32_t* kout, uint32_t* vout, int lowb,
+              int64_t* bstart) {
     constexpr int U = 8;                              // loads in flight per thread
     constexpr int W = FINISH_BLOCK / WAVE;
     constexpr int SLICE = FINISH_SPAN / W;            // counters scanned by one wave
@@ -138,7 +146,12 @@ k_finish_sort(const uint32_t* kin, const uint32_t* vin, int64_t n, uint32_t* kou
     for (int i = tid; i < FINISH_SPAN; i += FINISH_BLOCK) cnt[i] = 0;
     __syncthreads();
     const int64_t lo = s_lo, hi = s_hi;
-    if (lo >= hi) return;
+    const int nb_span = bstart ? 1 << (FINISH_LOG2 - lowb) : 0;          // buckets per span
+    if (bstart && blockIdx.x == gridDim.x - 1 && tid == 0) bstart[(int64_t)gridDim.x * nb_span] = hi;
+    if (lo >= hi) {
+        for (int q = tid; q < nb_span; q += FINISH_BLOCK) bstart[(int64_t)blockIdx.x * nb_span + q] = lo;
+        return;
+    }
     // keys outside the span occur only in inputs that are not sorted on the
     // high bits (a broken key width): skipped, never indexed
     for (int64_t i0 = lo + tid; i0 < hi; i0 += (int64_t)FINISH_BLOCK * U) {
@@ -170,6 +183,11 @@ k_finish_sort(const uint32_t* kin, const uint32_t* vin, int64_t n, uint32_t* kou
     if (off)
         for (int c = w * SLICE; c < (w + 1) * SLICE; c += WAVE) cnt[c + l] += off;
     __syncthreads();
+    if (bstart) {
+        for (int q = tid; q < nb_span; q += FINISH_BLOCK)
+            bstart[(int64_t)blockIdx.x * nb_span + q] = lo + cnt[q << lowb];
+        __syncthreads();                        // read before the scatter below advances the counters
+    }
     for (int64_t i0 = lo + tid; i0 < hi; i0 += (int64_t)FINISH_BLOCK * U) {
         uint32_t k[U], v[U];
 #pragma unroll

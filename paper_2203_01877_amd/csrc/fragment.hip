@@ -127,13 +127,16 @@ void cust_reserve(Arena& a, const tqp_cust_fragment& f, const tqp_cust_out& o, C
     // histogram kernel more than the pass saves while the mid sort shares HBM
     b.fact = radix_reserve<Cfg, VT>(a, f.n_fact, kb, b.fact_lowb, false);
     // the mid keys: radix passes over the same high bits, then one finishing
-    // pass sorts each span of 8192 keys in LDS (the join's binary-search
-    // fallback needs them fully sorted)
+    // pass sorts each span of 4096 keys in LDS (the join's binary-search
+    // fallback needs them fully sorted) and records where each bucket of
+    // 2^fact_lowb keys starts (the join tiles' windows)
     b.mid = radix_reserve<Cfg, uint32_t>(a, f.n_mid, kb, b.fact_lowb);
     if (b.fact_lowb > 0) {
         b.mkeys_full = a.scratch<uint32_t>(f.n_mid);
         b.mvals_full = a.scratch<uint32_t>(f.n_mid);
         b.nspans = ((int64_t(1) << kb) + FINISH_SPAN - 1) >> FINISH_LOG2;
+        b.nmbkt = b.nspans << (FINISH_LOG2 - b.fact_lowb);
+        b.mbstart = a.scratch<int64_t>(b.nmbkt + 1);
     }
     b.join = join_reserve<JCfgFrag>(a, f.n_fact);
     b.d_join = a.zero<int64_t>(1);
@@ -153,7 +156,8 @@ void cust_reserve(Arena& a, const tqp_cust_fragment& f, const tqp_cust_out& o, C
     b.gvals_in = a.scratch<VT>(f.join_cap);
     b.gkeys = a.scratch<uint32_t>(f.join_cap);
     b.gvals = a.scratch<VT>(f.join_cap);
-    b.topk = topk_reserve(a, o.gcap, f.k);
+    // top-k candidates: the first k groups of every bucket (at most the groups)
+    b.topk = topk_reserve(a, std::min<int64_t>(o.gcap, b.nbuckets * f.k), f.k);
 }
 
 template <class Cfg, class VT>
@@ -176,8 +180,8 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
         // the join's fallback searches need the mid keys fully sorted: finish
         // the low bits span by span
         TQP_LAUNCH(ctx, ctx->side, "finish_sort",
-                   k_finish_sort<<<(unsigned)b.nspans, FINISH_BLOCK, 0, ctx->side>>>(b.mkeys, b.mvals, f.n_mid,
-                                                                                    b.mkeys_full, b.mvals_full));
+                   k_finish_sort<<<(unsigned)b.nspans, FINISH_BLOCK, 0, ctx->side>>>(
+                       b.mkeys, b.mvals, f.n_mid, b.mkeys_full, b.mvals_full, b.fact_lowb, b.mbstart));
         mk = b.mkeys_full;
         mv = b.mvals_full;
     }
@@ -206,7 +210,8 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
     }
     if ((st = join_launch<JCfgFrag, VT, uint32_t>(ctx, s, "join_keyval", b.join, b.fkeys, b.fvals, f.n_fact,
                                                   b.fact.d_cnt, mk, mv, f.n_mid, (const int64_t*)nullptr, b.d_join,
-                                                  f.join_cap, e, b.fact_lowb, o.d_join)) != TQP_OK)
+                                                  f.join_cap, e, b.fact_lowb, o.d_join, b.mbstart, b.nmbkt)) !=
+        TQP_OK)
         return st;
     // group-by: sort (custkey, revenue) on the custkey bits above lowb (the
     // histogram came from the join), then aggregate each bucket
@@ -230,15 +235,17 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
     if (b.lowb <= BUCKET_SMALL_LOWB) {
         TQP_LAUNCH(ctx, s, "bucket_agg",
                    (k_bucket_agg<256, 1 << BUCKET_SMALL_LOWB, AV><<<(unsigned)b.nbuckets, 256, 0, s>>>(
-                       b.gkeys, gv, b.bstarts, bhist, b.lowb, b.nbuckets, b.sstatus, b.scounter, so, ctx->d_err)));
+                       b.gkeys, gv, b.bstarts, bhist, b.lowb, b.nbuckets, b.sstatus, b.scounter, so, ctx->d_err,
+                       b.topk.filtered, b.topk.d_nf, f.k)));
     } else {
         TQP_LAUNCH(ctx, s, "bucket_agg",
                    (k_bucket_agg<1024, 1 << BUCKET_LOWB_MAX, AV><<<(unsigned)b.nbuckets, 1024, 0, s>>>(
-                       b.gkeys, gv, b.bstarts, bhist, b.lowb, b.nbuckets, b.sstatus, b.scounter, so, ctx->d_err)));
+                       b.gkeys, gv, b.bstarts, bhist, b.lowb, b.nbuckets, b.sstatus, b.scounter, so, ctx->d_err,
+                       b.topk.filtered, b.topk.d_nf, f.k)));
     }
-    // ORDER BY sum DESC, custkey ASC LIMIT k
-    if ((st = topk_launch(b.topk, o.key, o.sum, o.cnt, o.d_ngroups, f.k, o.top_key, o.top_sum, o.top_cnt,
-                          o.d_topk, s, ctx)) != TQP_OK)
+    // ORDER BY sum DESC, custkey ASC LIMIT k, over the buckets' candidates
+    if ((st = topk_launch_candidates(b.topk, o.cnt, f.k, o.top_key, o.top_sum, o.top_cnt, o.d_topk, s, ctx)) !=
+        TQP_OK)
         return st;
     return TQP_OK;
 }

@@ -44,12 +44,14 @@ template <class Cfg, class LP, class RP, class Emit>
 tqp_status join_launch(tqp_ctx* ctx, hipStream_t s, const char* name, const JoinBufs& b, const uint32_t* lkey,
                        const LP* lpay, int64_t nl, const int64_t* d_nl, const uint32_t* rkey, const RP* rpay,
                        int64_t nr, const int64_t* d_nr, int64_t* d_count, int64_t cap, const Emit& e,
-                       int lowb = 0, int64_t* d_count_out = nullptr) {
+                       int lowb = 0, int64_t* d_count_out = nullptr, const int64_t* rbstart = nullptr,
+                       int64_t nbkt = 0) {
     const int64_t tiles = b.tiles;
     if (tiles > 0) {
         TQP_LAUNCH(ctx, s, "join_windows",
                    k_join_windows<<<grid_for(tiles, 256, 0), 256, 0, s>>>(lkey, nl, d_nl, rkey, nr, d_nr,
-                                                                            Cfg::TILE, b.win, lowb));
+                                                                            Cfg::TILE, b.win, lowb, rbstart,
+                                                                            nbkt));
     }
     // persistent blocks: as many as fit on the chip at once (both kernels
     // split the tiles over the same grid)
@@ -103,6 +105,10 @@ TopkBufs topk_reserve(Arena& a, int64_t n_upper, int k);
 tqp_status topk_launch(const TopkBufs& t, const int32_t* key, const int64_t* sum, const int64_t* cnt,
                        const int64_t* d_n, int k, int32_t* out_key, int64_t* out_sum, int64_t* out_cnt,
                        int32_t* d_k, hipStream_t s, tqp_ctx* ctx);
+// Steps 3-4 only, over candidates already in t.filtered (count in *t.d_nf,
+// at most t.n_upper), e.g. each group bucket's own first k.
+tqp_status topk_launch_candidates(const TopkBufs& t, const int64_t* cnt, int k, int32_t* out_key,
+                                  int64_t* out_sum, int64_t* out_cnt, int32_t* d_k, hipStream_t s, tqp_ctx* ctx);
 
 template <class Cfg, class VT>
 struct CustBufs {
@@ -121,6 +127,8 @@ struct CustBufs {
     uint32_t *fkeys = nullptr, *mkeys = nullptr, *mvals = nullptr, *gkeys_in = nullptr, *gkeys = nullptr;
     uint32_t *mkeys_full = nullptr, *mvals_full = nullptr;   // mid after the finishing pass (fact_lowb > 0)
     int64_t nspans = 0;                                       // 4096-key spans of the finishing pass
+    int64_t* mbstart = nullptr;    // start of every 2^fact_lowb-key bucket in the finished mid keys
+    int64_t nmbkt = 0;             // buckets (mbstart holds nmbkt + 1 entries)
     VT *fvals = nullptr, *gvals_in = nullptr, *gvals = nullptr;
     TopkBufs topk;
 };

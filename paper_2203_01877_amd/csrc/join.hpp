@@ -160,10 +160,11 @@ struct EmitFlagsAgg {
 
 // ------------------------------------------------------------------ kernels
 // R window of every left tile: [lower_bound(R, first key), upper_bound(R, last
-// key)).  One thread per tile; all tiles search at once.
+// key)).  One thread per tile; all tiles search at once, or, given the start
+// of every bucket of 2^lowb key values in R (rbstart[0..nbkt]), read it there.
 __global__ void k_join_windows(const uint32_t* lkey, int64_t nl_upper, const int64_t* d_nl,
                                const uint32_t* rkey, int64_t nr_upper, const int64_t* d_nr, int tile_size,
-                               int64_t* win, int lowb);
+                               int64_t* win, int lowb, const int64_t* rbstart, int64_t nbkt);
 
 template <class Cfg, class RP>
 struct JoinSmem {

@@ -41,6 +41,11 @@ tqp_status topk_launch(const TopkBufs& t, const int32_t* key, const int64_t* sum
     TQP_LAUNCH(ctx, s, "topk_filter",
                k_topk_filter<<<grid_for(t.n_upper, 256 * 8, (int64_t)ctx->num_cus * 4), 256, 0, s>>>(
                    key, sum, t.n_upper, d_n, t.thr, t.filtered, t.d_nf));
+    return topk_launch_candidates(t, cnt, k, out_key, out_sum, out_cnt, d_k, s, ctx);
+}
+
+tqp_status topk_launch_candidates(const TopkBufs& t, const int64_t* cnt, int k, int32_t* out_key,
+                                  int64_t* out_sum, int64_t* out_cnt, int32_t* d_k, hipStream_t s, tqp_ctx* ctx) {
     for (int l = 0; l < t.levels; ++l) {
         TQP_LAUNCH(ctx, s, "topk_level",
                    (k_topk_level<TOPK_BLOCK, TOPK_CH><<<(unsigned)t.blocks[l], TOPK_BLOCK, 0, s>>>(

@@ -630,10 +630,15 @@ k_radix_pass_counted(Src src, DstPairs<V> dst, int shift, int bits, PassCounts p
 // (lowb <= FINISH_LOG2): the rows whose key lies in one span [s << FINISH_LOG2,
 // (s + 1) << FINISH_LOG2) are contiguous (two 64-way wave searches find
 // them), so one block per span counting-sorts them in LDS (count per key,
-// scan, scatter).  Equal keys end up in arbitrary order.
+// scan, scatter).  Equal keys end up in arbitrary order.  With bstart (and
+// 0 < lowb <= FINISH_LOG2), each block also records where every bucket of
+// 2^lowb key values in its span starts in the output, and the last block the
+// end of the last bucket: bstart[b] = lower_bound(kout, b << lowb) for b in
+// [0, nspans << (FINISH_LOG2 - lowb)].
 constexpr int FINISH_LOG2 = 12;
 constexpr int FINISH_SPAN = 1 << FINISH_LOG2;
 constexpr int FINISH_BLOCK = 256;
-__global__ void k_finish_sort(const uint32_t* kin, const uint32_t* vin, int64_t n, uint32_t* kout, uint32_t* vout);
+__global__ void k_finish_sort(const uint32_t* kin, const uint32_t* vin, int64_t n, uint32_t* kout, uint32_t* vout,
+                              int lowb, int64_t* bstart);
 
 }  // namespace tqp

@@ -12,6 +12,7 @@
 // (integer adds, so the result does not depend on their order).
 #pragma once
 #include "dev.hpp"
+#include "topk.hpp"
 
 namespace tqp {
 
@@ -194,17 +195,24 @@ __global__ void k_bucket_bounds(const uint32_t* keys, int64_t n_upper, const int
                                 int64_t nbuckets, int64_t* starts);
 
 // vals: int64 values (VT = int64_t) or values in [0, 2^32) (VT = uint32_t).
+// With cand, each block also appends the first k of its groups in the
+// order sum DESC, key ASC (step 1 of the top-k: the overall first k are among
+// them) to cand, counting them in *d_cand.
 template <int BLOCK, int SLOTS, class VT = int64_t>
 __global__ void __launch_bounds__(BLOCK)
 k_bucket_agg(const uint32_t* keys, const VT* vals, const int64_t* starts, const uint32_t* bhist, int lowb,
-             int64_t nbuckets, uint64_t* status, uint32_t* counter, SegOut out, uint32_t* flags) {
+             int64_t nbuckets, uint64_t* status, uint32_t* counter, SegOut out, uint32_t* flags,
+             TopCand* cand = nullptr, int64_t* d_cand = nullptr, int k = 0) {
     static_assert(SLOTS <= (1 << BUCKET_LOWB_MAX), "slot table larger than the LDS budget");
     constexpr int U = 8;                               // loads in flight per thread
+    constexpr int PER = (SLOTS + BLOCK - 1) / BLOCK;   // most slots per thread
     __shared__ unsigned long long s_sum[SLOTS];
     __shared__ uint32_t s_cnt[SLOTS];
     __shared__ int64_t s_base;
     __shared__ int32_t s_wave[BLOCK / WAVE];
     __shared__ uint32_t s_b;
+    __shared__ BlockSelect<BLOCK, PER, true> s_sel;
+    __shared__ int32_t s_nc;
     const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
     if (tid == 0) s_b = atomicAdd(counter, 1u);
     const int slots = 1 << lowb;
@@ -277,15 +285,66 @@ k_bucket_agg(const uint32_t* keys, const VT* vals, const int64_t* starts, const 
     }
     __syncthreads();
     int64_t g = s_base + woff + incl - mine;
-    for (int q = 0; q < per; ++q) {
+    // the block's groups as top-k candidates: order key (sum, ~key), group index
+    uint64_t chi[PER];
+    uint32_t clo[PER];
+    int32_t cidx[PER];
+    bool cval[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
         const int sl = tid * per + q;
-        if (sl < slots && s_cnt[sl]) {
+        cval[q] = false;
+        chi[q] = 0;
+        clo[q] = 0;
+        cidx[q] = 0;
+        if (q < per && sl < slots && s_cnt[sl]) {
+            const int32_t key = (int32_t)((b << lowb) | sl);
+            const int64_t sum = (int64_t)s_sum[sl];
             if (g < out.gcap) {
-                out.key[g] = (int32_t)((b << lowb) | sl);
-                out.sum[g] = (int64_t)s_sum[sl];
+                out.key[g] = key;
+                out.sum[g] = sum;
                 out.cnt[g] = (int64_t)s_cnt[sl];
+                chi[q] = order_hi(sum);
+                clo[q] = order_lo(key);
+                cidx[q] = (int32_t)g;
+                cval[q] = true;
             }
             ++g;
+        }
+    }
+    if (!cand) return;
+    // candidates stored (groups past the output capacity are not)
+    int nv = 0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) nv += cval[q];
+    nv = wave_sum(nv);
+    if (tid == 0) s_nc = 0;
+    __syncthreads();
+    if (l == 0 && nv) atomicAdd(&s_nc, nv);
+    __syncthreads();
+    const int need = s_nc < k ? s_nc : k;
+    if (need == 0) return;
+    uint64_t t_hi;
+    uint32_t t_lo;
+    block_select<BLOCK, PER, true>(s_sel, chi, clo, cval, need, t_hi, t_lo);
+    __syncthreads();
+    if (tid == 0) {
+        s_base = atomic_add(d_cand, (int64_t)need);
+        s_nc = 0;
+    }
+    __syncthreads();
+    // exactly need candidates are not after the need-th (group keys are unique)
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        if (cval[q] && (chi[q] > t_hi || (chi[q] == t_hi && clo[q] >= t_lo))) {
+            const int slot = atomicAdd(&s_nc, 1);
+            if (slot < need) {
+                TopCand x;
+                x.sum = (int64_t)(chi[q] ^ (uint64_t(1) << 63));
+                x.key = (int32_t)~clo[q];
+                x.idx = cidx[q];
+                cand[s_base + slot] = x;
+            }
         }
     }
 }

@@ -6,9 +6,12 @@
 //    holds k groups whose sum is at least T, so no group with a smaller sum
 //    can be among the overall first k.
 // 2. Filter.  One streaming pass keeps the groups with sum >= T.
-// 3. Chunk levels (only when many groups survive).  Each level sorts chunks
-//    of CH candidates in LDS with a bitonic network and keeps the first k of
-//    each chunk; a level runs only while its input exceeds TOPK_DIRECT.
+//    (Steps 1-2 alternative, in the custkey fragment: each group-by bucket
+//    block appends its own first k groups, a superset of the overall first
+//    k, as it writes them; see k_bucket_agg.)
+// 3. Chunk levels (only when many groups survive).  Each level keeps the
+//    first k of each chunk of CH candidates (radix select in one block); a
+//    level runs only while its input exceeds TOPK_DIRECT.
 // 4. Final.  One block selects the exact k-th remaining candidate by radix
 //    select on (sum, key), gathers the k candidates not after it and sorts
 //    them.
@@ -52,27 +55,6 @@ __device__ __forceinline__ int64_t topk_level_n(int64_t n0, int level, int k) {
     int64_t n = n0;
     for (int l = 0; l < level; ++l) n = (n + TOPK_CH - 1) / TOPK_CH * k;
     return n;
-}
-
-// Sorts c[0, CH) into "before" order; all BLOCK threads take part and the
-// sorted chunk is visible to the block on return.  Pairs at a stride below
-// 128 lie in the 128 slots of one wave, so only wider strides need a block
-// barrier.
-template <int BLOCK, int CH>
-__device__ __forceinline__ void bitonic_sort_lds(TopCand* c) {
-    static_assert(BLOCK * 2 == CH, "one compare-exchange per thread");
-    const int t = threadIdx.x;
-    for (int size = 2; size <= CH; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            const int lo = 2 * t - (t & (stride - 1));
-            const int hi = lo + stride;
-            const bool asc = ((lo & size) == 0);
-            const TopCand a = c[lo], b = c[hi];
-            if (asc ? top_before(b, a) : top_before(a, b)) { c[lo] = b; c[hi] = a; }
-            if (stride >= 2 * WAVE || stride == 1) __syncthreads();
-            else __builtin_amdgcn_wave_barrier();
-        }
-    }
 }
 
 // Radix select in one block over up to BLOCK * PER candidates held in
@@ -249,25 +231,69 @@ __global__ void k_topk_filter(const int32_t* gkey, const int64_t* gsum, int64_t 
                               const int64_t* thr, TopCand* out, int64_t* d_out);
 
 // Step 3, level `level`: runs only while its input count exceeds TOPK_DIRECT.
-// Block 0 always writes its k rows (padding included).
+// Each block keeps the first k of its chunk of CH candidates (radix select,
+// then a gather, in no particular order; padding when the chunk holds fewer).
+// Block 0 always writes its k rows.
 template <int BLOCK, int CH>
 __global__ void __launch_bounds__(BLOCK)
 k_topk_level(const int64_t* d_n0, const TopCand* cin, TopCand* cout, int k, int level) {
-    __shared__ TopCand c[CH];
+    constexpr int PER = CH / BLOCK;
+    static_assert(PER * BLOCK == CH, "whole chunks per block");
+    __shared__ BlockSelect<BLOCK, PER, true> sm;
+    __shared__ int s_n;
     const int64_t n = topk_level_n(*d_n0, level, k);
     if (n <= TOPK_DIRECT) return;
     const int64_t c0 = (int64_t)blockIdx.x * CH;
     if (c0 >= n && blockIdx.x != 0) return;
-    for (int i = threadIdx.x; i < CH; i += BLOCK) {
-        const int64_t g = c0 + i;
+    const int tid = threadIdx.x;
+    uint64_t hi[PER];
+    uint32_t lo[PER];
+    int32_t idx[PER];
+    bool valid[PER];
+    int nv = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int64_t g = c0 + (int64_t)j * BLOCK + tid;
         TopCand x;
         x.sum = 0; x.key = 0; x.idx = -1;
         if (g < n) x = cin[g];
-        c[i] = x;
+        valid[j] = x.idx >= 0;
+        hi[j] = order_hi(x.sum);
+        lo[j] = order_lo(x.key);
+        idx[j] = x.idx;
+        nv += valid[j];
     }
+    nv = wave_sum(nv);
+    if (tid == 0) s_n = 0;
     __syncthreads();
-    bitonic_sort_lds<BLOCK, CH>(c);
-    for (int i = threadIdx.x; i < k; i += BLOCK) cout[(int64_t)blockIdx.x * k + i] = c[i];
+    if (lane_id() == 0 && nv) atomicAdd(&s_n, nv);
+    __syncthreads();
+    const int need = s_n < k ? s_n : k;
+    __syncthreads();
+    if (tid == 0) s_n = 0;
+    uint64_t t_hi = 0;
+    uint32_t t_lo = 0;
+    if (need > 0) block_select<BLOCK, PER, true>(sm, hi, lo, valid, need, t_hi, t_lo);
+    __syncthreads();
+    TopCand* dst = cout + (int64_t)blockIdx.x * k;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        if (need > 0 && valid[j] && (hi[j] > t_hi || (hi[j] == t_hi && lo[j] >= t_lo))) {
+            const int slot = atomicAdd(&s_n, 1);
+            if (slot < need) {
+                TopCand x;
+                x.sum = (int64_t)(hi[j] ^ (uint64_t(1) << 63));
+                x.key = (int32_t)~lo[j];
+                x.idx = idx[j];
+                dst[slot] = x;
+            }
+        }
+    }
+    for (int i = need + tid; i < k; i += BLOCK) {
+        TopCand x;
+        x.sum = 0; x.key = 0; x.idx = -1;
+        dst[i] = x;
+    }
 }
 
 // Step 4: one block.  The input is the first level whose count is at most
