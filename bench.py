@@ -45,8 +45,8 @@ def algorithmic_bytes(plan, N, n_f, M, J, G, PB):
     bytes, 8 or 4)."""
     R = 4 + PB                                                # a (key, revenue) row
     return {
-        "radix_hist": 8 * N + 4 * M,                          # fact fk+date, mid pk
-        "fact_pass_fused": 24 * N + R * n_f,                  # fk, date, price, disc per row; key+revenue per kept row
+        "radix_hist": 8 * N + N // 8 + 4 * M,                 # fact fk+date in, predicate bits out; mid pk
+        "fact_pass_fused": 20 * N + N // 8 + R * n_f,         # fk, price, disc, predicate bit per row; key+revenue per kept row
         "fact_pass": 2 * R * n_f * (plan["fact_passes"] - 1),
         "mid_pass_first": 16 * M,                             # pk, custkey in; key+custkey out
         "mid_pass": 16 * M * (plan["mid_passes"] - 1),
@@ -63,7 +63,7 @@ def launch_bytes(plan, N, n_f, M, J, G, PB):
     """Algorithmic bytes of each launch of the kernel families the roofline may describe."""
     R = 4 + PB
     return {
-        "fact_pass_fused": [24 * N + R * n_f],
+        "fact_pass_fused": [20 * N + N // 8 + R * n_f],
         "fact_pass": [2 * R * n_f] * (plan["fact_passes"] - 1),
         "group_pass": [2 * R * J] * plan["group_passes"],
         "join_keyval": [R * n_f + 8 * M + R * J],
@@ -80,7 +80,7 @@ def roofline_families(PB):
     cfg = "RadixCfg<8,512,%d,8,16>" % (12 if PB == 8 else 16)      # 8-bit digits, 512 threads x 12 or 16 items
     radix = ("radix.hpp", "dev.hpp", "host.hpp")
     return {
-        "fact_pass_fused": ("k_radix_pass<%s, SrcFilterRevenue<%s>, %s, 1>" % (cfg, v, v), radix),
+        "fact_pass_fused": ("k_radix_pass<%s, SrcFilterRevenue<%s, true>, %s, 1>" % (cfg, v, v), radix),
         "fact_pass": ("k_radix_pass<%s, SrcPairs<%s>, %s, 1>" % (cfg, v, v), radix),
         "group_pass": ("k_radix_pass<%s, SrcPairs<%s>, %s, 3>" % (cfg, v, v), radix),
         "join_keyval": ("k_join<JoinCfg<256,8,2048>, %s, u32, EmitKeyVal<256,8,%s>>" % (v, v),

@@ -150,6 +150,7 @@ void cust_reserve(Arena& a, const tqp_cust_fragment& f, const tqp_cust_out& o, C
     b.scounter = a.zero<uint32_t>(1);
     b.fkeys = a.scratch<uint32_t>(f.n_fact);
     b.fvals = a.scratch<VT>(f.n_fact);
+    b.fmask = a.scratch<uint64_t>((f.n_fact + 63) / 64 + 1);
     b.mkeys = a.scratch<uint32_t>(f.n_mid);
     b.mvals = a.scratch<uint32_t>(f.n_mid);
     b.gkeys_in = a.scratch<uint32_t>(f.join_cap);
@@ -187,7 +188,7 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
     }
     // fact side: date < D fused into the sort; the payload is the revenue
     // price * (100 - disc), evaluated while the row is read
-    SrcFilterRevenue<VT> fsrc{f.fk, f.date, f.price, f.disc, CMP_LT, f.D, f.n_fact};
+    SrcFilterRevenue<VT, true> fsrc{f.fk, f.date, f.price, f.disc, CMP_LT, f.D, f.n_fact, b.fmask};
     if ((st = radix_launch<Cfg, VT, SORT_TAG_FACT>(b.fact, fsrc, f.n_fact, true, nullptr, key_mask_for(kb),
                                                    b.fkeys, b.fvals, ctx, s, "fact_pass_fused", "fact_pass")) !=
         TQP_OK)

@@ -130,6 +130,7 @@ struct CustBufs {
     int64_t* mbstart = nullptr;    // start of every 2^fact_lowb-key bucket in the finished mid keys
     int64_t nmbkt = 0;             // buckets (mbstart holds nmbkt + 1 entries)
     VT *fvals = nullptr, *gvals_in = nullptr, *gvals = nullptr;
+    uint64_t* fmask = nullptr;     // date < D of every fact row, one bit each
     TopkBufs topk;
 };
 

@@ -133,9 +133,13 @@ struct SrcFilterRowid {
 // carried as VT: uint64_t (the int64 value), or uint32_t when the caller
 // declares that every kept row's revenue lies in [0, 2^32) (a kept row
 // outside is reported through the pass's value-range flag).
-template <class VT>
+// MASK: the histogram kernel, which evaluates the predicate anyway, stores it
+// as one bit per row (mask, one 64-bit word per 64 rows); the pass then reads
+// that bit instead of the 4-byte date.
+template <class VT, bool MASK = false>
 struct SrcFilterRevenue {
     static constexpr bool CHECKS = sizeof(VT) < 8;
+    static constexpr bool WRITES_MASK = MASK;
     const int32_t* key;
     const int32_t* date;
     const int64_t* price;
@@ -143,21 +147,24 @@ struct SrcFilterRevenue {
     int32_t op;
     int64_t k;
     int64_t n;
+    uint64_t* mask;            // MASK: ceil(n / 64) words
     __device__ int64_t size() const { return n; }
     __device__ bool load_key(int64_t i, uint32_t& kk) const {
         kk = (uint32_t)key[i];
         return cmp_eval((int64_t)date[i], op, k);
     }
-    // price and disc are read with the key and date, whatever the predicate
-    // says, so a row costs one memory round trip instead of two (the rows the
-    // filter drops cost their 16 bytes).  bad collects kept rows whose value
-    // does not fit VT.
+    // price and disc are read with the key and the predicate, whatever the
+    // predicate says, so a row costs one memory round trip instead of two
+    // (the rows the filter drops cost their 16 bytes).  bad collects kept
+    // rows whose value does not fit VT.
     __device__ bool load(int64_t i, uint32_t& kk, VT& v, uint32_t& bad) const {
         kk = (uint32_t)key[i];
         const int64_t p = price[i], d = disc[i];
         const int64_t rev = p * (100 - d);
         v = (VT)rev;
-        const bool ok = cmp_eval((int64_t)date[i], op, k);
+        bool ok;
+        if constexpr (MASK) ok = (mask[i >> 6] >> (i & 63)) & 1;
+        else ok = cmp_eval((int64_t)date[i], op, k);
         if constexpr (CHECKS) bad |= (uint32_t)ok & (uint32_t)((uint64_t)rev >> 32 != 0);
         return ok;
     }
@@ -166,6 +173,13 @@ struct SrcFilterRevenue {
         return load(i, kk, v, unused);
     }
 };
+
+// Sources with WRITES_MASK = true get their predicate bits from the histogram
+// kernel.
+template <class S, class = void>
+struct SrcWritesMask : std::false_type {};
+template <class S>
+struct SrcWritesMask<S, std::void_t<decltype(S::WRITES_MASK)>> : std::integral_constant<bool, S::WRITES_MASK> {};
 
 // Sources with CHECKS = true take a fourth load argument that collects values
 // outside their declared width.
@@ -270,6 +284,15 @@ k_radix_hist(Src src, PassDesc pd, uint32_t key_mask, uint32_t* hist, int64_t* d
             const int64_t i = base + (int64_t)j * Cfg::BLOCK;
             const bool in = i < n;
             ok[j] = src.load_key(in ? i : n - 1, kk[j]) && in;     // base < n, so n >= 1
+        }
+        if constexpr (SrcWritesMask<Src>::value) {
+            // the 64 rows of item j of a wave are consecutive and 64-aligned
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const uint64_t m = ballot(ok[j]);
+                const int64_t i0 = base - lane_id() + (int64_t)j * Cfg::BLOCK;
+                if (lane_id() == 0 && i0 < n) src.mask[i0 >> 6] = m;
+            }
         }
 #pragma unroll
         for (int j = 0; j < U; ++j) {
