@@ -252,7 +252,14 @@ k_bucket_agg(const uint32_t* keys, const VT* vals, const int64_t* starts, const 
 #pragma unroll
         for (int j = 0; j < U; ++j) {
             if (i0 + (int64_t)j * BLOCK < hi) {
-                atomicAdd(&s_sum[k[j]], (unsigned long long)v[j]);
+                if constexpr (std::is_same<VT, uint32_t>::value) {
+                    // 32-bit add on the low word; a wrap carries into the high word
+                    uint32_t* w2 = reinterpret_cast<uint32_t*>(&s_sum[k[j]]);
+                    const uint32_t old = atomicAdd(&w2[0], v[j]);
+                    if (old + v[j] < old) atomicAdd(&w2[1], 1u);
+                } else {
+                    atomicAdd(&s_sum[k[j]], (unsigned long long)v[j]);
+                }
                 atomicAdd(&s_cnt[k[j]], 1u);
             }
         }
