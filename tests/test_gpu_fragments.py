@@ -146,6 +146,21 @@ def test_cust_revenue_width(hip, ctx, digit_bits):
     assert ctx.errors() == 0
 
 
+@pytest.mark.parametrize("k", [1, 100, 1024])
+@pytest.mark.parametrize("revenue_bits", [64, 32])
+def test_cust_topk_ties(hip, ctx, k, revenue_bits):
+    """One revenue for every row, so group sums tie whenever counts do: the
+    first k follow custkey order among equal sums, across group-by buckets
+    (each bucket contributes its own first k candidates)."""
+    fr = datagen.config2(seed=44, n=600_000, m=150_000, cust_hi=40_000)
+    fact = dict(fr.fact, price=np.full_like(fr.fact["price"], 100_000), disc=np.full_like(fr.fact["disc"], 5))
+    fr = dataclasses.replace(fr, fact=fact, k=k)
+    want = oracle.fragment_cust(fr.fact, fr.mid, fr.D, fr.k, gcap=fr.cust_hi)
+    assert len(np.unique(want["sum"])) < len(want["sum"]) // 10       # heavy ties
+    _assert_cust(_cust(hip, ctx, fr, revenue_bits=revenue_bits), want)
+    assert ctx.errors() == 0
+
+
 def test_cust_revenue_bits_rejected(hip, ctx):
     fr = datagen.config2(seed=5, n=1000, m=300, cust_hi=100)
     with pytest.raises(hip.TQPError):
