@@ -520,27 +520,36 @@ __device__ __forceinline__ void radix_pass_tile(const Src& src, const DstPairs<V
         if (bad) set_flag(flags, FLAG_VALUE_RANGE);
     }
 
-    // Rank: peers with the same digit found by one ballot per digit bit; the
-    // per-wave counter of the digit gives the rank of earlier items.
+    // Rank: peers with the same digit found by one ballot per digit bit (a
+    // lane differs from this one where the ballot of a bit disagrees with this
+    // lane's bit); the per-wave counter of the digit gives the rank of earlier
+    // items.  Full-width digits (the common case) unroll without bounds.
+    auto rank = [&](auto full) {
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-        const uint32_t d = valid[j] ? (key[j] >> shift) & dmask : 0;
-        uint64_t peers = ballot(valid[j]);
+        for (int j = 0; j < ITEMS; ++j) {
+            const uint32_t d = valid[j] ? (key[j] >> shift) & dmask : 0;
+            uint32_t dlo = 0, dhi = 0;
 #pragma unroll
-        for (int b = 0; b < Cfg::RADIX_BITS; ++b) {
-            if (b < bits) {
-                const bool bit = (d >> b) & 1;
-                const uint64_t t = ballot(bit);
-                peers &= bit ? t : ~t;
+            for (int b = 0; b < Cfg::RADIX_BITS; ++b) {
+                if (decltype(full)::value || b < bits) {
+                    const uint32_t bit = (d >> b) & 1u;
+                    const uint64_t t = ballot(bit != 0);
+                    const uint32_t m = 0u - bit;
+                    dlo |= (uint32_t)t ^ m;
+                    dhi |= (uint32_t)(t >> 32) ^ m;
+                }
+            }
+            const uint64_t peers = ballot(valid[j]) & ~(((uint64_t)dhi << 32) | dlo);
+            if (valid[j]) {
+                const uint32_t before = sm.u.wave_hist[w][d];
+                const uint64_t lower = peers & lanemask_lt();
+                pos[j] = before + popc64(lower);
+                if ((peers >> l) == 1) sm.u.wave_hist[w][d] = before + popc64(peers);   // last peer
             }
         }
-        if (valid[j]) {
-            const uint32_t before = sm.u.wave_hist[w][d];
-            const uint64_t lower = peers & lanemask_lt();
-            pos[j] = before + popc64(lower);
-            if ((peers >> l) == 1) sm.u.wave_hist[w][d] = before + popc64(peers);   // last peer
-        }
-    }
+    };
+    if (bits == Cfg::RADIX_BITS) rank(std::true_type{});
+    else rank(std::false_type{});
     __syncthreads();
 
     // Per digit: exclusive prefix over waves (in place), tile count, publish
