@@ -50,6 +50,8 @@ def _L():
         lib.orc_sort_pairs.restype = None
         lib.orc_join.argtypes = [vp, vp, i64, vp, vp, i64, vp, vp, i64]
         lib.orc_join.restype = i64
+        lib.orc_join_kind.argtypes = [ctypes.c_int, vp, vp, i64, vp, vp, i64, vp, vp, i64]
+        lib.orc_join_kind.restype = i64
         lib.orc_groupby.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, i64]
         lib.orc_groupby.restype = i64
         lib.orc_fragment_flags.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp, vp, i64, i32, i32,
@@ -114,6 +116,25 @@ def join(lkey, rkey, lrow=None, rrow=None, cap=None):
     ol, orr = np.empty(max(1, cap), np.int32), np.empty(max(1, cap), np.int32)
     J = _L().orc_join(lkey.ctypes.data, _p(lrow), len(lkey), rkey.ctypes.data, _p(rrow), len(rkey),
                       ol.ctypes.data, orr.ctypes.data, cap)
+    w = min(J, cap)
+    return ol[:w].copy(), orr[:w].copy(), J
+
+
+JOIN_INNER, JOIN_LEFT_SEMI, JOIN_LEFT_ANTI, JOIN_LEFT_OUTER = 0, 1, 2, 3
+
+
+def join_kind(kind, lkey, rkey, lrow=None, rrow=None, cap=None):
+    """Inner (0), left semi (1), left anti (2) or left outer (3) join: rows (left payload,
+    right payload or -1) in left order, then right order, and the true count."""
+    lkey, rkey = _c(lkey, np.int32), _c(rkey, np.int32)
+    lrow = None if lrow is None else _c(lrow, np.int32)
+    rrow = None if rrow is None else _c(rrow, np.int32)
+    if cap is None:
+        cap = _L().orc_join_kind(kind, lkey.ctypes.data, _p(lrow), len(lkey), rkey.ctypes.data, _p(rrow),
+                                 len(rkey), None, None, 0)
+    ol, orr = np.empty(max(1, cap), np.int32), np.empty(max(1, cap), np.int32)
+    J = _L().orc_join_kind(kind, lkey.ctypes.data, _p(lrow), len(lkey), rkey.ctypes.data, _p(rrow), len(rkey),
+                           ol.ctypes.data, orr.ctypes.data, cap)
     w = min(J, cap)
     return ol[:w].copy(), orr[:w].copy(), J
 

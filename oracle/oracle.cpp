@@ -19,7 +19,9 @@
 //               whose keys are equal; late materialisation returns index
 //               pairs.  Canonical order: left input order, then right input
 //               order (for key-sorted inputs this is the left-major order of
-//               the quotient / remainder step of Algorithm 1).
+//               the quotient / remainder step of Algorithm 1).  Left semi,
+//               left anti and left outer joins (Section 5) mark a missing
+//               right row with -1.
 //   group-by    Section 5.4 / Algorithm 2: one output row per distinct key,
 //               in ascending key order, with sum, count and average.
 //   fragments   the whole filter -> join -> group-by query of the workloads,
@@ -141,6 +143,44 @@ int64_t orc_join(const int32_t* lkey, const int32_t* lrow, int64_t nl, const int
                 out_r[w] = rrow ? rrow[j] : static_cast<int32_t>(j);
             }
             ++w;
+        }
+    }
+    return w;
+}
+
+// Join kinds (the operator list at the start of Section 5 names left-outer,
+// left-semi and left-anti joins beside the natural join; Section 5.2 reaches
+// them by small changes to the sort-based join).  kind 0: inner, as orc_join.  kind 1, left semi: one row
+// (lrow[i], -1) for every left row with at least one match.  kind 2, left
+// anti: (lrow[i], -1) for every left row with none.  kind 3, left outer: the
+// inner pairs of every left row, or (lrow[i], -1) when it has none.  Left
+// input order, then right input order.  At most cap rows written; returns
+// the true count.
+int64_t orc_join_kind(int kind, const int32_t* lkey, const int32_t* lrow, int64_t nl, const int32_t* rkey,
+                      const int32_t* rrow, int64_t nr, int32_t* out_l, int32_t* out_r, int64_t cap) {
+    std::unordered_map<int32_t, std::vector<int64_t>> right;
+    right.reserve(static_cast<size_t>(nr));
+    for (int64_t j = 0; j < nr; ++j) right[rkey[j]].push_back(j);
+    int64_t w = 0;
+    auto put = [&](int32_t l, int32_t r) {
+        if (w < cap) {
+            out_l[w] = l;
+            out_r[w] = r;
+        }
+        ++w;
+    };
+    for (int64_t i = 0; i < nl; ++i) {
+        const int32_t l = lrow ? lrow[i] : static_cast<int32_t>(i);
+        auto it = right.find(lkey[i]);
+        const bool matched = it != right.end();
+        if (kind == 1) {
+            if (matched) put(l, -1);
+        } else if (kind == 2) {
+            if (!matched) put(l, -1);
+        } else if (matched) {
+            for (int64_t j : it->second) put(l, rrow ? rrow[j] : static_cast<int32_t>(j));
+        } else if (kind == 3) {
+            put(l, -1);
         }
     }
     return w;

@@ -115,6 +115,56 @@ def check_join():
     assert J == 6 and list(zip(ol, orr)) == [(0, 0), (0, 1), (1, 0)]
 
 
+def _brute_join_kind(kind, lkey, rkey, lrow, rrow):
+    """Join kinds written out from their definitions, one left row at a time."""
+    out = []
+    for i in range(len(lkey)):
+        hits = [int(rrow[j]) for j in range(len(rkey)) if rkey[j] == lkey[i]]
+        if kind == oracle.JOIN_INNER:
+            out += [(int(lrow[i]), r) for r in hits]
+        elif kind == oracle.JOIN_LEFT_SEMI:
+            out += [(int(lrow[i]), -1)] if hits else []
+        elif kind == oracle.JOIN_LEFT_ANTI:
+            out += [] if hits else [(int(lrow[i]), -1)]
+        else:
+            out += [(int(lrow[i]), r) for r in hits] if hits else [(int(lrow[i]), -1)]
+    return out
+
+
+def check_join_kinds():
+    rng = _rng(31)
+    kinds = (oracle.JOIN_INNER, oracle.JOIN_LEFT_SEMI, oracle.JOIN_LEFT_ANTI, oracle.JOIN_LEFT_OUTER)
+    for trial in range(10):
+        nl, nr = int(rng.integers(0, 200)), int(rng.integers(0, 80))
+        hi = int(rng.integers(1, 50))
+        lkey = np.sort(rng.integers(0, hi, nl)).astype(np.int32)
+        rkey = np.sort(rng.integers(0, hi, nr)).astype(np.int32)
+        lrow = rng.permutation(max(nl, 1))[:nl].astype(np.int32)
+        rrow = rng.permutation(max(nr, 1))[:nr].astype(np.int32)
+        got = {}
+        for kind in kinds:
+            ol, orr, J = oracle.join_kind(kind, lkey, rkey, lrow, rrow)
+            want = _brute_join_kind(kind, lkey, rkey, lrow, rrow)
+            assert J == len(want), ("join kind size", kind, trial)
+            assert list(zip(ol.tolist(), orr.tolist())) == want, ("join kind rows", kind, trial)
+            got[kind] = (ol, orr)
+        # semi and anti split the left rows: membership by np.isin, in order
+        member = np.isin(lkey, rkey)
+        assert np.array_equal(got[oracle.JOIN_LEFT_SEMI][0], lrow[member])
+        assert np.array_equal(got[oracle.JOIN_LEFT_ANTI][0], lrow[~member])
+        # inner equals the plain join; outer is inner plus one row per unmatched left row
+        ol, orr, _ = oracle.join(lkey, rkey, lrow, rrow)
+        assert np.array_equal(got[oracle.JOIN_INNER][0], ol) and np.array_equal(got[oracle.JOIN_INNER][1], orr)
+        o_l, o_r = got[oracle.JOIN_LEFT_OUTER]
+        assert len(o_l) == len(ol) + int((~member).sum())
+        assert np.array_equal(o_l[o_r != -1], ol) and np.array_equal(o_r[o_r != -1], orr)
+        assert np.array_equal(o_l[o_r == -1], lrow[~member])
+    # capacity: the first cap rows, true count returned
+    ol, orr, J = oracle.join_kind(oracle.JOIN_LEFT_OUTER, np.array([1, 2, 3], np.int32),
+                                  np.array([2, 2], np.int32), cap=2)
+    assert J == 4 and list(zip(ol, orr)) == [(0, -1), (1, 0)]
+
+
 # --------------------------------------------------------------------------- group-by
 
 def check_groupby():
@@ -243,5 +293,5 @@ def check_topk_ties():
     assert got["top_key"].tolist() == [1, 4, 7] and got["top_sum"].tolist() == [10000] * 3
 
 
-ALL_CHECKS = [check_filter, check_sort, check_join, check_groupby, check_fragment_flags,
+ALL_CHECKS = [check_filter, check_sort, check_join, check_join_kinds, check_groupby, check_fragment_flags,
               check_fragment_flags_invariants, check_fragment_cust, check_topk_ties]
