@@ -158,6 +158,25 @@ tqp_status tqp_join(tqp_ctx* ctx, const int32_t* lkey, const int32_t* lrow, int6
                     const int64_t* d_nr, int32_t* out_l, int32_t* out_r, int64_t cap,
                     int64_t* d_count, void* ws, size_t* ws_bytes, hipStream_t stream);
 
+/* Join kinds (the operator list at the start of Section 5; Section 5.2 gets
+ * them from Algorithm 1 by changing the number of output rows per left row):
+ *   TQP_JOIN_INNER       as tqp_join;
+ *   TQP_JOIN_LEFT_SEMI   one row (lrow[i], -1) per left row with a match;
+ *   TQP_JOIN_LEFT_ANTI   one row (lrow[i], -1) per left row without one;
+ *   TQP_JOIN_LEFT_OUTER  the inner rows of every left row, or (lrow[i], -1)
+ *                        when it has no match.
+ * Rows in left order, then right order.  Arguments, sizes, sortedness and
+ * capacity as tqp_join; out_r may be NULL for the semi and anti joins (it
+ * would hold only -1).  An unknown kind returns TQP_ERR_INVALID. */
+#define TQP_JOIN_INNER 0
+#define TQP_JOIN_LEFT_SEMI 1
+#define TQP_JOIN_LEFT_ANTI 2
+#define TQP_JOIN_LEFT_OUTER 3
+tqp_status tqp_join_kind(tqp_ctx* ctx, int kind, const int32_t* lkey, const int32_t* lrow, int64_t nl,
+                         const int64_t* d_nl, const int32_t* rkey, const int32_t* rrow, int64_t nr,
+                         const int64_t* d_nr, int32_t* out_l, int32_t* out_r, int64_t cap,
+                         int64_t* d_count, void* ws, size_t* ws_bytes, hipStream_t stream);
+
 /* ---------------------------------------------------------------- group-by
  * Section 5.4, Algorithm 2: sort the group keys, permute the value columns
  * by the sorted order, find the runs of equal keys and evaluate the

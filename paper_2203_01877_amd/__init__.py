@@ -22,12 +22,13 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import (DEVERR_CAPACITY, DEVERR_KEY_RANGE, DEVERR_SPIN, DEVERR_VALUE_RANGE, TQP_EQ, TQP_GE, TQP_GT,
-                   TQP_LE, TQP_LT, TQP_NE, TQPError, check)
+from ._lib import (DEVERR_CAPACITY, DEVERR_KEY_RANGE, DEVERR_SPIN, DEVERR_VALUE_RANGE, JOIN_INNER, JOIN_LEFT_ANTI,
+                   JOIN_LEFT_OUTER, JOIN_LEFT_SEMI, TQP_EQ, TQP_GE, TQP_GT, TQP_LE, TQP_LT, TQP_NE, TQPError, check)
 
 __all__ = ["Context", "filter", "sort", "join", "groupby_agg", "topk", "FlagsFragmentRunner",
            "CustFragmentRunner", "BatchRunner", "Server", "TQPError", "TQP_LT", "TQP_LE", "TQP_GT", "TQP_GE", "TQP_EQ", "TQP_NE",
-           "DEVERR_KEY_RANGE", "DEVERR_SPIN", "DEVERR_CAPACITY", "DEVERR_VALUE_RANGE"]
+           "DEVERR_KEY_RANGE", "DEVERR_SPIN", "DEVERR_CAPACITY", "DEVERR_VALUE_RANGE", "JOIN_INNER", "JOIN_LEFT_SEMI",
+           "JOIN_LEFT_ANTI", "JOIN_LEFT_OUTER"]
 
 _DTYPES = {torch.int8: _lib.TQP_I8, torch.int32: _lib.TQP_I32, torch.int64: _lib.TQP_I64}
 
@@ -135,8 +136,9 @@ def sort(ctx: Context, keys, vals=None, key_bits: int = 0, perm: bool = False, d
 
 
 def join(ctx: Context, lkey, rkey, lrow=None, rrow=None, cap: int | None = None, d_nl=None, d_nr=None,
-         stream=None):
-    """Sort-based equi-join of key-sorted inputs.  Returns (out_l, out_r, d_count)."""
+         stream=None, kind: int = JOIN_INNER):
+    """Sort-based join of key-sorted inputs: inner (default), or JOIN_LEFT_SEMI / JOIN_LEFT_ANTI /
+    JOIN_LEFT_OUTER (-1 marks a missing right row).  Returns (out_l, out_r, d_count)."""
     nl, nr = lkey.numel(), rkey.numel()
     cap = nl if cap is None else cap
     dev = _dev(ctx)
@@ -144,8 +146,13 @@ def join(ctx: Context, lkey, rkey, lrow=None, rrow=None, cap: int | None = None,
     orr = torch.empty(max(1, cap), dtype=torch.int32, device=dev)
     cnt = torch.empty(1, dtype=torch.int64, device=dev)
     s = _stream(stream)
-    _run(lambda ws, sz: ctx.lib.tqp_join(ctx.h, _p(lkey), _p(lrow), nl, _p(d_nl), _p(rkey), _p(rrow), nr, _p(d_nr),
-                                         _p(ol), _p(orr), cap, _p(cnt), ws, sz, s), "tqp_join", dev)
+    if kind == JOIN_INNER:
+        _run(lambda ws, sz: ctx.lib.tqp_join(ctx.h, _p(lkey), _p(lrow), nl, _p(d_nl), _p(rkey), _p(rrow), nr,
+                                             _p(d_nr), _p(ol), _p(orr), cap, _p(cnt), ws, sz, s), "tqp_join", dev)
+    else:
+        _run(lambda ws, sz: ctx.lib.tqp_join_kind(ctx.h, kind, _p(lkey), _p(lrow), nl, _p(d_nl), _p(rkey), _p(rrow),
+                                                  nr, _p(d_nr), _p(ol), _p(orr), cap, _p(cnt), ws, sz, s),
+             "tqp_join_kind", dev)
     return ol, orr, cnt
 
 

@@ -15,6 +15,7 @@ STATUS_NAMES = {0: "TQP_OK", 1: "TQP_ERR_INVALID", 2: "TQP_ERR_WORKSPACE", 3: "T
                 4: "TQP_ERR_HIP", 5: "TQP_ERR_UNSUPPORTED"}
 TQP_I8, TQP_I32, TQP_I64 = 1, 2, 3
 TQP_LT, TQP_LE, TQP_GT, TQP_GE, TQP_EQ, TQP_NE = range(6)
+JOIN_INNER, JOIN_LEFT_SEMI, JOIN_LEFT_ANTI, JOIN_LEFT_OUTER = range(4)
 DEVERR_KEY_RANGE, DEVERR_SPIN, DEVERR_CAPACITY, DEVERR_VALUE_RANGE = 1, 2, 4, 8
 
 
@@ -115,6 +116,8 @@ def load() -> ctypes.CDLL:
     lib.tqp_join.argtypes = [c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_i64, c_vp,
                              c_vp, c_size_p, c_vp]
     lib.tqp_join.restype = S
+    lib.tqp_join_kind.argtypes = [c_vp, c_i32] + lib.tqp_join.argtypes[1:]
+    lib.tqp_join_kind.restype = S
     lib.tqp_groupby_agg.argtypes = [c_vp, c_vp, c_i64, c_vp, c_int, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i64,
                                     c_vp, c_vp, c_size_p, c_vp]
     lib.tqp_groupby_agg.restype = S

@@ -40,7 +40,7 @@ JoinBufs join_reserve(Arena& a, int64_t nl_upper) {
 // tiles); aggregating emitters need only the join size and run the expansion
 // directly.  Either way *d_count ends up holding the join size; for the
 // aggregating form it must be zero on entry.
-template <class Cfg, class LP, class RP, class Emit>
+template <class Cfg, class LP, class RP, class Emit, int KIND = JOIN_INNER>
 tqp_status join_launch(tqp_ctx* ctx, hipStream_t s, const char* name, const JoinBufs& b, const uint32_t* lkey,
                        const LP* lpay, int64_t nl, const int64_t* d_nl, const uint32_t* rkey, const RP* rpay,
                        int64_t nr, const int64_t* d_nr, int64_t* d_count, int64_t cap, const Emit& e,
@@ -58,9 +58,9 @@ tqp_status join_launch(tqp_ctx* ctx, hipStream_t s, const char* name, const Join
     static const int per_cu = [] {
         int a = 8, b = 8;
         if (Emit::ORDERED &&
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_join_count<Cfg>, Cfg::BLOCK, 0) != hipSuccess)
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_join_count<Cfg, KIND>, Cfg::BLOCK, 0) != hipSuccess)
             a = 4;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_join<Cfg, LP, RP, Emit>, Cfg::BLOCK, 0) != hipSuccess)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_join<Cfg, LP, RP, Emit, KIND>, Cfg::BLOCK, 0) != hipSuccess)
             b = 4;
         const int m = a < b ? a : b;
         return m < 1 ? 1 : m > 8 ? 8 : m;
@@ -68,11 +68,11 @@ tqp_status join_launch(tqp_ctx* ctx, hipStream_t s, const char* name, const Join
     const int grid = grid_for(tiles, 1, (int64_t)ctx->num_cus * per_cu);
     if (Emit::ORDERED && tiles > 0) {
         TQP_LAUNCH(ctx, s, "join_count",
-                   k_join_count<Cfg><<<grid, Cfg::BLOCK, 0, s>>>(lkey, nl, d_nl, rkey, b.win, b.tile_cnt,
+                   k_join_count<Cfg, KIND><<<grid, Cfg::BLOCK, 0, s>>>(lkey, nl, d_nl, rkey, b.win, b.tile_cnt,
                                                                  b.blk_total, lowb));
     }
     TQP_LAUNCH(ctx, s, name,
-               (k_join<Cfg, LP, RP, Emit><<<grid, Cfg::BLOCK, 0, s>>>(
+               (k_join<Cfg, LP, RP, Emit, KIND><<<grid, Cfg::BLOCK, 0, s>>>(
                    lkey, lpay, nl, d_nl, rkey, rpay, b.win, b.counter, b.tile_cnt, b.blk_total, d_count,
                    d_count_out, cap, e, ctx->d_err, lowb)));
     return TQP_OK;

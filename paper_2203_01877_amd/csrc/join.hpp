@@ -41,6 +41,22 @@ struct JoinCfg {
 constexpr int TABLE_ITEMS = 4;
 constexpr int COUNT_TABLE_ITEMS = 8;
 
+// Join kinds: the inner join, and the left semi, left anti and left outer
+// joins of the operator list at the start of Section 5, which Section 5.2
+// reaches by small changes to the sort-based join.  Only the number of output
+// rows per left element changes: semi keeps an element with at least one
+// match once, anti keeps one with none, outer emits an unmatched element once
+// with no right row.  A missing right row is written as -1 (JOIN_NONE).
+constexpr int JOIN_INNER = 0, JOIN_SEMI = 1, JOIN_ANTI = 2, JOIN_OUTER = 3;
+constexpr uint32_t JOIN_NONE = 0xFFFFFFFFu;
+template <int KIND>
+__device__ __forceinline__ int64_t join_out_rows(int64_t matches) {
+    if constexpr (KIND == JOIN_SEMI) return matches > 0;
+    else if constexpr (KIND == JOIN_ANTI) return matches == 0;
+    else if constexpr (KIND == JOIN_OUTER) return matches > 0 ? matches : 1;
+    else return matches;
+}
+
 // Matches of one left element at most this many are emitted by its own lane;
 // elements with more are expanded by the whole wave, 64 outputs at a time.
 constexpr int JOIN_LANE_MAX = 4;
@@ -57,7 +73,7 @@ struct EmitPairs {
     __device__ void operator()(int64_t o, uint32_t, uint32_t lp, uint32_t rp, Smem&) {
         if (o < cap) {
             out_l[o] = (int32_t)lp;
-            out_r[o] = (int32_t)rp;
+            if (out_r) out_r[o] = (int32_t)rp;
         }
     }
     __device__ void finish(Smem&) {}
@@ -218,7 +234,7 @@ __device__ __forceinline__ void tile_key_range(const TileGeo& g, int lowb, uint3
 // Output rows of one left tile, for the counting kernel of the two-kernel
 // join: the same direct table (counts only) or global searches as join_tile,
 // with no payload traffic.  The value is returned to every thread.
-template <class Cfg, class RP>
+template <class Cfg, class RP, int KIND = JOIN_INNER>
 __device__ __forceinline__ int64_t join_tile_count(const uint32_t* lkey, int64_t nl, const uint32_t* rkey,
                                                    const TileGeo& g, int64_t tile, JoinSmem<Cfg, RP>& sm,
                                                    int lowb) {
@@ -287,10 +303,10 @@ __device__ __forceinline__ int64_t join_tile_count(const uint32_t* lkey, int64_t
         if (i < nl) {
             if (direct) {
                 const uint32_t v = key[j] - kmin;
-                if (v <= kmax - kmin) c += sm.cnt[v];
+                c += join_out_rows<KIND>(v <= kmax - kmin ? sm.cnt[v] : 0);
             } else {
                 const int64_t lb = lower_bound_glb(rkey, wlo, whi, key[j]);
-                c += upper_bound_glb(rkey, lb, whi, key[j]) - lb;
+                c += join_out_rows<KIND>(upper_bound_glb(rkey, lb, whi, key[j]) - lb);
             }
         }
     }
@@ -306,7 +322,7 @@ __device__ __forceinline__ int64_t join_tile_count(const uint32_t* lkey, int64_t
 // base: the tile's output base (emitters that write at output positions;
 // the counting kernel's totals give it).  Emitters that only aggregate add
 // the tile's total to *d_count instead.
-template <class Cfg, class LP, class RP, class Emit>
+template <class Cfg, class LP, class RP, class Emit, int KIND = JOIN_INNER>
 __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, int64_t nl, const uint32_t* rkey,
                                           const RP* rpay, const TileGeo& g, int64_t tile, int64_t base,
                                           int64_t* d_count, Emit& e, typename Emit::Smem& esm,
@@ -378,6 +394,11 @@ __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, 
     // wave scans, which costs less than holding them across the look-back.
     int32_t cnt[ITEMS], first[ITEMS];
     int64_t wave_total = 0;
+    // output rows of item j (its matches for the inner join)
+    auto out_rows = [&](int j) -> int64_t {
+        if constexpr (KIND == JOIN_INNER) return cnt[j];
+        else return chunk + j * WAVE + l < nl ? join_out_rows<KIND>(cnt[j]) : 0;
+    };
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const int64_t i = chunk + j * WAVE + l;
@@ -397,7 +418,7 @@ __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, 
                 cnt[j] = (int32_t)(ub - lb);
             }
         }
-        wave_total += wave_sum((int64_t)cnt[j]);
+        wave_total += wave_sum(out_rows(j));
     }
     if (l == 0) sm.wave[w] = wave_total;
     __syncthreads();
@@ -417,7 +438,7 @@ __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, 
     // Writing emitters read the first match of every element ahead of the
     // stores (independent reads: their latencies overlap); the aggregating
     // ones keep their registers for the gathers.
-    constexpr bool AHEAD = Emit::ORDERED;
+    constexpr bool AHEAD = Emit::ORDERED && (KIND == JOIN_INNER || KIND == JOIN_OUTER);
     RP r0[AHEAD ? ITEMS : 1];
     if constexpr (AHEAD) {
 #pragma unroll
@@ -425,9 +446,17 @@ __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, 
     }
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-        const int64_t incl = wave_incl_sum((int64_t)cnt[j]);
-        const int64_t o = wbase + incl - cnt[j];
+        const int64_t oc = out_rows(j);
+        const int64_t incl = wave_incl_sum(oc);
+        const int64_t o = wbase + incl - oc;
         wbase += wave_read(incl, WAVE - 1);
+        if constexpr (KIND == JOIN_SEMI || KIND == JOIN_ANTI) {
+            if (oc) e(o, key[j], pay[j], (RP)JOIN_NONE, esm);
+            continue;
+        }
+        if constexpr (KIND == JOIN_OUTER) {
+            if (oc && cnt[j] == 0) e(o, key[j], pay[j], (RP)JOIN_NONE, esm);
+        }
         const bool small = cnt[j] <= JOIN_LANE_MAX;
         if constexpr (AHEAD) {
             if (small && cnt[j] > 0) {
@@ -463,7 +492,7 @@ __device__ __forceinline__ void join_block_range(int64_t ntiles, int64_t& t0, in
 
 // Per-tile output counts (first kernel of the two-kernel join): tile_cnt of
 // every tile and blk_total of every block's contiguous range of tiles.
-template <class Cfg>
+template <class Cfg, int KIND = JOIN_INNER>
 __global__ void __launch_bounds__(Cfg::BLOCK)
 k_join_count(const uint32_t* lkey, int64_t nl_upper, const int64_t* d_nl, const uint32_t* rkey,
              const int64_t* win, int64_t* tile_cnt, int64_t* blk_total, int lowb) {
@@ -478,7 +507,7 @@ k_join_count(const uint32_t* lkey, int64_t nl_upper, const int64_t* d_nl, const 
     for (int64_t tile = t0; tile < t1; ++tile) {
         const TileGeo cur = g;
         if (tile + 1 < t1) g = tile_geo(lkey, nl, win, tile + 1, Cfg::TILE);     // one tile ahead
-        const int64_t t = join_tile_count<Cfg, uint8_t>(lkey, nl, rkey, cur, tile, sm, lowb);
+        const int64_t t = join_tile_count<Cfg, uint8_t, KIND>(lkey, nl, rkey, cur, tile, sm, lowb);
         if (threadIdx.x == 0) tile_cnt[tile] = t;
         sum += t;
     }
@@ -492,7 +521,7 @@ k_join_count(const uint32_t* lkey, int64_t nl_upper, const int64_t* d_nl, const 
 // emitters: tiles are pulled from a
 // counter.  The kernel is persistent, so emitters can accumulate across tiles
 // and flush once.
-template <class Cfg, class LP, class RP, class Emit>
+template <class Cfg, class LP, class RP, class Emit, int KIND = JOIN_INNER>
 __global__ void __launch_bounds__(Cfg::BLOCK)
 k_join(const uint32_t* lkey, const LP* lpay, int64_t nl_upper, const int64_t* d_nl,
        const uint32_t* rkey, const RP* rpay, const int64_t* win, uint32_t* tile_counter, const int64_t* tile_cnt,
@@ -519,8 +548,8 @@ k_join(const uint32_t* lkey, const LP* lpay, int64_t nl_upper, const int64_t* d_
         for (int64_t tile = t0; tile < t1; ++tile) {
             const int64_t base = run;
             run += tile_cnt[tile];
-            join_tile<Cfg, LP, RP, Emit>(lkey, lpay, nl, rkey, rpay, tile_geo(lkey, nl, win, tile, Cfg::TILE), tile,
-                                         base, d_count, e, esm, sm, lowb);
+            join_tile<Cfg, LP, RP, Emit, KIND>(lkey, lpay, nl, rkey, rpay, tile_geo(lkey, nl, win, tile, Cfg::TILE),
+                                               tile, base, d_count, e, esm, sm, lowb);
         }
         if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
             *d_count = run;
@@ -533,8 +562,8 @@ k_join(const uint32_t* lkey, const LP* lpay, int64_t nl_upper, const int64_t* d_
             __syncthreads();
             const int64_t tile = sm.tile;
             if (tile >= ntiles) break;
-            join_tile<Cfg, LP, RP, Emit>(lkey, lpay, nl, rkey, rpay, tile_geo(lkey, nl, win, tile, Cfg::TILE), tile,
-                                         0, d_count, e, esm, sm, lowb);
+            join_tile<Cfg, LP, RP, Emit, KIND>(lkey, lpay, nl, rkey, rpay, tile_geo(lkey, nl, win, tile, Cfg::TILE),
+                                               tile, 0, d_count, e, esm, sm, lowb);
         }
     }
     e.finish(esm);

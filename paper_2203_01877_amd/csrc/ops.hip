@@ -149,13 +149,16 @@ tqp_status tqp_sort(tqp_ctx* ctx, const int32_t* keys, const int32_t* vals, int6
     });
 }
 
-tqp_status tqp_join(tqp_ctx* ctx, const int32_t* lkey, const int32_t* lrow, int64_t nl, const int64_t* d_nl,
-                    const int32_t* rkey, const int32_t* rrow, int64_t nr, const int64_t* d_nr, int32_t* out_l,
-                    int32_t* out_r, int64_t cap, int64_t* d_count, void* ws, size_t* ws_bytes,
-                    hipStream_t stream) {
+tqp_status tqp_join_kind(tqp_ctx* ctx, int kind, const int32_t* lkey, const int32_t* lrow, int64_t nl,
+                         const int64_t* d_nl, const int32_t* rkey, const int32_t* rrow, int64_t nr,
+                         const int64_t* d_nr, int32_t* out_l, int32_t* out_r, int64_t cap, int64_t* d_count,
+                         void* ws, size_t* ws_bytes, hipStream_t stream) {
     clear_error();
+    if (kind < TQP_JOIN_INNER || kind > TQP_JOIN_LEFT_OUTER)
+        return fail(TQP_ERR_INVALID, "tqp_join_kind: kind %d", kind);
+    const bool need_r = kind == TQP_JOIN_INNER || kind == TQP_JOIN_LEFT_OUTER;
     if (!ctx || !d_count || nl < 0 || nr < 0 || cap < 0 || (nl > 0 && !lkey) || (nr > 0 && !rkey) ||
-        (cap > 0 && (!out_l || !out_r)))
+        (cap > 0 && (!out_l || (need_r && !out_r))))
         return fail(TQP_ERR_INVALID, "tqp_join: null pointer or negative size");
     if (nl > MAX_ELEMS || nr > MAX_ELEMS) return fail(TQP_ERR_UNSUPPORTED, "tqp_join: input too large");
     JoinBufs b;
@@ -165,14 +168,28 @@ tqp_status tqp_join(tqp_ctx* ctx, const int32_t* lkey, const int32_t* lrow, int6
     if (st != TQP_OK || !ws) return st;
     if ((st = fill_zero(a.base, a.zsize, stream, ctx)) != TQP_OK) return st;
     EmitPairs e{out_l, out_r, cap};
-    if ((st = join_launch<JCfg, uint32_t, uint32_t>(ctx, stream, "join_pairs", b,
-                                                    reinterpret_cast<const uint32_t*>(lkey),
-                                                    reinterpret_cast<const uint32_t*>(lrow), nl, d_nl,
-                                                    reinterpret_cast<const uint32_t*>(rkey),
-                                                    reinterpret_cast<const uint32_t*>(rrow), nr, d_nr, d_count, cap,
-                                                    e)) != TQP_OK)
-        return st;
-    return TQP_OK;
+    const uint32_t* lk = reinterpret_cast<const uint32_t*>(lkey);
+    const uint32_t* lp = reinterpret_cast<const uint32_t*>(lrow);
+    const uint32_t* rk = reinterpret_cast<const uint32_t*>(rkey);
+    const uint32_t* rp = reinterpret_cast<const uint32_t*>(rrow);
+    auto run = [&](auto kc, const char* name) {
+        return join_launch<JCfg, uint32_t, uint32_t, EmitPairs, decltype(kc)::value>(
+            ctx, stream, name, b, lk, lp, nl, d_nl, rk, rp, nr, d_nr, d_count, cap, e);
+    };
+    switch (kind) {
+        case TQP_JOIN_LEFT_SEMI: return run(std::integral_constant<int, JOIN_SEMI>{}, "join_semi");
+        case TQP_JOIN_LEFT_ANTI: return run(std::integral_constant<int, JOIN_ANTI>{}, "join_anti");
+        case TQP_JOIN_LEFT_OUTER: return run(std::integral_constant<int, JOIN_OUTER>{}, "join_outer");
+        default: return run(std::integral_constant<int, JOIN_INNER>{}, "join_pairs");
+    }
+}
+
+tqp_status tqp_join(tqp_ctx* ctx, const int32_t* lkey, const int32_t* lrow, int64_t nl, const int64_t* d_nl,
+                    const int32_t* rkey, const int32_t* rrow, int64_t nr, const int64_t* d_nr, int32_t* out_l,
+                    int32_t* out_r, int64_t cap, int64_t* d_count, void* ws, size_t* ws_bytes,
+                    hipStream_t stream) {
+    return tqp_join_kind(ctx, TQP_JOIN_INNER, lkey, lrow, nl, d_nl, rkey, rrow, nr, d_nr, out_l, out_r, cap,
+                         d_count, ws, ws_bytes, stream);
 }
 
 tqp_status tqp_groupby_agg(tqp_ctx* ctx, const int32_t* gkey, int64_t n, const int64_t* d_n, int key_bits,

@@ -28,7 +28,7 @@ def _lib():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for required in ("tqp_filter", "tqp_sort", "tqp_join", "tqp_groupby_agg", "tqp_topk",
+    for required in ("tqp_filter", "tqp_sort", "tqp_join", "tqp_join_kind", "tqp_groupby_agg", "tqp_topk",
                      "tqp_fragment_flags", "tqp_fragment_cust", "tqp_ctx_create"):
         assert required in names
 
@@ -37,6 +37,17 @@ def test_every_declared_symbol_is_exported():
     lib = _lib()
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
+
+
+def test_unknown_join_kind_is_rejected_without_a_device():
+    lib = _lib()
+    lib.tqp_join_kind.restype = ctypes.c_int
+    sz = ctypes.c_size_t(0)
+    st = lib.tqp_join_kind(None, 9, None, None, ctypes.c_int64(0), None, None, None, ctypes.c_int64(0), None, None,
+                           None, ctypes.c_int64(0), None, None, ctypes.byref(sz), None)
+    assert st == 1
+    lib.tqp_last_error.restype = ctypes.c_char_p
+    assert b"kind 9" in lib.tqp_last_error()
 
 
 def test_null_arguments_are_rejected_without_a_device():

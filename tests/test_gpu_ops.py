@@ -140,6 +140,41 @@ def _join_case(hip, ctx, lkey, rkey, cap=None):
     assert np.array_equal(_np(ol, w), wl) and np.array_equal(_np(orr, w), wr)
 
 
+_KINDS = {"semi": 1, "anti": 2, "outer": 3, "inner": 0}
+
+
+@pytest.mark.parametrize("kind", list(_KINDS))
+@pytest.mark.parametrize("nl,nr,hi", [(0, 10, 5), (10, 0, 5), (1, 1, 1), (5000, 300, 1500), (300_007, 40_000, 150_000),
+                                      (4097, 5, 3), (250_000, 60_000, 400_000), (20_000, 20_000, 1_000_000)])
+def test_join_kinds(hip, ctx, kind, nl, nr, hi):
+    """Left semi / anti / outer joins against the oracle: the rows, their
+    order and the count, over windows that fit the LDS table and ones that
+    do not (few distinct keys), with empty sides and partial tiles."""
+    k = _KINDS[kind]
+    rng = _rng(nl * 7 + nr + k)
+    lkey = np.sort(rng.integers(0, hi, nl)).astype(np.int32)
+    rkey = np.sort(rng.integers(0, hi, nr)).astype(np.int32)
+    lrow = rng.permutation(max(1, nl))[:nl].astype(np.int32)
+    rrow = rng.permutation(max(1, nr))[:nr].astype(np.int32)
+    wl, wr, J = oracle.join_kind(k, lkey, rkey, lrow, rrow)
+    ol, orr, cnt = hip.join(ctx, _dev(lkey), _dev(rkey), _dev(lrow), _dev(rrow), cap=max(J, 1), kind=k)
+    assert int(_np(cnt)[0]) == J
+    assert np.array_equal(_np(ol, J), wl)
+    assert np.array_equal(_np(orr, J), wr)
+    assert ctx.errors() == 0
+
+
+def test_join_kind_capacity(hip, ctx):
+    """Past the capacity only the count is exact and the flag is raised."""
+    lkey = np.sort(_rng(3).integers(0, 100, 5000)).astype(np.int32)
+    rkey = np.arange(0, 100, 2, dtype=np.int32)
+    wl, wr, J = oracle.join_kind(3, lkey, rkey)
+    ol, orr, cnt = hip.join(ctx, _dev(lkey), _dev(rkey), cap=1000, kind=3)
+    assert int(_np(cnt)[0]) == J
+    assert np.array_equal(_np(ol, 1000), wl[:1000]) and np.array_equal(_np(orr, 1000), wr[:1000])
+    assert ctx.errors() == hip.DEVERR_CAPACITY
+
+
 @pytest.mark.parametrize("nl,nr,hi", [(0, 10, 5), (10, 0, 5), (1, 1, 1), (5000, 300, 1500), (300_007, 40_000, 150_000),
                                       (200_000, 150_000, 150_000), (4097, 5, 3), (20_000, 20_000, 1_000_000)])
 def test_join_parity(hip, ctx, nl, nr, hi):
