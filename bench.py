@@ -150,9 +150,10 @@ def main():
                          "and a row outside the declared width sets a device error flag)")
     ap.add_argument("--date-lt", type=int, default=None,
                     help="config 2 with another filter constant D (date < D; the workload uses 2400)")
-    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 4],
+    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 4, 5],
                     help="2: the 60M-row custkey fragment (default); 3: 256 flags fragments, batched vs plain; "
-                         "4: served mix under Poisson arrivals, concurrent vs serial")
+                         "4: served mix under Poisson arrivals, concurrent vs serial; 5: the join kinds on the "
+                         "config-2 join inputs")
     ap.add_argument("--rates", default="50,100,200,400,800", help="arrival rates (fragments/s) for --config 4")
     ap.add_argument("--requests", type=int, default=400, help="requests per rate for --config 4")
     ap.add_argument("--slots", type=int, default=8)
@@ -176,6 +177,8 @@ def main():
         sys.exit(2)
     if args.config == 3:
         return bench_batch(args)
+    if args.config == 5:
+        return bench_joins(args)
     if args.config == 4:
         return bench_serve(args)
 
@@ -322,6 +325,64 @@ def main():
                                          "%.1f s" % (N, M, dt),
                                "matches_gpu": bool(ok)}
     print(json.dumps(out), flush=True)
+
+
+def bench_joins(args):
+    """The join kinds (inner, left semi, left anti, left outer) on the config-2 join's inputs: the
+    56.3M fact keys that pass date < 2400, sorted, against the 15M sorted mid keys.  Per kind: the
+    kernels' own event durations (windows + counting + expansion), the output rows, and the
+    expansion's algorithmic bytes per second; the counts are checked against numpy's searchsorted."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2203_01877_amd as tqp
+
+    fr = datagen.config2()
+    lkey = np.sort(fr.fact["fk"][fr.fact["date"] < fr.D]).astype(np.int32)
+    rkey = np.sort(fr.mid["pk"]).astype(np.int32)
+    nl, nr = len(lkey), len(rkey)
+    hits = np.searchsorted(rkey, lkey, "right") - np.searchsorted(rkey, lkey, "left")
+    want = {tqp.JOIN_INNER: int(hits.sum()), tqp.JOIN_LEFT_SEMI: int((hits > 0).sum()),
+            tqp.JOIN_LEFT_ANTI: int((hits == 0).sum()), tqp.JOIN_LEFT_OUTER: int(np.maximum(hits, 1).sum())}
+    dev = torch.device("cuda", 0)
+    lk, rk = torch.from_numpy(lkey).to(dev), torch.from_numpy(rkey).to(dev)
+    ctx = tqp.Context(0)
+    names = {tqp.JOIN_INNER: "inner", tqp.JOIN_LEFT_SEMI: "left_semi", tqp.JOIN_LEFT_ANTI: "left_anti",
+             tqp.JOIN_LEFT_OUTER: "left_outer"}
+    expansion = {tqp.JOIN_INNER: "join_pairs", tqp.JOIN_LEFT_SEMI: "join_semi", tqp.JOIN_LEFT_ANTI: "join_anti",
+                 tqp.JOIN_LEFT_OUTER: "join_outer"}
+    out = {}
+    for kind, name in names.items():
+        cap = want[kind]
+        for _ in range(args.warmup):
+            tqp.join(ctx, lk, rk, cap=cap, kind=kind)
+        torch.cuda.synchronize()
+        ctx.profile_read()
+        ctx.set_profiling(True)
+        for _ in range(args.steps):
+            _, _, cnt = tqp.join(ctx, lk, rk, cap=cap, kind=kind)
+        torch.cuda.synchronize()
+        recs = ctx.profile_read()
+        ctx.set_profiling(False)
+        got = int(cnt.item())
+        if got != want[kind] or ctx.errors():
+            log("join %s: %d rows, expected %d" % (name, got, want[kind]))
+            sys.exit(3)
+        ms = sum(t for _, t in recs) / args.steps
+        ems = sum(t for k, t in recs if k == expansion[kind]) / args.steps
+        # expansion: left keys 4 B, window keys 4 B, output (left, right) positions 8 B per row
+        eb = 4 * nl + 4 * nr + 8 * got
+        out[name] = {"ms": round(ms, 4), "expansion_ms": round(ems, 4), "rows_out": got,
+                     "left_rows_per_s": round(nl / (ms * 1e-3), 1),
+                     "expansion_gbps": round(eb / (ems * 1e-3) / 1e9, 1)}
+        log("%s: %s" % (name, out[name]))
+    print(json.dumps({"metric": "left rows/s per join kind (sorted 56.3M x 15M keys)", "unit": "left rows/s",
+                      "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+                      "data": "synthetic", "dtype": "int32",
+                      "config": {"workload": "config-2 join inputs: %d sorted fact keys (date < %d) x %d sorted mid "
+                                             "keys, row positions as payloads" % (nl, fr.D, nr)},
+                      "kinds": out, "counts_match_numpy": True}), flush=True)
 
 
 def bench_batch(args):
