@@ -168,6 +168,19 @@ tqp_status tqp_join(tqp_ctx* ctx, const int32_t* lkey, const int32_t* lrow, int6
  * Rows in left order, then right order.  Arguments, sizes, sortedness and
  * capacity as tqp_join; out_r may be NULL for the semi and anti joins (it
  * would hold only -1).  An unknown kind returns TQP_ERR_INVALID. */
+/* Section 5.3, Algorithm 3: the hash-based equi-join.  Same rows as
+ * tqp_join (every (lrow[i], rrow[j]) with lkey[i] == rkey[j]), but the inputs
+ * need not be sorted: the right rows are chained per slot of a table of m
+ * slots (m = the power of two at or above 2 * nr, slot = key mod m), and every
+ * left row walks its slot's chain twice (count, then write).  Rows come in
+ * left input order; the rows of one left row come in no fixed right order.
+ * Keys are non-negative int32.  Arguments, device counts and capacity as
+ * tqp_join. */
+tqp_status tqp_hash_join(tqp_ctx* ctx, const int32_t* lkey, const int32_t* lrow, int64_t nl,
+                         const int64_t* d_nl, const int32_t* rkey, const int32_t* rrow, int64_t nr,
+                         const int64_t* d_nr, int32_t* out_l, int32_t* out_r, int64_t cap,
+                         int64_t* d_count, void* ws, size_t* ws_bytes, hipStream_t stream);
+
 #define TQP_JOIN_INNER 0
 #define TQP_JOIN_LEFT_SEMI 1
 #define TQP_JOIN_LEFT_ANTI 2

@@ -140,6 +140,32 @@ def _join_case(hip, ctx, lkey, rkey, cap=None):
     assert np.array_equal(_np(ol, w), wl) and np.array_equal(_np(orr, w), wr)
 
 
+@pytest.mark.parametrize("nl,nr,hi,sort", [(0, 10, 5, False), (10, 0, 5, False), (1, 1, 1, False),
+                                           (5000, 300, 1500, False), (300_007, 40_000, 150_000, False),
+                                           (200_000, 150_000, 150_000, True), (4097, 5, 3, False),
+                                           (20_000, 20_000, 1_000_000, False), (100_000, 64_000, 1_000, False)])
+def test_hash_join(hip, ctx, nl, nr, hi, sort):
+    """Hash join of unsorted inputs: the same rows as the oracle's join, left
+    rows in input order; the right rows of one left row in any order (the
+    oracle's are compared as sorted pairs).  (100000, 64000, 1000): 64 right
+    rows per key, long chains."""
+    rng = _rng(nl * 5 + nr + hi)
+    lkey = rng.integers(0, hi, nl).astype(np.int32)
+    rkey = rng.integers(0, hi, nr).astype(np.int32)
+    if sort:
+        lkey, rkey = np.sort(lkey), np.sort(rkey)
+    lrow = rng.permutation(max(1, nl))[:nl].astype(np.int32)
+    rrow = rng.permutation(max(1, nr))[:nr].astype(np.int32)
+    wl, wr, J = oracle.join(lkey, rkey, lrow, rrow)
+    ol, orr, cnt = hip.hash_join(ctx, _dev(lkey), _dev(rkey), _dev(lrow), _dev(rrow), cap=max(J, 1))
+    assert int(_np(cnt)[0]) == J
+    gl, gr = _np(ol, J), _np(orr, J)
+    assert np.array_equal(gl, wl)                           # left order is fixed
+    order_w, order_g = np.lexsort((wr, wl)), np.lexsort((gr, gl))
+    assert np.array_equal(gl[order_g], wl[order_w]) and np.array_equal(gr[order_g], wr[order_w])
+    assert ctx.errors() == 0
+
+
 _KINDS = {"semi": 1, "anti": 2, "outer": 3, "inner": 0}
 
 
