@@ -150,10 +150,10 @@ def main():
                          "and a row outside the declared width sets a device error flag)")
     ap.add_argument("--date-lt", type=int, default=None,
                     help="config 2 with another filter constant D (date < D; the workload uses 2400)")
-    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 4, 5],
+    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 4, 5, 6],
                     help="2: the 60M-row custkey fragment (default); 3: 256 flags fragments, batched vs plain; "
                          "4: served mix under Poisson arrivals, concurrent vs serial; 5: the join kinds on the "
-                         "config-2 join inputs")
+                         "config-2 join inputs; 6: hash join vs sort join from unsorted inputs, 1 to 64 rows per key")
     ap.add_argument("--rates", default="50,100,200,400,800", help="arrival rates (fragments/s) for --config 4")
     ap.add_argument("--requests", type=int, default=400, help="requests per rate for --config 4")
     ap.add_argument("--slots", type=int, default=8)
@@ -179,6 +179,8 @@ def main():
         return bench_batch(args)
     if args.config == 5:
         return bench_joins(args)
+    if args.config == 6:
+        return bench_hash_vs_sort(args)
     if args.config == 4:
         return bench_serve(args)
 
@@ -383,6 +385,66 @@ def bench_joins(args):
                       "config": {"workload": "config-2 join inputs: %d sorted fact keys (date < %d) x %d sorted mid "
                                              "keys, row positions as payloads" % (nl, fr.D, nr)},
                       "kinds": out, "counts_match_numpy": True}), flush=True)
+
+
+def bench_hash_vs_sort(args):
+    """Hash join against the sort-based join from unsorted inputs (Section 5.3's comparison): n left
+    and n right rows, r right rows per key (keys i // r, shuffled), left keys uniform over the same
+    key range, r = 1, 4, 16, 64.  Sort-based = stable sort of both sides (with their permutations)
+    + the sort join; hash-based = tqp_hash_join.  Times from the library's own kernel events; the
+    two join sizes must agree."""
+    import numpy as np
+    import torch
+
+    import paper_2203_01877_amd as tqp
+
+    n = args.rows or 8_000_000
+    dev = torch.device("cuda", 0)
+    ctx = tqp.Context(0)
+    rng = np.random.default_rng(17)
+    sweep = []
+    for r in (1, 4, 16, 64):
+        dom = max(1, n // r)
+        rkey = rng.permutation(np.arange(n, dtype=np.int64) // r).astype(np.int32)
+        lkey = rng.integers(0, dom, n).astype(np.int32)
+        want = int((np.bincount(lkey, minlength=dom).astype(np.int64) *
+                    np.bincount(rkey, minlength=dom).astype(np.int64)).sum())
+        lk, rk = torch.from_numpy(lkey).to(dev), torch.from_numpy(rkey).to(dev)
+        kb = max(1, int(dom - 1).bit_length())
+
+        def sort_join():
+            ls, lp = tqp.sort(ctx, lk, key_bits=kb, perm=True)
+            rs, rp = tqp.sort(ctx, rk, key_bits=kb, perm=True)
+            return tqp.join(ctx, ls, rs, lp, rp, cap=want)[2]
+
+        def hash_join():
+            return tqp.hash_join(ctx, lk, rk, cap=want)[2]
+
+        res = {"rows_per_key": r, "join_rows": want}
+        for name, fn in (("sort", sort_join), ("hash", hash_join)):
+            for _ in range(args.warmup):
+                fn()
+            torch.cuda.synchronize()
+            ctx.profile_read()
+            ctx.set_profiling(True)
+            for _ in range(args.steps):
+                cnt = fn()
+            torch.cuda.synchronize()
+            recs = ctx.profile_read()
+            ctx.set_profiling(False)
+            if int(cnt.item()) != want or ctx.errors():
+                log("%s join, r = %d: %d rows, expected %d" % (name, r, int(cnt.item()), want))
+                sys.exit(3)
+            res[name + "_ms"] = round(sum(t for _, t in recs) / args.steps, 4)
+        res["hash_speedup"] = round(res["sort_ms"] / res["hash_ms"], 2)
+        log(str(res))
+        sweep.append(res)
+        del lk, rk
+        torch.cuda.empty_cache()
+    print(json.dumps({"metric": "join ms from unsorted inputs, hash vs sort", "unit": "ms", "n_gpus": 1,
+                      "steps": args.steps, "warmup": args.warmup, "higher_is_better": False, "data": "synthetic",
+                      "dtype": "int32", "config": {"workload": "%d x %d rows, r right rows per key" % (n, n)},
+                      "sweep": sweep}), flush=True)
 
 
 def bench_batch(args):
