@@ -436,6 +436,10 @@ def bench_hash_vs_sort(args):
                 log("%s join, r = %d: %d rows, expected %d" % (name, r, int(cnt.item()), want))
                 sys.exit(3)
             res[name + "_ms"] = round(sum(t for _, t in recs) / args.steps, 4)
+            per = {}
+            for k, t in recs:
+                per[k] = per.get(k, 0.0) + t / args.steps
+            res[name + "_kernels_ms"] = {k: round(v, 4) for k, v in sorted(per.items())}
         res["hash_speedup"] = round(res["sort_ms"] / res["hash_ms"], 2)
         log(str(res))
         sweep.append(res)
