@@ -52,6 +52,8 @@ def _L():
         lib.orc_join.restype = i64
         lib.orc_join_kind.argtypes = [ctypes.c_int, vp, vp, i64, vp, vp, i64, vp, vp, i64]
         lib.orc_join_kind.restype = i64
+        lib.orc_join_band.argtypes = [vp, vp, i64, vp, vp, i64, i64, vp, vp, i64]
+        lib.orc_join_band.restype = i64
         lib.orc_groupby.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, i64]
         lib.orc_groupby.restype = i64
         lib.orc_fragment_flags.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp, vp, i64, i32, i32,
@@ -137,6 +139,22 @@ def join_kind(kind, lkey, rkey, lrow=None, rrow=None, cap=None):
                            ol.ctypes.data, orr.ctypes.data, cap)
     w = min(J, cap)
     return ol[:w].copy(), orr[:w].copy(), J
+
+
+def join_band(lkey, rkey, w, lrow=None, rrow=None, cap=None):
+    """Band join |lkey - rkey| <= w: pairs (left payload, right payload) in left order, then right
+    order, and the true count (all pairs compared: small inputs only)."""
+    lkey, rkey = _c(lkey, np.int32), _c(rkey, np.int32)
+    lrow = None if lrow is None else _c(lrow, np.int32)
+    rrow = None if rrow is None else _c(rrow, np.int32)
+    if cap is None:
+        cap = _L().orc_join_band(lkey.ctypes.data, _p(lrow), len(lkey), rkey.ctypes.data, _p(rrow), len(rkey), w,
+                                 None, None, 0)
+    ol, orr = np.empty(max(1, cap), np.int32), np.empty(max(1, cap), np.int32)
+    J = _L().orc_join_band(lkey.ctypes.data, _p(lrow), len(lkey), rkey.ctypes.data, _p(rrow), len(rkey), w,
+                           ol.ctypes.data, orr.ctypes.data, cap)
+    w_ = min(J, cap)
+    return ol[:w_].copy(), orr[:w_].copy(), J
 
 
 def groupby(gkey, val, avg_in=None):

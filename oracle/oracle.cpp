@@ -186,6 +186,28 @@ int64_t orc_join_kind(int kind, const int32_t* lkey, const int32_t* lrow, int64_
     return w;
 }
 
+// Band join, the non-equi join of Section 5.2's list of variants: every
+// (lrow[i], rrow[j]) with |lkey[i] - rkey[j]| <= w (w >= 0; w = 0 is the
+// equi-join), ordered by i, then j.  At most cap rows written; returns the
+// true count.
+int64_t orc_join_band(const int32_t* lkey, const int32_t* lrow, int64_t nl, const int32_t* rkey,
+                      const int32_t* rrow, int64_t nr, int64_t w, int32_t* out_l, int32_t* out_r, int64_t cap) {
+    int64_t n = 0;
+    for (int64_t i = 0; i < nl; ++i) {
+        for (int64_t j = 0; j < nr; ++j) {
+            const int64_t d = static_cast<int64_t>(lkey[i]) - static_cast<int64_t>(rkey[j]);
+            if (d <= w && -d <= w) {
+                if (n < cap) {
+                    out_l[n] = lrow ? lrow[i] : static_cast<int32_t>(i);
+                    out_r[n] = rrow ? rrow[j] : static_cast<int32_t>(j);
+                }
+                ++n;
+            }
+        }
+    }
+    return n;
+}
+
 // Group-by aggregation (Section 5.4, Algorithm 2): one row per distinct key in
 // ascending order with sum(val), count and avg(avg_in) = (double)sum(avg_in) /
 // (double)count.  avg_in may be null (out_avg is then not written).  Writes at

@@ -165,6 +165,30 @@ def check_join_kinds():
     assert J == 4 and list(zip(ol, orr)) == [(0, -1), (1, 0)]
 
 
+def check_join_band():
+    rng = _rng(37)
+    for trial in range(8):
+        nl, nr = int(rng.integers(0, 120)), int(rng.integers(0, 90))
+        hi = int(rng.integers(1, 200))
+        w = int(rng.integers(0, 12))
+        lkey = np.sort(rng.integers(0, hi, nl)).astype(np.int32)
+        rkey = np.sort(rng.integers(0, hi, nr)).astype(np.int32)
+        lrow = rng.permutation(max(nl, 1))[:nl].astype(np.int32)
+        rrow = rng.permutation(max(nr, 1))[:nr].astype(np.int32)
+        ol, orr, J = oracle.join_band(lkey, rkey, w, lrow, rrow)
+        want = [(int(lrow[i]), int(rrow[j])) for i in range(nl) for j in range(nr)
+                if abs(int(lkey[i]) - int(rkey[j])) <= w]
+        assert J == len(want) and list(zip(ol.tolist(), orr.tolist())) == want, ("band rows", trial)
+        # closed form on sorted keys: per left key, the right keys in [k - w, k + w]
+        assert J == int((np.searchsorted(rkey, lkey.astype(np.int64) + w, "right")
+                         - np.searchsorted(rkey, lkey.astype(np.int64) - w, "left")).sum())
+        # w = 0 is the equi-join; widening the band never loses a row
+        e_l, e_r, e_J = oracle.join(lkey, rkey, lrow, rrow)
+        z_l, z_r, z_J = oracle.join_band(lkey, rkey, 0, lrow, rrow)
+        assert z_J == e_J and np.array_equal(z_l, e_l) and np.array_equal(z_r, e_r)
+        assert oracle.join_band(lkey, rkey, w + 1)[2] >= J
+
+
 # --------------------------------------------------------------------------- group-by
 
 def check_groupby():
@@ -293,5 +317,6 @@ def check_topk_ties():
     assert got["top_key"].tolist() == [1, 4, 7] and got["top_sum"].tolist() == [10000] * 3
 
 
-ALL_CHECKS = [check_filter, check_sort, check_join, check_join_kinds, check_groupby, check_fragment_flags,
+ALL_CHECKS = [check_filter, check_sort, check_join, check_join_kinds, check_join_band, check_groupby,
+              check_fragment_flags,
               check_fragment_flags_invariants, check_fragment_cust, check_topk_ties]
