@@ -379,6 +379,30 @@ def bench_joins(args):
                      "left_rows_per_s": round(nl / (ms * 1e-3), 1),
                      "expansion_gbps": round(eb / (ems * 1e-3) / 1e9, 1)}
         log("%s: %s" % (name, out[name]))
+    # band join |l - r| <= 1 (the non-equi variant) on the same keys
+    wband = 1
+    want_b = int((np.searchsorted(rkey, lkey.astype(np.int64) + wband, "right")
+                  - np.searchsorted(rkey, lkey.astype(np.int64) - wband, "left")).sum())
+    for _ in range(args.warmup):
+        tqp.join_band(ctx, lk, rk, wband, cap=want_b)
+    torch.cuda.synchronize()
+    ctx.profile_read()
+    ctx.set_profiling(True)
+    for _ in range(args.steps):
+        _, _, cnt = tqp.join_band(ctx, lk, rk, wband, cap=want_b)
+    torch.cuda.synchronize()
+    recs = ctx.profile_read()
+    ctx.set_profiling(False)
+    got = int(cnt.item())
+    if got != want_b or ctx.errors():
+        log("band join: %d rows, expected %d" % (got, want_b))
+        sys.exit(3)
+    ms = sum(t for _, t in recs) / args.steps
+    ems = sum(t for k, t in recs if k == "band_expand") / args.steps
+    out["band_w1"] = {"ms": round(ms, 4), "expansion_ms": round(ems, 4), "rows_out": got,
+                      "left_rows_per_s": round(nl / (ms * 1e-3), 1),
+                      "expansion_gbps": round((4 * nl + 4 * nr + 8 * got) / (ems * 1e-3) / 1e9, 1)}
+    log("band_w1: %s" % out["band_w1"])
     print(json.dumps({"metric": "left rows/s per join kind (sorted 56.3M x 15M keys)", "unit": "left rows/s",
                       "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
                       "data": "synthetic", "dtype": "int32",

@@ -181,6 +181,17 @@ tqp_status tqp_hash_join(tqp_ctx* ctx, const int32_t* lkey, const int32_t* lrow,
                          const int64_t* d_nr, int32_t* out_l, int32_t* out_r, int64_t cap,
                          int64_t* d_count, void* ws, size_t* ws_bytes, hipStream_t stream);
 
+/* Band join, the non-equi join of Section 5.2's variants: every
+ * (lrow[i], rrow[j]) with |lkey[i] - rkey[j]| <= w, w >= 0 (w = 0 is
+ * tqp_join).  Both inputs sorted by key (ascending); the matches of left row i
+ * are one contiguous range of the right side, emitted in the order (i, j)
+ * ascending.  Keys non-negative int32.  Arguments, device counts and capacity
+ * as tqp_join; w < 0 returns TQP_ERR_INVALID. */
+tqp_status tqp_join_band(tqp_ctx* ctx, const int32_t* lkey, const int32_t* lrow, int64_t nl,
+                         const int64_t* d_nl, const int32_t* rkey, const int32_t* rrow, int64_t nr,
+                         const int64_t* d_nr, int64_t w, int32_t* out_l, int32_t* out_r, int64_t cap,
+                         int64_t* d_count, void* ws, size_t* ws_bytes, hipStream_t stream);
+
 #define TQP_JOIN_INNER 0
 #define TQP_JOIN_LEFT_SEMI 1
 #define TQP_JOIN_LEFT_ANTI 2

@@ -25,7 +25,7 @@ from . import _lib
 from ._lib import (DEVERR_CAPACITY, DEVERR_KEY_RANGE, DEVERR_SPIN, DEVERR_VALUE_RANGE, JOIN_INNER, JOIN_LEFT_ANTI,
                    JOIN_LEFT_OUTER, JOIN_LEFT_SEMI, TQP_EQ, TQP_GE, TQP_GT, TQP_LE, TQP_LT, TQP_NE, TQPError, check)
 
-__all__ = ["Context", "filter", "sort", "join", "hash_join", "groupby_agg", "topk", "FlagsFragmentRunner",
+__all__ = ["Context", "filter", "sort", "join", "hash_join", "join_band", "groupby_agg", "topk", "FlagsFragmentRunner",
            "CustFragmentRunner", "BatchRunner", "Server", "TQPError", "TQP_LT", "TQP_LE", "TQP_GT", "TQP_GE", "TQP_EQ", "TQP_NE",
            "DEVERR_KEY_RANGE", "DEVERR_SPIN", "DEVERR_CAPACITY", "DEVERR_VALUE_RANGE", "JOIN_INNER", "JOIN_LEFT_SEMI",
            "JOIN_LEFT_ANTI", "JOIN_LEFT_OUTER"]
@@ -169,6 +169,22 @@ def hash_join(ctx: Context, lkey, rkey, lrow=None, rrow=None, cap: int | None = 
     s = _stream(stream)
     _run(lambda ws, sz: ctx.lib.tqp_hash_join(ctx.h, _p(lkey), _p(lrow), nl, _p(d_nl), _p(rkey), _p(rrow), nr,
                                               _p(d_nr), _p(ol), _p(orr), cap, _p(cnt), ws, sz, s), "tqp_hash_join",
+         dev)
+    return ol, orr, cnt
+
+
+def join_band(ctx: Context, lkey, rkey, w: int, lrow=None, rrow=None, cap: int | None = None, d_nl=None, d_nr=None,
+              stream=None):
+    """Band join |lkey - rkey| <= w of key-sorted inputs.  Returns (out_l, out_r, d_count)."""
+    nl, nr = lkey.numel(), rkey.numel()
+    cap = nl if cap is None else cap
+    dev = _dev(ctx)
+    ol = torch.empty(max(1, cap), dtype=torch.int32, device=dev)
+    orr = torch.empty(max(1, cap), dtype=torch.int32, device=dev)
+    cnt = torch.empty(1, dtype=torch.int64, device=dev)
+    s = _stream(stream)
+    _run(lambda ws, sz: ctx.lib.tqp_join_band(ctx.h, _p(lkey), _p(lrow), nl, _p(d_nl), _p(rkey), _p(rrow), nr,
+                                              _p(d_nr), w, _p(ol), _p(orr), cap, _p(cnt), ws, sz, s), "tqp_join_band",
          dev)
     return ol, orr, cnt
 

@@ -166,6 +166,34 @@ def test_hash_join(hip, ctx, nl, nr, hi, sort):
     assert ctx.errors() == 0
 
 
+@pytest.mark.parametrize("nl,nr,hi,w", [(0, 10, 5, 1), (10, 0, 5, 1), (1, 1, 1, 0), (5000, 300, 1500, 3),
+                                        (300_007, 40_000, 150_000, 2), (200_000, 150_000, 150_000, 0),
+                                        (4097, 5, 3, 1), (20_000, 20_000, 1_000_000, 40), (60_000, 50_000, 3_000, 5)])
+def test_join_band(hip, ctx, nl, nr, hi, w):
+    """Band join against the oracle (all pairs compared on the CPU, so the
+    sizes stay small): rows, order and count; windows that fit the LDS
+    staging and ones that do not (few distinct keys, wide bands)."""
+    rng = _rng(nl * 3 + nr + w)
+    lkey = np.sort(rng.integers(0, hi, nl)).astype(np.int32)
+    rkey = np.sort(rng.integers(0, hi, nr)).astype(np.int32)
+    lrow = rng.permutation(max(1, nl))[:nl].astype(np.int32)
+    rrow = rng.permutation(max(1, nr))[:nr].astype(np.int32)
+    # the rows from the contiguous ranges of the sorted right side (exact at any size) ...
+    lo = np.searchsorted(rkey, lkey.astype(np.int64) - w, "left")
+    cnt_ = np.searchsorted(rkey, lkey.astype(np.int64) + w, "right") - lo
+    J = int(cnt_.sum())
+    wl = np.repeat(lrow, cnt_)
+    wr = rrow[np.repeat(lo, cnt_) + np.arange(J) - np.repeat(np.cumsum(cnt_) - cnt_, cnt_)]
+    if nl * nr <= 2e9:
+        # ... and, where all pairs can be compared, the oracle's
+        ol_, or_, J2 = oracle.join_band(lkey, rkey, w, lrow, rrow)
+        assert J2 == J and np.array_equal(ol_, wl) and np.array_equal(or_, wr)
+    ol, orr, cnt = hip.join_band(ctx, _dev(lkey), _dev(rkey), w, _dev(lrow), _dev(rrow), cap=max(J, 1))
+    assert int(_np(cnt)[0]) == J
+    assert np.array_equal(_np(ol, J), wl) and np.array_equal(_np(orr, J), wr)
+    assert ctx.errors() == 0
+
+
 _KINDS = {"semi": 1, "anti": 2, "outer": 3, "inner": 0}
 
 
