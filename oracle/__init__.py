@@ -54,6 +54,8 @@ def _L():
         lib.orc_join_kind.restype = i64
         lib.orc_join_band.argtypes = [vp, vp, i64, vp, vp, i64, i64, vp, vp, i64]
         lib.orc_join_band.restype = i64
+        lib.orc_pack_keys.argtypes = [vp, vp, ctypes.c_int, i64, vp]
+        lib.orc_pack_keys.restype = i64
         lib.orc_groupby.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, i64]
         lib.orc_groupby.restype = i64
         lib.orc_fragment_flags.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp, vp, i64, i32, i32,
@@ -155,6 +157,18 @@ def join_band(lkey, rkey, w, lrow=None, rrow=None, cap=None):
                            ol.ctypes.data, orr.ctypes.data, cap)
     w_ = min(J, cap)
     return ol[:w_].copy(), orr[:w_].copy(), J
+
+
+def pack_keys(cols, bits):
+    """Columns packed into one int32 key, first column most significant; (keys, values outside
+    their width)."""
+    cols = [_c(c, np.int32) for c in cols]
+    n = len(cols[0]) if cols else 0
+    ptrs = (ctypes.c_void_p * max(1, len(cols)))(*[c.ctypes.data for c in cols])
+    b = np.asarray(bits, np.int32)
+    out = np.empty(max(1, n), np.int32)
+    bad = _L().orc_pack_keys(ctypes.cast(ptrs, ctypes.c_void_p), b.ctypes.data, len(cols), n, out.ctypes.data)
+    return out[:n].copy(), int(bad)
 
 
 def groupby(gkey, val, avg_in=None):

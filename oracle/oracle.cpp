@@ -208,6 +208,27 @@ int64_t orc_join_band(const int32_t* lkey, const int32_t* lrow, int64_t nl, cons
     return n;
 }
 
+// Composite keys (Section 5.4: the group-by columns are concatenated into one
+// key before the sort; Algorithm 3 matches several join-key columns): the
+// columns packed into one integer, the first column most significant, column
+// c taking bits[c] bits, so the packed order is the lexicographic order of
+// the tuples.  Returns the number of values outside their width (negative or
+// >= 2^bits[c]); those rows are packed from their masked values.
+int64_t orc_pack_keys(const int32_t* const* cols, const int32_t* bits, int ncols, int64_t n, int32_t* out) {
+    int64_t bad = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t v = 0;
+        for (int c = 0; c < ncols; ++c) {
+            const int64_t x = cols[c][i];
+            const int64_t lim = int64_t(1) << bits[c];
+            if (x < 0 || x >= lim) ++bad;
+            v = v * lim + (x & (lim - 1));
+        }
+        out[i] = static_cast<int32_t>(v);
+    }
+    return bad;
+}
+
 // Group-by aggregation (Section 5.4, Algorithm 2): one row per distinct key in
 // ascending order with sum(val), count and avg(avg_in) = (double)sum(avg_in) /
 // (double)count.  avg_in may be null (out_avg is then not written).  Writes at

@@ -189,6 +189,29 @@ def check_join_band():
         assert oracle.join_band(lkey, rkey, w + 1)[2] >= J
 
 
+def check_pack_keys():
+    rng = _rng(41)
+    bits = [7, 11, 5]
+    cols = [rng.integers(0, 1 << b, 5000).astype(np.int32) for b in bits]
+    packed, bad = oracle.pack_keys(cols, bits)
+    assert bad == 0
+    # the packed order is the tuples' lexicographic order (numpy lexsort, last key primary)
+    assert np.array_equal(np.argsort(packed, kind="stable"), np.lexsort(cols[::-1]))
+    # unpacking by shifts returns every column
+    assert np.array_equal(packed >> 16, cols[0]) and np.array_equal((packed >> 5) & 2047, cols[1])
+    assert np.array_equal(packed & 31, cols[2])
+    # a composite-key join is the join of the packed keys: brute force over tuples
+    a = [rng.integers(0, 4, 60).astype(np.int32), rng.integers(0, 3, 60).astype(np.int32)]
+    b = [rng.integers(0, 4, 40).astype(np.int32), rng.integers(0, 3, 40).astype(np.int32)]
+    ka, _ = oracle.pack_keys(a, [2, 2])
+    kb, _ = oracle.pack_keys(b, [2, 2])
+    ol, orr, J = oracle.join(ka, kb)
+    want = [(i, j) for i in range(60) for j in range(40) if a[0][i] == b[0][j] and a[1][i] == b[1][j]]
+    assert J == len(want) and list(zip(ol.tolist(), orr.tolist())) == want
+    # values outside their width are counted
+    assert oracle.pack_keys([np.array([3, 4, -1], np.int32)], [2])[1] == 2
+
+
 # --------------------------------------------------------------------------- group-by
 
 def check_groupby():
@@ -317,6 +340,6 @@ def check_topk_ties():
     assert got["top_key"].tolist() == [1, 4, 7] and got["top_sum"].tolist() == [10000] * 3
 
 
-ALL_CHECKS = [check_filter, check_sort, check_join, check_join_kinds, check_join_band, check_groupby,
-              check_fragment_flags,
+ALL_CHECKS = [check_filter, check_sort, check_join, check_join_kinds, check_join_band, check_pack_keys,
+              check_groupby, check_fragment_flags,
               check_fragment_flags_invariants, check_fragment_cust, check_topk_ties]

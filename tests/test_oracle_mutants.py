@@ -33,6 +33,7 @@ MUTANTS = [
     ("semi_as_anti", "if (kind == 1) {\n            if (matched) put(l, -1);", "if (kind == 1) {\n            if (!matched) put(l, -1);"),
     ("outer_drops_unmatched", "} else if (kind == 3) {\n            put(l, -1);", "} else if (kind == 3) {\n            (void)l;"),
     ("band_one_sided", "if (d <= w && -d <= w) {", "if (d <= w) {"),
+    ("pack_reversed", "v = v * lim + (x & (lim - 1));", "v = v + (x & (lim - 1)) * (lim - 1);"),
     ("cust_uses_fact_key", "Agg& a = groups[custkey[it->second]];", "Agg& a = groups[fk[f]];"),
     ("mid_first_match_only", "for (auto it = range.first; it != range.second; ++it) {\n            Agg& a = groups[custkey",
      "for (auto it = range.first; it != range.second; it = range.second) {\n            Agg& a = groups[custkey"),
