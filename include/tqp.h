@@ -201,6 +201,18 @@ tqp_status tqp_join_kind(tqp_ctx* ctx, int kind, const int32_t* lkey, const int3
                          const int64_t* d_nr, int32_t* out_l, int32_t* out_r, int64_t cap,
                          int64_t* d_count, void* ws, size_t* ws_bytes, hipStream_t stream);
 
+/* Composite keys (Section 5.4 concatenates the group-by columns into one key
+ * before the sort; Algorithm 3 compares several join-key columns): out[i]
+ * packs cols[0][i], ..., cols[ncols-1][i], the first column most significant
+ * and column c taking bits[c] bits, so sorting or joining the packed keys
+ * sorts or joins the tuples.  1 <= ncols <= 4, each bits[c] >= 1, their sum
+ * <= 31.  Values must lie in [0, 2^bits[c]); others set
+ * TQP_DEVERR_KEY_RANGE (their row is packed from the masked value).  cols and
+ * bits are host arrays of device column pointers and widths; n or *d_n rows.
+ * No workspace. */
+tqp_status tqp_pack_keys(tqp_ctx* ctx, const int32_t* const* cols, const int32_t* bits, int ncols, int64_t n,
+                         const int64_t* d_n, int32_t* out, hipStream_t stream);
+
 /* ---------------------------------------------------------------- group-by
  * Section 5.4, Algorithm 2: sort the group keys, permute the value columns
  * by the sorted order, find the runs of equal keys and evaluate the

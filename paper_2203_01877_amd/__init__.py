@@ -25,7 +25,7 @@ from . import _lib
 from ._lib import (DEVERR_CAPACITY, DEVERR_KEY_RANGE, DEVERR_SPIN, DEVERR_VALUE_RANGE, JOIN_INNER, JOIN_LEFT_ANTI,
                    JOIN_LEFT_OUTER, JOIN_LEFT_SEMI, TQP_EQ, TQP_GE, TQP_GT, TQP_LE, TQP_LT, TQP_NE, TQPError, check)
 
-__all__ = ["Context", "filter", "sort", "join", "hash_join", "join_band", "groupby_agg", "topk", "FlagsFragmentRunner",
+__all__ = ["Context", "filter", "sort", "join", "hash_join", "join_band", "pack_keys", "groupby_agg", "topk", "FlagsFragmentRunner",
            "CustFragmentRunner", "BatchRunner", "Server", "TQPError", "TQP_LT", "TQP_LE", "TQP_GT", "TQP_GE", "TQP_EQ", "TQP_NE",
            "DEVERR_KEY_RANGE", "DEVERR_SPIN", "DEVERR_CAPACITY", "DEVERR_VALUE_RANGE", "JOIN_INNER", "JOIN_LEFT_SEMI",
            "JOIN_LEFT_ANTI", "JOIN_LEFT_OUTER"]
@@ -187,6 +187,19 @@ def join_band(ctx: Context, lkey, rkey, w: int, lrow=None, rrow=None, cap: int |
                                               _p(d_nr), w, _p(ol), _p(orr), cap, _p(cnt), ws, sz, s), "tqp_join_band",
          dev)
     return ol, orr, cnt
+
+
+def pack_keys(ctx: Context, cols, bits, d_n=None, stream=None):
+    """Composite key: the int32 device columns packed into one int32 key, first column most
+    significant, column c taking bits[c] bits (sum <= 31)."""
+    n = cols[0].numel()
+    dev = _dev(ctx)
+    out = torch.empty(max(1, n), dtype=torch.int32, device=dev)
+    ptrs = (ctypes.c_void_p * len(cols))(*[c.data_ptr() for c in cols])
+    b = (ctypes.c_int32 * len(bits))(*bits)
+    check(ctx.lib.tqp_pack_keys(ctx.h, ctypes.cast(ptrs, ctypes.c_void_p), ctypes.cast(b, ctypes.c_void_p),
+                                len(cols), n, _p(d_n), _p(out), _stream(stream)), "tqp_pack_keys")
+    return out[:n]
 
 
 def groupby_agg(ctx: Context, gkey, sum_in, avg_in=None, key_bits: int = 0, gcap: int | None = None, d_n=None,

@@ -122,6 +122,8 @@ def load() -> ctypes.CDLL:
     lib.tqp_hash_join.restype = S
     lib.tqp_join_band.argtypes = lib.tqp_join.argtypes[:9] + [c_i64] + lib.tqp_join.argtypes[9:]
     lib.tqp_join_band.restype = S
+    lib.tqp_pack_keys.argtypes = [c_vp, c_vp, c_vp, c_int, c_i64, c_vp, c_vp, c_vp]
+    lib.tqp_pack_keys.restype = S
     lib.tqp_groupby_agg.argtypes = [c_vp, c_vp, c_i64, c_vp, c_int, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i64,
                                     c_vp, c_vp, c_size_p, c_vp]
     lib.tqp_groupby_agg.restype = S

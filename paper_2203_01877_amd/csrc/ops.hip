@@ -57,6 +57,36 @@ tqp_status topk_launch_candidates(const TopkBufs& t, const int64_t* cnt, int k, 
     return TQP_OK;
 }
 
+// Composite keys: the columns packed into one key, the first column most
+// significant (Section 5.4 concatenates the group-by columns before the
+// sort; Algorithm 3 compares several join-key columns).
+constexpr int PACK_MAX_COLS = 4;
+struct PackCols {
+    const int32_t* col[PACK_MAX_COLS];
+    int32_t bits[PACK_MAX_COLS];
+    int32_t n;
+};
+
+__global__ void k_pack_keys(PackCols pc, int64_t n_upper, const int64_t* d_n, int32_t* out, uint32_t* flags) {
+    int64_t n = n_upper;
+    if (d_n) { const int64_t t = *d_n; n = t < n ? t : n; }
+    uint32_t bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int c = 0; c < PACK_MAX_COLS; ++c) {
+            if (c < pc.n) {
+                const uint32_t x = (uint32_t)pc.col[c][i];
+                const uint32_t lim_mask = (1u << pc.bits[c]) - 1;
+                bad |= x & ~lim_mask;                        // negative values have the sign bit
+                v = (v << pc.bits[c]) | (x & lim_mask);
+            }
+        }
+        out[i] = (int32_t)v;
+    }
+    if (__any(bad != 0) && lane_id() == 0) set_flag(flags, FLAG_KEY_RANGE);
+}
+
 }  // namespace tqp
 
 using namespace tqp;
@@ -264,6 +294,31 @@ tqp_status tqp_topk(tqp_ctx* ctx, const int32_t* key, const int64_t* sum, const 
     if (st != TQP_OK || !ws) return st;
     if ((st = fill_zero(a.base, a.zsize, stream, ctx)) != TQP_OK) return st;
     return topk_launch(t, key, sum, cnt, d_n, k, out_key, out_sum, out_cnt, d_k, stream, ctx);
+}
+
+tqp_status tqp_pack_keys(tqp_ctx* ctx, const int32_t* const* cols, const int32_t* bits, int ncols, int64_t n,
+                         const int64_t* d_n, int32_t* out, hipStream_t stream) {
+    clear_error();
+    if (!ctx || n < 0 || (n > 0 && (!cols || !bits || !out)))
+        return fail(TQP_ERR_INVALID, "tqp_pack_keys: null pointer or negative size");
+    if (ncols < 1 || ncols > PACK_MAX_COLS) return fail(TQP_ERR_UNSUPPORTED, "tqp_pack_keys: %d columns", ncols);
+    PackCols pc{};
+    pc.n = ncols;
+    int total = 0;
+    for (int c = 0; c < ncols; ++c) {
+        if (bits[c] < 1 || bits[c] > 31) return fail(TQP_ERR_INVALID, "tqp_pack_keys: bits[%d] = %d", c, bits[c]);
+        if (n > 0 && !cols[c]) return fail(TQP_ERR_INVALID, "tqp_pack_keys: column %d is null", c);
+        pc.col[c] = cols[c];
+        pc.bits[c] = bits[c];
+        total += bits[c];
+    }
+    if (total > 31) return fail(TQP_ERR_UNSUPPORTED, "tqp_pack_keys: %d key bits (at most 31)", total);
+    if (n > MAX_ELEMS) return fail(TQP_ERR_UNSUPPORTED, "tqp_pack_keys: n = %lld", (long long)n);
+    if (n == 0) return TQP_OK;
+    TQP_LAUNCH(ctx, stream, "pack_keys",
+               k_pack_keys<<<grid_for(n, 256 * 4, (int64_t)ctx->num_cus * 8), 256, 0, stream>>>(pc, n, d_n, out,
+                                                                                            ctx->d_err));
+    return TQP_OK;
 }
 
 }  // extern "C"

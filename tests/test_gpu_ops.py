@@ -194,6 +194,46 @@ def test_join_band(hip, ctx, nl, nr, hi, w):
     assert ctx.errors() == 0
 
 
+@pytest.mark.parametrize("bits", [[7, 11, 5], [3, 28], [31], [2, 2, 2, 2]])
+def test_pack_keys(hip, ctx, bits):
+    """Composite keys packed on the GPU equal the oracle's packing."""
+    rng = _rng(sum(bits) * 13 + len(bits))
+    n = 300_007
+    cols = [rng.integers(0, 1 << b, n).astype(np.int32) for b in bits]
+    want, bad = oracle.pack_keys(cols, bits)
+    assert bad == 0
+    got = hip.pack_keys(ctx, [_dev(c) for c in cols], bits)
+    assert np.array_equal(_np(got), want)
+    assert ctx.errors() == 0
+
+
+def test_composite_key_join(hip, ctx):
+    """A two-column equi-join: both sides packed, sorted and joined on the GPU,
+    against the oracle's join of its own packed keys (brute force over tuples
+    pins that the packed join is the tuple join)."""
+    rng = _rng(99)
+    a = [rng.integers(0, 500, 100_000).astype(np.int32), rng.integers(0, 64, 100_000).astype(np.int32)]
+    b = [rng.integers(0, 500, 30_000).astype(np.int32), rng.integers(0, 64, 30_000).astype(np.int32)]
+    ka, _ = oracle.pack_keys(a, [9, 6])
+    kb, _ = oracle.pack_keys(b, [9, 6])
+    sa, sb = np.argsort(ka, kind="stable"), np.argsort(kb, kind="stable")
+    wl, wr, J = oracle.join(ka[sa], kb[sb], sa.astype(np.int32), sb.astype(np.int32))
+    pa = hip.pack_keys(ctx, [_dev(c) for c in a], [9, 6])
+    pb = hip.pack_keys(ctx, [_dev(c) for c in b], [9, 6])
+    ka_s, pa_perm = hip.sort(ctx, pa, key_bits=15, perm=True)
+    kb_s, pb_perm = hip.sort(ctx, pb, key_bits=15, perm=True)
+    ol, orr, cnt = hip.join(ctx, ka_s, kb_s, pa_perm, pb_perm, cap=max(J, 1))
+    assert int(_np(cnt)[0]) == J
+    assert np.array_equal(_np(ol, J), wl) and np.array_equal(_np(orr, J), wr)
+    assert ctx.errors() == 0
+
+
+def test_pack_keys_range_flag(hip, ctx):
+    cols = [np.array([1, 2, 3], np.int32), np.array([0, 8, 1], np.int32)]
+    hip.pack_keys(ctx, [_dev(c) for c in cols], [4, 3])
+    assert ctx.errors() & hip.DEVERR_KEY_RANGE
+
+
 _KINDS = {"semi": 1, "anti": 2, "outer": 3, "inner": 0}
 
 
