@@ -58,6 +58,8 @@ def _L():
         lib.orc_pack_keys.restype = i64
         lib.orc_groupby.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, i64]
         lib.orc_groupby.restype = i64
+        lib.orc_group_minmax.argtypes = [vp, i64, vp, vp, vp, vp, vp, i64]
+        lib.orc_group_minmax.restype = i64
         lib.orc_fragment_flags.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp, vp, i64, i32, i32,
                                            vp, vp, vp, vp, i64, vp]
         lib.orc_fragment_flags.restype = i64
@@ -183,6 +185,18 @@ def groupby(gkey, val, avg_in=None):
                          s.ctypes.data, c.ctypes.data, a.ctypes.data, cap)
     _check_overflow()
     return k[:G].copy(), s[:G].copy(), c[:G].copy(), (a[:G].copy() if avg_in is not None else None)
+
+
+def group_minmax(gkey, val):
+    """(keys, mins, maxs, ndistinct) with one row per distinct key, keys ascending."""
+    gkey, val = _c(gkey, np.int32), _c(val, np.int64)
+    n = len(gkey)
+    cap = max(1, n)
+    k, lo, hi, nd = (np.empty(cap, np.int32), np.empty(cap, np.int64), np.empty(cap, np.int64),
+                     np.empty(cap, np.int64))
+    G = _L().orc_group_minmax(gkey.ctypes.data, n, val.ctypes.data, k.ctypes.data, lo.ctypes.data,
+                              hi.ctypes.data, nd.ctypes.data, cap)
+    return k[:G].copy(), lo[:G].copy(), hi[:G].copy(), nd[:G].copy()
 
 
 def fragment_flags(fact: dict, dim: dict, D: int, c: int) -> dict:

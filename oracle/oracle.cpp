@@ -23,7 +23,9 @@
 //               left anti and left outer joins (Section 5) mark a missing
 //               right row with -1.
 //   group-by    Section 5.4 / Algorithm 2: one output row per distinct key,
-//               in ascending key order, with sum, count and average.
+//               in ascending key order, with sum, count and average; the
+//               other aggregates Section 4 lists (min, max, count distinct)
+//               by the same definition.
 //   fragments   the whole filter -> join -> group-by query of the workloads,
 //               as a hash join followed by a hash aggregation.
 //
@@ -35,6 +37,7 @@
 #include <cstdlib>
 #include <map>
 #include <numeric>
+#include <set>
 #include <unordered_map>
 #include <vector>
 
@@ -251,6 +254,27 @@ int64_t orc_groupby(const int32_t* gkey, int64_t n, const int64_t* val, const in
             out_cnt[g] = kv.second.cnt;
             if (avg_in && out_avg)
                 out_avg[g] = static_cast<double>(kv.second.sum_avg) / static_cast<double>(kv.second.cnt);
+        }
+        ++g;
+    }
+    return g;
+}
+
+// The remaining aggregates of Section 4 (min, max and count with DISTINCT),
+// per distinct key in ascending order: min(val), max(val) and the number of
+// different values of val in the group.  Writes at most gcap groups; returns
+// the number of groups.
+int64_t orc_group_minmax(const int32_t* gkey, int64_t n, const int64_t* val, int32_t* out_key,
+                         int64_t* out_min, int64_t* out_max, int64_t* out_ndist, int64_t gcap) {
+    std::map<int32_t, std::set<int64_t>> groups;
+    for (int64_t i = 0; i < n; ++i) groups[gkey[i]].insert(val[i]);
+    int64_t g = 0;
+    for (const auto& kv : groups) {
+        if (g < gcap) {
+            out_key[g] = kv.first;
+            out_min[g] = *kv.second.begin();
+            out_max[g] = *kv.second.rbegin();
+            out_ndist[g] = static_cast<int64_t>(kv.second.size());
         }
         ++g;
     }

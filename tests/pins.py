@@ -242,6 +242,39 @@ def check_groupby():
     assert len(k) == 0
 
 
+def check_group_minmax():
+    rng = _rng(14)
+    for trial in range(10):
+        n = int(rng.integers(1, 3000))
+        keys = rng.integers(0, int(rng.integers(1, 80)), n).astype(np.int32)
+        # few distinct values so that repeats inside a group are common
+        val = rng.integers(-int(rng.integers(1, 50)), int(rng.integers(1, 50)), n).astype(np.int64)
+        k, lo, hi, nd = oracle.group_minmax(keys, val)
+        # library routines: sort by key, reduce each run
+        o = np.argsort(keys, kind="stable")
+        sk, sv = keys[o], val[o]
+        heads = np.flatnonzero(np.r_[True, sk[1:] != sk[:-1]])
+        assert np.array_equal(k, sk[heads]), ("keys", trial)
+        assert np.array_equal(lo, np.minimum.reduceat(sv, heads)), ("min", trial)
+        assert np.array_equal(hi, np.maximum.reduceat(sv, heads)), ("max", trial)
+        pairs = np.unique(np.stack([keys.astype(np.int64), val]), axis=1)
+        assert np.array_equal(nd, np.unique(pairs[0], return_counts=True)[1]), ("distinct", trial)
+    # brute force on a tiny input, with Python sets
+    keys = np.array([3, 1, 3, 3, 1, 7, 3], np.int32)
+    val = np.array([5, -2, 5, -9, -2, 0, 4], np.int64)
+    k, lo, hi, nd = oracle.group_minmax(keys, val)
+    assert k.tolist() == [1, 3, 7] and lo.tolist() == [-2, -9, 0] and hi.tolist() == [-2, 5, 0]
+    assert nd.tolist() == [1, 3, 1]
+    # extremes of int64 survive; one constant group has min = max and one distinct value
+    big = np.array([np.iinfo(np.int64).min, np.iinfo(np.int64).max, 0], np.int64)
+    k, lo, hi, nd = oracle.group_minmax(np.zeros(3, np.int32), big)
+    assert lo[0] == big[0] and hi[0] == big[1] and nd[0] == 3
+    k, lo, hi, nd = oracle.group_minmax(np.full(50, 9, np.int32), np.full(50, 4, np.int64))
+    assert k.tolist() == [9] and lo[0] == hi[0] == 4 and nd[0] == 1
+    k, lo, hi, nd = oracle.group_minmax(np.zeros(0, np.int32), np.zeros(0, np.int64))
+    assert len(k) == 0
+
+
 # --------------------------------------------------------------------------- fragments
 
 def brute_flags(fact, dim, D, c):
@@ -341,5 +374,5 @@ def check_topk_ties():
 
 
 ALL_CHECKS = [check_filter, check_sort, check_join, check_join_kinds, check_join_band, check_pack_keys,
-              check_groupby, check_fragment_flags,
+              check_groupby, check_group_minmax, check_fragment_flags,
               check_fragment_flags_invariants, check_fragment_cust, check_topk_ties]

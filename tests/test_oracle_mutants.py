@@ -24,8 +24,8 @@ MUTANTS = [
     ("join_transposed", "out_l[w] = lrow ? lrow[i] : static_cast<int32_t>(i);",
      "out_l[w] = lrow ? lrow[i ? i - 1 : 0] : static_cast<int32_t>(i);"),
     ("group_key_transposed", "groups[flagA[f] * 2 + flagB[f]]", "groups[flagB[f] * 2 + flagA[f]]"),
-    ("avg_wrong_divisor", "static_cast<double>(kv.second.sum_avg) / static_cast<double>(kv.second.cnt);\n        }\n        ++g;\n    }\n    return g;\n}\n\n// Flags",
-     "static_cast<double>(kv.second.sum_avg) / static_cast<double>(kv.second.cnt + 1);\n        }\n        ++g;\n    }\n    return g;\n}\n\n// Flags"),
+    ("avg_wrong_divisor", "static_cast<double>(kv.second.sum_avg) / static_cast<double>(kv.second.cnt);\n        }\n        ++g;\n    }\n    return g;\n}\n\n// The remaining aggregates",
+     "static_cast<double>(kv.second.sum_avg) / static_cast<double>(kv.second.cnt + 1);\n        }\n        ++g;\n    }\n    return g;\n}\n\n// The remaining aggregates"),
     ("count_dropped", "a.cnt += 1;\n            a.sum_avg = add_checked(a.sum_avg, price[f]);",
      "a.sum_avg = add_checked(a.sum_avg, price[f]);"),
     ("topk_tiebreak", "return a.first < b.first;\n              });\n    const int64_t kk",
@@ -34,6 +34,9 @@ MUTANTS = [
     ("outer_drops_unmatched", "} else if (kind == 3) {\n            put(l, -1);", "} else if (kind == 3) {\n            (void)l;"),
     ("band_one_sided", "if (d <= w && -d <= w) {", "if (d <= w) {"),
     ("pack_reversed", "v = v * lim + (x & (lim - 1));", "v = v + (x & (lim - 1)) * (lim - 1);"),
+    ("min_is_max", "out_min[g] = *kv.second.begin();", "out_min[g] = *kv.second.rbegin();"),
+    ("distinct_counts_rows", "std::map<int32_t, std::set<int64_t>> groups;",
+     "std::map<int32_t, std::multiset<int64_t>> groups;"),
     ("cust_uses_fact_key", "Agg& a = groups[custkey[it->second]];", "Agg& a = groups[fk[f]];"),
     ("mid_first_match_only", "for (auto it = range.first; it != range.second; ++it) {\n            Agg& a = groups[custkey",
      "for (auto it = range.first; it != range.second; it = range.second) {\n            Agg& a = groups[custkey"),
