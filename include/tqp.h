@@ -227,6 +227,25 @@ tqp_status tqp_groupby_agg(tqp_ctx* ctx, const int32_t* gkey, int64_t n, const i
                            int64_t gcap, int64_t* d_ngroups, void* ws, size_t* ws_bytes,
                            hipStream_t stream);
 
+/* Hash-based group-by (the hash aggregation Section 6 contrasts with the
+ * sort-based one of Section 5.4) with the aggregates Section 4 lists:
+ * one row per distinct key of gkey, in no fixed order: out_key, out_cnt =
+ * count, and, for each of these outputs that is not NULL, out_sum =
+ * sum(val), out_min = min(val), out_max = max(val), out_ndist = the number
+ * of different values of dval in the group (COUNT(DISTINCT dval)).  val is
+ * needed for sum, min and max, dval for out_ndist.  Keys must be >= 0; a
+ * negative key sets TQP_DEVERR_KEY_RANGE and its row is skipped.  gcap:
+ * the caller's bound on groups, which sizes the table (2 * gcap slots of 32
+ * bytes, plus 2 * n slots of 8 bytes when out_ndist is given); groups beyond
+ * it, or a probe of more than 4096 slots, set TQP_DEVERR_CAPACITY and leave
+ * those rows out.  The group count goes to *d_ngroups; at most gcap rows
+ * are written.  n or *d_n rows. */
+tqp_status tqp_hash_groupby(tqp_ctx* ctx, const int32_t* gkey, int64_t n, const int64_t* d_n,
+                            const int64_t* val, const int32_t* dval, int32_t* out_key, int64_t* out_cnt,
+                            int64_t* out_sum, int64_t* out_min, int64_t* out_max, int64_t* out_ndist,
+                            int64_t gcap, int64_t* d_ngroups, void* ws, size_t* ws_bytes,
+                            hipStream_t stream);
+
 /* ---------------------------------------------------------------- top-k
  * ORDER BY sum DESC, key ASC LIMIT k over aggregated groups (keys must be
  * unique, as group-by output is): rows (key, sum, cnt) of the first min(k, n)

@@ -25,7 +25,7 @@ from . import _lib
 from ._lib import (DEVERR_CAPACITY, DEVERR_KEY_RANGE, DEVERR_SPIN, DEVERR_VALUE_RANGE, JOIN_INNER, JOIN_LEFT_ANTI,
                    JOIN_LEFT_OUTER, JOIN_LEFT_SEMI, TQP_EQ, TQP_GE, TQP_GT, TQP_LE, TQP_LT, TQP_NE, TQPError, check)
 
-__all__ = ["Context", "filter", "sort", "join", "hash_join", "join_band", "pack_keys", "groupby_agg", "topk", "FlagsFragmentRunner",
+__all__ = ["Context", "filter", "sort", "join", "hash_join", "join_band", "pack_keys", "groupby_agg", "hash_groupby", "topk", "FlagsFragmentRunner",
            "CustFragmentRunner", "BatchRunner", "Server", "TQPError", "TQP_LT", "TQP_LE", "TQP_GT", "TQP_GE", "TQP_EQ", "TQP_NE",
            "DEVERR_KEY_RANGE", "DEVERR_SPIN", "DEVERR_CAPACITY", "DEVERR_VALUE_RANGE", "JOIN_INNER", "JOIN_LEFT_SEMI",
            "JOIN_LEFT_ANTI", "JOIN_LEFT_OUTER"]
@@ -217,6 +217,26 @@ def groupby_agg(ctx: Context, gkey, sum_in, avg_in=None, key_bits: int = 0, gcap
     _run(lambda ws, sz: ctx.lib.tqp_groupby_agg(ctx.h, _p(gkey), n, _p(d_n), key_bits, _p(sum_in), _p(avg_in),
                                                 _p(out["key"]), _p(out["sum"]), _p(out["cnt"]), _p(out["avg"]),
                                                 gcap, _p(out["d_ngroups"]), ws, sz, s), "tqp_groupby_agg", dev)
+    return out
+
+
+def hash_groupby(ctx: Context, gkey, val=None, dval=None, gcap: int | None = None, with_sum: bool = True,
+                 minmax: bool = False, d_n=None, stream=None):
+    """Hash-based group-by: dict of device tensors key/cnt and, as asked, sum/min/max (of val) and
+    ndist (COUNT(DISTINCT dval)), capacity gcap, groups in no fixed order; and d_ngroups."""
+    n = gkey.numel()
+    gcap = max(1, n) if gcap is None else gcap
+    dev = _dev(ctx)
+    cap = max(1, gcap)
+    i64 = lambda on: torch.empty(cap, dtype=torch.int64, device=dev) if on else None
+    out = {"key": torch.empty(cap, dtype=torch.int32, device=dev), "cnt": i64(True),
+           "sum": i64(with_sum and val is not None), "min": i64(minmax), "max": i64(minmax),
+           "ndist": i64(dval is not None), "d_ngroups": torch.empty(1, dtype=torch.int64, device=dev)}
+    s = _stream(stream)
+    _run(lambda ws, sz: ctx.lib.tqp_hash_groupby(ctx.h, _p(gkey), n, _p(d_n), _p(val), _p(dval), _p(out["key"]),
+                                                 _p(out["cnt"]), _p(out["sum"]), _p(out["min"]), _p(out["max"]),
+                                                 _p(out["ndist"]), gcap, _p(out["d_ngroups"]), ws, sz, s),
+         "tqp_hash_groupby", dev)
     return out
 
 

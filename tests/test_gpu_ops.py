@@ -320,6 +320,97 @@ def test_groupby_parity(hip, ctx, n, domain):
     assert ctx.errors() == 0
 
 
+def _hash_groupby_case(hip, ctx, keys, val, dval, gcap=None, d_n=None):
+    """Hash group-by with every aggregate against the oracle's group-by and
+    min / max / count distinct.  The hash output has no fixed order: it is
+    sorted by key (keys are unique) before the element-wise comparison."""
+    n = len(keys) if d_n is None else d_n
+    wk, ws, wc, _ = oracle.groupby(keys[:n], val[:n])
+    mk, mlo, mhi, mnd = oracle.group_minmax(keys[:n], val[:n])
+    dk, _, _, dnd = oracle.group_minmax(keys[:n], dval[:n].astype(np.int64))
+    assert np.array_equal(wk, mk) and np.array_equal(wk, dk)
+    dn = None if d_n is None else _dev(np.array([d_n], np.int64))
+    out = hip.hash_groupby(ctx, _dev(keys), _dev(val), _dev(dval), minmax=True,
+                           gcap=max(1, len(wk)) if gcap is None else gcap, d_n=dn)
+    G = int(_np(out["d_ngroups"])[0])
+    assert G == len(wk)
+    o = np.argsort(_np(out["key"], G), kind="stable")
+    assert np.array_equal(_np(out["key"], G)[o], wk)
+    assert np.array_equal(_np(out["cnt"], G)[o], wc)
+    assert np.array_equal(_np(out["sum"], G)[o], ws)
+    assert np.array_equal(_np(out["min"], G)[o], mlo)
+    assert np.array_equal(_np(out["max"], G)[o], mhi)
+    assert np.array_equal(_np(out["ndist"], G)[o], dnd)
+    assert ctx.errors() == 0
+
+
+# few groups take the per-block LDS table (gcap <= 512), the rest the global table
+@pytest.mark.parametrize("n,domain", [(0, 5), (1, 5), (4097, 1), (70_001, 6), (300_007, 500), (300_007, 5000),
+                                      (300_007, 1 << 20), (65_536, 65_536), (1_000_003, 1 << 31)])
+def test_hash_groupby_parity(hip, ctx, n, domain):
+    rng = _rng(n + domain + 5)
+    keys = rng.integers(0, domain, n).astype(np.int32)
+    val = rng.integers(-(1 << 40), 1 << 40, n).astype(np.int64)
+    dval = rng.integers(0, 37, n).astype(np.int32)       # repeats inside every group
+    _hash_groupby_case(hip, ctx, keys, val, dval)
+
+
+def test_hash_groupby_paths(hip, ctx):
+    """The same 300 groups through the LDS path (gcap = 300) and the global
+    path (gcap = 10_000); the value extremes of int64 for min and max; the
+    device row count below the host bound."""
+    rng = _rng(77)
+    keys = rng.integers(0, 300, 200_000).astype(np.int32)
+    val = rng.integers(-5, 5, 200_000).astype(np.int64)
+    val[rng.integers(0, 200_000, 50)] = np.iinfo(np.int64).max
+    val[rng.integers(0, 200_000, 50)] = np.iinfo(np.int64).min + 1
+    dval = rng.integers(-3, 3, 200_000).astype(np.int32)
+    # sums would overflow with both extremes in one group: take min and max only from this input
+    wk, mlo, mhi, _ = oracle.group_minmax(keys, val)
+    for gcap in (300, 10_000):
+        out = hip.hash_groupby(ctx, _dev(keys), _dev(val), minmax=True, with_sum=False, gcap=gcap)
+        G = int(_np(out["d_ngroups"])[0])
+        assert G == len(wk)
+        o = np.argsort(_np(out["key"], G))
+        assert np.array_equal(_np(out["min"], G)[o], mlo) and np.array_equal(_np(out["max"], G)[o], mhi)
+        assert out["sum"] is None
+        assert ctx.errors() == 0
+        _hash_groupby_case(hip, ctx, keys, val % 1000, dval, gcap=gcap, d_n=150_001)
+
+
+def test_hash_groupby_count_only(hip, ctx):
+    """COUNT(*) and COUNT(DISTINCT) with no value column at all."""
+    rng = _rng(78)
+    keys = rng.integers(0, 3000, 100_000).astype(np.int32)
+    dval = rng.integers(0, 100, 100_000).astype(np.int32)
+    wk, _, wc, _ = oracle.groupby(keys, np.zeros(len(keys), np.int64))
+    _, _, _, wnd = oracle.group_minmax(keys, dval.astype(np.int64))
+    out = hip.hash_groupby(ctx, _dev(keys), dval=_dev(dval), gcap=4000)
+    G = int(_np(out["d_ngroups"])[0])
+    o = np.argsort(_np(out["key"], G))
+    assert G == len(wk) and np.array_equal(_np(out["key"], G)[o], wk)
+    assert np.array_equal(_np(out["cnt"], G)[o], wc) and np.array_equal(_np(out["ndist"], G)[o], wnd)
+    assert ctx.errors() == 0
+
+
+@pytest.mark.parametrize("gcap", [0, 100, 600, 5000])
+def test_hash_groupby_errors(hip, ctx, gcap):
+    """More groups than gcap: the capacity flag, and no more than gcap rows;
+    a negative key: the key-range flag and its row left out."""
+    rng = _rng(79)
+    keys = rng.integers(0, 8000, 50_000).astype(np.int32)
+    val = rng.integers(0, 100, 50_000).astype(np.int64)
+    hip.hash_groupby(ctx, _dev(keys), _dev(val), gcap=gcap)
+    assert ctx.errors() & hip.DEVERR_CAPACITY
+    keys[[5, 7]] = -4
+    wk, ws, wc, _ = oracle.groupby(keys[keys >= 0], val[keys >= 0])
+    out = hip.hash_groupby(ctx, _dev(keys), _dev(val), gcap=8000)
+    assert ctx.errors() == hip.DEVERR_KEY_RANGE
+    G = int(_np(out["d_ngroups"])[0])
+    o = np.argsort(_np(out["key"], G))
+    assert G == len(wk) and np.array_equal(_np(out["sum"], G)[o], ws) and np.array_equal(_np(out["cnt"], G)[o], wc)
+
+
 # ------------------------------------------------------------------ top-k
 @pytest.mark.parametrize("n,k", [(0, 10), (5, 10), (100, 100), (2048, 100), (2049, 7), (1_500_000, 100),
                                  (300_000, 1024)])
