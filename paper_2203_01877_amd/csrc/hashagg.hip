@@ -21,9 +21,22 @@
 // free slot is always confirmed by the compare-and-swap or an agent-scope
 // load.
 //
-// Few groups (gcap <= HA_LDS_GROUPS): each block first aggregates its rows
-// in a table in LDS and merges its groups into the global table at the end,
-// so the global atomics per block are one per group, not one per row.
+// Few groups (a table of 2 * gcap slots fits in 64 KB of LDS: gcap <= 2048
+// for sum and count, fewer with min / max and distinct counts): each block
+// first aggregates its rows in a table in LDS and merges its groups into the
+// global table at the end, so the global atomics per block are one per
+// group, not one per row.
+//
+// Many groups with sum / min / max (a partitioned hash aggregation): the
+// global table would take every row's update as device-scope atomics, which
+// on a chip of eight L2 caches are performed beyond them, far below the HBM
+// rate.  Instead one radix pass (two above 2^16 partitions) moves the rows,
+// values alongside, into 2^P partitions by the top P bits of h = key * HP_MUL
+// mod 2^32 (odd, so h is a bijection of the key and the key is h * HP_INV);
+// then one block per partition aggregates it in an LDS table keyed by the
+// next bits of h and writes its groups straight out.  P is chosen so that a
+// partition holds about a quarter of its table's slots; a partition that
+// still overflows its table sets TQP_DEVERR_CAPACITY.
 //
 // COUNT(DISTINCT d): a second table of 64-bit entries (key + 1, d) as a set;
 // the row that inserts a pair adds one to its group's distinct count.
@@ -32,14 +45,15 @@
 // ballots), the group count in *d_ngroups.
 #include "dev.hpp"
 #include "host.hpp"
+#include "radix.hpp"
 
 namespace tqp {
 namespace {
 
 constexpr int HA_BLOCK = 256;
 constexpr int HA_ITEMS = 4;                 // rows per thread per step, probed in lockstep
-constexpr int HA_LDS = 1024;                // slots of the per-block table
-constexpr int64_t HA_LDS_GROUPS = HA_LDS / 2;
+constexpr int HA_LDS_MIN = 256;             // slots of the per-block table: 2 * gcap, at least this
+constexpr int HA_LDS_BYTES = 65536;         // and at most this much LDS
 constexpr uint32_t HA_PROBE_LIMIT = 4096;
 constexpr unsigned long long ORD_BIAS = 1ull << 63;
 
@@ -250,15 +264,23 @@ __global__ void __launch_bounds__(HA_BLOCK) k_ha_global(HaArgs a) {
 // holds, which only an input with more than gcap groups reaches) goes to the
 // global table directly.
 template <bool VAL, bool MINMAX, bool DIST>
-__global__ void __launch_bounds__(HA_BLOCK) k_ha_local(HaArgs a) {
-    constexpr int SV = VAL ? HA_LDS : 1, SM = MINMAX ? HA_LDS : 1, SD = DIST ? HA_LDS : 1;
-    __shared__ uint32_t s_key[HA_LDS];
-    __shared__ uint32_t s_cnt[HA_LDS];
-    __shared__ unsigned long long s_sum[SV];
-    __shared__ unsigned long long s_max[SM];
-    __shared__ unsigned long long s_nmin[SM];
-    __shared__ uint32_t s_nd[SD];
-    for (int i = threadIdx.x; i < HA_LDS; i += HA_BLOCK) {
+constexpr int ha_lds_slot_bytes() {
+    return 8 + (VAL ? 8 : 0) + (MINMAX ? 16 : 0) + (DIST ? 4 : 0);
+}
+
+// The table has S = 2^lg slots in dynamic LDS (S * ha_lds_slot_bytes bytes):
+// the 8-byte columns first, then the 4-byte ones.
+template <bool VAL, bool MINMAX, bool DIST>
+__global__ void __launch_bounds__(HA_BLOCK) k_ha_local(HaArgs a, int lg) {
+    extern __shared__ __align__(16) unsigned long long ha_smem[];
+    const int S = 1 << lg;
+    unsigned long long* s_sum = ha_smem;
+    unsigned long long* s_max = s_sum + (VAL ? S : 0);
+    unsigned long long* s_nmin = s_max + (MINMAX ? S : 0);
+    uint32_t* s_key = reinterpret_cast<uint32_t*>(s_nmin + (MINMAX ? S : 0));
+    uint32_t* s_cnt = s_key + S;
+    uint32_t* s_nd = s_cnt + S;
+    for (int i = threadIdx.x; i < S; i += HA_BLOCK) {
         s_key[i] = 0u;
         s_cnt[i] = 0u;
         if (VAL) s_sum[i] = 0ull;
@@ -266,7 +288,6 @@ __global__ void __launch_bounds__(HA_BLOCK) k_ha_local(HaArgs a) {
         if (DIST) s_nd[i] = 0u;
     }
     __syncthreads();
-    const int lg = 31 - __clz(HA_LDS);
     const int64_t n = ha_rows(a);
     const int64_t step = (int64_t)gridDim.x * HA_BLOCK * HA_ITEMS;
     for (int64_t base = (int64_t)blockIdx.x * HA_BLOCK * HA_ITEMS; base < n; base += step) {
@@ -283,11 +304,11 @@ __global__ void __launch_bounds__(HA_BLOCK) k_ha_local(HaArgs a) {
             spill[j] = false;
             if (!in[j]) continue;
             uint32_t s = ha_home(k1[j], lg);
-            for (int p = 0; p < HA_LDS; ++p) {
+            for (int p = 0; p < S; ++p) {
                 uint32_t cur = s_key[s];
                 if (cur == 0u) cur = atomicCAS(&s_key[s], 0u, k1[j]);
                 if (cur == 0u || cur == k1[j]) { ls[j] = (int32_t)s; break; }
-                s = (s + 1) & (HA_LDS - 1);
+                s = (s + 1) & (S - 1);
             }
             spill[j] = ls[j] < 0;
             if (ls[j] >= 0) {
@@ -329,7 +350,7 @@ __global__ void __launch_bounds__(HA_BLOCK) k_ha_local(HaArgs a) {
     }
     __syncthreads();
     // merge this block's groups
-    for (int i0 = 0; i0 < HA_LDS; i0 += HA_BLOCK) {
+    for (int i0 = 0; i0 < S; i0 += HA_BLOCK) {
         const int i = i0 + threadIdx.x;
         uint32_t k1[1] = {s_key[i]};
         bool in[1] = {k1[0] != 0u};
@@ -358,30 +379,53 @@ struct HaOut {
     int64_t gcap;
 };
 
-// Compaction of the occupied slots: one atomic per wave reserves the wave's
-// output rows.
+// Compaction of the occupied slots.  A block takes chunks of HE_PER * 256
+// slots; one atomic per chunk reserves the chunk's output rows (a counter
+// shared by every wave would serialise the waves on one address).
+constexpr int HE_PER = 16;
+
 __global__ void __launch_bounds__(256)
 k_ha_emit(const HaSlot* t, int64_t m, const uint32_t* ndist, HaOut o, unsigned long long* d_out) {
-    const int l = lane_id();
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x - l); b < m; b += stride) {
-        const int64_t i = b + l;
-        const bool occ = i < m && t[i].key1 != 0u;
-        const uint64_t mk = ballot(occ);
-        if (!mk) continue;
-        unsigned long long base = 0;
-        if (l == 0) base = atomicAdd(d_out, (unsigned long long)popc64(mk));
-        base = __shfl(base, 0);
-        const int64_t r = (int64_t)base + popc64(mk & lanemask_lt());
-        if (occ && r < o.gcap) {
-            const HaSlot s = t[i];
-            o.key[r] = (int32_t)(s.key1 - 1u);
-            o.cnt[r] = s.cnt;
-            if (o.sum) o.sum[r] = (int64_t)s.sum;
-            if (o.max) o.max[r] = (int64_t)(s.max ^ ORD_BIAS);
-            if (o.min) o.min[r] = (int64_t)(~s.nmin ^ ORD_BIAS);
-            if (o.ndist) o.ndist[r] = ndist[i];
+    __shared__ int64_t s_w[256 / WAVE];
+    __shared__ unsigned long long s_base;
+    const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
+    constexpr int64_t CH = (int64_t)256 * HE_PER;
+    for (int64_t c0 = (int64_t)blockIdx.x * CH; c0 < m; c0 += (int64_t)gridDim.x * CH) {
+        uint32_t occ = 0;
+#pragma unroll
+        for (int q = 0; q < HE_PER; ++q) {
+            const int64_t i = c0 + (int64_t)q * 256 + tid;
+            if (i < m && t[i].key1 != 0u) occ |= 1u << q;
         }
+        const int64_t cnt = __popc(occ);
+        const int64_t incl = wave_incl_sum(cnt);
+        if (l == WAVE - 1) s_w[w] = incl;
+        __syncthreads();
+        int64_t before = 0, tot = 0;
+#pragma unroll
+        for (int ww = 0; ww < 256 / WAVE; ++ww) {
+            if (ww < w) before += s_w[ww];
+            tot += s_w[ww];
+        }
+        if (tid == 0) s_base = tot ? atomicAdd(d_out, (unsigned long long)tot) : 0ull;
+        __syncthreads();
+        int64_t r = (int64_t)s_base + before + incl - cnt;
+#pragma unroll
+        for (int q = 0; q < HE_PER; ++q) {
+            if (!((occ >> q) & 1u)) continue;
+            const int64_t i = c0 + (int64_t)q * 256 + tid;
+            if (r < o.gcap) {
+                const HaSlot s = t[i];
+                o.key[r] = (int32_t)(s.key1 - 1u);
+                o.cnt[r] = s.cnt;
+                if (o.sum) o.sum[r] = (int64_t)s.sum;
+                if (o.max) o.max[r] = (int64_t)(s.max ^ ORD_BIAS);
+                if (o.min) o.min[r] = (int64_t)(~s.nmin ^ ORD_BIAS);
+                if (o.ndist) o.ndist[r] = ndist[i];
+            }
+            ++r;
+        }
+        __syncthreads();
     }
 }
 
@@ -393,27 +437,216 @@ __global__ void k_ha_finish(const unsigned long long* d_out, int64_t gcap, int64
     }
 }
 
+// ---------------------------------------------------------------- partitioned
+constexpr uint32_t HP_MUL = 0x9E3779B1u;
+constexpr uint32_t inv_odd(uint32_t a) {
+    uint32_t x = a;                                   // Newton's iteration for the inverse mod 2^32
+    for (int i = 0; i < 5; ++i) x *= 2u - a * x;
+    return x;
+}
+constexpr uint32_t HP_INV = inv_odd(HP_MUL);
+static_assert(HP_MUL * HP_INV == 1u, "HP_INV inverts HP_MUL");
+constexpr int HP_BLOCK = 1024;
+constexpr int HP_MIN_BITS = 8;                  // at least 256 partitions: one block per CU or more
+
+// Rows as (h, value); a negative key is reported and its row left out.
+struct SrcHashPart {
+    const int32_t* key;
+    const int64_t* val;
+    int64_t n_upper;
+    const int64_t* d_n;
+    uint32_t* flags;
+    __device__ int64_t size() const {
+        if (!d_n) return n_upper;
+        const int64_t n = *d_n;
+        return n < n_upper ? n : n_upper;
+    }
+    __device__ bool load_key(int64_t i, uint32_t& k) const {
+        const int32_t x = key[i];
+        if (x < 0) set_flag(flags, FLAG_KEY_RANGE);
+        k = (uint32_t)x * HP_MUL;
+        return x >= 0;
+    }
+    __device__ bool load(int64_t i, uint32_t& k, uint64_t& v) const {
+        const int32_t x = key[i];
+        k = (uint32_t)x * HP_MUL;
+        v = (uint64_t)val[i];
+        return x >= 0;
+    }
+};
+
+// start[p] = first row of partition p (rows sorted by their top P bits of h),
+// start[2^P] = the row count.
+__global__ void __launch_bounds__(256)
+k_hp_bounds(const uint32_t* h, const int64_t* d_cnt, int P, int64_t* start) {
+    const int64_t np = int64_t(1) << P;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > np) return;
+    const int64_t n = *d_cnt;
+    if (p == np) {
+        start[p] = n;
+        return;
+    }
+    const int sh = 32 - P;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)(h[mid] >> sh) < p) lo = mid + 1;
+        else hi = mid;
+    }
+    start[p] = lo;
+}
+
+// One block per partition: LDS table of 2^lg slots, keyed by key + 1, home
+// slot from the bits of h below the partition bits; then the block's groups
+// are written at an offset reserved with one atomic.
+template <bool MINMAX>
+__global__ void __launch_bounds__(HP_BLOCK)
+k_hp_agg(const uint32_t* h, const uint64_t* v, const int64_t* start, int P, int lg, HaOut o,
+         unsigned long long* d_out, uint32_t* flags) {
+    extern __shared__ __align__(16) unsigned long long ha_smem[];
+    __shared__ int64_t s_w[HP_BLOCK / WAVE];
+    __shared__ unsigned long long s_base;
+    const int S = 1 << lg;
+    unsigned long long* s_sum = ha_smem;
+    unsigned long long* s_max = s_sum + S;
+    unsigned long long* s_nmin = s_max + (MINMAX ? S : 0);
+    uint32_t* s_key = reinterpret_cast<uint32_t*>(s_nmin + (MINMAX ? S : 0));
+    uint32_t* s_cnt = s_key + S;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < S; i += HP_BLOCK) {
+        s_key[i] = 0u;
+        s_cnt[i] = 0u;
+        s_sum[i] = 0ull;
+        if (MINMAX) s_max[i] = 0ull, s_nmin[i] = 0ull;
+    }
+    __syncthreads();
+    const int64_t b = start[blockIdx.x], e = start[blockIdx.x + 1];
+    const int hs = P + lg <= 32 ? 32 - lg : P;     // h << P >> hs: lg bits below the partition bits
+    for (int64_t i0 = b; i0 < e; i0 += (int64_t)HP_BLOCK * HA_ITEMS) {
+        uint32_t hh[HA_ITEMS];
+        uint64_t vv[HA_ITEMS];
+#pragma unroll
+        for (int j = 0; j < HA_ITEMS; ++j) {
+            const int64_t i = i0 + (int64_t)j * HP_BLOCK + tid;
+            hh[j] = i < e ? h[i] : 0u;
+            vv[j] = i < e ? v[i] : 0ull;
+        }
+#pragma unroll
+        for (int j = 0; j < HA_ITEMS; ++j) {
+            const int64_t i = i0 + (int64_t)j * HP_BLOCK + tid;
+            if (i >= e) continue;
+            const uint32_t k1 = hh[j] * HP_INV + 1u;
+            uint32_t sl = P < 32 ? ((hh[j] << P) >> hs) & (uint32_t)(S - 1) : 0u;
+            int found = -1;
+            for (int q = 0; q < S; ++q) {
+                uint32_t cur = s_key[sl];
+                if (cur == 0u) cur = atomicCAS(&s_key[sl], 0u, k1);
+                if (cur == 0u || cur == k1) { found = (int)sl; break; }
+                sl = (sl + 1) & (uint32_t)(S - 1);
+            }
+            if (found < 0) {
+                set_flag(flags, FLAG_CAPACITY);       // more groups in this partition than slots
+                continue;
+            }
+            atomicAdd(&s_cnt[found], 1u);
+            atomicAdd(&s_sum[found], (unsigned long long)vv[j]);
+            if (MINMAX) {
+                const unsigned long long ov = vv[j] ^ ORD_BIAS;
+                atomicMax(&s_max[found], ov);
+                atomicMax(&s_nmin[found], ~ov);
+            }
+        }
+    }
+    __syncthreads();
+    // compaction of the occupied slots: slot q * HP_BLOCK + tid is bit q of occ
+    const int per = S > HP_BLOCK ? S / HP_BLOCK : 1;
+    uint32_t occ = 0;
+    for (int q = 0; q < per; ++q) {
+        const int i = q * HP_BLOCK + tid;
+        if (i < S && s_key[i] != 0u) occ |= 1u << q;
+    }
+    const int64_t cnt = __popc(occ);
+    const int64_t incl = wave_incl_sum(cnt);
+    const int w = tid / WAVE;
+    if (lane_id() == WAVE - 1) s_w[w] = incl;
+    __syncthreads();
+    int64_t before = 0, tot = 0;
+    for (int ww = 0; ww < HP_BLOCK / WAVE; ++ww) {
+        if (ww < w) before += s_w[ww];
+        tot += s_w[ww];
+    }
+    if (tid == 0) s_base = tot ? atomicAdd(d_out, (unsigned long long)tot) : 0ull;
+    __syncthreads();
+    int64_t r = (int64_t)s_base + before + incl - cnt;
+    for (int q = 0; q < per; ++q) {
+        if (!((occ >> q) & 1u)) continue;
+        const int i = q * HP_BLOCK + tid;
+        if (r < o.gcap) {
+            o.key[r] = (int32_t)(s_key[i] - 1u);
+            o.cnt[r] = s_cnt[i];
+            if (o.sum) o.sum[r] = (int64_t)s_sum[i];
+            if (MINMAX) {
+                if (o.max) o.max[r] = (int64_t)(s_max[i] ^ ORD_BIAS);
+                if (o.min) o.min[r] = (int64_t)(~s_nmin[i] ^ ORD_BIAS);
+            }
+        }
+        ++r;
+    }
+}
+
+template <bool MINMAX>
+constexpr int hp_slot_bytes() {
+    return 16 + (MINMAX ? 16 : 0);
+}
+
+// Partition bits and LDS table size for gcap groups: about S / 4 groups per
+// partition, S at most 64 KB of LDS and at most 32 slots per thread.
+template <bool MINMAX>
+void hp_plan(int64_t gcap, int& P, int& lg) {
+    int lmax = 0;
+    while ((int64_t(2) << lmax) * hp_slot_bytes<MINMAX>() <= HA_LDS_BYTES) ++lmax;
+    P = HP_MIN_BITS;
+    while ((gcap >> P) > ((int64_t(1) << lmax) >> 2) && P < 24) ++P;
+    const int64_t per = (gcap + (int64_t(1) << P) - 1) >> P;
+    lg = 8;
+    while ((int64_t(1) << lg) < 4 * per && lg < lmax) ++lg;
+}
+
+// log2 of the LDS table's slots for gcap groups, or -1 when it would not fit
+// (the global table then takes every row).
 template <bool VAL, bool MINMAX, bool DIST>
-tqp_status ha_run(tqp_ctx* ctx, const HaArgs& a, bool local, int64_t n, hipStream_t stream) {
-    static const int per_cu[2] = {
-        [] {
-            int b = 4;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_ha_global<VAL, MINMAX, DIST>, HA_BLOCK, 0) !=
+int ha_lds_log2(int64_t gcap) {
+    int lg = 0;
+    while ((int64_t(1) << lg) < 2 * gcap || (1 << lg) < HA_LDS_MIN) ++lg;
+    return ((int64_t(1) << lg) * ha_lds_slot_bytes<VAL, MINMAX, DIST>() <= HA_LDS_BYTES) ? lg : -1;
+}
+
+template <bool VAL, bool MINMAX, bool DIST>
+tqp_status ha_run(tqp_ctx* ctx, const HaArgs& a, int64_t gcap, int64_t n, hipStream_t stream) {
+    static const int per_cu_global = [] {
+        int b = 4;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_ha_global<VAL, MINMAX, DIST>, HA_BLOCK, 0) !=
+            hipSuccess)
+            b = 4;
+        return b < 1 ? 1 : b;
+    }();
+    static int per_cu_local[32] = {};               // by log2 of the LDS slots
+    const int lg = ha_lds_log2<VAL, MINMAX, DIST>(gcap);
+    if (lg >= 0) {
+        const size_t lds = ((size_t)1 << lg) * ha_lds_slot_bytes<VAL, MINMAX, DIST>();
+        if (!per_cu_local[lg]) {
+            int b = 1;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_ha_local<VAL, MINMAX, DIST>, HA_BLOCK, lds) !=
                 hipSuccess)
-                b = 4;
-            return b < 1 ? 1 : b;
-        }(),
-        [] {
-            int b = 2;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_ha_local<VAL, MINMAX, DIST>, HA_BLOCK, 0) !=
-                hipSuccess)
-                b = 2;
-            return b < 1 ? 1 : b;
-        }()};
-    const int grid = grid_for(n, (int64_t)HA_BLOCK * HA_ITEMS, (int64_t)ctx->num_cus * per_cu[local ? 1 : 0]);
-    if (local) {
-        TQP_LAUNCH(ctx, stream, "hashagg_local", k_ha_local<VAL, MINMAX, DIST><<<grid, HA_BLOCK, 0, stream>>>(a));
+                b = 1;
+            per_cu_local[lg] = b < 1 ? 1 : b;
+        }
+        const int grid = grid_for(n, (int64_t)HA_BLOCK * HA_ITEMS, (int64_t)ctx->num_cus * per_cu_local[lg]);
+        TQP_LAUNCH(ctx, stream, "hashagg_local",
+                   k_ha_local<VAL, MINMAX, DIST><<<grid, HA_BLOCK, lds, stream>>>(a, lg));
     } else {
+        const int grid = grid_for(n, (int64_t)HA_BLOCK * HA_ITEMS, (int64_t)ctx->num_cus * per_cu_global);
         TQP_LAUNCH(ctx, stream, "hashagg_global", k_ha_global<VAL, MINMAX, DIST><<<grid, HA_BLOCK, 0, stream>>>(a));
     }
     return TQP_OK;
@@ -442,6 +675,52 @@ tqp_status tqp_hash_groupby(tqp_ctx* ctx, const int32_t* gkey, int64_t n, const 
     const bool want_val = out_sum || out_min || out_max;
     const bool want_mm = out_min || out_max;
     const bool want_dist = out_ndist != nullptr;
+    // many groups with sum / min / max: partitioned (no global table)
+    const bool part = want_val && !want_dist && n > 0 &&
+                      (want_mm ? ha_lds_log2<true, true, false>(gcap) : ha_lds_log2<true, false, false>(gcap)) < 0;
+    if (part) {
+        int P = 0, lg = 0;
+        if (want_mm) hp_plan<true>(gcap, P, lg);
+        else hp_plan<false>(gcap, P, lg);
+        RadixBufs<R8, uint64_t> rb;
+        uint32_t* hk = nullptr;
+        uint64_t* hv = nullptr;
+        int64_t* start = nullptr;
+        unsigned long long* d_out = nullptr;
+        Arena ar;
+        auto plan = [&](Arena& p) {
+            rb = radix_reserve<R8, uint64_t>(p, n, 32, 32 - P);
+            d_out = p.zero<unsigned long long>(1);
+            hk = p.scratch<uint32_t>(n);
+            hv = p.scratch<uint64_t>(n);
+            start = p.scratch<int64_t>((int64_t(1) << P) + 1);
+        };
+        tqp_status st = with_workspace(ctx, ws, ws_bytes, stream, plan, ar);
+        if (st != TQP_OK || !ws) return st;
+        if ((st = fill_zero(ar.base, ar.zsize, stream, ctx)) != TQP_OK) return st;
+        SrcHashPart src{gkey, val, n, d_n, ctx->d_err};
+        st = radix_launch<R8, uint64_t>(rb, src, n, true, nullptr, ~0u, hk, hv, ctx, stream, "hashpart_pass",
+                                        "hashpart_pass");
+        if (st != TQP_OK) return st;
+        const int64_t np = int64_t(1) << P;
+        TQP_LAUNCH(ctx, stream, "hashpart_bounds",
+                   k_hp_bounds<<<grid_for(np + 1, 256, 0), 256, 0, stream>>>(hk, rb.d_cnt, P, start));
+        HaOut o{out_key, out_cnt, out_sum, out_min, out_max, nullptr, gcap};
+        if (want_mm) {
+            const size_t lds = ((size_t)1 << lg) * hp_slot_bytes<true>();
+            TQP_LAUNCH(ctx, stream, "hashpart_agg",
+                       k_hp_agg<true><<<(unsigned)np, HP_BLOCK, lds, stream>>>(hk, hv, start, P, lg, o, d_out,
+                                                                                 ctx->d_err));
+        } else {
+            const size_t lds = ((size_t)1 << lg) * hp_slot_bytes<false>();
+            TQP_LAUNCH(ctx, stream, "hashpart_agg",
+                       k_hp_agg<false><<<(unsigned)np, HP_BLOCK, lds, stream>>>(hk, hv, start, P, lg, o, d_out,
+                                                                                  ctx->d_err));
+        }
+        TQP_LAUNCH(ctx, stream, "hashagg_finish",
+                   k_ha_finish<<<1, 64, 0, stream>>>(d_out, gcap, d_ngroups, ctx->d_err));
+        return TQP_OK;
+    }
     int log2m = 0;
     while ((int64_t(1) << log2m) < 2 * gcap) ++log2m;
     const int64_t m = int64_t(1) << log2m;
@@ -464,22 +743,21 @@ tqp_status tqp_hash_groupby(tqp_ctx* ctx, const int32_t* gkey, int64_t n, const 
     if (st != TQP_OK || !ws) return st;
     if ((st = fill_zero(ar.base, ar.zsize, stream, ctx)) != TQP_OK) return st;
     HaArgs a{gkey, val, dval, n, d_n, table, log2m, ndist, set, log2s, d_groups, (uint32_t)gcap, ctx->d_err};
-    const bool local = gcap <= HA_LDS_GROUPS;
     if (n > 0) {
         if (want_dist) {
-            if (want_mm) st = ha_run<true, true, true>(ctx, a, local, n, stream);
-            else if (want_val) st = ha_run<true, false, true>(ctx, a, local, n, stream);
-            else st = ha_run<false, false, true>(ctx, a, local, n, stream);
+            if (want_mm) st = ha_run<true, true, true>(ctx, a, gcap, n, stream);
+            else if (want_val) st = ha_run<true, false, true>(ctx, a, gcap, n, stream);
+            else st = ha_run<false, false, true>(ctx, a, gcap, n, stream);
         } else {
-            if (want_mm) st = ha_run<true, true, false>(ctx, a, local, n, stream);
-            else if (want_val) st = ha_run<true, false, false>(ctx, a, local, n, stream);
-            else st = ha_run<false, false, false>(ctx, a, local, n, stream);
+            if (want_mm) st = ha_run<true, true, false>(ctx, a, gcap, n, stream);
+            else if (want_val) st = ha_run<true, false, false>(ctx, a, gcap, n, stream);
+            else st = ha_run<false, false, false>(ctx, a, gcap, n, stream);
         }
         if (st != TQP_OK) return st;
     }
     HaOut o{out_key, out_cnt, out_sum, out_min, out_max, out_ndist, gcap};
     TQP_LAUNCH(ctx, stream, "hashagg_emit",
-               k_ha_emit<<<grid_for(m, 256 * 4, (int64_t)ctx->num_cus * 8), 256, 0, stream>>>(table, m, ndist, o,
+               k_ha_emit<<<grid_for(m, 256 * HE_PER, (int64_t)ctx->num_cus * 4), 256, 0, stream>>>(table, m, ndist, o,
                                                                                               d_out));
     TQP_LAUNCH(ctx, stream, "hashagg_finish", k_ha_finish<<<1, 64, 0, stream>>>(d_out, gcap, d_ngroups, ctx->d_err));
     return TQP_OK;

@@ -378,6 +378,62 @@ def test_hash_groupby_paths(hip, ctx):
         _hash_groupby_case(hip, ctx, keys, val % 1000, dval, gcap=gcap, d_n=150_001)
 
 
+@pytest.mark.parametrize("domain,gcap", [(1500, 1500), (2048, 2048), (2048, 2049), (3000, 4000)])
+def test_hash_groupby_sum_count(hip, ctx, domain, gcap):
+    """SUM and COUNT only: the LDS table grows to 4096 slots (gcap <= 2048);
+    gcap 2049 and 4000 take the global table."""
+    rng = _rng(domain + gcap)
+    keys = rng.integers(0, domain, 400_001).astype(np.int32)
+    val = rng.integers(-10**12, 10**12, 400_001).astype(np.int64)
+    wk, ws, wc, _ = oracle.groupby(keys, val)
+    out = hip.hash_groupby(ctx, _dev(keys), _dev(val), gcap=gcap)
+    G = int(_np(out["d_ngroups"])[0])
+    o = np.argsort(_np(out["key"], G))
+    assert G == len(wk) and np.array_equal(_np(out["key"], G)[o], wk)
+    assert np.array_equal(_np(out["sum"], G)[o], ws) and np.array_equal(_np(out["cnt"], G)[o], wc)
+    assert ctx.errors() == 0
+
+
+@pytest.mark.parametrize("n,domain,minmax", [(1, 1, False), (5000, 3000, True), (300_007, 150_000, False),
+                                             (1_000_003, 1 << 20, True), (1_000_003, 1 << 31, False),
+                                             (2_000_000, 40_000_000, True)])
+def test_hash_groupby_partitioned(hip, ctx, n, domain, minmax):
+    """Many groups with sum (and min / max): the radix-partitioned path, one
+    LDS table per partition; gcap = the key domain bound (2^20 partitions
+    and more for the widest), a device row count below the host bound."""
+    rng = _rng(n + domain)
+    keys = rng.integers(0, domain, n).astype(np.int32)
+    val = rng.integers(-(1 << 40), 1 << 40, n).astype(np.int64)
+    dn = n - n // 7
+    wk, ws, wc, _ = oracle.groupby(keys[:dn], val[:dn])
+    _, mlo, mhi, _ = oracle.group_minmax(keys[:dn], val[:dn])
+    gcap = max(3000, min(domain, 2 * n))
+    out = hip.hash_groupby(ctx, _dev(keys), _dev(val), gcap=gcap, minmax=minmax,
+                           d_n=_dev(np.array([dn], np.int64)))
+    G = int(_np(out["d_ngroups"])[0])
+    assert G == len(wk)
+    o = np.argsort(_np(out["key"], G))
+    assert np.array_equal(_np(out["key"], G)[o], wk)
+    assert np.array_equal(_np(out["cnt"], G)[o], wc) and np.array_equal(_np(out["sum"], G)[o], ws)
+    if minmax:
+        assert np.array_equal(_np(out["min"], G)[o], mlo) and np.array_equal(_np(out["max"], G)[o], mhi)
+    assert ctx.errors() == 0
+
+
+def test_hash_groupby_partitioned_negative_key(hip, ctx):
+    rng = _rng(91)
+    keys = rng.integers(0, 100_000, 200_000).astype(np.int32)
+    val = rng.integers(0, 1000, 200_000).astype(np.int64)
+    keys[[3, 99_999]] = [-1, -(1 << 31)]
+    wk, ws, wc, _ = oracle.groupby(keys[keys >= 0], val[keys >= 0])
+    out = hip.hash_groupby(ctx, _dev(keys), _dev(val), gcap=100_000)
+    assert ctx.errors() == hip.DEVERR_KEY_RANGE
+    G = int(_np(out["d_ngroups"])[0])
+    o = np.argsort(_np(out["key"], G))
+    assert G == len(wk) and np.array_equal(_np(out["key"], G)[o], wk)
+    assert np.array_equal(_np(out["sum"], G)[o], ws) and np.array_equal(_np(out["cnt"], G)[o], wc)
+
+
 def test_hash_groupby_count_only(hip, ctx):
     """COUNT(*) and COUNT(DISTINCT) with no value column at all."""
     rng = _rng(78)
