@@ -21,11 +21,11 @@
 // free slot is always confirmed by the compare-and-swap or an agent-scope
 // load.
 //
-// Few groups (a table of 2 * gcap slots fits in 64 KB of LDS: gcap <= 2048
-// for sum and count, fewer with min / max and distinct counts): each block
-// first aggregates its rows in a table in LDS and merges its groups into the
-// global table at the end, so the global atomics per block are one per
-// group, not one per row.
+// Few groups (a table of 2 * gcap slots fits in 64 KB of LDS, 128 KB with
+// distinct counts: gcap <= 2048 for sum and count, 1024 with everything):
+// each block first aggregates its rows in a table in LDS and merges its
+// groups into the global table at the end, so the global atomics per block
+// are one per group, not one per row.
 //
 // Many groups with sum / min / max (a partitioned hash aggregation): the
 // global table would take every row's update as device-scope atomics, which
@@ -53,7 +53,10 @@ namespace {
 constexpr int HA_BLOCK = 256;
 constexpr int HA_ITEMS = 4;                 // rows per thread per step, probed in lockstep
 constexpr int HA_LDS_MIN = 256;             // slots of the per-block table: 2 * gcap, at least this
-constexpr int HA_LDS_BYTES = 65536;         // and at most this much LDS
+constexpr int HA_LDS_BYTES = 65536;         // LDS of a partition's table
+// LDS of the per-block table: 64 KB, or 128 KB (of the 160 KB of a CU) with
+// distinct counts, which have no partitioned path to fall back on
+constexpr int ha_local_bytes(bool dist) { return dist ? 131072 : 65536; }
 constexpr uint32_t HA_PROBE_LIMIT = 4096;
 constexpr unsigned long long ORD_BIAS = 1ull << 63;
 
@@ -619,7 +622,7 @@ template <bool VAL, bool MINMAX, bool DIST>
 int ha_lds_log2(int64_t gcap) {
     int lg = 0;
     while ((int64_t(1) << lg) < 2 * gcap || (1 << lg) < HA_LDS_MIN) ++lg;
-    return ((int64_t(1) << lg) * ha_lds_slot_bytes<VAL, MINMAX, DIST>() <= HA_LDS_BYTES) ? lg : -1;
+    return ((int64_t(1) << lg) * ha_lds_slot_bytes<VAL, MINMAX, DIST>() <= ha_local_bytes(DIST)) ? lg : -1;
 }
 
 template <bool VAL, bool MINMAX, bool DIST>
@@ -636,6 +639,10 @@ tqp_status ha_run(tqp_ctx* ctx, const HaArgs& a, int64_t gcap, int64_t n, hipStr
     if (lg >= 0) {
         const size_t lds = ((size_t)1 << lg) * ha_lds_slot_bytes<VAL, MINMAX, DIST>();
         if (!per_cu_local[lg]) {
+            if (lds > 65536 &&
+                hipFuncSetAttribute(reinterpret_cast<const void*>(k_ha_local<VAL, MINMAX, DIST>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+                return fail(TQP_ERR_HIP, "tqp_hash_groupby: %zu bytes of LDS refused", lds);
             int b = 1;
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_ha_local<VAL, MINMAX, DIST>, HA_BLOCK, lds) !=
                 hipSuccess)

@@ -236,6 +236,43 @@ tqp_status tqp_groupby_agg(tqp_ctx* ctx, const int32_t* gkey, int64_t n, const i
     if (n > MAX_ELEMS) return fail(TQP_ERR_UNSUPPORTED, "tqp_groupby_agg: n = %lld", (long long)n);
     const int kb = norm_key_bits(key_bits);
     const uint32_t mask = key_mask_for(kb);
+    if (!avg_in) {
+        // One value column: sort it alongside the keys (8-byte payload), so
+        // the run reduction reads the values in order instead of gathering
+        // them through the permutation.
+        return with_radix_cfg(ctx->digit_bits, [&](auto cfg) -> tqp_status {
+            using Cfg = decltype(cfg);
+            RadixBufs<Cfg, uint64_t> b;
+            uint32_t* skeys = nullptr;
+            uint64_t* svals = nullptr;
+            uint64_t* sstatus = nullptr;
+            uint32_t* scounter = nullptr;
+            const int64_t stiles = (n + SCfg::TILE - 1) / SCfg::TILE;
+            Arena a;
+            auto plan = [&](Arena& ar) {
+                b = radix_reserve<Cfg, uint64_t>(ar, n, kb);
+                sstatus = ar.zero<uint64_t>(stiles);
+                scounter = ar.zero<uint32_t>(1);
+                skeys = ar.scratch<uint32_t>(n);
+                svals = ar.scratch<uint64_t>(n);
+            };
+            tqp_status st = with_workspace(ctx, ws, ws_bytes, stream, plan, a);
+            if (st != TQP_OK || !ws) return st;
+            if ((st = fill_zero(a.base, a.zsize, stream, ctx)) != TQP_OK) return st;
+            if ((st = fill_zero(out_sum, gcap * 8, stream, ctx)) != TQP_OK) return st;
+            if ((st = fill_zero(out_cnt, gcap * 8, stream, ctx)) != TQP_OK) return st;
+            SrcPairs<uint64_t> src{reinterpret_cast<const uint32_t*>(gkey), reinterpret_cast<const uint64_t*>(sum_in),
+                                   n, d_n};
+            st = radix_launch<Cfg, uint64_t>(b, src, n, true, nullptr, mask, skeys, svals, ctx, stream);
+            if (st != TQP_OK) return st;
+            ValsDirect vs{reinterpret_cast<const int64_t*>(svals), nullptr};
+            SegOut o{out_key, out_sum, out_cnt, nullptr, gcap, d_ngroups};
+            TQP_LAUNCH(ctx, stream, "segreduce",
+                       k_segreduce<SCfg, ValsDirect, false><<<grid_for(n, SCfg::TILE, 0), SCfg::BLOCK, 0, stream>>>(
+                           skeys, vs, n, b.d_cnt, sstatus, scounter, o, ctx->d_err));
+            return TQP_OK;
+        });
+    }
     return with_radix_cfg(ctx->digit_bits, [&](auto cfg) -> tqp_status {
         using Cfg = decltype(cfg);
         RadixBufs<Cfg, uint32_t> b;

@@ -320,6 +320,32 @@ def test_groupby_parity(hip, ctx, n, domain):
     assert ctx.errors() == 0
 
 
+@pytest.mark.parametrize("digit_bits", [4, 8, 11])
+@pytest.mark.parametrize("n,domain", [(0, 5), (1, 5), (70_001, 6), (300_007, 5000), (300_007, 1 << 20),
+                                      (1_000_003, 1 << 31)])
+def test_groupby_sum_only(hip, ctx, n, domain, digit_bits):
+    """Without an averaged column the values are sorted alongside the keys
+    (8-byte payload) instead of gathered through the permutation; every
+    digit width, and a device row count below the host bound."""
+    rng = _rng(n + domain + digit_bits)
+    keys = rng.integers(0, domain, n).astype(np.int32)
+    val = rng.integers(-(1 << 50), 1 << 50, n).astype(np.int64)
+    dn = n - n // 5
+    wk, ws, wc, _ = oracle.groupby(keys[:dn], val[:dn])
+    kb = max(1, int(domain - 1).bit_length())
+    ctx.set_digit_bits(digit_bits)
+    try:
+        out = hip.groupby_agg(ctx, _dev(keys), _dev(val), key_bits=kb, gcap=max(1, len(wk)),
+                              d_n=_dev(np.array([dn], np.int64)))
+    finally:
+        ctx.set_digit_bits(8)
+    G = int(_np(out["d_ngroups"])[0])
+    assert G == len(wk)
+    assert np.array_equal(_np(out["key"], G), wk)
+    assert np.array_equal(_np(out["sum"], G), ws) and np.array_equal(_np(out["cnt"], G), wc)
+    assert ctx.errors() == 0
+
+
 def _hash_groupby_case(hip, ctx, keys, val, dval, gcap=None, d_n=None):
     """Hash group-by with every aggregate against the oracle's group-by and
     min / max / count distinct.  The hash output has no fixed order: it is
@@ -345,7 +371,8 @@ def _hash_groupby_case(hip, ctx, keys, val, dval, gcap=None, d_n=None):
 
 
 # few groups take the per-block LDS table (gcap <= 512), the rest the global table
-@pytest.mark.parametrize("n,domain", [(0, 5), (1, 5), (4097, 1), (70_001, 6), (300_007, 500), (300_007, 5000),
+@pytest.mark.parametrize("n,domain", [(0, 5), (1, 5), (4097, 1), (70_001, 6), (300_007, 500), (300_007, 1000),
+                                      (300_007, 5000),
                                       (300_007, 1 << 20), (65_536, 65_536), (1_000_003, 1 << 31)])
 def test_hash_groupby_parity(hip, ctx, n, domain):
     rng = _rng(n + domain + 5)
