@@ -60,6 +60,8 @@ def _L():
         lib.orc_groupby.restype = i64
         lib.orc_group_minmax.argtypes = [vp, i64, vp, vp, vp, vp, vp, i64]
         lib.orc_group_minmax.restype = i64
+        lib.orc_join_chain.argtypes = [ctypes.c_int, vp, vp, vp, vp, i64]
+        lib.orc_join_chain.restype = i64
         lib.orc_fragment_flags.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp, vp, i64, i32, i32,
                                            vp, vp, vp, vp, i64, vp]
         lib.orc_fragment_flags.restype = i64
@@ -197,6 +199,23 @@ def group_minmax(gkey, val):
     G = _L().orc_group_minmax(gkey.ctypes.data, n, val.ctypes.data, k.ctypes.data, lo.ctypes.data,
                               hi.ctypes.data, nd.ctypes.data, cap)
     return k[:G].copy(), lo[:G].copy(), hi[:G].copy(), nd[:G].copy()
+
+
+def join_chain(keys_out, keys_pk):
+    """Tuples (r0, ..., r_hops) of a chain of equi-joins: keys_out[t] of table t against keys_pk[t]
+    (the matched column of table t + 1).  Returns an int32 array of shape (count, hops + 1), nested
+    in input order."""
+    hops = len(keys_pk)
+    outs = [_c(k, np.int32) for k in keys_out]
+    pks = [np.zeros(1, np.int32)] + [_c(k, np.int32) for k in keys_pk]
+    nrows = np.array([len(outs[0])] + [len(k) for k in keys_pk], np.int64)
+    optr = (ctypes.c_void_p * hops)(*[o.ctypes.data for o in outs])
+    pptr = (ctypes.c_void_p * (hops + 1))(*[p.ctypes.data for p in pks])
+    args = (hops, ctypes.cast(optr, ctypes.c_void_p), nrows.ctypes.data, ctypes.cast(pptr, ctypes.c_void_p))
+    cnt = _L().orc_join_chain(*args, None, 0)
+    out = np.empty((max(1, cnt), hops + 1), np.int32)
+    _L().orc_join_chain(*args, out.ctypes.data, cnt)
+    return out[:cnt].copy()
 
 
 def fragment_flags(fact: dict, dim: dict, D: int, c: int) -> dict:

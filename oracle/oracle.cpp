@@ -151,6 +151,37 @@ int64_t orc_join(const int32_t* lkey, const int32_t* lrow, int64_t nl, const int
     return w;
 }
 
+// A chain of equi-joins, the shape of the multi-join plans of Section 6
+// (hand-optimized plans, the six-join query): tables 0..hops; table t < hops
+// has the key column outk[t] into table t + 1, whose matched column is pk[t + 1]
+// (pk[0] is unused).  Every tuple (r0, ..., r_hops) of row positions with
+// outk[t][r_t] == pk[t + 1][r_{t + 1}] for every t, nested in input order (r0
+// ascending, then r1 in input order, ...).  Tuples row-major in out_rows
+// (hops + 1 ints each); at most cap tuples written; returns the true count.
+int64_t orc_join_chain(int hops, const int32_t* const* outk, const int64_t* nrows, const int32_t* const* pk,
+                       int32_t* out_rows, int64_t cap) {
+    std::vector<std::unordered_map<int32_t, std::vector<int32_t>>> index(static_cast<size_t>(hops) + 1);
+    for (int t = 1; t <= hops; ++t)
+        for (int64_t j = 0; j < nrows[t]; ++j) index[t][pk[t][j]].push_back(static_cast<int32_t>(j));
+    std::vector<int32_t> tuple(static_cast<size_t>(hops) + 1);
+    int64_t w = 0;
+    // depth-first: extend a partial tuple ending at table t, row r
+    auto extend = [&](auto&& self, int t, int32_t r) -> void {
+        tuple[t] = r;
+        if (t == hops) {
+            if (w < cap)
+                for (int u = 0; u <= hops; ++u) out_rows[w * (hops + 1) + u] = tuple[u];
+            ++w;
+            return;
+        }
+        auto it = index[t + 1].find(outk[t][r]);
+        if (it == index[t + 1].end()) return;
+        for (int32_t next : it->second) self(self, t + 1, next);
+    };
+    for (int64_t i = 0; i < nrows[0]; ++i) extend(extend, 0, static_cast<int32_t>(i));
+    return w;
+}
+
 // Join kinds (the operator list at the start of Section 5 names left-outer,
 // left-semi and left-anti joins beside the natural join; Section 5.2 reaches
 // them by small changes to the sort-based join).  kind 0: inner, as orc_join.  kind 1, left semi: one row

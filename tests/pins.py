@@ -214,6 +214,43 @@ def check_pack_keys():
 
 # --------------------------------------------------------------------------- group-by
 
+def check_join_chain():
+    rng = _rng(15)
+    for trial in range(8):
+        hops = int(rng.integers(1, 4))
+        sizes = [int(rng.integers(0, 40)) for _ in range(hops + 1)]
+        doms = [int(rng.integers(1, 12)) for _ in range(hops)]
+        outs = [rng.integers(0, doms[t], sizes[t]).astype(np.int32) for t in range(hops)]
+        pks = [rng.integers(0, doms[t], sizes[t + 1]).astype(np.int32) for t in range(hops)]
+        got = oracle.join_chain(outs, pks)
+        # brute force: grow the tuples hop by hop with Python loops, in input order
+        tuples = [(i,) for i in range(sizes[0])]
+        for t in range(hops):
+            tuples = [tp + (j,) for tp in tuples for j in range(sizes[t + 1]) if outs[t][tp[-1]] == pks[t][j]]
+        assert got.shape == (len(tuples), hops + 1), ("chain shape", trial)
+        assert [tuple(r) for r in got.tolist()] == tuples, ("chain tuples", trial)
+        # closed form for the count: path counts carried back with bincount
+        c = np.ones(sizes[hops], np.int64)
+        for t in range(hops - 1, -1, -1):
+            per_key = np.bincount(pks[t], weights=c, minlength=doms[t]).astype(np.int64)
+            c = per_key[outs[t]]
+        assert len(got) == int(c.sum()), ("chain count", trial)
+    # one hop is the plain join, in the same order
+    lk = rng.integers(0, 30, 500).astype(np.int32)
+    rk = rng.integers(0, 30, 200).astype(np.int32)
+    wl, wr, _ = oracle.join(lk, rk)
+    got = oracle.join_chain([lk], [rk])
+    assert np.array_equal(got[:, 0], wl) and np.array_equal(got[:, 1], wr)
+    # two hops equal a join, a gather of the next key through its right rows, and a second join
+    pk1 = rng.integers(0, 30, 300).astype(np.int32)
+    k1 = rng.integers(0, 50, 300).astype(np.int32)
+    pk2 = rng.integers(0, 50, 80).astype(np.int32)
+    a, b, _ = oracle.join(lk, pk1)
+    i, c, _ = oracle.join(k1[b], pk2)
+    got = oracle.join_chain([lk, k1], [pk1, pk2])
+    assert np.array_equal(got, np.stack([a[i], b[i], c], axis=1).reshape(-1, 3))
+
+
 def check_groupby():
     rng = _rng(4)
     for trial in range(10):
@@ -374,5 +411,5 @@ def check_topk_ties():
 
 
 ALL_CHECKS = [check_filter, check_sort, check_join, check_join_kinds, check_join_band, check_pack_keys,
-              check_groupby, check_group_minmax, check_fragment_flags,
+              check_join_chain, check_groupby, check_group_minmax, check_fragment_flags,
               check_fragment_flags_invariants, check_fragment_cust, check_topk_ties]

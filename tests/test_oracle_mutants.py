@@ -37,6 +37,8 @@ MUTANTS = [
     ("min_is_max", "out_min[g] = *kv.second.begin();", "out_min[g] = *kv.second.rbegin();"),
     ("distinct_counts_rows", "std::map<int32_t, std::set<int64_t>> groups;",
      "std::map<int32_t, std::multiset<int64_t>> groups;"),
+    ("chain_first_match_only", "for (int32_t next : it->second) self(self, t + 1, next);",
+     "self(self, t + 1, it->second.front());"),
     ("cust_uses_fact_key", "Agg& a = groups[custkey[it->second]];", "Agg& a = groups[fk[f]];"),
     ("mid_first_match_only", "for (auto it = range.first; it != range.second; ++it) {\n            Agg& a = groups[custkey",
      "for (auto it = range.first; it != range.second; it = range.second) {\n            Agg& a = groups[custkey"),
