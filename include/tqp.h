@@ -213,6 +213,15 @@ tqp_status tqp_join_kind(tqp_ctx* ctx, int kind, const int32_t* lkey, const int3
 tqp_status tqp_pack_keys(tqp_ctx* ctx, const int32_t* const* cols, const int32_t* bits, int ncols, int64_t n,
                          const int64_t* d_n, int32_t* out, hipStream_t stream);
 
+/* Gather by row position, the late materialisation of Section 5.2 (joins
+ * return row positions; the columns a later operator needs, such as the next
+ * join's key in a chain of joins, are read through them): out[i] =
+ * src[idx[i]] for i < n (or *d_n), elements of elem_bytes = 4 or 8 bytes.  A
+ * negative idx[i] (the missing right row of an outer join) gives -1; an
+ * index >= nsrc gives -1 and sets TQP_DEVERR_KEY_RANGE.  No workspace. */
+tqp_status tqp_gather(tqp_ctx* ctx, const void* src, int64_t nsrc, int elem_bytes, const int32_t* idx, int64_t n,
+                      const int64_t* d_n, void* out, hipStream_t stream);
+
 /* ---------------------------------------------------------------- group-by
  * Section 5.4, Algorithm 2: sort the group keys, permute the value columns
  * by the sorted order, find the runs of equal keys and evaluate the

@@ -25,7 +25,8 @@ from . import _lib
 from ._lib import (DEVERR_CAPACITY, DEVERR_KEY_RANGE, DEVERR_SPIN, DEVERR_VALUE_RANGE, JOIN_INNER, JOIN_LEFT_ANTI,
                    JOIN_LEFT_OUTER, JOIN_LEFT_SEMI, TQP_EQ, TQP_GE, TQP_GT, TQP_LE, TQP_LT, TQP_NE, TQPError, check)
 
-__all__ = ["Context", "filter", "sort", "join", "hash_join", "join_band", "pack_keys", "groupby_agg", "hash_groupby", "topk", "FlagsFragmentRunner",
+__all__ = ["Context", "filter", "sort", "join", "hash_join", "join_band", "pack_keys", "gather", "join_chain", "groupby_agg",
+           "hash_groupby", "topk", "FlagsFragmentRunner",
            "CustFragmentRunner", "BatchRunner", "Server", "TQPError", "TQP_LT", "TQP_LE", "TQP_GT", "TQP_GE", "TQP_EQ", "TQP_NE",
            "DEVERR_KEY_RANGE", "DEVERR_SPIN", "DEVERR_CAPACITY", "DEVERR_VALUE_RANGE", "JOIN_INNER", "JOIN_LEFT_SEMI",
            "JOIN_LEFT_ANTI", "JOIN_LEFT_OUTER"]
@@ -154,6 +155,54 @@ def join(ctx: Context, lkey, rkey, lrow=None, rrow=None, cap: int | None = None,
                                                   nr, _p(d_nr), _p(ol), _p(orr), cap, _p(cnt), ws, sz, s),
              "tqp_join_kind", dev)
     return ol, orr, cnt
+
+
+def gather(ctx: Context, src, idx, d_n=None, stream=None):
+    """out[i] = src[idx[i]] for an int32 or int64 device column; a negative index gives -1."""
+    n = idx.numel()
+    out = torch.empty(max(1, n), dtype=src.dtype, device=_dev(ctx))
+    check(ctx.lib.tqp_gather(ctx.h, _p(src), src.numel(), src.element_size(), _p(idx), n, _p(d_n), _p(out),
+                             _stream(stream)), "tqp_gather")
+    return out[:n]
+
+
+def join_chain(ctx: Context, keys_out, keys_pk, pk_sorted=None, key_bits: int = 0, caps=None, stream=None):
+    """A chain of sort-based equi-joins (a multi-join plan): table 0's column keys_out[0] joins table
+    1's keys_pk[0], table 1's keys_out[1] joins table 2's keys_pk[1], and so on.  Returns one int32
+    device tensor of row positions per table (the result tuples) and their count.
+
+    Each hop sorts the current left keys with their positions, sorts the right key column unless
+    pk_sorted[t] says it is already in order (the plan rule of skipping a sort over sorted data),
+    joins, and gathers the earlier position columns and the next hop's key through the join output.
+    caps[t] bounds hop t's result; a hop whose result is larger runs again at its exact size (the
+    join reports its true count).  Reads and clears the device error word; any error raises."""
+    hops = len(keys_pk)
+    if len(keys_out) != hops or hops < 1:
+        raise ValueError("join_chain: one outgoing key column per hop, at least one hop")
+    pk_sorted = pk_sorted or [False] * hops
+    cols = []
+    cur = keys_out[0]
+    for t in range(hops):
+        ls, lp = sort(ctx, cur, key_bits=key_bits, perm=True, stream=stream)
+        if pk_sorted[t]:
+            rs, rp = keys_pk[t], None
+        else:
+            rs, rp = sort(ctx, keys_pk[t], key_bits=key_bits, perm=True, stream=stream)
+        cap = caps[t] if caps else max(1, ls.numel())
+        li, rr, cnt = join(ctx, ls, rs, lp, rp, cap=cap, stream=stream)
+        J = int(cnt.item())
+        if J > cap:
+            ctx.errors()                                   # the capacity bit of the undersized run
+            li, rr, cnt = join(ctx, ls, rs, lp, rp, cap=J, stream=stream)
+        li, rr = li[:J], rr[:J]
+        cols = [gather(ctx, c, li, stream=stream) for c in cols] if cols else [li]
+        cols.append(rr)
+        if t + 1 < hops:
+            cur = gather(ctx, keys_out[t + 1], rr, stream=stream)
+    err = ctx.errors(stream=stream)
+    if err:
+        raise TQPError("join_chain: device error flags 0x%x" % err)
+    return cols, J
 
 
 def hash_join(ctx: Context, lkey, rkey, lrow=None, rrow=None, cap: int | None = None, d_nl=None, d_nr=None,

@@ -127,6 +127,8 @@ def load() -> ctypes.CDLL:
     lib.tqp_hash_groupby.argtypes = [c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp,
                                      c_i64, c_vp, c_vp, c_vp, c_vp]
     lib.tqp_hash_groupby.restype = S
+    lib.tqp_gather.argtypes = [c_vp, c_vp, c_i64, c_int, c_vp, c_i64, c_vp, c_vp, c_vp]
+    lib.tqp_gather.restype = S
     lib.tqp_groupby_agg.argtypes = [c_vp, c_vp, c_i64, c_vp, c_int, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i64,
                                     c_vp, c_vp, c_size_p, c_vp]
     lib.tqp_groupby_agg.restype = S

@@ -234,6 +234,59 @@ def test_pack_keys_range_flag(hip, ctx):
     assert ctx.errors() & hip.DEVERR_KEY_RANGE
 
 
+@pytest.mark.parametrize("n,nsrc", [(0, 5), (1, 1), (4097, 100), (300_007, 2_000_000)])
+def test_gather(hip, ctx, n, nsrc):
+    rng = _rng(n + nsrc)
+    idx = rng.integers(-1, nsrc, n).astype(np.int32)
+    for dt in (np.int32, np.int64):
+        src = rng.integers(-(1 << 30), 1 << 30, nsrc).astype(dt)
+        out = _np(hip.gather(ctx, _dev(src), _dev(idx)))
+        want = np.where(idx >= 0, src[np.maximum(idx, 0)], -1).astype(dt)
+        assert out.dtype == dt and np.array_equal(out, want)
+    assert ctx.errors() == 0
+    if n:
+        dn = _dev(np.array([n // 2], np.int64))
+        src = rng.integers(0, 9, nsrc).astype(np.int32)
+        out = _np(hip.gather(ctx, _dev(src), _dev(idx), d_n=dn))
+        assert np.array_equal(out[:n // 2], np.where(idx >= 0, src[np.maximum(idx, 0)], -1)[:n // 2])
+
+
+def test_gather_out_of_range(hip, ctx):
+    src = np.arange(10, dtype=np.int32)
+    out = _np(hip.gather(ctx, _dev(src), _dev(np.array([3, 10, 9], np.int32))))
+    assert out.tolist() == [3, -1, 9]
+    assert ctx.errors() == hip.DEVERR_KEY_RANGE
+
+
+def _lex(rows):
+    return rows[np.lexsort(rows.T[::-1])] if len(rows) else rows
+
+
+@pytest.mark.parametrize("sizes,doms,pk_sorted", [
+    ([1000, 300], [50], [False]),
+    ([20_000, 5000, 800], [3000, 500], [False, False]),
+    ([50_000, 20_000, 3000, 40], [20_000, 3000, 40], [True, False, True]),
+    ([0, 100, 10], [10, 5], [False, False]),
+    ([300_007, 100_000, 25], [100_000, 25], [True, True]),
+])
+def test_join_chain(hip, ctx, sizes, doms, pk_sorted):
+    """Chains of one to three sort-based joins (sorted inputs where pk_sorted says so, so that
+    hop skips its sort) against the oracle's nested chain, compared as sets of row tuples."""
+    rng = _rng(sum(sizes) + len(doms))
+    hops = len(doms)
+    outs = [rng.integers(0, doms[t], sizes[t]).astype(np.int32) for t in range(hops)]
+    pks = []
+    for t in range(hops):
+        k = rng.integers(0, doms[t], sizes[t + 1]).astype(np.int32)
+        pks.append(np.sort(k) if pk_sorted[t] else k)
+    want = oracle.join_chain(outs, pks)
+    cols, J = hip.join_chain(ctx, [_dev(o) for o in outs], [_dev(p) for p in pks], pk_sorted=pk_sorted,
+                             caps=[max(1, sizes[0] // 3)] * hops)        # small caps: hops rerun at their size
+    assert J == len(want)
+    got = np.stack([_np(c, J) for c in cols], axis=1) if J else np.zeros((0, hops + 1), np.int32)
+    assert np.array_equal(_lex(got), _lex(want))
+
+
 _KINDS = {"semi": 1, "anti": 2, "outer": 3, "inner": 0}
 
 
