@@ -150,11 +150,11 @@ def main():
                          "and a row outside the declared width sets a device error flag)")
     ap.add_argument("--date-lt", type=int, default=None,
                     help="config 2 with another filter constant D (date < D; the workload uses 2400)")
-    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 4, 5, 6, 7],
+    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 4, 5, 6, 7, 8],
                     help="2: the 60M-row custkey fragment (default); 3: 256 flags fragments, batched vs plain; "
                          "4: served mix under Poisson arrivals, concurrent vs serial; 5: the join kinds on the "
                          "config-2 join inputs; 6: hash join vs sort join from unsorted inputs, 1 to 64 rows per key; "
-                         "7: hash vs sort group-by over 60M rows, 6 to 15M groups")
+                         "7: hash vs sort group-by over 60M rows, 6 to 15M groups; 8: a chain of three joins")
     ap.add_argument("--rates", default="50,100,200,400,800", help="arrival rates (fragments/s) for --config 4")
     ap.add_argument("--requests", type=int, default=400, help="requests per rate for --config 4")
     ap.add_argument("--slots", type=int, default=8)
@@ -184,6 +184,8 @@ def main():
         return bench_hash_vs_sort(args)
     if args.config == 7:
         return bench_groupby(args)
+    if args.config == 8:
+        return bench_chain(args)
     if args.config == 4:
         return bench_serve(args)
 
@@ -543,6 +545,59 @@ def bench_groupby(args):
                       "warmup": args.warmup, "higher_is_better": False, "data": "synthetic", "dtype": "int64",
                       "config": {"workload": "%d rows, G uniform int32 keys, int64 values" % n},
                       "sweep": sweep}), flush=True)
+
+
+def bench_chain(args):
+    """A chain of three sort-based joins in the shape of the paper's multi-join plans: fact (60M rows,
+    key into mid) -> mid (15M rows, primary key in order, key into cust) -> cust (1.5M rows, primary
+    key shuffled, key into nation) -> nation (25 rows, in order).  Every fact row matches one row per
+    hop, so 60M tuples of 4 row positions come out.  Timed with the rule that skips the sort of a
+    key column already in order (mid and nation) and without it; kernel times from the library's
+    events, wall time includes the one host read of each hop's size.  The result count is checked."""
+    import numpy as np
+    import torch
+
+    import paper_2203_01877_amd as tqp
+
+    n = args.rows or 60_000_000
+    m, c, q = max(1, n // 4), max(1, n // 40), 25
+    dev = torch.device("cuda", 0)
+    ctx = tqp.Context(0)
+    rng = np.random.default_rng(29)
+    cols = {"fact_fk": rng.integers(0, m, n), "mid_pk": np.arange(m), "mid_fk": rng.integers(0, c, m),
+            "cust_pk": rng.permutation(c), "cust_fk": rng.integers(0, q, c), "nation_pk": np.arange(q)}
+    d = {k: torch.from_numpy(v.astype(np.int32)).to(dev) for k, v in cols.items()}
+    outs = [d["fact_fk"], d["mid_fk"], d["cust_fk"]]
+    pks = [d["mid_pk"], d["cust_pk"], d["nation_pk"]]
+    kb = [int(x - 1).bit_length() for x in (m, c, q)]      # key widths of the three hops
+    res = {"key_bits": kb}
+    for name, rule in (("skip_sorted", [True, False, True]), ("sort_all", [False, False, False])):
+        caps = [n, n, n]
+        for _ in range(args.warmup):
+            tqp.join_chain(ctx, outs, pks, pk_sorted=rule, key_bits=kb, caps=caps)
+        torch.cuda.synchronize()
+        ctx.profile_read()
+        ctx.set_profiling(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, J = tqp.join_chain(ctx, outs, pks, pk_sorted=rule, key_bits=kb, caps=caps)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3 / args.steps
+        recs = ctx.profile_read()
+        ctx.set_profiling(False)
+        if J != n:
+            log("join chain (%s): %d tuples, expected %d" % (name, J, n))
+            sys.exit(3)
+        per = {}
+        for k, t in recs:
+            per[k] = per.get(k, 0.0) + t / args.steps
+        res[name] = {"kernel_ms": round(sum(per.values()), 4), "wall_ms": round(wall, 4),
+                     "kernels_ms": {k: round(v, 4) for k, v in sorted(per.items())}}
+        log("%s: %s" % (name, res[name]))
+    print(json.dumps({"metric": "join chain ms, 3 joins", "unit": "ms", "n_gpus": 1, "steps": args.steps,
+                      "warmup": args.warmup, "higher_is_better": False, "data": "synthetic", "dtype": "int32",
+                      "config": {"workload": "%d fact -> %d mid -> %d cust -> %d nation rows, %d result tuples"
+                                 % (n, m, c, q, n)}, "result": res}), flush=True)
 
 
 def bench_batch(args):

@@ -9,7 +9,13 @@ Operators (the paper's Section 5 and Algorithms 1-2):
     filter        predicate -> selection vector of row ids   (Section 3.1)
     sort          stable LSD radix sort of (key, payload)     (Algorithms 1-2)
     join          sort-based equi-join -> index pairs          (Section 5.2, Algorithm 1)
+    join_kind     left semi / anti / outer joins; join_band: |l - r| <= w
+    hash_join     open-addressing hash join                    (Section 5.3, Algorithm 3)
+    pack_keys     composite keys packed into one key
+    gather        columns read through row positions           (late materialisation)
+    join_chain    a chain of joins (a multi-join plan)
     groupby_agg   sort-based group-by with sum/count/avg       (Section 5.4, Algorithm 2)
+    hash_groupby  hash-based group-by: sum/count/min/max/count distinct
     topk          ORDER BY sum DESC, key ASC LIMIT k
 Fragments (whole queries in one launch sequence):
     FlagsFragmentRunner   date < D AND seg = c, fact.fk = dim.pk, group by (flagA, flagB)
@@ -166,7 +172,7 @@ def gather(ctx: Context, src, idx, d_n=None, stream=None):
     return out[:n]
 
 
-def join_chain(ctx: Context, keys_out, keys_pk, pk_sorted=None, key_bits: int = 0, caps=None, stream=None):
+def join_chain(ctx: Context, keys_out, keys_pk, pk_sorted=None, key_bits=0, caps=None, stream=None):
     """A chain of sort-based equi-joins (a multi-join plan): table 0's column keys_out[0] joins table
     1's keys_pk[0], table 1's keys_out[1] joins table 2's keys_pk[1], and so on.  Returns one int32
     device tensor of row positions per table (the result tuples) and their count.
@@ -174,20 +180,21 @@ def join_chain(ctx: Context, keys_out, keys_pk, pk_sorted=None, key_bits: int = 
     Each hop sorts the current left keys with their positions, sorts the right key column unless
     pk_sorted[t] says it is already in order (the plan rule of skipping a sort over sorted data),
     joins, and gathers the earlier position columns and the next hop's key through the join output.
-    caps[t] bounds hop t's result; a hop whose result is larger runs again at its exact size (the
+    key_bits: the key width of every hop, or one per hop (fewer radix passes).  caps[t] bounds hop t's result; a hop whose result is larger runs again at its exact size (the
     join reports its true count).  Reads and clears the device error word; any error raises."""
     hops = len(keys_pk)
     if len(keys_out) != hops or hops < 1:
         raise ValueError("join_chain: one outgoing key column per hop, at least one hop")
     pk_sorted = pk_sorted or [False] * hops
+    kbits = list(key_bits) if isinstance(key_bits, (list, tuple)) else [key_bits] * hops
     cols = []
     cur = keys_out[0]
     for t in range(hops):
-        ls, lp = sort(ctx, cur, key_bits=key_bits, perm=True, stream=stream)
+        ls, lp = sort(ctx, cur, key_bits=kbits[t], perm=True, stream=stream)
         if pk_sorted[t]:
             rs, rp = keys_pk[t], None
         else:
-            rs, rp = sort(ctx, keys_pk[t], key_bits=key_bits, perm=True, stream=stream)
+            rs, rp = sort(ctx, keys_pk[t], key_bits=kbits[t], perm=True, stream=stream)
         cap = caps[t] if caps else max(1, ls.numel())
         li, rr, cnt = join(ctx, ls, rs, lp, rp, cap=cap, stream=stream)
         J = int(cnt.item())

@@ -280,8 +280,9 @@ def test_join_chain(hip, ctx, sizes, doms, pk_sorted):
         k = rng.integers(0, doms[t], sizes[t + 1]).astype(np.int32)
         pks.append(np.sort(k) if pk_sorted[t] else k)
     want = oracle.join_chain(outs, pks)
+    kb = [int(d - 1).bit_length() or 1 for d in doms] if hops > 1 else 0      # per hop, or the full width
     cols, J = hip.join_chain(ctx, [_dev(o) for o in outs], [_dev(p) for p in pks], pk_sorted=pk_sorted,
-                             caps=[max(1, sizes[0] // 3)] * hops)        # small caps: hops rerun at their size
+                             key_bits=kb, caps=[max(1, sizes[0] // 3)] * hops)  # small caps: hops rerun at their size
     assert J == len(want)
     got = np.stack([_np(c, J) for c in cols], axis=1) if J else np.zeros((0, hops + 1), np.int32)
     assert np.array_equal(_lex(got), _lex(want))
