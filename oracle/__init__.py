@@ -62,6 +62,8 @@ def _L():
         lib.orc_group_minmax.restype = i64
         lib.orc_join_chain.argtypes = [ctypes.c_int, vp, vp, vp, vp, i64]
         lib.orc_join_chain.restype = i64
+        lib.orc_eval.argtypes = [vp, ctypes.c_int, i64, vp, vp, ctypes.c_int, vp]
+        lib.orc_eval.restype = i64
         lib.orc_fragment_flags.argtypes = [vp, vp, vp, vp, vp, vp, i64, vp, vp, i64, i32, i32,
                                            vp, vp, vp, vp, i64, vp]
         lib.orc_fragment_flags.restype = i64
@@ -199,6 +201,27 @@ def group_minmax(gkey, val):
     G = _L().orc_group_minmax(gkey.ctypes.data, n, val.ctypes.data, k.ctypes.data, lo.ctypes.data,
                               hi.ctypes.data, nd.ctypes.data, cap)
     return k[:G].copy(), lo[:G].copy(), hi[:G].copy(), nd[:G].copy()
+
+
+# expression operator codes (postfix programs of (op, arg) pairs)
+X_COL, X_CONST, X_ADD, X_SUB, X_MUL, X_DIV, X_MOD, X_NEG = range(8)
+X_LT, X_LE, X_GT, X_GE, X_EQ, X_NE, X_AND, X_OR, X_NOT, X_SELECT = range(8, 18)
+
+
+def eval_expr(cols, prog):
+    """Values of a postfix expression program [(op, arg)] over int columns (as int64), and the number
+    of zero divisors met; raises ValueError for a malformed program."""
+    cs = [_c(np.asarray(c).astype(np.int64), np.int64) for c in cols]
+    n = len(cs[0]) if cs else 0
+    ptr = (ctypes.c_void_p * max(1, len(cs)))(*[c.ctypes.data for c in cs])
+    ops = np.array([p[0] for p in prog], np.int32)
+    args = np.array([p[1] for p in prog], np.int64)
+    out = np.empty(max(1, n), np.int64)
+    z = _L().orc_eval(ctypes.cast(ptr, ctypes.c_void_p), len(cs), n, ops.ctypes.data, args.ctypes.data, len(prog),
+                      out.ctypes.data)
+    if z < 0:
+        raise ValueError("malformed expression program")
+    return out[:n].copy(), int(z)
 
 
 def join_chain(keys_out, keys_pk):

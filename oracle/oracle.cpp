@@ -151,6 +151,91 @@ int64_t orc_join(const int32_t* lkey, const int32_t* lrow, int64_t nl, const int
     return w;
 }
 
+// Expressions (Section 5.1: arithmetic, comparisons and logic over columns,
+// CASE as a select).  The program is postfix; here it is first turned into a
+// tree (each operator node takes the subtrees left on the stack) and every row
+// is evaluated by recursion over the tree.  Values are int64 with wrap-around
+// (two's complement) for +, - and *, and for unary minus; / and % truncate
+// toward zero as in C, a zero divisor gives 0 (and is counted), INT64_MIN / -1
+// gives INT64_MIN and INT64_MIN % -1 gives 0; comparisons, AND, OR and NOT give
+// 0 or 1 (nonzero is true); SELECT(c, t, f) = c ? t : f.  Operator codes:
+// 0 column, 1 constant, 2 +, 3 -, 4 *, 5 /, 6 %, 7 unary -, 8 <, 9 <=, 10 >,
+// 11 >=, 12 ==, 13 !=, 14 AND, 15 OR, 16 NOT, 17 SELECT.  Returns the number of
+// zero divisors met, or -1 for a malformed program.
+namespace {
+struct XNode {
+    int op;
+    int64_t arg;
+    int kid[3];
+};
+int x_arity(int op) {
+    if (op == 0 || op == 1) return 0;
+    if (op == 7 || op == 16) return 1;
+    if (op == 17) return 3;
+    return (op >= 2 && op <= 15) ? 2 : -1;
+}
+int64_t x_eval(const std::vector<XNode>& t, int at, const int64_t* const* cols, int64_t row, int64_t& zdiv) {
+    const XNode& nd = t[static_cast<size_t>(at)];
+    auto kid = [&](int i) { return x_eval(t, nd.kid[i], cols, row, zdiv); };
+    auto wrap = [](uint64_t v) { return static_cast<int64_t>(v); };
+    switch (nd.op) {
+        case 0: return cols[nd.arg][row];
+        case 1: return nd.arg;
+        case 7: return wrap(0u - static_cast<uint64_t>(kid(0)));
+        case 16: return kid(0) == 0 ? 1 : 0;
+        case 17: {
+            const int64_t c = kid(0), a = kid(1), b = kid(2);
+            return c != 0 ? a : b;
+        }
+        default: break;
+    }
+    const int64_t a = kid(0), b = kid(1);
+    switch (nd.op) {
+        case 2: return wrap(static_cast<uint64_t>(a) + static_cast<uint64_t>(b));
+        case 3: return wrap(static_cast<uint64_t>(a) - static_cast<uint64_t>(b));
+        case 4: return wrap(static_cast<uint64_t>(a) * static_cast<uint64_t>(b));
+        case 5:
+            if (b == 0) { ++zdiv; return 0; }
+            if (a == INT64_MIN && b == -1) return INT64_MIN;
+            return a / b;
+        case 6:
+            if (b == 0) { ++zdiv; return 0; }
+            if (b == -1) return 0;
+            return a % b;
+        case 8: return a < b;
+        case 9: return a <= b;
+        case 10: return a > b;
+        case 11: return a >= b;
+        case 12: return a == b;
+        case 13: return a != b;
+        case 14: return (a != 0) && (b != 0);
+        default: return (a != 0) || (b != 0);
+    }
+}
+}  // namespace
+
+int64_t orc_eval(const int64_t* const* cols, int ncols, int64_t n, const int32_t* ops,
+                 const int64_t* args, int nprog, int64_t* out) {
+    std::vector<XNode> tree;
+    std::vector<int> stack;
+    for (int pc = 0; pc < nprog; ++pc) {
+        const int ar = x_arity(ops[pc]);
+        if (ar < 0 || static_cast<int>(stack.size()) < ar) return -1;
+        if (ops[pc] == 0 && (args[pc] < 0 || args[pc] >= ncols)) return -1;
+        XNode nd{ops[pc], args[pc], {-1, -1, -1}};
+        for (int i = ar - 1; i >= 0; --i) {
+            nd.kid[i] = stack.back();
+            stack.pop_back();
+        }
+        tree.push_back(nd);
+        stack.push_back(static_cast<int>(tree.size()) - 1);
+    }
+    if (stack.size() != 1) return -1;
+    int64_t zdiv = 0;
+    for (int64_t r = 0; r < n; ++r) out[r] = x_eval(tree, stack[0], cols, r, zdiv);
+    return zdiv;
+}
+
 // A chain of equi-joins, the shape of the multi-join plans of Section 6
 // (hand-optimized plans, the six-join query): tables 0..hops; table t < hops
 // has the key column outk[t] into table t + 1, whose matched column is pk[t + 1]

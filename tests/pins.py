@@ -214,6 +214,75 @@ def check_pack_keys():
 
 # --------------------------------------------------------------------------- group-by
 
+def _random_expr(rng, ncols, depth):
+    """A random expression tree as a postfix program, and the same tree as a numpy evaluator."""
+    O = oracle
+    if depth == 0 or rng.random() < 0.25:
+        if rng.random() < 0.6:
+            c = int(rng.integers(0, ncols))
+            return [(O.X_COL, c)], lambda cols, c=c: cols[c].astype(np.int64)
+        k = int(rng.integers(-50, 50))
+        return [(O.X_CONST, k)], lambda cols, k=k: np.full(len(cols[0]), k, np.int64)
+    op = int(rng.choice([O.X_ADD, O.X_SUB, O.X_MUL, O.X_NEG, O.X_LT, O.X_LE, O.X_GT, O.X_GE, O.X_EQ, O.X_NE,
+                         O.X_AND, O.X_OR, O.X_NOT, O.X_SELECT]))
+    ar = 1 if op in (O.X_NEG, O.X_NOT) else 3 if op == O.X_SELECT else 2
+    kids = [_random_expr(rng, ncols, depth - 1) for _ in range(ar)]
+    prog = [i for k in kids for i in k[0]] + [(op, 0)]
+    f = [k[1] for k in kids]
+    with np.errstate(over="ignore"):
+        ev = {O.X_ADD: lambda c: f[0](c) + f[1](c), O.X_SUB: lambda c: f[0](c) - f[1](c),
+              O.X_MUL: lambda c: f[0](c) * f[1](c), O.X_NEG: lambda c: -f[0](c),
+              O.X_LT: lambda c: (f[0](c) < f[1](c)).astype(np.int64),
+              O.X_LE: lambda c: (f[0](c) <= f[1](c)).astype(np.int64),
+              O.X_GT: lambda c: (f[0](c) > f[1](c)).astype(np.int64),
+              O.X_GE: lambda c: (f[0](c) >= f[1](c)).astype(np.int64),
+              O.X_EQ: lambda c: (f[0](c) == f[1](c)).astype(np.int64),
+              O.X_NE: lambda c: (f[0](c) != f[1](c)).astype(np.int64),
+              O.X_AND: lambda c: np.logical_and(f[0](c), f[1](c)).astype(np.int64),
+              O.X_OR: lambda c: np.logical_or(f[0](c), f[1](c)).astype(np.int64),
+              O.X_NOT: lambda c: np.logical_not(f[0](c)).astype(np.int64),
+              O.X_SELECT: lambda c: np.where(f[0](c) != 0, f[1](c), f[2](c))}[op]
+    return prog, ev
+
+
+def check_eval():
+    O = oracle
+    rng = _rng(16)
+    for trial in range(40):
+        n = int(rng.integers(1, 300))
+        cols = [rng.integers(-10**6, 10**6, n).astype(np.int64), rng.integers(-3, 4, n).astype(np.int32),
+                rng.integers(0, 2, n).astype(np.int8), rng.integers(-2**62, 2**62, n).astype(np.int64)]
+        prog, ev = _random_expr(rng, len(cols), int(rng.integers(1, 5)))
+        got, z = O.eval_expr(cols, prog)
+        with np.errstate(over="ignore"):
+            want = ev(cols)              # numpy's int64 arithmetic wraps the same way
+        assert z == 0 and np.array_equal(got, want), ("expression", trial, prog)
+    # division and remainder truncate toward zero (C), against hand-computed values
+    a = np.array([7, -7, 7, -7, 0, 5, np.iinfo(np.int64).min, np.iinfo(np.int64).min], np.int64)
+    b = np.array([2, 2, -2, -2, 3, 0, -1, 1], np.int64)
+    q, z = O.eval_expr([a, b], [(O.X_COL, 0), (O.X_COL, 1), (O.X_DIV, 0)])
+    assert q.tolist() == [3, -3, -3, 3, 0, 0, np.iinfo(np.int64).min, np.iinfo(np.int64).min] and z == 1
+    r, z = O.eval_expr([a, b], [(O.X_COL, 0), (O.X_COL, 1), (O.X_MOD, 0)])
+    assert r.tolist() == [1, -1, 1, -1, 0, 0, 0, 0] and z == 1
+    nz = b != 0
+    assert np.array_equal((q * b + r)[nz], a[nz])           # a = q * b + r wherever b != 0
+    # identities: SELECT(c, x, x) = x, NOT NOT x = (x != 0), x - y = x + (-y)
+    x = rng.integers(-5, 5, 100).astype(np.int64)
+    y = rng.integers(-5, 5, 100).astype(np.int64)
+    s1, _ = O.eval_expr([x, y], [(O.X_COL, 1), (O.X_COL, 0), (O.X_COL, 0), (O.X_SELECT, 0)])
+    s2, _ = O.eval_expr([x, y], [(O.X_COL, 0), (O.X_NOT, 0), (O.X_NOT, 0)])
+    s3, _ = O.eval_expr([x, y], [(O.X_COL, 0), (O.X_COL, 1), (O.X_SUB, 0)])
+    s4, _ = O.eval_expr([x, y], [(O.X_COL, 0), (O.X_COL, 1), (O.X_NEG, 0), (O.X_ADD, 0)])
+    assert np.array_equal(s1, x) and np.array_equal(s2, (x != 0).astype(np.int64)) and np.array_equal(s3, s4)
+    # malformed programs are refused
+    for bad in ([(O.X_ADD, 0)], [(O.X_CONST, 1), (O.X_CONST, 2)], [(O.X_COL, 5)], [(99, 0)], []):
+        try:
+            O.eval_expr([x], bad)
+        except ValueError:
+            continue
+        raise AssertionError(("malformed program accepted", bad))
+
+
 def check_join_chain():
     rng = _rng(15)
     for trial in range(8):
@@ -411,5 +480,5 @@ def check_topk_ties():
 
 
 ALL_CHECKS = [check_filter, check_sort, check_join, check_join_kinds, check_join_band, check_pack_keys,
-              check_join_chain, check_groupby, check_group_minmax, check_fragment_flags,
+              check_join_chain, check_eval, check_groupby, check_group_minmax, check_fragment_flags,
               check_fragment_flags_invariants, check_fragment_cust, check_topk_ties]

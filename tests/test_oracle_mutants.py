@@ -39,6 +39,9 @@ MUTANTS = [
      "std::map<int32_t, std::multiset<int64_t>> groups;"),
     ("chain_first_match_only", "for (int32_t next : it->second) self(self, t + 1, next);",
      "self(self, t + 1, it->second.front());"),
+    ("expr_sub_swapped", "case 3: return wrap(static_cast<uint64_t>(a) - static_cast<uint64_t>(b));",
+     "case 3: return wrap(static_cast<uint64_t>(b) - static_cast<uint64_t>(a));"),
+    ("expr_div_floor", "            return a / b;", "            return a / b - ((a % b != 0) && ((a < 0) != (b < 0)));"),
     ("cust_uses_fact_key", "Agg& a = groups[custkey[it->second]];", "Agg& a = groups[fk[f]];"),
     ("mid_first_match_only", "for (auto it = range.first; it != range.second; ++it) {\n            Agg& a = groups[custkey",
      "for (auto it = range.first; it != range.second; it = range.second) {\n            Agg& a = groups[custkey"),
