@@ -213,6 +213,31 @@ tqp_status tqp_join_kind(tqp_ctx* ctx, int kind, const int32_t* lkey, const int3
 tqp_status tqp_pack_keys(tqp_ctx* ctx, const int32_t* const* cols, const int32_t* bits, int ncols, int64_t n,
                          const int64_t* d_n, int32_t* out, hipStream_t stream);
 
+/* Expression programs (Section 5.1: arithmetic, comparisons, logic and CASE
+ * over columns), as a postfix program of at most 64 instructions over int64
+ * values, with at most 16 values on the stack and at most 8 columns (int8,
+ * int32 or int64, widened).  Binary operators pop b, then a, and push a op b;
+ * SELECT pops f, t, c and pushes c ? t : f.  +, -, * and unary minus wrap
+ * (two's complement); / and % truncate toward zero; a zero divisor gives 0
+ * and sets TQP_DEVERR_VALUE_RANGE; INT64_MIN / -1 = INT64_MIN, INT64_MIN %
+ * -1 = 0; comparisons, AND, OR and NOT give 0 or 1 (nonzero is true).  out[i]
+ * = the program's value on row i, for n or *d_n rows.  A malformed program
+ * (unknown operator, missing operands, a column out of range, not exactly
+ * one value left) is refused with TQP_ERR_INVALID before any launch.  No
+ * workspace. */
+typedef enum {
+    TQP_X_COL = 0, TQP_X_CONST = 1, TQP_X_ADD = 2, TQP_X_SUB = 3, TQP_X_MUL = 4, TQP_X_DIV = 5,
+    TQP_X_MOD = 6, TQP_X_NEG = 7, TQP_X_LT = 8, TQP_X_LE = 9, TQP_X_GT = 10, TQP_X_GE = 11,
+    TQP_X_EQ = 12, TQP_X_NE = 13, TQP_X_AND = 14, TQP_X_OR = 15, TQP_X_NOT = 16, TQP_X_SELECT = 17
+} tqp_xop;
+typedef struct {
+    int32_t op;               /* tqp_xop */
+    int32_t reserved;
+    int64_t arg;              /* column index (TQP_X_COL) or constant (TQP_X_CONST) */
+} tqp_xinstr;
+tqp_status tqp_eval(tqp_ctx* ctx, const tqp_column* cols, int ncols, int64_t n, const int64_t* d_n,
+                    const tqp_xinstr* prog, int nprog, int64_t* out, hipStream_t stream);
+
 /* Gather by row position, the late materialisation of Section 5.2 (joins
  * return row positions; the columns a later operator needs, such as the next
  * join's key in a chain of joins, are read through them): out[i] =

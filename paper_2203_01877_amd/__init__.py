@@ -9,9 +9,10 @@ Operators (the paper's Section 5 and Algorithms 1-2):
     filter        predicate -> selection vector of row ids   (Section 3.1)
     sort          stable LSD radix sort of (key, payload)     (Algorithms 1-2)
     join          sort-based equi-join -> index pairs          (Section 5.2, Algorithm 1)
-    join_kind     left semi / anti / outer joins; join_band: |l - r| <= w
+    join(kind=)   left semi / anti / outer joins; join_band: |l - r| <= w
     hash_join     open-addressing hash join                    (Section 5.3, Algorithm 3)
     pack_keys     composite keys packed into one key
+    eval_expr     postfix expression programs, one kernel      (Section 5.1)
     gather        columns read through row positions           (late materialisation)
     join_chain    a chain of joins (a multi-join plan)
     groupby_agg   sort-based group-by with sum/count/avg       (Section 5.4, Algorithm 2)
@@ -31,7 +32,7 @@ from . import _lib
 from ._lib import (DEVERR_CAPACITY, DEVERR_KEY_RANGE, DEVERR_SPIN, DEVERR_VALUE_RANGE, JOIN_INNER, JOIN_LEFT_ANTI,
                    JOIN_LEFT_OUTER, JOIN_LEFT_SEMI, TQP_EQ, TQP_GE, TQP_GT, TQP_LE, TQP_LT, TQP_NE, TQPError, check)
 
-__all__ = ["Context", "filter", "sort", "join", "hash_join", "join_band", "pack_keys", "gather", "join_chain", "groupby_agg",
+__all__ = ["Context", "filter", "sort", "join", "hash_join", "join_band", "pack_keys", "eval_expr", "gather", "join_chain", "groupby_agg",
            "hash_groupby", "topk", "FlagsFragmentRunner",
            "CustFragmentRunner", "BatchRunner", "Server", "TQPError", "TQP_LT", "TQP_LE", "TQP_GT", "TQP_GE", "TQP_EQ", "TQP_NE",
            "DEVERR_KEY_RANGE", "DEVERR_SPIN", "DEVERR_CAPACITY", "DEVERR_VALUE_RANGE", "JOIN_INNER", "JOIN_LEFT_SEMI",
@@ -161,6 +162,17 @@ def join(ctx: Context, lkey, rkey, lrow=None, rrow=None, cap: int | None = None,
                                                   nr, _p(d_nr), _p(ol), _p(orr), cap, _p(cnt), ws, sz, s),
              "tqp_join_kind", dev)
     return ol, orr, cnt
+
+
+def eval_expr(ctx: Context, cols: list, prog: list, d_n=None, stream=None):
+    """int64 values of a postfix expression program [(op, arg)] (TQP_X_* codes) over device columns."""
+    n = cols[0].numel() if cols else 0
+    carr = (_lib.Column * max(1, len(cols)))(*[_lib.Column(c.data_ptr(), _DTYPES[c.dtype], 0) for c in cols])
+    parr = (_lib.XInstr * max(1, len(prog)))(*[_lib.XInstr(int(o), 0, int(a)) for o, a in prog])
+    out = torch.empty(max(1, n), dtype=torch.int64, device=_dev(ctx))
+    check(ctx.lib.tqp_eval(ctx.h, carr, len(cols), n, _p(d_n), parr, len(prog), _p(out), _stream(stream)),
+          "tqp_eval")
+    return out[:n]
 
 
 def gather(ctx: Context, src, idx, d_n=None, stream=None):

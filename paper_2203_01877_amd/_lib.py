@@ -31,6 +31,10 @@ class Pred(ctypes.Structure):
     _fields_ = [("col", c_i32), ("op", c_i32), ("k", c_i64)]
 
 
+class XInstr(ctypes.Structure):
+    _fields_ = [("op", c_i32), ("reserved", c_i32), ("arg", c_i64)]
+
+
 class FlagsFragment(ctypes.Structure):
     _fields_ = [("fk", c_vp), ("date", c_vp), ("price", c_vp), ("disc", c_vp), ("flagA", c_vp),
                 ("flagB", c_vp), ("row0", c_i64), ("n_fact", c_i64), ("pk", c_vp), ("seg", c_vp),
@@ -129,6 +133,8 @@ def load() -> ctypes.CDLL:
     lib.tqp_hash_groupby.restype = S
     lib.tqp_gather.argtypes = [c_vp, c_vp, c_i64, c_int, c_vp, c_i64, c_vp, c_vp, c_vp]
     lib.tqp_gather.restype = S
+    lib.tqp_eval.argtypes = [c_vp, c_vp, c_int, c_i64, c_vp, c_vp, c_int, c_vp, c_vp]
+    lib.tqp_eval.restype = S
     lib.tqp_groupby_agg.argtypes = [c_vp, c_vp, c_i64, c_vp, c_int, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_i64,
                                     c_vp, c_vp, c_size_p, c_vp]
     lib.tqp_groupby_agg.restype = S

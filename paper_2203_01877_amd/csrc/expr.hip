@@ -1,0 +1,152 @@
+// Expression programs (Section 5.1: arithmetic, comparisons, logic and CASE
+// over columns).  The paper evaluates an expression one tensor operation at a
+// time, each writing its intermediate column to device memory.  Here the
+// expression comes as a postfix program (a small descriptor the host checks
+// once) and one kernel evaluates all of it per row, with the evaluation stack
+// of each thread in LDS: the intermediates never reach HBM, so the kernel
+// reads the referenced columns once and writes the result once.
+//
+// Values are int64; +, -, * and unary minus wrap (two's complement); / and %
+// truncate toward zero, a zero divisor gives 0 and sets
+// TQP_DEVERR_VALUE_RANGE, INT64_MIN / -1 = INT64_MIN and INT64_MIN % -1 = 0;
+// comparisons and logic give 0 or 1; SELECT(c, t, f) = c ? t : f.
+#include "dev.hpp"
+#include "host.hpp"
+
+namespace tqp {
+namespace {
+
+constexpr int XP_MAX = 64;       // instructions
+constexpr int XS_MAX = 16;       // stack depth
+constexpr int XC_MAX = 8;        // columns
+constexpr int XE_BLOCK = 256;
+
+enum : int32_t {
+    XO_COL = 0, XO_CONST, XO_ADD, XO_SUB, XO_MUL, XO_DIV, XO_MOD, XO_NEG,
+    XO_LT, XO_LE, XO_GT, XO_GE, XO_EQ, XO_NE, XO_AND, XO_OR, XO_NOT, XO_SELECT, XO_COUNT
+};
+
+struct XProg {
+    int32_t op[XP_MAX];
+    int64_t arg[XP_MAX];
+    const void* col[XC_MAX];
+    int32_t type[XC_MAX];
+    int32_t n;
+};
+
+__device__ __forceinline__ int64_t x_load(const XProg& p, int c, int64_t row) {
+    switch (p.type[c]) {
+        case TQP_I8: return static_cast<const int8_t*>(p.col[c])[row];
+        case TQP_I32: return static_cast<const int32_t*>(p.col[c])[row];
+        default: return static_cast<const int64_t*>(p.col[c])[row];
+    }
+}
+
+__global__ void __launch_bounds__(XE_BLOCK)
+k_eval(XProg p, int64_t n_upper, const int64_t* d_n, int64_t* out, uint32_t* flags) {
+    __shared__ int64_t st[XS_MAX][XE_BLOCK];
+    int64_t n = n_upper;
+    if (d_n) { const int64_t t = *d_n; n = t < n ? t : n; }
+    const int tid = threadIdx.x;
+    bool zdiv = false;
+    for (int64_t row = (int64_t)blockIdx.x * XE_BLOCK + tid; row < n; row += (int64_t)gridDim.x * XE_BLOCK) {
+        int sp = 0;                                   // the same at every step of every thread
+        for (int pc = 0; pc < p.n; ++pc) {
+            const int32_t op = p.op[pc];
+            if (op == XO_COL) { st[sp++][tid] = x_load(p, (int)p.arg[pc], row); continue; }
+            if (op == XO_CONST) { st[sp++][tid] = p.arg[pc]; continue; }
+            if (op == XO_NEG) { st[sp - 1][tid] = (int64_t)(0ull - (uint64_t)st[sp - 1][tid]); continue; }
+            if (op == XO_NOT) { st[sp - 1][tid] = st[sp - 1][tid] == 0; continue; }
+            if (op == XO_SELECT) {
+                const int64_t c = st[sp - 3][tid], t = st[sp - 2][tid], f = st[sp - 1][tid];
+                sp -= 2;
+                st[sp - 1][tid] = c != 0 ? t : f;
+                continue;
+            }
+            const int64_t a = st[sp - 2][tid], b = st[sp - 1][tid];
+            int64_t r;
+            switch (op) {
+                case XO_ADD: r = (int64_t)((uint64_t)a + (uint64_t)b); break;
+                case XO_SUB: r = (int64_t)((uint64_t)a - (uint64_t)b); break;
+                case XO_MUL: r = (int64_t)((uint64_t)a * (uint64_t)b); break;
+                case XO_DIV:
+                    if (b == 0) { zdiv = true; r = 0; }
+                    else if (b == -1) r = (int64_t)(0ull - (uint64_t)a);
+                    else r = a / b;
+                    break;
+                case XO_MOD:
+                    if (b == 0) { zdiv = true; r = 0; }
+                    else if (b == -1) r = 0;
+                    else r = a % b;
+                    break;
+                case XO_LT: r = a < b; break;
+                case XO_LE: r = a <= b; break;
+                case XO_GT: r = a > b; break;
+                case XO_GE: r = a >= b; break;
+                case XO_EQ: r = a == b; break;
+                case XO_NE: r = a != b; break;
+                case XO_AND: r = (a != 0) && (b != 0); break;
+                default: r = (a != 0) || (b != 0); break;
+            }
+            --sp;
+            st[sp - 1][tid] = r;
+        }
+        out[row] = st[0][tid];
+    }
+    if (__any(zdiv) && lane_id() == 0) set_flag(flags, FLAG_VALUE_RANGE);
+}
+
+int x_arity(int32_t op) {
+    if (op == XO_COL || op == XO_CONST) return 0;
+    if (op == XO_NEG || op == XO_NOT) return 1;
+    if (op == XO_SELECT) return 3;
+    return 2;
+}
+
+}  // namespace
+}  // namespace tqp
+
+using namespace tqp;
+
+extern "C" {
+
+tqp_status tqp_eval(tqp_ctx* ctx, const tqp_column* cols, int ncols, int64_t n, const int64_t* d_n,
+                    const tqp_xinstr* prog, int nprog, int64_t* out, hipStream_t stream) {
+    clear_error();
+    if (!ctx || n < 0 || ncols < 0 || (ncols > 0 && !cols) || !prog || (n > 0 && !out))
+        return fail(TQP_ERR_INVALID, "tqp_eval: null pointer or negative size");
+    if (ncols > XC_MAX) return fail(TQP_ERR_UNSUPPORTED, "tqp_eval: at most %d columns", XC_MAX);
+    if (nprog < 1 || nprog > XP_MAX) return fail(TQP_ERR_UNSUPPORTED, "tqp_eval: 1 to %d instructions", XP_MAX);
+    if (n > MAX_ELEMS) return fail(TQP_ERR_UNSUPPORTED, "tqp_eval: n = %lld", (long long)n);
+    XProg p{};
+    for (int c = 0; c < ncols; ++c) {
+        if (cols[c].type != TQP_I8 && cols[c].type != TQP_I32 && cols[c].type != TQP_I64)
+            return fail(TQP_ERR_INVALID, "tqp_eval: column %d has an unknown type", c);
+        if (n > 0 && !cols[c].data) return fail(TQP_ERR_INVALID, "tqp_eval: column %d is null", c);
+        p.col[c] = cols[c].data;
+        p.type[c] = cols[c].type;
+    }
+    // the stack depth before every instruction is known here: check the program once
+    int sp = 0;
+    for (int pc = 0; pc < nprog; ++pc) {
+        const int32_t op = prog[pc].op;
+        if (op < 0 || op >= XO_COUNT) return fail(TQP_ERR_INVALID, "tqp_eval: unknown operator %d at %d", op, pc);
+        if (op == XO_COL && (prog[pc].arg < 0 || prog[pc].arg >= ncols))
+            return fail(TQP_ERR_INVALID, "tqp_eval: column %lld out of range at %d", (long long)prog[pc].arg, pc);
+        const int ar = x_arity(op);
+        if (sp < ar) return fail(TQP_ERR_INVALID, "tqp_eval: operator %d at %d lacks operands", op, pc);
+        sp = sp - ar + 1;
+        if (sp > XS_MAX) return fail(TQP_ERR_UNSUPPORTED, "tqp_eval: stack deeper than %d", XS_MAX);
+        p.op[pc] = op;
+        p.arg[pc] = prog[pc].arg;
+    }
+    if (sp != 1) return fail(TQP_ERR_INVALID, "tqp_eval: the program leaves %d values", sp);
+    p.n = nprog;
+    if (n == 0) return TQP_OK;
+    TQP_LAUNCH(ctx, stream, "eval",
+               k_eval<<<grid_for(n, XE_BLOCK * 4, (int64_t)ctx->num_cus * 8), XE_BLOCK, 0, stream>>>(p, n, d_n, out,
+                                                                                                   ctx->d_err));
+    return TQP_OK;
+}
+
+}  // extern "C"

@@ -29,7 +29,7 @@ def _lib():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ("tqp_filter", "tqp_sort", "tqp_join", "tqp_join_kind", "tqp_hash_join", "tqp_join_band",
-                     "tqp_pack_keys", "tqp_groupby_agg", "tqp_hash_groupby", "tqp_gather",
+                     "tqp_pack_keys", "tqp_groupby_agg", "tqp_hash_groupby", "tqp_gather", "tqp_eval",
                      "tqp_topk",
                      "tqp_fragment_flags", "tqp_fragment_cust", "tqp_ctx_create"):
         assert required in names

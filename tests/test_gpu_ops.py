@@ -234,6 +234,61 @@ def test_pack_keys_range_flag(hip, ctx):
     assert ctx.errors() & hip.DEVERR_KEY_RANGE
 
 
+def _random_program(rng, ncols, length):
+    """A valid postfix program of about `length` instructions, every operator included."""
+    prog, sp = [], 0
+    while len(prog) < length or sp != 1:
+        can = [0, 1] if sp < 12 else []
+        if sp >= 1:
+            can += [oracle.X_NEG, oracle.X_NOT]
+        if sp >= 2:
+            can += list(range(2, 7)) + list(range(8, 16))
+        if sp >= 3:
+            can += [oracle.X_SELECT]
+        if len(prog) >= length and sp > 1:
+            can = [c for c in can if c not in (0, 1, oracle.X_NEG, oracle.X_NOT)]
+        op = int(rng.choice(can))
+        arg = int(rng.integers(0, ncols)) if op == 0 else int(rng.integers(-9, 10)) if op == 1 else 0
+        prog.append((op, arg))
+        sp += 1 if op in (0, 1) else 0 if op in (oracle.X_NEG, oracle.X_NOT) else -2 if op == oracle.X_SELECT else -1
+    return prog
+
+
+@pytest.mark.parametrize("n", [0, 1, 255, 4097, 300_007])
+def test_eval(hip, ctx, n):
+    """Random postfix programs (every operator, nested selects, divisions by columns that hold zeros)
+    over int8 / int32 / int64 columns against the oracle's tree evaluation, element by element."""
+    rng = _rng(n + 3)
+    cols = [rng.integers(-10**6, 10**6, n).astype(np.int64), rng.integers(-3, 4, n).astype(np.int32),
+            rng.integers(-2, 3, n).astype(np.int8), rng.integers(-2**62, 2**62, n).astype(np.int64)]
+    dc = [_dev(c) for c in cols]
+    for trial in range(12):
+        prog = _random_program(rng, len(cols), int(rng.integers(1, 40)))
+        want, z = oracle.eval_expr(cols, prog)
+        got = _np(hip.eval_expr(ctx, dc, prog))
+        assert np.array_equal(got, want), (trial, prog)
+        assert ctx.errors() == (hip.DEVERR_VALUE_RANGE if z else 0), (trial, prog)
+
+
+def test_eval_edges(hip, ctx):
+    X = oracle
+    a = np.array([7, -7, 7, -7, 0, 5, np.iinfo(np.int64).min, np.iinfo(np.int64).min, np.iinfo(np.int64).max],
+                 np.int64)
+    b = np.array([2, 2, -2, -2, 3, 0, -1, 1, -1], np.int64)
+    for op in (X.X_DIV, X.X_MOD, X.X_MUL, X.X_ADD, X.X_SUB):
+        prog = [(X.X_COL, 0), (X.X_COL, 1), (op, 0)]
+        want, z = oracle.eval_expr([a, b], prog)
+        assert np.array_equal(_np(hip.eval_expr(ctx, [_dev(a), _dev(b)], prog)), want)
+        assert ctx.errors() == (hip.DEVERR_VALUE_RANGE if z else 0)
+    dn = _dev(np.array([4], np.int64))
+    out = _np(hip.eval_expr(ctx, [_dev(a)], [(X.X_COL, 0), (X.X_CONST, 1), (X.X_ADD, 0)], d_n=dn))
+    assert np.array_equal(out[:4], a[:4] + 1)
+    for bad in ([(X.X_ADD, 0)], [(X.X_CONST, 1), (X.X_CONST, 2)], [(X.X_COL, 1)], [(99, 0)],
+                [(X.X_CONST, 1)] * 17 + [(X.X_ADD, 0)] * 16):
+        with pytest.raises(hip.TQPError):
+            hip.eval_expr(ctx, [_dev(a)], bad)
+
+
 @pytest.mark.parametrize("n,nsrc", [(0, 5), (1, 1), (4097, 100), (300_007, 2_000_000)])
 def test_gather(hip, ctx, n, nsrc):
     rng = _rng(n + nsrc)
