@@ -150,11 +150,11 @@ def main():
                          "and a row outside the declared width sets a device error flag)")
     ap.add_argument("--date-lt", type=int, default=None,
                     help="config 2 with another filter constant D (date < D; the workload uses 2400)")
-    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 4, 5, 6, 7, 8],
+    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 4, 5, 6, 7, 8, 9],
                     help="2: the 60M-row custkey fragment (default); 3: 256 flags fragments, batched vs plain; "
                          "4: served mix under Poisson arrivals, concurrent vs serial; 5: the join kinds on the "
                          "config-2 join inputs; 6: hash join vs sort join from unsorted inputs, 1 to 64 rows per key; "
-                         "7: hash vs sort group-by over 60M rows, 6 to 15M groups; 8: a chain of three joins")
+                         "7: hash vs sort group-by over 60M rows, 6 to 15M groups; 8: a chain of three joins; 9: expression programs")
     ap.add_argument("--rates", default="50,100,200,400,800", help="arrival rates (fragments/s) for --config 4")
     ap.add_argument("--requests", type=int, default=400, help="requests per rate for --config 4")
     ap.add_argument("--slots", type=int, default=8)
@@ -186,6 +186,8 @@ def main():
         return bench_groupby(args)
     if args.config == 8:
         return bench_chain(args)
+    if args.config == 9:
+        return bench_expr(args)
     if args.config == 4:
         return bench_serve(args)
 
@@ -598,6 +600,59 @@ def bench_chain(args):
                       "warmup": args.warmup, "higher_is_better": False, "data": "synthetic", "dtype": "int32",
                       "config": {"workload": "%d fact -> %d mid -> %d cust -> %d nation rows, %d result tuples"
                                  % (n, m, c, q, n)}, "result": res}), flush=True)
+
+
+def bench_expr(args):
+    """Expression programs over 60M rows: the revenue expression price * (100 - disc) and a CASE
+    (date < D ? price * (100 - disc) : 0) + flag over int64 / int32 / int8 columns, as one tqp_eval
+    launch each.  Reports the kernel time and the rate of algorithmic bytes (columns read once,
+    int64 result written once) against the 8 TB/s HBM peak; one result is checked against numpy."""
+    import numpy as np
+    import torch
+
+    import paper_2203_01877_amd as tqp
+    from paper_2203_01877_amd import _lib
+
+    n = args.rows or 60_000_000
+    dev = torch.device("cuda", 0)
+    ctx = tqp.Context(0)
+    rng = np.random.default_rng(31)
+    h = {"price": rng.integers(90_000, 10_500_000, n).astype(np.int64), "disc": rng.integers(0, 11, n).astype(np.int64),
+         "date": rng.integers(0, 2557, n).astype(np.int32), "flag": rng.integers(0, 3, n).astype(np.int8)}
+    d = {k: torch.from_numpy(v).to(dev) for k, v in h.items()}
+    X = _lib
+    progs = {
+        "revenue": ([d["price"], d["disc"]], [(X.TQP_X_COL, 0), (X.TQP_X_CONST, 100), (X.TQP_X_COL, 1),
+                                                (X.TQP_X_SUB, 0), (X.TQP_X_MUL, 0)], 8 + 8 + 8),
+        "case": ([d["date"], d["price"], d["disc"], d["flag"]],
+                 [(X.TQP_X_COL, 0), (X.TQP_X_CONST, 2400), (X.TQP_X_LT, 0), (X.TQP_X_COL, 1), (X.TQP_X_CONST, 100),
+                  (X.TQP_X_COL, 2), (X.TQP_X_SUB, 0), (X.TQP_X_MUL, 0), (X.TQP_X_CONST, 0), (X.TQP_X_SELECT, 0),
+                  (X.TQP_X_COL, 3), (X.TQP_X_ADD, 0)], 4 + 8 + 8 + 1 + 8),
+    }
+    res = {}
+    for name, (cols, prog, bpr) in progs.items():
+        for _ in range(args.warmup):
+            out = tqp.eval_expr(ctx, cols, prog)
+        torch.cuda.synchronize()
+        ctx.profile_read()
+        ctx.set_profiling(True)
+        for _ in range(args.steps):
+            out = tqp.eval_expr(ctx, cols, prog)
+        torch.cuda.synchronize()
+        recs = ctx.profile_read()
+        ctx.set_profiling(False)
+        ms = sum(t for _, t in recs) / args.steps
+        res[name] = {"ms": round(ms, 4), "bytes_per_row": bpr, "GB/s": round(n * bpr / ms / 1e6, 1),
+                     "frac_of_8TBps": round(n * bpr / ms / 1e6 / 8000.0, 3)}
+        log("%s: %s" % (name, res[name]))
+    want = h["price"] * (100 - h["disc"])
+    got = tqp.eval_expr(ctx, [d["price"], d["disc"]], progs["revenue"][1]).cpu().numpy()
+    if not np.array_equal(got, want) or ctx.errors():
+        log("expression result differs from numpy")
+        sys.exit(3)
+    print(json.dumps({"metric": "expression ms and GB/s", "unit": "ms", "n_gpus": 1, "steps": args.steps,
+                      "warmup": args.warmup, "higher_is_better": False, "data": "synthetic", "dtype": "int64",
+                      "config": {"workload": "%d rows, two expression programs" % n}, "result": res}), flush=True)
 
 
 def bench_batch(args):

@@ -15,6 +15,8 @@ STATUS_NAMES = {0: "TQP_OK", 1: "TQP_ERR_INVALID", 2: "TQP_ERR_WORKSPACE", 3: "T
                 4: "TQP_ERR_HIP", 5: "TQP_ERR_UNSUPPORTED"}
 TQP_I8, TQP_I32, TQP_I64 = 1, 2, 3
 TQP_LT, TQP_LE, TQP_GT, TQP_GE, TQP_EQ, TQP_NE = range(6)
+(TQP_X_COL, TQP_X_CONST, TQP_X_ADD, TQP_X_SUB, TQP_X_MUL, TQP_X_DIV, TQP_X_MOD, TQP_X_NEG, TQP_X_LT, TQP_X_LE,
+ TQP_X_GT, TQP_X_GE, TQP_X_EQ, TQP_X_NE, TQP_X_AND, TQP_X_OR, TQP_X_NOT, TQP_X_SELECT) = range(18)
 JOIN_INNER, JOIN_LEFT_SEMI, JOIN_LEFT_ANTI, JOIN_LEFT_OUTER = range(4)
 DEVERR_KEY_RANGE, DEVERR_SPIN, DEVERR_CAPACITY, DEVERR_VALUE_RANGE = 1, 2, 4, 8
 

@@ -32,6 +32,7 @@ struct XProg {
     const void* col[XC_MAX];
     int32_t type[XC_MAX];
     int32_t n;
+    uint32_t used;               // bit c: the program reads column c
 };
 
 __device__ __forceinline__ int64_t x_load(const XProg& p, int c, int64_t row) {
@@ -50,10 +51,21 @@ k_eval(XProg p, int64_t n_upper, const int64_t* d_n, int64_t* out, uint32_t* fla
     const int tid = threadIdx.x;
     bool zdiv = false;
     for (int64_t row = (int64_t)blockIdx.x * XE_BLOCK + tid; row < n; row += (int64_t)gridDim.x * XE_BLOCK) {
+        // the row's referenced columns, loads issued together before the program runs
+        int64_t cv[XC_MAX];
+#pragma unroll
+        for (int c = 0; c < XC_MAX; ++c) cv[c] = (p.used >> c) & 1u ? x_load(p, c, row) : 0;
         int sp = 0;                                   // the same at every step of every thread
         for (int pc = 0; pc < p.n; ++pc) {
             const int32_t op = p.op[pc];
-            if (op == XO_COL) { st[sp++][tid] = x_load(p, (int)p.arg[pc], row); continue; }
+            if (op == XO_COL) {
+                int64_t v = 0;
+#pragma unroll
+                for (int c = 0; c < XC_MAX; ++c)
+                    if (c == p.arg[pc]) v = cv[c];
+                st[sp++][tid] = v;
+                continue;
+            }
             if (op == XO_CONST) { st[sp++][tid] = p.arg[pc]; continue; }
             if (op == XO_NEG) { st[sp - 1][tid] = (int64_t)(0ull - (uint64_t)st[sp - 1][tid]); continue; }
             if (op == XO_NOT) { st[sp - 1][tid] = st[sp - 1][tid] == 0; continue; }
@@ -139,6 +151,7 @@ tqp_status tqp_eval(tqp_ctx* ctx, const tqp_column* cols, int ncols, int64_t n, 
         if (sp > XS_MAX) return fail(TQP_ERR_UNSUPPORTED, "tqp_eval: stack deeper than %d", XS_MAX);
         p.op[pc] = op;
         p.arg[pc] = prog[pc].arg;
+        if (op == XO_COL) p.used |= 1u << prog[pc].arg;
     }
     if (sp != 1) return fail(TQP_ERR_INVALID, "tqp_eval: the program leaves %d values", sp);
     p.n = nprog;
