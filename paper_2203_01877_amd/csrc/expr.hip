@@ -3,8 +3,9 @@
 // time, each writing its intermediate column to device memory.  Here the
 // expression comes as a postfix program (a small descriptor the host checks
 // once) and one kernel evaluates all of it per row, with the evaluation stack
-// of each thread in LDS: the intermediates never reach HBM, so the kernel
-// reads the referenced columns once and writes the result once.
+// in registers (its top) and LDS (the rest): the intermediates never reach
+// HBM, so the kernel reads the referenced columns once and writes the result
+// once.
 //
 // Values are int64; +, -, * and unary minus wrap (two's complement); / and %
 // truncate toward zero, a zero divisor gives 0 and sets
@@ -19,7 +20,8 @@ namespace {
 constexpr int XP_MAX = 64;       // instructions
 constexpr int XS_MAX = 16;       // stack depth
 constexpr int XC_MAX = 8;        // columns
-constexpr int XE_BLOCK = 256;
+constexpr int XE_BLOCK = 128;
+constexpr int XE_ROWS = 2;       // rows per thread
 
 enum : int32_t {
     XO_COL = 0, XO_CONST, XO_ADD, XO_SUB, XO_MUL, XO_DIV, XO_MOD, XO_NEG,
@@ -43,67 +45,102 @@ __device__ __forceinline__ int64_t x_load(const XProg& p, int c, int64_t row) {
     }
 }
 
+// Every thread evaluates XE_ROWS rows together, instruction by instruction:
+// the top of each row's stack stays in a register, the values below it in
+// LDS: level l of row slot q at st[l * XE_ROWS * XE_BLOCK + q], as many
+// levels as the program needs (its deepest stack less one).
 __global__ void __launch_bounds__(XE_BLOCK)
 k_eval(XProg p, int64_t n_upper, const int64_t* d_n, int64_t* out, uint32_t* flags) {
-    __shared__ int64_t st[XS_MAX][XE_BLOCK];
+    extern __shared__ int64_t xe_st[];
     int64_t n = n_upper;
     if (d_n) { const int64_t t = *d_n; n = t < n ? t : n; }
     const int tid = threadIdx.x;
     bool zdiv = false;
-    for (int64_t row = (int64_t)blockIdx.x * XE_BLOCK + tid; row < n; row += (int64_t)gridDim.x * XE_BLOCK) {
-        // the row's referenced columns, loads issued together before the program runs
-        int64_t cv[XC_MAX];
+    const int64_t step = (int64_t)gridDim.x * XE_BLOCK * XE_ROWS;
+    for (int64_t base = (int64_t)blockIdx.x * XE_BLOCK * XE_ROWS; base < n; base += step) {
+        // the rows' referenced columns, loads issued together before the program runs
+        int64_t cv[XE_ROWS][XC_MAX];
 #pragma unroll
-        for (int c = 0; c < XC_MAX; ++c) cv[c] = (p.used >> c) & 1u ? x_load(p, c, row) : 0;
-        int sp = 0;                                   // the same at every step of every thread
+        for (int j = 0; j < XE_ROWS; ++j) {
+            const int64_t row = base + (int64_t)j * XE_BLOCK + tid;
+            const int64_t r = row < n ? row : n - 1;          // base < n, so n >= 1
+#pragma unroll
+            for (int c = 0; c < XC_MAX; ++c) cv[j][c] = (p.used >> c) & 1u ? x_load(p, c, r) : 0;
+        }
+        int64_t top[XE_ROWS];
+#pragma unroll
+        for (int j = 0; j < XE_ROWS; ++j) top[j] = 0;
+        int sp = 0;                                   // values on the stack; the same in every thread
         for (int pc = 0; pc < p.n; ++pc) {
             const int32_t op = p.op[pc];
-            if (op == XO_COL) {
-                int64_t v = 0;
+            const int64_t arg = p.arg[pc];
+            if (op == XO_COL || op == XO_CONST) {
 #pragma unroll
-                for (int c = 0; c < XC_MAX; ++c)
-                    if (c == p.arg[pc]) v = cv[c];
-                st[sp++][tid] = v;
+                for (int j = 0; j < XE_ROWS; ++j) {
+                    if (sp > 0) xe_st[(sp - 1) * (XE_ROWS * XE_BLOCK) + j * XE_BLOCK + tid] = top[j];
+                    int64_t v = arg;
+                    if (op == XO_COL) {
+#pragma unroll
+                        for (int c = 0; c < XC_MAX; ++c)
+                            if (c == arg) v = cv[j][c];
+                    }
+                    top[j] = v;
+                }
+                ++sp;
                 continue;
             }
-            if (op == XO_CONST) { st[sp++][tid] = p.arg[pc]; continue; }
-            if (op == XO_NEG) { st[sp - 1][tid] = (int64_t)(0ull - (uint64_t)st[sp - 1][tid]); continue; }
-            if (op == XO_NOT) { st[sp - 1][tid] = st[sp - 1][tid] == 0; continue; }
+            if (op == XO_NEG || op == XO_NOT) {
+#pragma unroll
+                for (int j = 0; j < XE_ROWS; ++j)
+                    top[j] = op == XO_NEG ? (int64_t)(0ull - (uint64_t)top[j]) : (int64_t)(top[j] == 0);
+                continue;
+            }
             if (op == XO_SELECT) {
-                const int64_t c = st[sp - 3][tid], t = st[sp - 2][tid], f = st[sp - 1][tid];
+#pragma unroll
+                for (int j = 0; j < XE_ROWS; ++j) {
+                    const int64_t c = xe_st[(sp - 3) * (XE_ROWS * XE_BLOCK) + j * XE_BLOCK + tid];
+                    const int64_t t = xe_st[(sp - 2) * (XE_ROWS * XE_BLOCK) + j * XE_BLOCK + tid];
+                    top[j] = c != 0 ? t : top[j];
+                }
                 sp -= 2;
-                st[sp - 1][tid] = c != 0 ? t : f;
                 continue;
             }
-            const int64_t a = st[sp - 2][tid], b = st[sp - 1][tid];
-            int64_t r;
-            switch (op) {
-                case XO_ADD: r = (int64_t)((uint64_t)a + (uint64_t)b); break;
-                case XO_SUB: r = (int64_t)((uint64_t)a - (uint64_t)b); break;
-                case XO_MUL: r = (int64_t)((uint64_t)a * (uint64_t)b); break;
-                case XO_DIV:
-                    if (b == 0) { zdiv = true; r = 0; }
-                    else if (b == -1) r = (int64_t)(0ull - (uint64_t)a);
-                    else r = a / b;
-                    break;
-                case XO_MOD:
-                    if (b == 0) { zdiv = true; r = 0; }
-                    else if (b == -1) r = 0;
-                    else r = a % b;
-                    break;
-                case XO_LT: r = a < b; break;
-                case XO_LE: r = a <= b; break;
-                case XO_GT: r = a > b; break;
-                case XO_GE: r = a >= b; break;
-                case XO_EQ: r = a == b; break;
-                case XO_NE: r = a != b; break;
-                case XO_AND: r = (a != 0) && (b != 0); break;
-                default: r = (a != 0) || (b != 0); break;
+#pragma unroll
+            for (int j = 0; j < XE_ROWS; ++j) {
+                const int64_t a = xe_st[(sp - 2) * (XE_ROWS * XE_BLOCK) + j * XE_BLOCK + tid], b = top[j];
+                int64_t r;
+                switch (op) {
+                    case XO_ADD: r = (int64_t)((uint64_t)a + (uint64_t)b); break;
+                    case XO_SUB: r = (int64_t)((uint64_t)a - (uint64_t)b); break;
+                    case XO_MUL: r = (int64_t)((uint64_t)a * (uint64_t)b); break;
+                    case XO_DIV:
+                        if (b == 0) { zdiv = true; r = 0; }
+                        else if (b == -1) r = (int64_t)(0ull - (uint64_t)a);
+                        else r = a / b;
+                        break;
+                    case XO_MOD:
+                        if (b == 0) { zdiv = true; r = 0; }
+                        else if (b == -1) r = 0;
+                        else r = a % b;
+                        break;
+                    case XO_LT: r = a < b; break;
+                    case XO_LE: r = a <= b; break;
+                    case XO_GT: r = a > b; break;
+                    case XO_GE: r = a >= b; break;
+                    case XO_EQ: r = a == b; break;
+                    case XO_NE: r = a != b; break;
+                    case XO_AND: r = (a != 0) && (b != 0); break;
+                    default: r = (a != 0) || (b != 0); break;
+                }
+                top[j] = r;
             }
             --sp;
-            st[sp - 1][tid] = r;
         }
-        out[row] = st[0][tid];
+#pragma unroll
+        for (int j = 0; j < XE_ROWS; ++j) {
+            const int64_t row = base + (int64_t)j * XE_BLOCK + tid;
+            if (row < n) out[row] = top[j];
+        }
     }
     if (__any(zdiv) && lane_id() == 0) set_flag(flags, FLAG_VALUE_RANGE);
 }
@@ -139,7 +176,7 @@ tqp_status tqp_eval(tqp_ctx* ctx, const tqp_column* cols, int ncols, int64_t n, 
         p.type[c] = cols[c].type;
     }
     // the stack depth before every instruction is known here: check the program once
-    int sp = 0;
+    int sp = 0, deepest = 1;
     for (int pc = 0; pc < nprog; ++pc) {
         const int32_t op = prog[pc].op;
         if (op < 0 || op >= XO_COUNT) return fail(TQP_ERR_INVALID, "tqp_eval: unknown operator %d at %d", op, pc);
@@ -149,6 +186,7 @@ tqp_status tqp_eval(tqp_ctx* ctx, const tqp_column* cols, int ncols, int64_t n, 
         if (sp < ar) return fail(TQP_ERR_INVALID, "tqp_eval: operator %d at %d lacks operands", op, pc);
         sp = sp - ar + 1;
         if (sp > XS_MAX) return fail(TQP_ERR_UNSUPPORTED, "tqp_eval: stack deeper than %d", XS_MAX);
+        deepest = sp > deepest ? sp : deepest;
         p.op[pc] = op;
         p.arg[pc] = prog[pc].arg;
         if (op == XO_COL) p.used |= 1u << prog[pc].arg;
@@ -156,8 +194,9 @@ tqp_status tqp_eval(tqp_ctx* ctx, const tqp_column* cols, int ncols, int64_t n, 
     if (sp != 1) return fail(TQP_ERR_INVALID, "tqp_eval: the program leaves %d values", sp);
     p.n = nprog;
     if (n == 0) return TQP_OK;
+    const size_t lds = (size_t)(deepest > 1 ? deepest - 1 : 1) * XE_ROWS * XE_BLOCK * sizeof(int64_t);
     TQP_LAUNCH(ctx, stream, "eval",
-               k_eval<<<grid_for(n, XE_BLOCK * 4, (int64_t)ctx->num_cus * 8), XE_BLOCK, 0, stream>>>(p, n, d_n, out,
+               k_eval<<<grid_for(n, XE_BLOCK * XE_ROWS, (int64_t)ctx->num_cus * 16), XE_BLOCK, lds, stream>>>(p, n, d_n, out,
                                                                                                    ctx->d_err));
     return TQP_OK;
 }
