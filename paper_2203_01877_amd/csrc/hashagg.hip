@@ -39,7 +39,12 @@
 // still overflows its table sets TQP_DEVERR_CAPACITY.
 //
 // COUNT(DISTINCT d): a second table of 64-bit entries (key + 1, d) as a set;
-// the row that inserts a pair adds one to its group's distinct count.
+// the row that inserts a pair adds one to its group's distinct count.  With
+// many groups the rows are partitioned as above but carry their row index,
+// partitions are sized by rows too (about 1024), and each block keeps its
+// partition's pairs in an LDS set, falling back to the global set only when
+// that fills (k_hpd_agg).  A plain COUNT(*) with more groups than an LDS
+// table holds takes the global table directly.
 //
 // Output: one row per group in no fixed order (slot order, compacted by wave
 // ballots), the group count in *d_ngroups.
@@ -598,6 +603,222 @@ k_hp_agg(const uint32_t* h, const uint64_t* v, const int64_t* start, int P, int 
     }
 }
 
+// ---------------------------------------------------------------- partitioned, with distinct counts
+// Rows as (h, row index): the value and the distinct column are read through
+// the index by the aggregating block.
+struct SrcHashPartIdx {
+    const int32_t* key;
+    int64_t n_upper;
+    const int64_t* d_n;
+    uint32_t* flags;
+    __device__ int64_t size() const {
+        if (!d_n) return n_upper;
+        const int64_t n = *d_n;
+        return n < n_upper ? n : n_upper;
+    }
+    __device__ bool load_key(int64_t i, uint32_t& k) const {
+        const int32_t x = key[i];
+        if (x < 0) set_flag(flags, FLAG_KEY_RANGE);
+        k = (uint32_t)x * HP_MUL;
+        return x >= 0;
+    }
+    __device__ bool load(int64_t i, uint32_t& k, uint32_t& v) const {
+        const int32_t x = key[i];
+        k = (uint32_t)x * HP_MUL;
+        v = (uint32_t)i;
+        return x >= 0;
+    }
+};
+
+constexpr int HPD_BLOCK = 256;
+constexpr int HPD_SET = 2048;                   // LDS pair-set slots of a partition (about 1024 rows each)
+
+// One block per partition, with COUNT(DISTINCT d): the group table as in
+// k_hp_agg plus a set of the partition's (key + 1, d) pairs in LDS.  The row
+// that inserts a pair adds one to its group's distinct count.  A pair the
+// full LDS set cannot take goes to the global set (a partition with far more
+// rows than expected, e.g. one very frequent key); the LDS set never loses an
+// entry, so a pair is never counted in both.
+template <bool VAL, bool MINMAX>
+__global__ void __launch_bounds__(HPD_BLOCK)
+k_hpd_agg(const uint32_t* h, const uint32_t* idx, const int64_t* start, int P, int lg, const int64_t* val,
+          const int32_t* dval, unsigned long long* gset, int log2s, HaOut o, unsigned long long* d_out,
+          uint32_t* flags) {
+    extern __shared__ __align__(16) unsigned long long ha_smem[];
+    __shared__ int64_t s_w[HPD_BLOCK / WAVE];
+    __shared__ unsigned long long s_base;
+    const int S = 1 << lg;
+    unsigned long long* s_set = ha_smem;
+    unsigned long long* s_sum = s_set + HPD_SET;
+    unsigned long long* s_max = s_sum + (VAL ? S : 0);
+    unsigned long long* s_nmin = s_max + (MINMAX ? S : 0);
+    uint32_t* s_key = reinterpret_cast<uint32_t*>(s_nmin + (MINMAX ? S : 0));
+    uint32_t* s_cnt = s_key + S;
+    uint32_t* s_nd = s_cnt + S;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < HPD_SET; i += HPD_BLOCK) s_set[i] = 0ull;
+    for (int i = tid; i < S; i += HPD_BLOCK) {
+        s_key[i] = 0u;
+        s_cnt[i] = 0u;
+        s_nd[i] = 0u;
+        if (VAL) s_sum[i] = 0ull;
+        if (MINMAX) s_max[i] = 0ull, s_nmin[i] = 0ull;
+    }
+    __syncthreads();
+    const int64_t b = start[blockIdx.x], e = start[blockIdx.x + 1];
+    const int hs = P + lg <= 32 ? 32 - lg : P;
+    const uint32_t smask = (uint32_t)((uint64_t(1) << log2s) - 1);
+    const uint32_t slimit = smask + 1 < HA_PROBE_LIMIT ? smask + 1 : HA_PROBE_LIMIT;
+    for (int64_t i0 = b; i0 < e; i0 += (int64_t)HPD_BLOCK * HA_ITEMS) {
+        uint32_t hh[HA_ITEMS], ri[HA_ITEMS];
+#pragma unroll
+        for (int j = 0; j < HA_ITEMS; ++j) {
+            const int64_t i = i0 + (int64_t)j * HPD_BLOCK + tid;
+            hh[j] = i < e ? h[i] : 0u;
+            ri[j] = i < e ? idx[i] : 0u;
+        }
+        int64_t vv[HA_ITEMS];
+        int32_t dd[HA_ITEMS];
+#pragma unroll
+        for (int j = 0; j < HA_ITEMS; ++j) {
+            const int64_t i = i0 + (int64_t)j * HPD_BLOCK + tid;
+            vv[j] = VAL && i < e ? val[ri[j]] : 0;
+            dd[j] = i < e ? dval[ri[j]] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < HA_ITEMS; ++j) {
+            const int64_t i = i0 + (int64_t)j * HPD_BLOCK + tid;
+            if (i >= e) continue;
+            const uint32_t k1 = hh[j] * HP_INV + 1u;
+            uint32_t sl = P < 32 ? ((hh[j] << P) >> hs) & (uint32_t)(S - 1) : 0u;
+            int found = -1;
+            for (int q = 0; q < S; ++q) {
+                uint32_t cur = s_key[sl];
+                if (cur == 0u) cur = atomicCAS(&s_key[sl], 0u, k1);
+                if (cur == 0u || cur == k1) { found = (int)sl; break; }
+                sl = (sl + 1) & (uint32_t)(S - 1);
+            }
+            if (found < 0) {
+                set_flag(flags, FLAG_CAPACITY);
+                continue;
+            }
+            atomicAdd(&s_cnt[found], 1u);
+            if (VAL) atomicAdd(&s_sum[found], (unsigned long long)vv[j]);
+            if (MINMAX) {
+                const unsigned long long ov = (unsigned long long)vv[j] ^ ORD_BIAS;
+                atomicMax(&s_max[found], ov);
+                atomicMax(&s_nmin[found], ~ov);
+            }
+            // the pair, first in the LDS set, then (when that is full) in the global one
+            const unsigned long long pe = ((unsigned long long)k1 << 32) | (uint32_t)dd[j];
+            uint32_t ps = ha_home(pe, 31 - __clz(HPD_SET));
+            int inserted = -1;                          // 1 new, 0 already there, -1 no room
+            for (int q = 0; q < HPD_SET; ++q) {
+                unsigned long long cur = s_set[ps];
+                if (cur == 0ull) cur = atomicCAS(&s_set[ps], 0ull, pe);
+                if (cur == 0ull) { inserted = 1; break; }
+                if (cur == pe) { inserted = 0; break; }
+                ps = (ps + 1) & (HPD_SET - 1);
+            }
+            if (inserted < 0) {
+                uint32_t gs = ha_home(pe, log2s);
+                for (uint32_t q = 0; q < slimit; ++q) {
+                    unsigned long long cur = gset[gs];
+                    if (cur == 0ull) cur = atomicCAS(&gset[gs], 0ull, pe);
+                    if (cur == 0ull) { inserted = 1; break; }
+                    if (cur == pe) { inserted = 0; break; }
+                    gs = (gs + 1) & smask;
+                }
+                if (inserted < 0) set_flag(flags, FLAG_CAPACITY);
+            }
+            if (inserted == 1) atomicAdd(&s_nd[found], 1u);
+        }
+    }
+    __syncthreads();
+    const int per = S > HPD_BLOCK ? S / HPD_BLOCK : 1;
+    uint32_t occ = 0;
+    for (int q = 0; q < per; ++q) {
+        const int i = q * HPD_BLOCK + tid;
+        if (i < S && s_key[i] != 0u) occ |= 1u << q;
+    }
+    const int64_t cnt = __popc(occ);
+    const int64_t incl = wave_incl_sum(cnt);
+    const int w = tid / WAVE;
+    if (lane_id() == WAVE - 1) s_w[w] = incl;
+    __syncthreads();
+    int64_t before = 0, tot = 0;
+    for (int ww = 0; ww < HPD_BLOCK / WAVE; ++ww) {
+        if (ww < w) before += s_w[ww];
+        tot += s_w[ww];
+    }
+    if (tid == 0) s_base = tot ? atomicAdd(d_out, (unsigned long long)tot) : 0ull;
+    __syncthreads();
+    int64_t r = (int64_t)s_base + before + incl - cnt;
+    for (int q = 0; q < per; ++q) {
+        if (!((occ >> q) & 1u)) continue;
+        const int i = q * HPD_BLOCK + tid;
+        if (r < o.gcap) {
+            o.key[r] = (int32_t)(s_key[i] - 1u);
+            o.cnt[r] = s_cnt[i];
+            o.ndist[r] = s_nd[i];
+            if (VAL && o.sum) o.sum[r] = (int64_t)s_sum[i];
+            if (MINMAX) {
+                if (o.max) o.max[r] = (int64_t)(s_max[i] ^ ORD_BIAS);
+                if (o.min) o.min[r] = (int64_t)(~s_nmin[i] ^ ORD_BIAS);
+            }
+        }
+        ++r;
+    }
+}
+
+template <bool VAL, bool MINMAX>
+constexpr int hpd_slot_bytes() {
+    return 12 + (VAL ? 8 : 0) + (MINMAX ? 16 : 0);
+}
+
+template <bool VAL, bool MINMAX>
+tqp_status hpd_run(tqp_ctx* ctx, const int32_t* gkey, const int64_t* val, const int32_t* dval, int64_t n,
+                   const int64_t* d_n, HaOut o, int64_t gcap, int64_t* d_ngroups, void* ws, size_t* ws_bytes,
+                   hipStream_t stream) {
+    // partitions of about 1024 rows and about 256 groups
+    int P = HP_MIN_BITS;
+    while (((n >> P) > 1024 || (gcap >> P) > 256) && P < 24) ++P;
+    const int64_t per = (gcap + (int64_t(1) << P) - 1) >> P;
+    int lg = 8;
+    while ((int64_t(1) << lg) < 4 * per && lg < 10) ++lg;
+    int log2s = 0;
+    while ((int64_t(1) << log2s) < 2 * n) ++log2s;
+    RadixBufs<R8, uint32_t> rb;
+    uint32_t *hk = nullptr, *hi = nullptr;
+    int64_t* start = nullptr;
+    unsigned long long *gset = nullptr, *d_out = nullptr;
+    Arena ar;
+    auto plan = [&](Arena& p) {
+        rb = radix_reserve<R8, uint32_t>(p, n, 32, 32 - P);
+        d_out = p.zero<unsigned long long>(1);
+        gset = p.zero<unsigned long long>(int64_t(1) << log2s);
+        hk = p.scratch<uint32_t>(n);
+        hi = p.scratch<uint32_t>(n);
+        start = p.scratch<int64_t>((int64_t(1) << P) + 1);
+    };
+    tqp_status st = with_workspace(ctx, ws, ws_bytes, stream, plan, ar);
+    if (st != TQP_OK || !ws) return st;
+    if ((st = fill_zero(ar.base, ar.zsize, stream, ctx)) != TQP_OK) return st;
+    SrcHashPartIdx src{gkey, n, d_n, ctx->d_err};
+    st = radix_launch<R8, uint32_t>(rb, src, n, true, nullptr, ~0u, hk, hi, ctx, stream, "hashpart_pass",
+                                    "hashpart_pass");
+    if (st != TQP_OK) return st;
+    const int64_t np = int64_t(1) << P;
+    TQP_LAUNCH(ctx, stream, "hashpart_bounds",
+               k_hp_bounds<<<grid_for(np + 1, 256, 0), 256, 0, stream>>>(hk, rb.d_cnt, P, start));
+    const size_t lds = (size_t)HPD_SET * 8 + ((size_t)1 << lg) * hpd_slot_bytes<VAL, MINMAX>();
+    TQP_LAUNCH(ctx, stream, "hashpart_distinct",
+               k_hpd_agg<VAL, MINMAX><<<(unsigned)np, HPD_BLOCK, lds, stream>>>(hk, hi, start, P, lg, val, dval, gset,
+                                                                                log2s, o, d_out, ctx->d_err));
+    TQP_LAUNCH(ctx, stream, "hashagg_finish", k_ha_finish<<<1, 64, 0, stream>>>(d_out, gcap, d_ngroups, ctx->d_err));
+    return TQP_OK;
+}
+
 template <bool MINMAX>
 constexpr int hp_slot_bytes() {
     return 16 + (MINMAX ? 16 : 0);
@@ -727,6 +948,19 @@ tqp_status tqp_hash_groupby(tqp_ctx* ctx, const int32_t* gkey, int64_t n, const 
         TQP_LAUNCH(ctx, stream, "hashagg_finish",
                    k_ha_finish<<<1, 64, 0, stream>>>(d_out, gcap, d_ngroups, ctx->d_err));
         return TQP_OK;
+    }
+    // distinct counts with many groups: partitioned too
+    if (want_dist && n > 0) {
+        const int lg_local = want_mm ? ha_lds_log2<true, true, true>(gcap)
+                             : want_val ? ha_lds_log2<true, false, true>(gcap)
+                                        : ha_lds_log2<false, false, true>(gcap);
+        if (lg_local < 0) {
+            HaOut o{out_key, out_cnt, out_sum, out_min, out_max, out_ndist, gcap};
+            if (want_mm) return hpd_run<true, true>(ctx, gkey, val, dval, n, d_n, o, gcap, d_ngroups, ws, ws_bytes, stream);
+            if (want_val)
+                return hpd_run<true, false>(ctx, gkey, val, dval, n, d_n, o, gcap, d_ngroups, ws, ws_bytes, stream);
+            return hpd_run<false, false>(ctx, gkey, val, dval, n, d_n, o, gcap, d_ngroups, ws, ws_bytes, stream);
+        }
     }
     int log2m = 0;
     while ((int64_t(1) << log2m) < 2 * gcap) ++log2m;

@@ -570,6 +570,20 @@ def test_hash_groupby_partitioned_negative_key(hip, ctx):
     assert np.array_equal(_np(out["sum"], G)[o], ws) and np.array_equal(_np(out["cnt"], G)[o], wc)
 
 
+def test_hash_groupby_distinct_skewed(hip, ctx):
+    """COUNT(DISTINCT) with many groups (the partitioned path) where one key holds half the rows and
+    tens of thousands of distinct values: its partition's LDS pair set fills and the rest of its
+    pairs go to the global set."""
+    rng = _rng(92)
+    n = 400_000
+    keys = rng.integers(0, 100_000, n).astype(np.int32)
+    keys[: n // 2] = 7
+    keys = keys[rng.permutation(n)]
+    val = rng.integers(-1000, 1000, n).astype(np.int64)
+    dval = rng.integers(0, 60_000, n).astype(np.int32)
+    _hash_groupby_case(hip, ctx, keys, val, dval, gcap=100_000)
+
+
 def test_hash_groupby_count_only(hip, ctx):
     """COUNT(*) and COUNT(DISTINCT) with no value column at all."""
     rng = _rng(78)
