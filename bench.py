@@ -553,8 +553,9 @@ def bench_chain(args):
     """A chain of three sort-based joins in the shape of the paper's multi-join plans: fact (60M rows,
     key into mid) -> mid (15M rows, primary key in order, key into cust) -> cust (1.5M rows, primary
     key shuffled, key into nation) -> nation (25 rows, in order).  Every fact row matches one row per
-    hop, so 60M tuples of 4 row positions come out.  Timed with the rule that skips the sort of a
-    key column already in order (mid and nation) and without it; kernel times from the library's
+    hop, so 60M tuples of 4 row positions come out.  Timed with the rule that treats a key column
+    equal to 0..M-1 as dense (mid and nation: a filter instead of sort and join), with the rule that
+    only skips the sort of a key column already in order, and with neither; kernel times from the library's
     events, wall time includes the one host read of each hop's size.  The result count is checked."""
     import numpy as np
     import torch
@@ -573,16 +574,17 @@ def bench_chain(args):
     pks = [d["mid_pk"], d["cust_pk"], d["nation_pk"]]
     kb = [int(x - 1).bit_length() for x in (m, c, q)]      # key widths of the three hops
     res = {"key_bits": kb}
-    for name, rule in (("skip_sorted", [True, False, True]), ("sort_all", [False, False, False])):
+    for name, rule, dense in (("dense_keys", [True, False, True], [True, False, True]),
+                              ("skip_sorted", [True, False, True], None), ("sort_all", [False, False, False], None)):
         caps = [n, n, n]
         for _ in range(args.warmup):
-            tqp.join_chain(ctx, outs, pks, pk_sorted=rule, key_bits=kb, caps=caps)
+            tqp.join_chain(ctx, outs, pks, pk_sorted=rule, key_bits=kb, caps=caps, pk_dense=dense)
         torch.cuda.synchronize()
         ctx.profile_read()
         ctx.set_profiling(True)
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            _, J = tqp.join_chain(ctx, outs, pks, pk_sorted=rule, key_bits=kb, caps=caps)
+            _, J = tqp.join_chain(ctx, outs, pks, pk_sorted=rule, key_bits=kb, caps=caps, pk_dense=dense)
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) * 1e3 / args.steps
         recs = ctx.profile_read()

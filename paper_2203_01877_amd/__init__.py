@@ -184,7 +184,8 @@ def gather(ctx: Context, src, idx, d_n=None, stream=None):
     return out[:n]
 
 
-def join_chain(ctx: Context, keys_out, keys_pk, pk_sorted=None, key_bits=0, caps=None, stream=None):
+def join_chain(ctx: Context, keys_out, keys_pk, pk_sorted=None, key_bits=0, caps=None, pk_dense=None,
+               stream=None):
     """A chain of sort-based equi-joins (a multi-join plan): table 0's column keys_out[0] joins table
     1's keys_pk[0], table 1's keys_out[1] joins table 2's keys_pk[1], and so on.  Returns one int32
     device tensor of row positions per table (the result tuples) and their count.
@@ -192,16 +193,30 @@ def join_chain(ctx: Context, keys_out, keys_pk, pk_sorted=None, key_bits=0, caps
     Each hop sorts the current left keys with their positions, sorts the right key column unless
     pk_sorted[t] says it is already in order (the plan rule of skipping a sort over sorted data),
     joins, and gathers the earlier position columns and the next hop's key through the join output.
+    pk_dense[t]: hop t's key column is exactly 0, 1, ..., M - 1 (a dense key in row order), so a
+    left key is its own match's row position: the hop is a filter of the keys in [0, M), with the
+    key carried along as the right row, and no sort or join at all.
     key_bits: the key width of every hop, or one per hop (fewer radix passes).  caps[t] bounds hop t's result; a hop whose result is larger runs again at its exact size (the
     join reports its true count).  Reads and clears the device error word; any error raises."""
     hops = len(keys_pk)
     if len(keys_out) != hops or hops < 1:
         raise ValueError("join_chain: one outgoing key column per hop, at least one hop")
     pk_sorted = pk_sorted or [False] * hops
+    pk_dense = pk_dense or [False] * hops
     kbits = list(key_bits) if isinstance(key_bits, (list, tuple)) else [key_bits] * hops
     cols = []
     cur = keys_out[0]
     for t in range(hops):
+        if pk_dense[t]:
+            M = keys_pk[t].numel()
+            li, rr, cnt = filter(ctx, [cur], [(0, TQP_GE, 0), (0, TQP_LT, M)], carry=cur, stream=stream)
+            J = int(cnt.item())
+            li, rr = li[:J], rr[:J]
+            cols = [gather(ctx, c, li, stream=stream) for c in cols] if cols else [li]
+            cols.append(rr)
+            if t + 1 < hops:
+                cur = gather(ctx, keys_out[t + 1], rr, stream=stream)
+            continue
         ls, lp = sort(ctx, cur, key_bits=kbits[t], perm=True, stream=stream)
         if pk_sorted[t]:
             rs, rp = keys_pk[t], None
@@ -220,7 +235,7 @@ def join_chain(ctx: Context, keys_out, keys_pk, pk_sorted=None, key_bits=0, caps
             cur = gather(ctx, keys_out[t + 1], rr, stream=stream)
     err = ctx.errors(stream=stream)
     if err:
-        raise TQPError("join_chain: device error flags 0x%x" % err)
+        raise RuntimeError("join_chain: device error flags 0x%x" % err)
     return cols, J
 
 

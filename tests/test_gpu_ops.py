@@ -343,6 +343,23 @@ def test_join_chain(hip, ctx, sizes, doms, pk_sorted):
     assert np.array_equal(_lex(got), _lex(want))
 
 
+def test_join_chain_dense(hip, ctx):
+    """Hops whose key column is 0..M-1 in order take the dense rule (a filter, no sort or join);
+    left keys at or above M drop out; mixed with ordinary hops."""
+    rng = _rng(93)
+    outs = [rng.integers(0, 12_000, 200_000).astype(np.int32), rng.integers(0, 3000, 10_000).astype(np.int32),
+            rng.integers(0, 40, 3000).astype(np.int32)]
+    pks = [np.arange(10_000, dtype=np.int32), rng.integers(0, 3000, 3000).astype(np.int32),
+           np.arange(40, dtype=np.int32)]
+    want = oracle.join_chain(outs, pks)
+    for dense in ([True, False, True], [False, False, False]):
+        cols, J = hip.join_chain(ctx, [_dev(o) for o in outs], [_dev(p) for p in pks], pk_dense=dense,
+                                 pk_sorted=[True, False, True])
+        assert J == len(want)
+        got = np.stack([_np(c, J) for c in cols], axis=1)
+        assert np.array_equal(_lex(got), _lex(want))
+
+
 _KINDS = {"semi": 1, "anti": 2, "outer": 3, "inner": 0}
 
 
