@@ -487,8 +487,9 @@ def bench_groupby(args):
     aggregation to this difference): N rows (60M, the fact table of the custkey fragment), G
     uniform keys, G = 6 .. 15M; SUM and COUNT per group.  Sort-based = tqp_groupby_agg (radix sort
     of the key, trimmed to its width, then the run reduction); hash-based = tqp_hash_groupby; hash
-    with every aggregate adds MIN, MAX and COUNT(DISTINCT) of a second column.  Times from the
-    library's own kernel events; both outputs are compared in full."""
+    with every aggregate adds MIN, MAX and COUNT(DISTINCT) of a second column; hash_distinct is COUNT
+    and COUNT(DISTINCT) alone.  Times from the library's own kernel events; the outputs are compared
+    in full."""
     import numpy as np
     import torch
 
@@ -508,7 +509,8 @@ def bench_groupby(args):
         kb = max(1, int(G - 1).bit_length())
         runs = {"sort": lambda: tqp.groupby_agg(ctx, gk, val, key_bits=kb, gcap=G),
                 "hash": lambda: tqp.hash_groupby(ctx, gk, val, gcap=G),
-                "hash_all": lambda: tqp.hash_groupby(ctx, gk, val, dv, gcap=G, minmax=True)}
+                "hash_all": lambda: tqp.hash_groupby(ctx, gk, val, dv, gcap=G, minmax=True),
+                "hash_distinct": lambda: tqp.hash_groupby(ctx, gk, dval=dv, gcap=G)}
         res = {"groups": G}
         outs = {}
         for name, fn in runs.items():
@@ -528,13 +530,14 @@ def bench_groupby(args):
                 sys.exit(3)
             k = out["key"][:ng].cpu().numpy()
             o = np.argsort(k)
-            outs[name] = (k[o], out["sum"][:ng].cpu().numpy()[o], out["cnt"][:ng].cpu().numpy()[o])
+            outs[name] = (k[o], out["cnt"][:ng].cpu().numpy()[o]) + (
+                (out["sum"][:ng].cpu().numpy()[o],) if out["sum"] is not None else ())
             res[name + "_ms"] = round(sum(t for _, t in recs) / args.steps, 4)
             per = {}
             for kname, t in recs:
                 per[kname] = per.get(kname, 0.0) + t / args.steps
             res[name + "_kernels_ms"] = {kk: round(v, 4) for kk, v in sorted(per.items())}
-        for name in ("hash", "hash_all"):
+        for name in ("hash", "hash_all", "hash_distinct"):
             if not all(np.array_equal(a, b) for a, b in zip(outs["sort"], outs[name])):
                 log("G = %d: %s and sort group-by differ" % (G, name))
                 sys.exit(3)

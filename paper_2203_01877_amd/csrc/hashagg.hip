@@ -605,9 +605,11 @@ k_hp_agg(const uint32_t* h, const uint64_t* v, const int64_t* start, int P, int 
 
 // ---------------------------------------------------------------- partitioned, with distinct counts
 // Rows as (h, row index): the value and the distinct column are read through
-// the index by the aggregating block.
+// the index by the aggregating block.  With no value column (COUNT and
+// COUNT(DISTINCT) only) the payload is the distinct column itself (dval set).
 struct SrcHashPartIdx {
     const int32_t* key;
+    const int32_t* dval;
     int64_t n_upper;
     const int64_t* d_n;
     uint32_t* flags;
@@ -625,7 +627,7 @@ struct SrcHashPartIdx {
     __device__ bool load(int64_t i, uint32_t& k, uint32_t& v) const {
         const int32_t x = key[i];
         k = (uint32_t)x * HP_MUL;
-        v = (uint32_t)i;
+        v = dval ? (uint32_t)dval[i] : (uint32_t)i;
         return x >= 0;
     }
 };
@@ -683,7 +685,7 @@ k_hpd_agg(const uint32_t* h, const uint32_t* idx, const int64_t* start, int P, i
         for (int j = 0; j < HA_ITEMS; ++j) {
             const int64_t i = i0 + (int64_t)j * HPD_BLOCK + tid;
             vv[j] = VAL && i < e ? val[ri[j]] : 0;
-            dd[j] = i < e ? dval[ri[j]] : 0;
+            dd[j] = !VAL ? (int32_t)ri[j] : i < e ? dval[ri[j]] : 0;      // without values the payload is d
         }
 #pragma unroll
         for (int j = 0; j < HA_ITEMS; ++j) {
@@ -804,7 +806,7 @@ tqp_status hpd_run(tqp_ctx* ctx, const int32_t* gkey, const int64_t* val, const 
     tqp_status st = with_workspace(ctx, ws, ws_bytes, stream, plan, ar);
     if (st != TQP_OK || !ws) return st;
     if ((st = fill_zero(ar.base, ar.zsize, stream, ctx)) != TQP_OK) return st;
-    SrcHashPartIdx src{gkey, n, d_n, ctx->d_err};
+    SrcHashPartIdx src{gkey, VAL ? nullptr : dval, n, d_n, ctx->d_err};
     st = radix_launch<R8, uint32_t>(rb, src, n, true, nullptr, ~0u, hk, hi, ctx, stream, "hashpart_pass",
                                     "hashpart_pass");
     if (st != TQP_OK) return st;

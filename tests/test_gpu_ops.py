@@ -601,14 +601,16 @@ def test_hash_groupby_distinct_skewed(hip, ctx):
     _hash_groupby_case(hip, ctx, keys, val, dval, gcap=100_000)
 
 
-def test_hash_groupby_count_only(hip, ctx):
-    """COUNT(*) and COUNT(DISTINCT) with no value column at all."""
-    rng = _rng(78)
-    keys = rng.integers(0, 3000, 100_000).astype(np.int32)
-    dval = rng.integers(0, 100, 100_000).astype(np.int32)
+@pytest.mark.parametrize("domain,gcap", [(3000, 4000), (30_000, 50_000)])
+def test_hash_groupby_count_only(hip, ctx, domain, gcap):
+    """COUNT(*) and COUNT(DISTINCT) with no value column at all: a per-block LDS table (gcap 4000)
+    and the partitioned path that carries the distinct column as the payload (gcap 50000)."""
+    rng = _rng(78 + domain)
+    keys = rng.integers(0, domain, 100_000).astype(np.int32)
+    dval = rng.integers(-50, 50, 100_000).astype(np.int32)
     wk, _, wc, _ = oracle.groupby(keys, np.zeros(len(keys), np.int64))
     _, _, _, wnd = oracle.group_minmax(keys, dval.astype(np.int64))
-    out = hip.hash_groupby(ctx, _dev(keys), dval=_dev(dval), gcap=4000)
+    out = hip.hash_groupby(ctx, _dev(keys), dval=_dev(dval), gcap=gcap)
     G = int(_np(out["d_ngroups"])[0])
     o = np.argsort(_np(out["key"], G))
     assert G == len(wk) and np.array_equal(_np(out["key"], G)[o], wk)
