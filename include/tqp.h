@@ -272,8 +272,9 @@ tqp_status tqp_groupby_agg(tqp_ctx* ctx, const int32_t* gkey, int64_t n, const i
  * the caller's bound on groups, which sizes the table (2 * gcap slots of 32
  * bytes, plus 2 * n slots of 8 bytes when out_ndist is given); groups beyond
  * it, or a probe of more than 4096 slots, set TQP_DEVERR_CAPACITY and leave
- * those rows out.  The group count goes to *d_ngroups; at most gcap rows
- * are written.  n or *d_n rows. */
+ * those rows out.  The group count goes to *d_ngroups (after an overflow:
+ * the groups that were taken in, which may be more or fewer than gcap); at
+ * most gcap rows are written.  n or *d_n rows. */
 tqp_status tqp_hash_groupby(tqp_ctx* ctx, const int32_t* gkey, int64_t n, const int64_t* d_n,
                             const int64_t* val, const int32_t* dval, int32_t* out_key, int64_t* out_cnt,
                             int64_t* out_sum, int64_t* out_min, int64_t* out_max, int64_t* out_ndist,

@@ -625,7 +625,10 @@ def test_hash_groupby_errors(hip, ctx, gcap):
     rng = _rng(79)
     keys = rng.integers(0, 8000, 50_000).astype(np.int32)
     val = rng.integers(0, 100, 50_000).astype(np.int64)
+    dval = rng.integers(0, 10, 50_000).astype(np.int32)
     hip.hash_groupby(ctx, _dev(keys), _dev(val), gcap=gcap)
+    assert ctx.errors() & hip.DEVERR_CAPACITY
+    hip.hash_groupby(ctx, _dev(keys), _dev(val), _dev(dval), minmax=True, gcap=gcap)
     assert ctx.errors() & hip.DEVERR_CAPACITY
     keys[[5, 7]] = -4
     wk, ws, wc, _ = oracle.groupby(keys[keys >= 0], val[keys >= 0])
