@@ -79,6 +79,7 @@ k_segreduce(const uint32_t* keys, VS vs, int64_t n_upper, const int64_t* d_n, ui
     __shared__ int64_t s_wave[W];
     __shared__ int64_t s_base;
     __shared__ uint32_t s_tile;
+    __shared__ int64_t s_pseg[W], s_pv[W], s_pc[W], s_pa[W];   // each wave's unfinished last run
     const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
 
     int64_t n = n_upper;
@@ -172,11 +173,42 @@ k_segreduce(const uint32_t* keys, VS vs, int64_t n_upper, const int64_t* d_n, ui
         }
         heads_so_far += popc64(h);
     }
+    bool partial = false;
     if (has_open) {                             // the chunk's last run may continue past it
         const int64_t last = chunk + (int64_t)ITEMS * WAVE - 1;
         const uint32_t lk = wave_read(key[ITEMS - 1], WAVE - 1);
         const bool ends = keys[last + 1] != lk;
-        if (l == 0) seg_flush(out, open_seg, open_v, open_c, open_a, open_here && ends);
+        if (open_here && ends) {
+            if (l == 0) seg_flush(out, open_seg, open_v, open_c, open_a, true);
+        } else {
+            partial = true;
+        }
+    }
+    // The waves' unfinished runs are merged in the block before they are added
+    // to the output: adjacent waves of a long run share one set of atomics.
+    if (l == 0) {
+        s_pseg[w] = partial ? open_seg : -1;
+        s_pv[w] = open_v;
+        s_pc[w] = open_c;
+        s_pa[w] = open_a;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int64_t cs = -1, cv = 0, cc = 0, ca = 0;
+        for (int ww = 0; ww < W; ++ww) {
+            const int64_t sg = s_pseg[ww];
+            if (sg != cs) {
+                if (cs >= 0) seg_flush(out, cs, cv, cc, ca, false);
+                cs = sg;
+                cv = cc = ca = 0;
+            }
+            if (sg >= 0) {
+                cv += s_pv[ww];
+                cc += s_pc[ww];
+                ca += s_pa[ww];
+            }
+        }
+        if (cs >= 0) seg_flush(out, cs, cv, cc, ca, false);
     }
 }
 
