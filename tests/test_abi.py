@@ -101,3 +101,12 @@ def test_struct_layouts_match_the_c_header(tmp_path):
         assert int(got[cname]) == ctypes.sizeof(py), cname
         for fname, _ in py._fields_:
             assert int(got["%s.%s" % (cname, fname)]) == getattr(py, fname).offset, (cname, fname)
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without libtqp.so the binding raises instead of computing anything another way."""
+    from paper_2203_01877_amd import _lib
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "SO", str(tmp_path / "libtqp.so"))
+    with pytest.raises(ImportError, match="no CPU fallback"):
+        _lib.load()
