@@ -40,10 +40,10 @@
 //
 // COUNT(DISTINCT d): a second table of 64-bit entries (key + 1, d) as a set;
 // the row that inserts a pair adds one to its group's distinct count.  With
-// many groups the rows are partitioned as above but carry their row index,
-// partitions are sized by rows too (about 1024), and each block keeps its
-// partition's pairs in an LDS set, falling back to the global set only when
-// that fills (k_hpd_agg).  A plain COUNT(*) with more groups than an LDS
+// many groups the rows are partitioned as above but carry d (and, with a
+// value column, their row index), partitions are sized by rows too (about
+// 1024), and each block keeps its partition's pairs in an LDS set, falling
+// back to the global set only when that fills (k_hpd_agg).  A plain COUNT(*) with more groups than an LDS
 // table holds takes the global table directly.
 //
 // Output: one row per group in no fixed order (slot order, compacted by wave
@@ -604,9 +604,11 @@ k_hp_agg(const uint32_t* h, const uint64_t* v, const int64_t* start, int P, int 
 }
 
 // ---------------------------------------------------------------- partitioned, with distinct counts
-// Rows as (h, row index): the value and the distinct column are read through
-// the index by the aggregating block.  With no value column (COUNT and
-// COUNT(DISTINCT) only) the payload is the distinct column itself (dval set).
+// Rows as (h, payload).  With a value column the payload (PL = uint64_t) is
+// the distinct value in the high half and the row index in the low half, and
+// the value is read through the index by the aggregating block; without one
+// (COUNT and COUNT(DISTINCT) only, PL = uint32_t) it is the distinct value.
+template <class PL>
 struct SrcHashPartIdx {
     const int32_t* key;
     const int32_t* dval;
@@ -624,10 +626,11 @@ struct SrcHashPartIdx {
         k = (uint32_t)x * HP_MUL;
         return x >= 0;
     }
-    __device__ bool load(int64_t i, uint32_t& k, uint32_t& v) const {
+    __device__ bool load(int64_t i, uint32_t& k, PL& v) const {
         const int32_t x = key[i];
         k = (uint32_t)x * HP_MUL;
-        v = dval ? (uint32_t)dval[i] : (uint32_t)i;
+        if constexpr (sizeof(PL) == 8) v = ((uint64_t)(uint32_t)dval[i] << 32) | (uint32_t)i;
+        else v = (uint32_t)dval[i];
         return x >= 0;
     }
 };
@@ -643,7 +646,7 @@ constexpr int HPD_SET = 2048;                   // LDS pair-set slots of a parti
 // entry, so a pair is never counted in both.
 template <bool VAL, bool MINMAX>
 __global__ void __launch_bounds__(HPD_BLOCK)
-k_hpd_agg(const uint32_t* h, const uint32_t* idx, const int64_t* start, int P, int lg, const int64_t* val,
+k_hpd_agg(const uint32_t* h, const typename std::conditional<VAL, uint64_t, uint32_t>::type* pay, const int64_t* start, int P, int lg, const int64_t* val,
           const int32_t* dval, unsigned long long* gset, int log2s, HaOut o, unsigned long long* d_out,
           uint32_t* flags) {
     extern __shared__ __align__(16) unsigned long long ha_smem[];
@@ -672,20 +675,21 @@ k_hpd_agg(const uint32_t* h, const uint32_t* idx, const int64_t* start, int P, i
     const uint32_t smask = (uint32_t)((uint64_t(1) << log2s) - 1);
     const uint32_t slimit = smask + 1 < HA_PROBE_LIMIT ? smask + 1 : HA_PROBE_LIMIT;
     for (int64_t i0 = b; i0 < e; i0 += (int64_t)HPD_BLOCK * HA_ITEMS) {
-        uint32_t hh[HA_ITEMS], ri[HA_ITEMS];
+        uint32_t hh[HA_ITEMS];
+        uint64_t pl[HA_ITEMS];
 #pragma unroll
         for (int j = 0; j < HA_ITEMS; ++j) {
             const int64_t i = i0 + (int64_t)j * HPD_BLOCK + tid;
             hh[j] = i < e ? h[i] : 0u;
-            ri[j] = i < e ? idx[i] : 0u;
+            pl[j] = i < e ? (uint64_t)pay[i] : 0ull;
         }
         int64_t vv[HA_ITEMS];
         int32_t dd[HA_ITEMS];
 #pragma unroll
         for (int j = 0; j < HA_ITEMS; ++j) {
             const int64_t i = i0 + (int64_t)j * HPD_BLOCK + tid;
-            vv[j] = VAL && i < e ? val[ri[j]] : 0;
-            dd[j] = !VAL ? (int32_t)ri[j] : i < e ? dval[ri[j]] : 0;      // without values the payload is d
+            vv[j] = VAL && i < e ? val[(uint32_t)pl[j]] : 0;                // the row index, low half
+            dd[j] = VAL ? (int32_t)(pl[j] >> 32) : (int32_t)(uint32_t)pl[j];
         }
 #pragma unroll
         for (int j = 0; j < HA_ITEMS; ++j) {
@@ -790,24 +794,26 @@ tqp_status hpd_run(tqp_ctx* ctx, const int32_t* gkey, const int64_t* val, const 
     while ((int64_t(1) << lg) < 4 * per && lg < 10) ++lg;
     int log2s = 0;
     while ((int64_t(1) << log2s) < 2 * n) ++log2s;
-    RadixBufs<R8, uint32_t> rb;
-    uint32_t *hk = nullptr, *hi = nullptr;
+    using PL = typename std::conditional<VAL, uint64_t, uint32_t>::type;
+    RadixBufs<R8, PL> rb;
+    uint32_t* hk = nullptr;
+    PL* hi = nullptr;
     int64_t* start = nullptr;
     unsigned long long *gset = nullptr, *d_out = nullptr;
     Arena ar;
     auto plan = [&](Arena& p) {
-        rb = radix_reserve<R8, uint32_t>(p, n, 32, 32 - P);
+        rb = radix_reserve<R8, PL>(p, n, 32, 32 - P);
         d_out = p.zero<unsigned long long>(1);
         gset = p.zero<unsigned long long>(int64_t(1) << log2s);
         hk = p.scratch<uint32_t>(n);
-        hi = p.scratch<uint32_t>(n);
+        hi = p.scratch<PL>(n);
         start = p.scratch<int64_t>((int64_t(1) << P) + 1);
     };
     tqp_status st = with_workspace(ctx, ws, ws_bytes, stream, plan, ar);
     if (st != TQP_OK || !ws) return st;
     if ((st = fill_zero(ar.base, ar.zsize, stream, ctx)) != TQP_OK) return st;
-    SrcHashPartIdx src{gkey, VAL ? nullptr : dval, n, d_n, ctx->d_err};
-    st = radix_launch<R8, uint32_t>(rb, src, n, true, nullptr, ~0u, hk, hi, ctx, stream, "hashpart_pass",
+    SrcHashPartIdx<PL> src{gkey, dval, n, d_n, ctx->d_err};
+    st = radix_launch<R8, PL>(rb, src, n, true, nullptr, ~0u, hk, hi, ctx, stream, "hashpart_pass",
                                     "hashpart_pass");
     if (st != TQP_OK) return st;
     const int64_t np = int64_t(1) << P;
