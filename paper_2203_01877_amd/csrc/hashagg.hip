@@ -278,11 +278,24 @@ constexpr int ha_lds_slot_bytes() {
 
 // The table has S = 2^lg slots in dynamic LDS (S * ha_lds_slot_bytes bytes):
 // the 8-byte columns first, then the 4-byte ones.
+// With distinct counts the block also keeps the (key + 1, d) pairs it has
+// seen in an LDS set of HA_LSET slots: only a pair new to the block is tried
+// in the global set, and one found there is not counted again.  A probe of
+// the LDS set stops after HA_LSET_PROBE slots (the pair then goes to the
+// global set, as does every later copy of it: slots are never freed, so they
+// meet the same full run).  The set is used only when gcap <= HA_LSET_GROUPS:
+// with more groups the pairs seen by a block outgrow it and the probes only
+// add work.
+constexpr int HA_LSET = 2048;
+constexpr int HA_LSET_PROBE = 16;
+constexpr int64_t HA_LSET_GROUPS = 64;
+
 template <bool VAL, bool MINMAX, bool DIST>
-__global__ void __launch_bounds__(HA_BLOCK) k_ha_local(HaArgs a, int lg) {
+__global__ void __launch_bounds__(HA_BLOCK) k_ha_local(HaArgs a, int lg, int pset) {
     extern __shared__ __align__(16) unsigned long long ha_smem[];
     const int S = 1 << lg;
-    unsigned long long* s_sum = ha_smem;
+    unsigned long long* s_pset = ha_smem;
+    unsigned long long* s_sum = s_pset + (DIST && pset ? HA_LSET : 0);
     unsigned long long* s_max = s_sum + (VAL ? S : 0);
     unsigned long long* s_nmin = s_max + (MINMAX ? S : 0);
     uint32_t* s_key = reinterpret_cast<uint32_t*>(s_nmin + (MINMAX ? S : 0));
@@ -295,6 +308,8 @@ __global__ void __launch_bounds__(HA_BLOCK) k_ha_local(HaArgs a, int lg) {
         if (MINMAX) s_max[i] = 0ull, s_nmin[i] = 0ull;
         if (DIST) s_nd[i] = 0u;
     }
+    if (DIST && pset)
+        for (int i = threadIdx.x; i < HA_LSET; i += HA_BLOCK) s_pset[i] = 0ull;
     __syncthreads();
     const int64_t n = ha_rows(a);
     const int64_t step = (int64_t)gridDim.x * HA_BLOCK * HA_ITEMS;
@@ -346,7 +361,20 @@ __global__ void __launch_bounds__(HA_BLOCK) k_ha_local(HaArgs a, int lg) {
         if (DIST) {
             bool ok[HA_ITEMS], ins[HA_ITEMS];
 #pragma unroll
-            for (int j = 0; j < HA_ITEMS; ++j) ok[j] = ls[j] >= 0 || gs[j] >= 0;
+            for (int j = 0; j < HA_ITEMS; ++j) {
+                ok[j] = ls[j] >= 0 || gs[j] >= 0;
+                if (!ok[j] || !pset) continue;
+                // seen before in this block: already tried globally, nothing to count
+                const unsigned long long pe = ((unsigned long long)k1[j] << 32) | (uint32_t)d[j];
+                uint32_t ps = ha_home(pe, 31 - __clz(HA_LSET));
+                for (int q = 0; q < HA_LSET_PROBE; ++q) {
+                    unsigned long long cur = s_pset[ps];
+                    if (cur == 0ull) cur = atomicCAS(&s_pset[ps], 0ull, pe);
+                    if (cur == 0ull) break;                        // new to the block
+                    if (cur == pe) { ok[j] = false; break; }
+                    ps = (ps + 1) & (HA_LSET - 1);
+                }                                                  // a full run: try globally
+            }
             ha_distinct(a, k1, d, ok, ins);
 #pragma unroll
             for (int j = 0; j < HA_ITEMS; ++j) {
@@ -851,7 +879,8 @@ template <bool VAL, bool MINMAX, bool DIST>
 int ha_lds_log2(int64_t gcap) {
     int lg = 0;
     while ((int64_t(1) << lg) < 2 * gcap || (1 << lg) < HA_LDS_MIN) ++lg;
-    return ((int64_t(1) << lg) * ha_lds_slot_bytes<VAL, MINMAX, DIST>() <= ha_local_bytes(DIST)) ? lg : -1;
+    const int64_t set = DIST && gcap <= HA_LSET_GROUPS ? HA_LSET * 8 : 0;
+    return ((int64_t(1) << lg) * ha_lds_slot_bytes<VAL, MINMAX, DIST>() + set <= ha_local_bytes(DIST)) ? lg : -1;
 }
 
 template <bool VAL, bool MINMAX, bool DIST>
@@ -863,11 +892,13 @@ tqp_status ha_run(tqp_ctx* ctx, const HaArgs& a, int64_t gcap, int64_t n, hipStr
             b = 4;
         return b < 1 ? 1 : b;
     }();
-    static int per_cu_local[32] = {};               // by log2 of the LDS slots
+    static int per_cu_local[2][32] = {};            // by the pair set's use and log2 of the LDS slots
     const int lg = ha_lds_log2<VAL, MINMAX, DIST>(gcap);
     if (lg >= 0) {
-        const size_t lds = ((size_t)1 << lg) * ha_lds_slot_bytes<VAL, MINMAX, DIST>();
-        if (!per_cu_local[lg]) {
+        const int pset = DIST && gcap <= HA_LSET_GROUPS;
+        const size_t lds = ((size_t)1 << lg) * ha_lds_slot_bytes<VAL, MINMAX, DIST>() + (pset ? HA_LSET * 8 : 0);
+        int& per_cu = per_cu_local[pset][lg];
+        if (!per_cu) {
             if (lds > 65536 &&
                 hipFuncSetAttribute(reinterpret_cast<const void*>(k_ha_local<VAL, MINMAX, DIST>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
@@ -876,11 +907,11 @@ tqp_status ha_run(tqp_ctx* ctx, const HaArgs& a, int64_t gcap, int64_t n, hipStr
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_ha_local<VAL, MINMAX, DIST>, HA_BLOCK, lds) !=
                 hipSuccess)
                 b = 1;
-            per_cu_local[lg] = b < 1 ? 1 : b;
+            per_cu = b < 1 ? 1 : b;
         }
-        const int grid = grid_for(n, (int64_t)HA_BLOCK * HA_ITEMS, (int64_t)ctx->num_cus * per_cu_local[lg]);
+        const int grid = grid_for(n, (int64_t)HA_BLOCK * HA_ITEMS, (int64_t)ctx->num_cus * per_cu);
         TQP_LAUNCH(ctx, stream, "hashagg_local",
-                   k_ha_local<VAL, MINMAX, DIST><<<grid, HA_BLOCK, lds, stream>>>(a, lg));
+                   k_ha_local<VAL, MINMAX, DIST><<<grid, HA_BLOCK, lds, stream>>>(a, lg, pset));
     } else {
         const int grid = grid_for(n, (int64_t)HA_BLOCK * HA_ITEMS, (int64_t)ctx->num_cus * per_cu_global);
         TQP_LAUNCH(ctx, stream, "hashagg_global", k_ha_global<VAL, MINMAX, DIST><<<grid, HA_BLOCK, 0, stream>>>(a));
