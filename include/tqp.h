@@ -67,7 +67,7 @@ typedef enum { TQP_LT = 0, TQP_LE = 1, TQP_GT = 2, TQP_GE = 3, TQP_EQ = 4, TQP_N
 #define TQP_DEVERR_KEY_RANGE 1u   /* a key was negative or >= 2^key_bits */
 #define TQP_DEVERR_SPIN 2u        /* an inter-tile wait hit its safety bound */
 #define TQP_DEVERR_CAPACITY 4u    /* an output count exceeded its capacity */
-#define TQP_DEVERR_VALUE_RANGE 8u /* a value was outside its declared width (revenue_bits) */
+#define TQP_DEVERR_VALUE_RANGE 8u /* a value was outside its declared width or domain */
 
 /* One column: device pointer to n contiguous values of `type`. */
 typedef struct {
@@ -170,12 +170,13 @@ tqp_status tqp_join(tqp_ctx* ctx, const int32_t* lkey, const int32_t* lrow, int6
  * would hold only -1).  An unknown kind returns TQP_ERR_INVALID. */
 /* Section 5.3, Algorithm 3: the hash-based equi-join.  Same rows as
  * tqp_join (every (lrow[i], rrow[j]) with lkey[i] == rkey[j]), but the inputs
- * need not be sorted: the right rows are chained per slot of a table of m
- * slots (m = the power of two at or above 2 * nr, slot = key mod m), and every
- * left row walks its slot's chain twice (count, then write).  Rows come in
- * left input order; the rows of one left row come in no fixed right order.
- * Keys are non-negative int32.  Arguments, device counts and capacity as
- * tqp_join. */
+ * need not be sorted.  The right rows go into an open-addressing table of m
+ * 64-bit slots (m = the power of two at or above 2 * nr; home slot = a
+ * multiplicative hash of the key, linear probing; one compare-and-swap per
+ * right row), and every left row scans from its home slot to the first free
+ * slot twice (count, then write at its offset).  Rows come in left input
+ * order; the rows of one left row come in no fixed right order.  Keys are
+ * non-negative int32.  Arguments, device counts and capacity as tqp_join. */
 tqp_status tqp_hash_join(tqp_ctx* ctx, const int32_t* lkey, const int32_t* lrow, int64_t nl,
                          const int64_t* d_nl, const int32_t* rkey, const int32_t* rrow, int64_t nr,
                          const int64_t* d_nr, int32_t* out_l, int32_t* out_r, int64_t cap,
@@ -262,7 +263,8 @@ tqp_status tqp_groupby_agg(tqp_ctx* ctx, const int32_t* gkey, int64_t n, const i
                            hipStream_t stream);
 
 /* Hash-based group-by (the hash aggregation Section 6 contrasts with the
- * sort-based one of Section 5.4) with the aggregates Section 4 lists:
+ * sort-based one of Section 5.4) with the aggregates listed in the
+ * introduction of Section 5:
  * one row per distinct key of gkey, in no fixed order: out_key, out_cnt =
  * count, and, for each of these outputs that is not NULL, out_sum =
  * sum(val), out_min = min(val), out_max = max(val), out_ndist = the number
@@ -302,7 +304,9 @@ tqp_status tqp_topk(tqp_ctx* ctx, const int32_t* key, const int64_t* sum, const 
  *   WHERE fact.date < D AND dim.seg = c GROUP BY g ORDER BY g
  * price is int64 cents, disc int64 percent, so SUM is exact in cent*percent.
  * The fact rows are [row0, row0 + n_fact) of the given columns (row0 lets a
- * fragment cover a range of a larger resident table). */
+ * fragment cover a range of a larger resident table).  flagA must lie in
+ * 0..2 and flagB in 0..1 (six groups); a joined row with a flag outside its
+ * domain is left out of every aggregate and sets TQP_DEVERR_VALUE_RANGE. */
 typedef struct {
     const int32_t* fk;
     const int32_t* date;
@@ -356,7 +360,10 @@ typedef struct {
                                * every kept row's price*(100-disc) lies in [0, 2^32); it is carried
                                * in 4 bytes through the sorts and the join (sums stay exact int64).
                                * A row outside sets TQP_DEVERR_VALUE_RANGE (results unspecified). */
-    int32_t reserved;
+    int32_t mid_sorted;       /* non-zero: pk is already in ascending order (custkey row-aligned with it),
+                               * so the mid sort is skipped, as Section 6.6's hand-optimised plans skip
+                               * sorting data that is already sorted.  The caller guarantees the order
+                               * and pk < 2^key_bits; neither is checked. */
 } tqp_cust_fragment;
 
 typedef struct {
@@ -424,6 +431,9 @@ tqp_status tqp_batch_replay(tqp_batch* b, hipStream_t stream);
  * max_batch of them in one slot).  A background thread admits, launches and
  * collects; results are read with tqp_server_poll.  With slots = 1 and
  * max_batch = 1 the server runs one request at a time: the serial form.
+ * Every slot has its own stream, side stream and device error word, so the
+ * launches of different slots neither wait for each other nor mix their
+ * error bits.
  *
  * Resident tables (device, owned by the caller, unchanged while the server
  * lives): the fact table carries two keys, fk_mid into the mid table and
@@ -448,9 +458,13 @@ typedef struct {
     int32_t cust_bits;        /* custkey < 2^cust_bits */
     int32_t slots;            /* requests on the device at once (1..64) */
     int32_t max_batch;        /* flags requests coalesced into one launch (1..256) */
-    int32_t reserved;
+    int32_t revenue_bits;     /* custkey requests: revenue width, as tqp_cust_fragment.revenue_bits */
     int64_t max_flags_rows;   /* largest fact row range of a flags request */
     size_t budget_bytes;      /* HBM working-set budget of in-flight requests */
+    int32_t presort_mid;      /* non-zero: the mid table is sorted by pk once, when the server is
+                               * created (server memory: 8 bytes per mid row), and custkey requests
+                               * join against that order instead of sorting the mid table again */
+    int32_t reserved;
 } tqp_server_config;
 
 #define TQP_REQ_CUST 0        /* custkey fragment over the whole fact table, top-k */
@@ -487,6 +501,10 @@ typedef struct {
     double t_done;            /* result visible on the host */
     int32_t slot;
     int32_t batch_size;       /* requests launched together with this one */
+    uint32_t dev_errors;      /* TQP_DEVERR_* bits raised by this launch's kernels (every request of
+                               * a batched launch gets the launch's bits); when non-zero, status is
+                               * TQP_ERR_CAPACITY for a capacity overflow, else TQP_ERR_INVALID */
+    int32_t reserved;
 } tqp_result;
 
 typedef struct tqp_server tqp_server;

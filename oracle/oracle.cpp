@@ -24,8 +24,8 @@
 //               right row with -1.
 //   group-by    Section 5.4 / Algorithm 2: one output row per distinct key,
 //               in ascending key order, with sum, count and average; the
-//               other aggregates Section 4 lists (min, max, count distinct)
-//               by the same definition.
+//               other aggregates listed in the introduction of Section 5
+//               (min, max, count distinct) by the same definition.
 //   fragments   the whole filter -> join -> group-by query of the workloads,
 //               as a hash join followed by a hash aggregation.
 //
@@ -376,8 +376,8 @@ int64_t orc_groupby(const int32_t* gkey, int64_t n, const int64_t* val, const in
     return g;
 }
 
-// The remaining aggregates of Section 4 (min, max and count with DISTINCT),
-// per distinct key in ascending order: min(val), max(val) and the number of
+// The remaining aggregates of Section 5's introduction (min, max and count
+// with DISTINCT), per distinct key in ascending order: min(val), max(val) and the number of
 // different values of val in the group.  Writes at most gcap groups; returns
 // the number of groups.
 int64_t orc_group_minmax(const int32_t* gkey, int64_t n, const int64_t* val, int32_t* out_key,

@@ -381,7 +381,9 @@ class CustFragmentRunner:
     """Prepared custkey fragment (join to the mid table, group by custkey, top-k)."""
 
     def __init__(self, ctx: Context, fact: dict, mid: dict, D: int, k: int = 100, key_bits: int = 0,
-                 cust_bits: int = 0, gcap: int | None = None, join_cap: int | None = None, revenue_bits: int = 0):
+                 cust_bits: int = 0, gcap: int | None = None, join_cap: int | None = None, revenue_bits: int = 0,
+                 mid_sorted: bool = False):
+        """mid_sorted: mid["pk"] is already ascending (custkey row-aligned), so the mid sort is skipped."""
         self.ctx = ctx
         dev = _dev(ctx)
         self.fact, self.mid = fact, mid
@@ -392,7 +394,7 @@ class CustFragmentRunner:
         self.k = k
         self.desc = _lib.CustFragment(fact["fk"].data_ptr(), fact["date"].data_ptr(), fact["price"].data_ptr(),
                                       fact["disc"].data_ptr(), n, mid["pk"].data_ptr(), mid["custkey"].data_ptr(),
-                                      m, D, key_bits, cust_bits, k, join_cap, revenue_bits, 0)
+                                      m, D, key_bits, cust_bits, k, join_cap, revenue_bits, int(bool(mid_sorted)))
         self.out = {"key": torch.empty(gcap, dtype=torch.int32, device=dev),
                     "sum": torch.empty(gcap, dtype=torch.int64, device=dev),
                     "cnt": torch.empty(gcap, dtype=torch.int64, device=dev),
@@ -538,7 +540,7 @@ class Server:
 
     def __init__(self, tables: dict, slots: int = 8, max_batch: int = 32, max_flags_rows: int = 4_000_000,
                  budget_bytes: int = 200 << 30, key_bits_mid: int = 0, key_bits_dim: int = 0, cust_bits: int = 0,
-                 device: int = 0):
+                 revenue_bits: int = 0, presort_mid: bool = False, device: int = 0):
         self.ctx = Context(device)
         self.tables = tables
         f, m, d = tables["fact"], tables["mid"], tables["dim"]
@@ -546,8 +548,8 @@ class Server:
                                 f["price"].data_ptr(), f["disc"].data_ptr(), f["flagA"].data_ptr(),
                                 f["flagB"].data_ptr(), f["fk"].numel(), m["pk"].data_ptr(), m["custkey"].data_ptr(),
                                 m["pk"].numel(), d["pk"].data_ptr(), d["seg"].data_ptr(), d["pk"].numel(),
-                                key_bits_mid, key_bits_dim, cust_bits, slots, max_batch, 0,
-                                min(max_flags_rows, f["fk"].numel()), budget_bytes)
+                                key_bits_mid, key_bits_dim, cust_bits, slots, max_batch, revenue_bits,
+                                min(max_flags_rows, f["fk"].numel()), budget_bytes, int(bool(presort_mid)), 0)
         h = ctypes.c_void_p()
         torch.cuda.synchronize()
         check(self.ctx.lib.tqp_server_create(self.ctx.h, ctypes.byref(cfg), ctypes.byref(h)), "tqp_server_create")
@@ -584,7 +586,7 @@ class Server:
                 r = self._buf[i]
                 d = {"id": r.id, "tag": r.tag, "kind": r.kind, "status": r.status, "join_rows": r.join_rows,
                      "groups": r.groups, "t_arrival": r.t_arrival, "t_admit": r.t_admit, "t_done": r.t_done,
-                     "slot": r.slot, "batch_size": r.batch_size}
+                     "slot": r.slot, "batch_size": r.batch_size, "dev_errors": r.dev_errors}
                 if r.kind == _lib.REQ_FLAGS:
                     G = max(0, min(8, r.groups))
                     d.update(key=list(r.key[:G]), sum=list(r.sum[:G]), cnt=list(r.cnt[:G]), avg=list(r.avg[:G]))

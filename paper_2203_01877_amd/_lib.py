@@ -52,7 +52,7 @@ class CustFragment(ctypes.Structure):
     _fields_ = [("fk", c_vp), ("date", c_vp), ("price", c_vp), ("disc", c_vp), ("n_fact", c_i64),
                 ("pk", c_vp), ("custkey", c_vp), ("n_mid", c_i64), ("D", c_i32), ("key_bits", c_i32),
                 ("cust_bits", c_i32), ("k", c_i32), ("join_cap", c_i64), ("revenue_bits", c_i32),
-                ("reserved", c_i32)]
+                ("mid_sorted", c_i32)]
 
 
 class CustOut(ctypes.Structure):
@@ -69,7 +69,8 @@ class ServerConfig(ctypes.Structure):
                 ("flagA", c_vp), ("flagB", c_vp), ("n_fact", c_i64), ("mid_pk", c_vp), ("mid_custkey", c_vp),
                 ("n_mid", c_i64), ("dim_pk", c_vp), ("dim_seg", c_vp), ("n_dim", c_i64), ("key_bits_mid", c_i32),
                 ("key_bits_dim", c_i32), ("cust_bits", c_i32), ("slots", c_i32), ("max_batch", c_i32),
-                ("reserved", c_i32), ("max_flags_rows", c_i64), ("budget_bytes", ctypes.c_size_t)]
+                ("revenue_bits", c_i32), ("max_flags_rows", c_i64), ("budget_bytes", ctypes.c_size_t),
+                ("presort_mid", c_i32), ("reserved", c_i32)]
 
 
 class Request(ctypes.Structure):
@@ -82,7 +83,8 @@ class Result(ctypes.Structure):
                 ("join_rows", c_i64), ("groups", c_i64), ("key", c_i32 * 8), ("sum", c_i64 * 8), ("cnt", c_i64 * 8),
                 ("avg", ctypes.c_double * 8), ("top_n", c_i32), ("top_key", c_i32 * TOPK_MAX),
                 ("top_sum", c_i64 * TOPK_MAX), ("top_cnt", c_i64 * TOPK_MAX), ("t_arrival", ctypes.c_double),
-                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double), ("slot", c_i32), ("batch_size", c_i32)]
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double), ("slot", c_i32), ("batch_size", c_i32),
+                ("dev_errors", ctypes.c_uint32), ("reserved", c_i32)]
 
 
 _lib = None

@@ -217,6 +217,7 @@ k_batch_join(const BatchSeg* segs, const BatchFrag* frags, int nfrag, const int6
     __shared__ int64_t s_item;
     const int64_t total = prefix[nfrag];
     Emit e{};
+    e.flags = flags;
     e.init(esm);
     for (;;) {
         if (threadIdx.x == 0) {
@@ -255,7 +256,7 @@ __global__ void k_batch_finalize(const BatchFrag* frags, int nfrag) {
     if (f >= nfrag) return;
     const BatchFrag& fr = frags[f];
     int64_t g = 0;
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < 6; ++k) {
         const int64_t s = fr.acc[k * 3], c = fr.acc[k * 3 + 1], p = fr.acc[k * 3 + 2];
         if (c == 0) continue;
         fr.out.key[g] = k;

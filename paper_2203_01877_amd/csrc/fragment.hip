@@ -44,7 +44,7 @@ int fact_low_bits(int64_t n, int kb, int rb) {
 __global__ void k_flags_finalize(const int64_t* acc, const int64_t* d_join_in, tqp_flags_out o) {
     if (threadIdx.x != 0) return;
     int64_t g = 0;
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < 6; ++k) {
         const int64_t s = acc[k * 3], c = acc[k * 3 + 1], p = acc[k * 3 + 2];
         if (c == 0) continue;
         o.key[g] = k;
@@ -94,6 +94,7 @@ tqp_status flags_launch(tqp_ctx* ctx, const tqp_flags_fragment& f, const tqp_fla
     e.flagA = f.flagA;
     e.flagB = f.flagB;
     e.acc = b.acc;
+    e.flags = ctx->d_err;
     if ((st = join_launch<JCfgFrag, uint32_t, uint32_t>(ctx, s, "join_flags_agg", b.join, b.fkeys, b.fvals, f.n_fact,
                                                         b.fact.d_cnt, b.dkeys, (const uint32_t*)nullptr, f.n_dim,
                                                         b.dim.d_cnt, b.d_join, INT64_MAX, e)) != TQP_OK)
@@ -130,13 +131,24 @@ void cust_reserve(Arena& a, const tqp_cust_fragment& f, const tqp_cust_out& o, C
     // pass sorts each span of 4096 keys in LDS (the join's binary-search
     // fallback needs them fully sorted) and records where each bucket of
     // 2^fact_lowb keys starts (the join tiles' windows)
-    b.mid = radix_reserve<Cfg, uint32_t>(a, f.n_mid, kb, b.fact_lowb);
-    if (b.fact_lowb > 0) {
-        b.mkeys_full = a.scratch<uint32_t>(f.n_mid);
-        b.mvals_full = a.scratch<uint32_t>(f.n_mid);
-        b.nspans = ((int64_t(1) << kb) + FINISH_SPAN - 1) >> FINISH_LOG2;
-        b.nmbkt = b.nspans << (FINISH_LOG2 - b.fact_lowb);
-        b.mbstart = a.scratch<int64_t>(b.nmbkt + 1);
+    if (f.mid_sorted) {
+        // the caller's mid keys are in order already: only the bucket starts
+        // of the join windows are needed
+        if (b.fact_lowb > 0) {
+            b.nmbkt = ((int64_t(1) << kb) + (int64_t(1) << b.fact_lowb) - 1) >> b.fact_lowb;
+            b.mbstart = a.scratch<int64_t>(b.nmbkt + 1);
+        }
+    } else {
+        b.mid = radix_reserve<Cfg, uint32_t>(a, f.n_mid, kb, b.fact_lowb);
+        if (b.fact_lowb > 0) {
+            b.mkeys_full = a.scratch<uint32_t>(f.n_mid);
+            b.mvals_full = a.scratch<uint32_t>(f.n_mid);
+            b.nspans = ((int64_t(1) << kb) + FINISH_SPAN - 1) >> FINISH_LOG2;
+            b.nmbkt = b.nspans << (FINISH_LOG2 - b.fact_lowb);
+            b.mbstart = a.scratch<int64_t>(b.nmbkt + 1);
+        }
+        b.mkeys = a.scratch<uint32_t>(f.n_mid);
+        b.mvals = a.scratch<uint32_t>(f.n_mid);
     }
     b.join = join_reserve<JCfgFrag>(a, f.n_fact);
     b.d_join = a.zero<int64_t>(1);
@@ -151,8 +163,6 @@ void cust_reserve(Arena& a, const tqp_cust_fragment& f, const tqp_cust_out& o, C
     b.fkeys = a.scratch<uint32_t>(f.n_fact);
     b.fvals = a.scratch<VT>(f.n_fact);
     b.fmask = a.scratch<uint64_t>((f.n_fact + 63) / 64 + 1);
-    b.mkeys = a.scratch<uint32_t>(f.n_mid);
-    b.mvals = a.scratch<uint32_t>(f.n_mid);
     b.gkeys_in = a.scratch<uint32_t>(f.join_cap);
     b.gvals_in = a.scratch<VT>(f.join_cap);
     b.gkeys = a.scratch<uint32_t>(f.join_cap);
@@ -167,24 +177,36 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
     const int kb = norm_key_bits(f.key_bits);
     const int cb = norm_key_bits(f.cust_bits);
     tqp_status st;
-    // mid side, (pk, custkey), sorted on the side stream while the fact side
-    // is sorted on s
-    if ((st = side_fork(ctx, s)) != TQP_OK) return st;
-    SrcKeyCol msrc{f.pk, f.custkey, f.n_mid};
-    if ((st = radix_launch<Cfg, uint32_t, SORT_TAG_MID>(b.mid, msrc, f.n_mid, true, nullptr, key_mask_for(kb),
-                                                        b.mkeys, b.mvals, ctx, ctx->side, "mid_pass_first",
-                                                        "mid_pass")) != TQP_OK)
-        return st;
-    const uint32_t* mk = b.mkeys;
-    const uint32_t* mv = b.mvals;
-    if (b.fact_lowb > 0 && f.n_mid > 0) {
-        // the join's fallback searches need the mid keys fully sorted: finish
-        // the low bits span by span
-        TQP_LAUNCH(ctx, ctx->side, "finish_sort",
-                   k_finish_sort<<<(unsigned)b.nspans, FINISH_BLOCK, 0, ctx->side>>>(
-                       b.mkeys, b.mvals, f.n_mid, b.mkeys_full, b.mvals_full, b.fact_lowb, b.mbstart));
-        mk = b.mkeys_full;
-        mv = b.mvals_full;
+    const uint32_t* mk = reinterpret_cast<const uint32_t*>(f.pk);
+    const uint32_t* mv = reinterpret_cast<const uint32_t*>(f.custkey);
+    if (f.mid_sorted) {
+        // sorted by the caller: the start of every 2^fact_lowb-key bucket, one
+        // search each, for the join windows
+        if (b.fact_lowb > 0)
+            TQP_LAUNCH(ctx, s, "mid_bucket_bounds",
+                       k_bucket_bounds<<<grid_for(b.nmbkt + 1, 256, 0), 256, 0, s>>>(mk, f.n_mid, nullptr,
+                                                                                     b.fact_lowb, b.nmbkt,
+                                                                                     b.mbstart));
+    } else {
+        // mid side, (pk, custkey), sorted on the side stream while the fact
+        // side is sorted on s
+        if ((st = side_fork(ctx, s)) != TQP_OK) return st;
+        SrcKeyCol msrc{f.pk, f.custkey, f.n_mid};
+        if ((st = radix_launch<Cfg, uint32_t, SORT_TAG_MID>(b.mid, msrc, f.n_mid, true, nullptr, key_mask_for(kb),
+                                                            b.mkeys, b.mvals, ctx, ctx->side, "mid_pass_first",
+                                                            "mid_pass")) != TQP_OK)
+            return st;
+        mk = b.mkeys;
+        mv = b.mvals;
+        if (b.fact_lowb > 0 && f.n_mid > 0) {
+            // the join's fallback searches need the mid keys fully sorted:
+            // finish the low bits span by span
+            TQP_LAUNCH(ctx, ctx->side, "finish_sort",
+                       k_finish_sort<<<(unsigned)b.nspans, FINISH_BLOCK, 0, ctx->side>>>(
+                           b.mkeys, b.mvals, f.n_mid, b.mkeys_full, b.mvals_full, b.fact_lowb, b.mbstart));
+            mk = b.mkeys_full;
+            mv = b.mvals_full;
+        }
     }
     // fact side: date < D fused into the sort; the payload is the revenue
     // price * (100 - disc), evaluated while the row is read
@@ -194,7 +216,7 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
         TQP_OK)
         return st;
 
-    if ((st = side_join(ctx, s)) != TQP_OK) return st;
+    if (!f.mid_sorted && (st = side_join(ctx, s)) != TQP_OK) return st;
     // join: emits (custkey, revenue)
     using Emit = EmitKeyVal<JCfgFrag::BLOCK, Cfg::RADIX_BITS, VT>;
     Emit e{};

@@ -2,8 +2,9 @@
 // aggregation of Section 5.4 / Algorithm 2.  Section 6 traces the paper's
 // loss on aggregation-heavy queries to its sorting, against systems that
 // aggregate in hash tables; this is that hash aggregation, so the two can be
-// compared on the same inputs.  It also evaluates the aggregates Section 4
-// lists besides sum and count: min, max and count with DISTINCT.
+// compared on the same inputs.  It also evaluates the aggregates that the
+// introduction of Section 5 lists besides sum and count: min, max and count
+// with DISTINCT.
 //
 // Table: open addressing over m = 2^log2m slots of 32 bytes (the power of two
 // at or above 2 * gcap), home slot a multiplicative hash of the key, linear

@@ -123,16 +123,19 @@ struct EmitKeyVal {
 // Flags-fragment aggregation fused into the join output (the small-G direct
 // path): gather price / disc / flags of the left row, evaluate the revenue
 // expression and accumulate sum, count and sum(price) per packed group
-// flagA * 2 + flagB in registers; flush once per block.
+// flagA * 2 + flagB in registers; flush once per block.  flagA in 0..2 and
+// flagB in 0..1 give the six groups 0..5; a row with a flag outside its
+// domain is left out and sets FLAG_VALUE_RANGE.
 template <int BLOCK>
 struct EmitFlagsAgg {
     static constexpr bool ORDERED = false;     // aggregates only: positions unused
-    static constexpr int G = 8;
+    static constexpr int G = 6;
     const int64_t* price;
     const int64_t* disc;
     const int8_t* flagA;
     const int8_t* flagB;
     int64_t* acc;              // [G][3] global: sum, count, sum(price)
+    uint32_t* flags;
     int64_t s[G], c[G], p[G];
     struct Smem {
         int64_t a[BLOCK / WAVE][G * 3];
@@ -144,7 +147,10 @@ struct EmitFlagsAgg {
     __device__ void operator()(int64_t, uint32_t, uint32_t lp, uint32_t, Smem&) {
         const int64_t pr = price[lp];
         const int64_t v = pr * (100 - disc[lp]);
-        const int g = flagA[lp] * 2 + flagB[lp];
+        const int fa = flagA[lp], fb = flagB[lp];
+        const bool ok = (unsigned)fa <= 2u && (unsigned)fb <= 1u;
+        const int g = ok ? fa * 2 + fb : -1;
+        if (!ok) set_flag(flags, FLAG_VALUE_RANGE);
 #pragma unroll
         for (int k = 0; k < G; ++k) {
             const bool on = (g == k);

@@ -7,6 +7,14 @@
 // as one batch) on the slot's own stream, so launches of different slots
 // overlap on the device, and turns the slot's completion event into host
 // results.  Latency is arrival -> result visible on the host.
+//
+// Every slot has a context of its own: its own side stream (the mid-table
+// sort of a custkey request forks onto it) and its own device error word,
+// which the slot's last kernel moves into the slot's result block, so errors
+// come back with the request that raised them.  The mid table can be sorted
+// once when the server starts: it never changes, and custkey requests then
+// join against that order (the plan rule of skipping the sort of sorted
+// data) instead of sorting 8 bytes per mid row each time.
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -39,6 +47,8 @@ struct ResultBlock {
     int32_t tkey[TQP_TOPK_MAX];
     int64_t tsum[TQP_TOPK_MAX];
     int64_t tcnt[TQP_TOPK_MAX];
+    uint32_t err;              // the slot's device error bits of this launch
+    uint32_t pad2;
 };
 
 struct Pending {
@@ -48,6 +58,7 @@ struct Pending {
 };
 
 struct Slot {
+    tqp_ctx* ctx = nullptr;              // own error word and side stream
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     char* ws = nullptr;
@@ -85,6 +96,8 @@ struct tqp_server {
     std::thread worker;
     void* dev_block = nullptr;           // all slot device memory
     void* host_block = nullptr;          // all slot pinned result blocks
+    uint32_t* mid_keys = nullptr;        // the mid table sorted by pk (presort_mid), and its custkeys
+    uint32_t* mid_cust = nullptr;
 };
 
 namespace {
@@ -100,14 +113,16 @@ tqp_cust_fragment cust_desc(const tqp_server* s, const tqp_request& r) {
     f.price = s->cfg.price;
     f.disc = s->cfg.disc;
     f.n_fact = s->cfg.n_fact;
-    f.pk = s->cfg.mid_pk;
-    f.custkey = s->cfg.mid_custkey;
+    f.pk = s->mid_keys ? reinterpret_cast<const int32_t*>(s->mid_keys) : s->cfg.mid_pk;
+    f.custkey = s->mid_keys ? reinterpret_cast<const int32_t*>(s->mid_cust) : s->cfg.mid_custkey;
+    f.mid_sorted = s->mid_keys ? 1 : 0;
     f.n_mid = s->cfg.n_mid;
     f.D = r.D;
     f.key_bits = s->cfg.key_bits_mid;
     f.cust_bits = s->cfg.cust_bits;
     f.k = r.k;
     f.join_cap = s->cfg.n_fact;
+    f.revenue_bits = s->cfg.revenue_bits;
     return f;
 }
 
@@ -179,6 +194,13 @@ size_t launch_bytes(tqp_server* s, const std::vector<Pending>& reqs, Slot& sl) {
     return bytes;
 }
 
+// Moves the slot context's error bits into the result block and clears them
+// (one thread; runs after the slot's last kernel on the slot's stream).
+__global__ void k_take_errors(uint32_t* err, uint32_t* dst) {
+    *dst = *err;
+    *err = 0;
+}
+
 int launch(tqp_server* s, Slot& sl) {
     const std::vector<Pending>& reqs = sl.reqs;
     size_t bytes = sl.ws_bytes;
@@ -186,11 +208,11 @@ int launch(tqp_server* s, Slot& sl) {
     if (reqs[0].req.kind == TQP_REQ_CUST) {
         tqp_cust_fragment f = cust_desc(s, reqs[0].req);
         tqp_cust_out o = cust_out(s, sl);
-        st = tqp_fragment_cust(s->ctx, &f, &o, sl.ws, &bytes, sl.stream);
+        st = tqp_fragment_cust(sl.ctx, &f, &o, sl.ws, &bytes, sl.stream);
     } else if (reqs.size() == 1) {
         tqp_flags_fragment f = flags_desc(s, reqs[0].req);
         tqp_flags_out o = flags_out(sl.d_res, 0);
-        st = tqp_fragment_flags(s->ctx, &f, &o, sl.ws, &bytes, sl.stream);
+        st = tqp_fragment_flags(sl.ctx, &f, &o, sl.ws, &bytes, sl.stream);
     } else {
         std::vector<tqp_flags_fragment> fs;
         std::vector<tqp_flags_out> os;
@@ -198,12 +220,14 @@ int launch(tqp_server* s, Slot& sl) {
             fs.push_back(flags_desc(s, reqs[i].req));
             os.push_back(flags_out(sl.d_res, (int)i));
         }
-        st = tqp::batch_prepare(s->ctx, fs.data(), os.data(), (int)fs.size(), 1 << tqp::BATCH_CONFIG_DEFAULT,
+        st = tqp::batch_prepare(sl.ctx, fs.data(), os.data(), (int)fs.size(), 1 << tqp::BATCH_CONFIG_DEFAULT,
                                 tqp::BATCH_CONFIG_DEFAULT, sl.ws, &bytes, sl.stream, false, &sl.batch);
         if (st == TQP_OK) st = tqp::batch_launch(sl.batch, sl.stream);
     }
+    k_take_errors<<<1, 1, 0, sl.stream>>>(sl.ctx->d_err, &sl.d_res->err);     // also after a failed launch
     if (st != TQP_OK) return st;
-    if (hipMemcpyAsync(sl.h_res, sl.d_res, sizeof(ResultBlock), hipMemcpyDeviceToHost, sl.stream) != hipSuccess ||
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(sl.h_res, sl.d_res, sizeof(ResultBlock), hipMemcpyDeviceToHost, sl.stream) != hipSuccess ||
         hipEventRecord(sl.done, sl.stream) != hipSuccess)
         return TQP_ERR_HIP;
     return TQP_OK;
@@ -225,6 +249,10 @@ void complete(tqp_server* s, Slot& sl, double t_done) {
         r.t_done = t_done;
         r.slot = (int32_t)(&sl - s->slots.data());
         r.batch_size = (int32_t)sl.reqs.size();
+        if (sl.status == TQP_OK && h.err) {
+            r.dev_errors = h.err;
+            r.status = (h.err & TQP_DEVERR_CAPACITY) ? TQP_ERR_CAPACITY : TQP_ERR_INVALID;
+        }
         if (sl.status == TQP_OK) {
             if (p.req.kind == TQP_REQ_CUST) {
                 r.join_rows = h.cjoin;
@@ -327,6 +355,38 @@ void worker_main(tqp_server* s) {
     }
 }
 
+// The mid table sorted by pk once, with its custkeys (the resident order
+// custkey requests join against).  Uses the first slot's context; a key
+// outside key_bits_mid fails the server's creation.
+tqp_status presort_mid(tqp_server* s) {
+    const int64_t m = s->cfg.n_mid;
+    tqp_ctx* c = s->slots[0].ctx;
+    if (hipMalloc(&s->mid_keys, (size_t)m * 8) != hipSuccess) {
+        s->mid_keys = nullptr;
+        return tqp::fail(TQP_ERR_HIP, "tqp_server_create: %lld bytes for the sorted mid table", (long long)m * 8);
+    }
+    s->mid_cust = s->mid_keys + m;
+    size_t bytes = 0;
+    tqp_status st = tqp_sort(c, s->cfg.mid_pk, s->cfg.mid_custkey, m, nullptr, s->cfg.key_bits_mid,
+                             reinterpret_cast<int32_t*>(s->mid_keys), reinterpret_cast<int32_t*>(s->mid_cust),
+                             nullptr, &bytes, nullptr);
+    if (st != TQP_OK) return st;
+    void* ws = nullptr;
+    if (hipMalloc(&ws, bytes > 0 ? bytes : 256) != hipSuccess)
+        return tqp::fail(TQP_ERR_HIP, "tqp_server_create: %zu bytes of sort workspace", bytes);
+    hipStream_t stream = nullptr;      // the slots' streams do not exist yet
+    st = tqp_sort(c, s->cfg.mid_pk, s->cfg.mid_custkey, m, nullptr, s->cfg.key_bits_mid,
+                  reinterpret_cast<int32_t*>(s->mid_keys), reinterpret_cast<int32_t*>(s->mid_cust), ws, &bytes,
+                  stream);
+    uint32_t err = 0;
+    const tqp_status es = tqp_ctx_errors(c, stream, &err, 1);
+    (void)hipFree(ws);
+    if (st != TQP_OK) return st;
+    if (es != TQP_OK) return es;
+    if (err) return tqp::fail(TQP_ERR_INVALID, "tqp_server_create: sorting the mid table raised device errors %#x", err);
+    return TQP_OK;
+}
+
 }  // namespace
 
 using namespace tqp;
@@ -341,11 +401,29 @@ tqp_status tqp_server_create(tqp_ctx* ctx, const tqp_server_config* cfg, tqp_ser
     if (cfg->n_fact < 1 || cfg->n_mid < 1 || cfg->n_dim < 1 || cfg->max_flags_rows < 1 ||
         cfg->max_flags_rows > cfg->n_fact)
         return fail(TQP_ERR_INVALID, "tqp_server_create: table sizes");
+    if (cfg->revenue_bits != 0 && cfg->revenue_bits != 32 && cfg->revenue_bits != 64)
+        return fail(TQP_ERR_UNSUPPORTED, "tqp_server_create: revenue_bits = %d (0, 32 or 64)", cfg->revenue_bits);
     tqp_server* s = new tqp_server;
     s->ctx = ctx;
     s->cfg = *cfg;
     s->t0 = Clock::now();
     s->gcap = std::min<int64_t>(cfg->n_fact, int64_t(1) << norm_key_bits(cfg->cust_bits));
+    s->slots.resize(cfg->slots);
+    for (auto& sl : s->slots) {
+        tqp_status cs = tqp_ctx_create(ctx->device, &sl.ctx);
+        if (cs != TQP_OK) {
+            tqp_server_destroy(s);
+            return cs;
+        }
+        sl.ctx->digit_bits = ctx->digit_bits;
+    }
+    if (cfg->presort_mid) {
+        tqp_status ps = presort_mid(s);
+        if (ps != TQP_OK) {
+            tqp_server_destroy(s);
+            return ps;
+        }
+    }
     // Workspace of each kind of launch, from the library's own size queries.
     tqp_request rc{};
     rc.kind = TQP_REQ_CUST;
@@ -361,7 +439,7 @@ tqp_status tqp_server_create(tqp_ctx* ctx, const tqp_server_config* cfg, tqp_ser
     tqp_cust_out co = cust_out(s, probe);
     size_t cb = 0;
     tqp_status st = tqp_fragment_cust(ctx, &cf, &co, nullptr, &cb, nullptr);
-    if (st != TQP_OK) { delete s; return st; }
+    if (st != TQP_OK) { tqp_server_destroy(s); return st; }
     s->cust_ws = cb;
     std::vector<Pending> big((size_t)cfg->max_batch);
     for (auto& p : big) {
@@ -372,20 +450,23 @@ tqp_status tqp_server_create(tqp_ctx* ctx, const tqp_server_config* cfg, tqp_ser
     size_t fb = launch_bytes(s, big, probe);
     std::vector<Pending> one(big.begin(), big.begin() + 1);
     const size_t f1 = launch_bytes(s, one, probe);
-    if (fb == 0 || f1 == 0) { delete s; return fail(TQP_ERR_INVALID, "tqp_server_create: flags size query failed"); }
+    if (fb == 0 || f1 == 0) {
+        tqp_server_destroy(s);
+        return fail(TQP_ERR_INVALID, "tqp_server_create: flags size query failed");
+    }
     const size_t ws = Arena::align(std::max(cb, std::max(fb, f1)));
     const size_t gbytes = Arena::align((size_t)s->gcap * 4) + 2 * Arena::align((size_t)s->gcap * 8);
     const size_t per_slot = ws + gbytes + Arena::align(sizeof(ResultBlock));
     if (hipMalloc(&s->dev_block, per_slot * cfg->slots) != hipSuccess) {
-        delete s;
+        s->dev_block = nullptr;
+        tqp_server_destroy(s);
         return fail(TQP_ERR_HIP, "tqp_server_create: %zu bytes of slot memory", per_slot * cfg->slots);
     }
     if (hipHostMalloc(&s->host_block, sizeof(ResultBlock) * cfg->slots) != hipSuccess) {
-        (void)hipFree(s->dev_block);
-        delete s;
+        s->host_block = nullptr;
+        tqp_server_destroy(s);
         return fail(TQP_ERR_HIP, "tqp_server_create: pinned result memory");
     }
-    s->slots.resize(cfg->slots);
     for (int i = 0; i < cfg->slots; ++i) {
         Slot& sl = s->slots[i];
         char* p = static_cast<char*>(s->dev_block) + per_slot * i;
@@ -426,7 +507,9 @@ void tqp_server_destroy(tqp_server* s) {
         if (sl.batch) tqp::batch_free(sl.batch);
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        if (sl.ctx) tqp_ctx_destroy(sl.ctx);
     }
+    if (s->mid_keys) (void)hipFree(s->mid_keys);
     if (s->dev_block) (void)hipFree(s->dev_block);
     if (s->host_block) (void)hipHostFree(s->host_block);
     delete s;

@@ -82,6 +82,36 @@ def test_flags_row_range(hip, ctx):
     _assert_flags(r.result(), oracle.fragment_flags(sub, fr.dim, fr.D, fr.c))
 
 
+def test_flags_out_of_domain(hip, ctx):
+    """flagA outside 0..2 or flagB outside 0..1: the row is left out of every
+    group and the value-range flag is set, alone and in a batch; the other
+    rows aggregate exactly as the oracle does without the bad rows."""
+    fr = datagen.random_flags_fragment(110, 50_000, 2000, 2000)
+    fa, fb = fr.fact["flagA"].copy(), fr.fact["flagB"].copy()
+    fa[::501] = 3
+    fb[7::703] = 2
+    fb[11::907] = -1
+    bad = (fa > 2) | (fb > 1) | (fb < 0)
+    fact = dict(fr.fact, flagA=fa, flagB=fb)
+    want_all = oracle.fragment_flags(fact, fr.dim, fr.D, fr.c)
+    want = oracle.fragment_flags({k: v[~bad] for k, v in fact.items()}, fr.dim, fr.D, fr.c)
+    assert want_all["join_rows"] > want["join_rows"]         # some bad rows pass the filter and join
+    ctx.errors()
+    got = _flags(hip, ctx, dataclasses.replace(fr, fact=fact))[0]
+    assert ctx.errors() == hip.DEVERR_VALUE_RANGE
+    assert got["join_rows"] == want_all["join_rows"]
+    assert np.array_equal(got["key"], want["key"])
+    assert np.array_equal(got["sum"], want["sum"]) and np.array_equal(got["cnt"], want["cnt"])
+    assert np.array_equal(got["avg"].view(np.int64), want["avg"].view(np.int64))
+    b = hip.BatchRunner(ctx, [{"fact": hip.to_device(fact), "dim": hip.to_device(fr.dim), "D": fr.D, "c": fr.c,
+                               "key_bits": fr.key_bits}])
+    b.run()
+    got_b = b.results()[0]
+    b.close()
+    assert ctx.errors() == hip.DEVERR_VALUE_RANGE
+    assert np.array_equal(got_b["sum"], want["sum"]) and np.array_equal(got_b["cnt"], want["cnt"])
+
+
 def _cust(hip, ctx, fr, digit_bits=8, cust_bits=None, join_cap=None, revenue_bits=0):
     fact = hip.to_device({k: fr.fact[k] for k in ("fk", "date", "price", "disc")})
     mid = hip.to_device(fr.mid)

@@ -601,6 +601,20 @@ def test_hash_groupby_distinct_skewed(hip, ctx):
     _hash_groupby_case(hip, ctx, keys, val, dval, gcap=100_000)
 
 
+@pytest.mark.parametrize("groups", [1, 6, 64])
+def test_hash_groupby_distinct_set_overflow(hip, ctx, groups):
+    """At most 64 groups with about a million distinct values: every block's
+    LDS pair set fills, so most pairs take the global-set fallback after a
+    full probe run; about a third of the rows repeat a value already drawn.
+    No pair may be counted twice or lost."""
+    rng = _rng(1000 + groups)
+    n = 1_000_003
+    keys = rng.integers(0, groups, n).astype(np.int32)
+    val = rng.integers(-1000, 1000, n).astype(np.int64)
+    dval = rng.integers(0, 1_000_000, n).astype(np.int32)
+    _hash_groupby_case(hip, ctx, keys, val, dval, gcap=64)
+
+
 @pytest.mark.parametrize("domain,gcap", [(3000, 4000), (30_000, 50_000)])
 def test_hash_groupby_count_only(hip, ctx, domain, gcap):
     """COUNT(*) and COUNT(DISTINCT) with no value column at all: a per-block LDS table (gcap 4000)
@@ -648,8 +662,6 @@ def test_topk_parity(hip, ctx, n, k, dist):
     threshold, so the chunk levels and the final merge rounds all run);
     negative and positive sums; sums growing with the key (the strided
     sample still bounds the threshold)."""
-    if dist != "random" and n > 300_000:
-        pytest.skip("the large case runs with the random distribution only")
     rng = _rng(n + k)
     key = rng.permutation(max(1, 2 * n))[:n].astype(np.int32)       # unique keys
     if dist == "random":

@@ -35,7 +35,7 @@ def _want(t, r):
 
 
 def _check(got, want, kind):
-    assert got["status"] == 0
+    assert got["status"] == 0 and got["dev_errors"] == 0
     assert got["join_rows"] == want["join_rows"]
     if kind == "cust":
         assert got["groups"] == want["groups"]
@@ -59,11 +59,14 @@ def _run(hip, dev, reqs, **kw):
     return out, stats
 
 
-def test_mix_equals_oracle_and_alone(hip, resident):
+@pytest.mark.parametrize("presort,revenue_bits", [(False, 0), (True, 32), (True, 64)])
+def test_mix_equals_oracle_and_alone(hip, resident, presort, revenue_bits):
+    """The mix, with the mid table sorted per request or once at start-up, and the revenue carried in
+    64 or 32 bits, equals the oracle and the serial server's results."""
     t, dev = resident
     reqs = _requests(len(t["fact"]["fk"]), 48, seed=5)
     wants = [_want(t, r) for r in reqs]
-    mixed, stats = _run(hip, dev, reqs, slots=4, max_batch=8)
+    mixed, stats = _run(hip, dev, reqs, slots=4, max_batch=8, presort_mid=presort, revenue_bits=revenue_bits)
     assert stats["finished"] == len(reqs) and stats["launches"] <= len(reqs)
     assert max(r["batch_size"] for r in mixed.values()) > 1        # some flags requests ran batched
     serial, _ = _run(hip, dev, reqs, slots=1, max_batch=1)
@@ -93,3 +96,25 @@ def test_request_larger_than_budget_is_rejected(hip, resident):
     res = srv.poll()
     srv.close()
     assert len(res) == 1 and res[0]["status"] == 3     # TQP_ERR_CAPACITY
+
+
+def test_errors_come_back_with_their_request(hip, resident):
+    """A server whose declared custkey width is too small: every custkey request comes back with the
+    key-range bit and a non-OK status, while the flags requests served beside them (other slots,
+    other launches) come back clean and exact."""
+    t, dev = resident
+    reqs = _requests(len(t["fact"]["fk"]), 24, seed=8)
+    assert {r["kind"] for r in reqs} == {"cust", "flags"}
+    srv = hip.Server(dev, key_bits_mid=20, key_bits_dim=15, cust_bits=8, max_flags_rows=400_000, slots=4,
+                     max_batch=1)
+    for i, r in enumerate(reqs):
+        srv.submit(0 if r["kind"] == "cust" else 1, r["D"], c=r["c"], k=100, row0=r["start"], n_rows=r["len"],
+                   tag=i)
+    srv.drain()
+    out = {r["tag"]: r for r in srv.poll()}
+    srv.close()
+    for i, r in enumerate(reqs):
+        if r["kind"] == "cust":
+            assert out[i]["status"] != 0 and out[i]["dev_errors"] & hip.DEVERR_KEY_RANGE
+        else:
+            _check(out[i], _want(t, r), "flags")
