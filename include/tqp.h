@@ -133,6 +133,25 @@ tqp_status tqp_filter(tqp_ctx* ctx, const tqp_column* cols, int ncols, int64_t n
                       int32_t* out_rowid, int32_t* out_carry, int64_t cap, int64_t* d_count,
                       void* ws, size_t* ws_bytes, hipStream_t stream);
 
+/* The filter above without allocation or workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, semantics and results
+ * as tqp_filter, minus (ws, ws_bytes).  Its scratch (a tile counter and one
+ * look-back word per 4096 rows) is a fixed device array of
+ * TQP_NOALLOC_SCRATCH_BYTES per device, held until the process ends, so n is
+ * limited to TQP_FILTER_NOALLOC_MAX_ROWS (TQP_ERR_UNSUPPORTED above; checked
+ * before anything is launched).  The array's address is looked up when a
+ * context is created on the device.  Every call clears the part it uses with
+ * a kernel (no memset).  All calls on one device share the one array: calls
+ * that overlap in time on the same device (other streams, other host
+ * threads) race and give wrong results; serialise them. */
+#define TQP_NOALLOC_SCRATCH_BYTES 1048576
+#define TQP_FILTER_NOALLOC_MAX_ROWS 536739840LL   /* (1 MiB - 256 B) / 8 B per tile x 4096 rows per tile */
+tqp_status tqp_filter_noalloc(tqp_ctx* ctx, const tqp_column* cols, int ncols, int64_t n,
+                              const tqp_pred* preds, int npreds, const int32_t* carry,
+                              int32_t* out_rowid, int32_t* out_carry, int64_t cap, int64_t* d_count,
+                              hipStream_t stream);
+
 /* ---------------------------------------------------------------- sort
  * Algorithm 1 (sort of each join-key column with its index) and Algorithm 2
  * (sort of the group keys): stable ascending LSD radix sort of the pairs

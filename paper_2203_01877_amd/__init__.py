@@ -32,7 +32,7 @@ from . import _lib
 from ._lib import (DEVERR_CAPACITY, DEVERR_KEY_RANGE, DEVERR_SPIN, DEVERR_VALUE_RANGE, JOIN_INNER, JOIN_LEFT_ANTI,
                    JOIN_LEFT_OUTER, JOIN_LEFT_SEMI, TQP_EQ, TQP_GE, TQP_GT, TQP_LE, TQP_LT, TQP_NE, TQPError, check)
 
-__all__ = ["Context", "filter", "sort", "join", "hash_join", "join_band", "pack_keys", "eval_expr", "gather", "join_chain", "groupby_agg",
+__all__ = ["Context", "filter", "filter_noalloc", "sort", "join", "hash_join", "join_band", "pack_keys", "eval_expr", "gather", "join_chain", "groupby_agg",
            "hash_groupby", "topk", "FlagsFragmentRunner",
            "CustFragmentRunner", "BatchRunner", "Server", "TQPError", "TQP_LT", "TQP_LE", "TQP_GT", "TQP_GE", "TQP_EQ", "TQP_NE",
            "DEVERR_KEY_RANGE", "DEVERR_SPIN", "DEVERR_CAPACITY", "DEVERR_VALUE_RANGE", "JOIN_INNER", "JOIN_LEFT_SEMI",
@@ -128,6 +128,17 @@ def filter(ctx: Context, cols: list, preds: list, carry=None, cap: int | None = 
     _run(lambda ws, sz: ctx.lib.tqp_filter(ctx.h, carr, len(cols), n, parr, len(preds), _p(carry), _p(out),
                                            _p(outc), cap, _p(cnt), ws, sz, s), "tqp_filter", dev)
     return out, outc, cnt
+
+
+def filter_noalloc(ctx: Context, cols: list, preds: list, out, cnt, carry=None, out_carry=None, n: int | None = None,
+                   stream=None):
+    """tqp_filter_noalloc: the filter into caller-given outputs (out: int32 device tensor, its length is
+    the capacity; cnt: one int64), with no workspace and no allocation.  n defaults to the column length."""
+    n = (cols[0].numel() if cols else 0) if n is None else n
+    carr = (_lib.Column * max(1, len(cols)))(*[_lib.Column(c.data_ptr(), _DTYPES[c.dtype], 0) for c in cols])
+    parr = (_lib.Pred * max(1, len(preds)))(*[_lib.Pred(p[0], p[1], p[2]) for p in preds])
+    check(ctx.lib.tqp_filter_noalloc(ctx.h, carr, len(cols), n, parr, len(preds), _p(carry), _p(out), _p(out_carry),
+                                     out.numel(), _p(cnt), _stream(stream)), "tqp_filter_noalloc")
 
 
 def sort(ctx: Context, keys, vals=None, key_bits: int = 0, perm: bool = False, d_n=None, stream=None):

@@ -61,6 +61,7 @@ class CustOut(ctypes.Structure):
 
 
 TOPK_MAX = 128
+FILTER_NOALLOC_MAX_ROWS = 536_739_840     # TQP_FILTER_NOALLOC_MAX_ROWS
 REQ_CUST, REQ_FLAGS = 0, 1
 
 
@@ -119,6 +120,9 @@ def load() -> ctypes.CDLL:
     lib.tqp_filter.argtypes = [c_vp, ctypes.POINTER(Column), c_int, c_i64, ctypes.POINTER(Pred), c_int, c_vp,
                                c_vp, c_vp, c_i64, c_vp, c_vp, c_size_p, c_vp]
     lib.tqp_filter.restype = S
+    lib.tqp_filter_noalloc.argtypes = [c_vp, ctypes.POINTER(Column), c_int, c_i64, ctypes.POINTER(Pred), c_int,
+                                       c_vp, c_vp, c_vp, c_i64, c_vp, c_vp]
+    lib.tqp_filter_noalloc.restype = S
     lib.tqp_sort.argtypes = [c_vp, c_vp, c_vp, c_i64, c_vp, c_int, c_vp, c_vp, c_vp, c_size_p, c_vp]
     lib.tqp_sort.restype = S
     lib.tqp_join.argtypes = [c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_i64, c_vp,

@@ -288,6 +288,7 @@ tqp_status tqp_ctx_create(int device, tqp_ctx** out) {
     TQP_TRY_HIP(hipGetDeviceProperties(&prop, device));
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(TQP_ERR_UNSUPPORTED, "built for gfx950, device is %s", prop.gcnArchName);
+    if (noalloc_setup(device) != TQP_OK) return TQP_ERR_HIP;
     tqp_ctx* c = new tqp_ctx;
     c->device = device;
     c->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;

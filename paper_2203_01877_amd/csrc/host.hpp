@@ -108,6 +108,10 @@ tqp_status with_workspace(tqp_ctx* ctx, void* ws, size_t* ws_bytes, hipStream_t 
 
 tqp_status fill_zero(void* p, size_t bytes, hipStream_t stream, tqp_ctx* ctx = nullptr);
 
+// Looks up this device's scratch array of tqp_filter_noalloc (the device must
+// be current); done once per device, from tqp_ctx_create.
+tqp_status noalloc_setup(int device);
+
 // Fork: work launched on ctx->side after this call starts after everything
 // already queued on s.  Join: s waits for everything queued on ctx->side.
 inline tqp_status side_fork(tqp_ctx* ctx, hipStream_t s) {
