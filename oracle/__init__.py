@@ -70,6 +70,11 @@ def _L():
         lib.orc_fragment_cust.argtypes = [vp, vp, vp, vp, i64, vp, vp, i64, i32, vp, vp, vp, i64,
                                           i32, vp, vp, vp, vp, vp]
         lib.orc_fragment_cust.restype = i64
+        lib.orc_fragment_general.argtypes = [ctypes.c_int, vp, vp, i64, ctypes.c_int, vp, vp, i64, vp, vp,
+                                             ctypes.c_int, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_int, vp, vp, ctypes.c_int, vp, vp, vp, vp, vp, vp, i64, i32,
+                                             vp, vp, vp, vp, vp]
+        lib.orc_fragment_general.restype = i64
         lib.orc_overflow_flag.restype = ctypes.c_int
         lib.orc_clear_overflow.restype = None
         _lib = lib
@@ -279,3 +284,60 @@ def fragment_cust(fact: dict, mid: dict, D: int, k: int = 100, gcap: int | None 
     return {"key": key[:w].copy(), "sum": s[:w].copy(), "cnt": cn[:w].copy(), "groups": int(G),
             "top_key": tk[:kk].copy(), "top_sum": ts[:kk].copy(), "top_cnt": tc[:kk].copy(),
             "join_rows": int(J[0])}
+
+
+AGG_COUNT, AGG_SUM, AGG_MIN, AGG_MAX, AGG_AVG, AGG_COUNT_DISTINCT = range(6)
+
+
+def fragment_general(fact: list, dim: list | None, fpred: list, dpred: list, fkey: int, dkey: int, group: list,
+                     aggs: list, topk: int = 0, gcap: int | None = None) -> dict:
+    """A general fragment by its definition: the fact rows whose predicate program is nonzero, joined on
+    fact column fkey = dim column dkey to the dim rows whose predicate is nonzero (no join when dim is
+    None or fkey < 0), grouped by the packed columns group = [(joined column, bits)], with aggregates
+    aggs = [(op, program)] (op AGG_*; the program over the joined row's columns, fact first, is
+    ignored for AGG_COUNT).  Returns keys ascending, one array per aggregate (float64 for AVG), the
+    group and joined-row counts, the count of group values outside their width, and the first topk
+    groups by (aggregate 0 desc, key asc)."""
+    join = dim is not None and fkey >= 0
+    fc = [np.ascontiguousarray(c) for c in fact]
+    dc = [np.ascontiguousarray(c) for c in (dim or [])] if join else []
+    n_fact = len(fc[0]) if fc else 0
+    n_dim = len(dc[0]) if dc else 0
+    fptr = (ctypes.c_void_p * max(1, len(fc)))(*[c.ctypes.data for c in fc])
+    dptr = (ctypes.c_void_p * max(1, len(dc)))(*[c.ctypes.data for c in dc])
+    ftyp = np.array([_TYPES[c.dtype] for c in fc] or [0], np.int32)
+    dtyp = np.array([_TYPES[c.dtype] for c in dc] or [0], np.int32)
+    prog = lambda p: (np.array([x[0] for x in p] or [0], np.int32), np.array([x[1] for x in p] or [0], np.int64))
+    fo, fa = prog(fpred)
+    do, da = prog(dpred if join else [])
+    gcol = np.array([g[0] for g in group] or [0], np.int32)
+    gbits = np.array([g[1] for g in group] or [0], np.int32)
+    aop = np.array([a[0] for a in aggs] or [0], np.int32)
+    alen = np.array([0 if a[0] == AGG_COUNT else len(a[1]) for a in aggs] or [0], np.int32)
+    flat = [x for a in aggs if a[0] != AGG_COUNT for x in a[1]]
+    ao, aa = prog(flat)
+    if gcap is None:
+        gcap = max(1, n_fact * max(1, n_dim) if join else n_fact)
+        gcap = min(gcap, 1 << 22)
+    key = np.empty(gcap, np.int32)
+    vals = np.empty((max(1, len(aggs)), gcap), np.int64)
+    tk, tv = np.empty(max(1, topk), np.int32), np.empty(max(1, topk), np.int64)
+    kout, J, bad = np.zeros(1, np.int32), np.zeros(1, np.int64), np.zeros(1, np.int64)
+    G = _L().orc_fragment_general(len(fc), ctypes.cast(fptr, ctypes.c_void_p), ftyp.ctypes.data, n_fact, len(dc),
+                                  ctypes.cast(dptr, ctypes.c_void_p), dtyp.ctypes.data, n_dim, fo.ctypes.data,
+                                  fa.ctypes.data, len(fpred), do.ctypes.data, da.ctypes.data,
+                                  len(dpred) if join else 0, fkey if join else -1, dkey, len(group), gcol.ctypes.data,
+                                  gbits.ctypes.data, len(aggs), aop.ctypes.data, alen.ctypes.data, ao.ctypes.data,
+                                  aa.ctypes.data, key.ctypes.data, vals.ctypes.data, gcap, topk, tk.ctypes.data,
+                                  tv.ctypes.data, kout.ctypes.data, J.ctypes.data, bad.ctypes.data)
+    if G < 0:
+        raise ValueError("malformed program")
+    _check_overflow()
+    w = min(G, gcap)
+    out_vals = []
+    for a, (op, _) in enumerate(aggs):
+        v = vals[a, :w].copy()
+        out_vals.append(v.view(np.float64) if op == AGG_AVG else v)
+    kk = int(kout[0])
+    return {"key": key[:w].copy(), "vals": out_vals, "groups": int(G), "join_rows": int(J[0]), "bad": int(bad[0]),
+            "top_key": tk[:kk].copy(), "top_val": tv[:kk].copy()}

@@ -35,6 +35,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <map>
 #include <numeric>
 #include <set>
@@ -214,14 +215,14 @@ int64_t x_eval(const std::vector<XNode>& t, int at, const int64_t* const* cols, 
 }
 }  // namespace
 
-int64_t orc_eval(const int64_t* const* cols, int ncols, int64_t n, const int32_t* ops,
-                 const int64_t* args, int nprog, int64_t* out) {
-    std::vector<XNode> tree;
+namespace {
+// The tree of a postfix program over ncols columns; false if malformed.
+bool x_build(const int32_t* ops, const int64_t* args, int nprog, int ncols, std::vector<XNode>& tree, int& root) {
     std::vector<int> stack;
     for (int pc = 0; pc < nprog; ++pc) {
         const int ar = x_arity(ops[pc]);
-        if (ar < 0 || static_cast<int>(stack.size()) < ar) return -1;
-        if (ops[pc] == 0 && (args[pc] < 0 || args[pc] >= ncols)) return -1;
+        if (ar < 0 || static_cast<int>(stack.size()) < ar) return false;
+        if (ops[pc] == 0 && (args[pc] < 0 || args[pc] >= ncols)) return false;
         XNode nd{ops[pc], args[pc], {-1, -1, -1}};
         for (int i = ar - 1; i >= 0; --i) {
             nd.kid[i] = stack.back();
@@ -230,9 +231,19 @@ int64_t orc_eval(const int64_t* const* cols, int ncols, int64_t n, const int32_t
         tree.push_back(nd);
         stack.push_back(static_cast<int>(tree.size()) - 1);
     }
-    if (stack.size() != 1) return -1;
+    if (stack.size() != 1) return false;
+    root = stack[0];
+    return true;
+}
+}  // namespace
+
+int64_t orc_eval(const int64_t* const* cols, int ncols, int64_t n, const int32_t* ops,
+                 const int64_t* args, int nprog, int64_t* out) {
+    std::vector<XNode> tree;
+    int root = 0;
+    if (!x_build(ops, args, nprog, ncols, tree, root)) return -1;
     int64_t zdiv = 0;
-    for (int64_t r = 0; r < n; ++r) out[r] = x_eval(tree, stack[0], cols, r, zdiv);
+    for (int64_t r = 0; r < n; ++r) out[r] = x_eval(tree, root, cols, r, zdiv);
     return zdiv;
 }
 
@@ -490,6 +501,162 @@ int64_t orc_fragment_cust(const int32_t* fk, const int32_t* date, const int64_t*
     }
     *out_k = static_cast<int32_t>(kk);
     return G;
+}
+
+// A general query fragment (the operators of Section 5 composed: filters,
+// an equi-join, a group-by over several columns and a list of aggregates,
+// ORDER BY ... LIMIT k), by its relational definition:
+//
+//   SELECT pack(g_1, ..., g_q), agg_1, ..., agg_m
+//   FROM fact [JOIN dim ON fact.col[fkey] = dim.col[dkey]]
+//   WHERE fpred(fact row) [AND dpred(dim row)]
+//   GROUP BY pack(g_1, ..., g_q) ORDER BY the packed key
+//   [then, separately, ORDER BY agg_1 DESC, key ASC LIMIT topk]
+//
+// Columns are int8 / int32 / int64 (types 1 / 2 / 3), widened to int64.  A
+// joined row numbers the fact columns 0..nf-1 and the dim columns nf..nf+nd-1
+// (without a join, fkey < 0: the kept fact rows, fact columns only).
+// Predicates and aggregate values are postfix programs (the operator codes of
+// orc_eval) over the row's columns; an empty predicate keeps every row, a row
+// is kept when the predicate is nonzero.  The group key packs the columns
+// gcol[0..q-1] (joined numbering), column i taking gbits[i] bits, the first
+// most significant (a value outside [0, 2^bits) enters masked and is counted
+// in *out_bad); q = 0 puts every row in group 0.  Aggregates: 0 COUNT(*), 1
+// SUM(v), 2 MIN(v), 3 MAX(v), 4 AVG(v) = (double)SUM / (double)COUNT, 5
+// COUNT(DISTINCT v).  Output per group, keys ascending: out_key[g] and
+// out_vals[a * gcap + g] (int64, or the bits of the double for AVG).  At most
+// gcap groups written; returns the number of groups (-1: malformed
+// program).  topk > 0: the first topk groups in the order (agg_1 desc, key
+// asc) go to top_key / top_val, *out_k = their number.  *out_join = the
+// number of joined rows (rows of the join that pass both predicates).
+int64_t orc_fragment_general(int nf, const void* const* fcols, const int32_t* ftypes, int64_t n_fact, int nd,
+                             const void* const* dcols, const int32_t* dtypes, int64_t n_dim,
+                             const int32_t* fp_ops, const int64_t* fp_args, int n_fp, const int32_t* dp_ops,
+                             const int64_t* dp_args, int n_dp, int fkey, int dkey, int ngroup, const int32_t* gcol,
+                             const int32_t* gbits, int nagg, const int32_t* agg_op, const int32_t* agg_len,
+                             const int32_t* agg_ops, const int64_t* agg_args, int32_t* out_key, int64_t* out_vals,
+                             int64_t gcap, int32_t topk, int32_t* top_key, int64_t* top_val, int32_t* out_k,
+                             int64_t* out_join, int64_t* out_bad) {
+    const bool join = fkey >= 0;
+    const int ncol = nf + (join ? nd : 0);
+    // the programs as trees
+    std::vector<XNode> fpt, dpt;
+    int fpr = 0, dpr = 0;
+    if (n_fp > 0 && !x_build(fp_ops, fp_args, n_fp, nf, fpt, fpr)) return -1;
+    if (join && n_dp > 0 && !x_build(dp_ops, dp_args, n_dp, nd, dpt, dpr)) return -1;
+    std::vector<std::vector<XNode>> at(static_cast<size_t>(nagg));
+    std::vector<int> ar(static_cast<size_t>(nagg), 0);
+    int off = 0;
+    for (int a = 0; a < nagg; ++a) {
+        if (agg_op[a] != 0 && !x_build(agg_ops + off, agg_args + off, agg_len[a], ncol, at[a], ar[a])) return -1;
+        off += agg_len[a];
+    }
+    // one row's columns as int64 values; the programs read cols[c][0]
+    std::vector<int64_t> val(static_cast<size_t>(ncol > 0 ? ncol : 1));
+    std::vector<const int64_t*> cp(val.size());
+    for (size_t c = 0; c < val.size(); ++c) cp[c] = &val[c];
+    int64_t zdiv = 0;
+    // build side: the dim rows that pass their predicate, by key
+    std::unordered_multimap<int64_t, int64_t> dim;
+    if (join) {
+        for (int64_t d = 0; d < n_dim; ++d) {
+            for (int c = 0; c < nd; ++c) val[static_cast<size_t>(nf + c)] = load_value(dcols[c], dtypes[c], d);
+            if (n_dp > 0) {
+                // the dim predicate reads the dim columns as its columns 0..nd-1
+                if (x_eval(dpt, dpr, cp.data() + nf, 0, zdiv) == 0) continue;
+            }
+            dim.emplace(load_value(dcols[dkey], dtypes[dkey], d), d);
+        }
+    }
+    struct G {
+        int64_t cnt = 0;
+        std::vector<int64_t> sum, mn, mx;
+        std::vector<std::set<int64_t>> dist;
+    };
+    std::map<int32_t, G> groups;
+    int64_t joined = 0, bad = 0;
+    auto emit = [&]() {
+        int64_t key = 0;
+        for (int i = 0; i < ngroup; ++i) {
+            const int64_t x = val[static_cast<size_t>(gcol[i])];
+            const int64_t lim = int64_t(1) << gbits[i];
+            if (x < 0 || x >= lim) ++bad;
+            key = key * lim + (x & (lim - 1));
+        }
+        G& g = groups[static_cast<int32_t>(key)];
+        if (g.sum.empty()) {
+            g.sum.assign(static_cast<size_t>(nagg), 0);
+            g.mn.assign(static_cast<size_t>(nagg), INT64_MAX);
+            g.mx.assign(static_cast<size_t>(nagg), INT64_MIN);
+            g.dist.resize(static_cast<size_t>(nagg));
+        }
+        g.cnt += 1;
+        for (int a = 0; a < nagg; ++a) {
+            if (agg_op[a] == 0) continue;
+            const int64_t v = x_eval(at[a], ar[a], cp.data(), 0, zdiv);
+            const size_t i = static_cast<size_t>(a);
+            g.sum[i] = add_checked(g.sum[i], v);
+            g.mn[i] = std::min(g.mn[i], v);
+            g.mx[i] = std::max(g.mx[i], v);
+            if (agg_op[a] == 5) g.dist[i].insert(v);
+        }
+        ++joined;
+    };
+    // probe side: the fact rows that pass their predicate
+    for (int64_t f = 0; f < n_fact; ++f) {
+        for (int c = 0; c < nf; ++c) val[static_cast<size_t>(c)] = load_value(fcols[c], ftypes[c], f);
+        if (n_fp > 0 && x_eval(fpt, fpr, cp.data(), 0, zdiv) == 0) continue;
+        if (!join) {
+            emit();
+            continue;
+        }
+        auto range = dim.equal_range(val[static_cast<size_t>(fkey)]);
+        for (auto it = range.first; it != range.second; ++it) {
+            for (int c = 0; c < nd; ++c) val[static_cast<size_t>(nf + c)] = load_value(dcols[c], dtypes[c], it->second);
+            emit();
+        }
+    }
+    if (out_join) *out_join = joined;
+    if (out_bad) *out_bad = bad;
+    auto result = [&](const G& g, int a) -> int64_t {
+        const size_t i = static_cast<size_t>(a);
+        switch (agg_op[a]) {
+            case 0: return g.cnt;
+            case 1: return g.sum[i];
+            case 2: return g.mn[i];
+            case 3: return g.mx[i];
+            case 4: {
+                const double d = static_cast<double>(g.sum[i]) / static_cast<double>(g.cnt);
+                int64_t bits;
+                std::memcpy(&bits, &d, sizeof bits);
+                return bits;
+            }
+            default: return static_cast<int64_t>(g.dist[i].size());
+        }
+    };
+    std::vector<std::pair<int32_t, int64_t>> order;     // (key, agg_1) for the top rows
+    int64_t w = 0;
+    for (const auto& kv : groups) {
+        if (w < gcap) {
+            out_key[w] = kv.first;
+            for (int a = 0; a < nagg; ++a) out_vals[a * gcap + w] = result(kv.second, a);
+        }
+        if (topk > 0 && nagg > 0) order.emplace_back(kv.first, result(kv.second, 0));
+        ++w;
+    }
+    if (topk > 0) {
+        std::sort(order.begin(), order.end(), [](const std::pair<int32_t, int64_t>& x, const std::pair<int32_t, int64_t>& y) {
+            if (x.second != y.second) return x.second > y.second;
+            return x.first < y.first;
+        });
+        const int64_t kk = std::min<int64_t>(topk, static_cast<int64_t>(order.size()));
+        for (int64_t i = 0; i < kk; ++i) {
+            top_key[i] = order[static_cast<size_t>(i)].first;
+            top_val[i] = order[static_cast<size_t>(i)].second;
+        }
+        *out_k = static_cast<int32_t>(kk);
+    }
+    return w;
 }
 
 }  // extern "C"

@@ -479,6 +479,146 @@ def check_topk_ties():
     assert got["top_key"].tolist() == [1, 4, 7] and got["top_sum"].tolist() == [10000] * 3
 
 
+# --------------------------------------------------------------------------- general fragments
+
+def _general_tables(rng, n, m, fk_hi, dup):
+    fact = [rng.integers(0, fk_hi, n).astype(np.int32), rng.integers(-1000, 1000, n).astype(np.int32),
+            rng.integers(-1000, 1000, n).astype(np.int64), rng.integers(0, 4, n).astype(np.int8)]
+    pk = rng.integers(0, fk_hi, m) if dup else rng.permutation(max(m, fk_hi))[:m]
+    dim = [pk.astype(np.int32), rng.integers(0, 4, m).astype(np.int8), rng.integers(-500, 500, m).astype(np.int32)]
+    return fact, dim
+
+
+def brute_general(fact, dim, fpred, dpred, fkey, dkey, group, aggs, topk):
+    """Every fact x dim pair compared directly (numpy evaluators of the programs), groups in a dict,
+    aggregates in Python integers; AVG by Python's correctly rounded integer division."""
+    n = len(fact[0])
+    keep_f = fpred(fact) != 0 if fpred else np.ones(n, bool)
+    if dim is not None:
+        keep_d = dpred(dim) != 0 if dpred else np.ones(len(dim[0]), bool)
+        eq = (fact[fkey].astype(np.int64)[:, None] == dim[dkey].astype(np.int64)[None, :])
+        eq &= keep_f[:, None] & keep_d[None, :]
+        fi, di = np.nonzero(eq)
+        cols = [c[fi] for c in fact] + [c[di] for c in dim]
+    else:
+        fi = np.flatnonzero(keep_f)
+        cols = [c[fi] for c in fact]
+    J = len(fi)
+    keys = np.zeros(J, np.int64)
+    for col, bits in group:
+        keys = keys * (1 << bits) + (cols[col].astype(np.int64) & ((1 << bits) - 1))
+    vals = [None if op == oracle.AGG_COUNT else ev(cols) for op, ev in aggs] if J else [None] * len(aggs)
+    ref = {}
+    for i in range(J):
+        ref.setdefault(int(keys[i]), []).append(i)
+    out = {}
+    for k, rows in ref.items():
+        res = []
+        for (op, _), v in zip(aggs, vals):
+            if op == oracle.AGG_COUNT:
+                res.append(len(rows))
+                continue
+            xs = [int(v[i]) for i in rows]
+            res.append({oracle.AGG_SUM: sum(xs), oracle.AGG_MIN: min(xs), oracle.AGG_MAX: max(xs),
+                        oracle.AGG_AVG: sum(xs) / len(xs), oracle.AGG_COUNT_DISTINCT: len(set(xs))}[op])
+        out[k] = res
+    top = sorted(out, key=lambda k: (-out[k][0], k))[:topk] if topk and aggs else []
+    return out, J, top
+
+
+def _value_expr(rng, ncols):
+    """An arithmetic value over the columns (a postfix program and its numpy evaluator): a*k + b,
+    a - b, SELECT(a > k, b, c), -a + k or a*b, with random columns a, b, c and a small constant k."""
+    O = oracle
+    a, b, c = (int(x) for x in rng.integers(0, ncols, 3))
+    k = int(rng.integers(-20, 20))
+    i64 = lambda cols, i: cols[i].astype(np.int64)
+    forms = [([(O.X_COL, a), (O.X_CONST, k), (O.X_MUL, 0), (O.X_COL, b), (O.X_ADD, 0)],
+              lambda cols: i64(cols, a) * k + i64(cols, b)),
+             ([(O.X_COL, a), (O.X_COL, b), (O.X_SUB, 0)], lambda cols: i64(cols, a) - i64(cols, b)),
+             ([(O.X_COL, a), (O.X_CONST, k), (O.X_GT, 0), (O.X_COL, b), (O.X_COL, c), (O.X_SELECT, 0)],
+              lambda cols: np.where(i64(cols, a) > k, i64(cols, b), i64(cols, c))),
+             ([(O.X_COL, a), (O.X_NEG, 0), (O.X_CONST, k), (O.X_ADD, 0)], lambda cols: -i64(cols, a) + k),
+             ([(O.X_COL, a), (O.X_COL, b), (O.X_MUL, 0)], lambda cols: i64(cols, a) * i64(cols, b))]
+    return forms[int(rng.integers(0, len(forms)))]
+
+
+def _pred_expr(rng, cols):
+    """A predicate keeping a fair share of rows: a < k, or (a < k1) AND (b >= k2), or (a != k1) OR
+    (b < k2), with thresholds drawn from the columns' own values."""
+    O = oracle
+    a, b = (int(x) for x in rng.integers(0, len(cols), 2))
+    pick = lambda i: int(cols[i][int(rng.integers(0, len(cols[i])))]) if len(cols[i]) else 0
+    k1, k2 = pick(a), pick(b)
+    i64 = lambda cs, i: cs[i].astype(np.int64)
+    forms = [([(O.X_COL, a), (O.X_CONST, k1), (O.X_LT, 0)], lambda cs: (i64(cs, a) < k1).astype(np.int64)),
+             ([(O.X_COL, a), (O.X_CONST, k1), (O.X_LT, 0), (O.X_COL, b), (O.X_CONST, k2), (O.X_GE, 0), (O.X_AND, 0)],
+              lambda cs: ((i64(cs, a) < k1) & (i64(cs, b) >= k2)).astype(np.int64)),
+             ([(O.X_COL, a), (O.X_CONST, k1), (O.X_NE, 0), (O.X_COL, b), (O.X_CONST, k2), (O.X_LT, 0), (O.X_OR, 0)],
+              lambda cs: ((i64(cs, a) != k1) | (i64(cs, b) < k2)).astype(np.int64))]
+    return forms[int(rng.integers(0, len(forms)))]
+
+
+def check_fragment_general():
+    O = oracle
+    rng = _rng(31)
+    for trial in range(30):
+        n, m = int(rng.integers(0, 400)), int(rng.integers(1, 120))
+        fact, dim = _general_tables(rng, n, m, int(rng.integers(1, 150)), trial % 3 == 0)
+        join = trial % 5 != 4
+        nf, nd = len(fact), len(dim)
+        ncol = nf + (nd if join else 0)
+        fp, fev = (_random_expr(rng, nf, 2) if trial % 8 == 1 else _pred_expr(rng, fact)) if trial % 4 else ([], None)
+        dp, dev_ = _pred_expr(rng, dim) if trial % 3 else ([], None)
+        group = [(3, 2), (nf + 1, 2)] if join else [(3, 2)]
+        if trial % 7 == 6:
+            group = []
+        aggs_p, aggs_e = [], []
+        for op in (O.AGG_SUM, O.AGG_COUNT, O.AGG_MIN, O.AGG_MAX, O.AGG_AVG, O.AGG_COUNT_DISTINCT):
+            prog, ev = _random_expr(rng, ncol, 2) if trial % 6 == 5 else _value_expr(rng, ncol)
+            aggs_p.append((op, prog))
+            aggs_e.append((op, ev))
+        topk = int(rng.integers(0, 6))
+        got = O.fragment_general(fact, dim if join else None, fp, dp if join else [], 0, 0, group, aggs_p, topk=topk)
+        ref, J, top = brute_general(fact, dim if join else None, fev, dev_ if join else None, 0, 0, group, aggs_e,
+                                    topk)
+        assert got["join_rows"] == J, ("general join size", trial)
+        assert got["key"].tolist() == sorted(ref), ("general groups", trial)
+        for a in range(len(aggs_p)):
+            want = [ref[k][a] for k in sorted(ref)]
+            assert got["vals"][a].tolist() == want, ("general aggregate", trial, a)
+        assert got["top_key"].tolist() == top, ("general top-k", trial)
+        assert got["top_val"].tolist() == [ref[k][0] for k in top], ("general top-k values", trial)
+    # the flags fragment written as a general one equals the flags fragment (pinned by brute force)
+    fr = datagen.random_flags_fragment(77, 3000, 300, 300, 1500, 2, dup_dim=True)
+    f, d = fr.fact, fr.dim
+    fact = [f["fk"], f["date"], f["price"], f["disc"], f["flagA"], f["flagB"]]
+    dim = [d["pk"], d["seg"]]
+    rev = [(O.X_COL, 2), (O.X_CONST, 100), (O.X_COL, 3), (O.X_SUB, 0), (O.X_MUL, 0)]
+    got = O.fragment_general(fact, dim, [(O.X_COL, 1), (O.X_CONST, fr.D), (O.X_LT, 0)],
+                             [(O.X_COL, 1), (O.X_CONST, fr.c), (O.X_EQ, 0)], 0, 0, [(4, 2), (5, 1)],
+                             [(O.AGG_SUM, rev), (O.AGG_COUNT, []), (O.AGG_AVG, [(O.X_COL, 2)])])
+    want = O.fragment_flags(f, d, fr.D, fr.c)
+    assert got["join_rows"] == want["join_rows"] and np.array_equal(got["key"], want["key"])
+    assert np.array_equal(got["vals"][0], want["sum"]) and np.array_equal(got["vals"][1], want["cnt"])
+    assert np.array_equal(got["vals"][2].view(np.int64), want["avg"].view(np.int64))
+    # no join, no group: one group, COUNT = the kept rows, SUM = their plain sum
+    x = _rng(32).integers(-100, 100, 1000).astype(np.int64)
+    got = O.fragment_general([x], None, [(O.X_COL, 0), (O.X_CONST, 0), (O.X_GT, 0)], [], -1, 0, [],
+                             [(O.AGG_COUNT, []), (O.AGG_SUM, [(O.X_COL, 0)])])
+    assert got["key"].tolist() == [0] and got["vals"][0][0] == int((x > 0).sum())
+    assert got["vals"][1][0] == int(x[x > 0].sum())
+    # group values outside their width are counted; a malformed program is refused
+    got = O.fragment_general([np.array([0, 5, 9], np.int32)], None, [], [], -1, 0, [(0, 3)], [(O.AGG_COUNT, [])])
+    assert got["bad"] == 1 and got["key"].tolist() == [0, 1, 5]
+    try:
+        O.fragment_general([x], None, [(O.X_ADD, 0)], [], -1, 0, [], [(O.AGG_COUNT, [])])
+    except ValueError:
+        pass
+    else:
+        raise AssertionError("malformed predicate accepted")
+
+
 ALL_CHECKS = [check_filter, check_sort, check_join, check_join_kinds, check_join_band, check_pack_keys,
               check_join_chain, check_eval, check_groupby, check_group_minmax, check_fragment_flags,
-              check_fragment_flags_invariants, check_fragment_cust, check_topk_ties]
+              check_fragment_flags_invariants, check_fragment_cust, check_topk_ties, check_fragment_general]

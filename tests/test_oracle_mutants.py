@@ -43,6 +43,13 @@ MUTANTS = [
      "case 3: return wrap(static_cast<uint64_t>(b) - static_cast<uint64_t>(a));"),
     ("expr_div_floor", "            return a / b;", "            return a / b - ((a % b != 0) && ((a < 0) != (b < 0)));"),
     ("cust_uses_fact_key", "Agg& a = groups[custkey[it->second]];", "Agg& a = groups[fk[f]];"),
+    ("general_dim_pred_ignored", "if (x_eval(dpt, dpr, cp.data() + nf, 0, zdiv) == 0) continue;",
+     "if (x_eval(dpt, dpr, cp.data() + nf, 0, zdiv) == 0) {}"),
+    ("general_group_first_column_low", "key = key * lim + (x & (lim - 1));", "key = key + (x & (lim - 1)) * lim;"),
+    ("general_distinct_counts_rows", "if (agg_op[a] == 5) g.dist[i].insert(v);",
+     "if (agg_op[a] == 5) g.dist[i].insert(v + g.cnt);"),
+    ("general_min_starts_at_zero", "g.mn.assign(static_cast<size_t>(nagg), INT64_MAX);",
+     "g.mn.assign(static_cast<size_t>(nagg), 0);"),
     ("mid_first_match_only", "for (auto it = range.first; it != range.second; ++it) {\n            Agg& a = groups[custkey",
      "for (auto it = range.first; it != range.second; it = range.second) {\n            Agg& a = groups[custkey"),
 ]
