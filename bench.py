@@ -476,9 +476,9 @@ def bench_joins(args):
 def bench_hash_vs_sort(args):
     """Hash join against the sort-based join from unsorted inputs (Section 5.3's comparison): n left
     and n right rows, r right rows per key (keys i // r, shuffled), left keys uniform over the same
-    key range, r = 1, 4, 16, 64.  Sort-based = stable sort of both sides (with their permutations)
-    + the sort join; hash-based = tqp_hash_join.  Times from the library's own kernel events; the
-    two join sizes must agree."""
+    key range, r = 1, 2, 4, ..., 64.  Sort-based = stable sort of both sides (with their
+    permutations) + the sort join; hash-based = tqp_hash_join (partitioned).  Times from the library's
+    own kernel events; the two join sizes must agree, and at r = 1 the two sets of pairs too."""
     import numpy as np
     import torch
 
@@ -489,7 +489,7 @@ def bench_hash_vs_sort(args):
     ctx = tqp.Context(0)
     rng = np.random.default_rng(17)
     sweep = []
-    for r in (1, 4, 16, 64):
+    for r in (1, 2, 4, 8, 16, 32, 64):
         dom = max(1, n // r)
         rkey = rng.permutation(np.arange(n, dtype=np.int64) // r).astype(np.int32)
         lkey = rng.integers(0, dom, n).astype(np.int32)
@@ -505,6 +505,19 @@ def bench_hash_vs_sort(args):
 
         def hash_join():
             return tqp.hash_join(ctx, lk, rk, cap=want)[2]
+
+        if r == 1:
+            # the same pairs: (left, right) positions, compared as sorted sets
+            ls, lp = tqp.sort(ctx, lk, key_bits=kb, perm=True)
+            rs, rp = tqp.sort(ctx, rk, key_bits=kb, perm=True)
+            a_l, a_r, _ = tqp.join(ctx, ls, rs, lp, rp, cap=want)
+            b_l, b_r, _ = tqp.hash_join(ctx, lk, rk, cap=want)
+            ka = np.sort(a_l[:want].cpu().numpy().astype(np.int64) * n + a_r[:want].cpu().numpy())
+            kb_ = np.sort(b_l[:want].cpu().numpy().astype(np.int64) * n + b_r[:want].cpu().numpy())
+            if not np.array_equal(ka, kb_):
+                log("r = 1: the hash join's pairs differ from the sort join's")
+                sys.exit(3)
+            del ls, lp, rs, rp, a_l, a_r, b_l, b_r
 
         res = {"rows_per_key": r, "join_rows": want}
         for name, fn in (("sort", sort_join), ("hash", hash_join)):
@@ -531,10 +544,11 @@ def bench_hash_vs_sort(args):
         sweep.append(res)
         del lk, rk
         torch.cuda.empty_cache()
+    faster = [x["rows_per_key"] for x in sweep if x["hash_ms"] < x["sort_ms"]]
     print(json.dumps({"metric": "join ms from unsorted inputs, hash vs sort", "unit": "ms", "n_gpus": 1,
                       "steps": args.steps, "warmup": args.warmup, "higher_is_better": False, "data": "synthetic",
                       "dtype": "int32", "config": {"workload": "%d x %d rows, r right rows per key" % (n, n)},
-                      "sweep": sweep}), flush=True)
+                      "hash_faster_at_rows_per_key": faster, "sweep": sweep}), flush=True)
 
 
 def bench_groupby(args):

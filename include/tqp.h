@@ -187,15 +187,17 @@ tqp_status tqp_join(tqp_ctx* ctx, const int32_t* lkey, const int32_t* lrow, int6
  * Rows in left order, then right order.  Arguments, sizes, sortedness and
  * capacity as tqp_join; out_r may be NULL for the semi and anti joins (it
  * would hold only -1).  An unknown kind returns TQP_ERR_INVALID. */
-/* Section 5.3, Algorithm 3: the hash-based equi-join.  Same rows as
- * tqp_join (every (lrow[i], rrow[j]) with lkey[i] == rkey[j]), but the inputs
- * need not be sorted.  The right rows go into an open-addressing table of m
- * 64-bit slots (m = the power of two at or above 2 * nr; home slot = a
- * multiplicative hash of the key, linear probing; one compare-and-swap per
- * right row), and every left row scans from its home slot to the first free
- * slot twice (count, then write at its offset).  Rows come in left input
- * order; the rows of one left row come in no fixed right order.  Keys are
- * non-negative int32.  Arguments, device counts and capacity as tqp_join. */
+/* Section 5.3, Algorithm 3: the hash-based equi-join, partitioned.  Same
+ * rows as tqp_join (every (lrow[i], rrow[j]) with lkey[i] == rkey[j]), but
+ * the inputs need not be sorted.  Both sides are split into 2^P partitions
+ * (P <= 11, about 1536 right rows each) by the top bits of a multiplicative
+ * hash of the key, one radix pass per side; then every partition is joined
+ * in LDS: a table of its right rows (one slot per distinct key, the rows of a
+ * key stored as one run from a count and a scan, so duplicates cost O(1) per
+ * insert), probed once per left row.  Output rows come in no fixed order; the
+ * set of rows is exact.  A negative key sets TQP_DEVERR_KEY_RANGE and its row
+ * is left out.  Arguments, device counts and capacity as tqp_join (with an
+ * overflow, which cap rows are written is not fixed). */
 tqp_status tqp_hash_join(tqp_ctx* ctx, const int32_t* lkey, const int32_t* lrow, int64_t nl,
                          const int64_t* d_nl, const int32_t* rkey, const int32_t* rrow, int64_t nr,
                          const int64_t* d_nr, int32_t* out_l, int32_t* out_r, int64_t cap,
@@ -266,6 +268,39 @@ tqp_status tqp_eval(tqp_ctx* ctx, const tqp_column* cols, int ncols, int64_t n, 
  * index >= nsrc gives -1 and sets TQP_DEVERR_KEY_RANGE.  No workspace. */
 tqp_status tqp_gather(tqp_ctx* ctx, const void* src, int64_t nsrc, int elem_bytes, const int32_t* idx, int64_t n,
                       const int64_t* d_n, void* out, hipStream_t stream);
+
+/* Chains of equi-joins (a multi-join plan, such as the six-join query of
+ * Section 6.3): table 0's key column key_out joins table 1's key_pk, table
+ * 1's key_out joins table 2's key_pk, and so on.  Each hop sorts the current
+ * tuples' keys, sorts table t's key column (unless its rule says otherwise)
+ * and runs the sort-based join of tqp_join, then reads the earlier row
+ * positions and the next key through the join's output (late
+ * materialisation).  Rules (Section 6.6's hand-optimised plans; asserted by
+ * the caller, not checked): TQP_CHAIN_PK_SORTED, key_pk is already ascending
+ * (its sort is skipped); TQP_CHAIN_PK_DENSE, key_pk is exactly 0..n_rows-1
+ * in row order (no sort and no join: the tuples whose key lies in
+ * [0, n_rows) are kept, the key being the row position; key_pk may be NULL).
+ * Every hop's size stays on the device; the hop into table t writes at most
+ * tables[t].cap tuples (a larger true size sets TQP_DEVERR_CAPACITY and the
+ * later hops work on the written ones).  Output: out_rows[u] (device, at
+ * least tables[ntables-1].cap entries each) receives the final tuples' row
+ * positions in table u, *d_count (device) the final tuple count.  Tuples come
+ * in no fixed order.  2 <= ntables <= TQP_CHAIN_MAX_TABLES; keys are
+ * non-negative int32 below 2^key_bits of their hop (TQP_DEVERR_KEY_RANGE
+ * otherwise). */
+#define TQP_CHAIN_MAX_TABLES 8
+#define TQP_CHAIN_PK_SORTED 1
+#define TQP_CHAIN_PK_DENSE 2
+typedef struct {
+    const int32_t* key_out;   /* n_rows keys into the next table (unused for the last table) */
+    const int32_t* key_pk;    /* n_rows keys joined by the previous table's key_out (unused for table 0) */
+    int64_t n_rows;
+    int64_t cap;              /* tuples the hop into this table may write (unused for table 0) */
+    int32_t key_bits;         /* key width of the hop into this table (0: 31) */
+    int32_t rule;             /* 0, TQP_CHAIN_PK_SORTED or TQP_CHAIN_PK_DENSE */
+} tqp_chain_table;
+tqp_status tqp_join_chain(tqp_ctx* ctx, const tqp_chain_table* tables, int ntables, int32_t* const* out_rows,
+                          int64_t* d_count, void* ws, size_t* ws_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------- group-by
  * Section 5.4, Algorithm 2: sort the group keys, permute the value columns

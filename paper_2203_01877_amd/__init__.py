@@ -197,57 +197,51 @@ def gather(ctx: Context, src, idx, d_n=None, stream=None):
 
 def join_chain(ctx: Context, keys_out, keys_pk, pk_sorted=None, key_bits=0, caps=None, pk_dense=None,
                stream=None):
-    """A chain of sort-based equi-joins (a multi-join plan): table 0's column keys_out[0] joins table
-    1's keys_pk[0], table 1's keys_out[1] joins table 2's keys_pk[1], and so on.  Returns one int32
-    device tensor of row positions per table (the result tuples) and their count.
+    """A chain of sort-based equi-joins (a multi-join plan) in one tqp_join_chain launch sequence: table
+    0's column keys_out[0] joins table 1's keys_pk[0], table 1's keys_out[1] joins table 2's
+    keys_pk[1], and so on.  Returns one int32 device tensor of row positions per table (the result
+    tuples, in no fixed order) and their count.
 
-    Each hop sorts the current left keys with their positions, sorts the right key column unless
-    pk_sorted[t] says it is already in order (the plan rule of skipping a sort over sorted data),
-    joins, and gathers the earlier position columns and the next hop's key through the join output.
-    pk_dense[t]: hop t's key column is exactly 0, 1, ..., M - 1 (a dense key in row order), so a
-    left key is its own match's row position: the hop is a filter of the keys in [0, M), with the
-    key carried along as the right row, and no sort or join at all.
-    key_bits: the key width of every hop, or one per hop (fewer radix passes).  caps[t] bounds hop t's result; a hop whose result is larger runs again at its exact size (the
-    join reports its true count).  Reads and clears the device error word; any error raises."""
+    pk_sorted[t]: hop t's key column is already in order (its sort is skipped).  pk_dense[t]: it is
+    exactly 0, 1, ..., M - 1 in row order (the hop is a filter of the keys in [0, M)).  key_bits: the
+    key width of every hop, or one per hop.  caps[t] bounds hop t's tuples (default: the tuples
+    entering the hop, exact for primary keys); when a hop overflows its bound the whole chain runs
+    again with four times the bounds.  The hop sizes stay on the device; the only host reads are the
+    final count and the error word, which is cleared; any other error raises."""
     hops = len(keys_pk)
-    if len(keys_out) != hops or hops < 1:
-        raise ValueError("join_chain: one outgoing key column per hop, at least one hop")
+    if len(keys_out) != hops or hops < 1 or hops + 1 > _lib.CHAIN_MAX_TABLES:
+        raise ValueError("join_chain: one outgoing key column per hop, 1..%d hops" % (_lib.CHAIN_MAX_TABLES - 1))
     pk_sorted = pk_sorted or [False] * hops
     pk_dense = pk_dense or [False] * hops
     kbits = list(key_bits) if isinstance(key_bits, (list, tuple)) else [key_bits] * hops
-    cols = []
-    cur = keys_out[0]
-    for t in range(hops):
-        if pk_dense[t]:
-            M = keys_pk[t].numel()
-            li, rr, cnt = filter(ctx, [cur], [(0, TQP_GE, 0), (0, TQP_LT, M)], carry=cur, stream=stream)
-            J = int(cnt.item())
-            li, rr = li[:J], rr[:J]
-            cols = [gather(ctx, c, li, stream=stream) for c in cols] if cols else [li]
-            cols.append(rr)
-            if t + 1 < hops:
-                cur = gather(ctx, keys_out[t + 1], rr, stream=stream)
+    n0 = keys_out[0].numel()
+    if caps is None:
+        caps = []
+        for t in range(hops):
+            caps.append(max(1, n0 if t == 0 else caps[-1]))
+    caps = [max(1, int(c)) for c in caps]
+    dev = _dev(ctx)
+    s = _stream(stream)
+    while True:
+        tabs = (_lib.ChainTable * (hops + 1))()
+        tabs[0] = _lib.ChainTable(keys_out[0].data_ptr(), None, n0, 0, 0, 0)
+        for t in range(hops):
+            rule = _lib.CHAIN_PK_DENSE if pk_dense[t] else (_lib.CHAIN_PK_SORTED if pk_sorted[t] else 0)
+            nxt = keys_out[t + 1].data_ptr() if t + 1 < hops else None
+            tabs[t + 1] = _lib.ChainTable(nxt, keys_pk[t].data_ptr(), keys_pk[t].numel(), caps[t], kbits[t], rule)
+        outs = [torch.empty(caps[-1], dtype=torch.int32, device=dev) for _ in range(hops + 1)]
+        ptrs = (ctypes.c_void_p * (hops + 1))(*[o.data_ptr() for o in outs])
+        cnt = torch.empty(1, dtype=torch.int64, device=dev)
+        _run(lambda ws, sz: ctx.lib.tqp_join_chain(ctx.h, tabs, hops + 1, ptrs, _p(cnt), ws, sz, s),
+             "tqp_join_chain", dev)
+        err = ctx.errors(stream=stream)
+        if err & DEVERR_CAPACITY and not err & ~DEVERR_CAPACITY:
+            caps = [4 * c for c in caps]
             continue
-        ls, lp = sort(ctx, cur, key_bits=kbits[t], perm=True, stream=stream)
-        if pk_sorted[t]:
-            rs, rp = keys_pk[t], None
-        else:
-            rs, rp = sort(ctx, keys_pk[t], key_bits=kbits[t], perm=True, stream=stream)
-        cap = caps[t] if caps else max(1, ls.numel())
-        li, rr, cnt = join(ctx, ls, rs, lp, rp, cap=cap, stream=stream)
+        if err:
+            raise RuntimeError("join_chain: device error flags 0x%x" % err)
         J = int(cnt.item())
-        if J > cap:
-            ctx.errors()                                   # the capacity bit of the undersized run
-            li, rr, cnt = join(ctx, ls, rs, lp, rp, cap=J, stream=stream)
-        li, rr = li[:J], rr[:J]
-        cols = [gather(ctx, c, li, stream=stream) for c in cols] if cols else [li]
-        cols.append(rr)
-        if t + 1 < hops:
-            cur = gather(ctx, keys_out[t + 1], rr, stream=stream)
-    err = ctx.errors(stream=stream)
-    if err:
-        raise RuntimeError("join_chain: device error flags 0x%x" % err)
-    return cols, J
+        return [o[:J] for o in outs], J
 
 
 def hash_join(ctx: Context, lkey, rkey, lrow=None, rrow=None, cap: int | None = None, d_nl=None, d_nr=None,

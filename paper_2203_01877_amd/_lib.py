@@ -74,6 +74,14 @@ class ServerConfig(ctypes.Structure):
                 ("presort_mid", c_i32), ("reserved", c_i32)]
 
 
+CHAIN_MAX_TABLES, CHAIN_PK_SORTED, CHAIN_PK_DENSE = 8, 1, 2
+
+
+class ChainTable(ctypes.Structure):
+    _fields_ = [("key_out", c_vp), ("key_pk", c_vp), ("n_rows", c_i64), ("cap", c_i64), ("key_bits", c_i32),
+                ("rule", c_i32)]
+
+
 class Request(ctypes.Structure):
     _fields_ = [("kind", c_i32), ("D", c_i32), ("c", c_i32), ("k", c_i32), ("row0", c_i64), ("n_rows", c_i64),
                 ("tag", ctypes.c_uint64)]
@@ -123,6 +131,9 @@ def load() -> ctypes.CDLL:
     lib.tqp_filter_noalloc.argtypes = [c_vp, ctypes.POINTER(Column), c_int, c_i64, ctypes.POINTER(Pred), c_int,
                                        c_vp, c_vp, c_vp, c_i64, c_vp, c_vp]
     lib.tqp_filter_noalloc.restype = S
+    lib.tqp_join_chain.argtypes = [c_vp, ctypes.POINTER(ChainTable), c_int, ctypes.POINTER(c_vp), c_vp, c_vp,
+                                   c_size_p, c_vp]
+    lib.tqp_join_chain.restype = S
     lib.tqp_sort.argtypes = [c_vp, c_vp, c_vp, c_i64, c_vp, c_int, c_vp, c_vp, c_vp, c_size_p, c_vp]
     lib.tqp_sort.restype = S
     lib.tqp_join.argtypes = [c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_i64, c_vp,

@@ -1,0 +1,257 @@
+// Chains of sort-based equi-joins: multi-join plans such as the six-join
+// query of Section 6.3, with the plan rules of Section 6.6 (the sort of a key
+// column that is already in order is skipped; a key column that is exactly
+// 0..M-1 in row order turns its join into a filter).
+//
+// Table 0's key column joins table 1's key, table 1's next key column joins
+// table 2's, and so on.  A tuple is one row position per table joined so far.
+// Hop t (t >= 1) joins the current tuples to table t:
+//   1. the tuples' keys into table t are sorted with the tuple index as the
+//      payload (radix sort at the hop's key width);
+//   2. table t's key column is sorted with its row positions, unless the
+//      caller declares it sorted (then the positions are the indexes) or
+//      dense (then no sort and no join: the key is its own row position, and
+//      a filter keeps the tuples whose key lies in [0, M));
+//   3. the sort-based join gives (tuple index, row of table t) pairs;
+//   4. one gather kernel reads the earlier position columns through the tuple
+//      index (late materialisation) and the next hop's key through the new
+//      row of table t.
+// Every hop's size stays on the device and bounds the next hop's kernels
+// (their grids come from the caller's capacities), so the whole chain is one
+// launch sequence with no host synchronisation.
+#include "filter.hpp"
+#include "fragment.hpp"
+
+namespace tqp {
+namespace {
+
+using JCfgChain = JoinCfg<256, 8, 4096>;
+constexpr int CH_FILTER_BLOCK = 256, CH_FILTER_ITEMS = 16;
+constexpr int CH_GATHER_BLOCK = 256, CH_GATHER_ITEMS = 4;
+
+struct ChainGather {
+    const int32_t* src[TQP_CHAIN_MAX_TABLES];   // earlier position columns, read through li
+    int32_t* dst[TQP_CHAIN_MAX_TABLES];
+    int32_t ncols;
+    const int32_t* key_src;                     // the next hop's key column, read through rr (nullable)
+    int32_t* key_dst;
+};
+
+// dst[c][i] = src[c][li[i]] and key_dst[i] = key_src[rr[i]] for i below the
+// hop's tuple count (at most n_upper).  Positions come from the hop's own
+// join or filter, so they are in range.
+__global__ void __launch_bounds__(CH_GATHER_BLOCK)
+k_chain_gather(ChainGather g, const int32_t* li, const int32_t* rr, int64_t n_upper, const int64_t* d_n) {
+    int64_t n = *d_n;
+    n = n < n_upper ? n : n_upper;
+    const int64_t step = (int64_t)gridDim.x * CH_GATHER_BLOCK * CH_GATHER_ITEMS;
+    for (int64_t base = (int64_t)blockIdx.x * CH_GATHER_BLOCK * CH_GATHER_ITEMS; base < n; base += step) {
+        int32_t l[CH_GATHER_ITEMS], r[CH_GATHER_ITEMS];
+        bool in[CH_GATHER_ITEMS];
+#pragma unroll
+        for (int j = 0; j < CH_GATHER_ITEMS; ++j) {
+            const int64_t i = base + (int64_t)j * CH_GATHER_BLOCK + threadIdx.x;
+            in[j] = i < n;
+            const int64_t ic = in[j] ? i : base;
+            l[j] = li[ic];
+            r[j] = rr[ic];
+        }
+        for (int c = 0; c < g.ncols; ++c) {
+            int32_t v[CH_GATHER_ITEMS];
+#pragma unroll
+            for (int j = 0; j < CH_GATHER_ITEMS; ++j) v[j] = g.src[c][l[j]];
+#pragma unroll
+            for (int j = 0; j < CH_GATHER_ITEMS; ++j)
+                if (in[j]) g.dst[c][base + (int64_t)j * CH_GATHER_BLOCK + threadIdx.x] = v[j];
+        }
+        if (g.key_src) {
+            int32_t v[CH_GATHER_ITEMS];
+#pragma unroll
+            for (int j = 0; j < CH_GATHER_ITEMS; ++j) v[j] = g.key_src[r[j]];
+#pragma unroll
+            for (int j = 0; j < CH_GATHER_ITEMS; ++j)
+                if (in[j]) g.key_dst[base + (int64_t)j * CH_GATHER_BLOCK + threadIdx.x] = v[j];
+        }
+    }
+}
+
+template <class Cfg>
+struct HopBufs {
+    bool dense = false, sorted = false;
+    int64_t n_left = 0;                      // host bound on the tuples entering the hop
+    RadixBufs<Cfg, uint32_t> lsort, rsort;
+    JoinBufs join;
+    uint64_t* fstatus = nullptr;             // dense rule: the filter's look-back words
+    uint32_t* fcounter = nullptr;
+    uint32_t *lsk = nullptr, *lsv = nullptr, *rsk = nullptr, *rsv = nullptr;
+    int32_t* li = nullptr;                   // tuple index of every output tuple
+    int64_t* d_cnt = nullptr;                // tuples after the hop
+};
+
+template <class Cfg>
+struct ChainBufs {
+    int hops = 0;
+    HopBufs<Cfg> hop[TQP_CHAIN_MAX_TABLES];
+    int32_t* cols[2][TQP_CHAIN_MAX_TABLES] = {};   // ping-pong position columns of the inner hops
+    int32_t* key[2] = {};                          // ping-pong next-hop keys
+};
+
+template <class Cfg>
+void chain_reserve(Arena& a, const tqp_chain_table* t, int nt, int64_t* d_count, ChainBufs<Cfg>& b) {
+    const int H = nt - 1;
+    b.hops = H;
+    int64_t inner_cap = 0;
+    for (int h = 1; h <= H; ++h) {
+        HopBufs<Cfg>& hb = b.hop[h];
+        const int kb = norm_key_bits(t[h].key_bits);
+        hb.dense = t[h].rule == TQP_CHAIN_PK_DENSE;
+        hb.sorted = t[h].rule == TQP_CHAIN_PK_SORTED;
+        hb.n_left = h == 1 ? t[0].n_rows : t[h - 1].cap;
+        if (hb.dense) {
+            const int64_t tiles = (hb.n_left + CH_FILTER_BLOCK * CH_FILTER_ITEMS - 1) / (CH_FILTER_BLOCK * CH_FILTER_ITEMS);
+            hb.fstatus = a.zero<uint64_t>(tiles);
+            hb.fcounter = a.zero<uint32_t>(1);
+        } else {
+            hb.lsort = radix_reserve<Cfg, uint32_t>(a, hb.n_left, kb);
+            hb.lsk = a.scratch<uint32_t>(hb.n_left);
+            hb.lsv = a.scratch<uint32_t>(hb.n_left);
+            if (!hb.sorted) {
+                hb.rsort = radix_reserve<Cfg, uint32_t>(a, t[h].n_rows, kb);
+                hb.rsk = a.scratch<uint32_t>(t[h].n_rows);
+                hb.rsv = a.scratch<uint32_t>(t[h].n_rows);
+            }
+            hb.join = join_reserve<JCfgChain>(a, hb.n_left);
+        }
+        hb.li = a.scratch<int32_t>(t[h].cap);
+        hb.d_cnt = h == H ? d_count : a.zero<int64_t>(1);
+        if (h < H && t[h].cap > inner_cap) inner_cap = t[h].cap;
+    }
+    for (int s = 0; s < 2; ++s) {
+        for (int u = 0; u < H; ++u) b.cols[s][u] = a.scratch<int32_t>(inner_cap);
+        b.key[s] = a.scratch<int32_t>(inner_cap);
+    }
+}
+
+template <class Cfg>
+tqp_status chain_launch(tqp_ctx* ctx, const tqp_chain_table* t, int nt, int32_t* const* out_rows,
+                        const ChainBufs<Cfg>& b, hipStream_t s) {
+    const int H = nt - 1;
+    tqp_status st;
+    const int32_t* cur = t[0].key_out;              // the tuples' keys into the next table
+    const int64_t* d_prev = nullptr;                // tuples entering the hop (device), null: all of table 0
+    int32_t* const* prev_cols = nullptr;
+    for (int h = 1; h <= H; ++h) {
+        const HopBufs<Cfg>& hb = b.hop[h];
+        const int kb = norm_key_bits(t[h].key_bits);
+        const uint32_t mask = key_mask_for(kb);
+        int32_t* const* dst = h == H ? out_rows : b.cols[h & 1];
+        // hop 1: the tuple index is table 0's row position, so it goes to its column directly
+        int32_t* li = h == 1 ? dst[0] : hb.li;
+        int32_t* rr = dst[h];
+        if (hb.dense) {
+            FilterPreds fp{};
+            fp.np = 2;
+            fp.col[0] = cur;
+            fp.col[1] = cur;
+            fp.type[0] = fp.type[1] = TQP_I32;
+            fp.op[0] = CMP_GE;
+            fp.k[0] = 0;
+            fp.op[1] = CMP_LT;
+            fp.k[1] = t[h].n_rows;
+            constexpr int64_t TILE = CH_FILTER_BLOCK * CH_FILTER_ITEMS;
+            TQP_LAUNCH(ctx, s, "chain_dense",
+                       (k_filter<CH_FILTER_BLOCK, CH_FILTER_ITEMS><<<grid_for(hb.n_left, TILE, 0), CH_FILTER_BLOCK,
+                                                                     0, s>>>(fp, hb.n_left, cur, li, rr, t[h].cap,
+                                                                             hb.d_cnt, hb.fstatus, hb.fcounter,
+                                                                             ctx->d_err, d_prev)));
+        } else {
+            SrcKeysIndex lsrc{reinterpret_cast<const uint32_t*>(cur), hb.n_left, d_prev};
+            if ((st = radix_launch<Cfg, uint32_t>(hb.lsort, lsrc, hb.n_left, true, nullptr, mask, hb.lsk, hb.lsv, ctx,
+                                                  s, "chain_sort_left", "chain_sort_left")) != TQP_OK)
+                return st;
+            const uint32_t* rk = reinterpret_cast<const uint32_t*>(t[h].key_pk);
+            const uint32_t* rp = nullptr;           // sorted by the caller: the positions are the indexes
+            if (!hb.sorted) {
+                SrcKeysIndex rsrc{reinterpret_cast<const uint32_t*>(t[h].key_pk), t[h].n_rows, nullptr};
+                if ((st = radix_launch<Cfg, uint32_t>(hb.rsort, rsrc, t[h].n_rows, true, nullptr, mask, hb.rsk,
+                                                      hb.rsv, ctx, s, "chain_sort_right", "chain_sort_right")) !=
+                    TQP_OK)
+                    return st;
+                rk = hb.rsk;
+                rp = hb.rsv;
+            }
+            EmitPairs e{li, rr, t[h].cap};
+            // left elements that took part in the sort: the histogram's count
+            if ((st = join_launch<JCfgChain, uint32_t, uint32_t, EmitPairs>(
+                     ctx, s, "chain_join", hb.join, hb.lsk, hb.lsv, hb.n_left, hb.lsort.d_cnt, rk, rp, t[h].n_rows,
+                     nullptr, hb.d_cnt, t[h].cap, e)) != TQP_OK)
+                return st;
+        }
+        // earlier position columns through the tuple index, the next key through the new row
+        ChainGather g{};
+        g.ncols = h == 1 ? 0 : h;
+        for (int u = 0; u < g.ncols; ++u) {
+            g.src[u] = prev_cols[u];
+            g.dst[u] = dst[u];
+        }
+        int32_t* next_key = b.key[h & 1];
+        if (h < H) {
+            g.key_src = t[h].key_out;
+            g.key_dst = next_key;
+        }
+        if (g.ncols > 0 || g.key_src) {
+            const int grid = grid_for(t[h].cap, (int64_t)CH_GATHER_BLOCK * CH_GATHER_ITEMS, (int64_t)ctx->num_cus * 16);
+            TQP_LAUNCH(ctx, s, "chain_gather",
+                       k_chain_gather<<<grid, CH_GATHER_BLOCK, 0, s>>>(g, li, rr, t[h].cap, hb.d_cnt));
+        }
+        cur = next_key;
+        d_prev = hb.d_cnt;
+        prev_cols = dst;
+    }
+    return TQP_OK;
+}
+
+tqp_status check_chain(const tqp_chain_table* t, int nt, int32_t* const* out_rows, const int64_t* d_count) {
+    if (!t || !out_rows || !d_count) return fail(TQP_ERR_INVALID, "tqp_join_chain: null argument");
+    if (nt < 2 || nt > TQP_CHAIN_MAX_TABLES)
+        return fail(TQP_ERR_UNSUPPORTED, "tqp_join_chain: %d tables (2..%d)", nt, TQP_CHAIN_MAX_TABLES);
+    for (int u = 0; u < nt; ++u) {
+        if (t[u].n_rows < 0 || (u > 0 && t[u].cap < 0))
+            return fail(TQP_ERR_INVALID, "tqp_join_chain: table %d: negative size", u);
+        if (t[u].n_rows > MAX_ELEMS || (u > 0 && t[u].cap > MAX_ELEMS))
+            return fail(TQP_ERR_UNSUPPORTED, "tqp_join_chain: table %d: too large", u);
+        if (u + 1 < nt && t[u].n_rows > 0 && !t[u].key_out)
+            return fail(TQP_ERR_INVALID, "tqp_join_chain: table %d has no outgoing key column", u);
+        if (u > 0 && t[u].n_rows > 0 && !t[u].key_pk && t[u].rule != TQP_CHAIN_PK_DENSE)
+            return fail(TQP_ERR_INVALID, "tqp_join_chain: table %d has no key column", u);
+        if (u > 0 && t[u].rule != 0 && t[u].rule != TQP_CHAIN_PK_SORTED && t[u].rule != TQP_CHAIN_PK_DENSE)
+            return fail(TQP_ERR_INVALID, "tqp_join_chain: table %d: rule %d", u, t[u].rule);
+        if (t[nt - 1].cap > 0 && !out_rows[u])
+            return fail(TQP_ERR_INVALID, "tqp_join_chain: no output column for table %d", u);
+    }
+    return TQP_OK;
+}
+
+}  // namespace
+}  // namespace tqp
+
+using namespace tqp;
+
+extern "C" tqp_status tqp_join_chain(tqp_ctx* ctx, const tqp_chain_table* tables, int ntables,
+                                     int32_t* const* out_rows, int64_t* d_count, void* ws, size_t* ws_bytes,
+                                     hipStream_t stream) {
+    clear_error();
+    if (!ctx) return fail(TQP_ERR_INVALID, "tqp_join_chain: null context");
+    tqp_status st = check_chain(tables, ntables, out_rows, d_count);
+    if (st != TQP_OK) return st;
+    return with_radix_cfg(ctx->digit_bits, [&](auto cfg) -> tqp_status {
+        using Cfg = decltype(cfg);
+        ChainBufs<Cfg> b;
+        Arena a;
+        auto plan = [&](Arena& ar) { chain_reserve<Cfg>(ar, tables, ntables, d_count, b); };
+        tqp_status s2 = with_workspace(ctx, ws, ws_bytes, stream, plan, a);
+        if (s2 != TQP_OK || !ws) return s2;
+        if ((s2 = fill_zero(a.base, a.zsize, stream, ctx)) != TQP_OK) return s2;
+        return chain_launch<Cfg>(ctx, tables, ntables, out_rows, b, stream);
+    });
+}

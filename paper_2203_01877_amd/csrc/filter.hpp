@@ -4,7 +4,8 @@
 //
 // Per tile: one ballot per 64 rows gives the wave's survivors and each lane's
 // rank among them; a block scan and a decoupled look-back give the tile's
-// output base.  The row count stays on the device.
+// output base.  The row count stays on the device (and the input's may come
+// from the device: d_n).
 #pragma once
 #include "dev.hpp"
 #include "radix.hpp"
@@ -48,12 +49,17 @@ struct FilterPreds {
 template <int BLOCK, int ITEMS>
 __global__ void __launch_bounds__(BLOCK)
 k_filter(FilterPreds fp, int64_t n, const int32_t* carry, int32_t* out_row, int32_t* out_carry,
-         int64_t cap, int64_t* d_count, uint64_t* status, uint32_t* tile_counter, uint32_t* flags) {
+         int64_t cap, int64_t* d_count, uint64_t* status, uint32_t* tile_counter, uint32_t* flags,
+         const int64_t* d_n = nullptr) {
     constexpr int TILE = BLOCK * ITEMS, W = BLOCK / WAVE;
     __shared__ int64_t s_wave[W];
     __shared__ int64_t s_base;
     __shared__ uint32_t s_tile;
     const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
+    if (d_n) {                                 // rows counted on the device, at most n
+        const int64_t t = *d_n;
+        n = t < n ? t : n;
+    }
     if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
     __syncthreads();
     const int64_t tile = s_tile;

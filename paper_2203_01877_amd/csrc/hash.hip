@@ -1,224 +1,322 @@
 // Hash-based equi-join (Section 5.3, Algorithm 3), the variant of the join
-// the paper measures against the sort-based one.
+// the paper measures against the sort-based one, in the partitioned form the
+// section names as the next step.
 //
 // The paper builds a table of m slots indexed by a hash of the key from one
 // side, probes it with the other, and repeats build and probe as many times
 // as the most crowded slot holds rows, because a PyTorch scatter keeps one
-// row per slot.  On the GPU a slot conflict can be resolved in the table
-// itself (open addressing, linear probing), so one build and one probe
-// suffice:
+// row per slot.  Here both sides are first split into 2^P partitions by the
+// top bits of h = key * odd constant mod 2^32 (a bijection of the key, so
+// equal keys and only equal keys share h), and each partition is joined in
+// LDS, where a table build and its probes cost no HBM traffic:
 //
-//   build   every right row claims the first free slot at or after the home
-//           slot of its key with a 64-bit compare-and-swap of (row + 1, key);
-//   count   every left element scans from its key's home slot to the first
-//           free slot and counts the entries with an equal key (the per-tile
-//           and per-block totals give the output offsets, as in the
-//           sort-based join);
-//   expand  the same scan again, writing (lrow, rrow) at the element's offset.
+//   partition  one radix pass per side over the top P bits of h (the sort's
+//              histogram + pre-counted pass), rows carried as (h, row);
+//   plan       one small kernel turns the two digit histograms into the
+//              partition starts and a list of work items: (partition, chunk
+//              of left rows);
+//   join       persistent blocks take items.  For every chunk of at most
+//              PJ_RCAP right rows of the item's partition the block builds
+//              an LDS table keyed by key + 1: one slot per distinct key
+//              (linear probing, one compare-and-swap per row), the rows of a
+//              key counted, an exclusive scan of the counts over the slots,
+//              then every right row placed in its key's run (the slot's
+//              count-then-scan layout: inserts are O(1) per row whatever the
+//              number of duplicates, and the matches of a key are one
+//              contiguous run).  Each left row then finds its key's run with
+//              one probe; a round of left rows reserves its output range
+//              with one atomic add and writes (lrow, rrow) pairs, short runs
+//              by the row's own lane, long runs by the whole wave.
 //
-// m is the power of two at or above 2 * nr (at most half full, so every scan
-// ends), the home slot a multiplicative (Fibonacci) hash of the key: the
-// paper's key mod m would pile the duplicates of consecutive keys into one
-// run of slots.  Inputs need not be sorted.  Output rows follow the left
-// input order; the rows of one left element follow the table, i.e. no fixed
-// right order.
+// Output rows come in no fixed order (partition order, then the order in
+// which rounds reserve their ranges); the set of pairs is exact.
 #include "dev.hpp"
 #include "host.hpp"
 
 namespace tqp {
 namespace {
 
-constexpr int HJ_BLOCK = 256;
-constexpr int HJ_ITEMS = 8;
-constexpr int HJ_TILE = HJ_BLOCK * HJ_ITEMS;
-constexpr int HJ_REG = 2;          // matches per element kept in registers between count and write
+constexpr uint32_t PJ_MUL = 0x9E3779B1u;        // odd: key -> h is a bijection mod 2^32
+constexpr int PJ_BLOCK = 512;
+constexpr int PJ_ITEMS = 4;                      // left rows per thread per round
+constexpr int PJ_ROUND = PJ_BLOCK * PJ_ITEMS;
+constexpr int PJ_RCAP = 3072;                    // right rows per table build
+constexpr int PJ_LOG2S = 13;                     // table slots: 8192 (load factor <= 0.375)
+constexpr int PJ_S = 1 << PJ_LOG2S;
+constexpr int PJ_LCHUNK = 16384;                 // left rows per work item
+constexpr int PJ_MAXP = 11;                      // partition bits: one 11-bit radix pass
+constexpr int PJ_LANE_MAX = 4;                   // longer runs are written by the whole wave
+constexpr int PJ_PLAN_BLOCK = 1024;
 
-__device__ __forceinline__ uint32_t hj_home(uint32_t key, int log2m) {
-    return log2m ? (uint32_t)(((uint64_t)key * 0x9E3779B97F4A7C15ull) >> (64 - log2m)) : 0u;
-}
+static_assert(PJ_RCAP % PJ_BLOCK == 0, "right rows split evenly over the block");
+static_assert(PJ_S % PJ_BLOCK == 0, "slots split evenly over the block");
+static_assert(32 - PJ_MAXP - PJ_LOG2S >= 0, "slot bits lie below the partition bits");
 
-__global__ void __launch_bounds__(256)
-k_hash_build(const uint32_t* rkey, int64_t nr_upper, const int64_t* d_nr, unsigned long long* table,
-             int log2m) {
-    int64_t nr = nr_upper;
-    if (d_nr) { const int64_t t = *d_nr; nr = t < nr ? t : nr; }
-    const uint32_t mask = (uint32_t)((uint64_t(1) << log2m) - 1);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nr; i += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t k = rkey[i];
-        const unsigned long long e = ((unsigned long long)(i + 1) << 32) | k;
-        uint32_t s = hj_home(k, log2m);
-        // the table is at most half full: a free slot is always reached
-        while (atomicCAS(&table[s], 0ull, e) != 0ull) s = (s + 1) & mask;
+// Rows as (h, row): row = the caller's row id, or the element index.  A
+// negative key is reported and its row left out.
+struct SrcHashRows {
+    const int32_t* key;
+    const int32_t* row;
+    int64_t n_upper;
+    const int64_t* d_n;
+    uint32_t* flags;
+    __device__ int64_t size() const {
+        if (!d_n) return n_upper;
+        const int64_t n = *d_n;
+        return n < n_upper ? n : n_upper;
     }
-}
-
-// Scans the runs of a thread's ITEMS elements in lockstep (one round of slot
-// loads per step, issued together); visit(j, row) sees every entry whose key
-// equals the element's.
-template <class Visit>
-__device__ __forceinline__ void hash_walk(const uint32_t (&key)[HJ_ITEMS], const bool (&in)[HJ_ITEMS],
-                                          const unsigned long long* table, int log2m, Visit visit) {
-    const uint32_t mask = (uint32_t)((uint64_t(1) << log2m) - 1);
-    uint32_t s[HJ_ITEMS];
-    bool live[HJ_ITEMS];
-#pragma unroll
-    for (int j = 0; j < HJ_ITEMS; ++j) {
-        s[j] = hj_home(key[j], log2m);
-        live[j] = in[j];
+    __device__ bool load_key(int64_t i, uint32_t& k) const {
+        const int32_t x = key[i];
+        if (x < 0) set_flag(flags, FLAG_KEY_RANGE);
+        k = (uint32_t)x * PJ_MUL;
+        return x >= 0;
     }
-    for (;;) {
-        bool any = false;
-#pragma unroll
-        for (int j = 0; j < HJ_ITEMS; ++j) any |= live[j];
-        if (!any) break;
-        unsigned long long e[HJ_ITEMS];
-#pragma unroll
-        for (int j = 0; j < HJ_ITEMS; ++j) e[j] = table[s[j]];
-#pragma unroll
-        for (int j = 0; j < HJ_ITEMS; ++j) {
-            if (live[j]) {
-                if (e[j] == 0ull) {
-                    live[j] = false;
-                } else {
-                    if ((uint32_t)e[j] == key[j]) visit(j, (uint32_t)(e[j] >> 32) - 1u);
-                    s[j] = (s[j] + 1) & mask;
-                }
-            }
+    __device__ bool load(int64_t i, uint32_t& k, uint32_t& v) const {
+        const int32_t x = key[i];
+        k = (uint32_t)x * PJ_MUL;
+        v = row ? (uint32_t)row[i] : (uint32_t)i;
+        return x >= 0;
+    }
+};
+
+constexpr uint32_t pj_inv(uint32_t a) {
+    uint32_t x = a;                                  // Newton's iteration for the inverse mod 2^32
+    for (int i = 0; i < 5; ++i) x *= 2u - a * x;
+    return x;
+}
+constexpr uint32_t PJ_INV = pj_inv(PJ_MUL);
+static_assert(PJ_MUL * PJ_INV == 1u, "PJ_INV inverts PJ_MUL");
+
+// Partition starts of both sides (from the partition pass's digit
+// histograms: the rows with a smaller top-P value come first), and the work
+// items: a partition with rows on both sides gives ceil(left rows / LCHUNK)
+// items.  One block; writes lstart / rstart [np + 1] and item_pre [np + 1].
+__global__ void __launch_bounds__(PJ_PLAN_BLOCK)
+k_pj_plan(const uint32_t* hist_l, const uint32_t* hist_r, int np, int64_t* lstart, int64_t* rstart,
+          int64_t* item_pre) {
+    __shared__ int64_t s_w[PJ_PLAN_BLOCK / WAVE];
+    __shared__ int64_t s_carry[3];
+    if (threadIdx.x == 0) { s_carry[0] = 0; s_carry[1] = 0; s_carry[2] = 0; }
+    __syncthreads();
+    for (int p0 = 0; p0 < np; p0 += PJ_PLAN_BLOCK) {
+        const int p = p0 + threadIdx.x;
+        const int64_t nl = p < np ? hist_l[p] : 0, nr = p < np ? hist_r[p] : 0;
+        const int64_t it = (nl > 0 && nr > 0) ? (nl + PJ_LCHUNK - 1) / PJ_LCHUNK : 0;
+        int64_t tot;
+        const int64_t el = block_excl_sum<PJ_PLAN_BLOCK>(nl, s_w, &tot);
+        int64_t tr, ti;
+        const int64_t er = block_excl_sum<PJ_PLAN_BLOCK>(nr, s_w, &tr);
+        const int64_t ei = block_excl_sum<PJ_PLAN_BLOCK>(it, s_w, &ti);
+        if (p < np) {
+            lstart[p] = s_carry[0] + el;
+            rstart[p] = s_carry[1] + er;
+            item_pre[p] = s_carry[2] + ei;
         }
-    }
-}
-
-__device__ __forceinline__ void hj_block_range(int64_t ntiles, int64_t& t0, int64_t& t1) {
-    const int64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
-    t0 = (int64_t)blockIdx.x * per;
-    t1 = t0 + per < ntiles ? t0 + per : ntiles;
-    if (t0 > t1) t0 = t1;
-}
-
-__device__ __forceinline__ void hj_load(const uint32_t* lkey, int64_t nl, int64_t tile, uint32_t (&key)[HJ_ITEMS],
-                                        bool (&in)[HJ_ITEMS]) {
-    const int w = threadIdx.x / WAVE, l = lane_id();
-    const int64_t chunk = tile * HJ_TILE + (int64_t)w * HJ_ITEMS * WAVE;
-#pragma unroll
-    for (int j = 0; j < HJ_ITEMS; ++j) {
-        const int64_t i = chunk + j * WAVE + l;
-        in[j] = i < nl;
-        key[j] = lkey[in[j] ? i : nl - 1];                  // the tile exists, so nl >= 1
-    }
-}
-
-__global__ void __launch_bounds__(HJ_BLOCK)
-k_hash_count(const uint32_t* lkey, int64_t nl_upper, const int64_t* d_nl, const unsigned long long* table, int log2m,
-             int64_t* tile_cnt, int64_t* blk_total) {
-    __shared__ int64_t s_wave[HJ_BLOCK / WAVE];
-    int64_t nl = nl_upper;
-    if (d_nl) { const int64_t t = *d_nl; nl = t < nl ? t : nl; }
-    const int64_t ntiles = (nl + HJ_TILE - 1) / HJ_TILE;
-    int64_t t0, t1, sum = 0;
-    hj_block_range(ntiles, t0, t1);
-    for (int64_t tile = t0; tile < t1; ++tile) {
-        uint32_t key[HJ_ITEMS];
-        bool in[HJ_ITEMS];
-        hj_load(lkey, nl, tile, key, in);
-        int64_t c = 0;
-        hash_walk(key, in, table, log2m, [&](int, uint32_t) { ++c; });
-        c = wave_sum(c);
-        if (lane_id() == 0) s_wave[threadIdx.x / WAVE] = c;
         __syncthreads();
-        int64_t t = 0;
-        for (int w = 0; w < HJ_BLOCK / WAVE; ++w) t += s_wave[w];
+        if (threadIdx.x == 0) { s_carry[0] += tot; s_carry[1] += tr; s_carry[2] += ti; }
         __syncthreads();
-        if (threadIdx.x == 0) tile_cnt[tile] = t;
-        sum += t;
     }
-    if (threadIdx.x == 0) blk_total[blockIdx.x] = sum;
+    if (threadIdx.x == 0) {
+        lstart[np] = s_carry[0];
+        rstart[np] = s_carry[1];
+        item_pre[np] = s_carry[2];
+    }
 }
 
-__global__ void __launch_bounds__(HJ_BLOCK)
-k_hash_expand(const uint32_t* lkey, const int32_t* lrow, int64_t nl_upper, const int64_t* d_nl,
-              const int32_t* rrow, const unsigned long long* table, int log2m, const int64_t* tile_cnt,
-              const int64_t* blk_total, int32_t* out_l, int32_t* out_r, int64_t cap, int64_t* d_count,
-              uint32_t* flags) {
-    __shared__ int64_t s_wave[HJ_BLOCK / WAVE];
-    __shared__ int64_t s_base;
-    const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
-    int64_t nl = nl_upper;
-    if (d_nl) { const int64_t t = *d_nl; nl = t < nl ? t : nl; }
-    const int64_t ntiles = (nl + HJ_TILE - 1) / HJ_TILE;
-    if (tid < WAVE) {
-        int64_t acc = 0;
-        for (int64_t b = tid; b < blockIdx.x; b += WAVE) acc += blk_total[b];
-        acc = wave_sum(acc);
-        if (tid == 0) s_base = acc;
+struct PjSmem {
+    uint32_t key[PJ_S];          // key + 1, 0 = free
+    uint32_t cur[PJ_S];          // count, then (after the scan and placement) the end of the key's run
+    uint32_t rows[PJ_RCAP];      // right rows grouped by key
+    int64_t w64[PJ_BLOCK / WAVE];
+    uint32_t w32[PJ_BLOCK / WAVE];
+    int64_t base;
+    int64_t item;
+    int32_t part;
+};
+
+__device__ __forceinline__ uint32_t pj_slot(uint32_t h, int P) {
+    return (h >> (32 - P - PJ_LOG2S)) & (PJ_S - 1);
+}
+
+// Builds the table of right rows [r0, r1) of a partition (hashes rh, rows rv).
+__device__ void pj_build(PjSmem& sm, const uint32_t* rh, const uint32_t* rv, int64_t r0, int64_t r1, int P) {
+    constexpr int RPT = PJ_RCAP / PJ_BLOCK;
+    for (int i = threadIdx.x; i < PJ_S; i += PJ_BLOCK) {
+        sm.key[i] = 0;
+        sm.cur[i] = 0;
     }
     __syncthreads();
-    int64_t run = s_base;
-    int64_t t0, t1;
-    hj_block_range(ntiles, t0, t1);
-    for (int64_t tile = t0; tile < t1; ++tile) {
-        uint32_t key[HJ_ITEMS];
-        bool in[HJ_ITEMS];
-        hj_load(lkey, nl, tile, key, in);
-        // first walk: counts, and the first HJ_REG matches of each element
-        int32_t cnt[HJ_ITEMS];
-        uint32_t m[HJ_ITEMS][HJ_REG];
+    uint32_t slot[RPT], val[RPT];
+    bool in[RPT];
 #pragma unroll
-        for (int j = 0; j < HJ_ITEMS; ++j) cnt[j] = 0;
-        hash_walk(key, in, table, log2m, [&](int j, uint32_t node) {
+    for (int j = 0; j < RPT; ++j) {
+        const int64_t i = r0 + threadIdx.x + (int64_t)j * PJ_BLOCK;
+        in[j] = i < r1;
+        const int64_t ic = in[j] ? i : r0;         // r1 > r0: the chunk is not empty
+        const uint32_t h = rh[ic];
+        val[j] = rv[ic];
+        slot[j] = pj_slot(h, P);
+        const uint32_t k1 = h * PJ_INV + 1u;      // key + 1, never 0 for keys in [0, 2^31)
+        if (in[j]) {
+            // at most PJ_RCAP keys in PJ_S slots: a free or matching slot is always reached
+            for (;;) {
+                const uint32_t old = atomicCAS(&sm.key[slot[j]], 0u, k1);
+                if (old == 0u || old == k1) break;
+                slot[j] = (slot[j] + 1) & (PJ_S - 1);
+            }
+            atomicAdd(&sm.cur[slot[j]], 1u);
+        }
+    }
+    __syncthreads();
+    block_excl_scan_array<PJ_BLOCK>(sm.cur, PJ_S, sm.w32);     // count -> start of the key's run
 #pragma unroll
-            for (int q = 0; q < HJ_REG; ++q)
-                if (cnt[j] == q) m[j][q] = node;
-            ++cnt[j];
-        });
-        // offsets: wave scans over the elements in order, then the waves before
-        int64_t wt = 0;
+    for (int j = 0; j < RPT; ++j)
+        if (in[j]) sm.rows[atomicAdd(&sm.cur[slot[j]], 1u)] = val[j];   // cur ends at the run's end
+    __syncthreads();
+}
+
+// Joins left rows [l0, l1) of a partition against the table in sm.
+__device__ void pj_probe(PjSmem& sm, const uint32_t* lh, const uint32_t* lv, int64_t l0, int64_t l1, int P,
+                         int32_t* out_l, int32_t* out_r, int64_t cap, int64_t* total) {
+    const int w = threadIdx.x / WAVE, l = lane_id();
+    for (int64_t b = l0; b < l1; b += PJ_ROUND) {
+        uint32_t start[PJ_ITEMS], cnt[PJ_ITEMS], lrow[PJ_ITEMS];
+        // item j of lane l of wave w: row b + (w * ITEMS + j) * 64 + l (coalesced)
 #pragma unroll
-        for (int j = 0; j < HJ_ITEMS; ++j) wt += wave_sum((int64_t)cnt[j]);
-        if (l == 0) s_wave[w] = wt;
-        __syncthreads();
-        int64_t wbase = run;
-        for (int ww = 0; ww < w; ++ww) wbase += s_wave[ww];
-        run += tile_cnt[tile];
-        __syncthreads();
-        const int64_t chunk = tile * HJ_TILE + (int64_t)w * HJ_ITEMS * WAVE;
-        bool more = false;
-        int64_t o0[HJ_ITEMS];
-#pragma unroll
-        for (int j = 0; j < HJ_ITEMS; ++j) {
-            const int64_t incl = wave_incl_sum((int64_t)cnt[j]);
-            const int64_t o = wbase + incl - cnt[j];
-            wbase += wave_read(incl, WAVE - 1);
-            o0[j] = o;
-            const int64_t i = chunk + j * WAVE + l;
-            const int32_t lp = lrow ? lrow[in[j] ? i : 0] : (int32_t)i;
-#pragma unroll
-            for (int q = 0; q < HJ_REG; ++q) {
-                if (q < cnt[j] && o + q < cap) {
-                    out_l[o + q] = lp;
-                    out_r[o + q] = rrow ? rrow[m[j][q]] : (int32_t)m[j][q];
+        for (int j = 0; j < PJ_ITEMS; ++j) {
+            const int64_t i = b + (int64_t)(w * PJ_ITEMS + j) * WAVE + l;
+            const bool in = i < l1;
+            const int64_t ic = in ? i : l0;
+            const uint32_t h = lh[ic];
+            lrow[j] = lv[ic];
+            uint32_t s = pj_slot(h, P);
+            const uint32_t k1 = h * PJ_INV + 1u;
+            start[j] = 0;
+            cnt[j] = 0;
+            if (in) {
+                for (;;) {
+                    const uint32_t kk = sm.key[s];
+                    if (kk == k1) {
+                        const uint32_t e = sm.cur[s];
+                        const uint32_t st = s ? sm.cur[s - 1] : 0u;       // the run before ends where this begins
+                        start[j] = st;
+                        cnt[j] = e - st;
+                        break;
+                    }
+                    if (kk == 0u) break;
+                    s = (s + 1) & (PJ_S - 1);
                 }
             }
-            more |= cnt[j] > HJ_REG;
         }
-        // elements with more matches: a second walk writes the rest
-        if (__any(more)) {
-            int32_t seen[HJ_ITEMS];
+        // output offsets: wave scans in item order, then the waves before, then one atomic per round
+        int64_t off[PJ_ITEMS];
+        int64_t run = 0;
 #pragma unroll
-            for (int j = 0; j < HJ_ITEMS; ++j) seen[j] = 0;
-            hash_walk(key, in, table, log2m, [&](int j, uint32_t node) {
-                const int32_t q = seen[j]++;
-                if (q >= HJ_REG && o0[j] + q < cap) {
-                    const int64_t i = chunk + j * WAVE + l;
-                    out_l[o0[j] + q] = lrow ? lrow[i] : (int32_t)i;
-                    out_r[o0[j] + q] = rrow ? rrow[node] : (int32_t)node;
+        for (int j = 0; j < PJ_ITEMS; ++j) {
+            const int64_t inc = wave_incl_sum((int64_t)cnt[j]);
+            off[j] = run + inc - cnt[j];
+            run += wave_read(inc, WAVE - 1);
+        }
+        if (l == 0) sm.w64[w] = run;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int64_t t = 0;
+            for (int ww = 0; ww < PJ_BLOCK / WAVE; ++ww) t += sm.w64[ww];
+            sm.base = t ? atomic_add(total, t) : 0;
+        }
+        __syncthreads();
+        int64_t wbase = sm.base;
+        for (int ww = 0; ww < w; ++ww) wbase += sm.w64[ww];
+        bool wide = false;
+#pragma unroll
+        for (int j = 0; j < PJ_ITEMS; ++j) {
+            const int64_t o = wbase + off[j];
+            if (cnt[j] <= (uint32_t)PJ_LANE_MAX) {
+                for (uint32_t q = 0; q < cnt[j]; ++q) {
+                    if (o + q < cap) {
+                        out_l[o + q] = (int32_t)lrow[j];
+                        out_r[o + q] = (int32_t)sm.rows[start[j] + q];
+                    }
                 }
-            });
+            } else {
+                wide = true;
+            }
+        }
+        if (__any(wide)) {
+#pragma unroll
+            for (int j = 0; j < PJ_ITEMS; ++j) {
+                uint64_t m = ballot(cnt[j] > (uint32_t)PJ_LANE_MAX);
+                while (m) {
+                    const int src = __ffsll((unsigned long long)m) - 1;
+                    m &= m - 1;
+                    const int64_t o = wave_read(wbase + off[j], src);
+                    const uint32_t c = wave_read(cnt[j], src);
+                    const uint32_t st = wave_read(start[j], src);
+                    const int32_t lr = (int32_t)wave_read(lrow[j], src);
+                    for (uint32_t q = l; q < c; q += WAVE) {
+                        if (o + q < cap) {
+                            out_l[o + q] = lr;
+                            out_r[o + q] = (int32_t)sm.rows[st + q];
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();         // sm.base and sm.w64 are rewritten by the next round
+    }
+}
+
+// Two blocks per CU: 2 x 76 KB of LDS, and at most 128 VGPRs (4 waves per SIMD).
+__global__ void __launch_bounds__(PJ_BLOCK, 4)
+k_pj_join(const uint32_t* lh, const uint32_t* lv, const uint32_t* rh, const uint32_t* rv, const int64_t* lstart,
+          const int64_t* rstart, const int64_t* item_pre, int P, uint32_t* counter, int32_t* out_l, int32_t* out_r,
+          int64_t cap, int64_t* total) {
+    __shared__ PjSmem sm;
+    const int np = 1 << P;
+    const int64_t nitems = item_pre[np];
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const int64_t g = atomicAdd(counter, 1u);
+            sm.item = g;
+            if (g < nitems) {
+                int lo = 0, hi = np - 1;                  // the last partition p with item_pre[p] <= g
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (item_pre[mid] <= g) lo = mid;
+                    else hi = mid - 1;
+                }
+                sm.part = lo;
+            }
+        }
+        __syncthreads();
+        const int64_t g = sm.item;
+        const int p = sm.part;
+        __syncthreads();
+        if (g >= nitems) break;
+        const int64_t lc = g - item_pre[p];
+        const int64_t l0 = lstart[p] + lc * PJ_LCHUNK;
+        const int64_t l1 = l0 + PJ_LCHUNK < lstart[p + 1] ? l0 + PJ_LCHUNK : lstart[p + 1];
+        for (int64_t r0 = rstart[p]; r0 < rstart[p + 1]; r0 += PJ_RCAP) {
+            const int64_t r1 = r0 + PJ_RCAP < rstart[p + 1] ? r0 + PJ_RCAP : rstart[p + 1];
+            pj_build(sm, rh, rv, r0, r1, P);
+            pj_probe(sm, lh, lv, l0, l1, P, out_l, out_r, cap, total);
         }
     }
-    if (blockIdx.x == gridDim.x - 1 && tid == 0) {
-        *d_count = run;
-        if (run > cap) set_flag(flags, FLAG_CAPACITY);
-    }
+}
+
+__global__ void k_pj_finish(const int64_t* total, int64_t cap, int64_t* d_count, uint32_t* flags) {
+    const int64_t t = *total;
+    *d_count = t;
+    if (t > cap) set_flag(flags, FLAG_CAPACITY);
+}
+
+// Partition bits for nr right rows: about PJ_RCAP / 2 right rows per
+// partition, at most PJ_MAXP bits (larger partitions take several table
+// builds), at least one bit.
+int pj_bits(int64_t nr) {
+    int P = 1;
+    while (P < PJ_MAXP && (nr >> P) > PJ_RCAP / 2) ++P;
+    return P;
 }
 
 }  // namespace
@@ -237,47 +335,55 @@ tqp_status tqp_hash_join(tqp_ctx* ctx, const int32_t* lkey, const int32_t* lrow,
         (cap > 0 && (!out_l || !out_r)))
         return fail(TQP_ERR_INVALID, "tqp_hash_join: null pointer or negative size");
     if (nl > MAX_ELEMS || nr > MAX_ELEMS) return fail(TQP_ERR_UNSUPPORTED, "tqp_hash_join: input too large");
-    int log2m = 0;
-    while ((int64_t(1) << log2m) < 2 * nr) ++log2m;
-    const int64_t m = int64_t(1) << log2m;
-    const int64_t tiles = (nl + HJ_TILE - 1) / HJ_TILE;
-    static const int per_cu = [] {
-        int a = 4, b = 4;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_hash_count, HJ_BLOCK, 0) != hipSuccess) a = 4;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_hash_expand, HJ_BLOCK, 0) != hipSuccess) b = 4;
-        const int c = a < b ? a : b;
-        return c < 1 ? 1 : c;
-    }();
-    const int grid = grid_for(tiles, 1, (int64_t)ctx->num_cus * per_cu);
-    unsigned long long* table = nullptr;
-    int64_t *tile_cnt = nullptr, *blk_total = nullptr;
+    const int P = pj_bits(nr);
+    const int np = 1 << P;
+    using Cfg = R11;
+    RadixBufs<Cfg, uint32_t> lb, rb;
+    uint32_t *lh = nullptr, *lv = nullptr, *rh = nullptr, *rv = nullptr, *counter = nullptr;
+    int64_t *lstart = nullptr, *rstart = nullptr, *item_pre = nullptr, *total = nullptr;
     Arena a;
     auto plan = [&](Arena& ar) {
-        table = ar.zero<unsigned long long>(m);
-        tile_cnt = ar.scratch<int64_t>(tiles > 0 ? tiles : 1);
-        blk_total = ar.scratch<int64_t>(tiles > 0 ? tiles : 1);
+        lb = radix_reserve<Cfg, uint32_t>(ar, nl, 32, 32 - P);
+        rb = radix_reserve<Cfg, uint32_t>(ar, nr, 32, 32 - P);
+        counter = ar.zero<uint32_t>(1);
+        total = ar.zero<int64_t>(1);
+        lh = ar.scratch<uint32_t>(nl);
+        lv = ar.scratch<uint32_t>(nl);
+        rh = ar.scratch<uint32_t>(nr);
+        rv = ar.scratch<uint32_t>(nr);
+        lstart = ar.scratch<int64_t>(np + 1);
+        rstart = ar.scratch<int64_t>(np + 1);
+        item_pre = ar.scratch<int64_t>(np + 1);
     };
     tqp_status st = with_workspace(ctx, ws, ws_bytes, stream, plan, a);
     if (st != TQP_OK || !ws) return st;
     if ((st = fill_zero(a.base, a.zsize, stream, ctx)) != TQP_OK) return st;
-    const uint32_t* rk = reinterpret_cast<const uint32_t*>(rkey);
-    const uint32_t* lk = reinterpret_cast<const uint32_t*>(lkey);
-    if (nr > 0) {
-        TQP_LAUNCH(ctx, stream, "hash_build",
-                   k_hash_build<<<grid_for(nr, 256 * 4, (int64_t)ctx->num_cus * 8), 256, 0, stream>>>(
-                       rk, nr, d_nr, table, log2m));
+    // both sides into 2^P partitions by the top bits of h (one pass each; an
+    // empty side launches nothing and leaves its histogram zero)
+    SrcHashRows ls{lkey, lrow, nl, d_nl, ctx->d_err};
+    SrcHashRows rs{rkey, rrow, nr, d_nr, ctx->d_err};
+    if ((st = radix_launch<Cfg, uint32_t>(lb, ls, nl, true, nullptr, ~0u, lh, lv, ctx, stream, "hashjoin_part_l",
+                                          "hashjoin_part_l")) != TQP_OK)
+        return st;
+    if ((st = radix_launch<Cfg, uint32_t>(rb, rs, nr, true, nullptr, ~0u, rh, rv, ctx, stream, "hashjoin_part_r",
+                                          "hashjoin_part_r")) != TQP_OK)
+        return st;
+    TQP_LAUNCH(ctx, stream, "hashjoin_plan",
+               k_pj_plan<<<1, PJ_PLAN_BLOCK, 0, stream>>>(lb.hist, rb.hist, np, lstart, rstart, item_pre));
+    static const int per_cu = [] {
+        int b = 2;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_pj_join, PJ_BLOCK, 0) != hipSuccess) b = 2;
+        return b < 1 ? 1 : b;
+    }();
+    // items: at most one per partition plus one per LCHUNK left rows
+    const int64_t items_upper = (nl + PJ_LCHUNK - 1) / PJ_LCHUNK + np;
+    if (nl > 0 && nr > 0) {
+        const int grid = grid_for(items_upper, 1, (int64_t)ctx->num_cus * per_cu);
+        TQP_LAUNCH(ctx, stream, "hashjoin_join",
+                   k_pj_join<<<grid, PJ_BLOCK, 0, stream>>>(lh, lv, rh, rv, lstart, rstart, item_pre, P, counter,
+                                                            out_l, out_r, cap, total));
     }
-    if (tiles == 0) {
-        // no left rows: the join is empty
-        TQP_LAUNCH(ctx, stream, "hash_empty", k_fill_u32<<<1, 64, 0, stream>>>(
-                                                  reinterpret_cast<uint32_t*>(d_count), 2, 0u));
-        return TQP_OK;
-    }
-    TQP_LAUNCH(ctx, stream, "hash_count",
-               k_hash_count<<<grid, HJ_BLOCK, 0, stream>>>(lk, nl, d_nl, table, log2m, tile_cnt, blk_total));
-    TQP_LAUNCH(ctx, stream, "hash_expand",
-               k_hash_expand<<<grid, HJ_BLOCK, 0, stream>>>(lk, lrow, nl, d_nl, rrow, table, log2m, tile_cnt,
-                                                            blk_total, out_l, out_r, cap, d_count, ctx->d_err));
+    TQP_LAUNCH(ctx, stream, "hashjoin_finish", k_pj_finish<<<1, 1, 0, stream>>>(total, cap, d_count, ctx->d_err));
     return TQP_OK;
 }
 

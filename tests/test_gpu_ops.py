@@ -140,15 +140,25 @@ def _join_case(hip, ctx, lkey, rkey, cap=None):
     assert np.array_equal(_np(ol, w), wl) and np.array_equal(_np(orr, w), wr)
 
 
+def _pairs_sorted(l, r):
+    o = np.lexsort((r, l))
+    return l[o], r[o]
+
+
 @pytest.mark.parametrize("nl,nr,hi,sort", [(0, 10, 5, False), (10, 0, 5, False), (1, 1, 1, False),
                                            (5000, 300, 1500, False), (300_007, 40_000, 150_000, False),
                                            (200_000, 150_000, 150_000, True), (4097, 5, 3, False),
-                                           (20_000, 20_000, 1_000_000, False), (100_000, 64_000, 1_000, False)])
+                                           (20_000, 20_000, 1_000_000, False), (100_000, 64_000, 1_000, False),
+                                           (1_000_003, 3_000_000, 3_500_000, False),
+                                           (400_000, 1_500_000, 25_000, False)])
 def test_hash_join(hip, ctx, nl, nr, hi, sort):
-    """Hash join of unsorted inputs: the same rows as the oracle's join, left
-    rows in input order; the right rows of one left row in any order (the
-    oracle's are compared as sorted pairs).  (100000, 64000, 1000): 64 right
-    rows per key, long chains."""
+    """Partitioned hash join of unsorted inputs against the oracle's join: the
+    same set of (lrow, rrow) pairs (rows come in no fixed order, so both sides
+    are compared sorted; the row ids are permutations, so the pairs are
+    unique).  (100000, 64000, 1000): 64 right rows per key; (1000003,
+    3000000, ...): 2048 partitions of about 1500 right rows; (400000,
+    1500000, 25000): 60 right rows per key and partitions over the LDS
+    table's row capacity (several table builds per partition)."""
     rng = _rng(nl * 5 + nr + hi)
     lkey = rng.integers(0, hi, nl).astype(np.int32)
     rkey = rng.integers(0, hi, nr).astype(np.int32)
@@ -159,11 +169,60 @@ def test_hash_join(hip, ctx, nl, nr, hi, sort):
     wl, wr, J = oracle.join(lkey, rkey, lrow, rrow)
     ol, orr, cnt = hip.hash_join(ctx, _dev(lkey), _dev(rkey), _dev(lrow), _dev(rrow), cap=max(J, 1))
     assert int(_np(cnt)[0]) == J
-    gl, gr = _np(ol, J), _np(orr, J)
-    assert np.array_equal(gl, wl)                           # left order is fixed
-    order_w, order_g = np.lexsort((wr, wl)), np.lexsort((gr, gl))
-    assert np.array_equal(gl[order_g], wl[order_w]) and np.array_equal(gr[order_g], wr[order_w])
+    gl, gr = _pairs_sorted(_np(ol, J), _np(orr, J))
+    wl, wr = _pairs_sorted(wl, wr)
+    assert np.array_equal(gl, wl) and np.array_equal(gr, wr)
     assert ctx.errors() == 0
+
+
+def test_hash_join_hot_key_and_edges(hip, ctx):
+    """One key on 10000 right rows (its partition takes four table builds) and
+    on 300 left rows; element indexes as payloads (no row columns); a
+    negative key (flagged, its row left out); the device row counts below the
+    host bounds; an output capacity below the join size (capacity flag, the
+    true count, only cap rows written)."""
+    rng = _rng(4242)
+    nl, nr = 50_000, 40_000
+    lkey = rng.integers(0, 20_000, nl).astype(np.int32)
+    rkey = rng.integers(0, 20_000, nr).astype(np.int32)
+    rkey[:10_000] = 777
+    lkey[rng.integers(0, nl, 300)] = 777
+    wl, wr, J = oracle.join(lkey, rkey)
+    ol, orr, cnt = hip.hash_join(ctx, _dev(lkey), _dev(rkey), cap=J)
+    assert int(_np(cnt)[0]) == J and J > 2_500_000
+    gl, gr = _pairs_sorted(_np(ol, J), _np(orr, J))
+    wl, wr = _pairs_sorted(wl, wr)
+    assert np.array_equal(gl, wl) and np.array_equal(gr, wr)
+    assert ctx.errors() == 0
+    # device counts: only the first 30000 left and 25000 right rows take part
+    d_nl, d_nr = _dev(np.array([30_000], np.int64)), _dev(np.array([25_000], np.int64))
+    wl, wr, J = oracle.join(lkey[:30_000], rkey[:25_000])
+    ol, orr, cnt = hip.hash_join(ctx, _dev(lkey), _dev(rkey), cap=J, d_nl=d_nl, d_nr=d_nr)
+    assert int(_np(cnt)[0]) == J
+    gl, gr = _pairs_sorted(_np(ol, J), _np(orr, J))
+    wl, wr = _pairs_sorted(wl, wr)
+    assert np.array_equal(gl, wl) and np.array_equal(gr, wr)
+    assert ctx.errors() == 0
+    # a negative key
+    lbad = lkey.copy()
+    lbad[5] = -3
+    keep = np.flatnonzero(lbad >= 0).astype(np.int32)
+    wl, wr, J = oracle.join(lbad[keep], rkey, keep)
+    ol, orr, cnt = hip.hash_join(ctx, _dev(lbad), _dev(rkey), cap=J)
+    assert ctx.errors() == hip.DEVERR_KEY_RANGE
+    assert int(_np(cnt)[0]) == J
+    gl, gr = _pairs_sorted(_np(ol, J), _np(orr, J))
+    wl, wr = _pairs_sorted(wl, wr)
+    assert np.array_equal(gl, wl) and np.array_equal(gr, wr)
+    # capacity below the join size: the true count, cap rows that are all join rows
+    _, _, J = oracle.join(lkey, rkey)
+    cap = J // 3
+    ol, orr, cnt = hip.hash_join(ctx, _dev(lkey), _dev(rkey), cap=cap)
+    assert int(_np(cnt)[0]) == J
+    assert ctx.errors() == hip.DEVERR_CAPACITY
+    gl, gr = _np(ol, cap), _np(orr, cap)
+    assert np.array_equal(lkey[gl], rkey[gr])                  # every written row is a join row
+    assert len(np.unique(gl.astype(np.int64) * nr + gr)) == cap     # no row written twice
 
 
 @pytest.mark.parametrize("nl,nr,hi,w", [(0, 10, 5, 1), (10, 0, 5, 1), (1, 1, 1, 0), (5000, 300, 1500, 3),
@@ -358,6 +417,37 @@ def test_join_chain_dense(hip, ctx):
         assert J == len(want)
         got = np.stack([_np(c, J) for c in cols], axis=1)
         assert np.array_equal(_lex(got), _lex(want))
+
+
+@pytest.mark.parametrize("rules", ["none", "mixed"])
+def test_join_chain_six_hops(hip, ctx, rules):
+    """Six joins over seven tables (the shape of Section 6.3's six-join query) in one launch
+    sequence with every hop's size on the device, against the oracle's chain.  About 9% of each
+    hop's keys find no match.  mixed: hops 0 and 3 take the dense rule, hop 1 (a sorted key column
+    with duplicate keys) the sorted rule; its duplicates can push the tuples past the default
+    bounds, so the chain may run again with larger ones."""
+    rng = _rng(606 + len(rules))
+    sizes = [400_000, 150_000, 60_000, 30_000, 10_000, 2_000, 25]
+    outs = [rng.integers(0, int(sizes[t + 1] * 1.1), sizes[t]).astype(np.int32) for t in range(6)]
+    pks, dense, srt = [], [], []
+    for t in range(6):
+        M = sizes[t + 1]
+        if rules == "mixed" and t in (0, 3):
+            pks.append(np.arange(M, dtype=np.int32))
+        elif rules == "mixed" and t == 1:
+            pks.append(np.sort(rng.integers(0, M, M)).astype(np.int32))
+        else:
+            pks.append(rng.permutation(M).astype(np.int32))
+        dense.append(rules == "mixed" and t in (0, 3))
+        srt.append(rules == "mixed" and t in (0, 1, 3))
+    want = oracle.join_chain(outs, pks)
+    kb = [int(int(sizes[t + 1] * 1.1) - 1).bit_length() for t in range(6)]
+    cols, J = hip.join_chain(ctx, [_dev(o) for o in outs], [_dev(p) for p in pks], pk_sorted=srt, pk_dense=dense,
+                             key_bits=kb)
+    assert J == len(want) and J > 100_000
+    got = np.stack([_np(c, J) for c in cols], axis=1)
+    assert np.array_equal(_lex(got), _lex(want))
+    assert ctx.errors() == 0
 
 
 _KINDS = {"semi": 1, "anti": 2, "outer": 3, "inner": 0}
