@@ -444,6 +444,89 @@ tqp_status tqp_fragment_cust(tqp_ctx* ctx, const tqp_cust_fragment* f, const tqp
 tqp_status tqp_fragment_cust_plan(tqp_ctx* ctx, const tqp_cust_fragment* f, int* fact_passes, int* fact_lowb,
                                   int* mid_passes, int* group_passes, int* group_lowb);
 
+/* General fragment: the operators of Section 5 composed by a descriptor,
+ *   SELECT pack(g_1..g_q), agg_1, ..., agg_m
+ *   FROM fact [JOIN dim ON fact.col[fact_key] = dim.col[dim_key]]
+ *   WHERE fact_pred(fact row) [AND dim_pred(dim row)]
+ *   GROUP BY pack(g_1..g_q) ORDER BY the packed key
+ *   [and ORDER BY agg_1 DESC, key ASC LIMIT topk]
+ * run as one launch sequence with every data-dependent size on the device.
+ * Predicates and aggregate values are postfix programs (tqp_xinstr, the
+ * semantics of tqp_eval); a predicate keeps the rows where it is nonzero, and
+ * an empty one (n_*_pred = 0) keeps every row.  The fact predicate numbers the
+ * fact columns, the dim predicate the dim columns; group columns and aggregate
+ * programs number the joined row: fact columns 0..nf-1, then dim columns
+ * nf..nf+nd-1 (each program may read at most 8 different columns).  Without a
+ * join (fact_key < 0) the joined rows are the kept fact rows.  Join keys are
+ * int32 columns, non-negative and below 2^key_bits.  The group key packs the
+ * group columns (at most 4, any integer type), column i taking bits[i] bits,
+ * the first most significant, at most 31 bits in all (a value outside its
+ * width sets TQP_DEVERR_KEY_RANGE and enters masked); no group column puts
+ * every row in group 0.  Aggregates (at most 8): TQP_AGG_COUNT (no program),
+ * TQP_AGG_SUM (int64, wrapping), TQP_AGG_MIN, TQP_AGG_MAX, TQP_AGG_AVG
+ * ((double)SUM / (double)COUNT, written as a double), TQP_AGG_COUNT_DISTINCT
+ * (at most one per fragment).  Each aggregate writes one value per group to
+ * its out array (device, gcap entries of 8 bytes).  Groups come in ascending
+ * key order; *d_ngroups receives the group count (at most gcap written,
+ * TQP_DEVERR_CAPACITY beyond).  topk > 0 (1..1024, agg_1 not AVG): the first
+ * topk groups by (agg_1 desc, key asc) go to top_key / top_val and their
+ * number to *d_topk.  join_cap bounds the joined rows (TQP_DEVERR_CAPACITY
+ * beyond; the true count goes to *d_join when given).  The composition is
+ * sort-based throughout: both join sides are radix-sorted with their
+ * predicates fused into the sort, joined as by tqp_join, the group keys
+ * (and, for COUNT(DISTINCT), the distinct values first) radix-sorted with
+ * the joined-row index, and each group's run reduced. */
+#define TQP_AGG_COUNT 0
+#define TQP_AGG_SUM 1
+#define TQP_AGG_MIN 2
+#define TQP_AGG_MAX 3
+#define TQP_AGG_AVG 4
+#define TQP_AGG_COUNT_DISTINCT 5
+#define TQP_FRAGMENT_MAX_GROUP_COLS 4
+#define TQP_FRAGMENT_MAX_AGGS 8
+typedef struct {
+    int32_t col;              /* joined column number */
+    int32_t bits;             /* width of its values, >= 1 */
+} tqp_group_col;
+typedef struct {
+    int32_t op;               /* TQP_AGG_* */
+    int32_t nprog;            /* 0 for TQP_AGG_COUNT */
+    const tqp_xinstr* prog;   /* host */
+    void* out;                /* device, gcap values: int64, or double for TQP_AGG_AVG */
+} tqp_agg;
+typedef struct {
+    const tqp_column* fact_cols;   /* host array of device columns, n_fact rows each */
+    int32_t n_fact_cols;
+    int32_t fact_key;              /* fact column of the join key, -1: no join */
+    int64_t n_fact;
+    const tqp_xinstr* fact_pred;
+    int32_t n_fact_pred;
+    int32_t key_bits;              /* join keys < 2^key_bits (0: 31) */
+    const tqp_column* dim_cols;    /* n_dim rows each */
+    int32_t n_dim_cols;
+    int32_t dim_key;
+    int64_t n_dim;
+    const tqp_xinstr* dim_pred;
+    int32_t n_dim_pred;
+    int32_t n_group;
+    const tqp_group_col* group;
+    const tqp_agg* aggs;
+    int32_t n_agg;
+    int32_t topk;
+    int64_t join_cap;
+} tqp_fragment;
+typedef struct {
+    int32_t* key;             /* [gcap] packed group keys, ascending */
+    int64_t gcap;
+    int64_t* d_ngroups;
+    int64_t* d_join;          /* joined rows (nullable) */
+    int32_t* top_key;         /* [topk] (when topk > 0) */
+    int64_t* top_val;         /* [topk] */
+    int32_t* d_topk;
+} tqp_fragment_out;
+tqp_status tqp_fragment_run(tqp_ctx* ctx, const tqp_fragment* f, const tqp_fragment_out* o, void* ws,
+                            size_t* ws_bytes, hipStream_t stream);
+
 /* ---------------------------------------------------------------- batches
  * Many flags fragments (each with its own fact and dim columns, D and c) run
  * as one launch sequence: every stage is one persistent kernel over all

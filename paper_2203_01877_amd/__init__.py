@@ -32,7 +32,7 @@ from . import _lib
 from ._lib import (DEVERR_CAPACITY, DEVERR_KEY_RANGE, DEVERR_SPIN, DEVERR_VALUE_RANGE, JOIN_INNER, JOIN_LEFT_ANTI,
                    JOIN_LEFT_OUTER, JOIN_LEFT_SEMI, TQP_EQ, TQP_GE, TQP_GT, TQP_LE, TQP_LT, TQP_NE, TQPError, check)
 
-__all__ = ["Context", "filter", "filter_noalloc", "sort", "join", "hash_join", "join_band", "pack_keys", "eval_expr", "gather", "join_chain", "groupby_agg",
+__all__ = ["Context", "filter", "filter_noalloc", "fragment_run", "sort", "join", "hash_join", "join_band", "pack_keys", "eval_expr", "gather", "join_chain", "groupby_agg",
            "hash_groupby", "topk", "FlagsFragmentRunner",
            "CustFragmentRunner", "BatchRunner", "Server", "TQPError", "TQP_LT", "TQP_LE", "TQP_GT", "TQP_GE", "TQP_EQ", "TQP_NE",
            "DEVERR_KEY_RANGE", "DEVERR_SPIN", "DEVERR_CAPACITY", "DEVERR_VALUE_RANGE", "JOIN_INNER", "JOIN_LEFT_SEMI",
@@ -184,6 +184,48 @@ def eval_expr(ctx: Context, cols: list, prog: list, d_n=None, stream=None):
     check(ctx.lib.tqp_eval(ctx.h, carr, len(cols), n, _p(d_n), parr, len(prog), _p(out), _stream(stream)),
           "tqp_eval")
     return out[:n]
+
+
+def fragment_run(ctx: Context, fact: list, dim: list | None, fact_pred: list, dim_pred: list, fact_key: int,
+                 dim_key: int, group: list, aggs: list, topk: int = 0, key_bits: int = 0, join_cap: int | None = None,
+                 gcap: int | None = None, stream=None) -> dict:
+    """A general fragment (tqp_fragment_run): fact / dim are lists of device columns; predicates and
+    aggregate values are postfix programs [(op, arg)]; fact_key < 0 or dim None: no join; group =
+    [(joined column, bits)]; aggs = [(AGG_* op, program)].  join_cap defaults to the fact rows (exact
+    when dim keys are unique), gcap to join_cap.  Returns device tensors: key, vals (one per aggregate,
+    float64 for AVG), d_ngroups, d_join, top_key, top_val, d_topk."""
+    join = dim is not None and fact_key >= 0
+    dim = dim if join else []
+    n_fact = fact[0].numel()
+    n_dim = dim[0].numel() if dim else 0
+    join_cap = max(1, n_fact if join_cap is None else join_cap)
+    gcap = max(1, join_cap if gcap is None else gcap)
+    dev = _dev(ctx)
+    cols = lambda cs: (_lib.Column * max(1, len(cs)))(*[_lib.Column(c.data_ptr(), _DTYPES[c.dtype], 0) for c in cs])
+    prog = lambda p: (_lib.XInstr * max(1, len(p)))(*[_lib.XInstr(int(o), 0, int(a)) for o, a in p])
+    fc, dc, fp, dp = cols(fact), cols(dim), prog(fact_pred), prog(dim_pred if join else [])
+    ga = (_lib.GroupCol * max(1, len(group)))(*[_lib.GroupCol(c, b) for c, b in group])
+    vals = [torch.empty(gcap, dtype=torch.float64 if op == _lib.AGG_AVG else torch.int64, device=dev)
+            for op, _ in aggs]
+    progs = [prog(p) for _, p in aggs]
+    aa = (_lib.Agg * max(1, len(aggs)))(*[_lib.Agg(op, 0 if op == _lib.AGG_COUNT else len(p), ctypes.addressof(pp),
+                                                  v.data_ptr()) for (op, p), pp, v in zip(aggs, progs, vals)])
+    f = _lib.Fragment(ctypes.addressof(fc), len(fact), fact_key if join else -1, n_fact, ctypes.addressof(fp),
+                      len(fact_pred), key_bits, ctypes.addressof(dc), len(dim), dim_key, n_dim, ctypes.addressof(dp),
+                      len(dim_pred) if join else 0, len(group), ctypes.addressof(ga), ctypes.addressof(aa), len(aggs),
+                      topk, join_cap)
+    out = {"key": torch.empty(gcap, dtype=torch.int32, device=dev), "vals": vals,
+           "d_ngroups": torch.empty(1, dtype=torch.int64, device=dev), "d_join": torch.empty(1, dtype=torch.int64,
+                                                                                             device=dev),
+           "top_key": torch.empty(max(1, topk), dtype=torch.int32, device=dev),
+           "top_val": torch.empty(max(1, topk), dtype=torch.int64, device=dev),
+           "d_topk": torch.zeros(1, dtype=torch.int32, device=dev)}
+    o = _lib.FragmentOut(out["key"].data_ptr(), gcap, out["d_ngroups"].data_ptr(), out["d_join"].data_ptr(),
+                         out["top_key"].data_ptr(), out["top_val"].data_ptr(), out["d_topk"].data_ptr())
+    s = _stream(stream)
+    _run(lambda ws, sz: ctx.lib.tqp_fragment_run(ctx.h, ctypes.byref(f), ctypes.byref(o), ws, sz, s),
+         "tqp_fragment_run", dev)
+    return out
 
 
 def gather(ctx: Context, src, idx, d_n=None, stream=None):

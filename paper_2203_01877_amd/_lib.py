@@ -74,6 +74,30 @@ class ServerConfig(ctypes.Structure):
                 ("presort_mid", c_i32), ("reserved", c_i32)]
 
 
+AGG_COUNT, AGG_SUM, AGG_MIN, AGG_MAX, AGG_AVG, AGG_COUNT_DISTINCT = range(6)
+
+
+class GroupCol(ctypes.Structure):
+    _fields_ = [("col", c_i32), ("bits", c_i32)]
+
+
+class Agg(ctypes.Structure):
+    _fields_ = [("op", c_i32), ("nprog", c_i32), ("prog", c_vp), ("out", c_vp)]
+
+
+class Fragment(ctypes.Structure):
+    _fields_ = [("fact_cols", c_vp), ("n_fact_cols", c_i32), ("fact_key", c_i32), ("n_fact", c_i64),
+                ("fact_pred", c_vp), ("n_fact_pred", c_i32), ("key_bits", c_i32), ("dim_cols", c_vp),
+                ("n_dim_cols", c_i32), ("dim_key", c_i32), ("n_dim", c_i64), ("dim_pred", c_vp), ("n_dim_pred", c_i32),
+                ("n_group", c_i32), ("group", c_vp), ("aggs", c_vp), ("n_agg", c_i32), ("topk", c_i32),
+                ("join_cap", c_i64)]
+
+
+class FragmentOut(ctypes.Structure):
+    _fields_ = [("key", c_vp), ("gcap", c_i64), ("d_ngroups", c_vp), ("d_join", c_vp), ("top_key", c_vp),
+                ("top_val", c_vp), ("d_topk", c_vp)]
+
+
 CHAIN_MAX_TABLES, CHAIN_PK_SORTED, CHAIN_PK_DENSE = 8, 1, 2
 
 
@@ -134,6 +158,9 @@ def load() -> ctypes.CDLL:
     lib.tqp_join_chain.argtypes = [c_vp, ctypes.POINTER(ChainTable), c_int, ctypes.POINTER(c_vp), c_vp, c_vp,
                                    c_size_p, c_vp]
     lib.tqp_join_chain.restype = S
+    lib.tqp_fragment_run.argtypes = [c_vp, ctypes.POINTER(Fragment), ctypes.POINTER(FragmentOut), c_vp, c_size_p,
+                                     c_vp]
+    lib.tqp_fragment_run.restype = S
     lib.tqp_sort.argtypes = [c_vp, c_vp, c_vp, c_i64, c_vp, c_int, c_vp, c_vp, c_vp, c_size_p, c_vp]
     lib.tqp_sort.restype = S
     lib.tqp_join.argtypes = [c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_i64, c_vp, c_vp, c_vp, c_i64, c_vp,

@@ -19,7 +19,8 @@ namespace {
 
 constexpr int XP_MAX = 64;       // instructions
 constexpr int XS_MAX = 16;       // stack depth
-constexpr int XC_MAX = 8;        // columns
+constexpr int XC_MAX = 8;        // columns a program reads
+constexpr int XE_MAX_COLS = 64;  // columns a program may number
 constexpr int XE_BLOCK = 128;
 constexpr int XE_ROWS = 2;       // rows per thread
 
@@ -32,16 +33,18 @@ struct XProg {
     int32_t op[XP_MAX];
     int64_t arg[XP_MAX];
     const void* col[XC_MAX];
+    const int32_t* idx[XC_MAX];  // null: column c is read at the row itself; else at idx[c][row]
     int32_t type[XC_MAX];
     int32_t n;
     uint32_t used;               // bit c: the program reads column c
 };
 
 __device__ __forceinline__ int64_t x_load(const XProg& p, int c, int64_t row) {
+    const int64_t r = p.idx[c] ? (int64_t)p.idx[c][row] : row;
     switch (p.type[c]) {
-        case TQP_I8: return static_cast<const int8_t*>(p.col[c])[row];
-        case TQP_I32: return static_cast<const int32_t*>(p.col[c])[row];
-        default: return static_cast<const int64_t*>(p.col[c])[row];
+        case TQP_I8: return static_cast<const int8_t*>(p.col[c])[r];
+        case TQP_I32: return static_cast<const int32_t*>(p.col[c])[r];
+        default: return static_cast<const int64_t*>(p.col[c])[r];
     }
 }
 
@@ -153,6 +156,64 @@ int x_arity(int32_t op) {
 }
 
 }  // namespace
+
+// The program checked on the host (operators, operand counts, column
+// numbers, stack depth, one value left) and, when n > 0, evaluated for n (or
+// *d_n) rows.  The program may number up to XE_MAX_COLS columns, of which it
+// may read at most XC_MAX; columns read through idx[c] (when idx and idx[c]
+// are not null) are read at idx[c][row].
+tqp_status eval_program(tqp_ctx* ctx, const tqp_column* cols, const int32_t* const* idx, int ncols, int64_t n,
+                        const int64_t* d_n, const tqp_xinstr* prog, int nprog, int64_t* out, hipStream_t stream,
+                        const char* who, const char* label) {
+    if (nprog < 1 || nprog > XP_MAX) return fail(TQP_ERR_UNSUPPORTED, "%s: 1 to %d instructions", who, XP_MAX);
+    if (ncols < 0 || ncols > XE_MAX_COLS) return fail(TQP_ERR_UNSUPPORTED, "%s: %d columns", who, ncols);
+    XProg p{};
+    int slot[XE_MAX_COLS];
+    for (int c = 0; c < ncols; ++c) slot[c] = -1;
+    int used = 0;
+    // the stack depth before every instruction is known here: check the program once
+    int sp = 0, deepest = 1;
+    for (int pc = 0; pc < nprog; ++pc) {
+        const int32_t op = prog[pc].op;
+        if (op < 0 || op >= XO_COUNT) return fail(TQP_ERR_INVALID, "%s: unknown operator %d at %d", who, op, pc);
+        if (op == XO_COL && (prog[pc].arg < 0 || prog[pc].arg >= ncols))
+            return fail(TQP_ERR_INVALID, "%s: column %lld out of range at %d", who, (long long)prog[pc].arg, pc);
+        const int ar = x_arity(op);
+        if (sp < ar) return fail(TQP_ERR_INVALID, "%s: operator %d at %d lacks operands", who, op, pc);
+        sp = sp - ar + 1;
+        if (sp > XS_MAX) return fail(TQP_ERR_UNSUPPORTED, "%s: stack deeper than %d", who, XS_MAX);
+        deepest = sp > deepest ? sp : deepest;
+        p.op[pc] = op;
+        p.arg[pc] = prog[pc].arg;
+        if (op == XO_COL) {
+            // the columns the program reads get the kernel's column slots in order of first use
+            const int c = (int)prog[pc].arg;
+            if (slot[c] < 0) {
+                if (used == XC_MAX) return fail(TQP_ERR_UNSUPPORTED, "%s: more than %d columns read", who, XC_MAX);
+                const tqp_column& col = cols[c];
+                if (col.type != TQP_I8 && col.type != TQP_I32 && col.type != TQP_I64)
+                    return fail(TQP_ERR_INVALID, "%s: column %d has an unknown type", who, c);
+                if (n > 0 && !col.data) return fail(TQP_ERR_INVALID, "%s: column %d is null", who, c);
+                slot[c] = used;
+                p.col[used] = col.data;
+                p.type[used] = col.type;
+                p.idx[used] = idx ? idx[c] : nullptr;
+                p.used |= 1u << used;
+                ++used;
+            }
+            p.arg[pc] = slot[c];
+        }
+    }
+    if (sp != 1) return fail(TQP_ERR_INVALID, "%s: the program leaves %d values", who, sp);
+    p.n = nprog;
+    if (n == 0) return TQP_OK;
+    const size_t lds = (size_t)(deepest > 1 ? deepest - 1 : 1) * XE_ROWS * XE_BLOCK * sizeof(int64_t);
+    TQP_LAUNCH(ctx, stream, label,
+               k_eval<<<grid_for(n, XE_BLOCK * XE_ROWS, (int64_t)ctx->num_cus * 16), XE_BLOCK, lds, stream>>>(
+                   p, n, d_n, out, ctx->d_err));
+    return TQP_OK;
+}
+
 }  // namespace tqp
 
 using namespace tqp;
@@ -165,40 +226,13 @@ tqp_status tqp_eval(tqp_ctx* ctx, const tqp_column* cols, int ncols, int64_t n, 
     if (!ctx || n < 0 || ncols < 0 || (ncols > 0 && !cols) || !prog || (n > 0 && !out))
         return fail(TQP_ERR_INVALID, "tqp_eval: null pointer or negative size");
     if (ncols > XC_MAX) return fail(TQP_ERR_UNSUPPORTED, "tqp_eval: at most %d columns", XC_MAX);
-    if (nprog < 1 || nprog > XP_MAX) return fail(TQP_ERR_UNSUPPORTED, "tqp_eval: 1 to %d instructions", XP_MAX);
     if (n > MAX_ELEMS) return fail(TQP_ERR_UNSUPPORTED, "tqp_eval: n = %lld", (long long)n);
-    XProg p{};
     for (int c = 0; c < ncols; ++c) {
         if (cols[c].type != TQP_I8 && cols[c].type != TQP_I32 && cols[c].type != TQP_I64)
             return fail(TQP_ERR_INVALID, "tqp_eval: column %d has an unknown type", c);
         if (n > 0 && !cols[c].data) return fail(TQP_ERR_INVALID, "tqp_eval: column %d is null", c);
-        p.col[c] = cols[c].data;
-        p.type[c] = cols[c].type;
     }
-    // the stack depth before every instruction is known here: check the program once
-    int sp = 0, deepest = 1;
-    for (int pc = 0; pc < nprog; ++pc) {
-        const int32_t op = prog[pc].op;
-        if (op < 0 || op >= XO_COUNT) return fail(TQP_ERR_INVALID, "tqp_eval: unknown operator %d at %d", op, pc);
-        if (op == XO_COL && (prog[pc].arg < 0 || prog[pc].arg >= ncols))
-            return fail(TQP_ERR_INVALID, "tqp_eval: column %lld out of range at %d", (long long)prog[pc].arg, pc);
-        const int ar = x_arity(op);
-        if (sp < ar) return fail(TQP_ERR_INVALID, "tqp_eval: operator %d at %d lacks operands", op, pc);
-        sp = sp - ar + 1;
-        if (sp > XS_MAX) return fail(TQP_ERR_UNSUPPORTED, "tqp_eval: stack deeper than %d", XS_MAX);
-        deepest = sp > deepest ? sp : deepest;
-        p.op[pc] = op;
-        p.arg[pc] = prog[pc].arg;
-        if (op == XO_COL) p.used |= 1u << prog[pc].arg;
-    }
-    if (sp != 1) return fail(TQP_ERR_INVALID, "tqp_eval: the program leaves %d values", sp);
-    p.n = nprog;
-    if (n == 0) return TQP_OK;
-    const size_t lds = (size_t)(deepest > 1 ? deepest - 1 : 1) * XE_ROWS * XE_BLOCK * sizeof(int64_t);
-    TQP_LAUNCH(ctx, stream, "eval",
-               k_eval<<<grid_for(n, XE_BLOCK * XE_ROWS, (int64_t)ctx->num_cus * 16), XE_BLOCK, lds, stream>>>(p, n, d_n, out,
-                                                                                                   ctx->d_err));
-    return TQP_OK;
+    return eval_program(ctx, cols, nullptr, ncols, n, d_n, prog, nprog, out, stream, "tqp_eval", "eval");
 }
 
 }  // extern "C"

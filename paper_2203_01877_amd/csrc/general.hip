@@ -1,0 +1,568 @@
+// General fragments (tqp_fragment_run): the operators of Section 5 composed
+// by a descriptor instead of the two fixed fragment shapes.
+//
+//   1. predicates  Section 5.1's expressions: each side's predicate program is
+//                  evaluated once into a keep column (tqp_eval's kernel);
+//   2. join        Algorithm 1: both key columns radix-sorted with their row
+//                  ids, the keep column fused into the sort's first pass so
+//                  dropped rows are never written; the sort-based join gives
+//                  (fact row, dim row) pairs (late materialisation).  Without
+//                  a join the kept fact rows are compacted instead;
+//   3. group key   the group columns read through the pairs and packed into
+//                  one key (Algorithm 2's concatenated group columns);
+//   4. values      every aggregate's program evaluated over the joined rows,
+//                  its columns read through the pairs;
+//   5. group sort  Algorithm 2: the packed keys radix-sorted with the
+//                  joined-row index; for COUNT(DISTINCT v) the rows are first
+//                  sorted by v (two 32-bit passes) so the final stable sort
+//                  orders them by (key, v);
+//   6. runs        the first row of every run of equal keys compacted into the
+//                  group starts (a ballot per 64 rows and a decoupled
+//                  look-back), then one wave per group reduces its run: sum,
+//                  count, min, max, average and the number of value changes
+//                  (distinct values);
+//   7. top-k       ORDER BY the first aggregate DESC, key ASC LIMIT k, as
+//                  tqp_topk.
+// Every size after step 1 (kept rows, joined rows, groups) stays on the
+// device: the grids come from the caller's bounds and the kernels read the
+// counts.
+#include "filter.hpp"
+#include "fragment.hpp"
+
+namespace tqp {
+namespace {
+
+using JCfgGen = JoinCfg<256, 8, 4096>;
+constexpr int GF_FILTER_BLOCK = 256, GF_FILTER_ITEMS = 16;
+constexpr int GF_HEAD_BLOCK = 256, GF_HEAD_ITEMS = 8;
+constexpr int GF_AGG_BLOCK = 256;
+constexpr int GF_MAX_COLS = 64;
+
+// Sort source: the int32 key column with the row id as payload, rows whose
+// keep value is zero left out (keep null: every row).
+struct SrcKeepRow {
+    const int32_t* key;
+    const int64_t* keep;
+    int64_t n;
+    __device__ int64_t size() const { return n; }
+    __device__ bool load_key(int64_t i, uint32_t& k) const {
+        k = (uint32_t)key[i];
+        return keep ? keep[i] != 0 : true;
+    }
+    __device__ bool load(int64_t i, uint32_t& k, uint32_t& v) const {
+        k = (uint32_t)key[i];
+        v = (uint32_t)i;
+        return keep ? keep[i] != 0 : true;
+    }
+};
+
+// Sort source over the joined rows: row j = perm[i] (or i), key from an
+// int32 array (MODE 0), the low word of an int64 array (MODE 1) or its high
+// word with the sign bit flipped (MODE 2, so unsigned order is signed order);
+// the payload is j.
+template <int MODE>
+struct SrcPermKey {
+    const void* base;
+    const uint32_t* perm;
+    int64_t n_upper;
+    const int64_t* d_n;
+    __device__ int64_t size() const {
+        const int64_t n = *d_n;
+        return n < n_upper ? n : n_upper;
+    }
+    __device__ uint32_t key_of(int64_t j) const {
+        if constexpr (MODE == 0) return static_cast<const uint32_t*>(base)[j];
+        else if constexpr (MODE == 1) return (uint32_t)static_cast<const uint64_t*>(base)[j];
+        else return (uint32_t)(static_cast<const uint64_t*>(base)[j] >> 32) ^ 0x80000000u;
+    }
+    __device__ bool load_key(int64_t i, uint32_t& k) const {
+        k = key_of(perm ? (int64_t)perm[i] : i);
+        return true;
+    }
+    __device__ bool load(int64_t i, uint32_t& k, uint32_t& v) const {
+        const uint32_t j = perm ? perm[i] : (uint32_t)i;
+        k = key_of(j);
+        v = j;
+        return true;
+    }
+};
+
+struct GroupCols {
+    const void* col[TQP_FRAGMENT_MAX_GROUP_COLS];
+    int32_t type[TQP_FRAGMENT_MAX_GROUP_COLS];
+    int32_t side[TQP_FRAGMENT_MAX_GROUP_COLS];      // 0: read through the fact row, 1: the dim row
+    int32_t bits[TQP_FRAGMENT_MAX_GROUP_COLS];
+    int32_t n;
+};
+
+__device__ __forceinline__ int64_t gf_load(const void* col, int type, int64_t r) {
+    switch (type) {
+        case TQP_I8: return static_cast<const int8_t*>(col)[r];
+        case TQP_I32: return static_cast<const int32_t*>(col)[r];
+        default: return static_cast<const int64_t*>(col)[r];
+    }
+}
+
+// gkey[i] = the group columns of joined row i packed, first most significant.
+__global__ void __launch_bounds__(256)
+k_gf_pack(GroupCols g, const int32_t* li, const int32_t* ri, int64_t n_upper, const int64_t* d_n, uint32_t* gkey,
+          uint32_t* flags) {
+    int64_t n = *d_n;
+    n = n < n_upper ? n : n_upper;
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t v = 0;
+        for (int c = 0; c < g.n; ++c) {
+            const int64_t r = g.side[c] ? (int64_t)ri[i] : (int64_t)li[i];
+            const int64_t x = gf_load(g.col[c], g.type[c], r);
+            const int64_t lim = int64_t(1) << g.bits[c];
+            bad |= x < 0 || x >= lim;
+            v = (v << g.bits[c]) | (uint32_t)(x & (lim - 1));
+        }
+        gkey[i] = v;
+    }
+    if (__any(bad) && lane_id() == 0) set_flag(flags, FLAG_KEY_RANGE);
+}
+
+// Group starts: the positions i < n (n = *d_n, at most n_upper) of the
+// sorted keys where a run of equal keys begins, compacted in order into
+// start[]; *d_groups = their number.  Ballot per 64 rows, block scan,
+// decoupled look-back (as the filter).
+__global__ void __launch_bounds__(GF_HEAD_BLOCK)
+k_gf_heads(const uint32_t* skey, int64_t n_upper, const int64_t* d_n, int64_t* start, int64_t* d_groups,
+           uint64_t* status, uint32_t* tile_counter, uint32_t* flags) {
+    constexpr int TILE = GF_HEAD_BLOCK * GF_HEAD_ITEMS, W = GF_HEAD_BLOCK / WAVE;
+    __shared__ int64_t s_wave[W];
+    __shared__ int64_t s_base;
+    __shared__ uint32_t s_tile;
+    const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
+    int64_t n = *d_n;
+    n = n < n_upper ? n : n_upper;
+    if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    const int64_t ntiles = (n + TILE - 1) / TILE;
+    if (tile >= ntiles) {
+        if (ntiles == 0 && tile == 0 && tid == 0) *d_groups = 0;
+        return;
+    }
+    const int64_t chunk = tile * TILE + (int64_t)w * GF_HEAD_ITEMS * WAVE;
+    uint64_t m[GF_HEAD_ITEMS];
+    int64_t wc = 0;
+#pragma unroll
+    for (int j = 0; j < GF_HEAD_ITEMS; ++j) {
+        const int64_t i = chunk + j * WAVE + l;
+        const bool in = i < n;
+        const int64_t ic = in ? i : n - 1;
+        const bool head = in && (ic == 0 || skey[ic] != skey[ic - 1]);
+        m[j] = ballot(head);
+        wc += popc64(m[j]);
+    }
+    if (l == 0) s_wave[w] = wc;
+    __syncthreads();
+    if (w == 0) {
+        int64_t tot = 0;
+        for (int ww = 0; ww < W; ++ww) tot += s_wave[ww];
+        const int64_t base = lookback64(status, tile, tot, flags);
+        if (tid == 0) {
+            int64_t run = 0;
+            for (int ww = 0; ww < W; ++ww) { const int64_t x = s_wave[ww]; s_wave[ww] = run; run += x; }
+            s_base = base;
+            if (tile == ntiles - 1) *d_groups = base + tot;
+        }
+    }
+    __syncthreads();
+    int64_t pos = s_base + s_wave[w];
+#pragma unroll
+    for (int j = 0; j < GF_HEAD_ITEMS; ++j) {
+        const int64_t i = chunk + j * WAVE + l;
+        if ((m[j] >> l) & 1) start[pos + popc64(m[j] & lanemask_lt())] = i;
+        pos += popc64(m[j]);
+    }
+}
+
+struct AggSet {
+    const int64_t* val[TQP_FRAGMENT_MAX_AGGS];   // values per joined row (null for COUNT)
+    void* out[TQP_FRAGMENT_MAX_AGGS];
+    int32_t op[TQP_FRAGMENT_MAX_AGGS];
+    int32_t n;
+};
+
+__device__ __forceinline__ uint64_t gf_ord(int64_t x) { return (uint64_t)x ^ (uint64_t(1) << 63); }
+__device__ __forceinline__ int64_t gf_unord(uint64_t u) { return (int64_t)(u ^ (uint64_t(1) << 63)); }
+
+// One wave per group (grid-stride over the groups written): the run
+// [start[g], start[g + 1]) of the sorted keys, rows read through perm.
+__global__ void __launch_bounds__(GF_AGG_BLOCK)
+k_gf_agg(const uint32_t* skey, const uint32_t* perm, const int64_t* start, const int64_t* d_groups,
+         const int64_t* d_rows, int64_t rows_upper, AggSet a, const int64_t* dval, int32_t* out_key, int64_t gcap,
+         int64_t* d_ngroups, int64_t* d_written, uint32_t* flags) {
+    const int64_t G = *d_groups;
+    int64_t J = *d_rows;
+    J = J < rows_upper ? J : rows_upper;
+    const int64_t Gw = G < gcap ? G : gcap;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *d_ngroups = G;
+        *d_written = Gw;
+        if (G > gcap) set_flag(flags, FLAG_CAPACITY);
+    }
+    const int l = lane_id();
+    const int64_t wid = ((int64_t)blockIdx.x * GF_AGG_BLOCK + threadIdx.x) / WAVE;
+    const int64_t nw = (int64_t)gridDim.x * GF_AGG_BLOCK / WAVE;
+    for (int64_t g = wid; g < Gw; g += nw) {
+        const int64_t s = start[g], e = g + 1 < G ? start[g + 1] : J;
+        int64_t cnt = 0, dist = 0;
+        int64_t sum[TQP_FRAGMENT_MAX_AGGS];
+        uint64_t mn[TQP_FRAGMENT_MAX_AGGS], mx[TQP_FRAGMENT_MAX_AGGS];
+#pragma unroll
+        for (int k = 0; k < TQP_FRAGMENT_MAX_AGGS; ++k) { sum[k] = 0; mn[k] = ~uint64_t(0); mx[k] = 0; }
+        for (int64_t i = s + l; i < e; i += WAVE) {
+            const uint32_t j = perm[i];
+            ++cnt;
+#pragma unroll
+            for (int k = 0; k < TQP_FRAGMENT_MAX_AGGS; ++k) {
+                if (k < a.n && a.val[k]) {
+                    const int64_t v = a.val[k][j];
+                    sum[k] = (int64_t)((uint64_t)sum[k] + (uint64_t)v);
+                    const uint64_t o = gf_ord(v);
+                    mn[k] = o < mn[k] ? o : mn[k];
+                    mx[k] = o > mx[k] ? o : mx[k];
+                }
+            }
+            // rows are in (key, distinct value) order: a value starts where it differs from the row before
+            if (dval) dist += (i == s || dval[j] != dval[perm[i - 1]]) ? 1 : 0;
+        }
+        cnt = wave_sum(cnt);
+        dist = wave_sum(dist);
+        if (l == 0) out_key[g] = (int32_t)skey[s];
+#pragma unroll
+        for (int k = 0; k < TQP_FRAGMENT_MAX_AGGS; ++k) {
+            if (k >= a.n) continue;
+            const int64_t sk = wave_sum(sum[k]);
+            const uint64_t lo = wave_min(mn[k]), hi = wave_max(mx[k]);
+            if (l != 0) continue;
+            int64_t* o64 = static_cast<int64_t*>(a.out[k]);
+            switch (a.op[k]) {
+                case TQP_AGG_COUNT: o64[g] = cnt; break;
+                case TQP_AGG_SUM: o64[g] = sk; break;
+                case TQP_AGG_MIN: o64[g] = gf_unord(lo); break;
+                case TQP_AGG_MAX: o64[g] = gf_unord(hi); break;
+                case TQP_AGG_AVG: static_cast<double*>(a.out[k])[g] = (double)sk / (double)cnt; break;
+                default: o64[g] = dist; break;
+            }
+        }
+    }
+}
+
+template <class Cfg>
+struct GenBufs {
+    bool join = false;
+    int distinct = -1;                       // the COUNT(DISTINCT) aggregate, if any
+    int gbits = 1;
+    int64_t* fkeep = nullptr;
+    int64_t* dkeep = nullptr;
+    RadixBufs<Cfg, uint32_t> fsort, dsort, sa, sb, sc;
+    JoinBufs jb;
+    uint32_t *fsk = nullptr, *fsv = nullptr, *dsk = nullptr, *dsv = nullptr;
+    uint64_t* fstatus = nullptr;             // no join: the compaction of the kept fact rows
+    uint32_t* fcounter = nullptr;
+    int32_t *li = nullptr, *ri = nullptr;
+    int64_t* d_join = nullptr;
+    uint32_t* gkey = nullptr;
+    int64_t* vals[TQP_FRAGMENT_MAX_AGGS] = {};
+    uint32_t *ka = nullptr, *pa = nullptr, *kb = nullptr, *pb = nullptr, *kc = nullptr, *pc = nullptr;
+    int64_t* gstart = nullptr;
+    uint64_t* hstatus = nullptr;
+    uint32_t* hcounter = nullptr;
+    int64_t* d_groups = nullptr;
+    int64_t* d_written = nullptr;
+    TopkBufs topk;
+    int64_t* tcnt = nullptr;                 // the top rows' third column (not returned)
+};
+
+int gf_group_bits(const tqp_fragment& f) {
+    int b = 0;
+    for (int i = 0; i < f.n_group; ++i) b += f.group[i].bits;
+    return b > 0 ? b : 1;
+}
+
+template <class Cfg>
+void gen_reserve(Arena& a, const tqp_fragment& f, const tqp_fragment_out& o, GenBufs<Cfg>& b) {
+    const int kb = norm_key_bits(f.key_bits);
+    const int64_t N = f.n_fact, J = f.join_cap;
+    b.join = f.fact_key >= 0;
+    b.gbits = gf_group_bits(f);
+    for (int k = 0; k < f.n_agg; ++k)
+        if (f.aggs[k].op == TQP_AGG_COUNT_DISTINCT) b.distinct = k;
+    if (f.n_fact_pred > 0) b.fkeep = a.scratch<int64_t>(N);
+    if (b.join) {
+        if (f.n_dim_pred > 0) b.dkeep = a.scratch<int64_t>(f.n_dim);
+        b.fsort = radix_reserve<Cfg, uint32_t>(a, N, kb);
+        b.dsort = radix_reserve<Cfg, uint32_t>(a, f.n_dim, kb);
+        b.fsk = a.scratch<uint32_t>(N);
+        b.fsv = a.scratch<uint32_t>(N);
+        b.dsk = a.scratch<uint32_t>(f.n_dim);
+        b.dsv = a.scratch<uint32_t>(f.n_dim);
+        b.jb = join_reserve<JCfgGen>(a, N);
+        b.ri = a.scratch<int32_t>(J);
+    } else {
+        const int64_t tiles = (N + GF_FILTER_BLOCK * GF_FILTER_ITEMS - 1) / (GF_FILTER_BLOCK * GF_FILTER_ITEMS);
+        b.fstatus = a.zero<uint64_t>(tiles);
+        b.fcounter = a.zero<uint32_t>(1);
+    }
+    b.li = a.scratch<int32_t>(J);
+    b.d_join = a.zero<int64_t>(1);
+    b.gkey = a.scratch<uint32_t>(J);
+    for (int k = 0; k < f.n_agg; ++k)
+        if (f.aggs[k].op != TQP_AGG_COUNT) b.vals[k] = a.scratch<int64_t>(J);
+    if (b.distinct >= 0) {
+        b.sa = radix_reserve<Cfg, uint32_t>(a, J, 32);
+        b.sb = radix_reserve<Cfg, uint32_t>(a, J, 32);
+        b.ka = a.scratch<uint32_t>(J);
+        b.pa = a.scratch<uint32_t>(J);
+        b.kb = a.scratch<uint32_t>(J);
+        b.pb = a.scratch<uint32_t>(J);
+    }
+    b.sc = radix_reserve<Cfg, uint32_t>(a, J, b.gbits);
+    b.kc = a.scratch<uint32_t>(J);
+    b.pc = a.scratch<uint32_t>(J);
+    b.gstart = a.scratch<int64_t>(J + 1);
+    const int64_t htiles = (J + GF_HEAD_BLOCK * GF_HEAD_ITEMS - 1) / (GF_HEAD_BLOCK * GF_HEAD_ITEMS);
+    b.hstatus = a.zero<uint64_t>(htiles);
+    b.hcounter = a.zero<uint32_t>(1);
+    b.d_groups = a.zero<int64_t>(1);
+    b.d_written = a.zero<int64_t>(1);
+    if (f.topk > 0) {
+        b.topk = topk_reserve(a, o.gcap, f.topk);
+        b.tcnt = a.scratch<int64_t>(f.topk);
+    }
+}
+
+// The joined row's columns (fact, then dim) and the row arrays they are read through.
+struct JoinedCols {
+    tqp_column col[GF_MAX_COLS];
+    const int32_t* idx[GF_MAX_COLS];
+    int n = 0;
+};
+
+template <class Cfg>
+tqp_status gen_launch(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_out& o, const GenBufs<Cfg>& b,
+                      hipStream_t s) {
+    const int kb = norm_key_bits(f.key_bits);
+    const int64_t N = f.n_fact, J = f.join_cap;
+    tqp_status st;
+    // 1. predicates
+    if (b.fkeep && N > 0 &&
+        (st = eval_program(ctx, f.fact_cols, nullptr, f.n_fact_cols, N, nullptr, f.fact_pred, f.n_fact_pred, b.fkeep,
+                           s, "tqp_fragment_run", "fragment_fact_pred")) != TQP_OK)
+        return st;
+    if (b.dkeep && f.n_dim > 0 &&
+        (st = eval_program(ctx, f.dim_cols, nullptr, f.n_dim_cols, f.n_dim, nullptr, f.dim_pred, f.n_dim_pred, b.dkeep,
+                           s, "tqp_fragment_run", "fragment_dim_pred")) != TQP_OK)
+        return st;
+    // 2. join, or the kept fact rows
+    if (b.join) {
+        SrcKeepRow fs{static_cast<const int32_t*>(f.fact_cols[f.fact_key].data), b.fkeep, N};
+        SrcKeepRow ds{static_cast<const int32_t*>(f.dim_cols[f.dim_key].data), b.dkeep, f.n_dim};
+        if ((st = radix_launch<Cfg, uint32_t>(b.fsort, fs, N, true, nullptr, key_mask_for(kb), b.fsk, b.fsv, ctx, s,
+                                              "fragment_sort_fact", "fragment_sort_fact")) != TQP_OK)
+            return st;
+        if ((st = radix_launch<Cfg, uint32_t>(b.dsort, ds, f.n_dim, true, nullptr, key_mask_for(kb), b.dsk, b.dsv,
+                                              ctx, s, "fragment_sort_dim", "fragment_sort_dim")) != TQP_OK)
+            return st;
+        EmitPairs e{b.li, b.ri, J};
+        if ((st = join_launch<JCfgGen, uint32_t, uint32_t, EmitPairs>(ctx, s, "fragment_join", b.jb, b.fsk, b.fsv, N,
+                                                                     b.fsort.d_cnt, b.dsk, b.dsv, f.n_dim,
+                                                                     b.dsort.d_cnt, b.d_join, J, e)) != TQP_OK)
+            return st;
+    } else {
+        FilterPreds fp{};
+        if (b.fkeep) {
+            fp.np = 1;
+            fp.col[0] = b.fkeep;
+            fp.type[0] = TQP_I64;
+            fp.op[0] = CMP_NE;
+            fp.k[0] = 0;
+        }
+        constexpr int64_t TILE = GF_FILTER_BLOCK * GF_FILTER_ITEMS;
+        TQP_LAUNCH(ctx, s, "fragment_rows",
+                   (k_filter<GF_FILTER_BLOCK, GF_FILTER_ITEMS><<<grid_for(N, TILE, 0), GF_FILTER_BLOCK, 0, s>>>(
+                       fp, N, nullptr, b.li, nullptr, J, b.d_join, b.fstatus, b.fcounter, ctx->d_err)));
+    }
+    if (o.d_join) TQP_TRY_HIP(hipMemcpyAsync(o.d_join, b.d_join, 8, hipMemcpyDeviceToDevice, s));
+    // the joined rows' columns: fact columns through li, dim columns through ri
+    JoinedCols jc;
+    for (int c = 0; c < f.n_fact_cols; ++c) {
+        jc.col[jc.n] = f.fact_cols[c];
+        jc.idx[jc.n++] = b.li;
+    }
+    if (b.join)
+        for (int c = 0; c < f.n_dim_cols; ++c) {
+            jc.col[jc.n] = f.dim_cols[c];
+            jc.idx[jc.n++] = b.ri;
+        }
+    // 3. group key
+    GroupCols g{};
+    g.n = f.n_group;
+    for (int i = 0; i < f.n_group; ++i) {
+        const int c = f.group[i].col;
+        g.col[i] = jc.col[c].data;
+        g.type[i] = jc.col[c].type;
+        g.side[i] = c >= f.n_fact_cols ? 1 : 0;
+        g.bits[i] = f.group[i].bits;
+    }
+    TQP_LAUNCH(ctx, s, "fragment_pack",
+               k_gf_pack<<<grid_for(J, 256 * 4, (int64_t)ctx->num_cus * 8), 256, 0, s>>>(g, b.li, b.ri, J, b.d_join,
+                                                                                        b.gkey, ctx->d_err));
+    // 4. aggregate values (an empty side joins nothing: no row is read, and
+    // its columns may be null)
+    const bool no_rows = N == 0 || (b.join && f.n_dim == 0);
+    for (int k = 0; k < f.n_agg; ++k) {
+        if (!b.vals[k] || no_rows) continue;
+        if ((st = eval_program(ctx, jc.col, jc.idx, jc.n, J, b.d_join, f.aggs[k].prog, f.aggs[k].nprog, b.vals[k], s,
+                               "tqp_fragment_run", "fragment_value")) != TQP_OK)
+            return st;
+    }
+    // 5. group sort (distinct values first, low word then high word)
+    const uint32_t* perm_in = nullptr;
+    if (b.distinct >= 0) {
+        SrcPermKey<1> a1{b.vals[b.distinct], nullptr, J, b.d_join};
+        if ((st = radix_launch<Cfg, uint32_t>(b.sa, a1, J, true, nullptr, ~0u, b.ka, b.pa, ctx, s, "fragment_sort_value",
+                                              "fragment_sort_value")) != TQP_OK)
+            return st;
+        SrcPermKey<2> a2{b.vals[b.distinct], b.pa, J, b.d_join};
+        if ((st = radix_launch<Cfg, uint32_t>(b.sb, a2, J, true, nullptr, ~0u, b.kb, b.pb, ctx, s, "fragment_sort_value",
+                                              "fragment_sort_value")) != TQP_OK)
+            return st;
+        perm_in = b.pb;
+    }
+    SrcPermKey<0> a3{b.gkey, perm_in, J, b.d_join};
+    if ((st = radix_launch<Cfg, uint32_t>(b.sc, a3, J, true, nullptr, key_mask_for(b.gbits), b.kc, b.pc, ctx, s,
+                                          "fragment_sort_group", "fragment_sort_group")) != TQP_OK)
+        return st;
+    // 6. runs: group starts, then one wave per group
+    TQP_LAUNCH(ctx, s, "fragment_heads",
+               k_gf_heads<<<grid_for(J, GF_HEAD_BLOCK * GF_HEAD_ITEMS, 0), GF_HEAD_BLOCK, 0, s>>>(
+                   b.kc, J, b.d_join, b.gstart, b.d_groups, b.hstatus, b.hcounter, ctx->d_err));
+    AggSet as{};
+    as.n = f.n_agg;
+    for (int k = 0; k < f.n_agg; ++k) {
+        as.val[k] = b.vals[k];
+        as.out[k] = f.aggs[k].out;
+        as.op[k] = f.aggs[k].op;
+    }
+    const int64_t* dval = b.distinct >= 0 ? b.vals[b.distinct] : nullptr;
+    const int64_t waves = o.gcap < (int64_t)ctx->num_cus * 64 ? o.gcap : (int64_t)ctx->num_cus * 64;
+    TQP_LAUNCH(ctx, s, "fragment_agg",
+               k_gf_agg<<<grid_for(waves, GF_AGG_BLOCK / WAVE, 0), GF_AGG_BLOCK, 0, s>>>(
+                   b.kc, b.pc, b.gstart, b.d_groups, b.d_join, J, as, dval, o.key, o.gcap, o.d_ngroups, b.d_written,
+                   ctx->d_err));
+    // 7. top-k over the first aggregate
+    if (f.topk > 0) {
+        const int64_t* v0 = static_cast<const int64_t*>(f.aggs[0].out);
+        if ((st = topk_launch(b.topk, o.key, v0, v0, b.d_written, f.topk, o.top_key, o.top_val, b.tcnt, o.d_topk, s,
+                              ctx)) != TQP_OK)
+            return st;
+    }
+    return TQP_OK;
+}
+
+tqp_status check_general(tqp_ctx* ctx, const tqp_fragment* f, const tqp_fragment_out* o) {
+    const char* who = "tqp_fragment_run";
+    if (!f || !o) return fail(TQP_ERR_INVALID, "%s: null fragment or output", who);
+    if (f->n_fact < 0 || f->n_dim < 0 || f->join_cap < 0 || o->gcap < 0) return fail(TQP_ERR_INVALID, "%s: negative size", who);
+    if (f->n_fact > MAX_ELEMS || f->n_dim > MAX_ELEMS || f->join_cap > MAX_ELEMS || o->gcap > MAX_ELEMS)
+        return fail(TQP_ERR_UNSUPPORTED, "%s: too large", who);
+    const bool join = f->fact_key >= 0;
+    const int nd = join ? f->n_dim_cols : 0;
+    if (f->n_fact_cols < 1 || f->n_fact_cols + nd > GF_MAX_COLS || (join && f->n_dim_cols < 1) ||
+        !f->fact_cols || (join && !f->dim_cols))
+        return fail(TQP_ERR_INVALID, "%s: columns", who);
+    auto col_ok = [&](const tqp_column& c, int64_t rows) {
+        return (c.type == TQP_I8 || c.type == TQP_I32 || c.type == TQP_I64) && (rows == 0 || c.data);
+    };
+    for (int c = 0; c < f->n_fact_cols; ++c)
+        if (!col_ok(f->fact_cols[c], f->n_fact)) return fail(TQP_ERR_INVALID, "%s: fact column %d", who, c);
+    for (int c = 0; c < nd; ++c)
+        if (!col_ok(f->dim_cols[c], f->n_dim)) return fail(TQP_ERR_INVALID, "%s: dim column %d", who, c);
+    if (join) {
+        if (f->fact_key >= f->n_fact_cols || f->fact_cols[f->fact_key].type != TQP_I32 || f->dim_key < 0 ||
+            f->dim_key >= f->n_dim_cols || f->dim_cols[f->dim_key].type != TQP_I32)
+            return fail(TQP_ERR_INVALID, "%s: join keys must be int32 columns", who);
+    }
+    if (f->n_group < 0 || f->n_group > TQP_FRAGMENT_MAX_GROUP_COLS || (f->n_group > 0 && !f->group))
+        return fail(TQP_ERR_UNSUPPORTED, "%s: %d group columns", who, f->n_group);
+    int bits = 0;
+    for (int i = 0; i < f->n_group; ++i) {
+        if (f->group[i].col < 0 || f->group[i].col >= f->n_fact_cols + nd || f->group[i].bits < 1)
+            return fail(TQP_ERR_INVALID, "%s: group column %d", who, i);
+        bits += f->group[i].bits;
+    }
+    if (bits > 31) return fail(TQP_ERR_UNSUPPORTED, "%s: group key of %d bits", who, bits);
+    if (f->n_agg < 0 || f->n_agg > TQP_FRAGMENT_MAX_AGGS || (f->n_agg > 0 && !f->aggs))
+        return fail(TQP_ERR_UNSUPPORTED, "%s: %d aggregates", who, f->n_agg);
+    int ndist = 0;
+    for (int k = 0; k < f->n_agg; ++k) {
+        const tqp_agg& a = f->aggs[k];
+        if (a.op < TQP_AGG_COUNT || a.op > TQP_AGG_COUNT_DISTINCT)
+            return fail(TQP_ERR_INVALID, "%s: aggregate %d: op %d", who, k, a.op);
+        if (o->gcap > 0 && !a.out) return fail(TQP_ERR_INVALID, "%s: aggregate %d has no output", who, k);
+        ndist += a.op == TQP_AGG_COUNT_DISTINCT;
+    }
+    if (ndist > 1) return fail(TQP_ERR_UNSUPPORTED, "%s: at most one COUNT(DISTINCT)", who);
+    if (f->topk < 0 || f->topk > 1024 || (f->topk > 0 && (f->n_agg < 1 || f->aggs[0].op == TQP_AGG_AVG)))
+        return fail(TQP_ERR_UNSUPPORTED, "%s: topk %d (1..1024 over an integer first aggregate)", who, f->topk);
+    if (f->topk > 0 && (!o->top_key || !o->top_val || !o->d_topk)) return fail(TQP_ERR_INVALID, "%s: top outputs", who);
+    if (!o->key || !o->d_ngroups) return fail(TQP_ERR_INVALID, "%s: null output", who);
+    // every program checked before anything is launched
+    tqp_status st;
+    if (f->n_fact_pred > 0 &&
+        (st = eval_program(ctx, f->fact_cols, nullptr, f->n_fact_cols, 0, nullptr, f->fact_pred, f->n_fact_pred,
+                           nullptr, nullptr, "tqp_fragment_run: fact predicate", "")) != TQP_OK)
+        return st;
+    if (join && f->n_dim_pred > 0 &&
+        (st = eval_program(ctx, f->dim_cols, nullptr, f->n_dim_cols, 0, nullptr, f->dim_pred, f->n_dim_pred, nullptr,
+                           nullptr, "tqp_fragment_run: dim predicate", "")) != TQP_OK)
+        return st;
+    JoinedCols jc;
+    for (int c = 0; c < f->n_fact_cols; ++c) jc.col[jc.n++] = f->fact_cols[c];
+    for (int c = 0; c < nd; ++c) jc.col[jc.n++] = f->dim_cols[c];
+    for (int k = 0; k < f->n_agg; ++k) {
+        const tqp_agg& a = f->aggs[k];
+        if (a.op == TQP_AGG_COUNT) continue;
+        if (!a.prog) return fail(TQP_ERR_INVALID, "%s: aggregate %d has no program", who, k);
+        if ((st = eval_program(ctx, jc.col, nullptr, jc.n, 0, nullptr, a.prog, a.nprog, nullptr, nullptr,
+                               "tqp_fragment_run: aggregate", "")) != TQP_OK)
+            return st;
+    }
+    return TQP_OK;
+}
+
+}  // namespace
+}  // namespace tqp
+
+using namespace tqp;
+
+extern "C" tqp_status tqp_fragment_run(tqp_ctx* ctx, const tqp_fragment* f, const tqp_fragment_out* o, void* ws,
+                                       size_t* ws_bytes, hipStream_t stream) {
+    clear_error();
+    if (!ctx) return fail(TQP_ERR_INVALID, "tqp_fragment_run: null context");
+    tqp_status st = check_general(ctx, f, o);
+    if (st != TQP_OK) return st;
+    tqp_fragment fd = *f;
+    if (fd.fact_key < 0) {
+        fd.n_dim_cols = 0;
+        fd.n_dim = 0;
+        fd.n_dim_pred = 0;
+    }
+    return with_radix_cfg(ctx->digit_bits, [&](auto cfg) -> tqp_status {
+        using Cfg = decltype(cfg);
+        GenBufs<Cfg> b;
+        Arena a;
+        auto plan = [&](Arena& ar) { gen_reserve<Cfg>(ar, fd, *o, b); };
+        tqp_status s2 = with_workspace(ctx, ws, ws_bytes, stream, plan, a);
+        if (s2 != TQP_OK || !ws) return s2;
+        if ((s2 = fill_zero(a.base, a.zsize, stream, ctx)) != TQP_OK) return s2;
+        return gen_launch<Cfg>(ctx, fd, *o, b, stream);
+    });
+}

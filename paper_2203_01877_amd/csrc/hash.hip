@@ -10,11 +10,11 @@
 // equal keys and only equal keys share h), and each partition is joined in
 // LDS, where a table build and its probes cost no HBM traffic:
 //
-//   partition  one radix pass per side over the top P bits of h (the sort's
-//              histogram + pre-counted pass), rows carried as (h, row);
-//   plan       one small kernel turns the two digit histograms into the
-//              partition starts and a list of work items: (partition, chunk
-//              of left rows);
+//   partition  radix passes per side over the top P bits of h (the sort's
+//              histogram, a pre-counted 8-bit pass and, for P > 8, a second
+//              pass), rows carried as (h, row);
+//   plan       the partition starts (one search per partition) and a list of
+//              work items: (partition, chunk of left rows);
 //   join       persistent blocks take items.  For every chunk of at most
 //              PJ_RCAP right rows of the item's partition the block builds
 //              an LDS table keyed by key + 1: one slot per distinct key
@@ -44,7 +44,7 @@ constexpr int PJ_RCAP = 3072;                    // right rows per table build
 constexpr int PJ_LOG2S = 13;                     // table slots: 8192 (load factor <= 0.375)
 constexpr int PJ_S = 1 << PJ_LOG2S;
 constexpr int PJ_LCHUNK = 16384;                 // left rows per work item
-constexpr int PJ_MAXP = 11;                      // partition bits: one 11-bit radix pass
+constexpr int PJ_MAXP = 11;                      // partition bits: at most two 8-bit radix passes
 constexpr int PJ_LANE_MAX = 4;                   // longer runs are written by the whole wave
 constexpr int PJ_PLAN_BLOCK = 1024;
 
@@ -87,40 +87,50 @@ constexpr uint32_t pj_inv(uint32_t a) {
 constexpr uint32_t PJ_INV = pj_inv(PJ_MUL);
 static_assert(PJ_MUL * PJ_INV == 1u, "PJ_INV inverts PJ_MUL");
 
-// Partition starts of both sides (from the partition pass's digit
-// histograms: the rows with a smaller top-P value come first), and the work
-// items: a partition with rows on both sides gives ceil(left rows / LCHUNK)
-// items.  One block; writes lstart / rstart [np + 1] and item_pre [np + 1].
+// Start of every partition in the partitioned hashes of one side: start[p]
+// = first row whose top P bits of h are >= p, start[2^P] = the row count (one
+// binary search per partition).
+__global__ void __launch_bounds__(256)
+k_pj_bounds(const uint32_t* h, const int64_t* d_cnt, int P, int64_t* start) {
+    const int64_t np = int64_t(1) << P;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > np) return;
+    const int64_t n = *d_cnt;
+    if (p == np) {
+        start[p] = n;
+        return;
+    }
+    const int sh = 32 - P;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)(h[mid] >> sh) < p) lo = mid + 1;
+        else hi = mid;
+    }
+    start[p] = lo;
+}
+
+// The work items: a partition with rows on both sides gives ceil(left rows /
+// LCHUNK) items; item_pre[p] = the items of the partitions before p (np + 1
+// entries).  One block.
 __global__ void __launch_bounds__(PJ_PLAN_BLOCK)
-k_pj_plan(const uint32_t* hist_l, const uint32_t* hist_r, int np, int64_t* lstart, int64_t* rstart,
-          int64_t* item_pre) {
+k_pj_plan(const int64_t* lstart, const int64_t* rstart, int np, int64_t* item_pre) {
     __shared__ int64_t s_w[PJ_PLAN_BLOCK / WAVE];
-    __shared__ int64_t s_carry[3];
-    if (threadIdx.x == 0) { s_carry[0] = 0; s_carry[1] = 0; s_carry[2] = 0; }
+    __shared__ int64_t s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
     __syncthreads();
     for (int p0 = 0; p0 < np; p0 += PJ_PLAN_BLOCK) {
         const int p = p0 + threadIdx.x;
-        const int64_t nl = p < np ? hist_l[p] : 0, nr = p < np ? hist_r[p] : 0;
+        const int64_t nl = p < np ? lstart[p + 1] - lstart[p] : 0, nr = p < np ? rstart[p + 1] - rstart[p] : 0;
         const int64_t it = (nl > 0 && nr > 0) ? (nl + PJ_LCHUNK - 1) / PJ_LCHUNK : 0;
-        int64_t tot;
-        const int64_t el = block_excl_sum<PJ_PLAN_BLOCK>(nl, s_w, &tot);
-        int64_t tr, ti;
-        const int64_t er = block_excl_sum<PJ_PLAN_BLOCK>(nr, s_w, &tr);
+        int64_t ti;
         const int64_t ei = block_excl_sum<PJ_PLAN_BLOCK>(it, s_w, &ti);
-        if (p < np) {
-            lstart[p] = s_carry[0] + el;
-            rstart[p] = s_carry[1] + er;
-            item_pre[p] = s_carry[2] + ei;
-        }
+        if (p < np) item_pre[p] = s_carry + ei;
         __syncthreads();
-        if (threadIdx.x == 0) { s_carry[0] += tot; s_carry[1] += tr; s_carry[2] += ti; }
+        if (threadIdx.x == 0) s_carry += ti;
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        lstart[np] = s_carry[0];
-        rstart[np] = s_carry[1];
-        item_pre[np] = s_carry[2];
-    }
+    if (threadIdx.x == 0) item_pre[np] = s_carry;
 }
 
 struct PjSmem {
@@ -337,7 +347,7 @@ tqp_status tqp_hash_join(tqp_ctx* ctx, const int32_t* lkey, const int32_t* lrow,
     if (nl > MAX_ELEMS || nr > MAX_ELEMS) return fail(TQP_ERR_UNSUPPORTED, "tqp_hash_join: input too large");
     const int P = pj_bits(nr);
     const int np = 1 << P;
-    using Cfg = R11;
+    using Cfg = R8;            // P > 8 bits take two passes: 8-bit digit runs write longer runs than one 11-bit pass
     RadixBufs<Cfg, uint32_t> lb, rb;
     uint32_t *lh = nullptr, *lv = nullptr, *rh = nullptr, *rv = nullptr, *counter = nullptr;
     int64_t *lstart = nullptr, *rstart = nullptr, *item_pre = nullptr, *total = nullptr;
@@ -368,8 +378,12 @@ tqp_status tqp_hash_join(tqp_ctx* ctx, const int32_t* lkey, const int32_t* lrow,
     if ((st = radix_launch<Cfg, uint32_t>(rb, rs, nr, true, nullptr, ~0u, rh, rv, ctx, stream, "hashjoin_part_r",
                                           "hashjoin_part_r")) != TQP_OK)
         return st;
+    TQP_LAUNCH(ctx, stream, "hashjoin_bounds",
+               k_pj_bounds<<<grid_for(np + 1, 256, 0), 256, 0, stream>>>(lh, lb.d_cnt, P, lstart));
+    TQP_LAUNCH(ctx, stream, "hashjoin_bounds",
+               k_pj_bounds<<<grid_for(np + 1, 256, 0), 256, 0, stream>>>(rh, rb.d_cnt, P, rstart));
     TQP_LAUNCH(ctx, stream, "hashjoin_plan",
-               k_pj_plan<<<1, PJ_PLAN_BLOCK, 0, stream>>>(lb.hist, rb.hist, np, lstart, rstart, item_pre));
+               k_pj_plan<<<1, PJ_PLAN_BLOCK, 0, stream>>>(lstart, rstart, np, item_pre));
     static const int per_cu = [] {
         int b = 2;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_pj_join, PJ_BLOCK, 0) != hipSuccess) b = 2;

@@ -1,0 +1,173 @@
+"""General fragments (tqp_fragment_run) against the oracle's general fragment: random descriptors
+(predicate programs on both sides, an equi-join or none, one or two packed group columns or none,
+COUNT / SUM / MIN / MAX / AVG / COUNT(DISTINCT) over random value programs, an optional top-k) at
+sizes that span many tiles with ragged tails; and the two fixed workloads written as descriptors
+(the flags fragment of configs 0 / 1 and a scaled custkey fragment) against their own oracles."""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+import pins
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(hip):
+    return hip.Context(0)
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _np(t, n=None):
+    a = t.cpu().numpy()
+    return a if n is None else a[:n]
+
+
+def _check(got, want, topk):
+    G = int(_np(got["d_ngroups"])[0])
+    assert G == want["groups"]
+    assert int(_np(got["d_join"])[0]) == want["join_rows"]
+    assert np.array_equal(_np(got["key"], G), want["key"])
+    for g, w in zip(got["vals"], want["vals"]):
+        assert np.array_equal(_np(g, G).view(np.int64), np.asarray(w).view(np.int64))
+    if topk:
+        k = int(_np(got["d_topk"])[0])
+        assert k == len(want["top_key"])
+        assert np.array_equal(_np(got["top_key"], k), want["top_key"])
+        assert np.array_equal(_np(got["top_val"], k), want["top_val"])
+
+
+def _tables(rng, n, m, fk_hi, dup):
+    fact = [rng.integers(0, fk_hi, n).astype(np.int32), rng.integers(-1000, 1000, n).astype(np.int32),
+            rng.integers(-1000, 1000, n).astype(np.int64), rng.integers(0, 4, n).astype(np.int8),
+            rng.integers(0, 2557, n).astype(np.int32)]
+    pk = rng.integers(0, fk_hi, m) if dup else rng.permutation(max(m, fk_hi))[:m]
+    dim = [pk.astype(np.int32), rng.integers(0, 5, m).astype(np.int8), rng.integers(-500, 500, m).astype(np.int32)]
+    return fact, dim
+
+
+def _random_case(trial):
+    O = oracle
+    rng = np.random.default_rng(9000 + trial)
+    n = int(rng.choice([1000, 4097, 60_001, 250_003]))
+    m = int(rng.choice([300, 20_011]))
+    fk_hi = int(m * rng.choice([1.0, 1.25, 4.0]))              # match rates 1, 0.8 and 0.25
+    dup = trial % 3 == 0                                          # repeated dim keys: a many-to-many join
+    fact, dim = _tables(rng, n, m, fk_hi, dup)
+    join = trial % 5 != 4
+    nf, nd = len(fact), len(dim)
+    ncol = nf + (nd if join else 0)
+    fp = pins._pred_expr(rng, fact)[0] if trial % 4 else []
+    dp = pins._pred_expr(rng, dim)[0] if join and trial % 3 == 1 else []
+    if join:
+        group = [[(3, 2)], [(3, 2), (nf + 1, 3)], [(nf + 1, 3), (4, 12)], [(nf + 2, 10)], []][trial % 5]
+    else:
+        group = [(3, 2), (1, 11)]                                 # fact column 1 holds negative values
+    ops = [O.AGG_SUM, O.AGG_COUNT, O.AGG_MIN, O.AGG_MAX, O.AGG_AVG]
+    if trial % 2 == 0:
+        ops.append(O.AGG_COUNT_DISTINCT)
+    aggs = [(op, [] if op == O.AGG_COUNT else pins._value_expr(rng, ncol)[0]) for op in ops]
+    topk = int(rng.choice([0, 1, 10, 100]))
+    kb = datagen.bits_for(max(fk_hi, m, 2))
+    return fact, dim if join else None, fp, dp, group, aggs, topk, kb
+
+
+@pytest.mark.parametrize("trial", range(16))
+def test_general_random(hip, ctx, trial):
+    """Random descriptors; a group column with values outside its width (dim column 2, fact column 1
+    hold negative values) is masked into the key and raises the key-range flag, as in the oracle."""
+    fact, dim, fp, dp, group, aggs, topk, kb = _random_case(trial)
+    want = oracle.fragment_general(fact, dim, fp, dp, 0, 0, group, aggs, topk=topk, gcap=1 << 20)
+    got = hip.fragment_run(ctx, [_dev(c) for c in fact], [_dev(c) for c in dim] if dim is not None else None, fp, dp,
+                           0, 0, group, aggs, topk=topk, key_bits=kb, join_cap=max(1, want["join_rows"]),
+                           gcap=max(1, want["groups"]))
+    assert ctx.errors() == (hip.DEVERR_KEY_RANGE if want["bad"] else 0)
+    _check(got, want, topk)
+
+
+@pytest.mark.parametrize("n,m", [(0, 10), (1, 1), (10, 0)])
+def test_general_empty(hip, ctx, n, m):
+    """Empty and one-row sides: no joined rows and no groups (or the single match)."""
+    O = oracle
+    rng = np.random.default_rng(n + 3 * m)
+    fact, dim = _tables(rng, n, max(m, 1), 5, False)
+    dim = [c[:m] for c in dim]
+    aggs = [(O.AGG_SUM, [(O.X_COL, 2)]), (O.AGG_COUNT, []), (O.AGG_COUNT_DISTINCT, [(O.X_COL, 1)])]
+    want = O.fragment_general(fact, dim, [], [], 0, 0, [(3, 2)], aggs, topk=5, gcap=4)
+    got = hip.fragment_run(ctx, [_dev(c) for c in fact], [_dev(c) for c in dim], [], [], 0, 0, [(3, 2)], aggs,
+                           topk=5, key_bits=4, gcap=4)
+    assert ctx.errors() == 0
+    _check(got, want, 5)
+
+
+def test_general_flags_descriptor(hip, ctx):
+    """Config 1's flags fragment (6M fact rows) as a descriptor equals the flags fragment's oracle."""
+    O = oracle
+    fr = datagen.config1()
+    f, d = fr.fact, fr.dim
+    fact = [f["fk"], f["date"], f["price"], f["disc"], f["flagA"], f["flagB"]]
+    dim = [d["pk"], d["seg"]]
+    rev = [(O.X_COL, 2), (O.X_CONST, 100), (O.X_COL, 3), (O.X_SUB, 0), (O.X_MUL, 0)]
+    got = hip.fragment_run(ctx, [_dev(c) for c in fact], [_dev(c) for c in dim],
+                           [(O.X_COL, 1), (O.X_CONST, fr.D), (O.X_LT, 0)], [(O.X_COL, 1), (O.X_CONST, fr.c), (O.X_EQ, 0)],
+                           0, 0, [(4, 2), (5, 1)], [(O.AGG_SUM, rev), (O.AGG_COUNT, []), (O.AGG_AVG, [(O.X_COL, 2)])],
+                           key_bits=fr.key_bits, gcap=8)
+    want = O.fragment_flags(f, d, fr.D, fr.c)
+    assert ctx.errors() == 0
+    G = int(_np(got["d_ngroups"])[0])
+    assert G == len(want["key"]) and int(_np(got["d_join"])[0]) == want["join_rows"]
+    assert np.array_equal(_np(got["key"], G), want["key"])
+    assert np.array_equal(_np(got["vals"][0], G), want["sum"]) and np.array_equal(_np(got["vals"][1], G), want["cnt"])
+    assert np.array_equal(_np(got["vals"][2], G).view(np.int64), want["avg"].view(np.int64))
+
+
+def test_general_custkey_descriptor(hip, ctx):
+    """A scaled custkey fragment (1.5M fact rows, 400k mid rows, 50k custkeys) as a descriptor: group
+    by a dim column, SUM and COUNT, top-100 by the sum; equals the custkey fragment's oracle."""
+    O = oracle
+    fr = datagen.config2(seed=71, n=1_500_000, m=400_000, cust_hi=50_000)
+    f, m = fr.fact, fr.mid
+    rev = [(O.X_COL, 2), (O.X_CONST, 100), (O.X_COL, 3), (O.X_SUB, 0), (O.X_MUL, 0)]
+    got = hip.fragment_run(ctx, [_dev(f[k]) for k in ("fk", "date", "price", "disc")], [_dev(m["pk"]), _dev(m["custkey"])],
+                           [(O.X_COL, 1), (O.X_CONST, fr.D), (O.X_LT, 0)], [], 0, 0, [(5, 16)],
+                           [(O.AGG_SUM, rev), (O.AGG_COUNT, [])], topk=100,
+                           key_bits=datagen.bits_for(int(f["fk"].max()) + 1), gcap=fr.cust_hi)
+    want = O.fragment_cust(f, m, fr.D, 100, gcap=fr.cust_hi)
+    assert ctx.errors() == 0
+    G = int(_np(got["d_ngroups"])[0])
+    assert G == want["groups"] and int(_np(got["d_join"])[0]) == want["join_rows"]
+    assert np.array_equal(_np(got["key"], G), want["key"])
+    assert np.array_equal(_np(got["vals"][0], G), want["sum"]) and np.array_equal(_np(got["vals"][1], G), want["cnt"])
+    k = int(_np(got["d_topk"])[0])
+    assert np.array_equal(_np(got["top_key"], k), want["top_key"])
+    assert np.array_equal(_np(got["top_val"], k), want["top_sum"])
+
+
+def test_general_capacity_and_refusals(hip, ctx):
+    """Fewer group slots than groups: the capacity flag, the true group count, the first gcap groups
+    exact; malformed descriptors are refused before any launch."""
+    O = oracle
+    rng = np.random.default_rng(77)
+    fact, dim = _tables(rng, 50_000, 2000, 2000, False)
+    aggs = [(O.AGG_SUM, [(O.X_COL, 2)]), (O.AGG_COUNT, [])]
+    want = O.fragment_general(fact, dim, [], [], 0, 0, [(0, 11)], aggs)
+    got = hip.fragment_run(ctx, [_dev(c) for c in fact], [_dev(c) for c in dim], [], [], 0, 0, [(0, 11)], aggs,
+                           key_bits=11, gcap=100)
+    assert ctx.errors() == hip.DEVERR_CAPACITY
+    assert int(_np(got["d_ngroups"])[0]) == want["groups"] > 100
+    assert np.array_equal(_np(got["key"], 100), want["key"][:100])
+    assert np.array_equal(_np(got["vals"][0], 100), want["vals"][0][:100])
+    d = [_dev(c) for c in fact]
+    for bad in (dict(fact_pred=[(O.X_ADD, 0)]), dict(group=[(0, 20), (1, 20)]),
+                dict(aggs=[(O.AGG_SUM, [])]), dict(aggs=[(O.AGG_COUNT_DISTINCT, [(O.X_COL, 1)])] * 2),
+                dict(topk=5, aggs=[(O.AGG_AVG, [(O.X_COL, 1)])])):
+        kw = dict(fact_pred=[], group=[(3, 2)], aggs=[(O.AGG_COUNT, [])], topk=0)
+        kw.update(bad)
+        with pytest.raises(hip.TQPError):
+            hip.fragment_run(ctx, d, None, kw["fact_pred"], [], -1, 0, kw["group"], kw["aggs"], topk=kw["topk"])
+    assert ctx.errors() == 0
