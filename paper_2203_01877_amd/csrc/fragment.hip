@@ -179,6 +179,15 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
     tqp_status st;
     const uint32_t* mk = reinterpret_cast<const uint32_t*>(f.pk);
     const uint32_t* mv = reinterpret_cast<const uint32_t*>(f.custkey);
+    SrcKeyCol msrc{f.pk, f.custkey, f.n_mid};
+    // fact side: date < D fused into the sort; the payload is the revenue
+    // price * (100 - disc), evaluated while the row is read
+    SrcFilterRevenue<VT, true> fsrc{f.fk, f.date, f.price, f.disc, CMP_LT, f.D, f.n_fact, b.fmask};
+    // Two streams.  The mid sort's histogram and first pass run on the side
+    // stream beside the fact histogram; the fused fact pass then runs alone
+    // (it is the longest kernel, and sharing HBM cost it a third of its
+    // speed); the mid's remaining passes and its finishing sort run beside
+    // the second fact pass.
     if (f.mid_sorted) {
         // sorted by the caller: the start of every 2^fact_lowb-key bucket, one
         // search each, for the join windows
@@ -188,13 +197,30 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
                                                                                      b.fact_lowb, b.nmbkt,
                                                                                      b.mbstart));
     } else {
-        // mid side, (pk, custkey), sorted on the side stream while the fact
-        // side is sorted on s
         if ((st = side_fork(ctx, s)) != TQP_OK) return st;
-        SrcKeyCol msrc{f.pk, f.custkey, f.n_mid};
         if ((st = radix_launch<Cfg, uint32_t, SORT_TAG_MID>(b.mid, msrc, f.n_mid, true, nullptr, key_mask_for(kb),
                                                             b.mkeys, b.mvals, ctx, ctx->side, "mid_pass_first",
-                                                            "mid_pass")) != TQP_OK)
+                                                            "mid_pass", 0, 1)) != TQP_OK)
+            return st;
+    }
+    if (b.fact.ntiles > 0) {
+        // the fact histogram of every pass, and the filter as one bit per row
+        using FC = typename Cfg::template ForVal<VT>;
+        const int g = grid_for(f.n_fact, (int64_t)FC::BLOCK * HIST_ITEMS * 4, (int64_t)ctx->num_cus * 2);
+        TQP_LAUNCH(ctx, s, "radix_hist",
+                   (k_radix_hist<FC, SrcFilterRevenue<VT, true>><<<g, FC::BLOCK, 0, s>>>(
+                       fsrc, b.fact.pd, key_mask_for(kb), b.fact.hist, b.fact.d_cnt, ctx->d_err)));
+    }
+    if (!f.mid_sorted && (st = side_join(ctx, s)) != TQP_OK) return st;
+    if ((st = radix_launch<Cfg, VT, SORT_TAG_FACT>(b.fact, fsrc, f.n_fact, false, b.fact.d_cnt, key_mask_for(kb),
+                                                   b.fkeys, b.fvals, ctx, s, "fact_pass_fused", "fact_pass", 0,
+                                                   1)) != TQP_OK)
+        return st;
+    if (!f.mid_sorted) {
+        if ((st = side_fork(ctx, s)) != TQP_OK) return st;
+        if ((st = radix_launch<Cfg, uint32_t, SORT_TAG_MID>(b.mid, msrc, f.n_mid, true, nullptr, key_mask_for(kb),
+                                                            b.mkeys, b.mvals, ctx, ctx->side, "mid_pass_first",
+                                                            "mid_pass", 1)) != TQP_OK)
             return st;
         mk = b.mkeys;
         mv = b.mvals;
@@ -208,14 +234,10 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
             mv = b.mvals_full;
         }
     }
-    // fact side: date < D fused into the sort; the payload is the revenue
-    // price * (100 - disc), evaluated while the row is read
-    SrcFilterRevenue<VT, true> fsrc{f.fk, f.date, f.price, f.disc, CMP_LT, f.D, f.n_fact, b.fmask};
-    if ((st = radix_launch<Cfg, VT, SORT_TAG_FACT>(b.fact, fsrc, f.n_fact, true, nullptr, key_mask_for(kb),
-                                                   b.fkeys, b.fvals, ctx, s, "fact_pass_fused", "fact_pass")) !=
-        TQP_OK)
+    if ((st = radix_launch<Cfg, VT, SORT_TAG_FACT>(b.fact, fsrc, f.n_fact, false, b.fact.d_cnt, key_mask_for(kb),
+                                                   b.fkeys, b.fvals, ctx, s, "fact_pass_fused", "fact_pass",
+                                                   1)) != TQP_OK)
         return st;
-
     if (!f.mid_sorted && (st = side_join(ctx, s)) != TQP_OK) return st;
     // join: emits (custkey, revenue)
     using Emit = EmitKeyVal<JCfgFrag::BLOCK, Cfg::RADIX_BITS, VT>;

@@ -217,18 +217,24 @@ RadixBufs<Cfg0, V> radix_reserve(Arena& a, int64_t n_upper, int key_bits, int sk
 // digit.  Pass 0 reads src0; later passes read the previous pass's output,
 // bounded by the count of elements that took part (*count_src).
 // first_label / pass_label (string literals, optional) name the first and the
-// later pass kernels in the per-launch profile.
+// later pass kernels in the per-launch profile.  [p_begin, p_end) limits the
+// call to those passes (the histogram runs with pass 0), so a sort can be
+// split over two calls, e.g. around other work, with the same arguments.
 template <class Cfg0, class V, int Tag = 0, class Src0>
 tqp_status radix_launch(const RadixBufs<Cfg0, V>& b, const Src0& src0, int64_t n_upper, bool run_hist,
                         const int64_t* count_src, uint32_t key_mask, uint32_t* keys_out, V* vals_out,
                         tqp_ctx* ctx, hipStream_t s, const char* first_label = nullptr,
-                        const char* pass_label = nullptr) {
+                        const char* pass_label = nullptr, int p_begin = 0, int p_end = 8) {
     using Cfg = typename Cfg0::template ForVal<V>;
     const int np = b.pd.npass;
+    const int pe = p_end < np ? p_end : np;
     const int64_t tiles = b.ntiles;
     if (tiles == 0) return TQP_OK;
     const bool counted = run_hist && b.pre;
-    if (counted) {
+    if (run_hist) count_src = b.d_cnt;
+    if (p_begin > 0) {
+        // a later part of a split sort: the histogram has run with pass 0
+    } else if (counted) {
         TQP_LAUNCH(ctx, s, "radix_hist",
                    k_radix_hist_tiles<Cfg, Src0><<<(unsigned)b.nchunks, Cfg::BLOCK, 0, s>>>(
                        src0, b.pd, key_mask, b.hist, b.d_cnt, ctx->d_err, b.pre, b.ctot, b.tpc, tiles));
@@ -251,7 +257,12 @@ tqp_status radix_launch(const RadixBufs<Cfg0, V>& b, const Src0& src0, int64_t n
     if (first_label) first_name = first_label;
     const uint32_t* in_k = nullptr;
     const V* in_v = nullptr;
-    for (int p = 0; p < np; ++p) {
+    if (p_begin > 0) {                        // the output of the pass before p_begin
+        const bool prev_final = ((np - p_begin) % 2) == 0;
+        in_k = prev_final ? keys_out : b.ktmp;
+        in_v = prev_final ? vals_out : b.vtmp;
+    }
+    for (int p = p_begin; p < pe; ++p) {
         const bool to_final = ((np - 1 - p) % 2) == 0;
         uint32_t* ok = to_final ? keys_out : b.ktmp;
         V* ov = to_final ? vals_out : b.vtmp;
