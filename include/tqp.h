@@ -190,8 +190,9 @@ tqp_status tqp_join(tqp_ctx* ctx, const int32_t* lkey, const int32_t* lrow, int6
 /* Section 5.3, Algorithm 3: the hash-based equi-join, partitioned.  Same
  * rows as tqp_join (every (lrow[i], rrow[j]) with lkey[i] == rkey[j]), but
  * the inputs need not be sorted.  Both sides are split into 2^P partitions
- * (P <= 11, about 1536 right rows each) by the top bits of a multiplicative
- * hash of the key, one radix pass per side; then every partition is joined
+ * (P <= 16, up to about 2000 right rows each) by the top bits of a
+ * multiplicative hash of the key, one or two radix passes per side; then
+ * every partition is joined
  * in LDS: a table of its right rows (one slot per distinct key, the rows of a
  * key stored as one run from a count and a scan, so duplicates cost O(1) per
  * insert), probed once per left row.  Output rows come in no fixed order; the

@@ -12,7 +12,8 @@
 //
 //   partition  radix passes per side over the top P bits of h (the sort's
 //              histogram, a pre-counted 8-bit pass and, for P > 8, a second
-//              pass), rows carried as (h, row);
+//              pass), rows carried as (h, row); P leaves up to about 2000
+//              right rows per partition (one build of a 4096-slot table);
 //   plan       the partition starts (one search per partition) and a list of
 //              work items: (partition, chunk of left rows);
 //   join       persistent blocks take items.  For every chunk of at most
@@ -40,11 +41,11 @@ constexpr uint32_t PJ_MUL = 0x9E3779B1u;        // odd: key -> h is a bijection 
 constexpr int PJ_BLOCK = 512;
 constexpr int PJ_ITEMS = 4;                      // left rows per thread per round
 constexpr int PJ_ROUND = PJ_BLOCK * PJ_ITEMS;
-constexpr int PJ_RCAP = 3072;                    // right rows per table build
-constexpr int PJ_LOG2S = 13;                     // table slots: 8192 (load factor <= 0.375)
+constexpr int PJ_RCAP = 2048;                    // right rows per table build
+constexpr int PJ_LOG2S = 12;                     // table slots: 4096 (load factor <= 0.5)
 constexpr int PJ_S = 1 << PJ_LOG2S;
 constexpr int PJ_LCHUNK = 16384;                 // left rows per work item
-constexpr int PJ_MAXP = 11;                      // partition bits: at most two 8-bit radix passes
+constexpr int PJ_MAXP = 16;                      // partition bits: at most two 8-bit radix passes
 constexpr int PJ_LANE_MAX = 4;                   // longer runs are written by the whole wave
 constexpr int PJ_PLAN_BLOCK = 1024;
 
@@ -178,7 +179,27 @@ __device__ void pj_build(PjSmem& sm, const uint32_t* rh, const uint32_t* rv, int
         }
     }
     __syncthreads();
-    block_excl_scan_array<PJ_BLOCK>(sm.cur, PJ_S, sm.w32);     // count -> start of the key's run
+    // count -> start of the key's run: wave w scans its contiguous slice of
+    // slots 64 at a time (consecutive lanes, consecutive words: no bank
+    // conflicts), then adds the totals of the slices before it
+    {
+        constexpr int W = PJ_BLOCK / WAVE, SLICE = PJ_S / W;
+        const int w = threadIdx.x / WAVE, l = lane_id();
+        uint32_t carry = 0;
+        for (int c = w * SLICE; c < (w + 1) * SLICE; c += WAVE) {
+            const uint32_t x = sm.cur[c + l];
+            const uint32_t inc = wave_incl_sum(x);
+            sm.cur[c + l] = carry + inc - x;
+            carry += wave_read(inc, WAVE - 1);
+        }
+        if (l == 0) sm.w32[w] = carry;
+        __syncthreads();
+        uint32_t off = 0;
+        for (int ww = 0; ww < w; ++ww) off += sm.w32[ww];
+        if (off)
+            for (int c = w * SLICE; c < (w + 1) * SLICE; c += WAVE) sm.cur[c + l] += off;
+        __syncthreads();
+    }
 #pragma unroll
     for (int j = 0; j < RPT; ++j)
         if (in[j]) sm.rows[atomicAdd(&sm.cur[slot[j]], 1u)] = val[j];   // cur ends at the run's end
@@ -276,7 +297,7 @@ __device__ void pj_probe(PjSmem& sm, const uint32_t* lh, const uint32_t* lv, int
     }
 }
 
-// Two blocks per CU: 2 x 76 KB of LDS, and at most 128 VGPRs (4 waves per SIMD).
+// Two blocks per CU: 40 KB of LDS each, and at most 128 VGPRs (4 waves per SIMD).
 __global__ void __launch_bounds__(PJ_BLOCK, 4)
 k_pj_join(const uint32_t* lh, const uint32_t* lv, const uint32_t* rh, const uint32_t* rv, const int64_t* lstart,
           const int64_t* rstart, const int64_t* item_pre, int P, uint32_t* counter, int32_t* out_l, int32_t* out_r,
@@ -320,12 +341,13 @@ __global__ void k_pj_finish(const int64_t* total, int64_t cap, int64_t* d_count,
     if (t > cap) set_flag(flags, FLAG_CAPACITY);
 }
 
-// Partition bits for nr right rows: about PJ_RCAP / 2 right rows per
-// partition, at most PJ_MAXP bits (larger partitions take several table
-// builds), at least one bit.
+// Partition bits for nr right rows: the fewest that leave at most about
+// 31/32 of PJ_RCAP right rows per partition on average (so that most
+// partitions take one table build; larger ones take several), at most
+// PJ_MAXP, at least one.
 int pj_bits(int64_t nr) {
     int P = 1;
-    while (P < PJ_MAXP && (nr >> P) > PJ_RCAP / 2) ++P;
+    while (P < PJ_MAXP && (nr >> P) > PJ_RCAP - PJ_RCAP / 32) ++P;
     return P;
 }
 
@@ -347,7 +369,7 @@ tqp_status tqp_hash_join(tqp_ctx* ctx, const int32_t* lkey, const int32_t* lrow,
     if (nl > MAX_ELEMS || nr > MAX_ELEMS) return fail(TQP_ERR_UNSUPPORTED, "tqp_hash_join: input too large");
     const int P = pj_bits(nr);
     const int np = 1 << P;
-    using Cfg = R8;            // P > 8 bits take two passes: 8-bit digit runs write longer runs than one 11-bit pass
+    using Cfg = R8;            // P > 8 bits take two 8-bit passes (longer digit runs per write than wider digits)
     RadixBufs<Cfg, uint32_t> lb, rb;
     uint32_t *lh = nullptr, *lv = nullptr, *rh = nullptr, *rv = nullptr, *counter = nullptr;
     int64_t *lstart = nullptr, *rstart = nullptr, *item_pre = nullptr, *total = nullptr;
@@ -368,7 +390,7 @@ tqp_status tqp_hash_join(tqp_ctx* ctx, const int32_t* lkey, const int32_t* lrow,
     tqp_status st = with_workspace(ctx, ws, ws_bytes, stream, plan, a);
     if (st != TQP_OK || !ws) return st;
     if ((st = fill_zero(a.base, a.zsize, stream, ctx)) != TQP_OK) return st;
-    // both sides into 2^P partitions by the top bits of h (one pass each; an
+    // both sides into 2^P partitions by the top bits of h (one or two passes each; an
     // empty side launches nothing and leaves its histogram zero)
     SrcHashRows ls{lkey, lrow, nl, d_nl, ctx->d_err};
     SrcHashRows rs{rkey, rrow, nr, d_nr, ctx->d_err};

@@ -176,7 +176,7 @@ def test_hash_join(hip, ctx, nl, nr, hi, sort):
 
 
 def test_hash_join_hot_key_and_edges(hip, ctx):
-    """One key on 10000 right rows (its partition takes four table builds) and
+    """One key on 10000 right rows (its partition takes several table builds) and
     on 300 left rows; element indexes as payloads (no row columns); a
     negative key (flagged, its row left out); the device row counts below the
     host bounds; an output capacity below the join size (capacity flag, the
