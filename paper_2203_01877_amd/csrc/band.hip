@@ -19,7 +19,8 @@ constexpr int BJ_BLOCK = 256;
 constexpr int BJ_ITEMS = 8;
 constexpr int BJ_TILE = BJ_BLOCK * BJ_ITEMS;
 constexpr int BJ_RWIN = 4096;          // right keys a tile may stage in LDS
-constexpr int BJ_LANE_MAX = 4;         // matches an element writes from its own lane
+constexpr int BJ_LANE_MAX = 4;         // longer ranges in an item: the wave writes the item's rows together
+constexpr int BJ_WAVE_RUN = 32;        // ranges this long: one at a time, 64 consecutive rows per step
 
 struct BandSmem {
     uint32_t rk[BJ_RWIN];
@@ -178,27 +179,47 @@ k_band_expand(const uint32_t* lkey, const int32_t* lrow, int64_t nl_upper, const
             wbase += wave_read(incl, WAVE - 1);
             const int64_t i = chunk + j * WAVE + l;
             const int32_t lp = lrow ? lrow[in[j] ? i : 0] : (int32_t)i;
-            const bool small = cnt[j] <= BJ_LANE_MAX;
-            if (small)
+            if (!__any(cnt[j] > BJ_LANE_MAX)) {
                 for (int t = 0; t < cnt[j]; ++t)
                     if (o + t < cap) {
                         out_l[o + t] = lp;
                         out_r[o + t] = rrow ? rrow[lo[j] + t] : (int32_t)(lo[j] + t);
                     }
-            // wide ranges: the whole wave writes them, 64 rows at a time
-            uint64_t heavy = ballot(!small);
-            while (heavy) {
-                const int src = __ffsll((unsigned long long)heavy) - 1;
-                heavy &= heavy - 1;
-                const int c = wave_read(cnt[j], src);
-                const int64_t f = wave_read(lo[j], src);
-                const int64_t oo = wave_read(o, src);
-                const int32_t pp = wave_read(lp, src);
-                for (int q = l; q < c; q += WAVE)
-                    if (oo + q < cap) {
-                        out_l[oo + q] = pp;
-                        out_r[oo + q] = rrow ? rrow[f + q] : (int32_t)(f + q);
+            } else {
+                // some range is wide.  Ranges of at least BJ_WAVE_RUN rows: the
+                // whole wave writes each; the shorter ones: the wave writes
+                // their rows 64 at a time, each lane finding the left element
+                // its row belongs to
+                const bool lng = cnt[j] >= BJ_WAVE_RUN;
+                const int64_t oc2 = lng ? 0 : (int64_t)cnt[j];
+                const int64_t incl2 = wave_incl_sum(oc2);
+                const int64_t excl2 = incl2 - oc2, tot2 = wave_read(incl2, WAVE - 1);
+                for (int64_t q0 = 0; q0 < tot2; q0 += WAVE) {
+                    const int64_t q = q0 + l;
+                    const int src = wave_run_owner(excl2, q);
+                    const int64_t t = q - wave_shfl(excl2, src);
+                    const int64_t f = wave_shfl(lo[j], src);
+                    const int32_t pp = wave_shfl(lp, src);
+                    const int64_t oo = wave_shfl(o, src) + t;
+                    if (q < tot2 && oo < cap) {
+                        out_l[oo] = pp;
+                        out_r[oo] = rrow ? rrow[f + t] : (int32_t)(f + t);
                     }
+                }
+                uint64_t heavy = ballot(lng);
+                while (heavy) {
+                    const int src = __ffsll((unsigned long long)heavy) - 1;
+                    heavy &= heavy - 1;
+                    const int c = wave_read(cnt[j], src);
+                    const int64_t f = wave_read(lo[j], src);
+                    const int64_t oo = wave_read(o, src);
+                    const int32_t pp = wave_read(lp, src);
+                    for (int q = l; q < c; q += WAVE)
+                        if (oo + q < cap) {
+                            out_l[oo + q] = pp;
+                            out_r[oo + q] = rrow ? rrow[f + q] : (int32_t)(f + q);
+                        }
+                }
             }
         }
     }

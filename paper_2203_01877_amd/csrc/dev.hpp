@@ -113,6 +113,34 @@ __device__ __forceinline__ T wave_read(T v, int lane) {
     }
 }
 
+// Value of lane `src` (its own for every lane) in every lane: the LDS
+// crossbar permute, no LDS memory.
+template <class T>
+__device__ __forceinline__ T wave_shfl(T v, int src) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "4- or 8-byte values");
+    if constexpr (sizeof(T) == 4) {
+        return (T)(lane_word_t<T>)__builtin_amdgcn_ds_bpermute(src << 2, (int)(lane_word_t<T>)v);
+    } else {
+        const uint64_t x = (uint64_t)v;
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)x);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)(x >> 32));
+        return (T)(((uint64_t)hi << 32) | lo);
+    }
+}
+
+// The lane whose run holds item q of the wave's runs laid end to end, given
+// every lane's exclusive start (non-decreasing over the lanes): the last lane
+// whose start is <= q.  Every lane of the wave must take part.
+__device__ __forceinline__ int wave_run_owner(int64_t excl, int64_t q) {
+    int src = 0;
+#pragma unroll
+    for (int step = WAVE / 2; step >= 1; step >>= 1) {
+        const int64_t e = wave_shfl(excl, src + step);
+        if (e <= q) src += step;
+    }
+    return src;
+}
+
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {
     return wave_read(wave_incl_sum(v), WAVE - 1);

@@ -46,7 +46,8 @@ constexpr int PJ_LOG2S = 12;                     // table slots: 4096 (load fact
 constexpr int PJ_S = 1 << PJ_LOG2S;
 constexpr int PJ_LCHUNK = 16384;                 // left rows per work item
 constexpr int PJ_MAXP = 16;                      // partition bits: at most two 8-bit radix passes
-constexpr int PJ_LANE_MAX = 4;                   // longer runs are written by the whole wave
+constexpr int PJ_LANE_MAX = 4;                   // an item with a longer run is written by the whole wave
+constexpr int PJ_WAVE_RUN = 32;                  // runs this long: one at a time, 64 consecutive pairs per step
 constexpr int PJ_PLAN_BLOCK = 1024;
 
 static_assert(PJ_RCAP % PJ_BLOCK == 0, "right rows split evenly over the block");
@@ -258,11 +259,11 @@ __device__ void pj_probe(PjSmem& sm, const uint32_t* lh, const uint32_t* lv, int
         __syncthreads();
         int64_t wbase = sm.base;
         for (int ww = 0; ww < w; ++ww) wbase += sm.w64[ww];
-        bool wide = false;
 #pragma unroll
         for (int j = 0; j < PJ_ITEMS; ++j) {
-            const int64_t o = wbase + off[j];
-            if (cnt[j] <= (uint32_t)PJ_LANE_MAX) {
+            if (!__any(cnt[j] > (uint32_t)PJ_LANE_MAX)) {
+                // every run of the item is short: each lane writes its own
+                const int64_t o = wbase + off[j];
                 for (uint32_t q = 0; q < cnt[j]; ++q) {
                     if (o + q < cap) {
                         out_l[o + q] = (int32_t)lrow[j];
@@ -270,24 +271,39 @@ __device__ void pj_probe(PjSmem& sm, const uint32_t* lh, const uint32_t* lv, int
                     }
                 }
             } else {
-                wide = true;
-            }
-        }
-        if (__any(wide)) {
-#pragma unroll
-            for (int j = 0; j < PJ_ITEMS; ++j) {
-                uint64_t m = ballot(cnt[j] > (uint32_t)PJ_LANE_MAX);
+                // some run is long.  Runs of at least PJ_WAVE_RUN pairs: the
+                // whole wave writes each; the shorter ones: the wave writes
+                // their pairs 64 at a time, each lane finding the left row its
+                // pair belongs to
+                const bool lng = cnt[j] >= (uint32_t)PJ_WAVE_RUN;
+                const int64_t oc2 = lng ? 0 : (int64_t)cnt[j];
+                const int64_t incl2 = wave_incl_sum(oc2);
+                const int64_t excl2 = incl2 - oc2, tot2 = wave_read(incl2, WAVE - 1);
+                const int64_t o = wbase + off[j];
+                for (int64_t q0 = 0; q0 < tot2; q0 += WAVE) {
+                    const int64_t q = q0 + l;
+                    const int src = wave_run_owner(excl2, q);
+                    const int64_t t = q - wave_shfl(excl2, src);
+                    const uint32_t st = wave_shfl(start[j], src);
+                    const int32_t lr = (int32_t)wave_shfl(lrow[j], src);
+                    const int64_t oo = wave_shfl(o, src) + t;
+                    if (q < tot2 && oo < cap) {
+                        out_l[oo] = lr;
+                        out_r[oo] = (int32_t)sm.rows[st + t];
+                    }
+                }
+                uint64_t m = ballot(lng);
                 while (m) {
                     const int src = __ffsll((unsigned long long)m) - 1;
                     m &= m - 1;
-                    const int64_t o = wave_read(wbase + off[j], src);
+                    const int64_t oo = wave_read(o, src);
                     const uint32_t c = wave_read(cnt[j], src);
                     const uint32_t st = wave_read(start[j], src);
                     const int32_t lr = (int32_t)wave_read(lrow[j], src);
                     for (uint32_t q = l; q < c; q += WAVE) {
-                        if (o + q < cap) {
-                            out_l[o + q] = lr;
-                            out_r[o + q] = (int32_t)sm.rows[st + q];
+                        if (oo + q < cap) {
+                            out_l[oo + q] = lr;
+                            out_r[oo + q] = (int32_t)sm.rows[st + q];
                         }
                     }
                 }

@@ -57,9 +57,15 @@ __device__ __forceinline__ int64_t join_out_rows(int64_t matches) {
     else return matches;
 }
 
-// Matches of one left element at most this many are emitted by its own lane;
-// elements with more are expanded by the whole wave, 64 outputs at a time.
+// When every element of a wave's round has at most JOIN_LANE_MAX output
+// rows, each lane emits its own.  Otherwise runs of JOIN_WAVE_RUN rows or
+// more are emitted by the whole wave one run at a time (64 consecutive rows
+// per step), and the rest of the round's rows 64 at a time, each lane finding
+// the element its row belongs to (load-balanced expansion: full lanes
+// whatever the mix of short run lengths).  Aggregating emitters keep the
+// simpler form: short runs by their lane, each longer run by the whole wave.
 constexpr int JOIN_LANE_MAX = 4;
+constexpr int JOIN_WAVE_RUN = 32;      // runs this long are written by the whole wave, one at a time
 
 // ------------------------------------------------------------------ emitters
 // Index pairs (late materialisation: the join returns row-index pairs).
@@ -460,28 +466,73 @@ __device__ __forceinline__ void join_tile(const uint32_t* lkey, const LP* lpay, 
             if (oc) e(o, key[j], pay[j], (RP)JOIN_NONE, esm);
             continue;
         }
-        if constexpr (KIND == JOIN_OUTER) {
-            if (oc && cnt[j] == 0) e(o, key[j], pay[j], (RP)JOIN_NONE, esm);
-        }
-        const bool small = cnt[j] <= JOIN_LANE_MAX;
-        if constexpr (AHEAD) {
-            if (small && cnt[j] > 0) {
-                e(o, key[j], pay[j], r0[j], esm);
-                for (int t = 1; t < cnt[j]; ++t) e(o + t, key[j], pay[j], right(first[j] + t), esm);
+        if constexpr (!Emit::ORDERED) {
+            // aggregating emitters (fewer registers to spare): short runs by
+            // their own lane, each long one by the whole wave
+            if constexpr (KIND == JOIN_OUTER) {
+                if (oc && cnt[j] == 0) e(o, key[j], pay[j], (RP)JOIN_NONE, esm);
             }
-        } else if (small) {
-            for (int t = 0; t < cnt[j]; ++t) e(o + t, key[j], pay[j], right(first[j] + t), esm);
-        }
-        uint64_t heavy = ballot(!small);
-        while (heavy) {
-            const int src = __ffsll((unsigned long long)heavy) - 1;
-            heavy &= heavy - 1;
-            const int c = wave_read(cnt[j], src);
-            const int64_t f = wave_read(first[j], src);
-            const int64_t oo = wave_read(o, src);
-            const uint32_t kk = wave_read(key[j], src);
-            const LP pp = wave_read(pay[j], src);
-            for (int q = l; q < c; q += WAVE) e(oo + q, kk, pp, right(f + q), esm);
+            const bool small = cnt[j] <= JOIN_LANE_MAX;
+            if (small)
+                for (int t = 0; t < cnt[j]; ++t) e(o + t, key[j], pay[j], right(first[j] + t), esm);
+            uint64_t heavy = ballot(!small);
+            while (heavy) {
+                const int src = __ffsll((unsigned long long)heavy) - 1;
+                heavy &= heavy - 1;
+                const int c = wave_read(cnt[j], src);
+                const int64_t f = wave_read(first[j], src);
+                const int64_t oo = wave_read(o, src);
+                const uint32_t kk = wave_read(key[j], src);
+                const LP pp = wave_read(pay[j], src);
+                for (int q = l; q < c; q += WAVE) e(oo + q, kk, pp, right(f + q), esm);
+            }
+        } else if (!__any(cnt[j] > JOIN_LANE_MAX)) {
+            // every element of the round has a short run: each lane writes its own
+            if constexpr (KIND == JOIN_OUTER) {
+                if (oc && cnt[j] == 0) e(o, key[j], pay[j], (RP)JOIN_NONE, esm);
+            }
+            if constexpr (AHEAD) {
+                if (cnt[j] > 0) {
+                    e(o, key[j], pay[j], r0[j], esm);
+                    for (int t = 1; t < cnt[j]; ++t) e(o + t, key[j], pay[j], right(first[j] + t), esm);
+                }
+            } else {
+                for (int t = 0; t < cnt[j]; ++t) e(o + t, key[j], pay[j], right(first[j] + t), esm);
+            }
+        } else {
+            // some run is long.  Runs of at least JOIN_WAVE_RUN rows: the
+            // whole wave writes each, 64 consecutive rows per step; the
+            // shorter ones: the wave writes their rows 64 at a time, each
+            // lane finding the element its row belongs to
+            const bool lng = cnt[j] >= JOIN_WAVE_RUN;
+            const int64_t oc2 = lng ? 0 : oc;
+            const int64_t incl2 = wave_incl_sum(oc2);
+            const int64_t excl2 = incl2 - oc2, tot2 = wave_read(incl2, WAVE - 1);
+            for (int64_t q0 = 0; q0 < tot2; q0 += WAVE) {
+                const int64_t q = q0 + l;
+                const int src = wave_run_owner(excl2, q);
+                const int64_t t = q - wave_shfl(excl2, src);
+                const uint32_t kk = wave_shfl(key[j], src);
+                const LP pp = wave_shfl(pay[j], src);
+                const int32_t f = wave_shfl(first[j], src);
+                const int32_t c = wave_shfl(cnt[j], src);
+                const int64_t oo = wave_shfl(o, src);
+                if (q < tot2) {
+                    if (KIND == JOIN_OUTER && c == 0) e(oo, kk, pp, (RP)JOIN_NONE, esm);
+                    else e(oo + t, kk, pp, right(f + t), esm);
+                }
+            }
+            uint64_t heavy = ballot(lng);
+            while (heavy) {
+                const int src = __ffsll((unsigned long long)heavy) - 1;
+                heavy &= heavy - 1;
+                const int c = wave_read(cnt[j], src);
+                const int64_t f = wave_read(first[j], src);
+                const int64_t oo = wave_read(o, src);
+                const uint32_t kk = wave_read(key[j], src);
+                const LP pp = wave_read(pay[j], src);
+                for (int q = l; q < c; q += WAVE) e(oo + q, kk, pp, right(f + q), esm);
+            }
         }
     }
     __syncthreads();
