@@ -22,7 +22,7 @@ constexpr int XS_MAX = 16;       // stack depth
 constexpr int XC_MAX = 8;        // columns a program reads
 constexpr int XE_MAX_COLS = 64;  // columns a program may number
 constexpr int XE_BLOCK = 128;
-constexpr int XE_ROWS = 2;       // rows per thread
+constexpr int XE_ROWS_FEW = 4;   // rows per thread when the program reads at most 4 columns
 
 enum : int32_t {
     XO_COL = 0, XO_CONST, XO_ADD, XO_SUB, XO_MUL, XO_DIV, XO_MOD, XO_NEG,
@@ -48,12 +48,16 @@ __device__ __forceinline__ int64_t x_load(const XProg& p, int c, int64_t row) {
     }
 }
 
-// Every thread evaluates XE_ROWS rows together, instruction by instruction:
+// Every thread evaluates ROWS rows together, instruction by instruction:
 // the top of each row's stack stays in a register, the values below it in
-// LDS: level l of row slot q at st[l * XE_ROWS * XE_BLOCK + q], as many
-// levels as the program needs (its deepest stack less one).
+// LDS: level l of row slot q at st[l * ROWS * XE_BLOCK + q], as many levels
+// as the program needs (its deepest stack less one).  NC (>= the columns the
+// program reads) sizes the registers that hold the rows' column values, so
+// programs over few columns evaluate more rows per thread.
+template <int NC, int ROWS>
 __global__ void __launch_bounds__(XE_BLOCK)
 k_eval(XProg p, int64_t n_upper, const int64_t* d_n, int64_t* out, uint32_t* flags) {
+    constexpr int XE_ROWS = ROWS;
     extern __shared__ int64_t xe_st[];
     int64_t n = n_upper;
     if (d_n) { const int64_t t = *d_n; n = t < n ? t : n; }
@@ -62,13 +66,13 @@ k_eval(XProg p, int64_t n_upper, const int64_t* d_n, int64_t* out, uint32_t* fla
     const int64_t step = (int64_t)gridDim.x * XE_BLOCK * XE_ROWS;
     for (int64_t base = (int64_t)blockIdx.x * XE_BLOCK * XE_ROWS; base < n; base += step) {
         // the rows' referenced columns, loads issued together before the program runs
-        int64_t cv[XE_ROWS][XC_MAX];
+        int64_t cv[XE_ROWS][NC];
 #pragma unroll
         for (int j = 0; j < XE_ROWS; ++j) {
             const int64_t row = base + (int64_t)j * XE_BLOCK + tid;
             const int64_t r = row < n ? row : n - 1;          // base < n, so n >= 1
 #pragma unroll
-            for (int c = 0; c < XC_MAX; ++c) cv[j][c] = (p.used >> c) & 1u ? x_load(p, c, r) : 0;
+            for (int c = 0; c < NC; ++c) cv[j][c] = (p.used >> c) & 1u ? x_load(p, c, r) : 0;
         }
         int64_t top[XE_ROWS];
 #pragma unroll
@@ -84,7 +88,7 @@ k_eval(XProg p, int64_t n_upper, const int64_t* d_n, int64_t* out, uint32_t* fla
                     int64_t v = arg;
                     if (op == XO_COL) {
 #pragma unroll
-                        for (int c = 0; c < XC_MAX; ++c)
+                        for (int c = 0; c < NC; ++c)
                             if (c == arg) v = cv[j][c];
                     }
                     top[j] = v;
@@ -108,34 +112,39 @@ k_eval(XProg p, int64_t n_upper, const int64_t* d_n, int64_t* out, uint32_t* fla
                 sp -= 2;
                 continue;
             }
+            // binary operators: the operator is the same in every thread, so
+            // the branch is taken once per instruction, outside the row loop
+            auto binary = [&](auto f) {
 #pragma unroll
-            for (int j = 0; j < XE_ROWS; ++j) {
-                const int64_t a = xe_st[(sp - 2) * (XE_ROWS * XE_BLOCK) + j * XE_BLOCK + tid], b = top[j];
-                int64_t r;
-                switch (op) {
-                    case XO_ADD: r = (int64_t)((uint64_t)a + (uint64_t)b); break;
-                    case XO_SUB: r = (int64_t)((uint64_t)a - (uint64_t)b); break;
-                    case XO_MUL: r = (int64_t)((uint64_t)a * (uint64_t)b); break;
-                    case XO_DIV:
-                        if (b == 0) { zdiv = true; r = 0; }
-                        else if (b == -1) r = (int64_t)(0ull - (uint64_t)a);
-                        else r = a / b;
-                        break;
-                    case XO_MOD:
-                        if (b == 0) { zdiv = true; r = 0; }
-                        else if (b == -1) r = 0;
-                        else r = a % b;
-                        break;
-                    case XO_LT: r = a < b; break;
-                    case XO_LE: r = a <= b; break;
-                    case XO_GT: r = a > b; break;
-                    case XO_GE: r = a >= b; break;
-                    case XO_EQ: r = a == b; break;
-                    case XO_NE: r = a != b; break;
-                    case XO_AND: r = (a != 0) && (b != 0); break;
-                    default: r = (a != 0) || (b != 0); break;
-                }
-                top[j] = r;
+                for (int j = 0; j < XE_ROWS; ++j)
+                    top[j] = f(xe_st[(sp - 2) * (XE_ROWS * XE_BLOCK) + j * XE_BLOCK + tid], top[j]);
+            };
+            switch (op) {
+                case XO_ADD: binary([](int64_t a, int64_t b) { return (int64_t)((uint64_t)a + (uint64_t)b); }); break;
+                case XO_SUB: binary([](int64_t a, int64_t b) { return (int64_t)((uint64_t)a - (uint64_t)b); }); break;
+                case XO_MUL: binary([](int64_t a, int64_t b) { return (int64_t)((uint64_t)a * (uint64_t)b); }); break;
+                case XO_DIV:
+                    binary([&](int64_t a, int64_t b) -> int64_t {
+                        if (b == 0) { zdiv = true; return 0; }
+                        if (b == -1) return (int64_t)(0ull - (uint64_t)a);
+                        return a / b;
+                    });
+                    break;
+                case XO_MOD:
+                    binary([&](int64_t a, int64_t b) -> int64_t {
+                        if (b == 0) { zdiv = true; return 0; }
+                        if (b == -1) return 0;
+                        return a % b;
+                    });
+                    break;
+                case XO_LT: binary([](int64_t a, int64_t b) -> int64_t { return a < b; }); break;
+                case XO_LE: binary([](int64_t a, int64_t b) -> int64_t { return a <= b; }); break;
+                case XO_GT: binary([](int64_t a, int64_t b) -> int64_t { return a > b; }); break;
+                case XO_GE: binary([](int64_t a, int64_t b) -> int64_t { return a >= b; }); break;
+                case XO_EQ: binary([](int64_t a, int64_t b) -> int64_t { return a == b; }); break;
+                case XO_NE: binary([](int64_t a, int64_t b) -> int64_t { return a != b; }); break;
+                case XO_AND: binary([](int64_t a, int64_t b) -> int64_t { return (a != 0) && (b != 0); }); break;
+                default: binary([](int64_t a, int64_t b) -> int64_t { return (a != 0) || (b != 0); }); break;
             }
             --sp;
         }
@@ -207,11 +216,17 @@ tqp_status eval_program(tqp_ctx* ctx, const tqp_column* cols, const int32_t* con
     if (sp != 1) return fail(TQP_ERR_INVALID, "%s: the program leaves %d values", who, sp);
     p.n = nprog;
     if (n == 0) return TQP_OK;
-    const size_t lds = (size_t)(deepest > 1 ? deepest - 1 : 1) * XE_ROWS * XE_BLOCK * sizeof(int64_t);
-    TQP_LAUNCH(ctx, stream, label,
-               k_eval<<<grid_for(n, XE_BLOCK * XE_ROWS, (int64_t)ctx->num_cus * 16), XE_BLOCK, lds, stream>>>(
-                   p, n, d_n, out, ctx->d_err));
-    return TQP_OK;
+    auto launch = [&](auto kernel, int rows) -> tqp_status {
+        const size_t lds = (size_t)(deepest > 1 ? deepest - 1 : 1) * rows * XE_BLOCK * sizeof(int64_t);
+        TQP_LAUNCH(ctx, stream, label,
+                   kernel<<<grid_for(n, (int64_t)XE_BLOCK * rows, (int64_t)ctx->num_cus * 16), XE_BLOCK, lds,
+                            stream>>>(p, n, d_n, out, ctx->d_err));
+        return TQP_OK;
+    };
+    // rows per thread: as many as the column registers allow
+    if (used <= 2) return launch(k_eval<2, XE_ROWS_FEW>, XE_ROWS_FEW);
+    if (used <= 4) return launch(k_eval<4, XE_ROWS_FEW>, XE_ROWS_FEW);
+    return launch(k_eval<XC_MAX, 2>, 2);
 }
 
 }  // namespace tqp
