@@ -16,6 +16,13 @@
 //   4. one gather kernel reads the earlier position columns through the tuple
 //      index (late materialisation) and the next hop's key through the new
 //      row of table t.
+// The hop into table 2 carries the tuples' two earlier positions through its
+// sort instead (an 8-byte payload: both positions ride the radix passes, and
+// the join writes them with the new row), so its output needs no gather of
+// them: after the key sort the tuple order is a random permutation, and two
+// random 4-byte reads per tuple cost more than 8 more bytes per element in
+// each radix pass.  Later hops keep the tuple index (more positions than one
+// payload holds).
 // Every hop's size stays on the device and bounds the next hop's kernels
 // (their grids come from the caller's capacities), so the whole chain is one
 // launch sequence with no host synchronisation.
@@ -28,6 +35,49 @@ namespace {
 using JCfgChain = JoinCfg<256, 8, 4096>;
 constexpr int CH_FILTER_BLOCK = 256, CH_FILTER_ITEMS = 16;
 constexpr int CH_GATHER_BLOCK = 256, CH_GATHER_ITEMS = 4;
+
+// Sort source of the hop into table 2: the tuples' keys with both earlier
+// positions as the payload (table 1's in the high word).
+struct SrcKeysPos2 {
+    const uint32_t* keys;
+    const int32_t* pos0;
+    const int32_t* pos1;
+    int64_t n_upper;
+    const int64_t* d_n;
+    __device__ int64_t size() const {
+        if (!d_n) return n_upper;
+        const int64_t n = *d_n;
+        return n < n_upper ? n : n_upper;
+    }
+    __device__ bool load_key(int64_t i, uint32_t& k) const {
+        k = keys[i];
+        return true;
+    }
+    __device__ bool load(int64_t i, uint32_t& k, uint64_t& v) const {
+        k = keys[i];
+        v = ((uint64_t)(uint32_t)pos1[i] << 32) | (uint32_t)pos0[i];
+        return true;
+    }
+};
+
+// Join output of that hop: both carried positions and the new row.
+struct EmitPos3 {
+    static constexpr bool ORDERED = true;
+    int32_t* out0;
+    int32_t* out1;
+    int32_t* out_r;
+    int64_t cap;
+    struct Smem {};
+    __device__ void init(Smem&) {}
+    __device__ void operator()(int64_t o, uint32_t, uint64_t lp, uint32_t rp, Smem&) {
+        if (o < cap) {
+            out0[o] = (int32_t)(uint32_t)lp;
+            out1[o] = (int32_t)(uint32_t)(lp >> 32);
+            out_r[o] = (int32_t)rp;
+        }
+    }
+    __device__ void finish(Smem&) {}
+};
 
 struct ChainGather {
     const int32_t* src[TQP_CHAIN_MAX_TABLES];   // earlier position columns, read through li
@@ -78,8 +128,11 @@ k_chain_gather(ChainGather g, const int32_t* li, const int32_t* rr, int64_t n_up
 template <class Cfg>
 struct HopBufs {
     bool dense = false, sorted = false;
+    bool carry = false;                      // the hop into table 2: earlier positions ride the sort
     int64_t n_left = 0;                      // host bound on the tuples entering the hop
     RadixBufs<Cfg, uint32_t> lsort, rsort;
+    RadixBufs<Cfg, uint64_t> lsort2;         // carry: the key sort with both positions
+    uint64_t* lsv2 = nullptr;
     JoinBufs join;
     uint64_t* fstatus = nullptr;             // dense rule: the filter's look-back words
     uint32_t* fcounter = nullptr;
@@ -112,9 +165,15 @@ void chain_reserve(Arena& a, const tqp_chain_table* t, int nt, int64_t* d_count,
             hb.fstatus = a.zero<uint64_t>(tiles);
             hb.fcounter = a.zero<uint32_t>(1);
         } else {
-            hb.lsort = radix_reserve<Cfg, uint32_t>(a, hb.n_left, kb);
+            hb.carry = h == 2;
+            if (hb.carry) {
+                hb.lsort2 = radix_reserve<Cfg, uint64_t>(a, hb.n_left, kb);
+                hb.lsv2 = a.scratch<uint64_t>(hb.n_left);
+            } else {
+                hb.lsort = radix_reserve<Cfg, uint32_t>(a, hb.n_left, kb);
+                hb.lsv = a.scratch<uint32_t>(hb.n_left);
+            }
             hb.lsk = a.scratch<uint32_t>(hb.n_left);
-            hb.lsv = a.scratch<uint32_t>(hb.n_left);
             if (!hb.sorted) {
                 hb.rsort = radix_reserve<Cfg, uint32_t>(a, t[h].n_rows, kb);
                 hb.rsk = a.scratch<uint32_t>(t[h].n_rows);
@@ -165,10 +224,17 @@ tqp_status chain_launch(tqp_ctx* ctx, const tqp_chain_table* t, int nt, int32_t*
                                                                              hb.d_cnt, hb.fstatus, hb.fcounter,
                                                                              ctx->d_err, d_prev)));
         } else {
-            SrcKeysIndex lsrc{reinterpret_cast<const uint32_t*>(cur), hb.n_left, d_prev};
-            if ((st = radix_launch<Cfg, uint32_t>(hb.lsort, lsrc, hb.n_left, true, nullptr, mask, hb.lsk, hb.lsv, ctx,
-                                                  s, "chain_sort_left", "chain_sort_left")) != TQP_OK)
-                return st;
+            if (hb.carry) {
+                SrcKeysPos2 lsrc{reinterpret_cast<const uint32_t*>(cur), prev_cols[0], prev_cols[1], hb.n_left, d_prev};
+                if ((st = radix_launch<Cfg, uint64_t>(hb.lsort2, lsrc, hb.n_left, true, nullptr, mask, hb.lsk, hb.lsv2,
+                                                      ctx, s, "chain_sort_left", "chain_sort_left")) != TQP_OK)
+                    return st;
+            } else {
+                SrcKeysIndex lsrc{reinterpret_cast<const uint32_t*>(cur), hb.n_left, d_prev};
+                if ((st = radix_launch<Cfg, uint32_t>(hb.lsort, lsrc, hb.n_left, true, nullptr, mask, hb.lsk, hb.lsv,
+                                                      ctx, s, "chain_sort_left", "chain_sort_left")) != TQP_OK)
+                    return st;
+            }
             const uint32_t* rk = reinterpret_cast<const uint32_t*>(t[h].key_pk);
             const uint32_t* rp = nullptr;           // sorted by the caller: the positions are the indexes
             if (!hb.sorted) {
@@ -180,16 +246,24 @@ tqp_status chain_launch(tqp_ctx* ctx, const tqp_chain_table* t, int nt, int32_t*
                 rk = hb.rsk;
                 rp = hb.rsv;
             }
-            EmitPairs e{li, rr, t[h].cap};
             // left elements that took part in the sort: the histogram's count
-            if ((st = join_launch<JCfgChain, uint32_t, uint32_t, EmitPairs>(
-                     ctx, s, "chain_join", hb.join, hb.lsk, hb.lsv, hb.n_left, hb.lsort.d_cnt, rk, rp, t[h].n_rows,
-                     nullptr, hb.d_cnt, t[h].cap, e)) != TQP_OK)
-                return st;
+            if (hb.carry) {
+                EmitPos3 e{dst[0], dst[1], rr, t[h].cap};
+                if ((st = join_launch<JCfgChain, uint64_t, uint32_t, EmitPos3>(
+                         ctx, s, "chain_join", hb.join, hb.lsk, hb.lsv2, hb.n_left, hb.lsort2.d_cnt, rk, rp,
+                         t[h].n_rows, nullptr, hb.d_cnt, t[h].cap, e)) != TQP_OK)
+                    return st;
+            } else {
+                EmitPairs e{li, rr, t[h].cap};
+                if ((st = join_launch<JCfgChain, uint32_t, uint32_t, EmitPairs>(
+                         ctx, s, "chain_join", hb.join, hb.lsk, hb.lsv, hb.n_left, hb.lsort.d_cnt, rk, rp,
+                         t[h].n_rows, nullptr, hb.d_cnt, t[h].cap, e)) != TQP_OK)
+                    return st;
+            }
         }
         // earlier position columns through the tuple index, the next key through the new row
         ChainGather g{};
-        g.ncols = h == 1 ? 0 : h;
+        g.ncols = h == 1 || hb.carry ? 0 : h;      // hop 1: the tuple index is the row; carry: written by the join
         for (int u = 0; u < g.ncols; ++u) {
             g.src[u] = prev_cols[u];
             g.dst[u] = dst[u];
