@@ -205,11 +205,12 @@ def main():
                          "and a row outside the declared width sets a device error flag)")
     ap.add_argument("--date-lt", type=int, default=None,
                     help="config 2 with another filter constant D (date < D; the workload uses 2400)")
-    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 4, 5, 6, 7, 8, 9],
+    ap.add_argument("--config", type=int, default=2, choices=[2, 3, 4, 5, 6, 7, 8, 9, 10],
                     help="2: the 60M-row custkey fragment (default); 3: 256 flags fragments, batched vs plain; "
                          "4: served mix under Poisson arrivals, concurrent vs serial; 5: the join kinds on the "
                          "config-2 join inputs; 6: hash join vs sort join from unsorted inputs, 1 to 64 rows per key; "
-                         "7: hash vs sort group-by over 60M rows, 6 to 15M groups; 8: a chain of three joins; 9: expression programs")
+                         "7: hash vs sort group-by over 60M rows, 6 to 15M groups; 8: a chain of three joins; 9: expression programs; "
+                         "10: the custkey workload as a general fragment (tqp_fragment_run) against the fused one")
     ap.add_argument("--rates", default="25,50,100,200,400,800,1600,3200",
                     help="arrival rates (fragments/s) for --config 4, swept until no mode keeps up")
     ap.add_argument("--requests", type=int, default=2000, help="least requests per rate for --config 4")
@@ -248,6 +249,8 @@ def main():
         return bench_chain(args)
     if args.config == 9:
         return bench_expr(args)
+    if args.config == 10:
+        return bench_general(args)
     if args.config == 4:
         return bench_serve(args)
 
@@ -733,6 +736,95 @@ def bench_expr(args):
     print(json.dumps({"metric": "expression ms and GB/s", "unit": "ms", "n_gpus": 1, "steps": args.steps,
                       "warmup": args.warmup, "higher_is_better": False, "data": "synthetic", "dtype": "int64",
                       "config": {"workload": "%d rows, two expression programs" % n}, "result": res}), flush=True)
+
+
+def bench_general(args):
+    """The config-2 custkey workload (60M fact x 15M mid rows) written as a general fragment
+    descriptor (tqp_fragment_run: predicate program, join, group column, SUM and COUNT over value
+    programs, top-100) against the fused custkey fragment, both timed as launch sequences on the
+    stream; the general result must equal the fused one (every group, the join size, the top
+    rows)."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2203_01877_amd as tqp
+    from paper_2203_01877_amd import _lib as X
+
+    fr = datagen.config2() if not args.rows else datagen.config2(n=args.rows, m=max(1, args.rows // 4),
+                                                                  cust_hi=max(1, args.rows // 40))
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    N, M = len(fr.fact["fk"]), len(fr.mid["pk"])
+    fact = tqp.to_device({k: fr.fact[k] for k in ("fk", "date", "price", "disc")}, dev)
+    mid = tqp.to_device(fr.mid, dev)
+    key_bits = datagen.bits_for(max(int(fr.fact["fk"].max()), M - 1) + 1)
+    cust_bits = datagen.bits_for(fr.cust_hi)
+    ctx = tqp.Context(0)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        for _ in range(args.steps):
+            out = fn()
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / args.steps, out
+
+    res = {}
+    fused = {}
+    for bits in (32, 64):
+        run = tqp.CustFragmentRunner(ctx, fact, mid, fr.D, fr.k, key_bits=key_bits, cust_bits=cust_bits,
+                                     gcap=min(N, fr.cust_hi), revenue_bits=bits)
+        ms, _ = timed(lambda: run.run())
+        fused[bits] = run.result()
+        res["fused_rev%d_ms" % bits] = round(ms, 4)
+        log("fused custkey fragment, %d-bit revenue: %.3f ms" % (bits, ms))
+    cols = [fact["fk"], fact["date"], fact["price"], fact["disc"]]
+    dcols = [mid["pk"], mid["custkey"]]
+    rev = [(X.TQP_X_COL, 2), (X.TQP_X_CONST, 100), (X.TQP_X_COL, 3), (X.TQP_X_SUB, 0), (X.TQP_X_MUL, 0)]
+    pred = [(X.TQP_X_COL, 1), (X.TQP_X_CONST, fr.D), (X.TQP_X_LT, 0)]
+    gen = lambda: tqp.fragment_run(ctx, cols, dcols, pred, [], 0, 0, [(5, cust_bits)],
+                                   [(X.AGG_SUM, rev), (X.AGG_COUNT, [])], topk=fr.k, key_bits=key_bits,
+                                   join_cap=N, gcap=fr.cust_hi)
+    ms, out = timed(gen)
+    res["general_ms"] = round(ms, 4)
+    log("general fragment: %.3f ms" % ms)
+    # kernel time of one general call by the library's events
+    ctx.profile_read()
+    ctx.set_profiling(True)
+    gen()
+    torch.cuda.synchronize()
+    recs = ctx.profile_read()
+    ctx.set_profiling(False)
+    per = {}
+    for name, t in recs:
+        per[name] = round(per.get(name, 0.0) + t, 4)
+    res["general_kernels_ms"] = per
+    G = int(out["d_ngroups"].item())
+    f = fused[64]
+    ok = (G == f["groups"] and int(out["d_join"].item()) == f["join_rows"] and ctx.errors() == 0
+          and np.array_equal(out["key"][:G].cpu().numpy(), f["key"])
+          and np.array_equal(out["vals"][0][:G].cpu().numpy(), f["sum"])
+          and np.array_equal(out["vals"][1][:G].cpu().numpy(), f["cnt"]))
+    k = int(out["d_topk"].item())
+    ok = ok and np.array_equal(out["top_key"][:k].cpu().numpy(), f["top_key"])
+    ok = ok and all(np.array_equal(fused[32][x], fused[64][x]) for x in ("key", "sum", "cnt", "top_key"))
+    if not ok:
+        log("general fragment result differs from the fused one")
+        sys.exit(3)
+    res["general_vs_fused_rev32"] = round(res["general_ms"] / res["fused_rev32_ms"], 2)
+    res["general_fact_rows_per_s"] = round(N / (res["general_ms"] * 1e-3), 1)
+    print(json.dumps({"metric": "custkey fragment ms, general descriptor vs fused", "unit": "ms", "n_gpus": 1,
+                      "steps": args.steps, "warmup": args.warmup, "higher_is_better": False, "data": "synthetic",
+                      "dtype": "int64", "config": {"workload": "%d fact x %d mid rows: date<%d, fk=pk, group by "
+                                                             "custkey, sum+count, top-%d" % (N, M, fr.D, fr.k),
+                                                    "groups": G},
+                      "result": res, "results_equal": True}), flush=True)
 
 
 def bench_batch(args):
