@@ -15,12 +15,17 @@
 //   5. group sort  Algorithm 2: the packed keys radix-sorted with the
 //                  joined-row index; for COUNT(DISTINCT v) the rows are first
 //                  sorted by v (two 32-bit passes) so the final stable sort
-//                  orders them by (key, v);
+//                  orders them by (key, v).  When one aggregate alone has a
+//                  value (the others COUNT) and none is COUNT(DISTINCT), the
+//                  value itself rides the sort as an 8-byte payload instead,
+//                  so the reduction reads it in order;
 //   6. runs        the first row of every run of equal keys compacted into the
 //                  group starts (a ballot per 64 rows and a decoupled
-//                  look-back), then one wave per group reduces its run: sum,
-//                  count, min, max, average and the number of value changes
-//                  (distinct values);
+//                  look-back), then every run reduced: sum, count, min, max,
+//                  average and the number of value changes (distinct values).
+//                  A wave takes 64 consecutive groups: each lane reduces its
+//                  own group when every one of them is short, and the whole
+//                  wave reduces each long one;
 //   7. top-k       ORDER BY the first aggregate DESC, key ASC LIMIT k, as
 //                  tqp_topk.
 // Every size after step 1 (kept rows, joined rows, groups) stays on the
@@ -83,6 +88,28 @@ struct SrcPermKey {
         const uint32_t j = perm ? perm[i] : (uint32_t)i;
         k = key_of(j);
         v = j;
+        return true;
+    }
+};
+
+// Sort source over the joined rows: the packed key with the one valued
+// aggregate's value as the payload.
+struct SrcKeyVal64 {
+    const uint32_t* key;
+    const int64_t* val;
+    int64_t n_upper;
+    const int64_t* d_n;
+    __device__ int64_t size() const {
+        const int64_t n = *d_n;
+        return n < n_upper ? n : n_upper;
+    }
+    __device__ bool load_key(int64_t i, uint32_t& k) const {
+        k = key[i];
+        return true;
+    }
+    __device__ bool load(int64_t i, uint32_t& k, uint64_t& v) const {
+        k = key[i];
+        v = (uint64_t)val[i];
         return true;
     }
 };
@@ -182,7 +209,9 @@ k_gf_heads(const uint32_t* skey, int64_t n_upper, const int64_t* d_n, int64_t* s
 }
 
 struct AggSet {
-    const int64_t* val[TQP_FRAGMENT_MAX_AGGS];   // values per joined row (null for COUNT)
+    const int64_t* val[TQP_FRAGMENT_MAX_AGGS];   // values per joined row, read through perm (null for COUNT)
+    const int64_t* sval;                         // or the values of aggregate sk in sorted order
+    int32_t sk;
     void* out[TQP_FRAGMENT_MAX_AGGS];
     int32_t op[TQP_FRAGMENT_MAX_AGGS];
     int32_t n;
@@ -191,8 +220,60 @@ struct AggSet {
 __device__ __forceinline__ uint64_t gf_ord(int64_t x) { return (uint64_t)x ^ (uint64_t(1) << 63); }
 __device__ __forceinline__ int64_t gf_unord(uint64_t u) { return (int64_t)(u ^ (uint64_t(1) << 63)); }
 
-// One wave per group (grid-stride over the groups written): the run
-// [start[g], start[g + 1]) of the sorted keys, rows read through perm.
+constexpr int GF_LANE_GROUP = 64;    // runs at most this long are reduced by one lane
+
+// Partial reduction of rows [b, e) of one run, taking every `step`-th row
+// from b (one lane: step 1; a wave: its lane offset and step 64).
+struct GfPart {
+    int64_t cnt = 0, dist = 0;
+    int64_t sum[TQP_FRAGMENT_MAX_AGGS];
+    uint64_t mn[TQP_FRAGMENT_MAX_AGGS], mx[TQP_FRAGMENT_MAX_AGGS];
+    __device__ void clear() {
+#pragma unroll
+        for (int k = 0; k < TQP_FRAGMENT_MAX_AGGS; ++k) { sum[k] = 0; mn[k] = ~uint64_t(0); mx[k] = 0; }
+        cnt = 0;
+        dist = 0;
+    }
+    __device__ void add(const AggSet& a, const uint32_t* perm, const int64_t* dval, int64_t s, int64_t i) {
+        const uint32_t j = perm ? perm[i] : 0u;
+        ++cnt;
+#pragma unroll
+        for (int k = 0; k < TQP_FRAGMENT_MAX_AGGS; ++k) {
+            if (k >= a.n) continue;
+            const int64_t* vk = a.val[k];
+            if (!vk && !(a.sval && k == a.sk)) continue;
+            const int64_t v = vk ? vk[j] : a.sval[i];
+            sum[k] = (int64_t)((uint64_t)sum[k] + (uint64_t)v);
+            const uint64_t o = gf_ord(v);
+            mn[k] = o < mn[k] ? o : mn[k];
+            mx[k] = o > mx[k] ? o : mx[k];
+        }
+        // rows are in (key, distinct value) order: a value starts where it differs from the row before
+        if (dval) dist += (i == s || dval[j] != dval[perm[i - 1]]) ? 1 : 0;
+    }
+};
+
+__device__ __forceinline__ void gf_write(const AggSet& a, const GfPart& p, int64_t g, int64_t cnt) {
+#pragma unroll
+    for (int k = 0; k < TQP_FRAGMENT_MAX_AGGS; ++k) {
+        if (k >= a.n) continue;
+        int64_t* o64 = static_cast<int64_t*>(a.out[k]);
+        switch (a.op[k]) {
+            case TQP_AGG_COUNT: o64[g] = cnt; break;
+            case TQP_AGG_SUM: o64[g] = p.sum[k]; break;
+            case TQP_AGG_MIN: o64[g] = gf_unord(p.mn[k]); break;
+            case TQP_AGG_MAX: o64[g] = gf_unord(p.mx[k]); break;
+            case TQP_AGG_AVG: static_cast<double*>(a.out[k])[g] = (double)p.sum[k] / (double)cnt; break;
+            default: o64[g] = p.dist; break;
+        }
+    }
+}
+
+// Every group's aggregates: each wave takes 64 consecutive groups (grid-stride);
+// a lane reduces its own group when all 64 are at most GF_LANE_GROUP rows,
+// else the wave reduces the long ones one at a time and the lanes the rest.
+// The run of group g is [start[g], start[g + 1]) of the sorted keys; values
+// come through perm, or in sorted order (a.sval).
 __global__ void __launch_bounds__(GF_AGG_BLOCK)
 k_gf_agg(const uint32_t* skey, const uint32_t* perm, const int64_t* start, const int64_t* d_groups,
          const int64_t* d_rows, int64_t rows_upper, AggSet a, const int64_t* dval, int32_t* out_key, int64_t gcap,
@@ -209,46 +290,38 @@ k_gf_agg(const uint32_t* skey, const uint32_t* perm, const int64_t* start, const
     const int l = lane_id();
     const int64_t wid = ((int64_t)blockIdx.x * GF_AGG_BLOCK + threadIdx.x) / WAVE;
     const int64_t nw = (int64_t)gridDim.x * GF_AGG_BLOCK / WAVE;
-    for (int64_t g = wid; g < Gw; g += nw) {
-        const int64_t s = start[g], e = g + 1 < G ? start[g + 1] : J;
-        int64_t cnt = 0, dist = 0;
-        int64_t sum[TQP_FRAGMENT_MAX_AGGS];
-        uint64_t mn[TQP_FRAGMENT_MAX_AGGS], mx[TQP_FRAGMENT_MAX_AGGS];
-#pragma unroll
-        for (int k = 0; k < TQP_FRAGMENT_MAX_AGGS; ++k) { sum[k] = 0; mn[k] = ~uint64_t(0); mx[k] = 0; }
-        for (int64_t i = s + l; i < e; i += WAVE) {
-            const uint32_t j = perm[i];
-            ++cnt;
+    for (int64_t g0 = wid * WAVE; g0 < Gw; g0 += nw * WAVE) {
+        const int64_t g = g0 + l;
+        const bool has = g < Gw;
+        const int64_t s = has ? start[g] : 0, e = has ? (g + 1 < G ? start[g + 1] : J) : 0;
+        const bool lng = e - s > GF_LANE_GROUP;
+        if (has && !lng) {
+            GfPart p;
+            p.clear();
+            for (int64_t i = s; i < e; ++i) p.add(a, perm, dval, s, i);
+            out_key[g] = (int32_t)skey[s];
+            gf_write(a, p, g, p.cnt);
+        }
+        uint64_t big = ballot(has && lng);
+        while (big) {
+            const int src = __ffsll((unsigned long long)big) - 1;
+            big &= big - 1;
+            const int64_t gs = wave_read(s, src), ge = wave_read(e, src), gg = g0 + src;
+            GfPart p;
+            p.clear();
+            for (int64_t i = gs + l; i < ge; i += WAVE) p.add(a, perm, dval, gs, i);
+            const int64_t cnt = wave_sum(p.cnt);
+            p.dist = wave_sum(p.dist);
 #pragma unroll
             for (int k = 0; k < TQP_FRAGMENT_MAX_AGGS; ++k) {
-                if (k < a.n && a.val[k]) {
-                    const int64_t v = a.val[k][j];
-                    sum[k] = (int64_t)((uint64_t)sum[k] + (uint64_t)v);
-                    const uint64_t o = gf_ord(v);
-                    mn[k] = o < mn[k] ? o : mn[k];
-                    mx[k] = o > mx[k] ? o : mx[k];
-                }
+                if (k >= a.n) continue;
+                p.sum[k] = wave_sum(p.sum[k]);
+                p.mn[k] = wave_min(p.mn[k]);
+                p.mx[k] = wave_max(p.mx[k]);
             }
-            // rows are in (key, distinct value) order: a value starts where it differs from the row before
-            if (dval) dist += (i == s || dval[j] != dval[perm[i - 1]]) ? 1 : 0;
-        }
-        cnt = wave_sum(cnt);
-        dist = wave_sum(dist);
-        if (l == 0) out_key[g] = (int32_t)skey[s];
-#pragma unroll
-        for (int k = 0; k < TQP_FRAGMENT_MAX_AGGS; ++k) {
-            if (k >= a.n) continue;
-            const int64_t sk = wave_sum(sum[k]);
-            const uint64_t lo = wave_min(mn[k]), hi = wave_max(mx[k]);
-            if (l != 0) continue;
-            int64_t* o64 = static_cast<int64_t*>(a.out[k]);
-            switch (a.op[k]) {
-                case TQP_AGG_COUNT: o64[g] = cnt; break;
-                case TQP_AGG_SUM: o64[g] = sk; break;
-                case TQP_AGG_MIN: o64[g] = gf_unord(lo); break;
-                case TQP_AGG_MAX: o64[g] = gf_unord(hi); break;
-                case TQP_AGG_AVG: static_cast<double*>(a.out[k])[g] = (double)sk / (double)cnt; break;
-                default: o64[g] = dist; break;
+            if (l == 0) {
+                out_key[gg] = (int32_t)skey[gs];
+                gf_write(a, p, gg, cnt);
             }
         }
     }
@@ -262,6 +335,9 @@ struct GenBufs {
     int64_t* fkeep = nullptr;
     int64_t* dkeep = nullptr;
     RadixBufs<Cfg, uint32_t> fsort, dsort, sa, sb, sc;
+    int vsort = -1;                          // the one valued aggregate whose value rides the group sort
+    RadixBufs<Cfg, uint64_t> sv;
+    uint64_t* vc = nullptr;
     JoinBufs jb;
     uint32_t *fsk = nullptr, *fsv = nullptr, *dsk = nullptr, *dsv = nullptr;
     uint64_t* fstatus = nullptr;             // no join: the compaction of the kept fact rows
@@ -323,9 +399,21 @@ void gen_reserve(Arena& a, const tqp_fragment& f, const tqp_fragment_out& o, Gen
         b.kb = a.scratch<uint32_t>(J);
         b.pb = a.scratch<uint32_t>(J);
     }
-    b.sc = radix_reserve<Cfg, uint32_t>(a, J, b.gbits);
+    int valued = 0;
+    for (int k = 0; k < f.n_agg; ++k)
+        if (f.aggs[k].op != TQP_AGG_COUNT) {
+            ++valued;
+            b.vsort = k;
+        }
+    if (valued != 1 || b.distinct >= 0) b.vsort = -1;
     b.kc = a.scratch<uint32_t>(J);
-    b.pc = a.scratch<uint32_t>(J);
+    if (b.vsort >= 0) {
+        b.sv = radix_reserve<Cfg, uint64_t>(a, J, b.gbits);
+        b.vc = a.scratch<uint64_t>(J);
+    } else {
+        b.sc = radix_reserve<Cfg, uint32_t>(a, J, b.gbits);
+        b.pc = a.scratch<uint32_t>(J);
+    }
     b.gstart = a.scratch<int64_t>(J + 1);
     const int64_t htiles = (J + GF_HEAD_BLOCK * GF_HEAD_ITEMS - 1) / (GF_HEAD_BLOCK * GF_HEAD_ITEMS);
     b.hstatus = a.zero<uint64_t>(htiles);
@@ -436,23 +524,33 @@ tqp_status gen_launch(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_ou
             return st;
         perm_in = b.pb;
     }
-    SrcPermKey<0> a3{b.gkey, perm_in, J, b.d_join};
-    if ((st = radix_launch<Cfg, uint32_t>(b.sc, a3, J, true, nullptr, key_mask_for(b.gbits), b.kc, b.pc, ctx, s,
-                                          "fragment_sort_group", "fragment_sort_group")) != TQP_OK)
-        return st;
+    if (b.vsort >= 0) {
+        SrcKeyVal64 a3{b.gkey, b.vals[b.vsort], J, b.d_join};
+        if ((st = radix_launch<Cfg, uint64_t>(b.sv, a3, J, true, nullptr, key_mask_for(b.gbits), b.kc, b.vc, ctx, s,
+                                              "fragment_sort_group", "fragment_sort_group")) != TQP_OK)
+            return st;
+    } else {
+        SrcPermKey<0> a3{b.gkey, perm_in, J, b.d_join};
+        if ((st = radix_launch<Cfg, uint32_t>(b.sc, a3, J, true, nullptr, key_mask_for(b.gbits), b.kc, b.pc, ctx, s,
+                                              "fragment_sort_group", "fragment_sort_group")) != TQP_OK)
+            return st;
+    }
     // 6. runs: group starts, then one wave per group
     TQP_LAUNCH(ctx, s, "fragment_heads",
                k_gf_heads<<<grid_for(J, GF_HEAD_BLOCK * GF_HEAD_ITEMS, 0), GF_HEAD_BLOCK, 0, s>>>(
                    b.kc, J, b.d_join, b.gstart, b.d_groups, b.hstatus, b.hcounter, ctx->d_err));
     AggSet as{};
     as.n = f.n_agg;
+    as.sk = b.vsort;
+    as.sval = b.vsort >= 0 ? reinterpret_cast<const int64_t*>(b.vc) : nullptr;
     for (int k = 0; k < f.n_agg; ++k) {
-        as.val[k] = b.vals[k];
+        as.val[k] = k == b.vsort ? nullptr : b.vals[k];
         as.out[k] = f.aggs[k].out;
         as.op[k] = f.aggs[k].op;
     }
     const int64_t* dval = b.distinct >= 0 ? b.vals[b.distinct] : nullptr;
-    const int64_t waves = o.gcap < (int64_t)ctx->num_cus * 64 ? o.gcap : (int64_t)ctx->num_cus * 64;
+    const int64_t gw = (o.gcap + WAVE - 1) / WAVE;   // waves of 64 groups
+    const int64_t waves = gw < (int64_t)ctx->num_cus * 32 ? gw : (int64_t)ctx->num_cus * 32;
     TQP_LAUNCH(ctx, s, "fragment_agg",
                k_gf_agg<<<grid_for(waves, GF_AGG_BLOCK / WAVE, 0), GF_AGG_BLOCK, 0, s>>>(
                    b.kc, b.pc, b.gstart, b.d_groups, b.d_join, J, as, dval, o.key, o.gcap, o.d_ngroups, b.d_written,
