@@ -127,7 +127,11 @@ k_radix_chunk_scan(const uint32_t* ctot, int nchunks, const uint32_t* hist0, int
 
 __global__ void __launch_bounds__(FINISH_BLOCK)
 k_finish_sort(const uint32_t* kin, const uint32_t* vin, int64_t n, uint32_t* kout, uint32_t* vout, int lowb,
-              int64_t* bstart) {
+              int64_t* bstart, const int64_t* d_n) {
+    if (d_n) {
+        const int64_t t = *d_n;
+        n = t < n ? t : n;
+    }
     constexpr int U = 8;                              // loads in flight per thread
     constexpr int W = FINISH_BLOCK / WAVE;
     constexpr int SLICE = FINISH_SPAN / W;            // counters scanned by one wave

@@ -21,16 +21,16 @@ constexpr int BUCKET_SMALL_LOWB = 9;
 // profile tags of the custkey fragment's three sorts
 constexpr int SORT_TAG_FACT = 1, SORT_TAG_MID = 2, SORT_TAG_GROUP = 3;
 
-// Low key bits the fact sort may leave out.  A join tile of TILE left rows
+// Low key bits the left sort of a join may leave out.  A join tile of TILE left rows
 // over keys spread evenly on [0, 2^kb) spans about TILE * 2^kb / n key values
 // plus one bucket of 2^s; both must fit the join's LDS table (RWIN), and the
 // sorted high bits should fill whole radix passes.  Tiles that do not fit
 // fall back to binary searches, so this is a cost choice, not a correctness
 // condition.
-int fact_low_bits(int64_t n, int kb, int rb) {
+int join_low_bits(int64_t n, int kb, int rb, int tile, int rwin) {
     if (n <= 0) return 0;
-    const double spread = (double)JCfgFrag::TILE * std::ldexp(1.0, kb) / (double)n;
-    const double room = 0.85 * JCfgFrag::RWIN - spread;
+    const double spread = (double)tile * std::ldexp(1.0, kb) / (double)n;
+    const double room = 0.85 * rwin - spread;
     if (room < 64) return 0;
     int smax = 0;
     while (smax + 1 <= kb && std::ldexp(1.0, smax + 1) <= room) ++smax;
@@ -38,6 +38,7 @@ int fact_low_bits(int64_t n, int kb, int rb) {
     int s = kb - passes * rb;
     return s < 0 ? 0 : s;
 }
+int fact_low_bits(int64_t n, int kb, int rb) { return join_low_bits(n, kb, rb, JCfgFrag::TILE, JCfgFrag::RWIN); }
 
 // Groups of the flags fragment in ascending packed-key order, skipping
 // packed keys no row reached (SQL emits no empty group).
@@ -239,7 +240,8 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
                                                    1)) != TQP_OK)
         return st;
     if (!f.mid_sorted && (st = side_join(ctx, s)) != TQP_OK) return st;
-    // join: emits (custkey, revenue)
+    // join: emits (custkey, revenue); the bucket starts exist only for a
+    // non-empty mid (an empty one gives empty windows by search)
     using Emit = EmitKeyVal<JCfgFrag::BLOCK, Cfg::RADIX_BITS, VT>;
     Emit e{};
     e.out_key = b.gkeys_in;
@@ -255,7 +257,8 @@ tqp_status cust_launch(tqp_ctx* ctx, const tqp_cust_fragment& f, const tqp_cust_
     }
     if ((st = join_launch<JCfgFrag, VT, uint32_t>(ctx, s, "join_keyval", b.join, b.fkeys, b.fvals, f.n_fact,
                                                   b.fact.d_cnt, mk, mv, f.n_mid, (const int64_t*)nullptr, b.d_join,
-                                                  f.join_cap, e, b.fact_lowb, o.d_join, b.mbstart, b.nmbkt)) !=
+                                                  f.join_cap, e, b.fact_lowb, o.d_join,
+                                                  f.n_mid > 0 ? b.mbstart : nullptr, b.nmbkt)) !=
         TQP_OK)
         return st;
     // group-by: sort (custkey, revenue) on the custkey bits above lowb (the

@@ -135,6 +135,11 @@ struct CustBufs {
 };
 
 tqp_status check_flags(const tqp_flags_fragment* f, const tqp_flags_out* o);
+// Low key bits a join's left sort may leave unsorted (the join resolves them
+// in LDS) for n left rows of kb-bit keys, tiles of `tile` rows and LDS tables
+// of `rwin` keys; the right side then needs the same high-bit passes plus the
+// finishing pass.
+int join_low_bits(int64_t n, int kb, int rb, int tile, int rwin);
 
 // Batch preparation without any allocation: descriptor tables go into the
 // workspace, uploaded on `stream` (or synchronously); only the configurations

@@ -6,8 +6,12 @@
 //   2. join        Algorithm 1: both key columns radix-sorted with their row
 //                  ids, the keep column fused into the sort's first pass so
 //                  dropped rows are never written; the sort-based join gives
-//                  (fact row, dim row) pairs (late materialisation).  Without
-//                  a join the kept fact rows are compacted instead;
+//                  (fact row, dim row) pairs (late materialisation).  As in
+//                  the fused fragments, the sorts leave the low key bits a
+//                  join tile resolves in LDS unsorted on the fact side, and
+//                  the dim side gets the same high-bit passes plus one
+//                  finishing pass per 4096-key span.  Without a join the kept
+//                  fact rows are compacted instead;
 //   3. group key   the group columns read through the pairs and packed into
 //                  one key (Algorithm 2's concatenated group columns);
 //   4. values      every aggregate's program evaluated over the joined rows,
@@ -335,6 +339,10 @@ struct GenBufs {
     int64_t* fkeep = nullptr;
     int64_t* dkeep = nullptr;
     RadixBufs<Cfg, uint32_t> fsort, dsort, sa, sb, sc;
+    int flowb = 0;                           // fact key bits left to the join tiles
+    int64_t nspans = 0, nmbkt = 0;
+    uint32_t *dsk_full = nullptr, *dsv_full = nullptr;   // dim keys after the finishing pass
+    int64_t* mbstart = nullptr;              // start of every 2^flowb-key bucket in them
     int vsort = -1;                          // the one valued aggregate whose value rides the group sort
     RadixBufs<Cfg, uint64_t> sv;
     uint64_t* vc = nullptr;
@@ -373,8 +381,17 @@ void gen_reserve(Arena& a, const tqp_fragment& f, const tqp_fragment_out& o, Gen
     if (f.n_fact_pred > 0) b.fkeep = a.scratch<int64_t>(N);
     if (b.join) {
         if (f.n_dim_pred > 0) b.dkeep = a.scratch<int64_t>(f.n_dim);
-        b.fsort = radix_reserve<Cfg, uint32_t>(a, N, kb);
-        b.dsort = radix_reserve<Cfg, uint32_t>(a, f.n_dim, kb);
+        b.flowb = join_low_bits(N, kb, Cfg::RADIX_BITS, JCfgGen::TILE, JCfgGen::RWIN);
+        if (b.flowb > FINISH_LOG2) b.flowb = FINISH_LOG2;
+        b.fsort = radix_reserve<Cfg, uint32_t>(a, N, kb, b.flowb);
+        b.dsort = radix_reserve<Cfg, uint32_t>(a, f.n_dim, kb, b.flowb);
+        if (b.flowb > 0) {
+            b.dsk_full = a.scratch<uint32_t>(f.n_dim);
+            b.dsv_full = a.scratch<uint32_t>(f.n_dim);
+            b.nspans = ((int64_t(1) << kb) + FINISH_SPAN - 1) >> FINISH_LOG2;
+            b.nmbkt = b.nspans << (FINISH_LOG2 - b.flowb);
+            b.mbstart = a.scratch<int64_t>(b.nmbkt + 1);
+        }
         b.fsk = a.scratch<uint32_t>(N);
         b.fsv = a.scratch<uint32_t>(N);
         b.dsk = a.scratch<uint32_t>(f.n_dim);
@@ -458,10 +475,22 @@ tqp_status gen_launch(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_ou
         if ((st = radix_launch<Cfg, uint32_t>(b.dsort, ds, f.n_dim, true, nullptr, key_mask_for(kb), b.dsk, b.dsv,
                                               ctx, s, "fragment_sort_dim", "fragment_sort_dim")) != TQP_OK)
             return st;
+        const uint32_t* rk = b.dsk;
+        const uint32_t* rv = b.dsv;
+        if (b.flowb > 0 && f.n_dim > 0) {
+            // the low bits of the dim keys, span by span, and every bucket's start
+            TQP_LAUNCH(ctx, s, "fragment_finish_dim",
+                       k_finish_sort<<<(unsigned)b.nspans, FINISH_BLOCK, 0, s>>>(b.dsk, b.dsv, f.n_dim, b.dsk_full,
+                                                                              b.dsv_full, b.flowb, b.mbstart,
+                                                                              b.dsort.d_cnt));
+            rk = b.dsk_full;
+            rv = b.dsv_full;
+        }
         EmitPairs e{b.li, b.ri, J};
-        if ((st = join_launch<JCfgGen, uint32_t, uint32_t, EmitPairs>(ctx, s, "fragment_join", b.jb, b.fsk, b.fsv, N,
-                                                                     b.fsort.d_cnt, b.dsk, b.dsv, f.n_dim,
-                                                                     b.dsort.d_cnt, b.d_join, J, e)) != TQP_OK)
+        if ((st = join_launch<JCfgGen, uint32_t, uint32_t, EmitPairs>(
+                 ctx, s, "fragment_join", b.jb, b.fsk, b.fsv, N, b.fsort.d_cnt, rk, rv, f.n_dim, b.dsort.d_cnt,
+                 b.d_join, J, e, b.flowb, nullptr, b.flowb > 0 && f.n_dim > 0 ? b.mbstart : nullptr, b.nmbkt)) !=
+            TQP_OK)
             return st;
     } else {
         FilterPreds fp{};

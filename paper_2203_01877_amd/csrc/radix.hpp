@@ -666,11 +666,12 @@ k_radix_pass_counted(Src src, DstPairs<V> dst, int shift, int bits, PassCounts p
 // 0 < lowb <= FINISH_LOG2), each block also records where every bucket of
 // 2^lowb key values in its span starts in the output, and the last block the
 // end of the last bucket: bstart[b] = lower_bound(kout, b << lowb) for b in
-// [0, nspans << (FINISH_LOG2 - lowb)].
+// [0, nspans << (FINISH_LOG2 - lowb)].  With d_n, the keys are the first
+// min(n, *d_n).
 constexpr int FINISH_LOG2 = 12;
 constexpr int FINISH_SPAN = 1 << FINISH_LOG2;
 constexpr int FINISH_BLOCK = 256;
 __global__ void k_finish_sort(const uint32_t* kin, const uint32_t* vin, int64_t n, uint32_t* kout, uint32_t* vout,
-                              int lowb, int64_t* bstart);
+                              int lowb, int64_t* bstart, const int64_t* d_n = nullptr);
 
 }  // namespace tqp

@@ -216,6 +216,18 @@ def test_cust_partial_mid(hip, ctx, digit_bits, shape):
     assert ctx.errors() == 0
 
 
+def test_cust_empty_mid(hip, ctx):
+    """1.5M fact rows (so the fact sort leaves low bits to the join) against an empty mid table:
+    no joined rows, no groups, no top rows, no error."""
+    fr = datagen.config2(seed=78, n=1_500_000, m=400_000, cust_hi=50_000)
+    fr = dataclasses.replace(fr, mid={k: v[:0] for k, v in fr.mid.items()})
+    want = oracle.fragment_cust(fr.fact, fr.mid, fr.D, fr.k, gcap=fr.cust_hi)
+    assert want["join_rows"] == 0 and want["groups"] == 0
+    got = _cust(hip, ctx, fr)
+    _assert_cust(got, want)
+    assert ctx.errors() == 0
+
+
 @pytest.mark.timeout(600)
 def test_config2_full(hip, ctx):
     """The 60M-row workload the benchmark times (revenue carried in 32 bits),

@@ -90,9 +90,10 @@ def test_general_random(hip, ctx, trial):
     _check(got, want, topk)
 
 
-@pytest.mark.parametrize("n,m", [(0, 10), (1, 1), (10, 0)])
+@pytest.mark.parametrize("n,m", [(0, 10), (1, 1), (10, 0), (250_003, 0)])
 def test_general_empty(hip, ctx, n, m):
-    """Empty and one-row sides: no joined rows and no groups (or the single match)."""
+    """Empty and one-row sides: no joined rows and no groups (or the single match); 250,003 fact
+    rows against an empty dim table (the fact sort leaves low bits to the join)."""
     O = oracle
     rng = np.random.default_rng(n + 3 * m)
     fact, dim = _tables(rng, n, max(m, 1), 5, False)
