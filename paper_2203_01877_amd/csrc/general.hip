@@ -12,6 +12,14 @@
 //                  the dim side gets the same high-bit passes plus one
 //                  finishing pass per 4096-key span.  Without a join the kept
 //                  fact rows are compacted instead;
+//      Two plan rules of the hand-optimised plans (Section 6.6) carry what
+//      the join's output needs through the key sorts instead of row ids: when
+//      the only use of the fact rows after the join is one aggregate's value
+//      program over fact columns, the program runs over the fact rows in
+//      order before the sort and its value rides the sort (8-byte payload);
+//      when the only use of the dim rows is one int32 group column, that
+//      column rides the dim sort.  The join then emits those values directly
+//      and nothing is read through row ids (the fused fragments' layout);
 //   3. group key   the group columns read through the pairs and packed into
 //                  one key (Algorithm 2's concatenated group columns);
 //   4. values      every aggregate's program evaluated over the joined rows,
@@ -63,6 +71,58 @@ struct SrcKeepRow {
         v = (uint32_t)i;
         return keep ? keep[i] != 0 : true;
     }
+};
+
+// Sort sources that carry a value instead of the row id: a precomputed int64
+// per row (the fact value program), or an int32 column (the dim group column).
+struct SrcKeepVal64 {
+    const int32_t* key;
+    const int64_t* keep;
+    const int64_t* val;
+    int64_t n;
+    __device__ int64_t size() const { return n; }
+    __device__ bool load_key(int64_t i, uint32_t& k) const {
+        k = (uint32_t)key[i];
+        return keep ? keep[i] != 0 : true;
+    }
+    __device__ bool load(int64_t i, uint32_t& k, uint64_t& v) const {
+        k = (uint32_t)key[i];
+        v = (uint64_t)val[i];
+        return keep ? keep[i] != 0 : true;
+    }
+};
+struct SrcKeepCol {
+    const int32_t* key;
+    const int64_t* keep;
+    const int32_t* col;
+    int64_t n;
+    __device__ int64_t size() const { return n; }
+    __device__ bool load_key(int64_t i, uint32_t& k) const {
+        k = (uint32_t)key[i];
+        return keep ? keep[i] != 0 : true;
+    }
+    __device__ bool load(int64_t i, uint32_t& k, uint32_t& v) const {
+        k = (uint32_t)key[i];
+        v = (uint32_t)col[i];
+        return keep ? keep[i] != 0 : true;
+    }
+};
+
+// Join output with a carried fact value: (value, dim row or carried dim value).
+struct EmitValRow {
+    static constexpr bool ORDERED = true;
+    int64_t* out_v;
+    int32_t* out_r;
+    int64_t cap;
+    struct Smem {};
+    __device__ void init(Smem&) {}
+    __device__ void operator()(int64_t o, uint32_t, uint64_t lp, uint32_t rp, Smem&) {
+        if (o < cap) {
+            out_v[o] = (int64_t)lp;
+            out_r[o] = (int32_t)rp;
+        }
+    }
+    __device__ void finish(Smem&) {}
 };
 
 // Sort source over the joined rows: row j = perm[i] (or i), key from an
@@ -121,7 +181,7 @@ struct SrcKeyVal64 {
 struct GroupCols {
     const void* col[TQP_FRAGMENT_MAX_GROUP_COLS];
     int32_t type[TQP_FRAGMENT_MAX_GROUP_COLS];
-    int32_t side[TQP_FRAGMENT_MAX_GROUP_COLS];      // 0: read through the fact row, 1: the dim row
+    int32_t side[TQP_FRAGMENT_MAX_GROUP_COLS];      // 0: read through the fact row, 1: the dim row, 2: at the joined row
     int32_t bits[TQP_FRAGMENT_MAX_GROUP_COLS];
     int32_t n;
 };
@@ -144,7 +204,7 @@ k_gf_pack(GroupCols g, const int32_t* li, const int32_t* ri, int64_t n_upper, co
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         uint32_t v = 0;
         for (int c = 0; c < g.n; ++c) {
-            const int64_t r = g.side[c] ? (int64_t)ri[i] : (int64_t)li[i];
+            const int64_t r = g.side[c] == 2 ? i : g.side[c] ? (int64_t)ri[i] : (int64_t)li[i];
             const int64_t x = gf_load(g.col[c], g.type[c], r);
             const int64_t lim = int64_t(1) << g.bits[c];
             bad |= x < 0 || x >= lim;
@@ -344,6 +404,12 @@ struct GenBufs {
     uint32_t *dsk_full = nullptr, *dsv_full = nullptr;   // dim keys after the finishing pass
     int64_t* mbstart = nullptr;              // start of every 2^flowb-key bucket in them
     int vsort = -1;                          // the one valued aggregate whose value rides the group sort
+    bool fpush = false;                      // that value rides the fact sort (fact-only program)
+    int dpush = -1;                          // the dim column that rides the dim sort, or -1
+    int64_t* fval = nullptr;                 // fpush: the program over every fact row
+    RadixBufs<Cfg, uint64_t> fsort64;
+    uint64_t* fsv64 = nullptr;
+    int64_t* jval = nullptr;                 // fpush: the value of every joined row
     RadixBufs<Cfg, uint64_t> sv;
     uint64_t* vc = nullptr;
     JoinBufs jb;
@@ -378,12 +444,60 @@ void gen_reserve(Arena& a, const tqp_fragment& f, const tqp_fragment_out& o, Gen
     b.gbits = gf_group_bits(f);
     for (int k = 0; k < f.n_agg; ++k)
         if (f.aggs[k].op == TQP_AGG_COUNT_DISTINCT) b.distinct = k;
+    int valued = 0;
+    for (int k = 0; k < f.n_agg; ++k)
+        if (f.aggs[k].op != TQP_AGG_COUNT) {
+            ++valued;
+            b.vsort = k;
+        }
+    if (valued != 1 || b.distinct >= 0) b.vsort = -1;
+    if (b.join) {
+        // what the join's output is used for: columns of each side read after it
+        auto prog_sides = [&](const tqp_xinstr* pr, int np, bool& uses_f, bool& uses_d) {
+            for (int i = 0; i < np; ++i)
+                if (pr[i].op == TQP_X_COL) (pr[i].arg < f.n_fact_cols ? uses_f : uses_d) = true;
+        };
+        bool group_f = false, group_d = false;
+        int gd = -1;
+        bool gd_one = true;
+        for (int i = 0; i < f.n_group; ++i) {
+            const int c = f.group[i].col;
+            if (c < f.n_fact_cols) {
+                group_f = true;
+            } else {
+                group_d = true;
+                if (gd >= 0 && gd != c) gd_one = false;
+                gd = c;
+            }
+        }
+        bool prog_f = false, prog_d = false;
+        for (int k = 0; k < f.n_agg; ++k)
+            if (f.aggs[k].op != TQP_AGG_COUNT) prog_sides(f.aggs[k].prog, f.aggs[k].nprog, prog_f, prog_d);
+        // the fact rows serve only the one valued aggregate, whose program reads
+        // only fact columns; evaluated over every fact row, it must not divide
+        // (a zero divisor on a row the join drops would raise the value flag)
+        bool divides = false;
+        if (b.vsort >= 0)
+            for (int i = 0; i < f.aggs[b.vsort].nprog; ++i)
+                divides |= f.aggs[b.vsort].prog[i].op == TQP_X_DIV || f.aggs[b.vsort].prog[i].op == TQP_X_MOD;
+        b.fpush = b.vsort >= 0 && prog_f && !prog_d && !group_f && !divides;
+        // the dim rows serve only one int32 group column
+        if (group_d && gd_one && !prog_d && f.dim_cols[gd - f.n_fact_cols].type == TQP_I32) b.dpush = gd - f.n_fact_cols;
+    }
     if (f.n_fact_pred > 0) b.fkeep = a.scratch<int64_t>(N);
     if (b.join) {
         if (f.n_dim_pred > 0) b.dkeep = a.scratch<int64_t>(f.n_dim);
         b.flowb = join_low_bits(N, kb, Cfg::RADIX_BITS, JCfgGen::TILE, JCfgGen::RWIN);
         if (b.flowb > FINISH_LOG2) b.flowb = FINISH_LOG2;
-        b.fsort = radix_reserve<Cfg, uint32_t>(a, N, kb, b.flowb);
+        if (b.fpush) {
+            b.fval = a.scratch<int64_t>(N);
+            b.fsort64 = radix_reserve<Cfg, uint64_t>(a, N, kb, b.flowb);
+            b.fsv64 = a.scratch<uint64_t>(N);
+            b.jval = a.scratch<int64_t>(J);
+        } else {
+            b.fsort = radix_reserve<Cfg, uint32_t>(a, N, kb, b.flowb);
+            b.fsv = a.scratch<uint32_t>(N);
+        }
         b.dsort = radix_reserve<Cfg, uint32_t>(a, f.n_dim, kb, b.flowb);
         if (b.flowb > 0) {
             b.dsk_full = a.scratch<uint32_t>(f.n_dim);
@@ -393,7 +507,6 @@ void gen_reserve(Arena& a, const tqp_fragment& f, const tqp_fragment_out& o, Gen
             b.mbstart = a.scratch<int64_t>(b.nmbkt + 1);
         }
         b.fsk = a.scratch<uint32_t>(N);
-        b.fsv = a.scratch<uint32_t>(N);
         b.dsk = a.scratch<uint32_t>(f.n_dim);
         b.dsv = a.scratch<uint32_t>(f.n_dim);
         b.jb = join_reserve<JCfgGen>(a, N);
@@ -403,11 +516,11 @@ void gen_reserve(Arena& a, const tqp_fragment& f, const tqp_fragment_out& o, Gen
         b.fstatus = a.zero<uint64_t>(tiles);
         b.fcounter = a.zero<uint32_t>(1);
     }
-    b.li = a.scratch<int32_t>(J);
+    if (!b.fpush) b.li = a.scratch<int32_t>(J);
     b.d_join = a.zero<int64_t>(1);
     b.gkey = a.scratch<uint32_t>(J);
     for (int k = 0; k < f.n_agg; ++k)
-        if (f.aggs[k].op != TQP_AGG_COUNT) b.vals[k] = a.scratch<int64_t>(J);
+        if (f.aggs[k].op != TQP_AGG_COUNT) b.vals[k] = b.fpush && k == b.vsort ? b.jval : a.scratch<int64_t>(J);
     if (b.distinct >= 0) {
         b.sa = radix_reserve<Cfg, uint32_t>(a, J, 32);
         b.sb = radix_reserve<Cfg, uint32_t>(a, J, 32);
@@ -416,13 +529,6 @@ void gen_reserve(Arena& a, const tqp_fragment& f, const tqp_fragment_out& o, Gen
         b.kb = a.scratch<uint32_t>(J);
         b.pb = a.scratch<uint32_t>(J);
     }
-    int valued = 0;
-    for (int k = 0; k < f.n_agg; ++k)
-        if (f.aggs[k].op != TQP_AGG_COUNT) {
-            ++valued;
-            b.vsort = k;
-        }
-    if (valued != 1 || b.distinct >= 0) b.vsort = -1;
     b.kc = a.scratch<uint32_t>(J);
     if (b.vsort >= 0) {
         b.sv = radix_reserve<Cfg, uint64_t>(a, J, b.gbits);
@@ -467,14 +573,38 @@ tqp_status gen_launch(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_ou
         return st;
     // 2. join, or the kept fact rows
     if (b.join) {
-        SrcKeepRow fs{static_cast<const int32_t*>(f.fact_cols[f.fact_key].data), b.fkeep, N};
-        SrcKeepRow ds{static_cast<const int32_t*>(f.dim_cols[f.dim_key].data), b.dkeep, f.n_dim};
-        if ((st = radix_launch<Cfg, uint32_t>(b.fsort, fs, N, true, nullptr, key_mask_for(kb), b.fsk, b.fsv, ctx, s,
-                                              "fragment_sort_fact", "fragment_sort_fact")) != TQP_OK)
-            return st;
-        if ((st = radix_launch<Cfg, uint32_t>(b.dsort, ds, f.n_dim, true, nullptr, key_mask_for(kb), b.dsk, b.dsv,
-                                              ctx, s, "fragment_sort_dim", "fragment_sort_dim")) != TQP_OK)
-            return st;
+        const int32_t* fkey = static_cast<const int32_t*>(f.fact_cols[f.fact_key].data);
+        const int32_t* dkey = static_cast<const int32_t*>(f.dim_cols[f.dim_key].data);
+        const int64_t* fsort_cnt;
+        if (b.fpush) {
+            // the one value program over every fact row, in row order, before the sort
+            const tqp_agg& ag = f.aggs[b.vsort];
+            if (N > 0 && (st = eval_program(ctx, f.fact_cols, nullptr, f.n_fact_cols, N, nullptr, ag.prog, ag.nprog,
+                                            b.fval, s, "tqp_fragment_run", "fragment_fact_value")) != TQP_OK)
+                return st;
+            SrcKeepVal64 fs{fkey, b.fkeep, b.fval, N};
+            if ((st = radix_launch<Cfg, uint64_t>(b.fsort64, fs, N, true, nullptr, key_mask_for(kb), b.fsk, b.fsv64,
+                                                  ctx, s, "fragment_sort_fact", "fragment_sort_fact")) != TQP_OK)
+                return st;
+            fsort_cnt = b.fsort64.d_cnt;
+        } else {
+            SrcKeepRow fs{fkey, b.fkeep, N};
+            if ((st = radix_launch<Cfg, uint32_t>(b.fsort, fs, N, true, nullptr, key_mask_for(kb), b.fsk, b.fsv, ctx,
+                                                  s, "fragment_sort_fact", "fragment_sort_fact")) != TQP_OK)
+                return st;
+            fsort_cnt = b.fsort.d_cnt;
+        }
+        if (b.dpush >= 0) {
+            SrcKeepCol ds{dkey, b.dkeep, static_cast<const int32_t*>(f.dim_cols[b.dpush].data), f.n_dim};
+            if ((st = radix_launch<Cfg, uint32_t>(b.dsort, ds, f.n_dim, true, nullptr, key_mask_for(kb), b.dsk,
+                                                  b.dsv, ctx, s, "fragment_sort_dim", "fragment_sort_dim")) != TQP_OK)
+                return st;
+        } else {
+            SrcKeepRow ds{dkey, b.dkeep, f.n_dim};
+            if ((st = radix_launch<Cfg, uint32_t>(b.dsort, ds, f.n_dim, true, nullptr, key_mask_for(kb), b.dsk,
+                                                  b.dsv, ctx, s, "fragment_sort_dim", "fragment_sort_dim")) != TQP_OK)
+                return st;
+        }
         const uint32_t* rk = b.dsk;
         const uint32_t* rv = b.dsv;
         if (b.flowb > 0 && f.n_dim > 0) {
@@ -486,12 +616,20 @@ tqp_status gen_launch(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_ou
             rk = b.dsk_full;
             rv = b.dsv_full;
         }
-        EmitPairs e{b.li, b.ri, J};
-        if ((st = join_launch<JCfgGen, uint32_t, uint32_t, EmitPairs>(
-                 ctx, s, "fragment_join", b.jb, b.fsk, b.fsv, N, b.fsort.d_cnt, rk, rv, f.n_dim, b.dsort.d_cnt,
-                 b.d_join, J, e, b.flowb, nullptr, b.flowb > 0 && f.n_dim > 0 ? b.mbstart : nullptr, b.nmbkt)) !=
-            TQP_OK)
-            return st;
+        const int64_t* rbstart = b.flowb > 0 && f.n_dim > 0 ? b.mbstart : nullptr;
+        if (b.fpush) {
+            EmitValRow e{b.jval, b.ri, J};
+            if ((st = join_launch<JCfgGen, uint64_t, uint32_t, EmitValRow>(
+                     ctx, s, "fragment_join", b.jb, b.fsk, b.fsv64, N, fsort_cnt, rk, rv, f.n_dim, b.dsort.d_cnt,
+                     b.d_join, J, e, b.flowb, nullptr, rbstart, b.nmbkt)) != TQP_OK)
+                return st;
+        } else {
+            EmitPairs e{b.li, b.ri, J};
+            if ((st = join_launch<JCfgGen, uint32_t, uint32_t, EmitPairs>(
+                     ctx, s, "fragment_join", b.jb, b.fsk, b.fsv, N, fsort_cnt, rk, rv, f.n_dim, b.dsort.d_cnt,
+                     b.d_join, J, e, b.flowb, nullptr, rbstart, b.nmbkt)) != TQP_OK)
+                return st;
+        }
     } else {
         FilterPreds fp{};
         if (b.fkeep) {
@@ -526,6 +664,12 @@ tqp_status gen_launch(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_ou
         g.col[i] = jc.col[c].data;
         g.type[i] = jc.col[c].type;
         g.side[i] = c >= f.n_fact_cols ? 1 : 0;
+        if (b.dpush >= 0 && c >= f.n_fact_cols) {
+            // the dim sort carried this column: the join wrote its values where the rows would be
+            g.col[i] = b.ri;
+            g.type[i] = TQP_I32;
+            g.side[i] = 2;
+        }
         g.bits[i] = f.group[i].bits;
     }
     TQP_LAUNCH(ctx, s, "fragment_pack",
@@ -535,7 +679,7 @@ tqp_status gen_launch(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_ou
     // its columns may be null)
     const bool no_rows = N == 0 || (b.join && f.n_dim == 0);
     for (int k = 0; k < f.n_agg; ++k) {
-        if (!b.vals[k] || no_rows) continue;
+        if (!b.vals[k] || no_rows || (b.fpush && k == b.vsort)) continue;     // fpush: the join wrote it
         if ((st = eval_program(ctx, jc.col, jc.idx, jc.n, J, b.d_join, f.aggs[k].prog, f.aggs[k].nprog, b.vals[k], s,
                                "tqp_fragment_run", "fragment_value")) != TQP_OK)
             return st;

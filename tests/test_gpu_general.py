@@ -90,6 +90,43 @@ def test_general_random(hip, ctx, trial):
     _check(got, want, topk)
 
 
+@pytest.mark.parametrize("trial", range(12))
+def test_general_pushdown(hip, ctx, trial):
+    """Descriptors that take the plan rules carrying values through the join sorts instead of row
+    ids: one valued aggregate over fact columns (and COUNTs) grouped by one int32 dim column (both
+    carried: here the dim key itself), the same with no group columns (the fact value alone), and
+    several fact aggregates grouped by an int32 dim column holding negative values (the dim column
+    alone; masked into the key, key-range flag).  Predicates on both sides, repeated dim keys,
+    match rates 1 to 0.25; equal to the oracle's general fragment."""
+    O = oracle
+    rng = np.random.default_rng(9100 + trial)
+    n = int(rng.choice([4097, 60_001, 250_003]))
+    m = int(rng.choice([300, 20_011]))
+    fk_hi = int(m * rng.choice([1.0, 1.25, 4.0]))
+    fact, dim = _tables(rng, n, m, fk_hi, trial % 4 == 0)
+    nf = len(fact)
+    kb = datagen.bits_for(max(fk_hi, m, 2))
+    fp = pins._pred_expr(rng, fact)[0] if trial % 2 else []
+    dp = pins._pred_expr(rng, dim)[0] if trial % 4 == 1 else []
+    shape = trial % 3
+    if shape == 0:
+        group = [(nf + 0, kb)]
+        aggs = [(O.AGG_SUM, pins._value_expr(rng, nf)[0]), (O.AGG_COUNT, [])]
+    elif shape == 1:
+        group = []
+        aggs = [(O.AGG_COUNT, []), (O.AGG_MAX, pins._value_expr(rng, nf)[0])]
+    else:
+        group = [(nf + 2, 10)]
+        aggs = [(O.AGG_SUM, pins._value_expr(rng, nf)[0]), (O.AGG_MIN, pins._value_expr(rng, nf)[0]),
+                (O.AGG_AVG, pins._value_expr(rng, nf)[0]), (O.AGG_COUNT, [])]
+    topk = int(rng.choice([0, 10]))
+    want = oracle.fragment_general(fact, dim, fp, dp, 0, 0, group, aggs, topk=topk, gcap=1 << 20)
+    got = hip.fragment_run(ctx, [_dev(c) for c in fact], [_dev(c) for c in dim], fp, dp, 0, 0, group, aggs,
+                           topk=topk, key_bits=kb, join_cap=max(1, want["join_rows"]), gcap=max(1, want["groups"]))
+    assert ctx.errors() == (hip.DEVERR_KEY_RANGE if want["bad"] else 0)
+    _check(got, want, topk)
+
+
 @pytest.mark.parametrize("n,m", [(0, 10), (1, 1), (10, 0), (250_003, 0)])
 def test_general_empty(hip, ctx, n, m):
     """Empty and one-row sides: no joined rows and no groups (or the single match); 250,003 fact
