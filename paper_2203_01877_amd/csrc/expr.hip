@@ -11,6 +11,8 @@
 // truncate toward zero, a zero divisor gives 0 and sets
 // TQP_DEVERR_VALUE_RANGE, INT64_MIN / -1 = INT64_MIN and INT64_MIN % -1 = 0;
 // comparisons and logic give 0 or 1; SELECT(c, t, f) = c ? t : f.
+#include <type_traits>
+
 #include "dev.hpp"
 #include "host.hpp"
 
@@ -23,6 +25,10 @@ constexpr int XC_MAX = 8;        // columns a program reads
 constexpr int XE_MAX_COLS = 64;  // columns a program may number
 constexpr int XE_BLOCK = 128;
 constexpr int XE_ROWS_FEW = 4;   // rows per thread when the program reads at most 4 columns
+// Word 3 of a raw buffer descriptor on gfx9-family chips: 32-bit data format,
+// no swizzle, no stride; loads past the descriptor's byte range return 0.
+constexpr int XE_RSRC_WORD3 = 0x00020000;
+enum : int { XT_I8 = 1, XT_I32 = 2, XT_I64 = 4, XT_ALL = 7 };
 
 enum : int32_t {
     XO_COL = 0, XO_CONST, XO_ADD, XO_SUB, XO_MUL, XO_DIV, XO_MOD, XO_NEG,
@@ -39,22 +45,15 @@ struct XProg {
     uint32_t used;               // bit c: the program reads column c
 };
 
-__device__ __forceinline__ int64_t x_load(const XProg& p, int c, int64_t row) {
-    const int64_t r = p.idx[c] ? (int64_t)p.idx[c][row] : row;
-    switch (p.type[c]) {
-        case TQP_I8: return static_cast<const int8_t*>(p.col[c])[r];
-        case TQP_I32: return static_cast<const int32_t*>(p.col[c])[r];
-        default: return static_cast<const int64_t*>(p.col[c])[r];
-    }
-}
-
 // Every thread evaluates ROWS rows together, instruction by instruction:
 // the top of each row's stack stays in a register, the values below it in
 // LDS: level l of row slot q at st[l * ROWS * XE_BLOCK + q], as many levels
 // as the program needs (its deepest stack less one).  NC (>= the columns the
 // program reads) sizes the registers that hold the rows' column values, so
-// programs over few columns evaluate more rows per thread.
-template <int NC, int ROWS>
+// programs over few columns evaluate more rows per thread.  GATHER: some
+// column is read through a row id column.  TYPES (XT_* bits): the element
+// types the direct columns may have; loads of the other types are left out.
+template <int NC, int ROWS, bool GATHER, int TYPES = XT_ALL>
 __global__ void __launch_bounds__(XE_BLOCK)
 k_eval(XProg p, int64_t n_upper, const int64_t* d_n, int64_t* out, uint32_t* flags) {
     constexpr int XE_ROWS = ROWS;
@@ -65,14 +64,107 @@ k_eval(XProg p, int64_t n_upper, const int64_t* d_n, int64_t* out, uint32_t* fla
     bool zdiv = false;
     const int64_t step = (int64_t)gridDim.x * XE_BLOCK * XE_ROWS;
     for (int64_t base = (int64_t)blockIdx.x * XE_BLOCK * XE_ROWS; base < n; base += step) {
-        // the rows' referenced columns, loads issued together before the program runs
         int64_t cv[XE_ROWS][NC];
+        if constexpr (!GATHER && (TYPES == XT_I64 || TYPES == XT_I32)) {
+            // Direct columns of one element type: plain loads, rows past n
+            // clamped to the last row; an unused slot reads slot 0's column
+            // (always used here), so no branch separates the loads.
+            using E = typename std::conditional<TYPES == XT_I64, int64_t, int32_t>::type;
 #pragma unroll
-        for (int j = 0; j < XE_ROWS; ++j) {
-            const int64_t row = base + (int64_t)j * XE_BLOCK + tid;
-            const int64_t r = row < n ? row : n - 1;          // base < n, so n >= 1
+            for (int c = 0; c < NC; ++c) {
+                const E* col = static_cast<const E*>(p.col[(p.used >> c) & 1u ? c : 0]);
 #pragma unroll
-            for (int c = 0; c < NC; ++c) cv[j][c] = (p.used >> c) & 1u ? x_load(p, c, r) : 0;
+                for (int j = 0; j < XE_ROWS; ++j) {
+                    const int64_t row = base + (int64_t)j * XE_BLOCK + tid;
+                    cv[j][c] = (int64_t)col[row < n ? row : n - 1];          // base < n, so n >= 1
+                }
+            }
+        } else if constexpr (!GATHER) {
+            // Direct columns: buffer loads over this tile's rows, one
+            // descriptor per element type and column, whose range is zero
+            // where the type is not the column's (or the column is unused):
+            // a load out of its descriptor's range returns 0 without a memory
+            // access, and rows at or past n are out of range too.  No branch
+            // and no clamp: every load of the tile is in flight at once.
+            const int64_t left = n - base;
+            const uint32_t here = (uint32_t)(left < XE_ROWS * XE_BLOCK ? left : XE_ROWS * XE_BLOCK);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const int t = p.type[c];
+                const bool use = (p.used >> c) & 1u;
+                const int w = t == TQP_I64 ? 8 : t == TQP_I32 ? 4 : 1;
+                // (an unused slot's pointer may be null: its descriptors have no range)
+                char* at = reinterpret_cast<char*>(reinterpret_cast<uintptr_t>(p.col[c]) + (uintptr_t)(base * w));
+                const __amdgpu_buffer_rsrc_t r64 =
+                    __builtin_amdgcn_make_buffer_rsrc(at, 0, use && w == 8 ? (int)(here * 8) : 0, XE_RSRC_WORD3);
+                const __amdgpu_buffer_rsrc_t r32 =
+                    __builtin_amdgcn_make_buffer_rsrc(at, 0, use && w == 4 ? (int)(here * 4) : 0, XE_RSRC_WORD3);
+                const __amdgpu_buffer_rsrc_t r8 =
+                    __builtin_amdgcn_make_buffer_rsrc(at, 0, use && w == 1 ? (int)here : 0, XE_RSRC_WORD3);
+#pragma unroll
+                for (int j = 0; j < XE_ROWS; ++j) {
+                    const int off = j * XE_BLOCK + tid;
+                    int64_t v = 0;
+                    if constexpr ((TYPES & XT_I64) != 0) {
+                        const auto v64 = __builtin_amdgcn_raw_buffer_load_b64(r64, off * 8, 0, 0);
+                        v += (int64_t)(((uint64_t)v64[1] << 32) | v64[0]);
+                    }
+                    if constexpr ((TYPES & XT_I32) != 0)
+                        v += (int64_t)(int32_t)__builtin_amdgcn_raw_buffer_load_b32(r32, off * 4, 0, 0);
+                    if constexpr ((TYPES & XT_I8) != 0)
+                        v += (int64_t)(int8_t)__builtin_amdgcn_raw_buffer_load_b8(r8, off, 0, 0);
+                    cv[j][c] = v;
+                }
+            }
+        } else {
+            // Gathered columns: the row ids first (below 2^31, so 32 bits
+            // hold them), then per column a branch on its type (the same in
+            // every thread) that issues the tile's loads into registers of
+            // that type; the values are formed after the loads.
+            uint32_t rid[XE_ROWS][NC];
+#pragma unroll
+            for (int j = 0; j < XE_ROWS; ++j) {
+                const int64_t row = base + (int64_t)j * XE_BLOCK + tid;
+                const uint32_t r = (uint32_t)(row < n ? row : n - 1);     // base < n, so n >= 1
+#pragma unroll
+                for (int c = 0; c < NC; ++c) rid[j][c] = r;
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                if (((p.used >> c) & 1u) && p.idx[c]) {
+#pragma unroll
+                    for (int j = 0; j < XE_ROWS; ++j) rid[j][c] = (uint32_t)p.idx[c][rid[j][c]];
+                }
+            }
+            uint64_t w64[XE_ROWS][NC];
+            uint32_t w32[XE_ROWS][NC];
+            int32_t w8[XE_ROWS][NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+#pragma unroll
+                for (int j = 0; j < XE_ROWS; ++j) w64[j][c] = w32[j][c] = w8[j][c] = 0;
+                if (!((p.used >> c) & 1u)) continue;
+                const int t = p.type[c];
+                if (t == TQP_I64) {
+                    const uint64_t* col = static_cast<const uint64_t*>(p.col[c]);
+#pragma unroll
+                    for (int j = 0; j < XE_ROWS; ++j) w64[j][c] = col[rid[j][c]];
+                } else if (t == TQP_I32) {
+                    const uint32_t* col = static_cast<const uint32_t*>(p.col[c]);
+#pragma unroll
+                    for (int j = 0; j < XE_ROWS; ++j) w32[j][c] = col[rid[j][c]];
+                } else {
+                    const int8_t* col = static_cast<const int8_t*>(p.col[c]);
+#pragma unroll
+                    for (int j = 0; j < XE_ROWS; ++j) w8[j][c] = col[rid[j][c]];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+#pragma unroll
+                for (int j = 0; j < XE_ROWS; ++j)
+                    cv[j][c] = (int64_t)w64[j][c] + (int64_t)(int32_t)w32[j][c] + (int64_t)w8[j][c];
+            }
         }
         int64_t top[XE_ROWS];
 #pragma unroll
@@ -114,6 +206,13 @@ k_eval(XProg p, int64_t n_upper, const int64_t* d_n, int64_t* out, uint32_t* fla
             }
             // binary operators: the operator is the same in every thread, so
             // the branch is taken once per instruction, outside the row loop
+            // a zero divisor (the top of the stack) counts for rows below n only:
+            // the rows past n in the last tile read zeros
+            auto zero_divisors = [&] {
+#pragma unroll
+                for (int j = 0; j < XE_ROWS; ++j)
+                    zdiv |= top[j] == 0 && base + (int64_t)j * XE_BLOCK + tid < n;
+            };
             auto binary = [&](auto f) {
 #pragma unroll
                 for (int j = 0; j < XE_ROWS; ++j)
@@ -124,15 +223,17 @@ k_eval(XProg p, int64_t n_upper, const int64_t* d_n, int64_t* out, uint32_t* fla
                 case XO_SUB: binary([](int64_t a, int64_t b) { return (int64_t)((uint64_t)a - (uint64_t)b); }); break;
                 case XO_MUL: binary([](int64_t a, int64_t b) { return (int64_t)((uint64_t)a * (uint64_t)b); }); break;
                 case XO_DIV:
-                    binary([&](int64_t a, int64_t b) -> int64_t {
-                        if (b == 0) { zdiv = true; return 0; }
+                    zero_divisors();
+                    binary([](int64_t a, int64_t b) -> int64_t {
+                        if (b == 0) return 0;
                         if (b == -1) return (int64_t)(0ull - (uint64_t)a);
                         return a / b;
                     });
                     break;
                 case XO_MOD:
-                    binary([&](int64_t a, int64_t b) -> int64_t {
-                        if (b == 0) { zdiv = true; return 0; }
+                    zero_divisors();
+                    binary([](int64_t a, int64_t b) -> int64_t {
+                        if (b == 0) return 0;
                         if (b == -1) return 0;
                         return a % b;
                     });
@@ -224,9 +325,29 @@ tqp_status eval_program(tqp_ctx* ctx, const tqp_column* cols, const int32_t* con
         return TQP_OK;
     };
     // rows per thread: as many as the column registers allow
-    if (used <= 2) return launch(k_eval<2, XE_ROWS_FEW>, XE_ROWS_FEW);
-    if (used <= 4) return launch(k_eval<4, XE_ROWS_FEW>, XE_ROWS_FEW);
-    return launch(k_eval<XC_MAX, 2>, 2);
+    bool gather = false;
+    int types = 0;
+    for (int c = 0; c < used; ++c) {
+        gather |= p.idx[c] != nullptr;
+        types |= p.type[c] == TQP_I64 ? XT_I64 : p.type[c] == TQP_I32 ? XT_I32 : XT_I8;
+    }
+    if (gather) {
+        if (used <= 2) return launch(k_eval<2, XE_ROWS_FEW, true>, XE_ROWS_FEW);
+        if (used <= 4) return launch(k_eval<4, XE_ROWS_FEW, true>, XE_ROWS_FEW);
+        return launch(k_eval<XC_MAX, 2, true>, 2);
+    }
+    // columns of one element type (e.g. an int32 predicate, an int64 value
+    // expression) load only that type
+    if (used <= 2) {
+        if (types == XT_I64) return launch(k_eval<2, XE_ROWS_FEW, false, XT_I64>, XE_ROWS_FEW);
+        if (types == XT_I32) return launch(k_eval<2, XE_ROWS_FEW, false, XT_I32>, XE_ROWS_FEW);
+        return launch(k_eval<2, XE_ROWS_FEW, false>, XE_ROWS_FEW);
+    }
+    if (used <= 4) {
+        if (types == XT_I64) return launch(k_eval<4, XE_ROWS_FEW, false, XT_I64>, XE_ROWS_FEW);
+        return launch(k_eval<4, XE_ROWS_FEW, false>, XE_ROWS_FEW);
+    }
+    return launch(k_eval<XC_MAX, 2, false>, 2);
 }
 
 }  // namespace tqp

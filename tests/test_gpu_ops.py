@@ -329,6 +329,45 @@ def test_eval(hip, ctx, n):
         assert ctx.errors() == (hip.DEVERR_VALUE_RANGE if z else 0), (trial, prog)
 
 
+@pytest.mark.parametrize("n", [1, 513, 4097, 250_003])
+def test_eval_wide(hip, ctx, n):
+    """Programs reading 5 to 7 of seven columns (the 8-column kernel), each column a view that
+    starts 1 to 3 elements into its allocation (so int8 and int32 columns begin off an 8-byte
+    boundary), against the oracle element by element."""
+    rng = _rng(n + 11)
+    kinds = [np.int8, np.int32, np.int64, np.int8, np.int32, np.int64, np.int32]
+    full = [rng.integers(-100, 100, n + 3).astype(k) for k in kinds]
+    offs = [1, 3, 2, 1, 1, 3, 2]
+    cols = [f[o:o + n] for f, o in zip(full, offs)]
+    dc = [_dev(f)[o:o + n] for f, o in zip(full, offs)]
+    for trial in range(8):
+        want_cols = int(rng.integers(5, 8))
+        prog = [(oracle.X_COL, c) for c in range(want_cols)] + [(oracle.X_ADD, 0)] * (want_cols - 1)
+        mid = _random_program(rng, want_cols, int(rng.integers(3, 20)))
+        prog = prog + mid + [(oracle.X_ADD, 0)]
+        want, z = oracle.eval_expr(cols, prog)
+        got = _np(hip.eval_expr(ctx, dc, prog))
+        assert np.array_equal(got, want), (trial, prog)
+        assert ctx.errors() == (hip.DEVERR_VALUE_RANGE if z else 0), (trial, prog)
+
+
+@pytest.mark.parametrize("kinds", [[np.int64] * 2, [np.int64] * 4, [np.int32] * 2, [np.int32] * 4, [np.int8]])
+def test_eval_one_type(hip, ctx, kinds):
+    """Programs over columns of one element type (the kernels that load only that type), 70,001
+    rows (a ragged last tile), against the oracle element by element."""
+    n = 70_001
+    rng = _rng(len(kinds) * 7 + np.dtype(kinds[0]).itemsize)
+    cols = [rng.integers(-50, 50, n).astype(k) for k in kinds]
+    dc = [_dev(c) for c in cols]
+    for trial in range(6):
+        prog = [(oracle.X_COL, c) for c in range(len(cols))] + [(oracle.X_SUB, 0)] * (len(cols) - 1)
+        prog = prog + _random_program(rng, len(cols), int(rng.integers(1, 16))) + [(oracle.X_MUL, 0)]
+        want, z = oracle.eval_expr(cols, prog)
+        got = _np(hip.eval_expr(ctx, dc, prog))
+        assert np.array_equal(got, want), (trial, prog)
+        assert ctx.errors() == (hip.DEVERR_VALUE_RANGE if z else 0), (trial, prog)
+
+
 def test_eval_edges(hip, ctx):
     X = oracle
     a = np.array([7, -7, 7, -7, 0, 5, np.iinfo(np.int64).min, np.iinfo(np.int64).min, np.iinfo(np.int64).max],
