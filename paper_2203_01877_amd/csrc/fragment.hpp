@@ -140,6 +140,9 @@ tqp_status check_flags(const tqp_flags_fragment* f, const tqp_flags_out* o);
 // of `rwin` keys; the right side then needs the same high-bit passes plus the
 // finishing pass.
 int join_low_bits(int64_t n, int kb, int rb, int tile, int rwin);
+// Group-key bits left to the bucket-aggregation kernel for cb-bit keys and
+// rb-bit radix digits (the bits above them take one pass when cb <= rb + 13).
+int bucket_low_bits(int cb, int rb);
 
 // Batch preparation without any allocation: descriptor tables go into the
 // workspace, uploaded on `stream` (or synchronously); only the configurations

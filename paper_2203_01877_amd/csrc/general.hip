@@ -54,6 +54,10 @@ constexpr int GF_FILTER_BLOCK = 256, GF_FILTER_ITEMS = 16;
 constexpr int GF_HEAD_BLOCK = 256, GF_HEAD_ITEMS = 8;
 constexpr int GF_AGG_BLOCK = 256;
 constexpr int GF_MAX_COLS = 64;
+// Group keys of at least this many bits take the bucket group-by (when it
+// applies): a bucket then holds 2^8 or more keys, enough slots that a block's
+// LDS updates rarely meet on one.
+constexpr int GF_BUCKET_MIN_BITS = 16;
 
 // Sort source: the int32 key column with the row id as payload, rows whose
 // keep value is zero left out (keep null: every row).
@@ -333,6 +337,23 @@ __device__ __forceinline__ void gf_write(const AggSet& a, const GfPart& p, int64
     }
 }
 
+// The bucket group-by's outputs that are not written by its kernel: the
+// COUNTs other than the one it writes (cnt), and AVG (one IEEE division of
+// the exact int64 sum).
+__global__ void k_gf_bucket_out(AggSet a, const int64_t* v, const int64_t* cnt, const int64_t* d_groups,
+                                int64_t gcap) {
+    int64_t G = *d_groups;
+    G = G < gcap ? G : gcap;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < G; g += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < TQP_FRAGMENT_MAX_AGGS; ++k) {
+            if (k >= a.n) continue;
+            if (a.op[k] == TQP_AGG_COUNT && a.out[k] != cnt) static_cast<int64_t*>(a.out[k])[g] = cnt[g];
+            if (a.op[k] == TQP_AGG_AVG) static_cast<double*>(a.out[k])[g] = (double)v[g] / (double)cnt[g];
+        }
+    }
+}
+
 // Every group's aggregates: each wave takes 64 consecutive groups (grid-stride);
 // a lane reduces its own group when all 64 are at most GF_LANE_GROUP rows,
 // else the wave reduces the long ones one at a time and the lanes the rest.
@@ -412,6 +433,15 @@ struct GenBufs {
     int64_t* jval = nullptr;                 // fpush: the value of every joined row
     RadixBufs<Cfg, uint64_t> sv;
     uint64_t* vc = nullptr;
+    // the bucket group-by: the group sort covers the key bits above lowb, and
+    // one block per bucket of 2^lowb keys reduces it in LDS
+    bool bucket = false;
+    int lowb = 0;
+    int64_t nbuckets = 0;
+    int64_t* bstarts = nullptr;
+    uint64_t* bstatus = nullptr;
+    uint32_t* bcounter = nullptr;
+    int64_t *bval = nullptr, *bcnt = nullptr;   // per group: the value's reduction, the row count
     JoinBufs jb;
     uint32_t *fsk = nullptr, *fsv = nullptr, *dsk = nullptr, *dsv = nullptr;
     uint64_t* fstatus = nullptr;             // no join: the compaction of the kept fact rows
@@ -451,6 +481,7 @@ void gen_reserve(Arena& a, const tqp_fragment& f, const tqp_fragment_out& o, Gen
             b.vsort = k;
         }
     if (valued != 1 || b.distinct >= 0) b.vsort = -1;
+    b.bucket = b.vsort >= 0 && b.gbits >= GF_BUCKET_MIN_BITS;
     if (b.join) {
         // what the join's output is used for: columns of each side read after it
         auto prog_sides = [&](const tqp_xinstr* pr, int np, bool& uses_f, bool& uses_d) {
@@ -530,6 +561,23 @@ void gen_reserve(Arena& a, const tqp_fragment& f, const tqp_fragment_out& o, Gen
         b.pb = a.scratch<uint32_t>(J);
     }
     b.kc = a.scratch<uint32_t>(J);
+    if (b.bucket) {
+        b.lowb = bucket_low_bits(b.gbits, Cfg::RADIX_BITS);
+        b.nbuckets = int64_t(1) << (b.gbits - b.lowb);
+        b.sv = radix_reserve<Cfg, uint64_t>(a, J, b.gbits, b.lowb);
+        b.vc = a.scratch<uint64_t>(J);
+        b.bstarts = a.scratch<int64_t>(b.nbuckets + 1);
+        b.bstatus = a.zero<uint64_t>(b.nbuckets);
+        b.bcounter = a.zero<uint32_t>(1);
+        b.bval = a.scratch<int64_t>(o.gcap);
+        b.bcnt = a.scratch<int64_t>(o.gcap);
+        if (f.topk > 0) {
+            // candidates: the first k groups of every bucket
+            b.topk = topk_reserve(a, std::min<int64_t>(o.gcap, b.nbuckets * f.topk), f.topk);
+            b.tcnt = a.scratch<int64_t>(f.topk);
+        }
+        return;
+    }
     if (b.vsort >= 0) {
         b.sv = radix_reserve<Cfg, uint64_t>(a, J, b.gbits);
         b.vc = a.scratch<uint64_t>(J);
@@ -555,6 +603,77 @@ struct JoinedCols {
     const int32_t* idx[GF_MAX_COLS];
     int n = 0;
 };
+
+// The group-by by buckets, over the keys sorted on their bits above lowb
+// with the one valued aggregate's value (Algorithm 2 with the last digit
+// resolved in LDS, as in the custkey fragment): every bucket's block reduces
+// the value (sum, min or max) and counts the rows per key in LDS and writes
+// its groups in key order, with its first k groups as top-k candidates when
+// the fragment has a top-k.  Groups come out in ascending key order, as from
+// the full sort.
+template <class Cfg>
+tqp_status bucket_groupby(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_out& o, const GenBufs<Cfg>& b,
+                          hipStream_t s) {
+    const int64_t J = f.join_cap;
+    const int vop = f.aggs[b.vsort].op;
+    int64_t* vout = vop == TQP_AGG_AVG ? b.bval : static_cast<int64_t*>(f.aggs[b.vsort].out);
+    int64_t* cout = b.bcnt;
+    bool finish = false;
+    for (int k = 0; k < f.n_agg; ++k) {
+        if (f.aggs[k].op == TQP_AGG_COUNT) {
+            if (cout == b.bcnt) cout = static_cast<int64_t*>(f.aggs[k].out);
+            else finish = true;
+        }
+        finish |= f.aggs[k].op == TQP_AGG_AVG;
+    }
+    SegOut so{o.key, vout, cout, nullptr, o.gcap, o.d_ngroups};
+    // bucket starts: with one pass the buckets are its digits, and its
+    // histogram gives them; otherwise one search per bucket
+    const uint32_t* bhist = b.sv.pd.npass == 1 ? b.sv.hist : nullptr;
+    if (!bhist) {
+        TQP_LAUNCH(ctx, s, "fragment_bucket_bounds",
+                   k_bucket_bounds<<<grid_for(b.nbuckets + 1, 256, 0), 256, 0, s>>>(b.kc, J, b.d_join, b.lowb,
+                                                                                      b.nbuckets, b.bstarts));
+    }
+    TopCand* cand = f.topk > 0 ? b.topk.filtered : nullptr;
+    int64_t* d_cand = f.topk > 0 ? b.topk.d_nf : nullptr;
+    const bool bycnt = f.topk > 0 && f.aggs[0].op == TQP_AGG_COUNT;
+    const int64_t* vals = reinterpret_cast<const int64_t*>(b.vc);
+    constexpr int SLOTS = 1 << BUCKET_LOWB_MAX;
+    auto go = [&](auto kern) -> tqp_status {
+        TQP_LAUNCH(ctx, s, "fragment_bucket_agg",
+                   kern<<<(unsigned)b.nbuckets, 1024, 0, s>>>(b.kc, vals, b.bstarts, bhist, b.lowb, b.nbuckets,
+                                                              b.bstatus, b.bcounter, so, ctx->d_err, cand, d_cand,
+                                                              f.topk));
+        return TQP_OK;
+    };
+    tqp_status st;
+    if (vop == TQP_AGG_MIN)
+        st = bycnt ? go(k_bucket_agg<1024, SLOTS, int64_t, BUCKET_MIN, true>)
+                   : go(k_bucket_agg<1024, SLOTS, int64_t, BUCKET_MIN, false>);
+    else if (vop == TQP_AGG_MAX)
+        st = bycnt ? go(k_bucket_agg<1024, SLOTS, int64_t, BUCKET_MAX, true>)
+                   : go(k_bucket_agg<1024, SLOTS, int64_t, BUCKET_MAX, false>);
+    else
+        st = bycnt ? go(k_bucket_agg<1024, SLOTS, int64_t, BUCKET_SUM, true>)
+                   : go(k_bucket_agg<1024, SLOTS, int64_t, BUCKET_SUM, false>);
+    if (st != TQP_OK) return st;
+    if (finish && o.gcap > 0) {
+        AggSet as{};
+        as.n = f.n_agg;
+        for (int k = 0; k < f.n_agg; ++k) {
+            as.out[k] = f.aggs[k].out;
+            as.op[k] = f.aggs[k].op;
+        }
+        TQP_LAUNCH(ctx, s, "fragment_bucket_out",
+                   k_gf_bucket_out<<<grid_for(o.gcap, 256, (int64_t)ctx->num_cus * 8), 256, 0, s>>>(
+                       as, vout, cout, o.d_ngroups, o.gcap));
+    }
+    // ORDER BY the first aggregate DESC, key ASC LIMIT k, over the candidates
+    if (f.topk > 0)
+        return topk_launch_candidates(b.topk, cout, f.topk, o.top_key, o.top_val, b.tcnt, o.d_topk, s, ctx);
+    return TQP_OK;
+}
 
 template <class Cfg>
 tqp_status gen_launch(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_out& o, const GenBufs<Cfg>& b,
@@ -702,6 +821,7 @@ tqp_status gen_launch(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_ou
         if ((st = radix_launch<Cfg, uint64_t>(b.sv, a3, J, true, nullptr, key_mask_for(b.gbits), b.kc, b.vc, ctx, s,
                                               "fragment_sort_group", "fragment_sort_group")) != TQP_OK)
             return st;
+        if (b.bucket) return bucket_groupby(ctx, f, o, b, s);
     } else {
         SrcPermKey<0> a3{b.gkey, perm_in, J, b.d_join};
         if ((st = radix_launch<Cfg, uint32_t>(b.sc, a3, J, true, nullptr, key_mask_for(b.gbits), b.kc, b.pc, ctx, s,

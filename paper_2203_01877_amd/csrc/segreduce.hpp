@@ -227,15 +227,19 @@ __global__ void k_bucket_bounds(const uint32_t* keys, int64_t n_upper, const int
                                 int64_t nbuckets, int64_t* starts);
 
 // vals: int64 values (VT = int64_t) or values in [0, 2^32) (VT = uint32_t).
-// With cand, each block also appends the first k of its groups in the
-// order sum DESC, key ASC (step 1 of the top-k: the overall first k are among
-// them) to cand, counting them in *d_cand.
-template <int BLOCK, int SLOTS, class VT = int64_t>
+// OP: what the value column is reduced to (sum; min or max for int64
+// values), written to out.sum.  With cand, each block also appends the first
+// k of its groups in the order value DESC (the count with BYCNT), key ASC
+// (step 1 of the top-k: the overall first k are among them) to cand,
+// counting them in *d_cand.
+enum : int { BUCKET_SUM = 0, BUCKET_MIN = 1, BUCKET_MAX = 2 };
+template <int BLOCK, int SLOTS, class VT = int64_t, int OP = BUCKET_SUM, bool BYCNT = false>
 __global__ void __launch_bounds__(BLOCK)
 k_bucket_agg(const uint32_t* keys, const VT* vals, const int64_t* starts, const uint32_t* bhist, int lowb,
              int64_t nbuckets, uint64_t* status, uint32_t* counter, SegOut out, uint32_t* flags,
              TopCand* cand = nullptr, int64_t* d_cand = nullptr, int k = 0) {
     static_assert(SLOTS <= (1 << BUCKET_LOWB_MAX), "slot table larger than the LDS budget");
+    static_assert(OP == BUCKET_SUM || std::is_same<VT, int64_t>::value, "min / max over int64 values");
     constexpr int U = 8;                               // loads in flight per thread
     constexpr int PER = (SLOTS + BLOCK - 1) / BLOCK;   // most slots per thread
     __shared__ unsigned long long s_sum[SLOTS];
@@ -248,7 +252,9 @@ k_bucket_agg(const uint32_t* keys, const VT* vals, const int64_t* starts, const 
     const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
     if (tid == 0) s_b = atomicAdd(counter, 1u);
     const int slots = 1 << lowb;
-    for (int i = tid; i < slots; i += BLOCK) { s_sum[i] = 0; s_cnt[i] = 0; }
+    constexpr unsigned long long ident = OP == BUCKET_MIN ? 0x7FFFFFFFFFFFFFFFull
+                                         : OP == BUCKET_MAX ? 0x8000000000000000ull : 0ull;
+    for (int i = tid; i < slots; i += BLOCK) { s_sum[i] = ident; s_cnt[i] = 0; }
     __syncthreads();
     const int64_t b = s_b;
     if (b >= nbuckets) return;
@@ -284,7 +290,11 @@ k_bucket_agg(const uint32_t* keys, const VT* vals, const int64_t* starts, const 
 #pragma unroll
         for (int j = 0; j < U; ++j) {
             if (i0 + (int64_t)j * BLOCK < hi) {
-                if constexpr (std::is_same<VT, uint32_t>::value) {
+                if constexpr (OP == BUCKET_MIN) {
+                    atomicMin(reinterpret_cast<long long*>(&s_sum[k[j]]), (long long)v[j]);
+                } else if constexpr (OP == BUCKET_MAX) {
+                    atomicMax(reinterpret_cast<long long*>(&s_sum[k[j]]), (long long)v[j]);
+                } else if constexpr (std::is_same<VT, uint32_t>::value) {
                     // 32-bit add on the low word; a wrap carries into the high word
                     uint32_t* w2 = reinterpret_cast<uint32_t*>(&s_sum[k[j]]);
                     const uint32_t old = atomicAdd(&w2[0], v[j]);
@@ -343,7 +353,7 @@ k_bucket_agg(const uint32_t* keys, const VT* vals, const int64_t* starts, const 
                 out.key[g] = key;
                 out.sum[g] = sum;
                 out.cnt[g] = (int64_t)s_cnt[sl];
-                chi[q] = order_hi(sum);
+                chi[q] = order_hi(BYCNT ? (int64_t)s_cnt[sl] : sum);
                 clo[q] = order_lo(key);
                 cidx[q] = (int32_t)g;
                 cval[q] = true;

@@ -127,6 +127,62 @@ def test_general_pushdown(hip, ctx, trial):
     _check(got, want, topk)
 
 
+@pytest.mark.parametrize("trial", range(12))
+def test_general_bucket(hip, ctx, trial):
+    """Descriptors that take the bucket group-by (one valued aggregate, SUM / MIN / MAX / AVG, with
+    COUNTs; packed group keys of 19 to 27 bits, so one or two passes over the bits above the bucket
+    and 2^8 to 2^13 keys per bucket): none, one or two COUNTs, a top-k ordered by the value or by a
+    COUNT; equal to the oracle's general fragment."""
+    O = oracle
+    rng = np.random.default_rng(9300 + trial)
+    n = [60_001, 250_003, 400_000][trial % 3]
+    m = 20_011
+    fact, dim = _tables(rng, n, m, int(m * [1.0, 1.25][trial % 2]), trial % 4 == 0)
+    gb = [16, 18, 21, 24][trial % 4]
+    fact.append(rng.integers(0, 1 << gb, n).astype(np.int32))
+    nf = len(fact)
+    group = [(nf + 1, 3), (nf - 1, gb)]
+    vop = [O.AGG_SUM, O.AGG_MIN, O.AGG_MAX, O.AGG_AVG][(trial // 3) % 4]
+    prog = pins._value_expr(rng, nf + len(dim))[0]
+    shape = trial % 3
+    aggs = [[(vop, prog), (O.AGG_COUNT, [])], [(O.AGG_COUNT, []), (vop, prog), (O.AGG_COUNT, [])],
+            [(vop, prog)]][shape]
+    topk = 0 if aggs[0][0] == O.AGG_AVG else [10, 100, 0, 1][trial % 4]
+    fp = pins._pred_expr(rng, fact)[0] if trial % 2 else []
+    kb = datagen.bits_for(int(m * 1.25))
+    want = oracle.fragment_general(fact, dim, fp, [], 0, 0, group, aggs, topk=topk, gcap=1 << 20)
+    got = hip.fragment_run(ctx, [_dev(c) for c in fact], [_dev(c) for c in dim], fp, [], 0, 0, group, aggs,
+                           topk=topk, key_bits=kb, join_cap=max(1, want["join_rows"]), gcap=max(1, want["groups"]))
+    assert ctx.errors() == (hip.DEVERR_KEY_RANGE if want["bad"] else 0)
+    _check(got, want, topk)
+
+
+def test_general_bucket_capacity_and_empty(hip, ctx):
+    """The bucket group-by with fewer group slots than groups (capacity flag, the true group count,
+    the first gcap groups exact, top-k over the written groups as the oracle's) and with no joined
+    rows (an empty dim table)."""
+    O = oracle
+    rng = np.random.default_rng(78)
+    fact, dim = _tables(rng, 200_000, 5000, 5000, False)
+    fact.append(rng.integers(0, 1 << 20, 200_000).astype(np.int32))
+    aggs = [(O.AGG_SUM, [(O.X_COL, 2)]), (O.AGG_COUNT, [])]
+    group = [(len(fact) - 1, 20)]
+    want = O.fragment_general(fact, dim, [], [], 0, 0, group, aggs, gcap=1000)
+    got = hip.fragment_run(ctx, [_dev(c) for c in fact], [_dev(c) for c in dim], [], [], 0, 0, group, aggs,
+                           key_bits=13, gcap=1000)
+    assert ctx.errors() == hip.DEVERR_CAPACITY
+    assert int(_np(got["d_ngroups"])[0]) == want["groups"] > 1000
+    assert np.array_equal(_np(got["key"], 1000), want["key"][:1000])
+    assert np.array_equal(_np(got["vals"][0], 1000), want["vals"][0][:1000])
+    assert np.array_equal(_np(got["vals"][1], 1000), want["vals"][1][:1000])
+    empty = [c[:0] for c in dim]
+    want = O.fragment_general(fact, empty, [], [], 0, 0, group, aggs, topk=5, gcap=4)
+    got = hip.fragment_run(ctx, [_dev(c) for c in fact], [_dev(c) for c in empty], [], [], 0, 0, group, aggs, topk=5,
+                           key_bits=13, gcap=4)
+    assert ctx.errors() == 0
+    _check(got, want, 5)
+
+
 @pytest.mark.parametrize("n,m", [(0, 10), (1, 1), (10, 0), (250_003, 0)])
 def test_general_empty(hip, ctx, n, m):
     """Empty and one-row sides: no joined rows and no groups (or the single match); 250,003 fact
