@@ -2,7 +2,7 @@
 // by a descriptor instead of the two fixed fragment shapes.
 //
 //   1. predicates  Section 5.1's expressions: each side's predicate program is
-//                  evaluated once into a keep column (tqp_eval's kernel);
+//                  evaluated once into a keep byte per row (tqp_eval's kernel);
 //   2. join        Algorithm 1: both key columns radix-sorted with their row
 //                  ids, the keep column fused into the sort's first pass so
 //                  dropped rows are never written; the sort-based join gives
@@ -60,10 +60,10 @@ constexpr int GF_MAX_COLS = 64;
 constexpr int GF_BUCKET_MIN_BITS = 16;
 
 // Sort source: the int32 key column with the row id as payload, rows whose
-// keep value is zero left out (keep null: every row).
+// keep byte is zero left out (keep null: every row).
 struct SrcKeepRow {
     const int32_t* key;
-    const int64_t* keep;
+    const uint8_t* keep;
     int64_t n;
     __device__ int64_t size() const { return n; }
     __device__ bool load_key(int64_t i, uint32_t& k) const {
@@ -81,7 +81,7 @@ struct SrcKeepRow {
 // per row (the fact value program), or an int32 column (the dim group column).
 struct SrcKeepVal64 {
     const int32_t* key;
-    const int64_t* keep;
+    const uint8_t* keep;
     const int64_t* val;
     int64_t n;
     __device__ int64_t size() const { return n; }
@@ -97,7 +97,7 @@ struct SrcKeepVal64 {
 };
 struct SrcKeepCol {
     const int32_t* key;
-    const int64_t* keep;
+    const uint8_t* keep;
     const int32_t* col;
     int64_t n;
     __device__ int64_t size() const { return n; }
@@ -177,6 +177,31 @@ struct SrcKeyVal64 {
     }
     __device__ bool load(int64_t i, uint32_t& k, uint64_t& v) const {
         k = key[i];
+        v = (uint64_t)val[i];
+        return true;
+    }
+};
+
+// The group sort's source when the one group column rode the dim sort: the
+// key is that column's value (the join wrote it where the dim row would be),
+// given whole to the histogram, which raises the key-range flag for a value
+// outside the key width, and masked to the width for the passes.
+struct SrcColKeyVal64 {
+    const int32_t* key;
+    const int64_t* val;
+    int64_t n_upper;
+    const int64_t* d_n;
+    uint32_t mask;
+    __device__ int64_t size() const {
+        const int64_t n = *d_n;
+        return n < n_upper ? n : n_upper;
+    }
+    __device__ bool load_key(int64_t i, uint32_t& k) const {
+        k = (uint32_t)key[i];
+        return true;
+    }
+    __device__ bool load(int64_t i, uint32_t& k, uint64_t& v) const {
+        k = (uint32_t)key[i] & mask;
         v = (uint64_t)val[i];
         return true;
     }
@@ -417,8 +442,8 @@ struct GenBufs {
     bool join = false;
     int distinct = -1;                       // the COUNT(DISTINCT) aggregate, if any
     int gbits = 1;
-    int64_t* fkeep = nullptr;
-    int64_t* dkeep = nullptr;
+    uint8_t* fkeep = nullptr;                // predicate keep bytes (1: the row takes part)
+    uint8_t* dkeep = nullptr;
     RadixBufs<Cfg, uint32_t> fsort, dsort, sa, sb, sc;
     int flowb = 0;                           // fact key bits left to the join tiles
     int64_t nspans = 0, nmbkt = 0;
@@ -515,9 +540,9 @@ void gen_reserve(Arena& a, const tqp_fragment& f, const tqp_fragment_out& o, Gen
         // the dim rows serve only one int32 group column
         if (group_d && gd_one && !prog_d && f.dim_cols[gd - f.n_fact_cols].type == TQP_I32) b.dpush = gd - f.n_fact_cols;
     }
-    if (f.n_fact_pred > 0) b.fkeep = a.scratch<int64_t>(N);
+    if (f.n_fact_pred > 0) b.fkeep = a.scratch<uint8_t>(N);
     if (b.join) {
-        if (f.n_dim_pred > 0) b.dkeep = a.scratch<int64_t>(f.n_dim);
+        if (f.n_dim_pred > 0) b.dkeep = a.scratch<uint8_t>(f.n_dim);
         b.flowb = join_low_bits(N, kb, Cfg::RADIX_BITS, JCfgGen::TILE, JCfgGen::RWIN);
         if (b.flowb > FINISH_LOG2) b.flowb = FINISH_LOG2;
         if (b.fpush) {
@@ -681,19 +706,47 @@ tqp_status gen_launch(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_ou
     const int kb = norm_key_bits(f.key_bits);
     const int64_t N = f.n_fact, J = f.join_cap;
     tqp_status st;
-    // 1. predicates
-    if (b.fkeep && N > 0 &&
-        (st = eval_program(ctx, f.fact_cols, nullptr, f.n_fact_cols, N, nullptr, f.fact_pred, f.n_fact_pred, b.fkeep,
-                           s, "tqp_fragment_run", "fragment_fact_pred")) != TQP_OK)
-        return st;
+    // 1. predicates and 2. the join's sorts.  With a join the dim side (its
+    // predicate, its sort and the finishing pass) runs on the side stream
+    // beside the fact side, and the join waits for both.
+    const hipStream_t sd = b.join ? ctx->side : s;
+    if (b.join && (st = side_fork(ctx, s)) != TQP_OK) return st;
     if (b.dkeep && f.n_dim > 0 &&
         (st = eval_program(ctx, f.dim_cols, nullptr, f.n_dim_cols, f.n_dim, nullptr, f.dim_pred, f.n_dim_pred, b.dkeep,
-                           s, "tqp_fragment_run", "fragment_dim_pred")) != TQP_OK)
+                           sd, "tqp_fragment_run", "fragment_dim_pred", true)) != TQP_OK)
+        return st;
+    const uint32_t* rk = b.dsk;
+    const uint32_t* rv = b.dsv;
+    if (b.join) {
+        const int32_t* dkey = static_cast<const int32_t*>(f.dim_cols[f.dim_key].data);
+        if (b.dpush >= 0) {
+            SrcKeepCol ds{dkey, b.dkeep, static_cast<const int32_t*>(f.dim_cols[b.dpush].data), f.n_dim};
+            if ((st = radix_launch<Cfg, uint32_t>(b.dsort, ds, f.n_dim, true, nullptr, key_mask_for(kb), b.dsk,
+                                                  b.dsv, ctx, sd, "fragment_sort_dim", "fragment_sort_dim")) != TQP_OK)
+                return st;
+        } else {
+            SrcKeepRow ds{dkey, b.dkeep, f.n_dim};
+            if ((st = radix_launch<Cfg, uint32_t>(b.dsort, ds, f.n_dim, true, nullptr, key_mask_for(kb), b.dsk,
+                                                  b.dsv, ctx, sd, "fragment_sort_dim", "fragment_sort_dim")) != TQP_OK)
+                return st;
+        }
+        if (b.flowb > 0 && f.n_dim > 0) {
+            // the low bits of the dim keys, span by span, and every bucket's start
+            TQP_LAUNCH(ctx, sd, "fragment_finish_dim",
+                       k_finish_sort<<<(unsigned)b.nspans, FINISH_BLOCK, 0, sd>>>(b.dsk, b.dsv, f.n_dim, b.dsk_full,
+                                                                               b.dsv_full, b.flowb, b.mbstart,
+                                                                               b.dsort.d_cnt));
+            rk = b.dsk_full;
+            rv = b.dsv_full;
+        }
+    }
+    if (b.fkeep && N > 0 &&
+        (st = eval_program(ctx, f.fact_cols, nullptr, f.n_fact_cols, N, nullptr, f.fact_pred, f.n_fact_pred, b.fkeep,
+                           s, "tqp_fragment_run", "fragment_fact_pred", true)) != TQP_OK)
         return st;
     // 2. join, or the kept fact rows
     if (b.join) {
         const int32_t* fkey = static_cast<const int32_t*>(f.fact_cols[f.fact_key].data);
-        const int32_t* dkey = static_cast<const int32_t*>(f.dim_cols[f.dim_key].data);
         const int64_t* fsort_cnt;
         if (b.fpush) {
             // the one value program over every fact row, in row order, before the sort
@@ -713,28 +766,7 @@ tqp_status gen_launch(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_ou
                 return st;
             fsort_cnt = b.fsort.d_cnt;
         }
-        if (b.dpush >= 0) {
-            SrcKeepCol ds{dkey, b.dkeep, static_cast<const int32_t*>(f.dim_cols[b.dpush].data), f.n_dim};
-            if ((st = radix_launch<Cfg, uint32_t>(b.dsort, ds, f.n_dim, true, nullptr, key_mask_for(kb), b.dsk,
-                                                  b.dsv, ctx, s, "fragment_sort_dim", "fragment_sort_dim")) != TQP_OK)
-                return st;
-        } else {
-            SrcKeepRow ds{dkey, b.dkeep, f.n_dim};
-            if ((st = radix_launch<Cfg, uint32_t>(b.dsort, ds, f.n_dim, true, nullptr, key_mask_for(kb), b.dsk,
-                                                  b.dsv, ctx, s, "fragment_sort_dim", "fragment_sort_dim")) != TQP_OK)
-                return st;
-        }
-        const uint32_t* rk = b.dsk;
-        const uint32_t* rv = b.dsv;
-        if (b.flowb > 0 && f.n_dim > 0) {
-            // the low bits of the dim keys, span by span, and every bucket's start
-            TQP_LAUNCH(ctx, s, "fragment_finish_dim",
-                       k_finish_sort<<<(unsigned)b.nspans, FINISH_BLOCK, 0, s>>>(b.dsk, b.dsv, f.n_dim, b.dsk_full,
-                                                                              b.dsv_full, b.flowb, b.mbstart,
-                                                                              b.dsort.d_cnt));
-            rk = b.dsk_full;
-            rv = b.dsv_full;
-        }
+        if ((st = side_join(ctx, s)) != TQP_OK) return st;
         const int64_t* rbstart = b.flowb > 0 && f.n_dim > 0 ? b.mbstart : nullptr;
         if (b.fpush) {
             EmitValRow e{b.jval, b.ri, J};
@@ -754,7 +786,7 @@ tqp_status gen_launch(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_ou
         if (b.fkeep) {
             fp.np = 1;
             fp.col[0] = b.fkeep;
-            fp.type[0] = TQP_I64;
+            fp.type[0] = TQP_I8;
             fp.op[0] = CMP_NE;
             fp.k[0] = 0;
         }
@@ -791,9 +823,14 @@ tqp_status gen_launch(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_ou
         }
         g.bits[i] = f.group[i].bits;
     }
-    TQP_LAUNCH(ctx, s, "fragment_pack",
-               k_gf_pack<<<grid_for(J, 256 * 4, (int64_t)ctx->num_cus * 8), 256, 0, s>>>(g, b.li, b.ri, J, b.d_join,
-                                                                                        b.gkey, ctx->d_err));
+    // the one group column carried by the dim sort, with the bucket group-by
+    // (which masks the key as the pack would): the group sort reads it directly
+    const bool direct_key = b.bucket && f.n_group == 1 && g.side[0] == 2;
+    if (!direct_key) {
+        TQP_LAUNCH(ctx, s, "fragment_pack",
+                   k_gf_pack<<<grid_for(J, 256 * 4, (int64_t)ctx->num_cus * 8), 256, 0, s>>>(
+                       g, b.li, b.ri, J, b.d_join, b.gkey, ctx->d_err));
+    }
     // 4. aggregate values (an empty side joins nothing: no row is read, and
     // its columns may be null)
     const bool no_rows = N == 0 || (b.join && f.n_dim == 0);
@@ -815,6 +852,13 @@ tqp_status gen_launch(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_ou
                                               "fragment_sort_value")) != TQP_OK)
             return st;
         perm_in = b.pb;
+    }
+    if (direct_key) {
+        SrcColKeyVal64 a3{b.ri, b.vals[b.vsort], J, b.d_join, key_mask_for(b.gbits)};
+        if ((st = radix_launch<Cfg, uint64_t>(b.sv, a3, J, true, nullptr, key_mask_for(b.gbits), b.kc, b.vc, ctx, s,
+                                              "fragment_sort_group", "fragment_sort_group")) != TQP_OK)
+            return st;
+        return bucket_groupby(ctx, f, o, b, s);
     }
     if (b.vsort >= 0) {
         SrcKeyVal64 a3{b.gkey, b.vals[b.vsort], J, b.d_join};

@@ -157,6 +157,28 @@ def test_general_bucket(hip, ctx, trial):
     _check(got, want, topk)
 
 
+@pytest.mark.parametrize("neg", [False, True])
+def test_general_bucket_carried_key(hip, ctx, neg):
+    """The bucket group-by over the one int32 dim group column that rode the dim sort, read by the
+    group sort directly (no pack): in range (18 bits), or with negative values (16 bits: masked into
+    the key, key-range flag), a fact value program riding the fact sort; equal to the oracle."""
+    O = oracle
+    rng = np.random.default_rng(9400 + neg)
+    fact, dim = _tables(rng, 300_007, 20_011, 25_000, False)
+    if not neg:
+        dim[2] = rng.integers(0, 1 << 18, len(dim[2])).astype(np.int32)
+    nf = len(fact)
+    group = [(nf + 2, 16 if neg else 18)]
+    aggs = [(O.AGG_SUM, [(O.X_COL, 2), (O.X_COL, 1), (O.X_MUL, 0)]), (O.AGG_COUNT, [])]
+    fp = [(O.X_COL, 4), (O.X_CONST, 2000), (O.X_LT, 0)]
+    want = O.fragment_general(fact, dim, fp, [], 0, 0, group, aggs, topk=10, gcap=1 << 20)
+    got = hip.fragment_run(ctx, [_dev(c) for c in fact], [_dev(c) for c in dim], fp, [], 0, 0, group, aggs, topk=10,
+                           key_bits=15, join_cap=max(1, want["join_rows"]), gcap=max(1, want["groups"]))
+    assert ctx.errors() == (hip.DEVERR_KEY_RANGE if neg else 0)
+    assert bool(want["bad"]) == neg
+    _check(got, want, 10)
+
+
 def test_general_bucket_capacity_and_empty(hip, ctx):
     """The bucket group-by with fewer group slots than groups (capacity flag, the true group count,
     the first gcap groups exact, top-k over the written groups as the oracle's) and with no joined
