@@ -742,8 +742,8 @@ def bench_general(args):
     """The config-2 custkey workload (60M fact x 15M mid rows) written as a general fragment
     descriptor (tqp_fragment_run: predicate program, join, group column, SUM and COUNT over value
     programs, top-100) against the fused custkey fragment, both timed as launch sequences on the
-    stream; the general result must equal the fused one (every group, the join size, the top
-    rows)."""
+    stream, each with the revenue declared 32-bit and 64-bit; the general results must equal the
+    fused one (every group, the join size, the top rows)."""
     import numpy as np
     import torch
 
@@ -788,13 +788,24 @@ def bench_general(args):
     dcols = [mid["pk"], mid["custkey"]]
     rev = [(X.TQP_X_COL, 2), (X.TQP_X_CONST, 100), (X.TQP_X_COL, 3), (X.TQP_X_SUB, 0), (X.TQP_X_MUL, 0)]
     pred = [(X.TQP_X_COL, 1), (X.TQP_X_CONST, fr.D), (X.TQP_X_LT, 0)]
-    gen = lambda: tqp.fragment_run(ctx, cols, dcols, pred, [], 0, 0, [(5, cust_bits)],
-                                   [(X.AGG_SUM, rev), (X.AGG_COUNT, [])], topk=fr.k, key_bits=key_bits,
-                                   join_cap=N, gcap=fr.cust_hi)
-    ms, out = timed(gen)
-    res["general_ms"] = round(ms, 4)
-    log("general fragment: %.3f ms" % ms)
-    # kernel time of one general call by the library's events
+    f = fused[64]
+    ok = all(np.array_equal(fused[32][x], fused[64][x]) for x in ("key", "sum", "cnt", "top_key"))
+    for vb in (64, 32):
+        # the revenue declared int32 (value_bits = 32) or int64, as the fused fragment's revenue_bits
+        gen = lambda vb=vb: tqp.fragment_run(ctx, cols, dcols, pred, [], 0, 0, [(5, cust_bits)],
+                                             [(X.AGG_SUM, rev), (X.AGG_COUNT, [])], topk=fr.k, key_bits=key_bits,
+                                             join_cap=N, gcap=fr.cust_hi, value_bits=vb)
+        ms, out = timed(gen)
+        res["general_ms" if vb == 32 else "general_v64_ms"] = round(ms, 4)
+        log("general fragment, %d-bit value: %.3f ms" % (vb, ms))
+        G = int(out["d_ngroups"].item())
+        k = int(out["d_topk"].item())
+        ok = (ok and G == f["groups"] and int(out["d_join"].item()) == f["join_rows"] and ctx.errors() == 0
+              and np.array_equal(out["key"][:G].cpu().numpy(), f["key"])
+              and np.array_equal(out["vals"][0][:G].cpu().numpy(), f["sum"])
+              and np.array_equal(out["vals"][1][:G].cpu().numpy(), f["cnt"])
+              and np.array_equal(out["top_key"][:k].cpu().numpy(), f["top_key"]))
+    # kernel time of one general call (32-bit value) by the library's events
     ctx.profile_read()
     ctx.set_profiling(True)
     gen()
@@ -805,19 +816,11 @@ def bench_general(args):
     for name, t in recs:
         per[name] = round(per.get(name, 0.0) + t, 4)
     res["general_kernels_ms"] = per
-    G = int(out["d_ngroups"].item())
-    f = fused[64]
-    ok = (G == f["groups"] and int(out["d_join"].item()) == f["join_rows"] and ctx.errors() == 0
-          and np.array_equal(out["key"][:G].cpu().numpy(), f["key"])
-          and np.array_equal(out["vals"][0][:G].cpu().numpy(), f["sum"])
-          and np.array_equal(out["vals"][1][:G].cpu().numpy(), f["cnt"]))
-    k = int(out["d_topk"].item())
-    ok = ok and np.array_equal(out["top_key"][:k].cpu().numpy(), f["top_key"])
-    ok = ok and all(np.array_equal(fused[32][x], fused[64][x]) for x in ("key", "sum", "cnt", "top_key"))
     if not ok:
         log("general fragment result differs from the fused one")
         sys.exit(3)
     res["general_vs_fused_rev32"] = round(res["general_ms"] / res["fused_rev32_ms"], 2)
+    res["general_v64_vs_fused_rev64"] = round(res["general_v64_ms"] / res["fused_rev64_ms"], 2)
     res["general_fact_rows_per_s"] = round(N / (res["general_ms"] * 1e-3), 1)
     print(json.dumps({"metric": "custkey fragment ms, general descriptor vs fused", "unit": "ms", "n_gpus": 1,
                       "steps": args.steps, "warmup": args.warmup, "higher_is_better": False, "data": "synthetic",

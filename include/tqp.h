@@ -472,11 +472,19 @@ tqp_status tqp_fragment_cust_plan(tqp_ctx* ctx, const tqp_cust_fragment* f, int*
  * TQP_DEVERR_CAPACITY beyond).  topk > 0 (1..1024, agg_1 not AVG): the first
  * topk groups by (agg_1 desc, key asc) go to top_key / top_val and their
  * number to *d_topk.  join_cap bounds the joined rows (TQP_DEVERR_CAPACITY
- * beyond; the true count goes to *d_join when given).  The composition is
- * sort-based throughout: both join sides are radix-sorted with their
- * predicates fused into the sort, joined as by tqp_join, the group keys
- * (and, for COUNT(DISTINCT), the distinct values first) radix-sorted with
- * the joined-row index, and each group's run reduced. */
+ * beyond; the true count goes to *d_join when given).  value_bits = 32
+ * declares that the program of the one aggregate with a program lies in
+ * [-2^31, 2^31) on every fact row; when that program reads fact columns
+ * only (and the fragment is grouped by one int32 dim column of 16 bits or
+ * more) its value is then carried in 32 bits, and a value outside sets
+ * TQP_DEVERR_VALUE_RANGE; otherwise the declaration is not used.  The
+ * composition is sort-based throughout: both join sides are radix-sorted with
+ * their predicates fused into the sort, joined as by tqp_join, the group keys
+ * (and, for COUNT(DISTINCT), the distinct values first) radix-sorted with the
+ * joined-row index, and each group's run reduced; with one aggregate that has
+ * a program (no COUNT(DISTINCT)) and a key of 16 bits or more, the group sort
+ * covers the key bits above the last 8 to 13 and each bucket of keys is
+ * reduced in LDS. */
 #define TQP_AGG_COUNT 0
 #define TQP_AGG_SUM 1
 #define TQP_AGG_MIN 2
@@ -515,6 +523,8 @@ typedef struct {
     int32_t n_agg;
     int32_t topk;
     int64_t join_cap;
+    int32_t value_bits;            /* 0 or 64; 32: see below */
+    int32_t reserved;
 } tqp_fragment;
 typedef struct {
     int32_t* key;             /* [gcap] packed group keys, ascending */

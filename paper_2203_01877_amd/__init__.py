@@ -188,12 +188,13 @@ def eval_expr(ctx: Context, cols: list, prog: list, d_n=None, stream=None):
 
 def fragment_run(ctx: Context, fact: list, dim: list | None, fact_pred: list, dim_pred: list, fact_key: int,
                  dim_key: int, group: list, aggs: list, topk: int = 0, key_bits: int = 0, join_cap: int | None = None,
-                 gcap: int | None = None, stream=None) -> dict:
+                 gcap: int | None = None, value_bits: int = 0, stream=None) -> dict:
     """A general fragment (tqp_fragment_run): fact / dim are lists of device columns; predicates and
     aggregate values are postfix programs [(op, arg)]; fact_key < 0 or dim None: no join; group =
     [(joined column, bits)]; aggs = [(AGG_* op, program)].  join_cap defaults to the fact rows (exact
-    when dim keys are unique), gcap to join_cap.  Returns device tensors: key, vals (one per aggregate,
-    float64 for AVG), d_ngroups, d_join, top_key, top_val, d_topk."""
+    when dim keys are unique), gcap to join_cap; value_bits = 32 declares the one valued aggregate's
+    values int32.  Returns device tensors: key, vals (one per aggregate, float64 for AVG), d_ngroups,
+    d_join, top_key, top_val, d_topk."""
     join = dim is not None and fact_key >= 0
     dim = dim if join else []
     n_fact = fact[0].numel()
@@ -213,7 +214,7 @@ def fragment_run(ctx: Context, fact: list, dim: list | None, fact_pred: list, di
     f = _lib.Fragment(ctypes.addressof(fc), len(fact), fact_key if join else -1, n_fact, ctypes.addressof(fp),
                       len(fact_pred), key_bits, ctypes.addressof(dc), len(dim), dim_key, n_dim, ctypes.addressof(dp),
                       len(dim_pred) if join else 0, len(group), ctypes.addressof(ga), ctypes.addressof(aa), len(aggs),
-                      topk, join_cap)
+                      topk, join_cap, value_bits, 0)
     out = {"key": torch.empty(gcap, dtype=torch.int32, device=dev), "vals": vals,
            "d_ngroups": torch.empty(1, dtype=torch.int64, device=dev), "d_join": torch.empty(1, dtype=torch.int64,
                                                                                              device=dev),

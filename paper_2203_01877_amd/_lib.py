@@ -90,7 +90,7 @@ class Fragment(ctypes.Structure):
                 ("fact_pred", c_vp), ("n_fact_pred", c_i32), ("key_bits", c_i32), ("dim_cols", c_vp),
                 ("n_dim_cols", c_i32), ("dim_key", c_i32), ("n_dim", c_i64), ("dim_pred", c_vp), ("n_dim_pred", c_i32),
                 ("n_group", c_i32), ("group", c_vp), ("aggs", c_vp), ("n_agg", c_i32), ("topk", c_i32),
-                ("join_cap", c_i64)]
+                ("join_cap", c_i64), ("value_bits", c_i32), ("reserved", c_i32)]
 
 
 class FragmentOut(ctypes.Structure):

@@ -55,13 +55,13 @@ struct XProg {
 // types the direct columns may have; loads of the other types are left out.
 template <int NC, int ROWS, bool GATHER, int TYPES = XT_ALL>
 __global__ void __launch_bounds__(XE_BLOCK)
-k_eval(XProg p, int64_t n_upper, const int64_t* d_n, void* out, int flag_out, uint32_t* flags) {
+k_eval(XProg p, int64_t n_upper, const int64_t* d_n, void* out, int out_mode, uint32_t* flags) {
     constexpr int XE_ROWS = ROWS;
     extern __shared__ int64_t xe_st[];
     int64_t n = n_upper;
     if (d_n) { const int64_t t = *d_n; n = t < n ? t : n; }
     const int tid = threadIdx.x;
-    bool zdiv = false;
+    bool zdiv = false;            // a zero divisor, or (XOUT_I32) a value outside int32: the value-range flag
     const int64_t step = (int64_t)gridDim.x * XE_BLOCK * XE_ROWS;
     for (int64_t base = (int64_t)blockIdx.x * XE_BLOCK * XE_ROWS; base < n; base += step) {
         int64_t cv[XE_ROWS][NC];
@@ -253,8 +253,14 @@ k_eval(XProg p, int64_t n_upper, const int64_t* d_n, void* out, int flag_out, ui
         for (int j = 0; j < XE_ROWS; ++j) {
             const int64_t row = base + (int64_t)j * XE_BLOCK + tid;
             if (row < n) {
-                if (flag_out) static_cast<uint8_t*>(out)[row] = top[j] != 0;
-                else static_cast<int64_t*>(out)[row] = top[j];
+                if (out_mode == XOUT_FLAG) {
+                    static_cast<uint8_t*>(out)[row] = top[j] != 0;
+                } else if (out_mode == XOUT_I32) {
+                    static_cast<int32_t*>(out)[row] = (int32_t)top[j];
+                    zdiv |= top[j] != (int64_t)(int32_t)top[j];
+                } else {
+                    static_cast<int64_t*>(out)[row] = top[j];
+                }
             }
         }
     }
@@ -277,7 +283,7 @@ int x_arity(int32_t op) {
 // are not null) are read at idx[c][row].
 tqp_status eval_program(tqp_ctx* ctx, const tqp_column* cols, const int32_t* const* idx, int ncols, int64_t n,
                         const int64_t* d_n, const tqp_xinstr* prog, int nprog, void* out, hipStream_t stream,
-                        const char* who, const char* label, bool flag_out) {
+                        const char* who, const char* label, int out_mode) {
     if (nprog < 1 || nprog > XP_MAX) return fail(TQP_ERR_UNSUPPORTED, "%s: 1 to %d instructions", who, XP_MAX);
     if (ncols < 0 || ncols > XE_MAX_COLS) return fail(TQP_ERR_UNSUPPORTED, "%s: %d columns", who, ncols);
     XProg p{};
@@ -324,7 +330,7 @@ tqp_status eval_program(tqp_ctx* ctx, const tqp_column* cols, const int32_t* con
         const size_t lds = (size_t)(deepest > 1 ? deepest - 1 : 1) * rows * XE_BLOCK * sizeof(int64_t);
         TQP_LAUNCH(ctx, stream, label,
                    kernel<<<grid_for(n, (int64_t)XE_BLOCK * rows, (int64_t)ctx->num_cus * 16), XE_BLOCK, lds,
-                            stream>>>(p, n, d_n, out, flag_out ? 1 : 0, ctx->d_err));
+                            stream>>>(p, n, d_n, out, out_mode, ctx->d_err));
         return TQP_OK;
     };
     // rows per thread: as many as the column registers allow

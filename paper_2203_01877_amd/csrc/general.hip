@@ -437,6 +437,20 @@ k_gf_agg(const uint32_t* skey, const uint32_t* perm, const int64_t* start, const
     }
 }
 
+// The keyed form of the bucket group-by: the fact value rides the fact sort
+// (VT: int64 bits, or int32 bits under a declared 32-bit width), the join
+// emits (group key, value) with the group sort's digit counts, and the group
+// sort is its passes alone.
+template <class Cfg, class VT>
+struct GenKv {
+    RadixBufs<Cfg, VT> fsort, gsort;
+    VT* fsv = nullptr;
+    uint32_t* gk_in = nullptr;
+    VT* gv_in = nullptr;
+    uint32_t* gk = nullptr;
+    VT* gv = nullptr;
+};
+
 template <class Cfg>
 struct GenBufs {
     bool join = false;
@@ -467,6 +481,11 @@ struct GenBufs {
     uint64_t* bstatus = nullptr;
     uint32_t* bcounter = nullptr;
     int64_t *bval = nullptr, *bcnt = nullptr;   // per group: the value's reduction, the row count
+    bool kv = false;                         // the keyed form (one group column carried by the dim sort)
+    bool v32 = false;                        // its value carried in 32 bits
+    int32_t* fval32 = nullptr;
+    GenKv<Cfg, uint64_t> kv64;
+    GenKv<Cfg, uint32_t> kv32;
     JoinBufs jb;
     uint32_t *fsk = nullptr, *fsv = nullptr, *dsk = nullptr, *dsv = nullptr;
     uint64_t* fstatus = nullptr;             // no join: the compaction of the kept fact rows
@@ -507,6 +526,10 @@ void gen_reserve(Arena& a, const tqp_fragment& f, const tqp_fragment_out& o, Gen
         }
     if (valued != 1 || b.distinct >= 0) b.vsort = -1;
     b.bucket = b.vsort >= 0 && b.gbits >= GF_BUCKET_MIN_BITS;
+    if (b.bucket) {
+        b.lowb = bucket_low_bits(b.gbits, Cfg::RADIX_BITS);
+        b.nbuckets = int64_t(1) << (b.gbits - b.lowb);
+    }
     if (b.join) {
         // what the join's output is used for: columns of each side read after it
         auto prog_sides = [&](const tqp_xinstr* pr, int np, bool& uses_f, bool& uses_d) {
@@ -539,13 +562,33 @@ void gen_reserve(Arena& a, const tqp_fragment& f, const tqp_fragment_out& o, Gen
         b.fpush = b.vsort >= 0 && prog_f && !prog_d && !group_f && !divides;
         // the dim rows serve only one int32 group column
         if (group_d && gd_one && !prog_d && f.dim_cols[gd - f.n_fact_cols].type == TQP_I32) b.dpush = gd - f.n_fact_cols;
+        b.kv = b.bucket && b.fpush && b.dpush >= 0 && f.n_group == 1;
+        b.v32 = b.kv && f.value_bits == 32;
     }
     if (f.n_fact_pred > 0) b.fkeep = a.scratch<uint8_t>(N);
     if (b.join) {
         if (f.n_dim_pred > 0) b.dkeep = a.scratch<uint8_t>(f.n_dim);
         b.flowb = join_low_bits(N, kb, Cfg::RADIX_BITS, JCfgGen::TILE, JCfgGen::RWIN);
         if (b.flowb > FINISH_LOG2) b.flowb = FINISH_LOG2;
-        if (b.fpush) {
+        auto kv_reserve = [&](auto& k) {
+            using VT = typename std::remove_pointer<decltype(k.fsv)>::type;
+            k.fsort = radix_reserve<Cfg, VT>(a, N, kb, b.flowb);
+            k.fsv = a.scratch<VT>(N);
+            k.gsort = radix_reserve<Cfg, VT>(a, J, b.gbits, b.lowb, false);     // digit counts from the join
+            k.gk_in = a.scratch<uint32_t>(J);
+            k.gv_in = a.scratch<VT>(J);
+            k.gk = a.scratch<uint32_t>(J);
+            k.gv = a.scratch<VT>(J);
+        };
+        if (b.kv) {
+            if (b.v32) {
+                b.fval32 = a.scratch<int32_t>(N);
+                kv_reserve(b.kv32);
+            } else {
+                b.fval = a.scratch<int64_t>(N);
+                kv_reserve(b.kv64);
+            }
+        } else if (b.fpush) {
             b.fval = a.scratch<int64_t>(N);
             b.fsort64 = radix_reserve<Cfg, uint64_t>(a, N, kb, b.flowb);
             b.fsv64 = a.scratch<uint64_t>(N);
@@ -566,7 +609,7 @@ void gen_reserve(Arena& a, const tqp_fragment& f, const tqp_fragment_out& o, Gen
         b.dsk = a.scratch<uint32_t>(f.n_dim);
         b.dsv = a.scratch<uint32_t>(f.n_dim);
         b.jb = join_reserve<JCfgGen>(a, N);
-        b.ri = a.scratch<int32_t>(J);
+        if (!b.kv) b.ri = a.scratch<int32_t>(J);
     } else {
         const int64_t tiles = (N + GF_FILTER_BLOCK * GF_FILTER_ITEMS - 1) / (GF_FILTER_BLOCK * GF_FILTER_ITEMS);
         b.fstatus = a.zero<uint64_t>(tiles);
@@ -574,7 +617,7 @@ void gen_reserve(Arena& a, const tqp_fragment& f, const tqp_fragment_out& o, Gen
     }
     if (!b.fpush) b.li = a.scratch<int32_t>(J);
     b.d_join = a.zero<int64_t>(1);
-    b.gkey = a.scratch<uint32_t>(J);
+    if (!b.kv) b.gkey = a.scratch<uint32_t>(J);
     for (int k = 0; k < f.n_agg; ++k)
         if (f.aggs[k].op != TQP_AGG_COUNT) b.vals[k] = b.fpush && k == b.vsort ? b.jval : a.scratch<int64_t>(J);
     if (b.distinct >= 0) {
@@ -585,12 +628,12 @@ void gen_reserve(Arena& a, const tqp_fragment& f, const tqp_fragment_out& o, Gen
         b.kb = a.scratch<uint32_t>(J);
         b.pb = a.scratch<uint32_t>(J);
     }
-    b.kc = a.scratch<uint32_t>(J);
     if (b.bucket) {
-        b.lowb = bucket_low_bits(b.gbits, Cfg::RADIX_BITS);
-        b.nbuckets = int64_t(1) << (b.gbits - b.lowb);
-        b.sv = radix_reserve<Cfg, uint64_t>(a, J, b.gbits, b.lowb);
-        b.vc = a.scratch<uint64_t>(J);
+        if (!b.kv) {
+            b.sv = radix_reserve<Cfg, uint64_t>(a, J, b.gbits, b.lowb);
+            b.kc = a.scratch<uint32_t>(J);
+            b.vc = a.scratch<uint64_t>(J);
+        }
         b.bstarts = a.scratch<int64_t>(b.nbuckets + 1);
         b.bstatus = a.zero<uint64_t>(b.nbuckets);
         b.bcounter = a.zero<uint32_t>(1);
@@ -603,6 +646,7 @@ void gen_reserve(Arena& a, const tqp_fragment& f, const tqp_fragment_out& o, Gen
         }
         return;
     }
+    b.kc = a.scratch<uint32_t>(J);
     if (b.vsort >= 0) {
         b.sv = radix_reserve<Cfg, uint64_t>(a, J, b.gbits);
         b.vc = a.scratch<uint64_t>(J);
@@ -635,10 +679,11 @@ struct JoinedCols {
 // the value (sum, min or max) and counts the rows per key in LDS and writes
 // its groups in key order, with its first k groups as top-k candidates when
 // the fragment has a top-k.  Groups come out in ascending key order, as from
-// the full sort.
-template <class Cfg>
+// the full sort.  bhist: the digit counts of a one-pass group sort (the
+// buckets), else the bucket starts are searched for.
+template <class Cfg, class AV>
 tqp_status bucket_groupby(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_out& o, const GenBufs<Cfg>& b,
-                          hipStream_t s) {
+                          const uint32_t* keys, const AV* vals, const uint32_t* bhist, hipStream_t s) {
     const int64_t J = f.join_cap;
     const int vop = f.aggs[b.vsort].op;
     int64_t* vout = vop == TQP_AGG_AVG ? b.bval : static_cast<int64_t*>(f.aggs[b.vsort].out);
@@ -652,36 +697,32 @@ tqp_status bucket_groupby(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragmen
         finish |= f.aggs[k].op == TQP_AGG_AVG;
     }
     SegOut so{o.key, vout, cout, nullptr, o.gcap, o.d_ngroups};
-    // bucket starts: with one pass the buckets are its digits, and its
-    // histogram gives them; otherwise one search per bucket
-    const uint32_t* bhist = b.sv.pd.npass == 1 ? b.sv.hist : nullptr;
     if (!bhist) {
         TQP_LAUNCH(ctx, s, "fragment_bucket_bounds",
-                   k_bucket_bounds<<<grid_for(b.nbuckets + 1, 256, 0), 256, 0, s>>>(b.kc, J, b.d_join, b.lowb,
+                   k_bucket_bounds<<<grid_for(b.nbuckets + 1, 256, 0), 256, 0, s>>>(keys, J, b.d_join, b.lowb,
                                                                                       b.nbuckets, b.bstarts));
     }
     TopCand* cand = f.topk > 0 ? b.topk.filtered : nullptr;
     int64_t* d_cand = f.topk > 0 ? b.topk.d_nf : nullptr;
     const bool bycnt = f.topk > 0 && f.aggs[0].op == TQP_AGG_COUNT;
-    const int64_t* vals = reinterpret_cast<const int64_t*>(b.vc);
     constexpr int SLOTS = 1 << BUCKET_LOWB_MAX;
     auto go = [&](auto kern) -> tqp_status {
         TQP_LAUNCH(ctx, s, "fragment_bucket_agg",
-                   kern<<<(unsigned)b.nbuckets, 1024, 0, s>>>(b.kc, vals, b.bstarts, bhist, b.lowb, b.nbuckets,
+                   kern<<<(unsigned)b.nbuckets, 1024, 0, s>>>(keys, vals, b.bstarts, bhist, b.lowb, b.nbuckets,
                                                               b.bstatus, b.bcounter, so, ctx->d_err, cand, d_cand,
                                                               f.topk));
         return TQP_OK;
     };
     tqp_status st;
     if (vop == TQP_AGG_MIN)
-        st = bycnt ? go(k_bucket_agg<1024, SLOTS, int64_t, BUCKET_MIN, true>)
-                   : go(k_bucket_agg<1024, SLOTS, int64_t, BUCKET_MIN, false>);
+        st = bycnt ? go(k_bucket_agg<1024, SLOTS, AV, BUCKET_MIN, true>)
+                   : go(k_bucket_agg<1024, SLOTS, AV, BUCKET_MIN, false>);
     else if (vop == TQP_AGG_MAX)
-        st = bycnt ? go(k_bucket_agg<1024, SLOTS, int64_t, BUCKET_MAX, true>)
-                   : go(k_bucket_agg<1024, SLOTS, int64_t, BUCKET_MAX, false>);
+        st = bycnt ? go(k_bucket_agg<1024, SLOTS, AV, BUCKET_MAX, true>)
+                   : go(k_bucket_agg<1024, SLOTS, AV, BUCKET_MAX, false>);
     else
-        st = bycnt ? go(k_bucket_agg<1024, SLOTS, int64_t, BUCKET_SUM, true>)
-                   : go(k_bucket_agg<1024, SLOTS, int64_t, BUCKET_SUM, false>);
+        st = bycnt ? go(k_bucket_agg<1024, SLOTS, AV, BUCKET_SUM, true>)
+                   : go(k_bucket_agg<1024, SLOTS, AV, BUCKET_SUM, false>);
     if (st != TQP_OK) return st;
     if (finish && o.gcap > 0) {
         AggSet as{};
@@ -700,6 +741,62 @@ tqp_status bucket_groupby(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragmen
     return TQP_OK;
 }
 
+// The keyed bucket group-by from the fact value on (the dim side and the
+// fact predicate already launched): the value program over every fact row,
+// the fact sort carrying it, the join emitting (group key, value) with the
+// group sort's digit counts, the group sort's passes, the buckets.
+template <class Cfg, class VT>
+tqp_status kv_launch(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_out& o, const GenBufs<Cfg>& b,
+                     const GenKv<Cfg, VT>& k, const uint32_t* rk, const uint32_t* rv, hipStream_t s) {
+    constexpr bool V32 = sizeof(VT) == 4;
+    const int kb = norm_key_bits(f.key_bits);
+    const int64_t N = f.n_fact, J = f.join_cap;
+    const int32_t* fkey = static_cast<const int32_t*>(f.fact_cols[f.fact_key].data);
+    const tqp_agg& ag = f.aggs[b.vsort];
+    tqp_status st;
+    void* fv = V32 ? static_cast<void*>(b.fval32) : static_cast<void*>(b.fval);
+    if (N > 0 && (st = eval_program(ctx, f.fact_cols, nullptr, f.n_fact_cols, N, nullptr, ag.prog, ag.nprog, fv, s,
+                                    "tqp_fragment_run", "fragment_fact_value", V32 ? XOUT_I32 : XOUT_I64)) != TQP_OK)
+        return st;
+    if constexpr (V32) {
+        SrcKeepCol fs{fkey, b.fkeep, b.fval32, N};
+        st = radix_launch<Cfg, uint32_t>(k.fsort, fs, N, true, nullptr, key_mask_for(kb), b.fsk, k.fsv, ctx, s,
+                                         "fragment_sort_fact", "fragment_sort_fact");
+    } else {
+        SrcKeepVal64 fs{fkey, b.fkeep, b.fval, N};
+        st = radix_launch<Cfg, uint64_t>(k.fsort, fs, N, true, nullptr, key_mask_for(kb), b.fsk, k.fsv, ctx, s,
+                                         "fragment_sort_fact", "fragment_sort_fact");
+    }
+    if (st != TQP_OK) return st;
+    if ((st = side_join(ctx, s)) != TQP_OK) return st;
+    using Emit = EmitKeyVal<JCfgGen::BLOCK, Cfg::RADIX_BITS, VT>;
+    Emit e{};
+    e.out_key = k.gk_in;
+    e.out_val = k.gv_in;
+    e.cap = J;
+    e.key_mask = key_mask_for(b.gbits);
+    e.flags = ctx->d_err;
+    e.hist = k.gsort.hist;
+    e.npass = k.gsort.pd.npass;
+    for (int p = 0; p < k.gsort.pd.npass && p < Emit::NP; ++p) {
+        e.shift[p] = k.gsort.pd.shift[p];
+        e.bits[p] = k.gsort.pd.bits[p];
+    }
+    const int64_t* rbstart = b.flowb > 0 && f.n_dim > 0 ? b.mbstart : nullptr;
+    if ((st = join_launch<JCfgGen, VT, uint32_t, Emit>(ctx, s, "fragment_join", b.jb, b.fsk, k.fsv, N, k.fsort.d_cnt,
+                                                       rk, rv, f.n_dim, b.dsort.d_cnt, b.d_join, J, e, b.flowb,
+                                                       nullptr, rbstart, b.nmbkt)) != TQP_OK)
+        return st;
+    if (o.d_join) TQP_TRY_HIP(hipMemcpyAsync(o.d_join, b.d_join, 8, hipMemcpyDeviceToDevice, s));
+    SrcPairs<VT> gsrc{k.gk_in, k.gv_in, J, b.d_join};
+    if ((st = radix_launch<Cfg, VT>(k.gsort, gsrc, J, false, b.d_join, key_mask_for(b.gbits), k.gk, k.gv, ctx, s,
+                                    "fragment_sort_group", "fragment_sort_group")) != TQP_OK)
+        return st;
+    using AV = typename std::conditional<V32, int32_t, int64_t>::type;
+    return bucket_groupby<Cfg, AV>(ctx, f, o, b, k.gk, reinterpret_cast<const AV*>(k.gv),
+                                   k.gsort.pd.npass == 1 ? k.gsort.hist : nullptr, s);
+}
+
 template <class Cfg>
 tqp_status gen_launch(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_out& o, const GenBufs<Cfg>& b,
                       hipStream_t s) {
@@ -713,7 +810,7 @@ tqp_status gen_launch(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_ou
     if (b.join && (st = side_fork(ctx, s)) != TQP_OK) return st;
     if (b.dkeep && f.n_dim > 0 &&
         (st = eval_program(ctx, f.dim_cols, nullptr, f.n_dim_cols, f.n_dim, nullptr, f.dim_pred, f.n_dim_pred, b.dkeep,
-                           sd, "tqp_fragment_run", "fragment_dim_pred", true)) != TQP_OK)
+                           sd, "tqp_fragment_run", "fragment_dim_pred", XOUT_FLAG)) != TQP_OK)
         return st;
     const uint32_t* rk = b.dsk;
     const uint32_t* rv = b.dsv;
@@ -742,9 +839,12 @@ tqp_status gen_launch(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_ou
     }
     if (b.fkeep && N > 0 &&
         (st = eval_program(ctx, f.fact_cols, nullptr, f.n_fact_cols, N, nullptr, f.fact_pred, f.n_fact_pred, b.fkeep,
-                           s, "tqp_fragment_run", "fragment_fact_pred", true)) != TQP_OK)
+                           s, "tqp_fragment_run", "fragment_fact_pred", XOUT_FLAG)) != TQP_OK)
         return st;
     // 2. join, or the kept fact rows
+    if (b.kv)
+        return b.v32 ? kv_launch<Cfg, uint32_t>(ctx, f, o, b, b.kv32, rk, rv, s)
+                     : kv_launch<Cfg, uint64_t>(ctx, f, o, b, b.kv64, rk, rv, s);
     if (b.join) {
         const int32_t* fkey = static_cast<const int32_t*>(f.fact_cols[f.fact_key].data);
         const int64_t* fsort_cnt;
@@ -858,14 +958,17 @@ tqp_status gen_launch(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_ou
         if ((st = radix_launch<Cfg, uint64_t>(b.sv, a3, J, true, nullptr, key_mask_for(b.gbits), b.kc, b.vc, ctx, s,
                                               "fragment_sort_group", "fragment_sort_group")) != TQP_OK)
             return st;
-        return bucket_groupby(ctx, f, o, b, s);
+        return bucket_groupby<Cfg, int64_t>(ctx, f, o, b, b.kc, reinterpret_cast<const int64_t*>(b.vc),
+                                            b.sv.pd.npass == 1 ? b.sv.hist : nullptr, s);
     }
     if (b.vsort >= 0) {
         SrcKeyVal64 a3{b.gkey, b.vals[b.vsort], J, b.d_join};
         if ((st = radix_launch<Cfg, uint64_t>(b.sv, a3, J, true, nullptr, key_mask_for(b.gbits), b.kc, b.vc, ctx, s,
                                               "fragment_sort_group", "fragment_sort_group")) != TQP_OK)
             return st;
-        if (b.bucket) return bucket_groupby(ctx, f, o, b, s);
+        if (b.bucket)
+            return bucket_groupby<Cfg, int64_t>(ctx, f, o, b, b.kc, reinterpret_cast<const int64_t*>(b.vc),
+                                                b.sv.pd.npass == 1 ? b.sv.hist : nullptr, s);
     } else {
         SrcPermKey<0> a3{b.gkey, perm_in, J, b.d_join};
         if ((st = radix_launch<Cfg, uint32_t>(b.sc, a3, J, true, nullptr, key_mask_for(b.gbits), b.kc, b.pc, ctx, s,
@@ -945,6 +1048,8 @@ tqp_status check_general(tqp_ctx* ctx, const tqp_fragment* f, const tqp_fragment
         ndist += a.op == TQP_AGG_COUNT_DISTINCT;
     }
     if (ndist > 1) return fail(TQP_ERR_UNSUPPORTED, "%s: at most one COUNT(DISTINCT)", who);
+    if (f->value_bits != 0 && f->value_bits != 32 && f->value_bits != 64)
+        return fail(TQP_ERR_UNSUPPORTED, "%s: value_bits = %d (0, 32 or 64)", who, f->value_bits);
     if (f->topk < 0 || f->topk > 1024 || (f->topk > 0 && (f->n_agg < 1 || f->aggs[0].op == TQP_AGG_AVG)))
         return fail(TQP_ERR_UNSUPPORTED, "%s: topk %d (1..1024 over an integer first aggregate)", who, f->topk);
     if (f->topk > 0 && (!o->top_key || !o->top_val || !o->d_topk)) return fail(TQP_ERR_INVALID, "%s: top outputs", who);

@@ -109,13 +109,15 @@ tqp_status with_workspace(tqp_ctx* ctx, void* ws, size_t* ws_bytes, hipStream_t 
 tqp_status fill_zero(void* p, size_t bytes, hipStream_t stream, tqp_ctx* ctx = nullptr);
 
 // Checks a postfix expression program over ncols columns and, for n > 0,
-// evaluates it into out (n or *d_n rows): int64 values, or with flag_out one
-// byte per row, 1 where the value is nonzero (a predicate's keep column).
-// Column c is read at idx[c][row] when idx and idx[c] are given.  tqp_eval
-// and the general fragments use it.
+// evaluates it into out (n or *d_n rows) as out_mode says: int64 values; one
+// byte per row, 1 where the value is nonzero (a predicate's keep column); or
+// int32 values, a value outside int32 raising the value-range flag.  Column c
+// is read at idx[c][row] when idx and idx[c] are given.  tqp_eval and the
+// general fragments use it.
+enum : int { XOUT_I64 = 0, XOUT_FLAG = 1, XOUT_I32 = 2 };
 tqp_status eval_program(tqp_ctx* ctx, const tqp_column* cols, const int32_t* const* idx, int ncols, int64_t n,
                         const int64_t* d_n, const tqp_xinstr* prog, int nprog, void* out, hipStream_t stream,
-                        const char* who, const char* label, bool flag_out = false);
+                        const char* who, const char* label, int out_mode = XOUT_I64);
 
 // Looks up this device's scratch array of tqp_filter_noalloc (the device must
 // be current); done once per device, from tqp_ctx_create.

@@ -110,12 +110,13 @@ struct EmitKeyVal {
     }
     __device__ void operator()(int64_t o, uint32_t, uint64_t lp, uint32_t rp, Smem& s) {
         if (o < cap) {
-            out_key[o] = rp;
+            const uint32_t key = rp & key_mask;        // a key outside the width enters masked
+            out_key[o] = key;
             out_val[o] = lp;
             if (rp & ~key_mask) set_flag(flags, FLAG_KEY_RANGE);
             if (hist)
                 for (int p = 0; p < npass; ++p)
-                    atomicAdd(&s.h[p * R + ((rp >> shift[p]) & ((1u << bits[p]) - 1))], 1u);
+                    atomicAdd(&s.h[p * R + ((key >> shift[p]) & ((1u << bits[p]) - 1))], 1u);
         }
     }
     __device__ void finish(Smem& s) {

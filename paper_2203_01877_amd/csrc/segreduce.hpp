@@ -226,9 +226,9 @@ constexpr int BUCKET_LOWB_MAX = 13;        // 8192 slots: 96 KB of LDS
 __global__ void k_bucket_bounds(const uint32_t* keys, int64_t n_upper, const int64_t* d_n, int lowb,
                                 int64_t nbuckets, int64_t* starts);
 
-// vals: int64 values (VT = int64_t) or values in [0, 2^32) (VT = uint32_t).
-// OP: what the value column is reduced to (sum; min or max for int64
-// values), written to out.sum.  With cand, each block also appends the first
+// vals: int64 values (VT = int64_t), int32 values (VT = int32_t) or values in
+// [0, 2^32) (VT = uint32_t).  OP: what the value column is reduced to (sum;
+// min or max for signed values), written to out.sum.  With cand, each block also appends the first
 // k of its groups in the order value DESC (the count with BYCNT), key ASC
 // (step 1 of the top-k: the overall first k are among them) to cand,
 // counting them in *d_cand.
@@ -239,7 +239,8 @@ k_bucket_agg(const uint32_t* keys, const VT* vals, const int64_t* starts, const 
              int64_t nbuckets, uint64_t* status, uint32_t* counter, SegOut out, uint32_t* flags,
              TopCand* cand = nullptr, int64_t* d_cand = nullptr, int k = 0) {
     static_assert(SLOTS <= (1 << BUCKET_LOWB_MAX), "slot table larger than the LDS budget");
-    static_assert(OP == BUCKET_SUM || std::is_same<VT, int64_t>::value, "min / max over int64 values");
+    static_assert(OP == BUCKET_SUM || std::is_same<VT, int64_t>::value || std::is_same<VT, int32_t>::value,
+                  "min / max over signed values");
     constexpr int U = 8;                               // loads in flight per thread
     constexpr int PER = (SLOTS + BLOCK - 1) / BLOCK;   // most slots per thread
     __shared__ unsigned long long s_sum[SLOTS];

@@ -84,7 +84,8 @@ def test_struct_layouts_match_the_c_header(tmp_path):
     structs = {"tqp_column": L.Column, "tqp_pred": L.Pred, "tqp_flags_fragment": L.FlagsFragment,
                "tqp_flags_out": L.FlagsOut, "tqp_cust_fragment": L.CustFragment, "tqp_cust_out": L.CustOut,
                "tqp_prof_entry": L.ProfEntry, "tqp_server_config": L.ServerConfig, "tqp_request": L.Request,
-               "tqp_result": L.Result}
+               "tqp_result": L.Result, "tqp_xinstr": L.XInstr, "tqp_group_col": L.GroupCol, "tqp_agg": L.Agg,
+               "tqp_fragment": L.Fragment, "tqp_fragment_out": L.FragmentOut, "tqp_chain_table": L.ChainTable}
     lines = ['#include "tqp.h"', "#include <cstddef>", "#include <cstdio>", "int main() {"]
     for cname, py in structs.items():
         lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))

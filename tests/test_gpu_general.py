@@ -157,11 +157,12 @@ def test_general_bucket(hip, ctx, trial):
     _check(got, want, topk)
 
 
-@pytest.mark.parametrize("neg", [False, True])
-def test_general_bucket_carried_key(hip, ctx, neg):
-    """The bucket group-by over the one int32 dim group column that rode the dim sort, read by the
-    group sort directly (no pack): in range (18 bits), or with negative values (16 bits: masked into
-    the key, key-range flag), a fact value program riding the fact sort; equal to the oracle."""
+@pytest.mark.parametrize("neg,vb", [(False, 0), (True, 0), (False, 32), (True, 32), (False, 64)])
+def test_general_bucket_carried_key(hip, ctx, neg, vb):
+    """The keyed bucket group-by: the fact value program rides the fact sort (int64, or int32 under
+    value_bits = 32), the one int32 dim group column rides the dim sort, and the join emits (group
+    key, value) with the group sort's digit counts: keys in range (18 bits), or with negative values
+    (16 bits: masked into the key, key-range flag); equal to the oracle."""
     O = oracle
     rng = np.random.default_rng(9400 + neg)
     fact, dim = _tables(rng, 300_007, 20_011, 25_000, False)
@@ -173,10 +174,37 @@ def test_general_bucket_carried_key(hip, ctx, neg):
     fp = [(O.X_COL, 4), (O.X_CONST, 2000), (O.X_LT, 0)]
     want = O.fragment_general(fact, dim, fp, [], 0, 0, group, aggs, topk=10, gcap=1 << 20)
     got = hip.fragment_run(ctx, [_dev(c) for c in fact], [_dev(c) for c in dim], fp, [], 0, 0, group, aggs, topk=10,
-                           key_bits=15, join_cap=max(1, want["join_rows"]), gcap=max(1, want["groups"]))
+                           key_bits=15, join_cap=max(1, want["join_rows"]), gcap=max(1, want["groups"]), value_bits=vb)
     assert ctx.errors() == (hip.DEVERR_KEY_RANGE if neg else 0)
     assert bool(want["bad"]) == neg
     _check(got, want, 10)
+
+
+@pytest.mark.parametrize("op", [oracle.AGG_SUM, oracle.AGG_MIN, oracle.AGG_MAX, oracle.AGG_AVG])
+def test_general_value32(hip, ctx, op):
+    """value_bits = 32 with values spanning the whole int32 range (negative and positive extremes)
+    for every valued aggregate, a COUNT first for the top-k (AVG) or the value (the others); equal
+    to the oracle.  A value outside int32 raises the value-range flag."""
+    O = oracle
+    rng = np.random.default_rng(9500 + op)
+    fact, dim = _tables(rng, 250_003, 20_011, 20_011, False)
+    fact[2] = rng.integers(-(1 << 31), 1 << 31, len(fact[2])).astype(np.int64)
+    dim[2] = rng.integers(0, 1 << 17, len(dim[2])).astype(np.int32)
+    nf = len(fact)
+    aggs = [(op, [(O.X_COL, 2)]), (O.AGG_COUNT, [])]
+    if op == O.AGG_AVG:
+        aggs = aggs[::-1]
+    want = O.fragment_general(fact, dim, [], [], 0, 0, [(nf + 2, 17)], aggs, topk=20, gcap=1 << 20)
+    got = hip.fragment_run(ctx, [_dev(c) for c in fact], [_dev(c) for c in dim], [], [], 0, 0, [(nf + 2, 17)], aggs,
+                           topk=20, key_bits=15, join_cap=max(1, want["join_rows"]), gcap=max(1, want["groups"]),
+                           value_bits=32)
+    assert ctx.errors() == 0
+    _check(got, want, 20)
+    if op == O.AGG_SUM:
+        big = [(O.X_COL, 2), (O.X_CONST, 2), (O.X_MUL, 0)]
+        hip.fragment_run(ctx, [_dev(c) for c in fact], [_dev(c) for c in dim], [], [], 0, 0, [(nf + 2, 17)],
+                         [(O.AGG_SUM, big), (O.AGG_COUNT, [])], key_bits=15, gcap=1 << 17, value_bits=32)
+        assert ctx.errors() == hip.DEVERR_VALUE_RANGE
 
 
 def test_general_bucket_capacity_and_empty(hip, ctx):
