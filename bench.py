@@ -85,7 +85,7 @@ def roofline_families(PB):
         "group_pass": ("k_radix_pass<%s, SrcPairs<%s>, %s, 3>" % (cfg, v, v), radix),
         "join_keyval": ("k_join<JoinCfg<256,8,2048>, %s, u32, EmitKeyVal<256,8,%s>, 0>" % (v, v),
                         ("join.hpp", "dev.hpp", "fragment.hpp")),
-        "bucket_agg": ("k_bucket_agg<1024,8192,%s>" % a, ("segreduce.hpp", "dev.hpp")),
+        "bucket_agg": ("k_bucket_agg<1024,8192,%s,0,false>" % a, ("segreduce.hpp", "dev.hpp")),
     }
 
 
