@@ -570,9 +570,12 @@ void gen_reserve(Arena& a, const tqp_fragment& f, const tqp_fragment_out& o, Gen
         if (f.n_dim_pred > 0) b.dkeep = a.scratch<uint8_t>(f.n_dim);
         b.flowb = join_low_bits(N, kb, Cfg::RADIX_BITS, JCfgGen::TILE, JCfgGen::RWIN);
         if (b.flowb > FINISH_LOG2) b.flowb = FINISH_LOG2;
+        // the fact sorts' first pass looks back instead of reading per-tile
+        // counts, as the custkey fragment's fact sort: over tens of millions
+        // of rows the plain histogram costs less than the counting one
         auto kv_reserve = [&](auto& k) {
             using VT = typename std::remove_pointer<decltype(k.fsv)>::type;
-            k.fsort = radix_reserve<Cfg, VT>(a, N, kb, b.flowb);
+            k.fsort = radix_reserve<Cfg, VT>(a, N, kb, b.flowb, false);
             k.fsv = a.scratch<VT>(N);
             k.gsort = radix_reserve<Cfg, VT>(a, J, b.gbits, b.lowb, false);     // digit counts from the join
             k.gk_in = a.scratch<uint32_t>(J);
@@ -590,11 +593,11 @@ void gen_reserve(Arena& a, const tqp_fragment& f, const tqp_fragment_out& o, Gen
             }
         } else if (b.fpush) {
             b.fval = a.scratch<int64_t>(N);
-            b.fsort64 = radix_reserve<Cfg, uint64_t>(a, N, kb, b.flowb);
+            b.fsort64 = radix_reserve<Cfg, uint64_t>(a, N, kb, b.flowb, false);
             b.fsv64 = a.scratch<uint64_t>(N);
             b.jval = a.scratch<int64_t>(J);
         } else {
-            b.fsort = radix_reserve<Cfg, uint32_t>(a, N, kb, b.flowb);
+            b.fsort = radix_reserve<Cfg, uint32_t>(a, N, kb, b.flowb, false);
             b.fsv = a.scratch<uint32_t>(N);
         }
         b.dsort = radix_reserve<Cfg, uint32_t>(a, f.n_dim, kb, b.flowb);
@@ -741,6 +744,16 @@ tqp_status bucket_groupby(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragmen
     return TQP_OK;
 }
 
+// The one valued aggregate's program over every fact row, in row order (it
+// then rides the fact sort).
+template <class Cfg>
+tqp_status fact_value(tqp_ctx* ctx, const tqp_fragment& f, const GenBufs<Cfg>& b, void* out, int mode,
+                      hipStream_t s) {
+    const tqp_agg& ag = f.aggs[b.vsort];
+    return eval_program(ctx, f.fact_cols, nullptr, f.n_fact_cols, f.n_fact, nullptr, ag.prog, ag.nprog, out, s,
+                        "tqp_fragment_run", "fragment_fact_value", mode);
+}
+
 // The keyed bucket group-by from the fact value on (the dim side and the
 // fact predicate already launched): the value program over every fact row,
 // the fact sort carrying it, the join emitting (group key, value) with the
@@ -752,12 +765,9 @@ tqp_status kv_launch(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_out
     const int kb = norm_key_bits(f.key_bits);
     const int64_t N = f.n_fact, J = f.join_cap;
     const int32_t* fkey = static_cast<const int32_t*>(f.fact_cols[f.fact_key].data);
-    const tqp_agg& ag = f.aggs[b.vsort];
     tqp_status st;
     void* fv = V32 ? static_cast<void*>(b.fval32) : static_cast<void*>(b.fval);
-    if (N > 0 && (st = eval_program(ctx, f.fact_cols, nullptr, f.n_fact_cols, N, nullptr, ag.prog, ag.nprog, fv, s,
-                                    "tqp_fragment_run", "fragment_fact_value", V32 ? XOUT_I32 : XOUT_I64)) != TQP_OK)
-        return st;
+    if (N > 0 && (st = fact_value(ctx, f, b, fv, V32 ? XOUT_I32 : XOUT_I64, s)) != TQP_OK) return st;
     if constexpr (V32) {
         SrcKeepCol fs{fkey, b.fkeep, b.fval32, N};
         st = radix_launch<Cfg, uint32_t>(k.fsort, fs, N, true, nullptr, key_mask_for(kb), b.fsk, k.fsv, ctx, s,
@@ -850,10 +860,7 @@ tqp_status gen_launch(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_ou
         const int64_t* fsort_cnt;
         if (b.fpush) {
             // the one value program over every fact row, in row order, before the sort
-            const tqp_agg& ag = f.aggs[b.vsort];
-            if (N > 0 && (st = eval_program(ctx, f.fact_cols, nullptr, f.n_fact_cols, N, nullptr, ag.prog, ag.nprog,
-                                            b.fval, s, "tqp_fragment_run", "fragment_fact_value")) != TQP_OK)
-                return st;
+            if (N > 0 && (st = fact_value(ctx, f, b, b.fval, XOUT_I64, s)) != TQP_OK) return st;
             SrcKeepVal64 fs{fkey, b.fkeep, b.fval, N};
             if ((st = radix_launch<Cfg, uint64_t>(b.fsort64, fs, N, true, nullptr, key_mask_for(kb), b.fsk, b.fsv64,
                                                   ctx, s, "fragment_sort_fact", "fragment_sort_fact")) != TQP_OK)
