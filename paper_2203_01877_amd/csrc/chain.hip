@@ -7,11 +7,14 @@
 // table 2's, and so on.  A tuple is one row position per table joined so far.
 // Hop t (t >= 1) joins the current tuples to table t:
 //   1. the tuples' keys into table t are sorted with the tuple index as the
-//      payload (radix sort at the hop's key width);
+//      payload (radix sort at the hop's key width; as in the fused
+//      fragments, the low key bits a join tile resolves in LDS are left
+//      unsorted when that saves a pass);
 //   2. table t's key column is sorted with its row positions, unless the
 //      caller declares it sorted (then the positions are the indexes) or
 //      dense (then no sort and no join: the key is its own row position, and
-//      a filter keeps the tuples whose key lies in [0, M));
+//      one pass keeps the tuples whose key lies in [0, M), writing their
+//      positions, their row and the next key, steps 3 and 4 included);
 //   3. the sort-based join gives (tuple index, row of table t) pairs;
 //   4. one gather kernel reads the earlier position columns through the tuple
 //      index (late materialisation) and the next hop's key through the new
@@ -26,7 +29,6 @@
 // Every hop's size stays on the device and bounds the next hop's kernels
 // (their grids come from the caller's capacities), so the whole chain is one
 // launch sequence with no host synchronisation.
-#include "filter.hpp"
 #include "fragment.hpp"
 
 namespace tqp {
@@ -125,6 +127,108 @@ k_chain_gather(ChainGather g, const int32_t* li, const int32_t* rr, int64_t n_up
     }
 }
 
+// A hop by the dense rule in one pass: the tuples whose key k lies in
+// [0, M) are kept in order (ballot per 64 tuples, block scan, decoupled
+// look-back, as the filter), each written as its earlier positions (carried
+// columns, or the tuple index itself on the first hop), its row k of the
+// table, and the next hop's key read at row k.
+struct ChainDense {
+    const int32_t* key;
+    int64_t M;
+    const int32_t* src[TQP_CHAIN_MAX_TABLES];   // earlier position columns, in tuple order
+    int32_t* dst[TQP_CHAIN_MAX_TABLES];
+    int32_t ncols;
+    int32_t* index_dst;                         // the tuple index (first hop), nullable
+    int32_t* row_dst;
+    const int32_t* key_src;                     // the next hop's key column (nullable)
+    int32_t* key_dst;
+};
+
+template <int BLOCK, int ITEMS>
+__global__ void __launch_bounds__(BLOCK)
+k_chain_dense(ChainDense d, int64_t n, const int64_t* d_n, int64_t cap, int64_t* d_count, uint64_t* status,
+              uint32_t* tile_counter, uint32_t* flags) {
+    constexpr int TILE = BLOCK * ITEMS, W = BLOCK / WAVE;
+    __shared__ int64_t s_wave[W];
+    __shared__ int64_t s_base;
+    __shared__ uint32_t s_tile;
+    const int tid = threadIdx.x, w = tid / WAVE, l = lane_id();
+    if (d_n) {                                 // tuples counted on the device, at most n
+        const int64_t t = *d_n;
+        n = t < n ? t : n;
+    }
+    if (tid == 0) s_tile = atomicAdd(tile_counter, 1u);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    const int64_t ntiles = (n + TILE - 1) / TILE;
+    if (tile >= ntiles) {
+        if (ntiles == 0 && tile == 0 && tid == 0) *d_count = 0;
+        return;
+    }
+    const int64_t chunk = tile * TILE + (int64_t)w * ITEMS * WAVE;
+    int32_t k[ITEMS];
+    bool ok[ITEMS];
+    uint64_t m[ITEMS];
+    int64_t wc = 0;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int64_t i = chunk + j * WAVE + l;
+        k[j] = d.key[i < n ? i : n - 1];       // n >= 1: the tile exists
+    }
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        ok[j] = chunk + j * WAVE + l < n && k[j] >= 0 && (int64_t)k[j] < d.M;
+        m[j] = ballot(ok[j]);
+        wc += popc64(m[j]);
+    }
+    // the next keys of the kept tuples, in flight while the tile looks back
+    int32_t nk[ITEMS];
+    if (d.key_src && d.M > 0) {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) nk[j] = d.key_src[ok[j] ? k[j] : 0];
+    }
+    if (l == 0) s_wave[w] = wc;
+    __syncthreads();
+    if (w == 0) {
+        int64_t tot = 0;
+        for (int ww = 0; ww < W; ++ww) tot += s_wave[ww];
+        const int64_t base = lookback64(status, tile, tot, flags);
+        if (tid == 0) {
+            int64_t run = 0;
+            for (int ww = 0; ww < W; ++ww) { const int64_t x = s_wave[ww]; s_wave[ww] = run; run += x; }
+            s_base = base;
+            if (tile == ntiles - 1) {
+                *d_count = base + tot;
+                if (base + tot > cap) set_flag(flags, FLAG_CAPACITY);
+            }
+        }
+    }
+    __syncthreads();
+    int64_t o[ITEMS];
+    int64_t pos = s_base + s_wave[w];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        o[j] = ok[j] ? pos + popc64(m[j] & lanemask_lt()) : -1;
+        pos += popc64(m[j]);
+        if (o[j] >= 0 && o[j] < cap) {
+            d.row_dst[o[j]] = k[j];
+            if (d.index_dst) d.index_dst[o[j]] = (int32_t)(chunk + j * WAVE + l);
+            if (d.key_src) d.key_dst[o[j]] = nk[j];
+        }
+    }
+    for (int c = 0; c < d.ncols; ++c) {
+        int32_t v[ITEMS];
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const int64_t i = chunk + j * WAVE + l;
+            v[j] = d.src[c][i < n ? i : n - 1];
+        }
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j)
+            if (o[j] >= 0 && o[j] < cap) d.dst[c][o[j]] = v[j];
+    }
+}
+
 template <class Cfg>
 struct HopBufs {
     bool dense = false, sorted = false;
@@ -132,6 +236,9 @@ struct HopBufs {
     int64_t n_left = 0;                      // host bound on the tuples entering the hop
     RadixBufs<Cfg, uint32_t> lsort, rsort;
     RadixBufs<Cfg, uint64_t> lsort2;         // carry: the key sort with both positions
+    int lowb = 0;                            // key bits the left sort leaves to the join tiles
+    int64_t nbkt = 0;                        // 2^lowb-key buckets of the right keys
+    int64_t* rbstart = nullptr;              // the start of every bucket in the sorted right keys
     uint64_t* lsv2 = nullptr;
     JoinBufs join;
     uint64_t* fstatus = nullptr;             // dense rule: the filter's look-back words
@@ -166,11 +273,19 @@ void chain_reserve(Arena& a, const tqp_chain_table* t, int nt, int64_t* d_count,
             hb.fcounter = a.zero<uint32_t>(1);
         } else {
             hb.carry = h == 2;
+            // as in the fused fragments: the left sort covers the key bits
+            // above lowb and each join tile resolves the rest in LDS, its
+            // window found from the right keys' bucket starts
+            hb.lowb = join_low_bits(hb.n_left, kb, Cfg::RADIX_BITS, JCfgChain::TILE, JCfgChain::RWIN);
+            if (hb.lowb > 0) {
+                hb.nbkt = int64_t(1) << (kb - hb.lowb);
+                hb.rbstart = a.scratch<int64_t>(hb.nbkt + 1);
+            }
             if (hb.carry) {
-                hb.lsort2 = radix_reserve<Cfg, uint64_t>(a, hb.n_left, kb);
+                hb.lsort2 = radix_reserve<Cfg, uint64_t>(a, hb.n_left, kb, hb.lowb);
                 hb.lsv2 = a.scratch<uint64_t>(hb.n_left);
             } else {
-                hb.lsort = radix_reserve<Cfg, uint32_t>(a, hb.n_left, kb);
+                hb.lsort = radix_reserve<Cfg, uint32_t>(a, hb.n_left, kb, hb.lowb);
                 hb.lsv = a.scratch<uint32_t>(hb.n_left);
             }
             hb.lsk = a.scratch<uint32_t>(hb.n_left);
@@ -207,22 +322,34 @@ tqp_status chain_launch(tqp_ctx* ctx, const tqp_chain_table* t, int nt, int32_t*
         // hop 1: the tuple index is table 0's row position, so it goes to its column directly
         int32_t* li = h == 1 ? dst[0] : hb.li;
         int32_t* rr = dst[h];
+        int32_t* next_key = b.key[h & 1];
         if (hb.dense) {
-            FilterPreds fp{};
-            fp.np = 2;
-            fp.col[0] = cur;
-            fp.col[1] = cur;
-            fp.type[0] = fp.type[1] = TQP_I32;
-            fp.op[0] = CMP_GE;
-            fp.k[0] = 0;
-            fp.op[1] = CMP_LT;
-            fp.k[1] = t[h].n_rows;
+            ChainDense d{};
+            d.key = cur;
+            d.M = t[h].n_rows;
+            if (h == 1) {
+                d.index_dst = dst[0];
+            } else {
+                d.ncols = h;
+                for (int u = 0; u < h; ++u) {
+                    d.src[u] = prev_cols[u];
+                    d.dst[u] = dst[u];
+                }
+            }
+            d.row_dst = rr;
+            if (h < H) {
+                d.key_src = t[h].key_out;
+                d.key_dst = next_key;
+            }
             constexpr int64_t TILE = CH_FILTER_BLOCK * CH_FILTER_ITEMS;
             TQP_LAUNCH(ctx, s, "chain_dense",
-                       (k_filter<CH_FILTER_BLOCK, CH_FILTER_ITEMS><<<grid_for(hb.n_left, TILE, 0), CH_FILTER_BLOCK,
-                                                                     0, s>>>(fp, hb.n_left, cur, li, rr, t[h].cap,
-                                                                             hb.d_cnt, hb.fstatus, hb.fcounter,
-                                                                             ctx->d_err, d_prev)));
+                       (k_chain_dense<CH_FILTER_BLOCK, CH_FILTER_ITEMS><<<grid_for(hb.n_left, TILE, 0),
+                                                                         CH_FILTER_BLOCK, 0, s>>>(
+                           d, hb.n_left, d_prev, t[h].cap, hb.d_cnt, hb.fstatus, hb.fcounter, ctx->d_err)));
+            cur = next_key;
+            d_prev = hb.d_cnt;
+            prev_cols = dst;
+            continue;
         } else {
             if (hb.carry) {
                 SrcKeysPos2 lsrc{reinterpret_cast<const uint32_t*>(cur), prev_cols[0], prev_cols[1], hb.n_left, d_prev};
@@ -246,18 +373,26 @@ tqp_status chain_launch(tqp_ctx* ctx, const tqp_chain_table* t, int nt, int32_t*
                 rk = hb.rsk;
                 rp = hb.rsv;
             }
+            // the start of every 2^lowb-key bucket of the sorted right keys
+            // (an empty right side gives empty windows by search)
+            const int64_t* rbstart = hb.lowb > 0 && t[h].n_rows > 0 ? hb.rbstart : nullptr;
+            if (rbstart)
+                TQP_LAUNCH(ctx, s, "chain_bucket_bounds",
+                           k_bucket_bounds<<<grid_for(hb.nbkt + 1, 256, 0), 256, 0, s>>>(rk, t[h].n_rows, nullptr,
+                                                                                          hb.lowb, hb.nbkt,
+                                                                                          hb.rbstart));
             // left elements that took part in the sort: the histogram's count
             if (hb.carry) {
                 EmitPos3 e{dst[0], dst[1], rr, t[h].cap};
                 if ((st = join_launch<JCfgChain, uint64_t, uint32_t, EmitPos3>(
                          ctx, s, "chain_join", hb.join, hb.lsk, hb.lsv2, hb.n_left, hb.lsort2.d_cnt, rk, rp,
-                         t[h].n_rows, nullptr, hb.d_cnt, t[h].cap, e)) != TQP_OK)
+                         t[h].n_rows, nullptr, hb.d_cnt, t[h].cap, e, hb.lowb, nullptr, rbstart, hb.nbkt)) != TQP_OK)
                     return st;
             } else {
                 EmitPairs e{li, rr, t[h].cap};
                 if ((st = join_launch<JCfgChain, uint32_t, uint32_t, EmitPairs>(
                          ctx, s, "chain_join", hb.join, hb.lsk, hb.lsv, hb.n_left, hb.lsort.d_cnt, rk, rp,
-                         t[h].n_rows, nullptr, hb.d_cnt, t[h].cap, e)) != TQP_OK)
+                         t[h].n_rows, nullptr, hb.d_cnt, t[h].cap, e, hb.lowb, nullptr, rbstart, hb.nbkt)) != TQP_OK)
                     return st;
             }
         }
@@ -268,7 +403,6 @@ tqp_status chain_launch(tqp_ctx* ctx, const tqp_chain_table* t, int nt, int32_t*
             g.src[u] = prev_cols[u];
             g.dst[u] = dst[u];
         }
-        int32_t* next_key = b.key[h & 1];
         if (h < H) {
             g.key_src = t[h].key_out;
             g.key_dst = next_key;

@@ -458,6 +458,28 @@ def test_join_chain_dense(hip, ctx):
         assert np.array_equal(_lex(got), _lex(want))
 
 
+def test_join_chain_dense_edges(hip, ctx):
+    """The one-pass dense hop at its edges: negative keys and keys at or above M drop out, a dense
+    table with no rows keeps no tuple (the next key is never read), and a dense last hop carries
+    three earlier position columns."""
+    rng = _rng(95)
+    outs = [rng.integers(-50, 1100, 100_000).astype(np.int32), rng.integers(0, 700, 1000).astype(np.int32),
+            rng.integers(-3, 30, 700).astype(np.int32)]
+    pks = [np.arange(1000, dtype=np.int32), rng.permutation(700).astype(np.int32), np.arange(25, dtype=np.int32)]
+    want = oracle.join_chain(outs, pks)
+    cols, J = hip.join_chain(ctx, [_dev(o) for o in outs], [_dev(p) for p in pks], pk_dense=[True, False, True],
+                             pk_sorted=[True, False, True])
+    assert J == len(want) > 0
+    got = np.stack([_np(c, J) for c in cols], axis=1)
+    assert np.array_equal(_lex(got), _lex(want))
+    empty = [outs[0], np.zeros(0, np.int32), outs[2]]
+    pk0 = [np.zeros(0, np.int32), pks[1], pks[2]]
+    cols, J = hip.join_chain(ctx, [_dev(o) for o in empty], [_dev(p) for p in pk0], pk_dense=[True, False, True],
+                             pk_sorted=[True, False, True])
+    assert J == 0 == len(oracle.join_chain(empty, pk0))
+    assert ctx.errors() == 0
+
+
 @pytest.mark.parametrize("rules", ["none", "mixed"])
 def test_join_chain_six_hops(hip, ctx, rules):
     """Six joins over seven tables (the shape of Section 6.3's six-join query) in one launch
