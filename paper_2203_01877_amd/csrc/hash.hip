@@ -39,7 +39,7 @@ namespace {
 
 constexpr uint32_t PJ_MUL = 0x9E3779B1u;        // odd: key -> h is a bijection mod 2^32
 constexpr int PJ_BLOCK = 512;
-constexpr int PJ_ITEMS = 4;                      // left rows per thread per round
+constexpr int PJ_ITEMS = 2;                      // left rows per thread per round
 constexpr int PJ_ROUND = PJ_BLOCK * PJ_ITEMS;
 constexpr int PJ_RCAP = 2048;                    // right rows per table build
 constexpr int PJ_LOG2S = 12;                     // table slots: 4096 (load factor <= 0.5)
@@ -313,8 +313,9 @@ __device__ void pj_probe(PjSmem& sm, const uint32_t* lh, const uint32_t* lv, int
     }
 }
 
-// Two blocks per CU: 40 KB of LDS each, and at most 128 VGPRs (4 waves per SIMD).
-__global__ void __launch_bounds__(PJ_BLOCK, 4)
+// Three blocks per CU: 40 KB of LDS each, and at most 84 VGPRs (6 waves per
+// SIMD; two left rows per thread and round keep the spills to a few).
+__global__ void __launch_bounds__(PJ_BLOCK, 6)
 k_pj_join(const uint32_t* lh, const uint32_t* lv, const uint32_t* rh, const uint32_t* rv, const int64_t* lstart,
           const int64_t* rstart, const int64_t* item_pre, int P, uint32_t* counter, int32_t* out_l, int32_t* out_r,
           int64_t cap, int64_t* total) {
