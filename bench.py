@@ -742,8 +742,9 @@ def bench_general(args):
     """The config-2 custkey workload (60M fact x 15M mid rows) written as a general fragment
     descriptor (tqp_fragment_run: predicate program, join, group column, SUM and COUNT over value
     programs, top-100) against the fused custkey fragment, both timed as launch sequences on the
-    stream, each with the revenue declared 32-bit and 64-bit; the general results must equal the
-    fused one (every group, the join size, the top rows)."""
+    stream, each with the revenue declared 32-bit and 64-bit; then config 1's flags fragment, fused
+    and as a descriptor.  The general results must equal the fused ones (every group, the join
+    size, the top rows)."""
     import numpy as np
     import torch
 
@@ -816,8 +817,30 @@ def bench_general(args):
     for name, t in recs:
         per[name] = round(per.get(name, 0.0) + t, 4)
     res["general_kernels_ms"] = per
+    # the flags fragment of config 1 (6M fact x 150k dim rows, date < D and seg == c, six groups
+    # by flagA, flagB: SUM revenue, COUNT, AVG price) fused and as a descriptor (the direct group-by)
+    fr1 = datagen.config1()
+    f1, d1 = tqp.to_device(fr1.fact, dev), tqp.to_device(fr1.dim, dev)
+    frun = tqp.FlagsFragmentRunner(ctx, f1, d1, fr1.D, fr1.c, key_bits=fr1.key_bits)
+    ms, _ = timed(lambda: frun.run())
+    res["flags_fused_ms"] = round(ms, 4)
+    ff = frun.result()
+    gflags = lambda: tqp.fragment_run(ctx, [f1[k] for k in ("fk", "date", "price", "disc", "flagA", "flagB")],
+                                      [d1["pk"], d1["seg"]], [(X.TQP_X_COL, 1), (X.TQP_X_CONST, fr1.D), (X.TQP_X_LT, 0)],
+                                      [(X.TQP_X_COL, 1), (X.TQP_X_CONST, fr1.c), (X.TQP_X_EQ, 0)], 0, 0, [(4, 2), (5, 1)],
+                                      [(X.AGG_SUM, rev), (X.AGG_COUNT, []), (X.AGG_AVG, [(X.TQP_X_COL, 2)])],
+                                      key_bits=fr1.key_bits, gcap=8)
+    ms, out = timed(gflags)
+    res["flags_general_ms"] = round(ms, 4)
+    G = int(out["d_ngroups"].item())
+    ok = (ok and G == len(ff["key"]) and int(out["d_join"].item()) == ff["join_rows"] and ctx.errors() == 0
+          and np.array_equal(out["key"][:G].cpu().numpy(), ff["key"])
+          and np.array_equal(out["vals"][0][:G].cpu().numpy(), ff["sum"])
+          and np.array_equal(out["vals"][1][:G].cpu().numpy(), ff["cnt"])
+          and np.array_equal(out["vals"][2][:G].cpu().numpy().view(np.int64), ff["avg"].view(np.int64)))
+    log("flags fragment (config 1): fused %.3f ms, general %.3f ms" % (res["flags_fused_ms"], res["flags_general_ms"]))
     if not ok:
-        log("general fragment result differs from the fused one")
+        log("general flags fragment result differs from the fused one")
         sys.exit(3)
     res["general_vs_fused_rev32"] = round(res["general_ms"] / res["fused_rev32_ms"], 2)
     res["general_v64_vs_fused_rev64"] = round(res["general_v64_ms"] / res["fused_rev64_ms"], 2)

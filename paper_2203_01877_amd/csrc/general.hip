@@ -58,6 +58,12 @@ constexpr int GF_MAX_COLS = 64;
 // applies): a bucket then holds 2^8 or more keys, enough slots that a block's
 // LDS updates rarely meet on one.
 constexpr int GF_BUCKET_MIN_BITS = 16;
+// Group keys of at most this many bits (no COUNT(DISTINCT)) take the direct
+// group-by: every block reduces its rows into an LDS slot per (aggregate,
+// key), with no group sort (Algorithm 2's runs are then whole key values).
+constexpr int GF_DIRECT_MAX_BITS = 9;
+constexpr int GF_DIRECT_BLOCK = 256;
+constexpr int GF_DIRECT_PARTS = 256;    // its blocks (each writes one part of the slots)
 
 // Sort source: the int32 key column with the row id as payload, rows whose
 // keep byte is zero left out (keep null: every row).
@@ -379,6 +385,86 @@ __global__ void k_gf_bucket_out(AggSet a, const int64_t* v, const int64_t* cnt, 
     }
 }
 
+// The direct group-by.  Slot (k, g) of aggregate k and key g holds the sum
+// (SUM, AVG), the largest ord(v) (MAX) or the largest ~ord(v) (MIN), where
+// ord flips the sign bit so that unsigned order is signed order: every slot
+// starts at 0 and only adds or takes maxima.  Slot (n, g) counts the rows.
+// Each block reduces a grid-stride share of the joined rows in LDS and writes
+// its slots to part[block].
+__global__ void __launch_bounds__(GF_DIRECT_BLOCK)
+k_gf_direct(const uint32_t* gkey, AggSet a, int64_t n_upper, const int64_t* d_n, int gbits, uint64_t* part) {
+    extern __shared__ unsigned long long dslot[];
+    const int G2 = 1 << gbits, nslot = (a.n + 1) << gbits;
+    for (int i = threadIdx.x; i < nslot; i += GF_DIRECT_BLOCK) dslot[i] = 0;
+    __syncthreads();
+    int64_t n = *d_n;
+    n = n < n_upper ? n : n_upper;
+    const uint32_t gmask = (uint32_t)G2 - 1;
+    for (int64_t i = (int64_t)blockIdx.x * GF_DIRECT_BLOCK + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * GF_DIRECT_BLOCK) {
+        const uint32_t g = gkey[i] & gmask;
+        atomicAdd(&dslot[(a.n << gbits) + g], 1ull);
+#pragma unroll
+        for (int k = 0; k < TQP_FRAGMENT_MAX_AGGS; ++k) {
+            if (k >= a.n || !a.val[k]) continue;
+            const int64_t v = a.val[k][i];
+            unsigned long long* sl = &dslot[(k << gbits) + g];
+            if (a.op[k] == TQP_AGG_MIN) atomicMax(sl, (unsigned long long)~gf_ord(v));
+            else if (a.op[k] == TQP_AGG_MAX) atomicMax(sl, (unsigned long long)gf_ord(v));
+            else atomicAdd(sl, (unsigned long long)v);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nslot; i += GF_DIRECT_BLOCK) part[(int64_t)blockIdx.x * nslot + i] = dslot[i];
+}
+
+// Slot s of every block's part reduced by one wave: red[s].
+__global__ void __launch_bounds__(WAVE)
+k_gf_direct_reduce(const uint64_t* part, int nparts, AggSet a, int gbits, uint64_t* red) {
+    const int nslot = (a.n + 1) << gbits, sl = blockIdx.x, k = sl >> gbits;
+    const bool takes_max = k < a.n && (a.op[k] == TQP_AGG_MIN || a.op[k] == TQP_AGG_MAX);
+    uint64_t acc = 0;
+    for (int b = lane_id(); b < nparts; b += WAVE) {
+        const uint64_t x = part[(int64_t)b * nslot + sl];
+        acc = takes_max ? (x > acc ? x : acc) : acc + x;
+    }
+    acc = takes_max ? wave_max(acc) : wave_sum(acc);
+    if (lane_id() == 0) red[sl] = acc;
+}
+
+// The non-empty keys in ascending order with their aggregates (one block of
+// 2^GF_DIRECT_MAX_BITS threads, one key each).
+__global__ void __launch_bounds__(1 << GF_DIRECT_MAX_BITS)
+k_gf_direct_out(const uint64_t* red, AggSet a, int gbits, int32_t* out_key, int64_t gcap, int64_t* d_ngroups,
+                int64_t* d_written, uint32_t* flags) {
+    __shared__ int64_t scratch[(1 << GF_DIRECT_MAX_BITS) / WAVE];
+    const int g = threadIdx.x, G2 = 1 << gbits;
+    const int64_t cnt = g < G2 ? (int64_t)red[((int64_t)a.n << gbits) + g] : 0;
+    int64_t total;
+    const int64_t pos = block_excl_sum<1 << GF_DIRECT_MAX_BITS>((int64_t)(cnt > 0), scratch, &total);
+    if (cnt > 0 && pos < gcap) {
+        out_key[pos] = g;
+#pragma unroll
+        for (int k = 0; k < TQP_FRAGMENT_MAX_AGGS; ++k) {
+            if (k >= a.n) continue;
+            const uint64_t x = red[((int64_t)k << gbits) + g];
+            int64_t* o64 = static_cast<int64_t*>(a.out[k]);
+            switch (a.op[k]) {
+                case TQP_AGG_COUNT: o64[pos] = cnt; break;
+                case TQP_AGG_SUM: o64[pos] = (int64_t)x; break;
+                case TQP_AGG_MIN: o64[pos] = gf_unord(~x); break;
+                case TQP_AGG_MAX: o64[pos] = gf_unord(x); break;
+                default: static_cast<double*>(a.out[k])[pos] = (double)(int64_t)x / (double)cnt; break;
+            }
+        }
+    }
+    if (g == 0) {
+        *d_ngroups = total;
+        *d_written = total < gcap ? total : gcap;
+        if (total > gcap) set_flag(flags, FLAG_CAPACITY);
+    }
+}
+
 // Every group's aggregates: each wave takes 64 consecutive groups (grid-stride);
 // a lane reduces its own group when all 64 are at most GF_LANE_GROUP rows,
 // else the wave reduces the long ones one at a time and the lanes the rest.
@@ -481,6 +567,9 @@ struct GenBufs {
     uint64_t* bstatus = nullptr;
     uint32_t* bcounter = nullptr;
     int64_t *bval = nullptr, *bcnt = nullptr;   // per group: the value's reduction, the row count
+    bool direct = false;                     // the direct group-by (few keys)
+    int64_t dparts = 0;                      // its blocks, one part each
+    uint64_t *dpart = nullptr, *dred = nullptr;
     bool kv = false;                         // the keyed form (one group column carried by the dim sort)
     bool v32 = false;                        // its value carried in 32 bits
     int32_t* fval32 = nullptr;
@@ -526,6 +615,7 @@ void gen_reserve(Arena& a, const tqp_fragment& f, const tqp_fragment_out& o, Gen
         }
     if (valued != 1 || b.distinct >= 0) b.vsort = -1;
     b.bucket = b.vsort >= 0 && b.gbits >= GF_BUCKET_MIN_BITS;
+    b.direct = b.distinct < 0 && b.gbits <= GF_DIRECT_MAX_BITS;
     if (b.bucket) {
         b.lowb = bucket_low_bits(b.gbits, Cfg::RADIX_BITS);
         b.nbuckets = int64_t(1) << (b.gbits - b.lowb);
@@ -630,6 +720,18 @@ void gen_reserve(Arena& a, const tqp_fragment& f, const tqp_fragment_out& o, Gen
         b.pa = a.scratch<uint32_t>(J);
         b.kb = a.scratch<uint32_t>(J);
         b.pb = a.scratch<uint32_t>(J);
+    }
+    if (b.direct) {
+        const int64_t nslot = (int64_t)(f.n_agg + 1) << b.gbits;
+        b.dparts = GF_DIRECT_PARTS;
+        b.dpart = a.scratch<uint64_t>(b.dparts * nslot);
+        b.dred = a.scratch<uint64_t>(nslot);
+        b.d_written = a.zero<int64_t>(1);
+        if (f.topk > 0) {
+            b.topk = topk_reserve(a, o.gcap, f.topk);
+            b.tcnt = a.scratch<int64_t>(f.topk);
+        }
+        return;
     }
     if (b.bucket) {
         if (!b.kv) {
@@ -807,6 +909,42 @@ tqp_status kv_launch(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_out
                                    k.gsort.pd.npass == 1 ? k.gsort.hist : nullptr, s);
 }
 
+// The direct group-by over the packed keys and the aggregates' values of the
+// joined rows: per-block LDS slots, the blocks' parts reduced per slot, the
+// non-empty keys written in ascending order; then the top-k as for sorted
+// groups.
+template <class Cfg>
+tqp_status direct_groupby(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_out& o, const GenBufs<Cfg>& b,
+                          hipStream_t s) {
+    const int64_t J = f.join_cap;
+    AggSet as{};
+    as.n = f.n_agg;
+    as.sk = -1;
+    for (int k = 0; k < f.n_agg; ++k) {
+        as.val[k] = f.aggs[k].op == TQP_AGG_COUNT ? nullptr : b.vals[k];
+        as.out[k] = f.aggs[k].out;
+        as.op[k] = f.aggs[k].op;
+    }
+    // an empty side joins nothing and no value column was evaluated: the
+    // blocks see no rows (the join count is 0), so no value is read
+    const int nslot = (f.n_agg + 1) << b.gbits;
+    const size_t lds = (size_t)nslot * sizeof(uint64_t);
+    TQP_LAUNCH(ctx, s, "fragment_direct",
+               k_gf_direct<<<(unsigned)b.dparts, GF_DIRECT_BLOCK, lds, s>>>(b.gkey, as, J, b.d_join, b.gbits,
+                                                                          b.dpart));
+    TQP_LAUNCH(ctx, s, "fragment_direct_reduce",
+               k_gf_direct_reduce<<<(unsigned)nslot, WAVE, 0, s>>>(b.dpart, (int)b.dparts, as, b.gbits, b.dred));
+    TQP_LAUNCH(ctx, s, "fragment_direct_out",
+               k_gf_direct_out<<<1, 1 << GF_DIRECT_MAX_BITS, 0, s>>>(b.dred, as, b.gbits, o.key, o.gcap,
+                                                                    o.d_ngroups, b.d_written, ctx->d_err));
+    if (f.topk > 0) {
+        const int64_t* v0 = static_cast<const int64_t*>(f.aggs[0].out);
+        return topk_launch(b.topk, o.key, v0, v0, b.d_written, f.topk, o.top_key, o.top_val, b.tcnt, o.d_topk, s,
+                           ctx);
+    }
+    return TQP_OK;
+}
+
 template <class Cfg>
 tqp_status gen_launch(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_out& o, const GenBufs<Cfg>& b,
                       hipStream_t s) {
@@ -947,6 +1085,7 @@ tqp_status gen_launch(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_ou
                                "tqp_fragment_run", "fragment_value")) != TQP_OK)
             return st;
     }
+    if (b.direct) return direct_groupby(ctx, f, o, b, s);
     // 5. group sort (distinct values first, low word then high word)
     const uint32_t* perm_in = nullptr;
     if (b.distinct >= 0) {

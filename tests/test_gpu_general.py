@@ -207,6 +207,48 @@ def test_general_value32(hip, ctx, op):
         assert ctx.errors() == hip.DEVERR_VALUE_RANGE
 
 
+@pytest.mark.parametrize("trial", range(6))
+def test_general_direct(hip, ctx, trial):
+    """Descriptors that take the direct group-by (packed keys of at most 9 bits, no COUNT(DISTINCT)):
+    every aggregate, MIN / MAX over values of both signs up to 2^52, several valued
+    aggregates, with and without a join, a top-k; fewer group slots than groups (capacity flag,
+    the first gcap groups exact); equal to the oracle's general fragment."""
+    O = oracle
+    rng = np.random.default_rng(9600 + trial)
+    n = [60_001, 250_003, 4097][trial % 3]
+    fact, dim = _tables(rng, n, 20_011, 20_011, trial % 2 == 0)
+    ext = np.array([-(1 << 52), 1 << 52, -1, 0, 1], np.int64)      # large, and the oracle's sums stay exact
+    fact.append(np.where(rng.random(n) < 0.01, rng.choice(ext, n), fact[2]).astype(np.int64))
+    nf = len(fact)
+    join = trial % 3 != 2
+    group = [[(3, 2), (nf + 1, 3)], [(4, 9)], [(3, 2)], [(nf + 1, 3), (3, 2), (3, 1)], [], [(1, 5)]][trial]
+    if not join:
+        group = [g for g in group if g[0] < nf]
+    ops = [O.AGG_SUM, O.AGG_COUNT, O.AGG_MIN, O.AGG_MAX, O.AGG_AVG]
+    src = {O.AGG_SUM: 2, O.AGG_MIN: 5, O.AGG_MAX: 5, O.AGG_AVG: 1}      # column 5: values of +-2^52 mixed in
+    aggs = [(op, [] if op == O.AGG_COUNT else [(O.X_COL, src[op])]) for op in ops]
+    if trial % 2:
+        aggs = aggs[1:] + aggs[:1]
+    topk = [0, 5, 100][trial % 3] if aggs[0][0] != O.AGG_AVG else 0
+    fp = pins._pred_expr(rng, fact)[0] if trial % 2 else []
+    want = O.fragment_general(fact, dim if join else None, fp, [], 0, 0, group, aggs, topk=topk, gcap=1 << 20)
+    kw = dict(topk=topk, key_bits=15, join_cap=max(1, want["join_rows"]), gcap=max(1, want["groups"]))
+    got = hip.fragment_run(ctx, [_dev(c) for c in fact], [_dev(c) for c in dim] if join else None, fp, [],
+                           0 if join else -1, 0, group, aggs, **kw)
+    assert ctx.errors() == (hip.DEVERR_KEY_RANGE if want["bad"] else 0)
+    _check(got, want, topk)
+    if want["groups"] > 3:
+        cap = want["groups"] // 2
+        kw["gcap"] = cap
+        got = hip.fragment_run(ctx, [_dev(c) for c in fact], [_dev(c) for c in dim] if join else None, fp, [],
+                               0 if join else -1, 0, group, aggs, **kw)
+        assert ctx.errors() & hip.DEVERR_CAPACITY
+        assert int(_np(got["d_ngroups"])[0]) == want["groups"]
+        assert np.array_equal(_np(got["key"], cap), want["key"][:cap])
+        for g, w in zip(got["vals"], want["vals"]):
+            assert np.array_equal(_np(g, cap).view(np.int64), np.asarray(w)[:cap].view(np.int64))
+
+
 def test_general_bucket_capacity_and_empty(hip, ctx):
     """The bucket group-by with fewer group slots than groups (capacity flag, the true group count,
     the first gcap groups exact, top-k over the written groups as the oracle's) and with no joined
