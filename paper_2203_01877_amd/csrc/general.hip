@@ -64,6 +64,7 @@ constexpr int GF_BUCKET_MIN_BITS = 16;
 constexpr int GF_DIRECT_MAX_BITS = 9;
 constexpr int GF_DIRECT_BLOCK = 256;
 constexpr int GF_DIRECT_PARTS = 256;    // its blocks (each writes one part of the slots)
+constexpr int64_t GF_LORDER_MIN_BYTES = int64_t(256) << 20;   // MI355X's infinity cache
 
 // Sort source: the int32 key column with the row id as payload, rows whose
 // keep byte is zero left out (keep null: every row).
@@ -567,6 +568,11 @@ struct GenBufs {
     uint64_t* bstatus = nullptr;
     uint32_t* bcounter = nullptr;
     int64_t *bval = nullptr, *bcnt = nullptr;   // per group: the value's reduction, the row count
+    bool reads_fact = false;                 // group columns or value programs read fact columns after the join
+    int fact_row_bytes = 0;                  // their bytes per fact row
+    bool lorder = false;                     // the joined rows put in fact-row order before the gathers
+    RadixBufs<Cfg, uint32_t> lsort;
+    int32_t *li2 = nullptr, *ri2 = nullptr;
     bool direct = false;                     // the direct group-by (few keys)
     int64_t dparts = 0;                      // its blocks, one part each
     uint64_t *dpart = nullptr, *dred = nullptr;
@@ -652,6 +658,23 @@ void gen_reserve(Arena& a, const tqp_fragment& f, const tqp_fragment_out& o, Gen
         b.fpush = b.vsort >= 0 && prog_f && !prog_d && !group_f && !divides;
         // the dim rows serve only one int32 group column
         if (group_d && gd_one && !prog_d && f.dim_cols[gd - f.n_fact_cols].type == TQP_I32) b.dpush = gd - f.n_fact_cols;
+        // bytes of the fact columns read through the pairs (per fact row)
+        {
+            uint64_t seen = 0;
+            auto mark = [&](int c) {
+                if (c < f.n_fact_cols && !((seen >> c) & 1)) {
+                    seen |= uint64_t(1) << c;
+                    const int t = f.fact_cols[c].type;
+                    b.fact_row_bytes += t == TQP_I64 ? 8 : t == TQP_I32 ? 4 : 1;
+                }
+            };
+            for (int i = 0; i < f.n_group; ++i) mark(f.group[i].col);
+            for (int k = 0; k < f.n_agg; ++k)
+                if (f.aggs[k].op != TQP_AGG_COUNT)
+                    for (int i = 0; i < f.aggs[k].nprog; ++i)
+                        if (f.aggs[k].prog[i].op == TQP_X_COL) mark((int)f.aggs[k].prog[i].arg);
+        }
+        b.reads_fact = group_f || prog_f;
         b.kv = b.bucket && b.fpush && b.dpush >= 0 && f.n_group == 1;
         b.v32 = b.kv && f.value_bits == 32;
     }
@@ -710,6 +733,21 @@ void gen_reserve(Arena& a, const tqp_fragment& f, const tqp_fragment_out& o, Gen
     }
     if (!b.fpush) b.li = a.scratch<int32_t>(J);
     b.d_join = a.zero<int64_t>(1);
+    // No result depends on the joined rows' order (groups come in key order,
+    // every aggregate is order-free).  With fact columns read through the
+    // pairs, sorting the pairs by fact row turns those reads from random into
+    // one forward sweep; the top 16 bits of the row suffice (two passes):
+    // rows then come in runs of nearby rows, which the caches serve.  Worth
+    // it when those columns outgrow the chip's last-level cache (random
+    // reads of a table that fits it are served there).
+    if (b.join && !b.fpush && b.reads_fact && N * b.fact_row_bytes > GF_LORDER_MIN_BYTES) {
+        int rb = 1;
+        while (rb < 31 && (int64_t(1) << rb) < N) ++rb;
+        b.lorder = true;
+        b.lsort = radix_reserve<Cfg, uint32_t>(a, J, rb, rb > 16 ? rb - 16 : 0);
+        b.li2 = a.scratch<int32_t>(J);
+        b.ri2 = a.scratch<int32_t>(J);
+    }
     if (!b.kv) b.gkey = a.scratch<uint32_t>(J);
     for (int k = 0; k < f.n_agg; ++k)
         if (f.aggs[k].op != TQP_AGG_COUNT) b.vals[k] = b.fpush && k == b.vsort ? b.jval : a.scratch<int64_t>(J);
@@ -1041,16 +1079,28 @@ tqp_status gen_launch(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_ou
                        fp, N, nullptr, b.li, nullptr, J, b.d_join, b.fstatus, b.fcounter, ctx->d_err)));
     }
     if (o.d_join) TQP_TRY_HIP(hipMemcpyAsync(o.d_join, b.d_join, 8, hipMemcpyDeviceToDevice, s));
+    int32_t* li = b.li;
+    int32_t* ri = b.ri;
+    if (b.lorder) {
+        SrcPairs<uint32_t> lp{reinterpret_cast<const uint32_t*>(b.li), reinterpret_cast<const uint32_t*>(b.ri), J,
+                              b.d_join};
+        if ((st = radix_launch<Cfg, uint32_t>(b.lsort, lp, J, true, nullptr, 0xFFFFFFFFu,
+                                              reinterpret_cast<uint32_t*>(b.li2), reinterpret_cast<uint32_t*>(b.ri2),
+                                              ctx, s, "fragment_sort_rows", "fragment_sort_rows")) != TQP_OK)
+            return st;
+        li = b.li2;
+        ri = b.ri2;
+    }
     // the joined rows' columns: fact columns through li, dim columns through ri
     JoinedCols jc;
     for (int c = 0; c < f.n_fact_cols; ++c) {
         jc.col[jc.n] = f.fact_cols[c];
-        jc.idx[jc.n++] = b.li;
+        jc.idx[jc.n++] = li;
     }
     if (b.join)
         for (int c = 0; c < f.n_dim_cols; ++c) {
             jc.col[jc.n] = f.dim_cols[c];
-            jc.idx[jc.n++] = b.ri;
+            jc.idx[jc.n++] = ri;
         }
     // 3. group key
     GroupCols g{};
@@ -1062,7 +1112,7 @@ tqp_status gen_launch(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_ou
         g.side[i] = c >= f.n_fact_cols ? 1 : 0;
         if (b.dpush >= 0 && c >= f.n_fact_cols) {
             // the dim sort carried this column: the join wrote its values where the rows would be
-            g.col[i] = b.ri;
+            g.col[i] = ri;
             g.type[i] = TQP_I32;
             g.side[i] = 2;
         }
@@ -1074,7 +1124,7 @@ tqp_status gen_launch(tqp_ctx* ctx, const tqp_fragment& f, const tqp_fragment_ou
     if (!direct_key) {
         TQP_LAUNCH(ctx, s, "fragment_pack",
                    k_gf_pack<<<grid_for(J, 256 * 4, (int64_t)ctx->num_cus * 8), 256, 0, s>>>(
-                       g, b.li, b.ri, J, b.d_join, b.gkey, ctx->d_err));
+                       g, li, ri, J, b.d_join, b.gkey, ctx->d_err));
     }
     // 4. aggregate values (an empty side joins nothing: no row is read, and
     // its columns may be null)

@@ -249,6 +249,28 @@ def test_general_direct(hip, ctx, trial):
             assert np.array_equal(_np(g, cap).view(np.int64), np.asarray(w)[:cap].view(np.int64))
 
 
+def test_general_fact_order(hip, ctx):
+    """A flags-style descriptor over 16M fact rows whose columns read through the pairs (flags,
+    price, disc: 18 B a row, 288 MB) outgrow the last-level cache, so the joined pairs are first
+    sorted by fact row; every aggregate, equal to the oracle's general fragment."""
+    O = oracle
+    fact = datagen.fact_table(4242, 16_000_000, 400_000)
+    dim = datagen.dim_table(4242, 400_000)
+    fc = [fact[k] for k in ("fk", "date", "price", "disc", "flagA", "flagB")]
+    dc = [dim["pk"], dim["seg"]]
+    rev = [(O.X_COL, 2), (O.X_CONST, 100), (O.X_COL, 3), (O.X_SUB, 0), (O.X_MUL, 0)]
+    aggs = [(O.AGG_SUM, rev), (O.AGG_COUNT, []), (O.AGG_AVG, [(O.X_COL, 2)]), (O.AGG_MIN, [(O.X_COL, 3)]),
+            (O.AGG_MAX, [(O.X_COL, 2)])]
+    fp = [(O.X_COL, 1), (O.X_CONST, 2400), (O.X_LT, 0)]
+    dp = [(O.X_COL, 1), (O.X_CONST, 1), (O.X_EQ, 0)]
+    group = [(4, 2), (5, 1)]
+    want = O.fragment_general(fc, dc, fp, dp, 0, 0, group, aggs, topk=3, gcap=8)
+    got = hip.fragment_run(ctx, [_dev(c) for c in fc], [_dev(c) for c in dc], fp, dp, 0, 0, group, aggs, topk=3,
+                           key_bits=datagen.bits_for(400_000), gcap=8)
+    assert ctx.errors() == 0
+    _check(got, want, 3)
+
+
 def test_general_bucket_capacity_and_empty(hip, ctx):
     """The bucket group-by with fewer group slots than groups (capacity flag, the true group count,
     the first gcap groups exact, top-k over the written groups as the oracle's) and with no joined
