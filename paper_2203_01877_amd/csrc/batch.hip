@@ -33,6 +33,7 @@ struct BatchSeg {
 
 struct BatchFrag {
     int32_t fseg, dseg;
+    int32_t lowb;              // fact key bits the fact sort leaves to the join tiles
     const int64_t* price;
     const int64_t* disc;
     const int8_t* flagA;
@@ -201,9 +202,13 @@ __global__ void k_batch_windows(const BatchSeg* segs, const BatchFrag* frags, in
     const uint32_t* lk = L.bk[(L.npass - 1) & 1];
     const uint32_t* rk = R.bk[(R.npass - 1) & 1];
     const int64_t i1 = (t * tile_size + tile_size < nl ? t * tile_size + tile_size : nl) - 1;
-    const int64_t lo = lower_bound_glb(rk, 0, nr, lk[t * tile_size]);
+    // the tile's keys are sorted on their bits above lowb: its key range runs
+    // from its first key's bucket to the end of its last key's
+    uint32_t kmin, kmax;
+    tile_key_range(TileGeo{0, 0, lk[t * tile_size], lk[i1]}, fr.lowb, kmin, kmax);
+    const int64_t lo = lower_bound_glb(rk, 0, nr, kmin);
     fr.win[2 * t] = lo;
-    fr.win[2 * t + 1] = upper_bound_glb(rk, lo, nr, lk[i1]);
+    fr.win[2 * t + 1] = upper_bound_glb(rk, lo, nr, kmax);
 }
 
 // Join + gather + per-fragment aggregation; work item = (fragment, left tile).
@@ -243,7 +248,7 @@ k_batch_join(const BatchSeg* segs, const BatchFrag* frags, int nfrag, const int6
             join_tile<Cfg, uint32_t, uint32_t, Emit>(lk, L.bv[(L.npass - 1) & 1], nl, R.bk[(R.npass - 1) & 1],
                                                      (const uint32_t*)nullptr,
                                                      tile_geo(lk, nl, fr.win, tile, Cfg::TILE), tile, 0, fr.d_join,
-                                                     e, esm, sm);
+                                                     e, esm, sm, fr.lowb);
             e.flush(esm, fr.acc);
         }
         __syncthreads();
@@ -356,8 +361,15 @@ void plan_candidate(tqp_batch* b, int c, char* base, size_t& off, size_t scratch
     for (int f = 0; f < F; ++f) {
         const tqp_flags_fragment& fr = b->frags[f];
         const int kb = norm_key_bits(fr.key_bits);
-        const PassDesc pd = make_passes(kb, Cfg::RADIX_BITS);
+        // the fact sort covers the key bits above lowb (the join tiles resolve
+        // the rest in LDS; at least one pass stays, which also compacts the
+        // kept rows), the dim sort all of them
+        int lowb = join_low_bits(fr.n_fact, kb, Cfg::RADIX_BITS, BJCfg::TILE, BJCfg::RWIN);
+        lowb = lowb < kb - 1 ? lowb : kb - 1;
+        PassDesc pds[2] = {make_passes(kb - lowb, Cfg::RADIX_BITS), make_passes(kb, Cfg::RADIX_BITS)};
+        for (int q = 0; q < pds[0].npass; ++q) pds[0].shift[q] += lowb;
         for (int side = 0; side < 2; ++side) {
+            const PassDesc& pd = pds[side];
             BatchSeg& sg = ht.segs[2 * f + side];
             sg.key = side == 0 ? fr.fk + fr.row0 : fr.pk;
             sg.fcol = side == 0 ? (const void*)(fr.date + fr.row0) : (const void*)fr.seg;
@@ -381,6 +393,7 @@ void plan_candidate(tqp_batch* b, int c, char* base, size_t& off, size_t scratch
         BatchFrag& bf = ht.frags[f];
         bf.fseg = 2 * f;
         bf.dseg = 2 * f + 1;
+        bf.lowb = lowb;
         bf.price = fr.price;
         bf.disc = fr.disc;
         bf.flagA = fr.flagA;

@@ -61,7 +61,12 @@ __global__ void k_flags_finalize(const int64_t* acc, const int64_t* d_join_in, t
 template <class Cfg>
 void flags_reserve(Arena& a, const tqp_flags_fragment& f, FlagsBufs<Cfg>& b) {
     const int kb = norm_key_bits(f.key_bits);
-    b.fact = radix_reserve<Cfg, uint32_t>(a, f.n_fact, kb);
+    // the fact sort covers the key bits above lowb (the join tiles resolve
+    // the rest in LDS; at least one pass stays, which also drops the filtered
+    // rows), the dim sort all of them
+    b.lowb = join_low_bits(f.n_fact, kb, Cfg::RADIX_BITS, JCfgFrag::TILE, JCfgFrag::RWIN);
+    b.lowb = b.lowb < kb - 1 ? b.lowb : kb - 1;
+    b.fact = radix_reserve<Cfg, uint32_t>(a, f.n_fact, kb, b.lowb);
     b.dim = radix_reserve<Cfg, uint32_t>(a, f.n_dim, kb);
     b.join = join_reserve<JCfgFrag>(a, f.n_fact);
     b.d_join = a.zero<int64_t>(1);
@@ -98,7 +103,7 @@ tqp_status flags_launch(tqp_ctx* ctx, const tqp_flags_fragment& f, const tqp_fla
     e.flags = ctx->d_err;
     if ((st = join_launch<JCfgFrag, uint32_t, uint32_t>(ctx, s, "join_flags_agg", b.join, b.fkeys, b.fvals, f.n_fact,
                                                         b.fact.d_cnt, b.dkeys, (const uint32_t*)nullptr, f.n_dim,
-                                                        b.dim.d_cnt, b.d_join, INT64_MAX, e)) != TQP_OK)
+                                                        b.dim.d_cnt, b.d_join, INT64_MAX, e, b.lowb)) != TQP_OK)
         return st;
     TQP_LAUNCH(ctx, s, "flags_finalize", k_flags_finalize<<<1, 64, 0, s>>>(b.acc, b.d_join, o));
     return TQP_OK;

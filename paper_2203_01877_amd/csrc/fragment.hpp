@@ -81,6 +81,7 @@ tqp_status join_launch(tqp_ctx* ctx, hipStream_t s, const char* name, const Join
 template <class Cfg>
 struct FlagsBufs {
     RadixBufs<Cfg, uint32_t> fact, dim;
+    int lowb = 0;              // fact key bits the fact sort leaves to the join tiles
     JoinBufs join;
     int64_t* d_join = nullptr;
     int64_t* acc = nullptr;
