@@ -271,6 +271,28 @@ def test_general_fact_order(hip, ctx):
     _check(got, want, 3)
 
 
+@pytest.mark.parametrize("n,m", [(0, 1000), (1000, 0), (1, 1)])
+def test_general_keyed_empty(hip, ctx, n, m):
+    """The keyed bucket group-by and the direct group-by with an empty or one-row side: no joined
+    rows and no groups (or the single match), with and without a top-k."""
+    O = oracle
+    rng = np.random.default_rng(n + 7 * m)
+    fact, dim = _tables(rng, n, max(m, 1), 5, False)
+    dim = [c[:m] for c in dim]
+    dim[2] = rng.integers(0, 1 << 18, m).astype(np.int32)
+    if n and m:
+        dim[0][:] = fact[0][0]                     # the one row matches
+    nf = len(fact)
+    for group, aggs, vb in (([(nf + 2, 18)], [(O.AGG_SUM, [(O.X_COL, 2)]), (O.AGG_COUNT, [])], 32),
+                            ([(3, 2)], [(O.AGG_SUM, [(O.X_COL, 2)]), (O.AGG_MAX, [(O.X_COL, 1)])], 0)):
+        for topk in (0, 5):
+            want = O.fragment_general(fact, dim, [], [], 0, 0, group, aggs, topk=topk, gcap=4)
+            got = hip.fragment_run(ctx, [_dev(c) for c in fact], [_dev(c) for c in dim], [], [], 0, 0, group, aggs,
+                                   topk=topk, key_bits=10, gcap=4, value_bits=vb)
+            assert ctx.errors() == 0
+            _check(got, want, topk)
+
+
 def test_general_bucket_capacity_and_empty(hip, ctx):
     """The bucket group-by with fewer group slots than groups (capacity flag, the true group count,
     the first gcap groups exact, top-k over the written groups as the oracle's) and with no joined
