@@ -18,6 +18,7 @@ int bucket_low_bits(int cb, int rb) {
     return lowb;
 }
 constexpr int BUCKET_SMALL_LOWB = 9;
+constexpr int64_t FLAGS_SIDE_MIN_DIM = 32768;   // dim rows from which the flags fragment's dim sort forks
 // profile tags of the custkey fragment's three sorts
 constexpr int SORT_TAG_FACT = 1, SORT_TAG_MID = 2, SORT_TAG_GROUP = 3;
 
@@ -83,16 +84,22 @@ tqp_status flags_launch(tqp_ctx* ctx, const tqp_flags_fragment& f, const tqp_fla
     const int kb = norm_key_bits(f.key_bits);
     const uint32_t mask = key_mask_for(kb);
     tqp_status st;
+    // dim side (seg == c fused into the sort, payload = dim row id) on the
+    // side stream beside the fact side when it is big enough for the overlap
+    // to outweigh the two stream events
+    const bool fork = f.n_dim >= FLAGS_SIDE_MIN_DIM;
+    const hipStream_t sd = fork ? ctx->side : s;
+    if (fork && (st = side_fork(ctx, s)) != TQP_OK) return st;
+    SrcFilterRowid<int8_t> dsrc{f.pk, f.seg, CMP_EQ, f.c, f.n_dim, 0};
+    if ((st = radix_launch<Cfg, uint32_t>(b.dim, dsrc, f.n_dim, true, nullptr, mask, b.dkeys, b.dvals, ctx, sd)) !=
+        TQP_OK)
+        return st;
     // fact side: date < D fused into the sort, payload = global fact row id
     SrcFilterRowid<int32_t> fsrc{f.fk + f.row0, f.date + f.row0, CMP_LT, f.D, f.n_fact, f.row0};
     if ((st = radix_launch<Cfg, uint32_t>(b.fact, fsrc, f.n_fact, true, nullptr, mask, b.fkeys, b.fvals, ctx,
                                           s)) != TQP_OK)
         return st;
-    // dim side: seg == c fused into the sort, payload = dim row id
-    SrcFilterRowid<int8_t> dsrc{f.pk, f.seg, CMP_EQ, f.c, f.n_dim, 0};
-    if ((st = radix_launch<Cfg, uint32_t>(b.dim, dsrc, f.n_dim, true, nullptr, mask, b.dkeys, b.dvals, ctx,
-                                          s)) != TQP_OK)
-        return st;
+    if (fork && (st = side_join(ctx, s)) != TQP_OK) return st;
     // join + gather + direct aggregation over the six packed groups
     EmitFlagsAgg<JCfgFrag::BLOCK> e{};
     e.price = f.price;
