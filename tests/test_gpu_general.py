@@ -293,6 +293,34 @@ def test_general_keyed_empty(hip, ctx, n, m):
             _check(got, want, topk)
 
 
+@pytest.mark.parametrize("digit_bits", [4, 11])
+def test_general_digit_widths(hip, ctx, digit_bits):
+    """The plan rules under 4- and 11-bit radix digits (other pass counts, bucket widths and join
+    low bits): the keyed bucket group-by (32-bit value), the bucket group-by through the pairs,
+    the direct group-by and the fact-sorted pairs, each equal to the oracle."""
+    O = oracle
+    rng = np.random.default_rng(9700 + digit_bits)
+    fact, dim = _tables(rng, 250_003, 20_011, 25_000, False)
+    dim[2] = rng.integers(0, 1 << 19, len(dim[2])).astype(np.int32)
+    nf = len(fact)
+    cases = [([(nf + 2, 19)], [(O.AGG_SUM, [(O.X_COL, 2), (O.X_COL, 1), (O.X_MUL, 0)]), (O.AGG_COUNT, [])], 10, 32),
+             ([(nf + 1, 3), (nf + 2, 19)], [(O.AGG_MAX, [(O.X_COL, 2), (O.X_COL, nf + 1), (O.X_ADD, 0)])], 5, 0),
+             ([(3, 2), (nf + 1, 3)], [(O.AGG_SUM, [(O.X_COL, 2)]), (O.AGG_MIN, [(O.X_COL, 1)]), (O.AGG_COUNT, [])], 3, 0)]
+    ctx.set_digit_bits(digit_bits)
+    try:
+        for group, aggs, topk, vb in cases:
+            want = O.fragment_general(fact, dim, [(O.X_COL, 4), (O.X_CONST, 2000), (O.X_LT, 0)], [], 0, 0, group, aggs,
+                                      topk=topk, gcap=1 << 20)
+            got = hip.fragment_run(ctx, [_dev(c) for c in fact], [_dev(c) for c in dim],
+                                   [(O.X_COL, 4), (O.X_CONST, 2000), (O.X_LT, 0)], [], 0, 0, group, aggs, topk=topk,
+                                   key_bits=15, join_cap=max(1, want["join_rows"]), gcap=max(1, want["groups"]),
+                                   value_bits=vb)
+            assert ctx.errors() == 0
+            _check(got, want, topk)
+    finally:
+        ctx.set_digit_bits(8)
+
+
 def test_general_bucket_capacity_and_empty(hip, ctx):
     """The bucket group-by with fewer group slots than groups (capacity flag, the true group count,
     the first gcap groups exact, top-k over the written groups as the oracle's) and with no joined
