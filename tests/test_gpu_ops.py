@@ -480,6 +480,28 @@ def test_join_chain_dense_edges(hip, ctx):
     assert ctx.errors() == 0
 
 
+@pytest.mark.parametrize("digit_bits", [4, 11])
+def test_join_chain_digit_widths(hip, ctx, digit_bits):
+    """A three-join chain (a dense hop, a sorted one, a shuffled one) under 4- and 11-bit radix
+    digits, where the left sorts leave other low-bit widths to the join tiles; against the oracle."""
+    rng = _rng(97 + digit_bits)
+    outs = [rng.integers(0, 60_000, 400_000).astype(np.int32), rng.integers(0, 9000, 50_000).astype(np.int32),
+            rng.integers(0, 700, 9000).astype(np.int32)]
+    pks = [np.arange(50_000, dtype=np.int32), np.sort(rng.integers(0, 9000, 9000)).astype(np.int32),
+           rng.permutation(700).astype(np.int32)]
+    want = oracle.join_chain(outs, pks)
+    ctx.set_digit_bits(digit_bits)
+    try:
+        cols, J = hip.join_chain(ctx, [_dev(o) for o in outs], [_dev(p) for p in pks], pk_dense=[True, False, False],
+                                 pk_sorted=[True, True, False])
+    finally:
+        ctx.set_digit_bits(8)
+    assert J == len(want) > 0
+    got = np.stack([_np(c, J) for c in cols], axis=1)
+    assert np.array_equal(_lex(got), _lex(want))
+    assert ctx.errors() == 0
+
+
 @pytest.mark.parametrize("rules", ["none", "mixed"])
 def test_join_chain_six_hops(hip, ctx, rules):
     """Six joins over seven tables (the shape of Section 6.3's six-join query) in one launch
