@@ -9,6 +9,11 @@
 
 namespace tqp {
 
+// The sort-based group-by's bucket form: keys of at least this many bits,
+// and buckets of this many rows on average (or at most 256 buckets).
+constexpr int GB_BUCKET_MIN_BITS = 16;
+constexpr int64_t GB_BUCKET_MIN_ROWS = 2048;
+
 using JCfg = JoinCfg<256, 8, 4096>;
 using SCfg = SegCfg<256, 16>;
 constexpr int FILTER_BLOCK = 256, FILTER_ITEMS = 16;
@@ -237,6 +242,55 @@ tqp_status tqp_groupby_agg(tqp_ctx* ctx, const int32_t* gkey, int64_t n, const i
     const int kb = norm_key_bits(key_bits);
     const uint32_t mask = key_mask_for(kb);
     if (!avg_in) {
+        // Wide keys over many rows: Algorithm 2 with the last key bits
+        // resolved in LDS (as the custkey fragment's group-by): the sort
+        // covers the key bits above lowb, and one block per bucket of 2^lowb
+        // keys sums and counts its rows in LDS and writes its groups in key
+        // order.  Taken when the buckets hold enough rows to fill a block.
+        const bool bucket = n > 0 && kb >= GB_BUCKET_MIN_BITS && [&] {
+            const int lowb = bucket_low_bits(kb, ctx->digit_bits == 4 ? 4 : ctx->digit_bits == 11 ? 11 : 8);
+            const int64_t nb = int64_t(1) << (kb - lowb);
+            return nb <= 256 || nb * GB_BUCKET_MIN_ROWS <= n;
+        }();
+        if (bucket)
+            return with_radix_cfg(ctx->digit_bits, [&](auto cfg) -> tqp_status {
+                using Cfg = decltype(cfg);
+                const int lowb = bucket_low_bits(kb, Cfg::RADIX_BITS);
+                const int64_t nb = int64_t(1) << (kb - lowb);
+                RadixBufs<Cfg, uint64_t> b;
+                uint32_t* skeys = nullptr;
+                uint64_t* svals = nullptr;
+                int64_t* bstarts = nullptr;
+                uint64_t* bstatus = nullptr;
+                uint32_t* bcounter = nullptr;
+                Arena a;
+                auto plan = [&](Arena& ar) {
+                    b = radix_reserve<Cfg, uint64_t>(ar, n, kb, lowb);
+                    bstatus = ar.zero<uint64_t>(nb);
+                    bcounter = ar.zero<uint32_t>(1);
+                    bstarts = ar.scratch<int64_t>(nb + 1);
+                    skeys = ar.scratch<uint32_t>(n);
+                    svals = ar.scratch<uint64_t>(n);
+                };
+                tqp_status st = with_workspace(ctx, ws, ws_bytes, stream, plan, a);
+                if (st != TQP_OK || !ws) return st;
+                if ((st = fill_zero(a.base, a.zsize, stream, ctx)) != TQP_OK) return st;
+                SrcPairs<uint64_t> src{reinterpret_cast<const uint32_t*>(gkey),
+                                       reinterpret_cast<const uint64_t*>(sum_in), n, d_n};
+                st = radix_launch<Cfg, uint64_t>(b, src, n, true, nullptr, mask, skeys, svals, ctx, stream);
+                if (st != TQP_OK) return st;
+                const uint32_t* bhist = b.pd.npass == 1 ? b.hist : nullptr;
+                if (!bhist)
+                    TQP_LAUNCH(ctx, stream, "groupby_bucket_bounds",
+                               k_bucket_bounds<<<grid_for(nb + 1, 256, 0), 256, 0, stream>>>(skeys, n, b.d_cnt, lowb, nb,
+                                                                                            bstarts));
+                SegOut o{out_key, out_sum, out_cnt, nullptr, gcap, d_ngroups};
+                TQP_LAUNCH(ctx, stream, "groupby_bucket_agg",
+                           (k_bucket_agg<1024, 1 << BUCKET_LOWB_MAX, int64_t><<<(unsigned)nb, 1024, 0, stream>>>(
+                               skeys, reinterpret_cast<const int64_t*>(svals), bstarts, bhist, lowb, nb, bstatus,
+                               bcounter, o, ctx->d_err)));
+                return TQP_OK;
+            });
         // One value column: sort it alongside the keys (8-byte payload), so
         // the run reduction reads the values in order instead of gathering
         // them through the permutation.

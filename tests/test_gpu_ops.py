@@ -645,6 +645,34 @@ def test_groupby_sum_only(hip, ctx, n, domain, digit_bits):
     assert ctx.errors() == 0
 
 
+@pytest.mark.parametrize("digit_bits", [4, 8, 11])
+@pytest.mark.parametrize("n,domain", [(5_000_003, 1 << 24), (2_000_000, 1 << 17)])
+def test_groupby_bucket(hip, ctx, n, domain, digit_bits):
+    """The sort-based group-by's bucket form (wide keys over many rows: the sort covers the key
+    bits above the bucket, one or two passes, and each bucket of keys is summed and counted in LDS),
+    a device row count below the host bound, and fewer group slots than groups (capacity flag, the
+    first gcap groups exact)."""
+    rng = _rng(n + digit_bits)
+    keys = rng.integers(0, domain, n).astype(np.int32)
+    val = rng.integers(-(1 << 40), 1 << 40, n).astype(np.int64)
+    dn = n - 12345
+    wk, ws, wc, _ = oracle.groupby(keys[:dn], val[:dn])
+    kb = int(domain - 1).bit_length()
+    ctx.set_digit_bits(digit_bits)
+    try:
+        out = hip.groupby_agg(ctx, _dev(keys), _dev(val), key_bits=kb, gcap=len(wk), d_n=_dev(np.array([dn], np.int64)))
+        G = int(_np(out["d_ngroups"])[0])
+        assert G == len(wk) and ctx.errors() == 0
+        assert np.array_equal(_np(out["key"], G), wk)
+        assert np.array_equal(_np(out["sum"], G), ws) and np.array_equal(_np(out["cnt"], G), wc)
+        cap = len(wk) // 3
+        out = hip.groupby_agg(ctx, _dev(keys), _dev(val), key_bits=kb, gcap=cap, d_n=_dev(np.array([dn], np.int64)))
+        assert int(_np(out["d_ngroups"])[0]) == len(wk) and ctx.errors() == hip.DEVERR_CAPACITY
+        assert np.array_equal(_np(out["key"], cap), wk[:cap]) and np.array_equal(_np(out["sum"], cap), ws[:cap])
+    finally:
+        ctx.set_digit_bits(8)
+
+
 def _hash_groupby_case(hip, ctx, keys, val, dval, gcap=None, d_n=None):
     """Hash group-by with every aggregate against the oracle's group-by and
     min / max / count distinct.  The hash output has no fixed order: it is
