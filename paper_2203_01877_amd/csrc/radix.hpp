@@ -334,15 +334,22 @@ __global__ void __launch_bounds__(Cfg::BLOCK)
 k_radix_hist_tiles(Src src, PassDesc pd, uint32_t key_mask, uint32_t* hist, int64_t* d_count,
                    uint32_t* flags, uint32_t* pre, uint32_t* ctot, int tpc, int64_t ntiles_cap) {
     constexpr int R = Cfg::RADIX, ITEMS = Cfg::ITEMS, TILE = Cfg::TILE;
-    // h[0, R): the current tile's first-pass counts; h[R, npass*R): later
-    // passes' counts over the chunk
+    // h[0, R): the chunk's first-pass counts so far; h[R, npass*R): later
+    // passes' counts over the chunk.  The counters only grow: a tile's
+    // counts are the difference of two readings.  (Clearing them between
+    // tiles raced with the next tile's increments: the back edge of the tile
+    // loop reached its barrier with the clearing stores still in flight, and
+    // another wave's increments could land first and be erased.)
     __shared__ uint32_t h[Cfg::MAX_PASSES * R];
-    __shared__ uint32_t run[R];
     __shared__ uint32_t s_cnt;
     __shared__ uint32_t s_bad;
+    constexpr int PER = (R + Cfg::BLOCK - 1) / Cfg::BLOCK;   // digits per thread
+    uint32_t run[PER];                    // digit tid + q * BLOCK: the chunk's count before the tile
+#pragma unroll
+    for (int q = 0; q < PER; ++q) run[q] = 0;
     for (int i = threadIdx.x; i < pd.npass * R; i += Cfg::BLOCK) h[i] = 0;
-    for (int i = threadIdx.x; i < R; i += Cfg::BLOCK) run[i] = 0;
     if (threadIdx.x == 0) { s_cnt = 0; s_bad = 0; }
+    __syncthreads();
     const int64_t n = src.size();
     int64_t ntiles = (n + TILE - 1) / TILE;
     if (ntiles > ntiles_cap) ntiles = ntiles_cap;          // the tiles pre holds
@@ -365,7 +372,7 @@ k_radix_hist_tiles(Src src, PassDesc pd, uint32_t key_mask, uint32_t* hist, int6
     if (t0 < t1) load(t0, kc, oc);
     for (int64_t t = t0; t < t1; ++t) {
         if (t + 1 < t1) load(t + 1, kn, on);
-        __syncthreads();                      // the tile counters are clear
+        __syncthreads();                      // the previous tile's readings are taken
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
             if (!oc[j]) continue;
@@ -377,11 +384,18 @@ k_radix_hist_tiles(Src src, PassDesc pd, uint32_t key_mask, uint32_t* hist, int6
                 atomicAdd(&h[p * R + ((k >> pd.shift[p]) & ((1u << pd.bits[p]) - 1))], 1u);
         }
         __syncthreads();
-        for (int d = threadIdx.x; d < R; d += Cfg::BLOCK) {
-            const uint32_t c = h[d];
-            pre[t * R + d] = run[d];
-            run[d] += c;
-            h[d] = 0;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int d = threadIdx.x + q * Cfg::BLOCK;
+            if (d < R) {
+                const uint32_t c = h[d];      // through this tile
+                // taken before this thread reaches the next barrier (the
+                // compiler does not wait for LDS on the loop's back edge),
+                // so that no increment of the next tile can reach it
+                asm volatile("" : : "v"(c));
+                pre[t * R + d] = run[q];
+                run[q] = c;
+            }
         }
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) { kc[j] = kn[j]; oc[j] = on[j]; }
@@ -390,9 +404,13 @@ k_radix_hist_tiles(Src src, PassDesc pd, uint32_t key_mask, uint32_t* hist, int6
     if (lane_id() == 0 && cnt) atomicAdd(&s_cnt, cnt);
     if (bad) atomicOr(&s_bad, 1u);
     __syncthreads();
-    for (int d = threadIdx.x; d < R; d += Cfg::BLOCK) {
-        ctot[(int64_t)blockIdx.x * R + d] = run[d];
-        if (run[d]) atomic_add(&hist[d], run[d]);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int d = threadIdx.x + q * Cfg::BLOCK;
+        if (d < R) {
+            ctot[(int64_t)blockIdx.x * R + d] = run[q];
+            if (run[q]) atomic_add(&hist[d], run[q]);
+        }
     }
     for (int i = R + threadIdx.x; i < pd.npass * R; i += Cfg::BLOCK)
         if (h[i]) atomic_add(&hist[i], h[i]);

@@ -109,6 +109,25 @@ def test_sort_many_tiles_per_chunk(hip, ctx, digit_bits):
     assert ctx.errors() == 0
 
 
+def test_sort_one_first_digit(hip, ctx):
+    """16M keys whose first-pass digit is the same for every key (multiples of 256, 8-bit digits):
+    every count of the histogram kernel lands on one counter per chunk.  Regression test for the
+    histogram kernel clearing its counters between the tiles of a chunk, where the clearing store
+    could land after the next tile's first increments (lost counts shift every later chunk by a
+    wave's 64 rows).  Three calls, each against a stable sort."""
+    n = 16_000_001
+    rng = _rng(907)
+    keys = (rng.integers(0, 25, n) * 256).astype(np.int32)
+    vals = np.arange(n, dtype=np.int32)
+    order = np.argsort(keys, kind="stable")
+    wk, wv = keys[order], vals[order]
+    dk, dv = _dev(keys), _dev(vals)
+    for _ in range(3):
+        ko, vo = hip.sort(ctx, dk, dv, key_bits=13)
+        assert np.array_equal(_np(ko), wk) and np.array_equal(_np(vo), wv)
+    assert ctx.errors() == 0
+
+
 def test_sort_device_count(hip, ctx):
     import torch
     rng = _rng(5)
@@ -477,6 +496,29 @@ def test_join_chain_dense_edges(hip, ctx):
     cols, J = hip.join_chain(ctx, [_dev(o) for o in empty], [_dev(p) for p in pk0], pk_dense=[True, False, True],
                              pk_sorted=[True, False, True])
     assert J == 0 == len(oracle.join_chain(empty, pk0))
+    assert ctx.errors() == 0
+
+
+@pytest.mark.parametrize("digit_bits", [8, 4, 11])
+def test_join_chain_dense_partitioned(hip, ctx, digit_bits):
+    """The first dense hop into a table of at least 2^20 rows, entered by at least 2^20 tuples: a
+    radix pass over the keys' top digit partitions the tuples (keys below 0 or at or above M take no
+    part), then the dense pass reads them in that order.  Against the oracle, with a sort-based
+    hop after it."""
+    rng = _rng(131 + digit_bits)
+    M, C = 1_200_000, 40_000
+    outs = [rng.integers(-2000, M + 3000, 1_500_000).astype(np.int32), rng.integers(0, C, M).astype(np.int32)]
+    pks = [np.arange(M, dtype=np.int32), rng.permutation(C).astype(np.int32)]
+    want = oracle.join_chain(outs, pks)
+    ctx.set_digit_bits(digit_bits)
+    try:
+        cols, J = hip.join_chain(ctx, [_dev(o) for o in outs], [_dev(p) for p in pks], pk_dense=[True, False],
+                                 pk_sorted=[True, False])
+    finally:
+        ctx.set_digit_bits(8)
+    assert J == len(want) > 1_400_000
+    got = np.stack([_np(c, J) for c in cols], axis=1)
+    assert np.array_equal(_lex(got), _lex(want))
     assert ctx.errors() == 0
 
 
