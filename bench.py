@@ -655,6 +655,7 @@ def bench_chain(args):
     pks = [d["mid_pk"], d["cust_pk"], d["nation_pk"]]
     kb = [int(x - 1).bit_length() for x in (m, c, q)]      # key widths of the three hops
     res = {"key_bits": kb}
+    ref = {}
     for name, rule, dense in (("dense_keys", [True, False, True], [True, False, True]),
                               ("skip_sorted", [True, False, True], None), ("sort_all", [False, False, False], None)):
         caps = [n, n, n]
@@ -672,6 +673,16 @@ def bench_chain(args):
         ctx.set_profiling(False)
         if J != n:
             log("join chain (%s): %d tuples, expected %d" % (name, J, n))
+            sys.exit(3)
+        # the same tuples from every plan (their order is free): each fact row matches once, so
+        # the tuples ordered by their fact row must agree column by column
+        out_cols, _ = tqp.join_chain(ctx, outs, pks, pk_sorted=rule, key_bits=kb, caps=caps, pk_dense=dense)
+        first, order = torch.sort(out_cols[0][:J])
+        tup = [first] + [col[:J][order] for col in out_cols[1:]]
+        if "first" not in ref:
+            ref["first"] = tup
+        elif not all(torch.equal(a, b) for a, b in zip(ref["first"], tup)):
+            log("join chain (%s): tuples differ from the first plan's" % name)
             sys.exit(3)
         per = {}
         for k, t in recs:

@@ -14,7 +14,10 @@
 //      caller declares it sorted (then the positions are the indexes) or
 //      dense (then no sort and no join: the key is its own row position, and
 //      one pass keeps the tuples whose key lies in [0, M), writing their
-//      positions, their row and the next key, steps 3 and 4 included);
+//      positions, their row and the next key, steps 3 and 4 included; on the
+//      first hop into a large table a radix pass over the keys' top digit
+//      goes first, so that the next-key reads of a tile share a slice of
+//      the table in L2 instead of each missing it);
 //   3. the sort-based join gives (tuple index, row of table t) pairs;
 //   4. one gather kernel reads the earlier position columns through the tuple
 //      index (late materialisation) and the next hop's key through the new
@@ -35,7 +38,12 @@ namespace tqp {
 namespace {
 
 using JCfgChain = JoinCfg<256, 8, 4096>;
-constexpr int CH_FILTER_BLOCK = 256, CH_FILTER_ITEMS = 16;
+constexpr int CH_FILTER_BLOCK = 256;
+// The first dense hop reads the next key at random rows of its table; from
+// this many table rows (4 MB of keys, an XCD's L2) and as many tuples, the
+// tuples are first partitioned by the key's high bits, so that the reads of
+// a tile fall in one slice of the table.
+constexpr int64_t CH_PART_MIN_ROWS = int64_t(1) << 20;
 constexpr int CH_GATHER_BLOCK = 256, CH_GATHER_ITEMS = 4;
 
 // Sort source of the hop into table 2: the tuples' keys with both earlier
@@ -59,6 +67,29 @@ struct SrcKeysPos2 {
         k = keys[i];
         v = ((uint64_t)(uint32_t)pos1[i] << 32) | (uint32_t)pos0[i];
         return true;
+    }
+};
+
+// Sort source of the first hop's partition pass (dense rule): the tuples
+// whose key lies in [0, M), with their tuple index; the rest take no part.
+struct SrcDenseKeys {
+    const int32_t* keys;
+    int64_t M;
+    int64_t n_upper;
+    const int64_t* d_n;
+    __device__ int64_t size() const {
+        if (!d_n) return n_upper;
+        const int64_t n = *d_n;
+        return n < n_upper ? n : n_upper;
+    }
+    __device__ bool load_key(int64_t i, uint32_t& k) const {
+        const int32_t x = keys[i];
+        k = (uint32_t)x;
+        return x >= 0 && (int64_t)x < M;
+    }
+    __device__ bool load(int64_t i, uint32_t& k, uint32_t& v) const {
+        v = (uint32_t)i;
+        return load_key(i, k);
     }
 };
 
@@ -144,11 +175,17 @@ struct ChainDense {
     int32_t* key_dst;
 };
 
-template <int BLOCK, int ITEMS>
+// Rows per thread of a dense hop carrying nc position columns: every column
+// of a tile is held in registers from its load to its store, so the tile
+// shrinks as the columns grow.
+constexpr int dense_items(int nc) { return nc <= 3 ? 16 : nc <= 5 ? 8 : 4; }
+constexpr int dense_cols(int h) { return h == 1 ? 0 : h; }
+
+template <int BLOCK, int NC>
 __global__ void __launch_bounds__(BLOCK)
 k_chain_dense(ChainDense d, int64_t n, const int64_t* d_n, int64_t cap, int64_t* d_count, uint64_t* status,
               uint32_t* tile_counter, uint32_t* flags) {
-    constexpr int TILE = BLOCK * ITEMS, W = BLOCK / WAVE;
+    constexpr int ITEMS = dense_items(NC), TILE = BLOCK * ITEMS, W = BLOCK / WAVE;
     __shared__ int64_t s_wave[W];
     __shared__ int64_t s_base;
     __shared__ uint32_t s_tile;
@@ -166,15 +203,25 @@ k_chain_dense(ChainDense d, int64_t n, const int64_t* d_n, int64_t cap, int64_t*
         return;
     }
     const int64_t chunk = tile * TILE + (int64_t)w * ITEMS * WAVE;
+    // the keys and the carried positions of the whole tile are loaded before
+    // any of it is written, so all of the tile's reads are in flight at once
     int32_t k[ITEMS];
-    bool ok[ITEMS];
-    uint64_t m[ITEMS];
-    int64_t wc = 0;
+    int32_t v[NC > 0 ? NC : 1][ITEMS];
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const int64_t i = chunk + j * WAVE + l;
         k[j] = d.key[i < n ? i : n - 1];       // n >= 1: the tile exists
     }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) {
+            const int64_t i = chunk + j * WAVE + l;
+            v[c][j] = d.src[c][i < n ? i : n - 1];
+        }
+    bool ok[ITEMS];
+    uint64_t m[ITEMS];
+    int64_t wc = 0;
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         ok[j] = chunk + j * WAVE + l < n && k[j] >= 0 && (int64_t)k[j] < d.M;
@@ -204,29 +251,35 @@ k_chain_dense(ChainDense d, int64_t n, const int64_t* d_n, int64_t cap, int64_t*
         }
     }
     __syncthreads();
-    int64_t o[ITEMS];
     int64_t pos = s_base + s_wave[w];
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-        o[j] = ok[j] ? pos + popc64(m[j] & lanemask_lt()) : -1;
+        const int64_t o = ok[j] ? pos + popc64(m[j] & lanemask_lt()) : -1;
         pos += popc64(m[j]);
-        if (o[j] >= 0 && o[j] < cap) {
-            d.row_dst[o[j]] = k[j];
-            if (d.index_dst) d.index_dst[o[j]] = (int32_t)(chunk + j * WAVE + l);
-            if (d.key_src) d.key_dst[o[j]] = nk[j];
+        if (o >= 0 && o < cap) {
+            d.row_dst[o] = k[j];
+            if (d.index_dst) d.index_dst[o] = (int32_t)(chunk + j * WAVE + l);
+            if (d.key_src) d.key_dst[o] = nk[j];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) d.dst[c][o] = v[c][j];
         }
     }
-    for (int c = 0; c < d.ncols; ++c) {
-        int32_t v[ITEMS];
-#pragma unroll
-        for (int j = 0; j < ITEMS; ++j) {
-            const int64_t i = chunk + j * WAVE + l;
-            v[j] = d.src[c][i < n ? i : n - 1];
-        }
-#pragma unroll
-        for (int j = 0; j < ITEMS; ++j)
-            if (o[j] >= 0 && o[j] < cap) d.dst[c][o[j]] = v[j];
+}
+
+template <int NC>
+tqp_status dense_launch(tqp_ctx* ctx, hipStream_t s, const ChainDense& d, int64_t n, const int64_t* d_n, int64_t cap,
+                        int64_t* d_count, uint64_t* status, uint32_t* counter) {
+    if (d.ncols != NC) {
+        if constexpr (NC + 1 < TQP_CHAIN_MAX_TABLES)
+            return dense_launch<NC + 1>(ctx, s, d, n, d_n, cap, d_count, status, counter);
+        else
+            return fail(TQP_ERR_INVALID, "tqp_join_chain: %d position columns in a dense hop", d.ncols);
     }
+    constexpr int64_t TILE = (int64_t)CH_FILTER_BLOCK * dense_items(NC);
+    TQP_LAUNCH(ctx, s, "chain_dense",
+               (k_chain_dense<CH_FILTER_BLOCK, NC><<<grid_for(n, TILE, 0), CH_FILTER_BLOCK, 0, s>>>(
+                   d, n, d_n, cap, d_count, status, counter, ctx->d_err)));
+    return TQP_OK;
 }
 
 template <class Cfg>
@@ -243,6 +296,11 @@ struct HopBufs {
     JoinBufs join;
     uint64_t* fstatus = nullptr;             // dense rule: the filter's look-back words
     uint32_t* fcounter = nullptr;
+    bool part = false;                       // dense first hop: partition pass before the gather
+    int part_bits = 0;
+    RadixBufs<Cfg, uint32_t> psort;
+    uint32_t* pk = nullptr;                  // partitioned keys and tuple indexes
+    uint32_t* pv = nullptr;
     uint32_t *lsk = nullptr, *lsv = nullptr, *rsk = nullptr, *rsv = nullptr;
     int32_t* li = nullptr;                   // tuple index of every output tuple
     int64_t* d_cnt = nullptr;                // tuples after the hop
@@ -268,7 +326,18 @@ void chain_reserve(Arena& a, const tqp_chain_table* t, int nt, int64_t* d_count,
         hb.sorted = t[h].rule == TQP_CHAIN_PK_SORTED;
         hb.n_left = h == 1 ? t[0].n_rows : t[h - 1].cap;
         if (hb.dense) {
-            const int64_t tiles = (hb.n_left + CH_FILTER_BLOCK * CH_FILTER_ITEMS - 1) / (CH_FILTER_BLOCK * CH_FILTER_ITEMS);
+            hb.part = h == 1 && h < H && t[h].n_rows >= CH_PART_MIN_ROWS && hb.n_left >= CH_PART_MIN_ROWS;
+            if (hb.part) {
+                // one radix pass over the top digit of the keys below M
+                int pb = 1;
+                while (pb < 31 && (int64_t(1) << pb) < t[h].n_rows) ++pb;
+                hb.part_bits = pb;
+                hb.psort = radix_reserve<Cfg, uint32_t>(a, hb.n_left, pb, pb > Cfg::RADIX_BITS ? pb - Cfg::RADIX_BITS : 0);
+                hb.pk = a.scratch<uint32_t>(hb.n_left);
+                hb.pv = a.scratch<uint32_t>(hb.n_left);
+            }
+            const int64_t tile = (int64_t)CH_FILTER_BLOCK * dense_items(hb.part ? 1 : dense_cols(h));
+            const int64_t tiles = (hb.n_left + tile - 1) / tile;
             hb.fstatus = a.zero<uint64_t>(tiles);
             hb.fcounter = a.zero<uint32_t>(1);
         } else {
@@ -330,7 +399,7 @@ tqp_status chain_launch(tqp_ctx* ctx, const tqp_chain_table* t, int nt, int32_t*
             if (h == 1) {
                 d.index_dst = dst[0];
             } else {
-                d.ncols = h;
+                d.ncols = dense_cols(h);
                 for (int u = 0; u < h; ++u) {
                     d.src[u] = prev_cols[u];
                     d.dst[u] = dst[u];
@@ -341,11 +410,25 @@ tqp_status chain_launch(tqp_ctx* ctx, const tqp_chain_table* t, int nt, int32_t*
                 d.key_src = t[h].key_out;
                 d.key_dst = next_key;
             }
-            constexpr int64_t TILE = CH_FILTER_BLOCK * CH_FILTER_ITEMS;
-            TQP_LAUNCH(ctx, s, "chain_dense",
-                       (k_chain_dense<CH_FILTER_BLOCK, CH_FILTER_ITEMS><<<grid_for(hb.n_left, TILE, 0),
-                                                                         CH_FILTER_BLOCK, 0, s>>>(
-                           d, hb.n_left, d_prev, t[h].cap, hb.d_cnt, hb.fstatus, hb.fcounter, ctx->d_err)));
+            const int64_t* dn = d_prev;
+            if (hb.part) {
+                // the kept tuples partitioned by their key's top digit (the
+                // tuple index as the payload), then the pass below reads them
+                // in that order: its index becomes the carried position
+                SrcDenseKeys psrc{cur, t[h].n_rows, hb.n_left, d_prev};
+                if ((st = radix_launch<Cfg, uint32_t>(hb.psort, psrc, hb.n_left, true, nullptr,
+                                                      key_mask_for(hb.part_bits), hb.pk, hb.pv, ctx, s,
+                                                      "chain_dense_part", "chain_dense_part")) != TQP_OK)
+                    return st;
+                d.key = reinterpret_cast<const int32_t*>(hb.pk);
+                d.index_dst = nullptr;
+                d.ncols = 1;
+                d.src[0] = reinterpret_cast<const int32_t*>(hb.pv);
+                d.dst[0] = dst[0];
+                dn = hb.psort.d_cnt;
+            }
+            if ((st = dense_launch<0>(ctx, s, d, hb.n_left, dn, t[h].cap, hb.d_cnt, hb.fstatus, hb.fcounter)) != TQP_OK)
+                return st;
             cur = next_key;
             d_prev = hb.d_cnt;
             prev_cols = dst;
