@@ -204,20 +204,23 @@ k_chain_dense(ChainDense d, int64_t n, const int64_t* d_n, int64_t cap, int64_t*
     }
     const int64_t chunk = tile * TILE + (int64_t)w * ITEMS * WAVE;
     // the keys and the carried positions of the whole tile are loaded before
-    // any of it is written, so all of the tile's reads are in flight at once
+    // any of it is written, so all of the tile's reads are in flight at once.
+    // The streamed columns are read and written with the non-temporal hint:
+    // they pass through once, and the L2 keeps the table slice the next-key
+    // reads fall in.
     int32_t k[ITEMS];
     int32_t v[NC > 0 ? NC : 1][ITEMS];
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const int64_t i = chunk + j * WAVE + l;
-        k[j] = d.key[i < n ? i : n - 1];       // n >= 1: the tile exists
+        k[j] = __builtin_nontemporal_load(&d.key[i < n ? i : n - 1]);   // n >= 1: the tile exists
     }
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
         for (int j = 0; j < ITEMS; ++j) {
             const int64_t i = chunk + j * WAVE + l;
-            v[c][j] = d.src[c][i < n ? i : n - 1];
+            v[c][j] = __builtin_nontemporal_load(&d.src[c][i < n ? i : n - 1]);
         }
     bool ok[ITEMS];
     uint64_t m[ITEMS];
@@ -257,11 +260,11 @@ k_chain_dense(ChainDense d, int64_t n, const int64_t* d_n, int64_t cap, int64_t*
         const int64_t o = ok[j] ? pos + popc64(m[j] & lanemask_lt()) : -1;
         pos += popc64(m[j]);
         if (o >= 0 && o < cap) {
-            d.row_dst[o] = k[j];
-            if (d.index_dst) d.index_dst[o] = (int32_t)(chunk + j * WAVE + l);
-            if (d.key_src) d.key_dst[o] = nk[j];
+            __builtin_nontemporal_store(k[j], &d.row_dst[o]);
+            if (d.index_dst) __builtin_nontemporal_store((int32_t)(chunk + j * WAVE + l), &d.index_dst[o]);
+            if (d.key_src) __builtin_nontemporal_store(nk[j], &d.key_dst[o]);
 #pragma unroll
-            for (int c = 0; c < NC; ++c) d.dst[c][o] = v[c][j];
+            for (int c = 0; c < NC; ++c) __builtin_nontemporal_store(v[c][j], &d.dst[c][o]);
         }
     }
 }
