@@ -28,6 +28,10 @@ constexpr int XE_ROWS_FEW = 4;   // rows per thread when the program reads at mo
 // Word 3 of a raw buffer descriptor on gfx9-family chips: 32-bit data format,
 // no swizzle, no stride; loads past the descriptor's byte range return 0.
 constexpr int XE_RSRC_WORD3 = 0x00020000;
+// Cache policy of the column loads: the non-temporal bit (each column byte is
+// read once; with it, and non-temporal result stores, the 60M-row revenue
+// program takes about 0.288 instead of 0.295 ms).
+constexpr int XE_LOAD_NT = 2;
 enum : int { XT_I8 = 1, XT_I32 = 2, XT_I64 = 4, XT_ALL = 7 };
 
 enum : int32_t {
@@ -106,13 +110,13 @@ k_eval(XProg p, int64_t n_upper, const int64_t* d_n, void* out, int out_mode, ui
                     const int off = j * XE_BLOCK + tid;
                     int64_t v = 0;
                     if constexpr ((TYPES & XT_I64) != 0) {
-                        const auto v64 = __builtin_amdgcn_raw_buffer_load_b64(r64, off * 8, 0, 0);
+                        const auto v64 = __builtin_amdgcn_raw_buffer_load_b64(r64, off * 8, 0, XE_LOAD_NT);
                         v += (int64_t)(((uint64_t)v64[1] << 32) | v64[0]);
                     }
                     if constexpr ((TYPES & XT_I32) != 0)
-                        v += (int64_t)(int32_t)__builtin_amdgcn_raw_buffer_load_b32(r32, off * 4, 0, 0);
+                        v += (int64_t)(int32_t)__builtin_amdgcn_raw_buffer_load_b32(r32, off * 4, 0, XE_LOAD_NT);
                     if constexpr ((TYPES & XT_I8) != 0)
-                        v += (int64_t)(int8_t)__builtin_amdgcn_raw_buffer_load_b8(r8, off, 0, 0);
+                        v += (int64_t)(int8_t)__builtin_amdgcn_raw_buffer_load_b8(r8, off, 0, XE_LOAD_NT);
                     cv[j][c] = v;
                 }
             }
@@ -259,7 +263,7 @@ k_eval(XProg p, int64_t n_upper, const int64_t* d_n, void* out, int out_mode, ui
                     static_cast<int32_t*>(out)[row] = (int32_t)top[j];
                     zdiv |= top[j] != (int64_t)(int32_t)top[j];
                 } else {
-                    static_cast<int64_t*>(out)[row] = top[j];
+                    __builtin_nontemporal_store(top[j], &static_cast<int64_t*>(out)[row]);
                 }
             }
         }
